@@ -1,0 +1,351 @@
+"""FP64 CPU oracle for the tomography likelihood path -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import or call this module.  The product path (the HIP
+library and its Python binding) never does; they share no code with it.
+
+What it computes, written from the paper (Wang, Cheng, Li, Chen,
+"Ultrafast quantum state tomography with feed-forward neural networks"):
+
+* state map   rho = T T^dagger / Tr(T T^dagger)
+              (Sec. 2.2.1 Eq. T_matrix; Sec. 3.2 Eq. unified_DP and Eq. abs_P
+              at P = 2 -- see the reading of T^dagger T vs T T^dagger below)
+* Born rule   p_k = Tr(M_k rho)                  (Sec. 2.1, Born rule)
+* product POVM M_k = M_{k_1} (x) ... (x) M_{k_N}   (Sec. 3.3)
+* tetrahedral single-qubit POVM M_a = (I + s_a . sigma)/4   (Sec. 4.1 setup)
+* loss        L = -sum_k f_k log p_k              (Sec. 2.1 Eq. MLE; Sec. 3.1)
+* gradient    dL/dT (PyTorch convention dL/dRe T + i dL/dIm T)
+* fidelity    F_q (Sec. 2.3 Eq. F_QF) and F_c (Eq. F_CF)
+
+Everything is numpy float64 / complex128.  Sums that define a scalar result
+use ``math.fsum`` (correctly rounded).  Nothing is blocked, fused or
+reordered beyond what the definitions state; the only library primitives are
+``@`` (matrix product), ``np.kron`` and ``np.tensordot``.
+
+Readings of the paper taken here (each also listed in the design notes):
+
+1. The paper writes rho = T^dagger T / Tr(...).  This oracle maps rho = T T^dagger
+   / Tr(T T^dagger); the two are the same map applied to T vs T^dagger, and
+   coincide for the Hermitian T of the unified map (Eq. unified_DP).
+2. Qubit 1 is the leftmost Kronecker factor, i.e. the most significant bit of
+   the row index r and of the column index c of rho; the outcome index is
+   k = sum_i k_i 4^(N-i); outcome a of one qubit is s_a in the paper's order.
+3. Eq. PS pairs b_i with block B; the Born rule Tr(M rho) = sum_ab M_ab rho_ba
+   pairs the (0,1) entry of M with the (1,0) block of rho.  The oracle follows
+   the Born rule, not the printed pairing (which computes Tr(M^T rho)).
+4. sigma = (X, Y, Z) with Y = [[0, -i], [i, 0]].
+5. f is used as given (counts or frequencies); log is natural; terms with
+   f_k = 0 contribute 0; a term with f_k > 0 and p_k <= 0 makes L = +inf.
+
+Parity pins: every function here is checked in ``tests/test_oracle_pins.py``
+against brute force, closed forms and invariants (no function is unpinned).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# Single-qubit POVM (Sec. 4.1, experimental setups)
+# ----------------------------------------------------------------------------
+
+_T3 = 1.0 / math.sqrt(3.0)
+
+#: Bloch vectors s_0..s_3 of the tetrahedral POVM, in the paper's order.
+TETRA_S = np.array(
+    [
+        [_T3, _T3, _T3],
+        [-_T3, -_T3, _T3],
+        [-_T3, _T3, -_T3],
+        [_T3, -_T3, -_T3],
+    ],
+    dtype=np.float64,
+)
+
+PAULI = (
+    np.array([[0, 1], [1, 0]], dtype=np.complex128),
+    np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
+    np.array([[1, 0], [0, -1]], dtype=np.complex128),
+)
+
+
+def povm_from_bloch(s: np.ndarray) -> np.ndarray:
+    """M_a = (I + s_a . sigma)/4 for each row s_a of ``s``; shape (K, 2, 2)."""
+    s = np.asarray(s, dtype=np.float64)
+    out = np.empty((s.shape[0], 2, 2), dtype=np.complex128)
+    for a in range(s.shape[0]):
+        m = np.eye(2, dtype=np.complex128)
+        for j in range(3):
+            m = m + s[a, j] * PAULI[j]
+        out[a] = m / 4.0
+    return out
+
+
+def tetrahedral_povm() -> np.ndarray:
+    """The paper's single-qubit POVM {M_a}, a = 0..3; shape (4, 2, 2)."""
+    return povm_from_bloch(TETRA_S)
+
+
+# ----------------------------------------------------------------------------
+# State map (Sec. 2.2.1 Eq. T_matrix; Sec. 3.2 Eq. unified_DP, Eq. abs_P)
+# ----------------------------------------------------------------------------
+
+def trace_tt(T: np.ndarray) -> float:
+    """tau = Tr(T T^dagger) = sum_ij |T_ij|^2, correctly rounded."""
+    a = np.asarray(T, dtype=np.complex128)
+    return math.fsum((a.real.ravel() ** 2).tolist() + (a.imag.ravel() ** 2).tolist())
+
+
+def state_map(T: np.ndarray) -> tuple[np.ndarray, float]:
+    """rho = T T^dagger / tau and tau (Eq. T_matrix with reading 1).
+
+    ``T`` may be d x r (a rank-r factor); rho is d x d.
+    """
+    a = np.asarray(T, dtype=np.complex128)
+    tau = trace_tt(a)
+    rho = (a @ a.conj().T) / tau
+    return rho, tau
+
+
+# ----------------------------------------------------------------------------
+# Product-structured POVM probabilities (Sec. 2.1 Born rule; Sec. 3.3)
+# ----------------------------------------------------------------------------
+
+def n_qubits_of(dim: int) -> int:
+    n = dim.bit_length() - 1
+    if dim != 1 << n or n < 1:
+        raise ValueError(f"dimension {dim} is not 2^N with N >= 1")
+    return n
+
+
+def product_element(povm: np.ndarray, ks) -> np.ndarray:
+    """M_k = M_{k_1} (x) ... (x) M_{k_N}, qubit 1 leftmost (Sec. 3.3)."""
+    m = np.ones((1, 1), dtype=np.complex128)
+    for a in ks:
+        m = np.kron(m, povm[a])
+    return m
+
+
+def outcome_tuples(n: int, K: int = 4):
+    """All k = (k_1..k_N) in the order k = sum_i k_i K^(N-i)."""
+    return itertools.product(range(K), repeat=n)
+
+
+def probs_kron(rho: np.ndarray, povm: np.ndarray | None = None) -> np.ndarray:
+    """Brute force: p_k = Tr(M_k rho) with explicit Kronecker products.
+
+    Exponential cost; intended for N <= 5.  Returns the real part; the
+    imaginary part (zero for Hermitian rho) is checked by the tests.
+    """
+    povm = tetrahedral_povm() if povm is None else povm
+    n = n_qubits_of(rho.shape[0])
+    out = np.empty(povm.shape[0] ** n, dtype=np.complex128)
+    for idx, ks in enumerate(outcome_tuples(n, povm.shape[0])):
+        out[idx] = np.trace(product_element(povm, ks) @ rho)
+    return out
+
+
+def _pair_tensor(mat: np.ndarray) -> np.ndarray:
+    """View a d x d matrix as a tensor over per-qubit pair indices
+    m_i = 2 r_i + c_i, axes ordered qubit 1..N."""
+    n = n_qubits_of(mat.shape[0])
+    t = mat.reshape((2,) * (2 * n))  # (r_1..r_N, c_1..c_N)
+    order = [ax for i in range(n) for ax in (i, n + i)]  # (r_1, c_1, r_2, c_2, ...)
+    return t.transpose(order).reshape((4,) * n)
+
+
+def _from_pair_tensor(t: np.ndarray) -> np.ndarray:
+    n = t.ndim
+    d = 1 << n
+    x = t.reshape((2,) * (2 * n))  # (r_1, c_1, r_2, c_2, ...)
+    order = [2 * i for i in range(n)] + [2 * i + 1 for i in range(n)]
+    return x.transpose(order).reshape(d, d)
+
+
+def probs(rho: np.ndarray, povm: np.ndarray | None = None) -> np.ndarray:
+    """p_k = Tr(M_k rho) via the product structure (Sec. 3.3): one 4 x 4
+    contraction per qubit over its pair index m_i = 2 r_i + c_i, with
+    W[a, 2r + c] = (M_a)_{c, r} so that sum_m W[a, m] rho_m = Tr(M_a rho)
+    for one qubit (Born rule).  Complex result (imaginary part ~ 0)."""
+    povm = tetrahedral_povm() if povm is None else povm
+    K = povm.shape[0]
+    W = np.transpose(povm, (0, 2, 1)).reshape(K, 4)  # W[a, 2r+c] = M_a[c, r]
+    x = _pair_tensor(np.asarray(rho, dtype=np.complex128))
+    n = x.ndim
+    for i in range(n):
+        x = np.tensordot(W, x, axes=([1], [i]))  # new axis first
+        x = np.moveaxis(x, 0, i)
+    return x.reshape(K ** n)
+
+
+def probs_real(rho: np.ndarray, povm: np.ndarray | None = None, check: bool = True) -> np.ndarray:
+    """Real probabilities; asserts the imaginary part is at rounding level."""
+    pc = probs(rho, povm)
+    if check:
+        scale = max(float(np.max(np.abs(pc.real))), 1e-300)
+        if float(np.max(np.abs(pc.imag))) > 1e-12 * scale:
+            raise AssertionError("probabilities have a non-negligible imaginary part; rho not Hermitian")
+    return pc.real.copy()
+
+
+# ----------------------------------------------------------------------------
+# Adjoint of the POVM map: G = sum_k g_k M_k
+# ----------------------------------------------------------------------------
+
+def adjoint_kron(g: np.ndarray, n: int, povm: np.ndarray | None = None) -> np.ndarray:
+    """Brute force G = sum_k g_k M_k (N <= 5)."""
+    povm = tetrahedral_povm() if povm is None else povm
+    d = 1 << n
+    G = np.zeros((d, d), dtype=np.complex128)
+    for idx, ks in enumerate(outcome_tuples(n, povm.shape[0])):
+        G += g[idx] * product_element(povm, ks)
+    return G
+
+
+def adjoint(g: np.ndarray, n: int, povm: np.ndarray | None = None) -> np.ndarray:
+    """G = sum_k g_k M_k via per-qubit contractions: G[r, c] =
+    sum_k g_k prod_i (M_{k_i})_{r_i, c_i}, i.e. V[2r + c, a] = (M_a)_{r, c}
+    applied along each qubit axis."""
+    povm = tetrahedral_povm() if povm is None else povm
+    K = povm.shape[0]
+    V = povm.reshape(K, 4).T  # V[2r+c, a] = M_a[r, c]
+    x = np.asarray(g, dtype=np.complex128).reshape((K,) * n)
+    for i in range(n):
+        x = np.tensordot(V, x, axes=([1], [i]))
+        x = np.moveaxis(x, 0, i)
+    return _from_pair_tensor(x)
+
+
+# ----------------------------------------------------------------------------
+# Negative log-likelihood (Sec. 2.1 Eq. MLE; Sec. 3.1 loss)
+# ----------------------------------------------------------------------------
+
+def nll(p: np.ndarray, f: np.ndarray) -> float:
+    """L = -sum_{k: f_k > 0} f_k ln p_k; +inf if some f_k > 0 has p_k <= 0."""
+    p = np.asarray(p, dtype=np.float64).ravel()
+    f = np.asarray(f, dtype=np.float64).ravel()
+    terms = []
+    for fk, pk in zip(f.tolist(), p.tolist()):
+        if fk == 0.0:
+            continue
+        if pk <= 0.0:
+            return math.inf
+        terms.append(-fk * math.log(pk))
+    return math.fsum(terms)
+
+
+def nll_vec(p: np.ndarray, f: np.ndarray) -> float:
+    """Same value as :func:`nll` for large vectors (vectorised log, fsum)."""
+    p = np.asarray(p, dtype=np.float64).ravel()
+    f = np.asarray(f, dtype=np.float64).ravel()
+    m = f != 0.0
+    if np.any(p[m] <= 0.0):
+        return math.inf
+    return math.fsum((-f[m] * np.log(p[m])).tolist())
+
+
+def likelihood(T: np.ndarray, f: np.ndarray, povm: np.ndarray | None = None):
+    """Forward chain T -> (rho, tau) -> p -> L.  Returns (L, p, rho, tau)."""
+    rho, tau = state_map(T)
+    n = n_qubits_of(rho.shape[0])
+    p = probs_real(rho, povm) if n > 5 else probs_kron(rho, povm).real.copy()
+    return nll_vec(p, f), p, rho, tau
+
+
+# ----------------------------------------------------------------------------
+# Gradient of L with respect to T
+# ----------------------------------------------------------------------------
+
+def cotangent(p: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """g'_k = F - f_k / p_k with F = sum_k f_k (g'_k = F where f_k = 0).
+
+    From dL = (1/tau) Tr(G' dS), S = T T^dagger, with G' = sum_k g'_k M_k:
+    the -f_k/p_k part is dL/dp_k, and F I = sum_k F M_k is the derivative of
+    the trace normalisation (sum_k M_k = I, Eq. MLE constraint)."""
+    p = np.asarray(p, dtype=np.float64).ravel()
+    f = np.asarray(f, dtype=np.float64).ravel()
+    F = math.fsum(f.tolist())
+    g = np.full(p.shape, F)
+    m = f != 0.0
+    g[m] = F - f[m] / p[m]
+    return g
+
+
+def grad_T(T: np.ndarray, f: np.ndarray, povm: np.ndarray | None = None):
+    """dL/dRe T + i dL/dIm T = (2/tau) G' T.  Returns (grad, L)."""
+    L, p, rho, tau = likelihood(T, f, povm)
+    n = n_qubits_of(rho.shape[0])
+    g = cotangent(p, f)
+    G = adjoint(g, n, povm) if n > 5 else adjoint_kron(g, n, povm)
+    return (2.0 / tau) * (G @ np.asarray(T, dtype=np.complex128)), L
+
+
+def loss_of_T(T: np.ndarray, f: np.ndarray, povm: np.ndarray | None = None) -> float:
+    return likelihood(T, f, povm)[0]
+
+
+# ----------------------------------------------------------------------------
+# Fidelities (Sec. 2.3)
+# ----------------------------------------------------------------------------
+
+def _psd_sqrt(a: np.ndarray) -> np.ndarray:
+    w, v = np.linalg.eigh((a + a.conj().T) / 2.0)
+    w = np.clip(w, 0.0, None)
+    return (v * np.sqrt(w)) @ v.conj().T
+
+
+def fidelity_q(rho_hat: np.ndarray, rho: np.ndarray) -> float:
+    """F_q = (Tr sqrt(sqrt(rho_hat) rho sqrt(rho_hat)))^2 (Eq. F_QF)."""
+    s = _psd_sqrt(rho_hat)
+    m = s @ rho @ s
+    w = np.clip(np.linalg.eigvalsh((m + m.conj().T) / 2.0), 0.0, None)
+    return float(math.fsum(np.sqrt(w).tolist()) ** 2)
+
+
+def fidelity_q_lowrank(rho_hat: np.ndarray, W: np.ndarray) -> float:
+    """F_q(rho_hat, rho) for a target rho = W W^dagger / Tr(W W^dagger) of low
+    rank r: sqrt(rho_hat) rho sqrt(rho_hat) and W^dagger rho_hat W / Tr share
+    their nonzero eigenvalues, so F_q = (sum sqrt(eig(W^dagger rho_hat W)/Tr))^2
+    needs only an r x r eigensolve."""
+    W = np.asarray(W, dtype=np.complex128)
+    tw = trace_tt(W)
+    m = W.conj().T @ rho_hat @ W / tw
+    w = np.clip(np.linalg.eigvalsh((m + m.conj().T) / 2.0), 0.0, None)
+    return float(math.fsum(np.sqrt(w).tolist()) ** 2)
+
+
+def fidelity_c(p_hat: np.ndarray, p: np.ndarray) -> float:
+    """F_c = (sum_k sqrt(p_hat_k p_k))^2 (Eq. F_CF)."""
+    a = np.clip(np.asarray(p_hat, dtype=np.float64), 0.0, None)
+    b = np.clip(np.asarray(p, dtype=np.float64), 0.0, None)
+    return math.fsum(np.sqrt(a * b).tolist()) ** 2
+
+
+# ----------------------------------------------------------------------------
+# Reference optimiser loop (training-shape workload): Adam on T directly
+# ----------------------------------------------------------------------------
+
+def adam_train(T0: np.ndarray, f: np.ndarray, steps: int, lr: float, betas=(0.9, 0.999),
+               eps: float = 1e-12, povm: np.ndarray | None = None):
+    """Plain Adam on the complex parameter T (real and imaginary parts as two
+    real parameters, the torch convention), minimising L(T).  Returns
+    (T_final, losses)."""
+    b1, b2 = betas
+    T = np.asarray(T0, dtype=np.complex128).copy()
+    m = np.zeros_like(T)
+    v = np.zeros(T.shape, dtype=np.float64)
+    vi = np.zeros(T.shape, dtype=np.float64)
+    losses = []
+    for t in range(1, steps + 1):
+        g, L = grad_T(T, f, povm)
+        losses.append(L)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g.real ** 2
+        vi = b2 * vi + (1 - b2) * g.imag ** 2
+        mh = m / (1 - b1 ** t)
+        vh = v / (1 - b2 ** t)
+        vih = vi / (1 - b2 ** t)
+        T = T - lr * (mh.real / (np.sqrt(vh) + eps) + 1j * mh.imag / (np.sqrt(vih) + eps))
+    return T, losses

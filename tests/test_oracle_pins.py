@@ -1,0 +1,385 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle:
+values the paper prints, closed forms, invariants, brute force on tiny
+inputs, and library routines for the special cases that reduce to them.
+
+Each test names the passage of the paper it rests on.  Tolerances are
+stated in the tests; all arithmetic is float64.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+
+import oracle as O
+import synth as S
+from conftest import read_table
+
+T3 = 1.0 / math.sqrt(3.0)
+
+
+def bloch_state(r):
+    """(I + r . sigma)/2 written out entrywise (no Pauli table reuse)."""
+    x, y, z = r
+    return 0.5 * np.array([[1 + z, x - 1j * y], [x + 1j * y, 1 - z]], dtype=np.complex128)
+
+
+def kron_all(mats):
+    out = np.ones((1, 1), dtype=np.complex128)
+    for m in mats:
+        out = np.kron(out, m)
+    return out
+
+
+# --------------------------------------------------------------------------
+# POVM constants (Sec. 4.1)
+# --------------------------------------------------------------------------
+
+def test_tetrahedral_constants_match_paper():
+    rows = read_table("tetrahedral_bloch.txt")
+    want = np.array([[float(v) * T3 for v in r[1:]] for r in rows])
+    assert [int(r[0]) for r in rows] == [0, 1, 2, 3]
+    np.testing.assert_allclose(O.TETRA_S, want, rtol=0, atol=1e-16)
+
+
+def test_tetrahedral_povm_is_a_povm():
+    M = O.tetrahedral_povm()
+    # entrywise form of (I + s.sigma)/4 written out independently
+    for a in range(4):
+        sx, sy, sz = O.TETRA_S[a]
+        want = 0.25 * np.array([[1 + sz, sx - 1j * sy], [sx + 1j * sy, 1 - sz]])
+        np.testing.assert_allclose(M[a], want, atol=1e-16)
+        w = np.linalg.eigvalsh(M[a])
+        np.testing.assert_allclose(w, [0.0, 0.5], atol=1e-15)  # rank 1, PSD
+        np.testing.assert_allclose(M[a], M[a].conj().T, atol=0)
+    np.testing.assert_allclose(M.sum(axis=0), np.eye(2), atol=1e-15)  # sum M = I (Eq. MLE)
+
+
+# --------------------------------------------------------------------------
+# Born rule and product structure (Sec. 2.1, Sec. 3.3)
+# --------------------------------------------------------------------------
+
+def test_single_qubit_born_rule_by_hand():
+    """N = 1: p_a = Tr(M_a rho) = sum_{x,y} (M_a)_{xy} rho_{yx}, summed by hand."""
+    g = S.rng(11)
+    M = O.tetrahedral_povm()
+    for _ in range(5):
+        rho, _ = O.state_map(S.ginibre(g, 2))
+        want = [sum(M[a][x, y] * rho[y, x] for x in range(2) for y in range(2)) for a in range(4)]
+        np.testing.assert_allclose(O.probs(rho), want, atol=1e-16)
+        np.testing.assert_allclose(O.probs_kron(rho), want, atol=1e-16)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_contraction_equals_kronecker(n):
+    """The per-qubit contraction is an exact refactoring of the Kronecker
+    sum (Sec. 3.3); checked also on non-Hermitian input, where both sides
+    are complex-valued linear maps."""
+    g = S.rng(100 + n)
+    d = 1 << n
+    rho, _ = O.state_map(S.ginibre(g, d))
+    X = S.ginibre(g, d)
+    for A in (rho, X):
+        pk = O.probs_kron(A)
+        pt = O.probs(A)
+        assert np.max(np.abs(pk - pt)) <= 1e-15 * max(1.0, np.max(np.abs(pk)))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_product_state_closed_form(n):
+    """rho = (x)_i (I + r_i.sigma)/2 gives p_k = prod_i (1 + s_{k_i}.r_i)/4.
+    Distinct Bloch vectors per qubit with r_y != 0 fail under a wrong qubit
+    order, a wrong outcome order, or the transposed pairing of Eq. PS."""
+    g = S.rng(200 + n)
+    r = g.standard_normal((n, 3))
+    r = 0.95 * r / np.linalg.norm(r, axis=1, keepdims=True)
+    assert np.all(np.abs(r[:, 1]) > 1e-3)
+    rho = kron_all([bloch_state(ri) for ri in r])
+    want = np.array([np.prod([(1.0 + O.TETRA_S[ks[i]] @ r[i]) / 4.0 for i in range(n)])
+                     for ks in itertools.product(range(4), repeat=n)])
+    p = O.probs_real(rho)
+    assert np.max(np.abs(p - want)) <= 1e-15
+    if n <= 5:
+        assert np.max(np.abs(O.probs_kron(rho).real - want)) <= 1e-15
+
+
+def test_eq_ps_literal_pairing_is_transposed():
+    """Reading of Eq. PS: pairing b_i (the (0,1) entry of M_i) with the
+    (0,1) block B computes Tr(M^T rho), which flips s_y.  The Born rule pairs
+    it with the (1,0) block.  On a state with r_y != 0 the two differ."""
+    M = O.tetrahedral_povm()
+    rho = bloch_state([0.1, 0.8, 0.2])
+    born = np.array([np.trace(M[a] @ rho) for a in range(4)]).real
+    literal = np.array([M[a][0, 0] * rho[0, 0] + M[a][0, 1] * rho[0, 1]
+                        + M[a][1, 0] * rho[1, 0] + M[a][1, 1] * rho[1, 1] for a in range(4)]).real
+    np.testing.assert_allclose(O.probs_real(rho), born, atol=1e-16)
+    assert np.max(np.abs(born - literal)) > 0.05
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 10])
+def test_ghzi_closed_form(n):
+    """GHZi target (Sec. 4): rho has four nonzero entries, so
+    p_k = 1/2 [prod (M_{k_i})_00 + prod (M_{k_i})_11] - Im prod (M_{k_i})_01."""
+    M = O.tetrahedral_povm()
+    psi = S.ghzi(n)
+    rho = np.outer(psi, psi.conj())
+    want = []
+    for ks in itertools.product(range(4), repeat=n):
+        a00 = np.prod([M[k][0, 0] for k in ks])
+        a11 = np.prod([M[k][1, 1] for k in ks])
+        a01 = np.prod([M[k][0, 1] for k in ks])
+        want.append((0.5 * (a00 + a11)).real - a01.imag)
+    assert np.max(np.abs(O.probs_real(rho) - np.array(want))) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 4, 9])
+def test_maximally_mixed_and_basis_state(n):
+    d = 1 << n
+    p = O.probs_real(np.eye(d, dtype=np.complex128) / d)
+    np.testing.assert_allclose(p, np.full(4 ** n, 4.0 ** -n), rtol=1e-14, atol=0)
+    e0 = np.zeros((d, d), dtype=np.complex128)
+    e0[0, 0] = 1.0
+    want = np.array([np.prod([(1.0 + O.TETRA_S[k][2]) / 4.0 for k in ks])
+                     for ks in itertools.product(range(4), repeat=n)])
+    np.testing.assert_allclose(O.probs_real(e0), want, rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("n", [1, 3, 6, 8])
+def test_probability_invariants(n):
+    """sum_k p_k = Tr rho = 1 (sum M_k = I) and p_k >= 0 (M_k, rho PSD)."""
+    g = S.rng(300 + n)
+    rho, _ = O.state_map(S.ginibre(g, 1 << n))
+    p = O.probs_real(rho)
+    assert abs(math.fsum(p.tolist()) - 1.0) <= 1e-13
+    assert p.min() >= 0.0
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_dual_frame_round_trip(n):
+    """The tetrahedral POVM is informationally complete: with dual frame
+    D_a = (I + 3 s_a.sigma)/2, rho = sum_k p_k (x)_i D_{k_i}.  The dual frame
+    is built here entrywise, independent of the oracle's POVM table."""
+    g = S.rng(400 + n)
+    D = [bloch_state(3.0 * O.TETRA_S[a]) for a in range(4)]
+    rho, _ = O.state_map(S.ginibre(g, 1 << n))
+    p = O.probs_real(rho)
+    rec = sum(p[idx] * kron_all([D[a] for a in ks])
+              for idx, ks in enumerate(itertools.product(range(4), repeat=n)))
+    assert np.max(np.abs(rec - rho)) <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# State map (Sec. 2.2.1 Eq. T_matrix; Sec. 3.2 Eq. unified_DP / abs_P)
+# --------------------------------------------------------------------------
+
+def test_state_map_by_loops():
+    g = S.rng(500)
+    d = 4
+    T = S.ginibre(g, d)
+    tau_loop = 0.0
+    for i in range(d):
+        for j in range(d):
+            tau_loop += T[i, j].real ** 2 + T[i, j].imag ** 2
+    Sm = np.zeros((d, d), dtype=np.complex128)
+    for i in range(d):
+        for j in range(d):
+            for k in range(d):
+                Sm[i, j] += T[i, k] * np.conj(T[j, k])
+    rho, tau = O.state_map(T)
+    assert abs(tau - tau_loop) <= 1e-13 * tau
+    assert abs(tau - np.linalg.norm(T) ** 2) <= 1e-13 * tau
+    np.testing.assert_allclose(rho, Sm / tau_loop, atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_state_map_invariants(n):
+    g = S.rng(600 + n)
+    d = 1 << n
+    T = S.ginibre(g, d)
+    rho, _ = O.state_map(T)
+    assert abs(np.trace(rho) - 1.0) <= 1e-14
+    assert np.max(np.abs(rho - rho.conj().T)) <= 1e-16
+    assert np.linalg.eigvalsh(rho).min() >= -1e-15
+    # scale invariance and right-unitary invariance
+    U, _ = np.linalg.qr(S.ginibre(g, d))
+    np.testing.assert_allclose(O.state_map(3.7 * T)[0], rho, atol=1e-15)
+    np.testing.assert_allclose(O.state_map(T @ U)[0], rho, atol=1e-14)
+    np.testing.assert_allclose(O.state_map(np.eye(d))[0], np.eye(d) / d, atol=0)
+
+
+def test_state_map_kron_and_hermitian_reading():
+    """T = T1 (x) T2 gives rho1 (x) rho2; for Hermitian T (the unified map,
+    Eq. unified_DP) T T^dagger = T^dagger T = T^2, so reading 1 is moot there;
+    and at P = 2 the absolute map Q|L|^P Q^dagger/Tr|L|^P equals it
+    (Eq. abs_P), checked with a library eigensolver."""
+    g = S.rng(700)
+    T1, T2 = S.ginibre(g, 2), S.ginibre(g, 4)
+    np.testing.assert_allclose(O.state_map(np.kron(T1, T2))[0],
+                               np.kron(O.state_map(T1)[0], O.state_map(T2)[0]), atol=1e-15)
+    H = S.ginibre(g, 8)
+    H = (H + H.conj().T) / 2
+    rho, _ = O.state_map(H)
+    w, Q = scipy.linalg.eigh(H)
+    absP = (Q * np.abs(w) ** 2) @ Q.conj().T / np.sum(np.abs(w) ** 2)
+    np.testing.assert_allclose(rho, absP, atol=1e-14)
+    np.testing.assert_allclose(rho, (H.conj().T @ H) / np.trace(H.conj().T @ H).real, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Negative log-likelihood (Eq. MLE, Sec. 3.1 loss)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 4, 7])
+def test_nll_maximally_mixed(n):
+    """rho = I/d: every p_k = 4^-N, so L = N ln 4 * sum f."""
+    g = S.rng(800 + n)
+    f = g.integers(0, 5, size=4 ** n).astype(np.float64)
+    p = O.probs_real(np.eye(1 << n, dtype=np.complex128) / (1 << n))
+    want = n * math.log(4.0) * math.fsum(f.tolist())
+    assert abs(O.nll(p, f) - want) <= 1e-13 * want
+    assert abs(O.nll_vec(p, f) - want) <= 1e-13 * want
+
+
+def test_nll_entropy_and_gibbs():
+    """f = p(T) gives L = Shannon entropy H(p) (library routine); for any
+    normalised f, L >= H(f) (Gibbs), with equality iff p = f."""
+    g = S.rng(900)
+    n = 4
+    rho, _ = O.state_map(S.ginibre(g, 1 << n))
+    p = O.probs_real(rho)
+    assert abs(O.nll(p, p) - scipy.stats.entropy(p)) <= 1e-13
+    f = S.multinomial_freqs(g, 1000, p)
+    assert O.nll(p, f) >= scipy.stats.entropy(f) - 1e-14
+    assert O.nll_vec(p, f) == O.nll(p, f)
+
+
+def test_nll_zero_and_nonpositive_terms():
+    p = np.array([0.5, 0.0, 0.25, 0.25])
+    f = np.array([0.5, 0.0, 0.5, 0.0])
+    assert O.nll(p, f) == pytest.approx(-(0.5 * math.log(0.5) + 0.5 * math.log(0.25)), rel=1e-15)
+    f2 = np.array([0.5, 0.1, 0.4, 0.0])
+    assert O.nll(p, f2) == math.inf and O.nll_vec(p, f2) == math.inf
+
+
+# --------------------------------------------------------------------------
+# Adjoint and gradient
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 4, 6])
+def test_adjoint_dot_product(n):
+    """<A(X), y> = Tr(X A^dagger(y)) for complex X and real y, where
+    A(X)_k = Tr(M_k X): the adjoint is pinned to the (pinned) forward map."""
+    g = S.rng(1000 + n)
+    d = 1 << n
+    X = S.ginibre(g, d)
+    y = g.standard_normal(4 ** n)
+    lhs = np.sum(O.probs(X) * y)
+    rhs = np.trace(X @ O.adjoint(y, n))
+    assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+    np.testing.assert_allclose(O.adjoint(np.ones(4 ** n), n), np.eye(d), atol=1e-14)
+    if n <= 4:
+        np.testing.assert_allclose(O.adjoint(y, n), O.adjoint_kron(y, n), atol=1e-14)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (3, 3), (4, 4), (6, 5)])
+def test_gradient_central_differences(n, seed):
+    """Central finite differences of the forward loss on random complex
+    directions E: (L(T+hE) - L(T-hE))/2h = Re<grad, E> (PyTorch convention)."""
+    g = S.rng(1100 + seed)
+    d = 1 << n
+    T = S.ginibre(g, d)
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 5000, O.probs_real(S.depolarised_pure(psi, 0.3)))
+    grad, _ = O.grad_T(T, f)
+    h = 1e-5 * np.linalg.norm(T)
+    for E in S.unit_directions(g, d, 6):
+        fd = (O.loss_of_T(T + h * E, f) - O.loss_of_T(T - h * E, f)) / (2 * h)
+        an = float(np.sum(grad.real * E.real + grad.imag * E.imag))
+        assert abs(fd - an) <= 1e-6 * np.linalg.norm(grad) + 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 5])
+def test_gradient_invariants(n):
+    """L(T U) = L(T) for unitary U and L(cT) = L(T) make T^dagger grad
+    Hermitian (skew part 0) and traceless; grad = 0 when f is proportional
+    to p(T); G' = G + F I with G = sum_k (f_k/p_k) M_k."""
+    g = S.rng(1200 + n)
+    d = 1 << n
+    T = S.ginibre(g, d)
+    f = S.multinomial_freqs(g, 10000, O.probs_real(O.state_map(S.ginibre(g, d))[0]))
+    grad, _ = O.grad_T(T, f)
+    X = T.conj().T @ grad
+    scale = np.max(np.abs(X))
+    assert np.max(np.abs(X - X.conj().T)) <= 1e-13 * scale
+    assert abs(np.trace(X)) <= 1e-13 * scale * d
+    rho, tau = O.state_map(T)
+    p = O.probs_real(rho)
+    g0, _ = O.grad_T(T, 2.5 * p)
+    assert np.max(np.abs(g0)) <= 1e-15 * np.max(np.abs(grad)) * 1e3
+    F = math.fsum(f.tolist())
+    Gp = O.adjoint(O.cotangent(p, f), n)
+    G = O.adjoint(np.where(f != 0, f / p, 0.0), n)
+    np.testing.assert_allclose(Gp, F * np.eye(d) - G, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Fidelities (Sec. 2.3) and the caption closed forms
+# --------------------------------------------------------------------------
+
+def test_caption_closed_forms():
+    g = S.rng(1300)
+    for kind, n, param, value in read_table("caption_closed_forms.txt"):
+        n, param, value = int(n), float(param), float(value)
+        psi = S.haar_vector(g, 1 << n)
+        if kind == "purity":
+            rho = S.depolarised_pure(psi, 1.0 - param)  # p|psi><psi| + (1-p) I/d
+            assert abs(np.trace(rho @ rho).real - value) <= 1e-13
+        else:
+            rho = S.depolarised_pure(psi, param)
+            pure = np.outer(psi, psi.conj())
+            # the matrix-square-root route amplifies rounding in the d-1 zero
+            # eigenvalues of the pure target (sqrt of ~1e-17 each), hence 1e-5
+            assert abs(O.fidelity_q(rho, pure) - value) <= 1e-5
+            assert abs(np.vdot(psi, rho @ psi).real - value) <= 1e-13
+
+
+def test_fidelity_forms():
+    g = S.rng(1400)
+    d = 16
+    rho, _ = O.state_map(S.ginibre(g, d))
+    assert abs(O.fidelity_q(rho, rho) - 1.0) <= 1e-10
+    W = S.ginibre(g, d, 3)
+    target, _ = O.state_map(W)
+    fq = O.fidelity_q(rho, target)
+    # symmetric, low-rank shortcut, and the classical-fidelity upper bound
+    # (Eq. F_CF).  The full square-root route loses ~1e-9 to the 13 zero
+    # eigenvalues of the rank-3 target; the low-rank route has no such loss.
+    assert abs(fq - O.fidelity_q(target, rho)) <= 1e-7
+    assert abs(fq - O.fidelity_q_lowrank(rho, W)) <= 1e-7
+    assert O.fidelity_c(O.probs_real(rho), O.probs_real(target)) >= fq - 1e-12
+    # scipy's sqrtm as an independent route to Eq. F_QF
+    s = scipy.linalg.sqrtm(rho)
+    ref = np.trace(scipy.linalg.sqrtm(s @ target @ s)).real ** 2
+    assert abs(fq - ref) <= 1e-8
+
+
+def test_adam_matches_torch():
+    """The oracle's Adam loop equals torch.optim.Adam (CPU, float64) driven by
+    the oracle gradient, on a complex parameter."""
+    import torch
+    g = S.rng(1500)
+    n = 2
+    T0 = S.ginibre(g, 1 << n)
+    f = S.multinomial_freqs(g, 1000, O.probs_real(S.depolarised_pure(S.haar_vector(g, 4), 0.2)))
+    Tn, losses = O.adam_train(T0, f, steps=5, lr=1e-2)
+    P = torch.nn.Parameter(torch.from_numpy(T0.copy()))
+    opt = torch.optim.Adam([P], lr=1e-2, betas=(0.9, 0.999), eps=1e-12)
+    for _ in range(5):
+        opt.zero_grad()
+        gr, _ = O.grad_T(P.detach().numpy(), f)
+        P.grad = torch.from_numpy(gr)
+        opt.step()
+    np.testing.assert_allclose(P.detach().numpy(), Tn, atol=1e-13)
+    assert losses[-1] < losses[0]
