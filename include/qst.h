@@ -1,0 +1,168 @@
+/*
+ * qst.h -- C ABI of the MI355X (gfx950) likelihood path of neural-network
+ * maximum-likelihood quantum state tomography:
+ *
+ *   T  ->  rho = T T^dagger / Tr(T T^dagger)          (state map)
+ *      ->  p_k = Tr(rho M_k), M_k = M_{k_1} (x) ... (x) M_{k_N}   (POVM map)
+ *      ->  L = -sum_k f_k ln p_k                        (negative log-likelihood)
+ *   and back: dL/dT.
+ *
+ * Source: Wang, Cheng, Li, Chen, "Ultrafast quantum state tomography with
+ * feed-forward neural networks": Sec. 2.1 (Born rule, Eq. MLE), Sec. 2.2.1
+ * (Eq. T_matrix, Eq. MLE_T), Sec. 3.2 (Eq. unified_DP, Eq. abs_P at P = 2),
+ * Sec. 3.3 (product-structured POVM, Eq. PS), Sec. 4.1 (tetrahedral POVM).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - N = n_qubits, d = 2^N, D = 4^N.  1 <= N <= QST_MAX_QUBITS.
+ * - Complex values are interleaved (re, im): complex128 for QST_F64,
+ *   complex64 for QST_F32 and QST_BF16GEMM.  Matrices are row-major with a
+ *   leading dimension (row stride) counted in complex elements, ld >= d.
+ * - Qubit 1 is the most significant bit of the row index r and of the column
+ *   index c of a d x d matrix (the leftmost Kronecker factor).
+ * - Outcome index k = sum_i k_i 4^(N-i), k_i in {0,1,2,3} the single-qubit
+ *   outcome a of M_a.
+ * - Real vectors (p, f) are float64 for QST_F64, float32 otherwise.
+ * - Every pointer named *_dev or described as device memory must be device
+ *   memory; povm_host is host memory.  The caller allocates and owns every
+ *   buffer; the library never frees or keeps a pointer after a call returns.
+ * - stream is a hipStream_t (NULL = the null stream).  Every call only
+ *   enqueues work on that stream and returns without synchronising; scalar
+ *   results are written to device memory, so call sequences can be captured
+ *   into a HIP graph.
+ * - Argument errors are detected on the host before anything is enqueued
+ *   and returned as a status; a failed launch returns QST_ERR_HIP.  No call
+ *   aborts or throws.  qst_last_error() gives a message for the last
+ *   failure on the calling thread.
+ * - ws / ws_bytes: caller-provided device workspace of at least
+ *   qst_workspace_bytes(N, prec, op) bytes (may be NULL when that is 0).
+ *   Its content on entry is ignored.
+ * - Calls on different streams with distinct buffers may run concurrently.
+ */
+#ifndef QST_H
+#define QST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QST_MAX_QUBITS 13
+
+typedef enum {
+  QST_OK = 0,
+  QST_ERR_INVALID_ARG = 1, /* null pointer, N out of range, ld < d, bad POVM */
+  QST_ERR_UNSUPPORTED = 2, /* valid request this build does not implement   */
+  QST_ERR_WORKSPACE = 3,   /* ws_bytes smaller than qst_workspace_bytes()    */
+  QST_ERR_HIP = 4          /* a HIP runtime call or kernel launch failed     */
+} qst_status;
+
+typedef enum {
+  /* complex128 T and rho, float64 p and f; FP64 MFMA products. */
+  QST_F64 = 0,
+  /* complex64 T and rho, float32 p and f; FP32 MFMA products with FP32
+   * accumulation; tau and the log-likelihood sum in FP64. */
+  QST_F32 = 1,
+  /* complex64 storage as QST_F32.  T T^dagger takes T rounded to bfloat16
+   * (round-to-nearest-even) on the BF16 MFMA with FP32 accumulation, and tau
+   * is the FP64 sum over that same rounded T.  The gradient product G' T
+   * uses split bfloat16 operands (hi + lo, three products) so that the
+   * gradient keeps ~1e-4 relative accuracy. */
+  QST_BF16GEMM = 2
+} qst_prec;
+
+typedef enum {
+  QST_OP_STATE_MAP = 0,
+  QST_OP_POVM_PROBS = 1,
+  QST_OP_NLL = 2,
+  QST_OP_NLL_BACKWARD = 3
+} qst_op;
+
+/*
+ * State map (Eq. T_matrix, with rho = T T^dagger / Tr; for Hermitian T this
+ * is the unified map of Eq. unified_DP, and Eq. abs_P at P = 2).
+ *   T      [in]  d x d complex, row stride ldT, device.
+ *   rho    [out] d x d complex, row stride ld_rho, device.  Written in full
+ *                (both triangles; Hermitian to rounding).
+ *   tau_dev[out] one double, device: tau = sum_ij |T_ij|^2 accumulated in
+ *                FP64 (over the bfloat16-rounded T for QST_BF16GEMM).
+ * rho must not overlap T.
+ */
+qst_status qst_state_map(int n_qubits, qst_prec prec, const void* T, int64_t ldT, void* rho,
+                         int64_t ld_rho, double* tau_dev, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/*
+ * Product-POVM map (Born rule, Sec. 2.1; product structure, Sec. 3.3):
+ *   p_k = Tr(rho M_k) for all k in [0, 4^N).
+ *   rho      [in]  d x d Hermitian complex, row stride ld_rho, device.  Only
+ *                  the lower triangle (row >= column) is read; the upper
+ *                  triangle is taken to be its conjugate transpose.
+ *   povm_host[in]  NULL for the paper's tetrahedral POVM (Sec. 4.1), else
+ *                  host array of 4 Hermitian 2 x 2 complex matrices M_0..M_3,
+ *                  32 doubles: M_a[x][y] at (re, im) = [8a + 4x + 2y + {0,1}].
+ *                  Must be Hermitian to 1e-12 (else QST_ERR_INVALID_ARG).
+ *   p        [out] 4^N reals, device.
+ */
+qst_status qst_povm_probs(int n_qubits, qst_prec prec, const void* rho, int64_t ld_rho,
+                          const double* povm_host, void* p, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/*
+ * Negative log-likelihood (Eq. MLE; loss of Sec. 3.1):
+ *   L = -sum_{k: f_k != 0} f_k ln p_k, accumulated in FP64.
+ *   p, f     [in]  4^N reals each, device.  f is used as given (counts or
+ *                  frequencies; F = sum f is not assumed to be 1).
+ *   nll_dev  [out] two doubles, device: nll_dev[0] = L, nll_dev[1] = F.
+ *   bad_dev  [out] two uint64, device, or NULL: bad_dev[0] = number of k
+ *                  with f_k > 0 and not p_k > 0 (such a term makes L = +inf),
+ *                  bad_dev[1] = number of NaN entries in p or f.
+ * The reduction order is fixed, so results are bitwise reproducible.
+ */
+qst_status qst_nll(int n_qubits, qst_prec prec, const void* p, const void* f, double* nll_dev,
+                   unsigned long long* bad_dev, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of the whole chain (derived from Eq. MLE_T with rho = T T^dagger/tau):
+ *   g'_k = F - f_k / p_k (g'_k = F where f_k = 0),  G' = sum_k g'_k M_k,
+ *   gradT = s * (2 / tau) * G' T
+ * which is dL/dRe T + i dL/dIm T (the PyTorch convention for complex
+ * parameters), times s = *upstream_dev (1 if upstream_dev is NULL).
+ *   T        [in]  d x d complex, row stride ldT, device (the same T as the
+ *                  forward call).
+ *   f        [in]  4^N reals, device.
+ *   p        [in]  4^N reals from the forward call, device; or NULL, in
+ *                  which case rho and p are recomputed from T inside this
+ *                  call (nothing of length 4^N needs to survive the forward).
+ *   tau_dev  [in]  the tau written by qst_state_map for this T, device; may
+ *                  be NULL only when p is NULL (then tau is recomputed).
+ *   povm_host[in]  as in qst_povm_probs.
+ *   upstream_dev[in] one double, device, or NULL.
+ *   gradT    [out] d x d complex, row stride ldG, device; must not overlap T.
+ */
+qst_status qst_nll_backward(int n_qubits, qst_prec prec, const void* T, int64_t ldT,
+                            const void* f, const void* p, const double* tau_dev,
+                            const double* povm_host, const double* upstream_dev, void* gradT,
+                            int64_t ldG, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace in bytes needed by op (a qst_op) at (n_qubits, prec); 0 for an
+ * invalid request. */
+size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op);
+
+/* Static string for a status code. */
+const char* qst_status_string(qst_status s);
+
+/* Message describing the last non-OK status returned on this thread ("" if
+ * none).  Valid until the next call on the same thread. */
+const char* qst_last_error(void);
+
+/* Library version string. */
+const char* qst_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QST_H */

@@ -1,0 +1,193 @@
+"""MI355X (gfx950) likelihood path of neural-network maximum-likelihood
+quantum state tomography (Wang, Cheng, Li, Chen): T -> rho = T T^dagger /
+Tr -> p_k = Tr(rho M_k) over the per-qubit tetrahedral product POVM ->
+L = -sum f_k ln p_k, and the hand-written adjoint back to dL/dT.
+
+This module only marshals torch tensors into the C ABI of libqst.so
+(include/qst.h); every step of the path runs in the library's HIP kernels on
+torch's current stream.  torch supplies device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_NLL, QST_OP_NLL_BACKWARD,
+                   QST_OP_POVM_PROBS, QST_OP_STATE_MAP, QstError, workspace_bytes)
+
+__all__ = [
+    "PRECISIONS", "state_map", "povm_probs", "nll", "nll_backward", "likelihood", "LikelihoodFn",
+    "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
+]
+
+PRECISIONS = {"f64": QST_F64, "f32": QST_F32, "bf16": QST_BF16GEMM}
+_NAMES = {v: k for k, v in PRECISIONS.items()}
+
+
+def _prec(dtype: torch.dtype, prec) -> int:
+    if prec is None:
+        if dtype == torch.complex128:
+            return QST_F64
+        if dtype == torch.complex64:
+            return QST_F32
+        raise TypeError(f"T must be complex128 or complex64, got {dtype}")
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    want = torch.complex128 if p == QST_F64 else torch.complex64
+    if dtype != want:
+        raise TypeError(f"precision {_NAMES.get(p, p)} needs {want} storage, got {dtype}")
+    return p
+
+
+def real_dtype(prec: int) -> torch.dtype:
+    return torch.float64 if prec == QST_F64 else torch.float32
+
+
+def complex_dtype(prec: int) -> torch.dtype:
+    return torch.complex128 if prec == QST_F64 else torch.complex64
+
+
+def _qubits(d: int) -> int:
+    n = d.bit_length() - 1
+    if d != 1 << n or not 1 <= n <= QST_MAX_QUBITS:
+        raise ValueError(f"matrix side {d} is not 2^N with 1 <= N <= {QST_MAX_QUBITS}")
+    return n
+
+
+def _matrix(x: torch.Tensor, name: str) -> tuple[int, int]:
+    if x.dim() != 2 or x.shape[0] != x.shape[1]:
+        raise ValueError(f"{name} must be a square matrix, got shape {tuple(x.shape)}")
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if x.stride(1) != 1 or x.stride(0) < x.shape[1]:
+        raise ValueError(f"{name} must be row-major with unit column stride")
+    return _qubits(x.shape[0]), x.stride(0)
+
+
+def _vector(x: torch.Tensor, name: str, n: int, dtype: torch.dtype) -> None:
+    if not x.is_cuda or x.dtype != dtype or not x.is_contiguous() or x.numel() != 4 ** n:
+        raise ValueError(f"{name} must be a contiguous GPU {dtype} vector of 4^{n} entries")
+
+
+def _stream(dev: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _workspace(n: int, prec: int, op: int, dev: torch.device):
+    nbytes = workspace_bytes(n, prec, op)
+    if nbytes == 0:
+        return None, 0
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev), nbytes
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _povm_arg(povm):
+    """None (tetrahedral) or a host array of 32 doubles from a (4, 2, 2) complex array."""
+    if povm is None:
+        return None
+    m = torch.as_tensor(povm).to(torch.complex128).reshape(4, 2, 2)
+    flat = torch.view_as_real(m.contiguous()).reshape(-1).tolist()
+    return (ctypes.c_double * 32)(*flat)
+
+
+def state_map(T: torch.Tensor, prec=None):
+    """rho = T T^dagger / tau and tau (a 0-dim float64 device tensor)."""
+    n, ld = _matrix(T, "T")
+    p = _prec(T.dtype, prec)
+    rho = torch.empty(T.shape, dtype=T.dtype, device=T.device)
+    tau = torch.empty((), dtype=torch.float64, device=T.device)
+    ws, nb = _workspace(n, p, QST_OP_STATE_MAP, T.device)
+    _lib.check(_lib.lib().qst_state_map(n, p, T.data_ptr(), ld, rho.data_ptr(), rho.stride(0), tau.data_ptr(),
+                                        _ptr(ws), nb, _stream(T.device)), "qst_state_map")
+    return rho, tau
+
+
+def povm_probs(rho: torch.Tensor, prec=None, povm=None) -> torch.Tensor:
+    """p_k = Tr(rho M_k) for all 4^N outcomes (lower triangle of rho read)."""
+    n, ld = _matrix(rho, "rho")
+    p = _prec(rho.dtype, prec)
+    out = torch.empty(4 ** n, dtype=real_dtype(p), device=rho.device)
+    ws, nb = _workspace(n, p, QST_OP_POVM_PROBS, rho.device)
+    _lib.check(_lib.lib().qst_povm_probs(n, p, rho.data_ptr(), ld, _povm_arg(povm), out.data_ptr(), _ptr(ws), nb,
+                                         _stream(rho.device)), "qst_povm_probs")
+    return out
+
+
+def nll(p: torch.Tensor, f: torch.Tensor, prec=None):
+    """(out, bad): out[0] = L, out[1] = F = sum f (float64); bad = uint64 counts
+    [f>0 with p<=0, NaN entries] stored as int64."""
+    n = (p.numel().bit_length() - 1) // 2
+    pr = QST_F64 if (prec is None and p.dtype == torch.float64) else (
+        QST_F32 if prec is None else (PRECISIONS[prec] if isinstance(prec, str) else int(prec)))
+    _vector(p, "p", n, real_dtype(pr))
+    _vector(f, "f", n, real_dtype(pr))
+    out = torch.empty(2, dtype=torch.float64, device=p.device)
+    bad = torch.empty(2, dtype=torch.int64, device=p.device)
+    ws, nb = _workspace(n, pr, QST_OP_NLL, p.device)
+    _lib.check(_lib.lib().qst_nll(n, pr, p.data_ptr(), f.data_ptr(), out.data_ptr(), bad.data_ptr(), _ptr(ws), nb,
+                                  _stream(p.device)), "qst_nll")
+    return out, bad
+
+
+def nll_backward(T: torch.Tensor, f: torch.Tensor, p: torch.Tensor | None, tau: torch.Tensor | None, prec=None,
+                 povm=None, upstream: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dRe T + i dL/dIm T (times *upstream).  p=None recomputes rho and p."""
+    n, ld = _matrix(T, "T")
+    pr = _prec(T.dtype, prec)
+    _vector(f, "f", n, real_dtype(pr))
+    if p is not None:
+        _vector(p, "p", n, real_dtype(pr))
+        if tau is None:
+            raise ValueError("tau is required when p is given")
+    for name, t in (("tau", tau), ("upstream", upstream)):
+        if t is not None and (t.dtype != torch.float64 or t.numel() != 1 or not t.is_cuda):
+            raise ValueError(f"{name} must be a one-element float64 GPU tensor")
+    grad = torch.empty(T.shape, dtype=T.dtype, device=T.device)
+    ws, nb = _workspace(n, pr, QST_OP_NLL_BACKWARD, T.device)
+    _lib.check(_lib.lib().qst_nll_backward(n, pr, T.data_ptr(), ld, f.data_ptr(), _ptr(p), _ptr(tau),
+                                           _povm_arg(povm), _ptr(upstream), grad.data_ptr(), grad.stride(0),
+                                           _ptr(ws), nb, _stream(T.device)), "qst_nll_backward")
+    return grad
+
+
+class LikelihoodFn(torch.autograd.Function):
+    """L(T) = -sum_k f_k ln Tr(M_k T T^dagger / Tr(T T^dagger)) with the
+    hand-written adjoint.  recompute=True keeps only T, f and tau for the
+    backward pass (rho and p are rebuilt there)."""
+
+    @staticmethod
+    def forward(ctx, T, f, prec, recompute, povm):
+        rho, tau = state_map(T, prec)
+        p = povm_probs(rho, prec, povm)
+        del rho
+        out, _ = nll(p, f, _prec(T.dtype, prec))
+        ctx.prec = prec
+        ctx.povm = povm
+        ctx.recompute = bool(recompute)
+        if ctx.recompute:
+            ctx.save_for_backward(T, f, tau)
+        else:
+            ctx.save_for_backward(T, f, tau, p)
+        return out[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        saved = ctx.saved_tensors
+        T, f, tau = saved[0], saved[1], saved[2]
+        p = None if ctx.recompute else saved[3]
+        up = g.detach().to(torch.float64).reshape(1).contiguous()
+        grad = nll_backward(T, f, p, None if p is None else tau, ctx.prec, ctx.povm, up)
+        return grad, None, None, None, None
+
+
+def likelihood(T: torch.Tensor, f: torch.Tensor, prec=None, recompute: bool | None = None, povm=None):
+    """Differentiable negative log-likelihood (0-dim float64 tensor).  By
+    default the probability vector is recomputed in the backward pass at
+    N >= 12 and kept from the forward pass below that."""
+    if recompute is None:
+        recompute = _qubits(T.shape[-1]) >= 12
+    return LikelihoodFn.apply(T, f, prec, recompute, povm)

@@ -1,0 +1,67 @@
+"""ctypes loader for libqst.so, the gfx950 likelihood-path library.
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqst.so")
+
+QST_OK, QST_ERR_INVALID_ARG, QST_ERR_UNSUPPORTED, QST_ERR_WORKSPACE, QST_ERR_HIP = range(5)
+QST_F64, QST_F32, QST_BF16GEMM = 0, 1, 2
+QST_OP_STATE_MAP, QST_OP_POVM_PROBS, QST_OP_NLL, QST_OP_NLL_BACKWARD = 0, 1, 2, 3
+QST_MAX_QUBITS = 13
+
+#: Every symbol include/qst.h declares, with (restype, argtypes).
+_vp, _i64, _sz, _int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int
+SIGNATURES = {
+    "qst_state_map": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "qst_povm_probs": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "qst_nll": (_int, [_int, _int, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qst_nll_backward": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
+    "qst_workspace_bytes": (_sz, [_int, _int, _int]),
+    "qst_status_string": (ctypes.c_char_p, [_int]),
+    "qst_last_error": (ctypes.c_char_p, []),
+    "qst_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class QstError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {status_string(status)}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (loaded on first use)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run `python -m paper_2207_05341_amd.build` "
+                "(or __graft_entry__.build()) first.  There is no non-HIP fallback.")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().qst_status_string(status).decode()
+
+
+def check(status: int, where: str) -> None:
+    if status != QST_OK:
+        raise QstError(status, where, lib().qst_last_error().decode())
+
+
+def workspace_bytes(n: int, prec: int, op: int) -> int:
+    return int(lib().qst_workspace_bytes(n, prec, op))

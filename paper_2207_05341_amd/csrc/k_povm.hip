@@ -1,0 +1,332 @@
+// Product-POVM map p_k = Tr(rho M_k), M_k = M_{k_1} (x) ... (x) M_{k_N}
+// (Born rule, Sec. 2.1; product structure, Sec. 3.3) and its adjoint
+// G = sum_k g_k M_k, as a sequence of passes of per-qubit 4 x 4 mode
+// contractions.
+//
+// Data view.  A d x d matrix X is a tensor over per-qubit pair indices
+// m_i = 2 r_i + c_i (r_i, c_i the row/column bits of qubit i; qubit 1 is the
+// most significant bit).  For one qubit, Tr(M_a X) = sum_m W[a][m] X_m with
+// W[a][2r+c] = (M_a)_{c,r}; the full map applies W along every qubit axis,
+// and the adjoint applies V[m][a] = (M_a)_{r,c}.  Each pass loads, for one
+// workgroup, all 4^g pair values of a group of g qubits (for J consecutive
+// values of the already-contracted outcome digits) into LDS, contracts the g
+// axes in place, and writes the result; see qst_plan.h for the pass plan.
+//
+// Hermitian symmetry.  rho, every forward intermediate and every adjoint
+// intermediate are Hermitian in the not-yet-contracted (row, column) bits,
+// so only entries with row >= column are ever read or written; the others
+// are the conjugates.  The forward map therefore reads only the lower
+// triangle of rho.
+//
+// For the paper's tetrahedral POVM (Sec. 4.1), M_a = (I + s_a.sigma)/4 with
+// s_a = (+-1, +-1, +-1)/sqrt(3), the 4 x 4 contraction factors as
+// (1/4) H diag(1, t, t, t) U with U x = (x0+x3, x1+x2, i(x1-x2), x0-x3),
+// H a 4 x 4 Hadamard matrix and t = 1/sqrt(3); the kernels use that form
+// (8 complex adds and 3 real-scalar products per 4 values) instead of a
+// generic complex 4 x 4 product.
+#include "qst_device.h"
+#include "qst_kernels.h"
+
+namespace qst {
+
+namespace {
+
+struct ModeMatrix {
+  double a[32];  // 4 x 4 complex, row-major (re, im)
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cadd(Cx<R> x, Cx<R> y) { return {x.re + y.re, x.im + y.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> csub(Cx<R> x, Cx<R> y) { return {x.re - y.re, x.im - y.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> cscale(Cx<R> x, R s) { return {x.re * s, x.im * s}; }
+// i * x
+template <typename R>
+__device__ __forceinline__ Cx<R> cmuli(Cx<R> x) { return {-x.im, x.re}; }
+
+// Forward tetrahedral contraction of one qubit: x[m] -> y[a] = sum_m W[a][m] x[m].
+template <typename R>
+__device__ __forceinline__ void tetra_fwd(Cx<R> x[4]) {
+  const R q = R(0.25), t4 = R(0.14433756729740644113);  // 1/4, 1/(4 sqrt 3)
+  const Cx<R> a = cscale(cadd(x[0], x[3]), q);
+  const Cx<R> b = cscale(cadd(x[1], x[2]), t4);
+  const Cx<R> c = cscale(cmuli(csub(x[1], x[2])), t4);
+  const Cx<R> e = cscale(csub(x[0], x[3]), t4);
+  const Cx<R> P = cadd(b, c), Q = csub(b, c);
+  const Cx<R> ape = cadd(a, e), ame = csub(a, e);
+  x[0] = cadd(ape, P);
+  x[1] = csub(ape, P);
+  x[2] = csub(ame, Q);
+  x[3] = cadd(ame, Q);
+}
+
+// Adjoint tetrahedral contraction: g[a] -> x[m] = sum_a V[m][a] g[a].
+template <typename R>
+__device__ __forceinline__ void tetra_adj(Cx<R> x[4]) {
+  const R q = R(0.25), t4 = R(0.14433756729740644113);
+  const Cx<R> s01 = cadd(x[0], x[1]), d01 = csub(x[0], x[1]);
+  const Cx<R> s23 = cadd(x[2], x[3]), d23 = csub(x[2], x[3]);
+  const Cx<R> v0 = cscale(cadd(s01, s23), q);   // g0+g1+g2+g3
+  const Cx<R> v1 = cscale(csub(d01, d23), t4);  // g0-g1-g2+g3
+  const Cx<R> v2 = cscale(cadd(d01, d23), t4);  // g0-g1+g2-g3
+  const Cx<R> v3 = cscale(csub(s01, s23), t4);  // g0+g1-g2-g3
+  const Cx<R> iv2 = cmuli(v2);
+  x[0] = cadd(v0, v3);
+  x[1] = csub(v1, iv2);
+  x[2] = cadd(v1, iv2);
+  x[3] = csub(v0, v3);
+}
+
+template <typename R>
+__device__ __forceinline__ void generic4(Cx<R> x[4], const ModeMatrix& A) {
+  Cx<R> y[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    R re = 0, im = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const R ar = R(A.a[2 * (4 * i + j)]), ai = R(A.a[2 * (4 * i + j) + 1]);
+      re += ar * x[j].re - ai * x[j].im;
+      im += ar * x[j].im + ai * x[j].re;
+    }
+    y[i] = {re, im};
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x[i] = y[i];
+}
+
+// Insert a zero bit at position b of x.
+__device__ __forceinline__ int ins0(int x, int b) { return ((x >> b) << (b + 1)) | (x & ((1 << b) - 1)); }
+
+// Bits of r and c interleaved, r above c: k = sum_b (2 r_b + c_b) 4^b.
+__device__ __forceinline__ int interleave(int r, int c, int g) {
+  int k = 0;
+  for (int b = 0; b < g; ++b) k |= (((r >> b) & 1) << (2 * b + 1)) | (((c >> b) & 1) << (2 * b));
+  return k;
+}
+__device__ __forceinline__ void deinterleave(int k, int g, int& r, int& c) {
+  r = 0;
+  c = 0;
+  for (int b = 0; b < g; ++b) {
+    r |= ((k >> (2 * b + 1)) & 1) << b;
+    c |= ((k >> (2 * b)) & 1) << b;
+  }
+}
+
+struct PassArgs {
+  const void* in;   // forward: rho (MATSIDE) or intermediate; adjoint: intermediate
+  void* out;        // forward: intermediate or p (PSIDE); adjoint: intermediate or G' (MATSIDE)
+  const void* p;    // adjoint PSIDE: probabilities
+  const void* f;    // adjoint PSIDE: frequencies
+  const double* F;  // adjoint PSIDE: F = sum f
+  int64_t ld;       // row stride of the matrix side
+  int n, U, g, J;
+};
+
+// In-place contraction of the g qubit axes held in LDS.
+template <typename R, bool ADJ, bool TETRA>
+__device__ __forceinline__ void contract_group(Cx<R>* buf, int g, int J, const ModeMatrix& A) {
+  const int groups = (1 << (2 * (g - 1))) * J;
+  for (int b = 0; b < g; ++b) {
+    for (int h = threadIdx.x; h < groups; h += blockDim.x) {
+      const int j = h % J;
+      const int rc = h / J;
+      const int c0 = ins0(rc & ((1 << (g - 1)) - 1), b);
+      const int r0 = ins0(rc >> (g - 1), b);
+      int pos[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int r = r0 | ((m >> 1) << b), c = c0 | ((m & 1) << b);
+        pos[m] = ((r << g) | c) * J + j;
+      }
+      Cx<R> x[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) x[m] = buf[pos[m]];
+      if constexpr (TETRA) {
+        if constexpr (ADJ) tetra_adj(x); else tetra_fwd(x);
+      } else {
+        generic4(x, A);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) buf[pos[m]] = x[m];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
+__global__ __launch_bounds__(256) void povm_fwd_pass(PassArgs a, ModeMatrix A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
+  const int g = a.g, J = a.J, U = a.U, n = a.n;
+  const int Up = U - g;
+  const int64_t kd = int64_t(1) << (2 * (n - U));
+  const int64_t nchunks = kd / J;
+  const int64_t bid = blockIdx.x;
+  const int64_t ch = bid % nchunks;
+  int Rhi, Chi;
+  tri_decode(bid / nchunks, Rhi, Chi);
+  const int64_t kd0 = ch * J;
+  const int tile = 1 << (2 * g);
+  const int elems = tile * J;
+  const int gm = (1 << g) - 1;
+
+  const Cx<R>* in = static_cast<const Cx<R>*>(a.in);
+  for (int e = threadIdx.x; e < elems; e += blockDim.x) {
+    const int j = e % J;
+    const int rc = e / J;
+    const int c = rc & gm, r = rc >> g;
+    const int64_t Rr = (int64_t(Rhi) << g) | r, Cr = (int64_t(Chi) << g) | c;
+    const bool mirror = Rr < Cr;
+    const int64_t rr = mirror ? Cr : Rr, cc = mirror ? Rr : Cr;
+    Cx<R> v;
+    if constexpr (MATSIDE) {
+      v = in[rr * a.ld + cc];
+    } else {
+      v = in[((rr << U) | cc) * kd + kd0 + j];
+    }
+    if (mirror) v.im = -v.im;
+    buf[e] = v;
+  }
+  __syncthreads();
+  contract_group<R, false, TETRA>(buf, g, J, A);
+
+  for (int e = threadIdx.x; e < elems; e += blockDim.x) {
+    const int j = e % J;
+    const int kg = e / J;
+    int r, c;
+    deinterleave(kg, g, r, c);
+    const Cx<R> v = buf[((r << g) | c) * J + j];
+    if constexpr (PSIDE) {
+      static_cast<R*>(a.out)[int64_t(kg) * kd + kd0 + j] = v.re;
+    } else {
+      const int64_t base = ((int64_t(Rhi) << Up) | Chi) * (kd * tile);
+      static_cast<Cx<R>*>(a.out)[base + int64_t(kg) * kd + kd0 + j] = v;
+    }
+  }
+}
+
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
+__global__ __launch_bounds__(256) void povm_adj_pass(PassArgs a, ModeMatrix A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem_raw);
+  const int g = a.g, J = a.J, U = a.U, n = a.n;
+  const int Up = U - g;
+  const int64_t kd = int64_t(1) << (2 * (n - U));
+  const int64_t nchunks = kd / J;
+  const int64_t bid = blockIdx.x;
+  const int64_t ch = bid % nchunks;
+  int Rhi, Chi;
+  tri_decode(bid / nchunks, Rhi, Chi);
+  const int64_t kd0 = ch * J;
+  const int tile = 1 << (2 * g);
+  const int elems = tile * J;
+  const int gm = (1 << g) - 1;
+
+  double F = 0.0;
+  if constexpr (PSIDE) F = *a.F;
+  for (int e = threadIdx.x; e < elems; e += blockDim.x) {
+    const int j = e % J;
+    const int kg = e / J;
+    int r, c;
+    deinterleave(kg, g, r, c);
+    Cx<R> v;
+    if constexpr (PSIDE) {
+      // cotangent g'_k = F - f_k / p_k (F where f_k = 0), in FP64
+      const int64_t k = int64_t(kg) * kd + kd0 + j;
+      const double fk = double(static_cast<const R*>(a.f)[k]);
+      double gk = F;
+      if (fk != 0.0) gk = F - fk / double(static_cast<const R*>(a.p)[k]);
+      v = {R(gk), R(0)};
+    } else {
+      const int64_t base = ((int64_t(Rhi) << Up) | Chi) * (kd * tile);
+      v = static_cast<const Cx<R>*>(a.in)[base + int64_t(kg) * kd + kd0 + j];
+    }
+    buf[((r << g) | c) * J + j] = v;
+  }
+  __syncthreads();
+  contract_group<R, true, TETRA>(buf, g, J, A);
+
+  Cx<R>* out = static_cast<Cx<R>*>(a.out);
+  for (int e = threadIdx.x; e < elems; e += blockDim.x) {
+    const int j = e % J;
+    const int rc = e / J;
+    const int c = rc & gm, r = rc >> g;
+    const int64_t Rr = (int64_t(Rhi) << g) | r, Cr = (int64_t(Chi) << g) | c;
+    if (Rr < Cr) continue;  // upper triangle: the conjugate of a stored entry
+    const Cx<R> v = buf[e];
+    if constexpr (MATSIDE) {
+      out[Rr * a.ld + Cr] = v;
+      if (Rr != Cr) out[Cr * a.ld + Rr] = Cx<R>{v.re, -v.im};
+    } else {
+      out[((Rr << U) | Cr) * kd + kd0 + j] = v;
+    }
+  }
+}
+
+template <typename R, bool ADJ, bool TETRA>
+hipError_t launch_pass_t(const PassArgs& a, const ModeMatrix& A, bool matside, bool pside,
+                         int64_t blocks, hipStream_t s) {
+  const size_t lds = (size_t(1) << (2 * a.g)) * size_t(a.J) * sizeof(Cx<R>);
+  const dim3 grid{unsigned(blocks), 1, 1}, block{256, 1, 1};
+#define QST_POVM_LAUNCH(M, P)                                                              \
+  do {                                                                                     \
+    if constexpr (ADJ) povm_adj_pass<R, TETRA, M, P><<<grid, block, lds, s>>>(a, A);        \
+    else povm_fwd_pass<R, TETRA, M, P><<<grid, block, lds, s>>>(a, A);                      \
+  } while (0)
+  if (matside && pside) QST_POVM_LAUNCH(true, true);
+  else if (matside) QST_POVM_LAUNCH(true, false);
+  else if (pside) QST_POVM_LAUNCH(false, true);
+  else QST_POVM_LAUNCH(false, false);
+#undef QST_POVM_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const double* mode_matrix,
+                       bool tetra, const void* mat, int64_t ld, void* pvec, const void* fvec,
+                       const double* F_dev, void* inter0, void* inter1, hipStream_t s) {
+  ModeMatrix A;
+  for (int i = 0; i < 32; ++i) A.a[i] = mode_matrix[i];
+  void* bufs[2] = {inter0, inter1};
+  const int P = pl.passes;
+  for (int step = 0; step < P; ++step) {
+    const int j = adjoint ? (P - 1 - step) : step;
+    PassArgs a{};
+    a.n = pl.n;
+    a.U = pl.U[j];
+    a.g = pl.g[j];
+    a.J = pl.J[j];
+    a.ld = ld;
+    const bool matside = (j == 0), pside = (j == P - 1);
+    if (!adjoint) {
+      a.in = matside ? mat : bufs[(j - 1) & 1];
+      a.out = pside ? pvec : bufs[j & 1];
+    } else {
+      a.in = pside ? nullptr : bufs[j & 1];
+      a.out = matside ? const_cast<void*>(mat) : bufs[(j - 1) & 1];
+      a.p = pvec;
+      a.f = fvec;
+      a.F = F_dev;
+    }
+    const int64_t blocks = povm_pass_blocks(pl, j);
+    hipError_t e;
+    if (prec == QST_F64) {
+      if (adjoint) e = tetra ? launch_pass_t<double, true, true>(a, A, matside, pside, blocks, s)
+                             : launch_pass_t<double, true, false>(a, A, matside, pside, blocks, s);
+      else e = tetra ? launch_pass_t<double, false, true>(a, A, matside, pside, blocks, s)
+                     : launch_pass_t<double, false, false>(a, A, matside, pside, blocks, s);
+    } else {
+      if (adjoint) e = tetra ? launch_pass_t<float, true, true>(a, A, matside, pside, blocks, s)
+                             : launch_pass_t<float, true, false>(a, A, matside, pside, blocks, s);
+      else e = tetra ? launch_pass_t<float, false, true>(a, A, matside, pside, blocks, s)
+                     : launch_pass_t<float, false, false>(a, A, matside, pside, blocks, s);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace qst

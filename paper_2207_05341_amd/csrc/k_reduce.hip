@@ -1,0 +1,163 @@
+// FP64 reductions of the likelihood path, deterministic two-stage form:
+//   tau = sum_ij |T_ij|^2                 (denominator of Eq. T_matrix)
+//   L = -sum_{f_k != 0} f_k ln p_k, F = sum_k f_k   (Eq. MLE / loss, Sec. 3.1)
+// Stage 1: block b of kReduceBlocks owns the contiguous element range
+// [b*chunk, (b+1)*chunk) and reduces it in a fixed order (strided per thread,
+// then a wave64 shuffle tree and a 4-wave combine).  Stage 2: one block
+// reduces the partials in a fixed order.  No floating-point atomics, so the
+// results are bitwise reproducible run to run.
+#include "qst_device.h"
+#include "qst_kernels.h"
+#include "qst_plan.h"
+
+namespace qst {
+
+namespace {
+
+template <typename R, bool ROUND>
+__global__ __launch_bounds__(256) void tau_partial_kernel(const Cx<R>* __restrict__ T, int64_t ld,
+                                                          int n, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int64_t d = int64_t(1) << n;
+  const int64_t total = d * d;
+  const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t beg = int64_t(blockIdx.x) * chunk;
+  const int64_t end = beg + chunk < total ? beg + chunk : total;
+  double acc = 0.0;
+  for (int64_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
+    const int64_t r = e >> n, c = e & (d - 1);
+    const Cx<R> v = T[r * ld + c];
+    double x = double(v.re), y = double(v.im);
+    if constexpr (ROUND) {
+      x = double(bf16_value(float(v.re)));
+      y = double(bf16_value(float(v.im)));
+    }
+    acc += x * x + y * y;
+  }
+  const double s = block_sum256(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// One 256-thread block: out[i] = sum_b partials[i*nb + b] for i < nsum.
+__global__ __launch_bounds__(256) void finish_sums_kernel(const double* __restrict__ partials, int nb,
+                                                          int nsum, double* __restrict__ out) {
+  __shared__ double red[4];
+  for (int i = 0; i < nsum; ++i) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partials[int64_t(i) * nb + b];
+    const double s = block_sum256(acc, red);
+    if (threadIdx.x == 0) out[i] = s;
+  }
+}
+
+// Stage 1 of the NLL: partials laid out [4][nb]: L, F, bad0, bad1.
+template <typename R, bool WITH_P>
+__global__ __launch_bounds__(256) void nll_partial_kernel(const R* __restrict__ p,
+                                                          const R* __restrict__ f, int64_t D,
+                                                          double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int nb = gridDim.x;
+  const int64_t chunk = (D + nb - 1) / nb;
+  const int64_t beg = int64_t(blockIdx.x) * chunk;
+  const int64_t end = beg + chunk < D ? beg + chunk : D;
+  double L = 0.0, F = 0.0, bad0 = 0.0, bad1 = 0.0;
+  for (int64_t k = beg + threadIdx.x; k < end; k += blockDim.x) {
+    const double fk = double(f[k]);
+    F += fk;
+    if constexpr (WITH_P) {
+      const double pk = double(p[k]);
+      if (fk != 0.0) {
+        if (pk > 0.0) {
+          L -= fk * log(pk);
+        } else {
+          bad0 += 1.0;
+        }
+      }
+      if (pk != pk || fk != fk) bad1 += 1.0;
+    }
+  }
+  double s = block_sum256(L, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  s = block_sum256(F, red);
+  if (threadIdx.x == 0) partials[nb + blockIdx.x] = s;
+  if constexpr (WITH_P) {
+    s = block_sum256(bad0, red);
+    if (threadIdx.x == 0) partials[2 * nb + blockIdx.x] = s;
+    s = block_sum256(bad1, red);
+    if (threadIdx.x == 0) partials[3 * nb + blockIdx.x] = s;
+  }
+}
+
+// Stage 2 of the NLL: nll[0] = L (+inf if a bad term, NaN if a NaN input),
+// nll[1] = F; bad[0], bad[1] counts.
+__global__ __launch_bounds__(256) void nll_finish_kernel(const double* __restrict__ partials, int nb,
+                                                         double* __restrict__ nll,
+                                                         unsigned long long* __restrict__ bad) {
+  __shared__ double red[4];
+  double sums[4];
+  for (int i = 0; i < 4; ++i) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partials[int64_t(i) * nb + b];
+    sums[i] = block_sum256(acc, red);
+  }
+  if (threadIdx.x == 0) {
+    double L = sums[0];
+    if (sums[1] != sums[1] || sums[3] > 0.0) {
+      L = __builtin_nan("");
+    } else if (sums[2] > 0.0) {
+      L = __builtin_inf();
+    }
+    nll[0] = L;
+    nll[1] = sums[1];
+    if (bad) {
+      bad[0] = (unsigned long long)sums[2];
+      bad[1] = (unsigned long long)sums[3];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
+                      double* tau_dev, hipStream_t s) {
+  const int nb = kReduceBlocks;
+  if (prec == QST_F64) {
+    tau_partial_kernel<double, false><<<nb, 256, 0, s>>>(static_cast<const Cx<double>*>(T), ld, n, partials);
+  } else if (prec == QST_F32) {
+    tau_partial_kernel<float, false><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
+  } else {
+    tau_partial_kernel<float, true><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
+  }
+  finish_sums_kernel<<<1, 256, 0, s>>>(partials, nb, 1, tau_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double* partials,
+                      double* nll_dev, unsigned long long* bad_dev, hipStream_t s) {
+  const int nb = kReduceBlocks;
+  const int64_t D = int64_t(1) << (2 * n);
+  if (prec == QST_F64) {
+    nll_partial_kernel<double, true><<<nb, 256, 0, s>>>(static_cast<const double*>(p),
+                                                        static_cast<const double*>(f), D, partials);
+  } else {
+    nll_partial_kernel<float, true><<<nb, 256, 0, s>>>(static_cast<const float*>(p),
+                                                       static_cast<const float*>(f), D, partials);
+  }
+  nll_finish_kernel<<<1, 256, 0, s>>>(partials, nb, nll_dev, bad_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_fsum(qst_prec prec, const void* f, int n, double* partials, double* F_dev,
+                       hipStream_t s) {
+  const int nb = kReduceBlocks;
+  const int64_t D = int64_t(1) << (2 * n);
+  if (prec == QST_F64) {
+    nll_partial_kernel<double, false><<<nb, 256, 0, s>>>(nullptr, static_cast<const double*>(f), D, partials);
+  } else {
+    nll_partial_kernel<float, false><<<nb, 256, 0, s>>>(nullptr, static_cast<const float*>(f), D, partials);
+  }
+  finish_sums_kernel<<<1, 256, 0, s>>>(partials + nb, nb, 1, F_dev);
+  return hipGetLastError();
+}
+
+}  // namespace qst

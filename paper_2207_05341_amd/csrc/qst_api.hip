@@ -1,0 +1,137 @@
+// extern "C" entry points of libqst: validation, workspace carving and
+// kernel dispatch for the likelihood path.  See include/qst.h for the
+// contract of each call.
+#include <string>
+
+#include "qst_kernels.h"
+#include "qst_plan.h"
+
+namespace {
+
+using namespace qst;
+
+inline unsigned char* ws_at(void* ws, size_t off) { return static_cast<unsigned char*>(ws) + off; }
+
+qst_status fail(qst_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+qst_status hip_fail(hipError_t e, const char* what) {
+  return fail(QST_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+qst_status qst_state_map(int n, qst_prec prec, const void* T, int64_t ldT, void* rho, int64_t ld_rho,
+                         double* tau_dev, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(rho, ld_rho, n, "rho", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(tau_dev, "tau_dev", msg)) != QST_OK) return fail(st, msg);
+  const WsLayout L = workspace_layout(n, prec, QST_OP_STATE_MAP, false);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+  if (T == rho) return fail(QST_ERR_INVALID_ARG, "rho must not alias T");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* partials = reinterpret_cast<double*>(ws_at(ws, L.partials));
+  hipError_t e = launch_tau(prec, T, ldT, n, partials, tau_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "tau reduction");
+  e = launch_herk(prec, T, ldT, rho, ld_rho, n, tau_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "T T^dagger");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_povm_probs(int n, qst_prec prec, const void* rho, int64_t ld_rho, const double* povm_host,
+                          void* p, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(rho, ld_rho, n, "rho", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(p, "p", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_povm(povm_host, msg)) != QST_OK) return fail(st, msg);
+  const WsLayout L = workspace_layout(n, prec, QST_OP_POVM_PROBS, false);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+  double W[32], V[32];
+  povm_mode_matrices(povm_host, W, V);
+  const PovmPlan pl = make_povm_plan(n, prec);
+  hipError_t e = launch_povm(false, prec, pl, W, povm_host == nullptr, rho, ld_rho, p, nullptr, nullptr,
+                             ws_at(ws, L.inter0), ws_at(ws, L.inter1), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "POVM map");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_nll(int n, qst_prec prec, const void* p, const void* f, double* nll_dev,
+                   unsigned long long* bad_dev, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(p, "p", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(f, "f", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(nll_dev, "nll_dev", msg)) != QST_OK) return fail(st, msg);
+  const WsLayout L = workspace_layout(n, prec, QST_OP_NLL, false);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+  hipError_t e = launch_nll(prec, p, f, n, reinterpret_cast<double*>(ws_at(ws, L.partials)), nll_dev, bad_dev,
+                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "NLL reduction");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_nll_backward(int n, qst_prec prec, const void* T, int64_t ldT, const void* f, const void* p,
+                            const double* tau_dev, const double* povm_host, const double* upstream_dev,
+                            void* gradT, int64_t ldG, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(gradT, ldG, n, "gradT", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(f, "f", msg)) != QST_OK) return fail(st, msg);
+  if (p && !tau_dev) return fail(QST_ERR_INVALID_ARG, "tau_dev is NULL while p is given");
+  if ((st = check_povm(povm_host, msg)) != QST_OK) return fail(st, msg);
+  if (T == gradT) return fail(QST_ERR_INVALID_ARG, "gradT must not alias T");
+  const bool recompute = (p == nullptr);
+  const WsLayout L = workspace_layout(n, prec, QST_OP_NLL_BACKWARD, recompute);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* partials = reinterpret_cast<double*>(ws_at(ws, L.partials));
+  double* scalars = reinterpret_cast<double*>(ws_at(ws, L.scalars));
+  double W[32], V[32];
+  povm_mode_matrices(povm_host, W, V);
+  const bool tetra = povm_host == nullptr;
+  const PovmPlan pl = make_povm_plan(n, prec);
+  const int64_t d = int64_t(1) << n;
+  hipError_t e;
+  if (recompute) {
+    // rho and p are rebuilt from T here; rho lives in the G' slot.
+    double* tau_ws = scalars + 1;
+    e = launch_tau(prec, T, ldT, n, partials, tau_ws, s);
+    if (e != hipSuccess) return hip_fail(e, "tau reduction (recompute)");
+    e = launch_herk(prec, T, ldT, ws_at(ws, L.rho), d, n, tau_ws, s);
+    if (e != hipSuccess) return hip_fail(e, "T T^dagger (recompute)");
+    e = launch_povm(false, prec, pl, W, tetra, ws_at(ws, L.rho), d, ws_at(ws, L.p), nullptr, nullptr,
+                    ws_at(ws, L.inter0), ws_at(ws, L.inter1), s);
+    if (e != hipSuccess) return hip_fail(e, "POVM map (recompute)");
+    p = ws_at(ws, L.p);
+    tau_dev = tau_ws;
+  }
+  double* F_dev = scalars;
+  e = launch_fsum(prec, f, n, partials, F_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "F reduction");
+  void* G = ws_at(ws, L.gmat);
+  e = launch_povm(true, prec, pl, V, tetra, G, d, const_cast<void*>(p), f, F_dev, ws_at(ws, L.inter0),
+                  ws_at(ws, L.inter1), s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint POVM map");
+  e = launch_hemm(prec, G, d, T, ldT, gradT, ldG, n, tau_dev, upstream_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "G' T");
+  clear_error();
+  return QST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Device-side helpers shared by the gfx950 kernels: complex storage types,
+// bfloat16 rounding, MFMA wrappers and deterministic wave64 reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qst {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) Cx {
+  R re, im;
+};
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// --------------------------------------------------------------------------
+// bfloat16 round-to-nearest-even of a float, returned as the 16-bit pattern
+// and as the float it represents.  Finite inputs only (the state-map inputs
+// are finite; NaN payloads are not preserved).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(float x) {
+  return __uint_as_float(uint32_t(bf16_bits(x)) << 16);
+}
+
+// --------------------------------------------------------------------------
+// MFMA 16x16 tiles.  For the fp64/fp32 K=4 forms lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; for the bf16 K=32 form lane l supplies
+// A[l%16][8(l/16)+0..7] and B[8(l/16)+0..7][l%16].  In all forms lane l
+// holds D[4(l/16)+v][l%16], v = 0..3.
+// --------------------------------------------------------------------------
+template <typename R>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ f4 mfma_bf16(u16x8 a, u16x8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                 __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ u16x8 bf16_neg(u16x8 a) { return a ^ (uint16_t)0x8000u; }
+
+// --------------------------------------------------------------------------
+// Deterministic reductions (fixed order for a fixed launch shape).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over a 256-thread block; result valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double* lds4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) lds4[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+  return s;
+}
+
+// Lower-triangular tile index t -> (R, C) with R >= C, t = R(R+1)/2 + C.
+__device__ __forceinline__ void tri_decode(int64_t t, int& R, int& C) {
+  int r = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (int64_t(r) * (r + 1) / 2 > t) --r;
+  while (int64_t(r + 1) * (r + 2) / 2 <= t) ++r;
+  R = r;
+  C = int(t - int64_t(r) * (r + 1) / 2);
+}
+
+}  // namespace qst

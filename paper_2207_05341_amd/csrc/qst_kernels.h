@@ -1,0 +1,43 @@
+// Launchers of the gfx950 kernels (host side).  Each enqueues work on the
+// given stream and returns hipGetLastError().
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qst.h"
+#include "qst_plan.h"
+
+namespace qst {
+
+// tau = sum |T_ij|^2 (FP64; over bf16-rounded T for QST_BF16GEMM).
+hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
+                      double* tau_dev, hipStream_t s);
+
+// rho = T T^dagger / *tau_dev, written in full.
+hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int64_t ldr, int n,
+                       const double* tau_dev, hipStream_t s);
+
+// out = (upstream ? *upstream : 1) * 2 / *tau_dev * G T.
+hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T, int64_t ldt,
+                       void* out, int64_t ldo, int n, const double* tau_dev,
+                       const double* upstream_dev, hipStream_t s);
+
+// Forward (adjoint=false): mat = rho (lower triangle read) -> pvec.
+// Adjoint (adjoint=true): g' = F - f/p from (pvec, fvec, F_dev) -> mat = G'
+// (written in full).  mode_matrix: W (forward) or V (adjoint) as 4 x 4
+// complex; tetra selects the tetrahedral fast form (mode_matrix unused).
+hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const double* mode_matrix,
+                       bool tetra, const void* mat, int64_t ld, void* pvec, const void* fvec,
+                       const double* F_dev, void* inter0, void* inter1, hipStream_t s);
+
+// nll[0] = L, nll[1] = F, bad[0..1] counts (bad may be NULL).
+hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double* partials,
+                      double* nll_dev, unsigned long long* bad_dev, hipStream_t s);
+
+// *F_dev = sum f.
+hipError_t launch_fsum(qst_prec prec, const void* f, int n, double* partials, double* F_dev,
+                       hipStream_t s);
+
+}  // namespace qst

@@ -1,0 +1,226 @@
+// HIP-free host logic: argument validation, POVM pass planning and
+// workspace layout.  Compiles with g++ alone (no HIP headers), so its tests
+// run on machines without a GPU.
+#include "qst_plan.h"
+
+#include <cmath>
+#include <cstdio>
+
+namespace qst {
+
+namespace {
+thread_local std::string g_last_error;
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+PovmPlan make_povm_plan(int n, qst_prec prec) {
+  PovmPlan pl;
+  pl.n = n;
+  const int kFirstMax = 6;  // 4^6 complex in the first (row-tile) pass
+  const int kLaterMax = 5;  // 4^5 complex x J in later passes
+  int passes = 1;
+  if (n > kFirstMax) passes = 1 + (n - kFirstMax + kLaterMax - 1) / kLaterMax;
+  pl.passes = passes;
+  const int base = n / passes, rem = n % passes;
+  for (int j = 0; j < passes; ++j) pl.g[j] = base + (j < rem ? 1 : 0);
+  int U = n;
+  const size_t cb = complex_bytes(prec);
+  for (int j = 0; j < passes; ++j) {
+    pl.U[j] = U;
+    if (j == 0) {
+      pl.J[j] = 1;
+    } else {
+      const int64_t kd = int64_t(1) << (2 * (n - U));
+      int64_t J = int64_t(65536) / ((int64_t(1) << (2 * pl.g[j])) * int64_t(cb));
+      if (J > 16) J = 16;
+      if (J > kd) J = kd;
+      if (J < 1) J = 1;
+      pl.J[j] = int(J);
+    }
+    U -= pl.g[j];
+  }
+  return pl;
+}
+
+int64_t povm_pass_blocks(const PovmPlan& pl, int j) {
+  const int Up = pl.U[j] - pl.g[j];
+  const int64_t side = int64_t(1) << Up;
+  const int64_t pairs = side * (side + 1) / 2;
+  const int64_t kd = int64_t(1) << (2 * (pl.n - pl.U[j]));
+  return pairs * (kd / pl.J[j]);
+}
+
+WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
+  WsLayout w;
+  const size_t cb = complex_bytes(prec), rb = real_bytes(prec);
+  const size_t d = size_t(1) << n;
+  const size_t D = d * d;
+  const PovmPlan pl = make_povm_plan(n, prec);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  switch (op) {
+    case QST_OP_STATE_MAP:
+    case QST_OP_NLL:
+      w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
+      break;
+    case QST_OP_POVM_PROBS:
+      if (pl.passes >= 2) w.inter0 = take(D * cb);
+      if (pl.passes >= 3) w.inter1 = take(D * cb);
+      break;
+    case QST_OP_NLL_BACKWARD:
+      w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
+      w.scalars = take(8 * sizeof(double));
+      if (pl.passes >= 2) w.inter0 = take(D * cb);
+      if (pl.passes >= 3) w.inter1 = take(D * cb);
+      w.gmat = take(D * cb);
+      if (recompute) {
+        w.rho = w.gmat;  // rho is dead once p exists; G' reuses its storage
+        w.p = take(D * rb);
+      }
+      break;
+    default:
+      return WsLayout{};
+  }
+  w.total = off;
+  return w;
+}
+
+qst_status check_common(int n, int prec, std::string& msg) {
+  if (n < 1 || n > QST_MAX_QUBITS) {
+    msg = "n_qubits=" + std::to_string(n) + " outside [1, " + std::to_string(QST_MAX_QUBITS) + "]";
+    return QST_ERR_INVALID_ARG;
+  }
+  if (!prec_valid(prec)) {
+    msg = "unknown precision " + std::to_string(prec);
+    return QST_ERR_INVALID_ARG;
+  }
+  return QST_OK;
+}
+
+qst_status check_ptr(const void* ptr, const char* name, std::string& msg) {
+  if (!ptr) {
+    msg = std::string(name) + " is NULL";
+    return QST_ERR_INVALID_ARG;
+  }
+  return QST_OK;
+}
+
+qst_status check_matrix(const void* ptr, int64_t ld, int n, const char* name, std::string& msg) {
+  if (check_ptr(ptr, name, msg) != QST_OK) return QST_ERR_INVALID_ARG;
+  const int64_t d = int64_t(1) << n;
+  if (ld < d) {
+    msg = std::string("leading dimension of ") + name + " (" + std::to_string(ld) +
+          ") is smaller than d=" + std::to_string(d);
+    return QST_ERR_INVALID_ARG;
+  }
+  return QST_OK;
+}
+
+qst_status check_ws(const void* ws, size_t ws_bytes, size_t need, std::string& msg) {
+  if (need == 0) return QST_OK;
+  if (!ws || ws_bytes < need) {
+    msg = "workspace of " + std::to_string(ws ? ws_bytes : 0) + " bytes is smaller than the " +
+          std::to_string(need) + " bytes required";
+    return QST_ERR_WORKSPACE;
+  }
+  return QST_OK;
+}
+
+qst_status check_povm(const double* M, std::string& msg) {
+  if (!M) return QST_OK;
+  double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 4; ++a) {
+    for (int x = 0; x < 2; ++x) {
+      for (int y = 0; y < 2; ++y) {
+        const double re = M[8 * a + 4 * x + 2 * y], im = M[8 * a + 4 * x + 2 * y + 1];
+        const double tre = M[8 * a + 4 * y + 2 * x], tim = M[8 * a + 4 * y + 2 * x + 1];
+        if (!std::isfinite(re) || !std::isfinite(im)) {
+          msg = "POVM entry is not finite";
+          return QST_ERR_INVALID_ARG;
+        }
+        if (std::fabs(re - tre) > 1e-12 || std::fabs(im + tim) > 1e-12) {
+          msg = "POVM element M_" + std::to_string(a) + " is not Hermitian";
+          return QST_ERR_INVALID_ARG;
+        }
+        sum[4 * x + 2 * y] += re;
+        sum[4 * x + 2 * y + 1] += im;
+      }
+    }
+  }
+  const double eye[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+  for (int i = 0; i < 8; ++i) {
+    if (std::fabs(sum[i] - eye[i]) > 1e-12) {
+      msg = "POVM elements do not sum to the identity";
+      return QST_ERR_INVALID_ARG;
+    }
+  }
+  return QST_OK;
+}
+
+void povm_mode_matrices(const double* M, double W[32], double V[32]) {
+  // Tetrahedral POVM of Sec. 4.1: M_a = (I + s_a . sigma)/4, s_a = (+-1,+-1,+-1)/sqrt(3).
+  double tet[32];
+  if (!M) {
+    const double t = 1.0 / std::sqrt(3.0);
+    const double s[4][3] = {{t, t, t}, {-t, -t, t}, {-t, t, -t}, {t, -t, -t}};
+    for (int a = 0; a < 4; ++a) {
+      const double sx = s[a][0], sy = s[a][1], sz = s[a][2];
+      double* m = tet + 8 * a;
+      m[0] = (1 + sz) / 4; m[1] = 0;         // [0][0]
+      m[2] = sx / 4;       m[3] = -sy / 4;   // [0][1]
+      m[4] = sx / 4;       m[5] = sy / 4;    // [1][0]
+      m[6] = (1 - sz) / 4; m[7] = 0;         // [1][1]
+    }
+    M = tet;
+  }
+  for (int a = 0; a < 4; ++a) {
+    for (int r = 0; r < 2; ++r) {
+      for (int c = 0; c < 2; ++c) {
+        const int m = 2 * r + c;
+        // W[a][m] = M_a[c][r]
+        W[2 * (4 * a + m)] = M[8 * a + 4 * c + 2 * r];
+        W[2 * (4 * a + m) + 1] = M[8 * a + 4 * c + 2 * r + 1];
+        // V[m][a] = M_a[r][c]
+        V[2 * (4 * m + a)] = M[8 * a + 4 * r + 2 * c];
+        V[2 * (4 * m + a) + 1] = M[8 * a + 4 * r + 2 * c + 1];
+      }
+    }
+  }
+}
+
+}  // namespace qst
+
+extern "C" {
+
+size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op) {
+  std::string msg;
+  if (qst::check_common(n_qubits, prec, msg) != QST_OK) return 0;
+  if (op < QST_OP_STATE_MAP || op > QST_OP_NLL_BACKWARD) return 0;
+  return qst::workspace_layout(n_qubits, prec, op, /*recompute=*/true).total;
+}
+
+const char* qst_status_string(qst_status s) {
+  switch (s) {
+    case QST_OK: return "QST_OK";
+    case QST_ERR_INVALID_ARG: return "QST_ERR_INVALID_ARG";
+    case QST_ERR_UNSUPPORTED: return "QST_ERR_UNSUPPORTED";
+    case QST_ERR_WORKSPACE: return "QST_ERR_WORKSPACE";
+    case QST_ERR_HIP: return "QST_ERR_HIP";
+  }
+  return "QST_ERR_UNKNOWN";
+}
+
+const char* qst_last_error(void) { return qst::last_error_cstr(); }
+
+const char* qst_version(void) { return "qst-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

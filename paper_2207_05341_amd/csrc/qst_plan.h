@@ -1,0 +1,75 @@
+// Host-side planning shared by the HIP entry points and the HIP-free
+// validation unit: argument checks, POVM pass plans, workspace layout.
+// Nothing in this header touches the HIP runtime.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "qst.h"
+
+namespace qst {
+
+// Elements of one complex scalar in bytes for a precision's storage type.
+inline size_t complex_bytes(qst_prec p) { return p == QST_F64 ? 16 : 8; }
+inline size_t real_bytes(qst_prec p) { return p == QST_F64 ? 8 : 4; }
+inline bool prec_valid(int p) { return p == QST_F64 || p == QST_F32 || p == QST_BF16GEMM; }
+
+// The product-POVM map is applied in passes.  Pass j contracts a group of
+// g_j consecutive qubits inside on-chip memory; groups run from the least
+// significant qubits (qubit N, N-1, ...) to qubit 1.  Before pass j the
+// intermediate is indexed [(R, C)][kdone]: R, C are the row/column bits of
+// the U_j qubits not yet contracted and kdone the outcome digits of the
+// contracted ones (4^(N-U_j) values, qubit N least significant).
+struct PovmPlan {
+  int n = 0;           // qubits
+  int passes = 0;      // number of passes
+  int g[4] = {0};      // group size of pass j (pass 0 = lowest qubits)
+  int U[4] = {0};      // remaining qubits before pass j
+  int J[4] = {0};      // consecutive kdone values per workgroup in pass j
+};
+
+// Largest group a pass may hold on chip: 4^g * J complex values in a 64 KiB
+// LDS buffer.
+PovmPlan make_povm_plan(int n, qst_prec prec);
+
+// Workgroups launched by a pass (lower block triangle of (R, C) times kdone
+// chunks).
+int64_t povm_pass_blocks(const PovmPlan& pl, int j);
+
+// Workspace layout (byte offsets) for each op; see the .cpp for the rules.
+struct WsLayout {
+  size_t total = 0;
+  size_t partials = 0;   // FP64 reduction partials
+  size_t scalars = 0;    // small FP64 scalars (F, tau when recomputed, L)
+  size_t inter0 = 0;     // first POVM intermediate (4^N complex)
+  size_t inter1 = 0;     // second POVM intermediate (4^N complex, >2 passes)
+  size_t gmat = 0;       // G' (d x d complex), backward only
+  size_t rho = 0;        // rho (d x d complex), recompute mode only
+  size_t p = 0;          // p (4^N real), recompute mode only
+};
+
+WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute);
+
+constexpr int kReduceBlocks = 1024;  // stage-1 blocks of every FP64 reduction
+constexpr int kReduceThreads = 256;
+
+// Argument validation.  Each returns QST_OK or an error status and fills msg.
+qst_status check_common(int n, int prec, std::string& msg);
+qst_status check_matrix(const void* ptr, int64_t ld, int n, const char* name, std::string& msg);
+qst_status check_ptr(const void* ptr, const char* name, std::string& msg);
+qst_status check_ws(const void* ws, size_t ws_bytes, size_t need, std::string& msg);
+qst_status check_povm(const double* povm_host, std::string& msg);
+
+// Per-thread last-error message.
+void set_error(const std::string& msg);
+void clear_error();
+const char* last_error_cstr();
+
+// Forward mode matrix W[a][m] (m = 2r + c) = (M_a)_{c,r} and adjoint mode
+// matrix V[m][a] = (M_a)_{r,c}, as 4 x 4 complex (re, im) in row-major
+// double[32], from a POVM given as in qst_povm_probs.
+void povm_mode_matrices(const double* povm_host, double W[32], double V[32]);
+
+}  // namespace qst

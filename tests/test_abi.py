@@ -1,0 +1,172 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/qst.h declares, sizes workspaces, and rejects invalid arguments on
+the host before any HIP call (every call here fails validation, so no kernel
+is ever launched)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+lib_mod = pytest.importorskip("paper_2207_05341_amd._lib")
+
+HEADER = os.path.join(ROOT, "include", "qst.h")
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+FAKE2 = ctypes.c_void_p(0x20000)
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lib_mod.LIB_PATH):
+        pytest.skip("libqst.so not built")
+    return lib_mod.lib()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b(qst_[a-z_]+)\s*\(", text))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == set(lib_mod.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_mod.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (qst_\w+)", out))
+    assert declared_symbols() <= exported
+
+
+def test_status_strings(L):
+    for code, name in enumerate(["QST_OK", "QST_ERR_INVALID_ARG", "QST_ERR_UNSUPPORTED", "QST_ERR_WORKSPACE",
+                                 "QST_ERR_HIP"]):
+        assert L.qst_status_string(code).decode() == name
+    assert L.qst_version().decode().startswith("qst-mi355x")
+
+
+def test_workspace_sizes(L):
+    ws = lib_mod.workspace_bytes
+    # invalid requests
+    assert ws(0, 0, 0) == 0 and ws(14, 0, 0) == 0 and ws(5, 7, 0) == 0 and ws(5, 0, 9) == 0
+    # single-pass POVM needs no workspace; N=11 needs one 4^N complex intermediate
+    assert ws(6, 0, lib_mod.QST_OP_POVM_PROBS) == 0
+    assert ws(11, lib_mod.QST_F64, lib_mod.QST_OP_POVM_PROBS) >= 16 * 4 ** 11
+    assert ws(11, lib_mod.QST_F32, lib_mod.QST_OP_POVM_PROBS) >= 8 * 4 ** 11
+    # backward (recompute bound): intermediate + G' + p
+    assert ws(12, lib_mod.QST_F32, lib_mod.QST_OP_NLL_BACKWARD) >= 8 * 4 ** 12 * 2 + 4 * 4 ** 12
+    for n in range(1, 14):
+        for prec in (0, 1, 2):
+            assert ws(n, prec, lib_mod.QST_OP_STATE_MAP) > 0
+            assert ws(n, prec, lib_mod.QST_OP_NLL_BACKWARD) >= ws(n, prec, lib_mod.QST_OP_POVM_PROBS)
+
+
+def _err(L):
+    return L.qst_last_error().decode()
+
+
+def test_state_map_validation(L):
+    ok_ws = lib_mod.workspace_bytes(4, 0, 0)
+    W = ctypes.c_void_p(0x30000)
+    st = L.qst_state_map(0, 0, FAKE, 16, FAKE2, 16, FAKE, W, ok_ws, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "n_qubits" in _err(L)
+    st = L.qst_state_map(14, 0, FAKE, 1 << 14, FAKE2, 1 << 14, FAKE, W, ok_ws, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG
+    st = L.qst_state_map(4, 5, FAKE, 16, FAKE2, 16, FAKE, W, ok_ws, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "precision" in _err(L)
+    st = L.qst_state_map(4, 0, None, 16, FAKE2, 16, FAKE, W, ok_ws, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "T is NULL" in _err(L)
+    st = L.qst_state_map(4, 0, FAKE, 15, FAKE2, 16, FAKE, W, ok_ws, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
+    st = L.qst_state_map(4, 0, FAKE, 16, FAKE2, 8, FAKE, W, ok_ws, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG
+    st = L.qst_state_map(4, 0, FAKE, 16, FAKE2, 16, None, W, ok_ws, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "tau_dev" in _err(L)
+    st = L.qst_state_map(4, 0, FAKE, 16, FAKE2, 16, FAKE, W, ok_ws - 1, None)
+    assert st == lib_mod.QST_ERR_WORKSPACE and "workspace" in _err(L)
+    st = L.qst_state_map(4, 0, FAKE, 16, FAKE2, 16, FAKE, None, ok_ws, None)
+    assert st == lib_mod.QST_ERR_WORKSPACE
+    st = L.qst_state_map(4, 0, FAKE, 16, FAKE, 16, FAKE2, W, ok_ws, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
+
+
+def _povm_array(vals):
+    return (ctypes.c_double * 32)(*vals)
+
+
+def _tetra_flat():
+    import oracle as O
+    M = O.tetrahedral_povm()
+    flat = []
+    for a in range(4):
+        for x in range(2):
+            for y in range(2):
+                flat += [M[a][x, y].real, M[a][x, y].imag]
+    return flat
+
+
+def test_povm_validation(L):
+    n = 8
+    need = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_POVM_PROBS)
+    assert need > 0
+    st = L.qst_povm_probs(n, 0, FAKE, 256, None, FAKE2, None, 0, None)
+    assert st == lib_mod.QST_ERR_WORKSPACE
+    st = L.qst_povm_probs(n, 0, FAKE, 256, None, None, FAKE, need, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "p is NULL" in _err(L)
+    flat = _tetra_flat()
+    bad = list(flat)
+    bad[8 * 1 + 2 * 1 + 1] += 0.1  # M_1[0][1] imaginary part: not Hermitian
+    st = L.qst_povm_probs(n, 0, FAKE, 256, _povm_array(bad), FAKE2, FAKE, need, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "Hermitian" in _err(L)
+    bad = list(flat)
+    bad[0] += 0.01  # M_0[0][0]: sum no longer the identity
+    st = L.qst_povm_probs(n, 0, FAKE, 256, _povm_array(bad), FAKE2, FAKE, need, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG and "identity" in _err(L)
+    bad = list(flat)
+    bad[5] = float("nan")
+    st = L.qst_povm_probs(n, 0, FAKE, 256, _povm_array(bad), FAKE2, FAKE, need, None)
+    assert st == lib_mod.QST_ERR_INVALID_ARG
+
+
+def test_nll_validation(L):
+    ws = lib_mod.workspace_bytes(5, 1, lib_mod.QST_OP_NLL)
+    W = ctypes.c_void_p(0x30000)
+    assert L.qst_nll(5, 1, None, FAKE, FAKE2, None, W, ws, None) == lib_mod.QST_ERR_INVALID_ARG
+    assert L.qst_nll(5, 1, FAKE, None, FAKE2, None, W, ws, None) == lib_mod.QST_ERR_INVALID_ARG
+    assert L.qst_nll(5, 1, FAKE, FAKE, None, None, W, ws, None) == lib_mod.QST_ERR_INVALID_ARG
+    assert L.qst_nll(5, 1, FAKE, FAKE, FAKE2, None, W, 8, None) == lib_mod.QST_ERR_WORKSPACE
+
+
+def test_backward_validation(L):
+    n, d = 7, 128
+    ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_NLL_BACKWARD)
+    W = ctypes.c_void_p(0x30000)
+    args = dict(T=FAKE, ldT=d, f=FAKE2, p=FAKE2, tau=FAKE, povm=None, up=None, G=W, ldG=d)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return L.qst_nll_backward(n, 0, a["T"], a["ldT"], a["f"], a["p"], a["tau"], a["povm"], a["up"], a["G"],
+                                  a["ldG"], W, kw.get("ws", ws), None)
+
+    assert call(T=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(f=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(G=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(ldT=d - 1) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(ldG=3) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(tau=None) == lib_mod.QST_ERR_INVALID_ARG and "tau_dev" in _err(L)
+    assert call(G=FAKE) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
+    assert call(ws=1024) == lib_mod.QST_ERR_WORKSPACE
+
+
+def test_plan_unit_builds_without_hip(tmp_path):
+    """The validation / planning unit is HIP-free: it compiles with g++."""
+    src = os.path.join(ROOT, "paper_2207_05341_amd", "csrc", "qst_plan.cpp")
+    obj = tmp_path / "plan.o"
+    res = subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", "-c", src, "-I",
+                          os.path.join(ROOT, "include"), "-o", str(obj)], capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
