@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Likelihood forward + adjoint throughput at N = 11 on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input, inputs resident
+in HBM before timing starts:
+    qst_state_map (tau, T T^dagger)  ->  qst_povm_probs (4^11 outcomes)
+    ->  qst_nll  ->  qst_nll_backward (F, cotangent + adjoint POVM map, G' T).
+
+Workload (N = 11): T 2048 x 2048 complex Ginibre (seed 6); frequencies from
+10^7 multinomial shots of a Porter-Thomas stand-in distribution of a
+depolarised random pure state (q = 0.05).
+
+Prints ONE JSON line with the throughput, the roofline of the dominant kernel
+(durations from HIP events recorded by the library on its launch stream over
+the timed region), accuracy against the FP64 path on the same GPU, the other
+precision paths, and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "likelihood fwd+bwd evals/sec at N=11 on 1 GPU; % HBM/MFMA peak; max|Δp| vs FP64"
+
+# MI355X published peaks
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--n", type=int, default=11)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other precision paths")
+    return ap.parse_args()
+
+
+def make_inputs(n: int):
+    import synth as S
+
+    g = S.rng(6)
+    d = 1 << n
+    T = S.ginibre(g, d)
+    f = S.multinomial_freqs(g, 10_000_000, S.porter_thomas_probs(g, 4 ** n, 0.05))
+    return T, f
+
+
+def to_prec(T, f, prec, dev):
+    import numpy as np
+    import torch
+
+    ct = np.complex128 if prec == "f64" else np.complex64
+    rt = np.float64 if prec == "f64" else np.float32
+    return (torch.from_numpy(np.ascontiguousarray(T.astype(ct))).to(dev),
+            torch.from_numpy(np.ascontiguousarray(f.astype(rt))).to(dev))
+
+
+def step(qst, T, f, prec):
+    rho, tau = qst.state_map(T, prec)
+    p = qst.povm_probs(rho, prec)
+    out, _ = qst.nll(p, f, prec)
+    grad = qst.nll_backward(T, f, p, tau, prec)
+    return p, out, grad
+
+
+def time_steps(qst, T, f, prec, steps, warmup, profile):
+    import torch
+
+    from paper_2207_05341_amd import _lib
+
+    for _ in range(warmup):
+        step(qst, T, f, prec)
+    torch.cuda.synchronize()
+    if profile:
+        _lib.profile_report(reset=True)
+        _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(qst, T, f, prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    if profile:
+        _lib.profile_enable(False)
+        kern = _lib.profile_report(reset=True)
+    return (t1 - t0) / steps, kern
+
+
+def cpu_baseline(T, f, prec):
+    """FP64 oracle on a bounded sample: full forward + adjoint evaluations of
+    the same N = 11 workload (the measured precision's T and f widened)."""
+    import numpy as np
+
+    import oracle as O
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    ct = np.complex128 if prec == "f64" else np.complex64
+    rt = np.float64 if prec == "f64" else np.float32
+    Tq = T.astype(ct).astype(np.complex128)
+    fq = f.astype(rt).astype(np.float64)
+    n = O.n_qubits_of(Tq.shape[0])
+    evals = 0
+    t0 = time.perf_counter()
+    while True:
+        rho, tau = O.state_map(Tq)
+        p = O.probs_real(rho)
+        O.nll_vec(p, fq)
+        G = O.adjoint(O.cotangent(p, fq), n)
+        _ = (2.0 / tau) * (G @ Tq)
+        evals += 1
+        el = time.perf_counter() - t0
+        if evals >= 3 or el > 20.0:
+            break
+    return {"value": evals / el, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{evals} full forward+adjoint evaluations of the N=11 workload in FP64 numpy "
+                      f"({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures the single-GPU likelihood path; this build uses exactly one GPU "
+              "(--gpus 1).  Multi-GPU sharding is a design note only.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2207_05341_amd as qst
+
+    dev = torch.device("cuda:0")
+    n, d = args.n, 1 << args.n
+    T_np, f_np = make_inputs(n)
+
+    # accuracy against the FP64 path on the same GPU
+    T64, f64 = to_prec(T_np, f_np, "f64", dev)
+    p64, out64, g64 = step(qst, T64, f64, "f64")
+    torch.cuda.synchronize()
+
+    def measure(prec, steps, warmup, profile):
+        T, f = to_prec(T_np, f_np, prec, dev)
+        p, out, grad = step(qst, T, f, prec)
+        torch.cuda.synchronize()
+        acc = {
+            "max_dp_rel": float((p.double() - p64).abs().max() / p64.abs().max()),
+            "L_rel": float(abs(out[0].item() - out64[0].item()) / abs(out64[0].item())),
+            "grad_rel": float(torch.linalg.vector_norm(grad.to(torch.complex128) - g64)
+                              / torch.linalg.vector_norm(g64)),
+        }
+        sec, kern = time_steps(qst, T, f, prec, steps, warmup, profile)
+        return sec, kern, acc
+
+    sec, kern, acc = measure(args.prec, args.steps, args.warmup, True)
+    kern_us = {k: 1e3 * ms / calls for k, (calls, ms) in kern.items()}
+
+    # roofline of the dominant kernel (largest share of the step)
+    dom = max(kern, key=lambda k: kern[k][1]) if kern else None
+    roofline = None
+    if dom:
+        avg_s = kern_us[dom] * 1e-6
+        if dom.startswith("hemm") or dom.startswith("herk"):
+            flops = 8.0 * d ** 3 if dom.startswith("hemm") else 4.0 * d * d * (d + 1)
+            peak_key = "bf16" if dom.endswith(("bf16", "bf16x3")) else ("f64" if dom.endswith("f64") else "f32")
+            ach = flops / avg_s / 1e12
+            roofline = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[peak_key],
+                        "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[peak_key], "traffic": None,
+                        "algorithmic_per_launch": f"{flops:.4g} flop ({'8d^3' if dom.startswith('hemm') else '4d^2(d+1)'}, d={d})"}
+    # POVM passes: achieved GB/s from algorithmic bytes (lower triangle read, see DESIGN)
+    cb = 16 if args.prec == "f64" else 8
+    rb = 8 if args.prec == "f64" else 4
+    tiles = (d // 64) * (d // 64 + 1) // 2
+    tri = d * (d + 1) // 2
+    povm_bytes = {
+        "povm_fwd_p0": tri * cb + tiles * 4096 * cb,
+        "povm_fwd_p1": tiles * 4096 * cb + 4 ** n * rb,
+        "povm_adj_p1": 2 * 4 ** n * rb + tiles * 4096 * cb,
+        "povm_adj_p0": tiles * 4096 * cb + d * d * cb,
+    }
+    povm_gbs = {k: v / (kern_us[k] * 1e-6) / 1e9 for k, v in povm_bytes.items() if k in kern_us} if n == 11 else {}
+
+    paths = {}
+    if not args.no_variants:
+        for prec in ("f64", "f32", "bf16"):
+            if prec == args.prec:
+                continue
+            s2, k2, a2 = measure(prec, max(10, args.steps // 2), 3, True)
+            paths[prec] = {"evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
+                           "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()}}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
+
+    line = {
+        "metric": METRIC,
+        "value": 1.0 / sec,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"N={n} single state: T {d}x{d} complex Ginibre, {4 ** n} tetrahedral-POVM "
+                               f"outcomes, f from 10^7 multinomial shots; stored-p forward+adjoint",
+                   "n_qubits": n, "precision": args.prec, "parallelism": "none (1 GPU)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "accuracy_vs_f64": acc,
+        "kernels_us": {k: round(v, 2) for k, v in sorted(kern_us.items())},
+        "povm_pass_gbs": {k: round(v, 1) for k, v in povm_gbs.items()},
+        "paths": paths,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,7 +103,8 @@ qst_status qst_state_map(int n_qubits, qst_prec prec, const void* T, int64_t ldT
  *   povm_host[in]  NULL for the paper's tetrahedral POVM (Sec. 4.1), else
  *                  host array of 4 Hermitian 2 x 2 complex matrices M_0..M_3,
  *                  32 doubles: M_a[x][y] at (re, im) = [8a + 4x + 2y + {0,1}].
- *                  Must be Hermitian to 1e-12 (else QST_ERR_INVALID_ARG).
+ *                  Each M_a must be Hermitian and sum_a M_a = I, both to
+ *                  1e-12 (else QST_ERR_INVALID_ARG).
  *   p        [out] 4^N reals, device.
  */
 qst_status qst_povm_probs(int n_qubits, qst_prec prec, const void* rho, int64_t ld_rho,
@@ -160,6 +161,22 @@ const char* qst_last_error(void);
 
 /* Library version string. */
 const char* qst_version(void);
+
+/*
+ * Kernel timing for measurement tools.  While enabled (on != 0), every
+ * kernel the library launches is bracketed by two hipEvents recorded on its
+ * launch stream.  Disabled by default; do not enable it while a stream is
+ * being captured into a HIP graph.
+ */
+qst_status qst_profile_enable(int on);
+
+/*
+ * Waits for the recorded events and writes one line "name calls total_ms"
+ * per kernel name seen since the last reset into buf (NUL-terminated,
+ * truncated to len).  Returns the size needed including the NUL.  reset != 0
+ * clears the totals afterwards.
+ */
+size_t qst_profile_report(char* buf, size_t len, int reset);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,8 @@ SIGNATURES = {
     "qst_status_string": (ctypes.c_char_p, [_int]),
     "qst_last_error": (ctypes.c_char_p, []),
     "qst_version": (ctypes.c_char_p, []),
+    "qst_profile_enable": (_int, [_int]),
+    "qst_profile_report": (_sz, [ctypes.c_char_p, _sz, _int]),
 }
 
 _lib = None
@@ -65,3 +67,20 @@ def check(status: int, where: str) -> None:
 
 def workspace_bytes(n: int, prec: int, op: int) -> int:
     return int(lib().qst_workspace_bytes(n, prec, op))
+
+
+def profile_enable(on: bool) -> None:
+    check(lib().qst_profile_enable(1 if on else 0), "qst_profile_enable")
+
+
+def profile_report(reset: bool = True) -> dict[str, tuple[int, float]]:
+    """{kernel name: (calls, total ms)} since the last reset (waits for the
+    recorded events)."""
+    need = int(lib().qst_profile_report(None, 0, 0))
+    buf = ctypes.create_string_buffer(need + 1024)
+    lib().qst_profile_report(buf, len(buf), 1 if reset else 0)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, calls, ms = line.split()
+        out[name] = (int(calls), float(ms))
+    return out

@@ -138,15 +138,12 @@ __global__ __launch_bounds__(256) void gemm_cx_kernel(const Cx<R>* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t col = C0 + wc * 32 + j * 16 + li;
-      const int64_t row0 = R0 + wr * 32 + i * 16 + lk * 4;
+      const int64_t rbase = R0 + wr * 32 + i * 16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        C[(row0 + v) * ldc + col] = Cx<R>{accR[i][j][v] * sc, accI[i][j][v] * sc};
-      }
-      if (HERK && tr != tc) {
-        Cx<R>* dst = C + col * ldc + row0;  // mirror: conj transpose
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dst[v] = Cx<R>{accR[i][j][v] * sc, -accI[i][j][v] * sc};
+        const int64_t row = rbase + Mfma<R>::row(lk, v);
+        C[row * ldc + col] = Cx<R>{accR[i][j][v] * sc, accI[i][j][v] * sc};
+        if (HERK && tr != tc) C[col * ldc + row] = Cx<R>{accR[i][j][v] * sc, -accI[i][j][v] * sc};
       }
     }
   }
@@ -412,6 +409,7 @@ __global__ void hemm_small_kernel(const Cx<R>* __restrict__ G, int64_t ldg, cons
 hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int64_t ldr, int n,
                        const double* tau_dev, hipStream_t s) {
   const int d = 1 << n;
+  ProfScope prof(d < BM ? "herk_small" : (prec == QST_F64 ? "herk_f64" : prec == QST_F32 ? "herk_f32" : "herk_bf16"), s);
   if (d < BM) {
     if (prec == QST_F64)
       herk_small_kernel<double, false><<<d, 64, 0, s>>>(static_cast<const Cx<double>*>(T), ldt,
@@ -445,6 +443,7 @@ hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T,
                        int64_t ldo, int n, const double* tau_dev, const double* upstream_dev,
                        hipStream_t s) {
   const int d = 1 << n;
+  ProfScope prof(d < BM ? "hemm_small" : (prec == QST_F64 ? "hemm_f64" : prec == QST_F32 ? "hemm_f32" : "hemm_bf16x3"), s);
   if (d < BM) {
     if (prec == QST_F64)
       hemm_small_kernel<double, false><<<d, 64, 0, s>>>(static_cast<const Cx<double>*>(G), ldg,

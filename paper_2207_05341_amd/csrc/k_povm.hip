@@ -312,6 +312,9 @@ hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const do
       a.F = F_dev;
     }
     const int64_t blocks = povm_pass_blocks(pl, j);
+    static const char* kNames[2][4] = {{"povm_fwd_p0", "povm_fwd_p1", "povm_fwd_p2", "povm_fwd_p3"},
+                                       {"povm_adj_p0", "povm_adj_p1", "povm_adj_p2", "povm_adj_p3"}};
+    ProfScope prof(kNames[adjoint ? 1 : 0][j], s);
     hipError_t e;
     if (prec == QST_F64) {
       if (adjoint) e = tetra ? launch_pass_t<double, true, true>(a, A, matside, pside, blocks, s)

@@ -121,6 +121,7 @@ __global__ __launch_bounds__(256) void nll_finish_kernel(const double* __restric
 hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
                       double* tau_dev, hipStream_t s) {
   const int nb = kReduceBlocks;
+  ProfScope prof("tau_reduce", s);
   if (prec == QST_F64) {
     tau_partial_kernel<double, false><<<nb, 256, 0, s>>>(static_cast<const Cx<double>*>(T), ld, n, partials);
   } else if (prec == QST_F32) {
@@ -135,6 +136,7 @@ hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* p
 hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double* partials,
                       double* nll_dev, unsigned long long* bad_dev, hipStream_t s) {
   const int nb = kReduceBlocks;
+  ProfScope prof("nll_reduce", s);
   const int64_t D = int64_t(1) << (2 * n);
   if (prec == QST_F64) {
     nll_partial_kernel<double, true><<<nb, 256, 0, s>>>(static_cast<const double*>(p),
@@ -151,6 +153,7 @@ hipError_t launch_fsum(qst_prec prec, const void* f, int n, double* partials, do
                        hipStream_t s) {
   const int nb = kReduceBlocks;
   const int64_t D = int64_t(1) << (2 * n);
+  ProfScope prof("fsum_reduce", s);
   if (prec == QST_F64) {
     nll_partial_kernel<double, false><<<nb, 256, 0, s>>>(nullptr, static_cast<const double*>(f), D, partials);
   } else {

@@ -35,8 +35,9 @@ __device__ __forceinline__ float bf16_value(float x) {
 // --------------------------------------------------------------------------
 // MFMA 16x16 tiles.  For the fp64/fp32 K=4 forms lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; for the bf16 K=32 form lane l supplies
-// A[l%16][8(l/16)+0..7] and B[8(l/16)+0..7][l%16].  In all forms lane l
-// holds D[4(l/16)+v][l%16], v = 0..3.
+// A[l%16][8(l/16)+0..7] and B[8(l/16)+0..7][l%16].  Lane l holds the four
+// outputs D[row(l/16, v)][l%16], v = 0..3, with row = 4(l/16) + v for the
+// fp32 and bf16 forms and row = l/16 + 4v for the fp64 form.
 // --------------------------------------------------------------------------
 template <typename R>
 struct Mfma;
@@ -47,6 +48,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ acc step(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int q, int v) { return q + 4 * v; }
 };
 
 template <>
@@ -55,6 +57,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ acc step(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
 };
 
 __device__ __forceinline__ f4 mfma_bf16(u16x8 a, u16x8 b, f4 c) {

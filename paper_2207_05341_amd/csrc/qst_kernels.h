@@ -11,6 +11,20 @@
 
 namespace qst {
 
+// Brackets the kernel launched while it is alive with timing events when
+// qst_profile_enable(1) is in effect (no-op otherwise).
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  int idx_ = -1;
+  hipStream_t s_;
+};
+
 // tau = sum |T_ij|^2 (FP64; over bf16-rounded T for QST_BF16GEMM).
 hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
                       double* tau_dev, hipStream_t s);
