@@ -70,7 +70,7 @@ def step(qst, T, f, prec):
     rho, tau = qst.state_map(T, prec)
     p = qst.povm_probs(rho, prec)
     out, _ = qst.nll(p, f, prec)
-    grad = qst.nll_backward(T, f, p, tau, prec)
+    grad = qst.nll_backward(T, f, p, tau, prec, nll_out=out)
     return p, out, grad
 
 

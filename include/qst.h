@@ -139,14 +139,18 @@ qst_status qst_nll(int n_qubits, qst_prec prec, const void* p, const void* f, do
  *                  call (nothing of length 4^N needs to survive the forward).
  *   tau_dev  [in]  the tau written by qst_state_map for this T, device; may
  *                  be NULL only when p is NULL (then tau is recomputed).
+ *   nll_dev  [in]  the two doubles written by qst_nll for this f (F is taken
+ *                  from nll_dev[1]), device; or NULL, in which case F = sum f
+ *                  is reduced here.
  *   povm_host[in]  as in qst_povm_probs.
  *   upstream_dev[in] one double, device, or NULL.
  *   gradT    [out] d x d complex, row stride ldG, device; must not overlap T.
  */
 qst_status qst_nll_backward(int n_qubits, qst_prec prec, const void* T, int64_t ldT,
                             const void* f, const void* p, const double* tau_dev,
-                            const double* povm_host, const double* upstream_dev, void* gradT,
-                            int64_t ldG, void* ws, size_t ws_bytes, void* stream);
+                            const double* nll_dev, const double* povm_host,
+                            const double* upstream_dev, void* gradT, int64_t ldG, void* ws,
+                            size_t ws_bytes, void* stream);
 
 /* Workspace in bytes needed by op (a qst_op) at (n_qubits, prec); 0 for an
  * invalid request. */

@@ -134,8 +134,9 @@ def nll(p: torch.Tensor, f: torch.Tensor, prec=None):
 
 
 def nll_backward(T: torch.Tensor, f: torch.Tensor, p: torch.Tensor | None, tau: torch.Tensor | None, prec=None,
-                 povm=None, upstream: torch.Tensor | None = None) -> torch.Tensor:
-    """dL/dRe T + i dL/dIm T (times *upstream).  p=None recomputes rho and p."""
+                 povm=None, upstream: torch.Tensor | None = None, nll_out: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dRe T + i dL/dIm T (times *upstream).  p=None recomputes rho and p;
+    nll_out (the [L, F] tensor of nll()) supplies F = sum f."""
     n, ld = _matrix(T, "T")
     pr = _prec(T.dtype, prec)
     _vector(f, "f", n, real_dtype(pr))
@@ -146,11 +147,14 @@ def nll_backward(T: torch.Tensor, f: torch.Tensor, p: torch.Tensor | None, tau: 
     for name, t in (("tau", tau), ("upstream", upstream)):
         if t is not None and (t.dtype != torch.float64 or t.numel() != 1 or not t.is_cuda):
             raise ValueError(f"{name} must be a one-element float64 GPU tensor")
+    if nll_out is not None and (nll_out.dtype != torch.float64 or nll_out.numel() != 2 or not nll_out.is_cuda
+                                or not nll_out.is_contiguous()):
+        raise ValueError("nll_out must be the contiguous two-element float64 GPU tensor returned by nll()")
     grad = torch.empty(T.shape, dtype=T.dtype, device=T.device)
     ws, nb = _workspace(n, pr, QST_OP_NLL_BACKWARD, T.device)
     _lib.check(_lib.lib().qst_nll_backward(n, pr, T.data_ptr(), ld, f.data_ptr(), _ptr(p), _ptr(tau),
-                                           _povm_arg(povm), _ptr(upstream), grad.data_ptr(), grad.stride(0),
-                                           _ptr(ws), nb, _stream(T.device)), "qst_nll_backward")
+                                           _ptr(nll_out), _povm_arg(povm), _ptr(upstream), grad.data_ptr(),
+                                           grad.stride(0), _ptr(ws), nb, _stream(T.device)), "qst_nll_backward")
     return grad
 
 
@@ -169,18 +173,18 @@ class LikelihoodFn(torch.autograd.Function):
         ctx.povm = povm
         ctx.recompute = bool(recompute)
         if ctx.recompute:
-            ctx.save_for_backward(T, f, tau)
+            ctx.save_for_backward(T, f, tau, out)
         else:
-            ctx.save_for_backward(T, f, tau, p)
-        return out[0]
+            ctx.save_for_backward(T, f, tau, out, p)
+        return out[0].clone()
 
     @staticmethod
     def backward(ctx, g):
         saved = ctx.saved_tensors
-        T, f, tau = saved[0], saved[1], saved[2]
-        p = None if ctx.recompute else saved[3]
+        T, f, tau, out = saved[0], saved[1], saved[2], saved[3]
+        p = None if ctx.recompute else saved[4]
         up = g.detach().to(torch.float64).reshape(1).contiguous()
-        grad = nll_backward(T, f, p, None if p is None else tau, ctx.prec, ctx.povm, up)
+        grad = nll_backward(T, f, p, None if p is None else tau, ctx.prec, ctx.povm, up, out)
         return grad, None, None, None, None
 
 

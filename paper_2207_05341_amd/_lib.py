@@ -21,7 +21,7 @@ SIGNATURES = {
     "qst_state_map": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
     "qst_povm_probs": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     "qst_nll": (_int, [_int, _int, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
-    "qst_nll_backward": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
+    "qst_nll_backward": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_workspace_bytes": (_sz, [_int, _int, _int]),
     "qst_status_string": (ctypes.c_char_p, [_int]),
     "qst_last_error": (ctypes.c_char_p, []),

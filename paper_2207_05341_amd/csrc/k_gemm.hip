@@ -10,129 +10,383 @@
 // computed and each off-diagonal tile is also written to its mirror
 // position as the conjugate transpose.
 //
-// Tiles: 256 threads (4 wave64), 64 x 64 complex output per workgroup, each
-// wave a 32 x 32 quadrant as 2 x 2 MFMA 16 x 16 blocks.  Operand panels are
-// staged through LDS with the next panel prefetched into registers while
-// the current one is consumed.
+// Tiles: 256 threads (4 wave64), 64 x 64 complex output per tile, each wave a
+// 32 x 32 quadrant as 2 x 2 MFMA 16 x 16 blocks.  Operand panels are staged
+// through LDS with the next panel prefetched into registers while the
+// current one is consumed.
+//
+// Scheduling: when the tile count divides evenly over the compute units,
+// one workgroup computes one tile.  Otherwise (the 528 lower tiles of
+// T T^dagger at d = 2048 land 2 or 3 per CU) the kernel runs stream-K: a
+// grid of P workgroups, each taking an equal contiguous share of the
+// (tile, K panel) iterations.  A tile cut between workgroups leaves partial
+// accumulators in the workspace (at most two per workgroup), and a fix-up
+// kernel adds them in K order -- no atomics, so results are deterministic.
+#include <algorithm>
+
 #include "qst_device.h"
 #include "qst_kernels.h"
+#include "qst_plan.h"
 
 namespace qst {
 
 namespace {
 
-constexpr int BM = 64;     // output tile (complex)
-constexpr int BK = 16;     // K panel for fp32/fp64 (complex)
-constexpr int PADC = 1;    // LDS row padding (complex elements)
-constexpr int BKH = 32;    // K panel for bf16 (complex) = one MFMA K step
-constexpr int PADH = 8;    // LDS row padding (bf16 elements)
+constexpr int BM = 64;    // output tile (complex)
+constexpr int PADC = 1;   // LDS row padding (complex elements), fp32/fp64 panels
+constexpr int PADH = 8;   // LDS row padding (bf16 elements), bf16 panels
+constexpr int TILE = BM * BM;
+
+struct GemmArgs {
+  const void* A;
+  int64_t lda;
+  const void* B;
+  int64_t ldb;
+  void* C;
+  int64_t ldc;
+  int d;
+  const double* tau;
+  const double* up;
+  int ntiles;     // output tiles
+  int kIters;     // K panels per tile
+  int64_t iters;  // ntiles * kIters
+  void* partial;  // stream-K partial accumulators [P][2][2 * TILE] (acc scalar)
+  const double* tau_part;  // HERK: FP64 partial sums of tau (kReduceBlocks), or NULL to read *tau
+  double* tau_out;         // HERK with tau_part: where workgroup 0 stores tau
+};
 
 // ---------------------------------------------------------------------------
-// fp32 / fp64 MFMA kernel.  HERK: C = A A^dagger (A = B = T), lower tiles.
-// HEMM: C = A B (A = G', B = T), all tiles.
+// Policies: one K-panel loop per (precision, product) with a common
+// accumulator shape acc[2][2] re/im, 4 values per lane.
 // ---------------------------------------------------------------------------
 template <typename R, bool HERK>
-__global__ __launch_bounds__(256) void gemm_cx_kernel(const Cx<R>* __restrict__ A, int64_t lda,
-                                                      const Cx<R>* __restrict__ B, int64_t ldb,
-                                                      Cx<R>* __restrict__ C, int64_t ldc, int d,
-                                                      const double* __restrict__ tau_dev,
-                                                      const double* __restrict__ upstream_dev) {
+struct CxPolicy {
+  typedef R scalar;
   typedef typename Mfma<R>::acc acc_t;
-  __shared__ Cx<R> As[BK][BM + PADC];
-  __shared__ Cx<R> Bs[BK][BM + PADC];
-
-  const int tiles = d / BM;
-  int tr, tc;
-  if constexpr (HERK) {
-    tri_decode(blockIdx.x, tr, tc);
-  } else {
-    tr = blockIdx.x / tiles;
-    tc = blockIdx.x % tiles;
-  }
-  const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
-  const int t = threadIdx.x;
-  const int lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int li = lane & 15, lk = lane >> 4;
-
-  // global -> register mapping
-  const int a_row = t >> 2, a_k = (t & 3) * 4;                  // A panel: 64 rows x 16 k
-  const int hb_k = t >> 4, hb_n = (t & 15) * 4;                 // HEMM B panel: 16 k x 64 n
-  const Cx<R>* Ap = A + (R0 + a_row) * lda + a_k;
-  const Cx<R>* Bp = HERK ? (B + (C0 + a_row) * ldb + a_k) : (B + int64_t(hb_k) * ldb + C0 + hb_n);
-
-  Cx<R> ra[4], rb[4];
-  auto load_panel = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ra[i] = Ap[k0 + i];
-    if constexpr (HERK) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) rb[i] = Bp[k0 + i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) rb[i] = Bp[int64_t(k0) * ldb + i];
-    }
+  static constexpr int KP = 16;  // complex K per panel
+  static constexpr bool kHerk = HERK;
+  static constexpr bool kStreamK = true;
+  struct Smem {
+    Cx<R> As[KP][BM + PADC];
+    Cx<R> Bs[KP][BM + PADC];
   };
+  static __device__ __forceinline__ int row(int q, int v) { return Mfma<R>::row(q, v); }
 
-  acc_t accR[2][2], accI[2][2];
+  static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
+                                             acc_t (&aR)[2][2], acc_t (&aI)[2][2]) {
+    const Cx<R>* A = static_cast<const Cx<R>*>(g.A);
+    const Cx<R>* B = static_cast<const Cx<R>*>(g.B);
+    const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    const int a_row = t >> 2, a_k = (t & 3) * 4;   // A panel: 64 rows x 16 k
+    const int hb_k = t >> 4, hb_n = (t & 15) * 4;  // HEMM B panel: 16 k x 64 n
+    const Cx<R>* Ap = A + (R0 + a_row) * g.lda + a_k;
+    const Cx<R>* Bp = HERK ? (B + (C0 + a_row) * g.ldb + a_k) : (B + int64_t(hb_k) * g.ldb + C0 + hb_n);
+    // register prefetch of the next panel (written out, not via a lambda:
+    // captured arrays would be kept in scratch memory)
+    // (held as native 2-vectors: an aligned struct array would go to scratch)
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2* Av = reinterpret_cast<const v2*>(Ap);
+    const v2* Bv = reinterpret_cast<const v2*>(Bp);
+    v2 ra[4], rb[4];
+#define QST_LOAD_PANEL(kp)                                                   \
+  do {                                                                       \
+    const int k0_ = (kp) * KP;                                               \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) ra[i] = Av[k0_ + i];       \
+    if constexpr (HERK) {                                                    \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) rb[i] = Bv[k0_ + i];     \
+    } else {                                                                 \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) rb[i] = Bv[int64_t(k0_) * g.ldb + i]; \
+    }                                                                        \
+  } while (0)
+    QST_LOAD_PANEL(kb);
+    for (int kp = kb; kp < ke; ++kp) {
+      __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i) sm.As[a_k + i][a_row] = Cx<R>{ra[i].x, ra[i].y};
+      if constexpr (HERK) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      accR[i][j] = acc_t{0, 0, 0, 0};
-      accI[i][j] = acc_t{0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) sm.Bs[a_k + i][a_row] = Cx<R>{rb[i].x, rb[i].y};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sm.Bs[hb_k][hb_n + i] = Cx<R>{rb[i].x, rb[i].y};
+      }
+      __syncthreads();
+      if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
+#undef QST_LOAD_PANEL
+#pragma unroll
+      for (int ks = 0; ks < KP / 4; ++ks) {
+        const int kk = ks * 4 + lk;
+        Cx<R> a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = sm.As[kk][wr * 32 + i * 16 + li];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = sm.Bs[kk][wc * 32 + j * 16 + li];
+        // eight independent accumulator chains, each advanced once per sweep
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            aR[i][j] = Mfma<R>::step(a[i].re, b[j].re, aR[i][j]);
+            aI[i][j] = Mfma<R>::step(HERK ? a[i].im : a[i].re, HERK ? b[j].re : b[j].im, aI[i][j]);
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            // HERK: re += ai bi, im -= ar bi;  HEMM: re -= ai bi, im += ai br
+            aR[i][j] = Mfma<R>::step(HERK ? a[i].im : -a[i].im, b[j].im, aR[i][j]);
+            aI[i][j] = Mfma<R>::step(HERK ? -a[i].re : a[i].im, HERK ? b[j].im : b[j].re, aI[i][j]);
+          }
+      }
     }
+  }
+};
 
-  load_panel(0);
-  for (int k0 = 0; k0 < d; k0 += BK) {
-    __syncthreads();
+// T T^dagger with T rounded to bf16 (RNE), fp32 accumulate.
+struct HerkBf16Policy {
+  typedef float scalar;
+  typedef f4 acc_t;
+  static constexpr int KP = 32;  // one MFMA K step
+  static constexpr bool kHerk = true;
+  static constexpr bool kStreamK = false;  // load-bound: splitting K only adds partial traffic
+  struct Smem {
+    uint16_t Ar[BM][KP + PADH], Ai[BM][KP + PADH], Br[BM][KP + PADH], Bi[BM][KP + PADH];
+  };
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+
+  static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
+                                             acc_t (&aR)[2][2], acc_t (&aI)[2][2]) {
+    const Cx<float>* T = static_cast<const Cx<float>*>(g.A);
+    const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int li = lane & 15, lq = lane >> 4;
+    const int row = t >> 2, kq = (t & 3) * 8;  // 64 rows x 32 k, 8 complex per thread
+    const Cx<float>* Ap = T + (R0 + row) * g.lda + kq;
+    const Cx<float>* Bp = T + (C0 + row) * g.lda + kq;
+    Cx<float> ra[8], rb[8];
+#define QST_LOAD_PANEL(kp)                                 \
+  do {                                                     \
+    const int k0_ = (kp) * KP;                             \
+    _Pragma("unroll") for (int i = 0; i < 8; ++i) {        \
+      ra[i] = Ap[k0_ + i];                                 \
+      rb[i] = Bp[k0_ + i];                                 \
+    }                                                      \
+  } while (0)
+    QST_LOAD_PANEL(kb);
+    for (int kp = kb; kp < ke; ++kp) {
+      __syncthreads();
+      {
+        u16x8 xr, xi, yr, yi;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) As[a_k + i][a_row] = ra[i];
-    if constexpr (HERK) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Bs[a_k + i][a_row] = rb[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Bs[hb_k][hb_n + i] = rb[i];
-    }
-    __syncthreads();
-    if (k0 + BK < d) load_panel(k0 + BK);
-#pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int kk = ks * 4 + lk;
-      Cx<R> a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kk][wr * 32 + i * 16 + li];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kk][wc * 32 + j * 16 + li];
+        for (int i = 0; i < 8; ++i) {
+          xr[i] = bf16_bits(ra[i].re);
+          xi[i] = bf16_bits(ra[i].im);
+          yr[i] = bf16_bits(rb[i].re);
+          yi[i] = bf16_bits(rb[i].im);
+        }
+        *reinterpret_cast<u16x8*>(&sm.Ar[row][kq]) = xr;
+        *reinterpret_cast<u16x8*>(&sm.Ai[row][kq]) = xi;
+        *reinterpret_cast<u16x8*>(&sm.Br[row][kq]) = yr;
+        *reinterpret_cast<u16x8*>(&sm.Bi[row][kq]) = yi;
+      }
+      __syncthreads();
+      if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
+#undef QST_LOAD_PANEL
+      u16x8 a_r[2], a_i[2], b_r[2], b_i[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
+        a_r[i] = *reinterpret_cast<const u16x8*>(&sm.Ar[wr * 32 + i * 16 + li][lq * 8]);
+        a_i[i] = *reinterpret_cast<const u16x8*>(&sm.Ai[wr * 32 + i * 16 + li][lq * 8]);
+        b_r[i] = *reinterpret_cast<const u16x8*>(&sm.Br[wc * 32 + i * 16 + li][lq * 8]);
+        b_i[i] = *reinterpret_cast<const u16x8*>(&sm.Bi[wc * 32 + i * 16 + li][lq * 8]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          if constexpr (HERK) {
-            accR[i][j] = Mfma<R>::step(a[i].re, b[j].re, accR[i][j]);
-            accR[i][j] = Mfma<R>::step(a[i].im, b[j].im, accR[i][j]);
-            accI[i][j] = Mfma<R>::step(a[i].im, b[j].re, accI[i][j]);
-            accI[i][j] = Mfma<R>::step(-a[i].re, b[j].im, accI[i][j]);
-          } else {
-            accR[i][j] = Mfma<R>::step(a[i].re, b[j].re, accR[i][j]);
-            accR[i][j] = Mfma<R>::step(-a[i].im, b[j].im, accR[i][j]);
-            accI[i][j] = Mfma<R>::step(a[i].re, b[j].im, accI[i][j]);
-            accI[i][j] = Mfma<R>::step(a[i].im, b[j].re, accI[i][j]);
-          }
+          aR[i][j] = mfma_bf16(a_r[i], b_r[j], aR[i][j]);
+          aI[i][j] = mfma_bf16(a_i[i], b_r[j], aI[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const u16x8 na = bf16_neg(a_r[i]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          aR[i][j] = mfma_bf16(a_i[i], b_i[j], aR[i][j]);
+          aI[i][j] = mfma_bf16(na, b_i[j], aI[i][j]);
         }
       }
     }
   }
+};
 
-  double scale;
-  if constexpr (HERK) {
-    scale = 1.0 / *tau_dev;
-  } else {
-    scale = 2.0 / *tau_dev;
-    if (upstream_dev) scale *= *upstream_dev;
+// G' T with split-bf16 operands: x = hi + lo, hi = bf16(x), lo = bf16(x - hi);
+// the product keeps hi*hi + hi*lo + lo*hi (lo*lo is below fp32 rounding).
+struct HemmBf16x3Policy {
+  typedef float scalar;
+  typedef f4 acc_t;
+  static constexpr int KP = 32;
+  static constexpr bool kHerk = false;
+  static constexpr bool kStreamK = true;
+  struct Smem {
+    uint16_t As[4][BM][KP + PADH];  // re_hi, im_hi, re_lo, im_lo
+    uint16_t Bt[4][BM][KP + PADH];  // transposed: [n][k]
+  };
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+
+  static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
+                                             acc_t (&aR)[2][2], acc_t (&aI)[2][2]) {
+    const Cx<float>* G = static_cast<const Cx<float>*>(g.A);
+    const Cx<float>* T = static_cast<const Cx<float>*>(g.B);
+    const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int li = lane & 15, lq = lane >> 4;
+    const int a_row = t >> 2, a_k = (t & 3) * 8;  // A panel: 64 rows x 32 k
+    const int b_k = t >> 3, b_n = (t & 7) * 8;    // B panel: 32 k x 64 n
+    const Cx<float>* Ap = G + (R0 + a_row) * g.lda + a_k;
+    const Cx<float>* Bp = T + int64_t(b_k) * g.ldb + C0 + b_n;
+    Cx<float> ra[8], rb[8];
+#define QST_LOAD_PANEL(kp)                                 \
+  do {                                                     \
+    const int k0_ = (kp) * KP;                             \
+    _Pragma("unroll") for (int i = 0; i < 8; ++i) {        \
+      ra[i] = Ap[k0_ + i];                                 \
+      rb[i] = Bp[int64_t(k0_) * g.ldb + i];                \
+    }                                                      \
+  } while (0)
+    QST_LOAD_PANEL(kb);
+    for (int kp = kb; kp < ke; ++kp) {
+      __syncthreads();
+      {
+        u16x8 h0, h1, l0, l1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint16_t hr = bf16_bits(ra[i].re), hm = bf16_bits(ra[i].im);
+          h0[i] = hr;
+          h1[i] = hm;
+          l0[i] = bf16_bits(ra[i].re - __uint_as_float(uint32_t(hr) << 16));
+          l1[i] = bf16_bits(ra[i].im - __uint_as_float(uint32_t(hm) << 16));
+        }
+        *reinterpret_cast<u16x8*>(&sm.As[0][a_row][a_k]) = h0;
+        *reinterpret_cast<u16x8*>(&sm.As[1][a_row][a_k]) = h1;
+        *reinterpret_cast<u16x8*>(&sm.As[2][a_row][a_k]) = l0;
+        *reinterpret_cast<u16x8*>(&sm.As[3][a_row][a_k]) = l1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint16_t hr = bf16_bits(rb[i].re), hm = bf16_bits(rb[i].im);
+          sm.Bt[0][b_n + i][b_k] = hr;
+          sm.Bt[1][b_n + i][b_k] = hm;
+          sm.Bt[2][b_n + i][b_k] = bf16_bits(rb[i].re - __uint_as_float(uint32_t(hr) << 16));
+          sm.Bt[3][b_n + i][b_k] = bf16_bits(rb[i].im - __uint_as_float(uint32_t(hm) << 16));
+        }
+      }
+      __syncthreads();
+      if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
+#undef QST_LOAD_PANEL
+      u16x8 a[2][4], b[2][4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+          a[i][pl] = *reinterpret_cast<const u16x8*>(&sm.As[pl][wr * 32 + i * 16 + li][lq * 8]);
+          b[i][pl] = *reinterpret_cast<const u16x8*>(&sm.Bt[pl][wc * 32 + i * 16 + li][lq * 8]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const u16x8 nih = bf16_neg(a[i][1]), nil = bf16_neg(a[i][3]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          // complex: re = ar br - ai bi, im = ar bi + ai br;  hi*hi, hi*lo, lo*hi
+          aR[i][j] = mfma_bf16(a[i][0], b[j][0], aR[i][j]);
+          aR[i][j] = mfma_bf16(nih, b[j][1], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[i][0], b[j][1], aI[i][j]);
+          aI[i][j] = mfma_bf16(a[i][1], b[j][0], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[i][0], b[j][2], aR[i][j]);
+          aR[i][j] = mfma_bf16(nih, b[j][3], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[i][0], b[j][3], aI[i][j]);
+          aI[i][j] = mfma_bf16(a[i][1], b[j][2], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[i][2], b[j][0], aR[i][j]);
+          aR[i][j] = mfma_bf16(nil, b[j][1], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[i][2], b[j][1], aI[i][j]);
+          aI[i][j] = mfma_bf16(a[i][3], b[j][0], aI[i][j]);
+        }
+      }
+    }
   }
+};
+
+// ---------------------------------------------------------------------------
+// Shared tile plumbing
+// ---------------------------------------------------------------------------
+template <class P>
+__device__ __forceinline__ void tile_coords(const GemmArgs& g, int tile, int& tr, int& tc) {
+  if constexpr (P::kHerk) {
+    tri_decode(tile, tr, tc);
+  } else {
+    const int tiles = g.d / BM;
+    tr = tile / tiles;
+    tc = tile % tiles;
+  }
+}
+
+template <class P>
+__device__ __forceinline__ void zero_acc(typename P::acc_t (&aR)[2][2], typename P::acc_t (&aI)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      aR[i][j] = typename P::acc_t{0, 0, 0, 0};
+      aI[i][j] = typename P::acc_t{0, 0, 0, 0};
+    }
+}
+
+// Output scale, evaluated by every workgroup at its start: 1/tau for
+// T T^dagger, s * 2/tau for G' T.  With tau partials, tau is their sum in a
+// fixed order (bitwise the same in every workgroup), and workgroup 0 stores it.
+template <class P>
+__device__ double tile_scale(const GemmArgs& g) {
+  double tau;
+  if (g.tau_part) {
+    __shared__ double red[4];
+    __shared__ double bcast;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < kReduceBlocks; b += blockDim.x) acc += g.tau_part[b];
+    const double sum = block_sum256(acc, red);
+    if (threadIdx.x == 0) {
+      bcast = sum;
+      if (blockIdx.x == 0 && g.tau_out) *g.tau_out = sum;
+    }
+    __syncthreads();
+    tau = bcast;
+  } else {
+    tau = *g.tau;
+  }
+  if constexpr (P::kHerk) {
+    return 1.0 / tau;
+  } else {
+    double s = 2.0 / tau;
+    if (g.up) s *= *g.up;
+    return s;
+  }
+}
+
+template <class P>
+__device__ __forceinline__ void epilogue(const GemmArgs& g, int tr, int tc, typename P::acc_t (&aR)[2][2],
+                                         typename P::acc_t (&aI)[2][2], double scale) {
+  typedef typename P::scalar R;
+  Cx<R>* C = static_cast<Cx<R>*>(g.C);
   const R sc = R(scale);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1, li = lane & 15, lq = lane >> 4;
+  const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
 #pragma unroll
@@ -141,219 +395,117 @@ __global__ __launch_bounds__(256) void gemm_cx_kernel(const Cx<R>* __restrict__ 
       const int64_t rbase = R0 + wr * 32 + i * 16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = rbase + Mfma<R>::row(lk, v);
-        C[row * ldc + col] = Cx<R>{accR[i][j][v] * sc, accI[i][j][v] * sc};
-        if (HERK && tr != tc) C[col * ldc + row] = Cx<R>{accR[i][j][v] * sc, -accI[i][j][v] * sc};
+        const int64_t row = rbase + P::row(lq, v);
+        C[row * g.ldc + col] = Cx<R>{aR[i][j][v] * sc, aI[i][j][v] * sc};
+        if (P::kHerk && tr != tc) C[col * g.ldc + row] = Cx<R>{aR[i][j][v] * sc, -aI[i][j][v] * sc};
       }
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// bf16 MFMA kernel for T T^dagger: T rounded to bf16 (RNE), fp32 accumulate.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void herk_bf16_kernel(const Cx<float>* __restrict__ T, int64_t ldt,
-                                                        Cx<float>* __restrict__ C, int64_t ldc, int d,
-                                                        const double* __restrict__ tau_dev) {
-  __shared__ __align__(16) uint16_t Ar[BM][BKH + PADH], Ai[BM][BKH + PADH];
-  __shared__ __align__(16) uint16_t Br[BM][BKH + PADH], Bi[BM][BKH + PADH];
+// Partial accumulators of one tile segment, stored per lane in the MFMA
+// layout: element ((((w*2 + i)*2 + j)*2 + part)*4 + v)*64 + lane.
+template <class P>
+__device__ __forceinline__ typename P::scalar* partial_slot(const GemmArgs& g, int wg, int which) {
+  return static_cast<typename P::scalar*>(g.partial) + (int64_t(wg) * 2 + which) * int64_t(2 * TILE);
+}
+
+template <class P>
+__device__ __forceinline__ void store_partial(typename P::scalar* dst, typename P::acc_t (&aR)[2][2],
+                                              typename P::acc_t (&aI)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        dst[((((w * 2 + i) * 2 + j) * 2 + 0) * 4 + v) * 64 + lane] = aR[i][j][v];
+        dst[((((w * 2 + i) * 2 + j) * 2 + 1) * 4 + v) * 64 + lane] = aI[i][j][v];
+      }
+}
+
+template <class P>
+__device__ __forceinline__ void add_partial(const typename P::scalar* src, typename P::acc_t (&aR)[2][2],
+                                            typename P::acc_t (&aI)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        aR[i][j][v] += src[((((w * 2 + i) * 2 + j) * 2 + 0) * 4 + v) * 64 + lane];
+        aI[i][j][v] += src[((((w * 2 + i) * 2 + j) * 2 + 1) * 4 + v) * 64 + lane];
+      }
+}
+
+// First iteration owned by stream-K workgroup w of P.
+__device__ __forceinline__ int64_t sk_start(int64_t w, int64_t P, int64_t iters) { return (w * iters) / P; }
+
+// One tile per workgroup.
+template <class P>
+__global__ __launch_bounds__(256) void gemm_dp_kernel(GemmArgs g) {
+  __shared__ typename P::Smem sm;
+  typename P::acc_t aR[2][2], aI[2][2];
+  const double scale = tile_scale<P>(g);
   int tr, tc;
-  tri_decode(blockIdx.x, tr, tc);
-  const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
-  const int t = threadIdx.x;
-  const int lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int li = lane & 15, lq = lane >> 4;
-  const int row = t >> 2, kq = (t & 3) * 8;  // 64 rows x 32 k, 8 complex per thread
-  const Cx<float>* Ap = T + (R0 + row) * ldt + kq;
-  const Cx<float>* Bp = T + (C0 + row) * ldt + kq;
+  tile_coords<P>(g, blockIdx.x, tr, tc);
+  zero_acc<P>(aR, aI);
+  P::run(g, sm, tr, tc, 0, g.kIters, aR, aI);
+  epilogue<P>(g, tr, tc, aR, aI, scale);
+}
 
-  Cx<float> ra[8], rb[8];
-  auto load_panel = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ra[i] = Ap[k0 + i];
-      rb[i] = Bp[k0 + i];
+// Stream-K: workgroup w owns iterations [start(w), start(w+1)).
+template <class P>
+__global__ __launch_bounds__(256) void gemm_sk_kernel(GemmArgs g) {
+  __shared__ typename P::Smem sm;
+  typename P::acc_t aR[2][2], aI[2][2];
+  const int64_t Pn = gridDim.x, w = blockIdx.x;
+  const double scale = tile_scale<P>(g);
+  int64_t it = sk_start(w, Pn, g.iters);
+  const int64_t end = sk_start(w + 1, Pn, g.iters);
+  const int first_tile = int(it / g.kIters);
+  while (it < end) {
+    const int tile = int(it / g.kIters);
+    const int kb = int(it % g.kIters);
+    const int ke = int(min(int64_t(g.kIters), int64_t(kb) + (end - it)));
+    int tr, tc;
+    tile_coords<P>(g, tile, tr, tc);
+    zero_acc<P>(aR, aI);
+    P::run(g, sm, tr, tc, kb, ke, aR, aI);
+    if (kb == 0 && ke == g.kIters) {
+      epilogue<P>(g, tr, tc, aR, aI, scale);
+    } else {
+      store_partial<P>(partial_slot<P>(g, int(w), tile == first_tile ? 0 : 1), aR, aI);
     }
-  };
-  f4 accR[2][2], accI[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      accR[i][j] = f4{0, 0, 0, 0};
-      accI[i][j] = f4{0, 0, 0, 0};
-    }
-  load_panel(0);
-  for (int k0 = 0; k0 < d; k0 += BKH) {
-    __syncthreads();
-    {
-      u16x8 xr, xi, yr, yi;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        xr[i] = bf16_bits(ra[i].re);
-        xi[i] = bf16_bits(ra[i].im);
-        yr[i] = bf16_bits(rb[i].re);
-        yi[i] = bf16_bits(rb[i].im);
-      }
-      *reinterpret_cast<u16x8*>(&Ar[row][kq]) = xr;
-      *reinterpret_cast<u16x8*>(&Ai[row][kq]) = xi;
-      *reinterpret_cast<u16x8*>(&Br[row][kq]) = yr;
-      *reinterpret_cast<u16x8*>(&Bi[row][kq]) = yi;
-    }
-    __syncthreads();
-    if (k0 + BKH < d) load_panel(k0 + BKH);
-    u16x8 a_r[2], a_i[2], b_r[2], b_i[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      a_r[i] = *reinterpret_cast<const u16x8*>(&Ar[wr * 32 + i * 16 + li][lq * 8]);
-      a_i[i] = *reinterpret_cast<const u16x8*>(&Ai[wr * 32 + i * 16 + li][lq * 8]);
-      b_r[i] = *reinterpret_cast<const u16x8*>(&Br[wc * 32 + i * 16 + li][lq * 8]);
-      b_i[i] = *reinterpret_cast<const u16x8*>(&Bi[wc * 32 + i * 16 + li][lq * 8]);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const u16x8 na = bf16_neg(a_r[i]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        accR[i][j] = mfma_bf16(a_r[i], b_r[j], accR[i][j]);
-        accR[i][j] = mfma_bf16(a_i[i], b_i[j], accR[i][j]);
-        accI[i][j] = mfma_bf16(a_i[i], b_r[j], accI[i][j]);
-        accI[i][j] = mfma_bf16(na, b_i[j], accI[i][j]);
-      }
-    }
-  }
-  const float sc = float(1.0 / *tau_dev);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t col = C0 + wc * 32 + j * 16 + li;
-      const int64_t row0 = R0 + wr * 32 + i * 16 + lq * 4;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) C[(row0 + v) * ldc + col] = Cx<float>{accR[i][j][v] * sc, accI[i][j][v] * sc};
-      if (tr != tc) {
-        Cx<float>* dst = C + col * ldc + row0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dst[v] = Cx<float>{accR[i][j][v] * sc, -accI[i][j][v] * sc};
-      }
-    }
+    it += ke - kb;
   }
 }
 
-// ---------------------------------------------------------------------------
-// Split-bf16 MFMA kernel for grad = s (2/tau) G' T: each operand x = hi + lo
-// with hi = bf16(x), lo = bf16(x - hi); the product keeps hi*hi + hi*lo +
-// lo*hi (the lo*lo term is below fp32 rounding of the sum).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void hemm_bf16x3_kernel(const Cx<float>* __restrict__ G, int64_t ldg,
-                                                          const Cx<float>* __restrict__ T, int64_t ldt,
-                                                          Cx<float>* __restrict__ C, int64_t ldc, int d,
-                                                          const double* __restrict__ tau_dev,
-                                                          const double* __restrict__ upstream_dev) {
-  // plane order: re_hi, im_hi, re_lo, im_lo
-  __shared__ __align__(16) uint16_t As[4][BM][BKH + PADH];
-  __shared__ __align__(16) uint16_t Bt[4][BM][BKH + PADH];  // transposed: [n][k]
-  const int tiles = d / BM;
-  const int tr = blockIdx.x / tiles, tc = blockIdx.x % tiles;
-  const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
-  const int t = threadIdx.x;
-  const int lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int li = lane & 15, lq = lane >> 4;
-  const int a_row = t >> 2, a_k = (t & 3) * 8;   // A panel: 64 rows x 32 k
-  const int b_k = t >> 3, b_n = (t & 7) * 8;     // B panel: 32 k x 64 n
-  const Cx<float>* Ap = G + (R0 + a_row) * ldg + a_k;
-  const Cx<float>* Bp = T + int64_t(b_k) * ldt + C0 + b_n;
-
-  Cx<float> ra[8], rb[8];
-  auto load_panel = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ra[i] = Ap[k0 + i];
-      rb[i] = Bp[int64_t(k0) * ldt + i];
-    }
-  };
-  f4 accR[2][2], accI[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      accR[i][j] = f4{0, 0, 0, 0};
-      accI[i][j] = f4{0, 0, 0, 0};
-    }
-  load_panel(0);
-  for (int k0 = 0; k0 < d; k0 += BKH) {
-    __syncthreads();
-    {
-      u16x8 h0, h1, l0, l1;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const uint16_t hr = bf16_bits(ra[i].re), hi = bf16_bits(ra[i].im);
-        h0[i] = hr;
-        h1[i] = hi;
-        l0[i] = bf16_bits(ra[i].re - __uint_as_float(uint32_t(hr) << 16));
-        l1[i] = bf16_bits(ra[i].im - __uint_as_float(uint32_t(hi) << 16));
-      }
-      *reinterpret_cast<u16x8*>(&As[0][a_row][a_k]) = h0;
-      *reinterpret_cast<u16x8*>(&As[1][a_row][a_k]) = h1;
-      *reinterpret_cast<u16x8*>(&As[2][a_row][a_k]) = l0;
-      *reinterpret_cast<u16x8*>(&As[3][a_row][a_k]) = l1;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const uint16_t hr = bf16_bits(rb[i].re), hi = bf16_bits(rb[i].im);
-        Bt[0][b_n + i][b_k] = hr;
-        Bt[1][b_n + i][b_k] = hi;
-        Bt[2][b_n + i][b_k] = bf16_bits(rb[i].re - __uint_as_float(uint32_t(hr) << 16));
-        Bt[3][b_n + i][b_k] = bf16_bits(rb[i].im - __uint_as_float(uint32_t(hi) << 16));
-      }
-    }
-    __syncthreads();
-    if (k0 + BKH < d) load_panel(k0 + BKH);
-    u16x8 a[2][4], b[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) {
-        a[i][pl] = *reinterpret_cast<const u16x8*>(&As[pl][wr * 32 + i * 16 + li][lq * 8]);
-        b[i][pl] = *reinterpret_cast<const u16x8*>(&Bt[pl][wc * 32 + i * 16 + li][lq * 8]);
-      }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const u16x8 nih = bf16_neg(a[i][1]), nil = bf16_neg(a[i][3]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        // (Ah + Al)(Bh + Bl) without Al Bl; complex: re = ar br - ai bi, im = ar bi + ai br
-        // hi * hi
-        accR[i][j] = mfma_bf16(a[i][0], b[j][0], accR[i][j]);
-        accR[i][j] = mfma_bf16(nih, b[j][1], accR[i][j]);
-        accI[i][j] = mfma_bf16(a[i][0], b[j][1], accI[i][j]);
-        accI[i][j] = mfma_bf16(a[i][1], b[j][0], accI[i][j]);
-        // hi * lo
-        accR[i][j] = mfma_bf16(a[i][0], b[j][2], accR[i][j]);
-        accR[i][j] = mfma_bf16(nih, b[j][3], accR[i][j]);
-        accI[i][j] = mfma_bf16(a[i][0], b[j][3], accI[i][j]);
-        accI[i][j] = mfma_bf16(a[i][1], b[j][2], accI[i][j]);
-        // lo * hi
-        accR[i][j] = mfma_bf16(a[i][2], b[j][0], accR[i][j]);
-        accR[i][j] = mfma_bf16(nil, b[j][1], accR[i][j]);
-        accI[i][j] = mfma_bf16(a[i][2], b[j][1], accI[i][j]);
-        accI[i][j] = mfma_bf16(a[i][3], b[j][0], accI[i][j]);
-      }
-    }
+// Sum the partial segments of every tile that stream-K cut, in K order.
+template <class P>
+__global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g, int Pn) {
+  const int tile = blockIdx.x;
+  const int64_t kb = int64_t(tile) * g.kIters, kl = kb + g.kIters - 1;
+  // workgroups owning the first and the last iteration of the tile
+  int64_t wlo = (kb * Pn) / g.iters;
+  while (wlo + 1 < Pn && sk_start(wlo + 1, Pn, g.iters) <= kb) ++wlo;
+  while (wlo > 0 && sk_start(wlo, Pn, g.iters) > kb) --wlo;
+  int64_t whi = (kl * Pn) / g.iters;
+  while (whi + 1 < Pn && sk_start(whi + 1, Pn, g.iters) <= kl) ++whi;
+  while (whi > 0 && sk_start(whi, Pn, g.iters) > kl) --whi;
+  if (wlo == whi) return;  // whole tile inside one workgroup: already written
+  const double scale = tile_scale<P>(g);
+  typename P::acc_t aR[2][2], aI[2][2];
+  zero_acc<P>(aR, aI);
+  for (int64_t w = wlo; w <= whi; ++w) {
+    const int first_tile = int(sk_start(w, Pn, g.iters) / g.kIters);
+    add_partial<P>(partial_slot<P>(g, int(w), tile == first_tile ? 0 : 1), aR, aI);
   }
-  double scale = 2.0 / *tau_dev;
-  if (upstream_dev) scale *= *upstream_dev;
-  const float sc = float(scale);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t col = C0 + wc * 32 + j * 16 + li;
-      const int64_t row0 = R0 + wr * 32 + i * 16 + lq * 4;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) C[(row0 + v) * ldc + col] = Cx<float>{accR[i][j][v] * sc, accI[i][j][v] * sc};
-    }
+  int tr, tc;
+  tile_coords<P>(g, tile, tr, tc);
+  epilogue<P>(g, tr, tc, aR, aI, scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,10 +556,63 @@ __global__ void hemm_small_kernel(const Cx<R>* __restrict__ G, int64_t ldg, cons
   C[int64_t(i) * ldc + j] = Cx<R>{R(sr * scale), R(si * scale)};
 }
 
+// Compute units of the current device (cached per device).
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
+// Workgroups of gemm_sk_kernel<P> resident per CU (queried once per process).
+template <class P>
+int sk_occupancy() {
+  static int occ = 0;
+  if (occ == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_sk_kernel<P>, 256, 0) != hipSuccess || n <= 0) n = 1;
+    occ = n;
+  }
+  return occ;
+}
+
+template <class P>
+hipError_t run_gemm(GemmArgs g, hipStream_t s) {
+  g.kIters = g.d / P::KP;
+  g.iters = int64_t(g.ntiles) * g.kIters;
+  const int cus = device_cus();
+  bool sk = P::kStreamK && g.partial != nullptr && g.ntiles % cus != 0;
+  int64_t Pn = 0;
+  if (sk) {
+    const int64_t min_iters = 32;  // at least 32 K panels per stream-K workgroup
+    const int occ = std::min(sk_occupancy<P>(), 4);
+    Pn = std::min<int64_t>(int64_t(kStreamKMaxGrid), std::min<int64_t>(int64_t(cus) * occ, g.iters / min_iters));
+    Pn = (Pn / cus) * cus;  // whole waves of workgroups over the compute units
+    sk = Pn >= cus;
+  }
+  if (!sk) {
+    gemm_dp_kernel<P><<<unsigned(g.ntiles), 256, 0, s>>>(g);
+    return hipGetLastError();
+  }
+  gemm_sk_kernel<P><<<unsigned(Pn), 256, 0, s>>>(g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  GemmArgs gf = g;
+  gf.tau_out = nullptr;
+  gemm_fixup_kernel<P><<<unsigned(g.ntiles), 256, 0, s>>>(gf, int(Pn));
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int64_t ldr, int n,
-                       const double* tau_dev, hipStream_t s) {
+                       const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s) {
   const int d = 1 << n;
   ProfScope prof(d < BM ? "herk_small" : (prec == QST_F64 ? "herk_f64" : prec == QST_F32 ? "herk_f32" : "herk_bf16"), s);
   if (d < BM) {
@@ -423,25 +628,28 @@ hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int
     return hipGetLastError();
   }
   const int tiles = d / BM;
-  const unsigned blocks = unsigned(tiles * (tiles + 1) / 2);
-  if (prec == QST_F64) {
-    gemm_cx_kernel<double, true><<<blocks, 256, 0, s>>>(static_cast<const Cx<double>*>(T), ldt,
-                                                        static_cast<const Cx<double>*>(T), ldt,
-                                                        static_cast<Cx<double>*>(rho), ldr, d, tau_dev, nullptr);
-  } else if (prec == QST_F32) {
-    gemm_cx_kernel<float, true><<<blocks, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ldt,
-                                                       static_cast<const Cx<float>*>(T), ldt,
-                                                       static_cast<Cx<float>*>(rho), ldr, d, tau_dev, nullptr);
-  } else {
-    herk_bf16_kernel<<<blocks, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ldt,
-                                            static_cast<Cx<float>*>(rho), ldr, d, tau_dev);
-  }
-  return hipGetLastError();
+  GemmArgs g{};
+  g.A = T;
+  g.lda = ldt;
+  g.B = T;
+  g.ldb = ldt;
+  g.C = rho;
+  g.ldc = ldr;
+  g.d = d;
+  g.tau = tau_dev;
+  g.up = nullptr;
+  g.ntiles = tiles * (tiles + 1) / 2;
+  g.partial = sk_partial;
+  g.tau_part = tau_partials;
+  g.tau_out = tau_partials ? tau_dev : nullptr;
+  if (prec == QST_F64) return run_gemm<CxPolicy<double, true>>(g, s);
+  if (prec == QST_F32) return run_gemm<CxPolicy<float, true>>(g, s);
+  return run_gemm<HerkBf16Policy>(g, s);
 }
 
 hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T, int64_t ldt, void* out,
                        int64_t ldo, int n, const double* tau_dev, const double* upstream_dev,
-                       hipStream_t s) {
+                       void* sk_partial, hipStream_t s) {
   const int d = 1 << n;
   ProfScope prof(d < BM ? "hemm_small" : (prec == QST_F64 ? "hemm_f64" : prec == QST_F32 ? "hemm_f32" : "hemm_bf16x3"), s);
   if (d < BM) {
@@ -463,23 +671,23 @@ hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T,
     return hipGetLastError();
   }
   const int tiles = d / BM;
-  const unsigned blocks = unsigned(tiles * tiles);
-  if (prec == QST_F64) {
-    gemm_cx_kernel<double, false><<<blocks, 256, 0, s>>>(static_cast<const Cx<double>*>(G), ldg,
-                                                         static_cast<const Cx<double>*>(T), ldt,
-                                                         static_cast<Cx<double>*>(out), ldo, d, tau_dev,
-                                                         upstream_dev);
-  } else if (prec == QST_F32) {
-    gemm_cx_kernel<float, false><<<blocks, 256, 0, s>>>(static_cast<const Cx<float>*>(G), ldg,
-                                                        static_cast<const Cx<float>*>(T), ldt,
-                                                        static_cast<Cx<float>*>(out), ldo, d, tau_dev,
-                                                        upstream_dev);
-  } else {
-    hemm_bf16x3_kernel<<<blocks, 256, 0, s>>>(static_cast<const Cx<float>*>(G), ldg,
-                                              static_cast<const Cx<float>*>(T), ldt,
-                                              static_cast<Cx<float>*>(out), ldo, d, tau_dev, upstream_dev);
-  }
-  return hipGetLastError();
+  GemmArgs g{};
+  g.A = G;
+  g.lda = ldg;
+  g.B = T;
+  g.ldb = ldt;
+  g.C = out;
+  g.ldc = ldo;
+  g.d = d;
+  g.tau = tau_dev;
+  g.up = upstream_dev;
+  g.ntiles = tiles * tiles;
+  g.partial = sk_partial;
+  g.tau_part = nullptr;
+  g.tau_out = nullptr;
+  if (prec == QST_F64) return run_gemm<CxPolicy<double, false>>(g, s);
+  if (prec == QST_F32) return run_gemm<CxPolicy<float, false>>(g, s);
+  return run_gemm<HemmBf16x3Policy>(g, s);
 }
 
 }  // namespace qst

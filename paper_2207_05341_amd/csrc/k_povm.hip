@@ -26,75 +26,11 @@
 // generic complex 4 x 4 product.
 #include "qst_device.h"
 #include "qst_kernels.h"
+#include "qst_povm_ops.h"
 
 namespace qst {
 
 namespace {
-
-struct ModeMatrix {
-  double a[32];  // 4 x 4 complex, row-major (re, im)
-};
-
-template <typename R>
-__device__ __forceinline__ Cx<R> cadd(Cx<R> x, Cx<R> y) { return {x.re + y.re, x.im + y.im}; }
-template <typename R>
-__device__ __forceinline__ Cx<R> csub(Cx<R> x, Cx<R> y) { return {x.re - y.re, x.im - y.im}; }
-template <typename R>
-__device__ __forceinline__ Cx<R> cscale(Cx<R> x, R s) { return {x.re * s, x.im * s}; }
-// i * x
-template <typename R>
-__device__ __forceinline__ Cx<R> cmuli(Cx<R> x) { return {-x.im, x.re}; }
-
-// Forward tetrahedral contraction of one qubit: x[m] -> y[a] = sum_m W[a][m] x[m].
-template <typename R>
-__device__ __forceinline__ void tetra_fwd(Cx<R> x[4]) {
-  const R q = R(0.25), t4 = R(0.14433756729740644113);  // 1/4, 1/(4 sqrt 3)
-  const Cx<R> a = cscale(cadd(x[0], x[3]), q);
-  const Cx<R> b = cscale(cadd(x[1], x[2]), t4);
-  const Cx<R> c = cscale(cmuli(csub(x[1], x[2])), t4);
-  const Cx<R> e = cscale(csub(x[0], x[3]), t4);
-  const Cx<R> P = cadd(b, c), Q = csub(b, c);
-  const Cx<R> ape = cadd(a, e), ame = csub(a, e);
-  x[0] = cadd(ape, P);
-  x[1] = csub(ape, P);
-  x[2] = csub(ame, Q);
-  x[3] = cadd(ame, Q);
-}
-
-// Adjoint tetrahedral contraction: g[a] -> x[m] = sum_a V[m][a] g[a].
-template <typename R>
-__device__ __forceinline__ void tetra_adj(Cx<R> x[4]) {
-  const R q = R(0.25), t4 = R(0.14433756729740644113);
-  const Cx<R> s01 = cadd(x[0], x[1]), d01 = csub(x[0], x[1]);
-  const Cx<R> s23 = cadd(x[2], x[3]), d23 = csub(x[2], x[3]);
-  const Cx<R> v0 = cscale(cadd(s01, s23), q);   // g0+g1+g2+g3
-  const Cx<R> v1 = cscale(csub(d01, d23), t4);  // g0-g1-g2+g3
-  const Cx<R> v2 = cscale(cadd(d01, d23), t4);  // g0-g1+g2-g3
-  const Cx<R> v3 = cscale(csub(s01, s23), t4);  // g0+g1-g2-g3
-  const Cx<R> iv2 = cmuli(v2);
-  x[0] = cadd(v0, v3);
-  x[1] = csub(v1, iv2);
-  x[2] = cadd(v1, iv2);
-  x[3] = csub(v0, v3);
-}
-
-template <typename R>
-__device__ __forceinline__ void generic4(Cx<R> x[4], const ModeMatrix& A) {
-  Cx<R> y[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    R re = 0, im = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const R ar = R(A.a[2 * (4 * i + j)]), ai = R(A.a[2 * (4 * i + j) + 1]);
-      re += ar * x[j].re - ai * x[j].im;
-      im += ar * x[j].im + ai * x[j].re;
-    }
-    y[i] = {re, im};
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) x[i] = y[i];
-}
 
 // Insert a zero bit at position b of x.
 __device__ __forceinline__ int ins0(int x, int b) { return ((x >> b) << (b + 1)) | (x & ((1 << b) - 1)); }
@@ -113,16 +49,6 @@ __device__ __forceinline__ void deinterleave(int k, int g, int& r, int& c) {
     c |= ((k >> (2 * b)) & 1) << b;
   }
 }
-
-struct PassArgs {
-  const void* in;   // forward: rho (MATSIDE) or intermediate; adjoint: intermediate
-  void* out;        // forward: intermediate or p (PSIDE); adjoint: intermediate or G' (MATSIDE)
-  const void* p;    // adjoint PSIDE: probabilities
-  const void* f;    // adjoint PSIDE: frequencies
-  const double* F;  // adjoint PSIDE: F = sum f
-  int64_t ld;       // row stride of the matrix side
-  int n, U, g, J;
-};
 
 // In-place contraction of the g qubit axes held in LDS.
 template <typename R, bool ADJ, bool TETRA>
@@ -143,11 +69,7 @@ __device__ __forceinline__ void contract_group(Cx<R>* buf, int g, int J, const M
       Cx<R> x[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) x[m] = buf[pos[m]];
-      if constexpr (TETRA) {
-        if constexpr (ADJ) tetra_adj(x); else tetra_fwd(x);
-      } else {
-        generic4(x, A);
-      }
+      apply4<R, ADJ, TETRA>(x, A);
 #pragma unroll
       for (int m = 0; m < 4; ++m) buf[pos[m]] = x[m];
     }
@@ -287,7 +209,7 @@ hipError_t launch_pass_t(const PassArgs& a, const ModeMatrix& A, bool matside, b
 
 hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const double* mode_matrix,
                        bool tetra, const void* mat, int64_t ld, void* pvec, const void* fvec,
-                       const double* F_dev, void* inter0, void* inter1, hipStream_t s) {
+                       const double* F_dev, void* inter0, void* inter1, hipStream_t s, bool use_fast) {
   ModeMatrix A;
   for (int i = 0; i < 32; ++i) A.a[i] = mode_matrix[i];
   void* bufs[2] = {inter0, inter1};
@@ -316,6 +238,10 @@ hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const do
                                        {"povm_adj_p0", "povm_adj_p1", "povm_adj_p2", "povm_adj_p3"}};
     ProfScope prof(kNames[adjoint ? 1 : 0][j], s);
     hipError_t e;
+    if (use_fast && launch_pass_fast(adjoint, prec, tetra, a, A, matside, pside, blocks, s, &e)) {
+      if (e != hipSuccess) return e;
+      continue;
+    }
     if (prec == QST_F64) {
       if (adjoint) e = tetra ? launch_pass_t<double, true, true>(a, A, matside, pside, blocks, s)
                              : launch_pass_t<double, true, false>(a, A, matside, pside, blocks, s);

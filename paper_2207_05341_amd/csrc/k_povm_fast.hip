@@ -1,0 +1,437 @@
+// Specialised product-POVM passes for the group shapes of N >= 7 (tetrahedral
+// and generic POVMs).  Same mathematics and data layout as the generic pass
+// kernels in k_povm.hip (see the comment there); what differs is how a
+// workgroup moves data:
+//
+//  * the group size G and chunk J are compile-time constants, so all index
+//    arithmetic is shifts and masks;
+//  * every thread holds 16 values: all (row, column) combinations of two
+//    qubit bits, times one output chunk position.  Two qubits are contracted
+//    in registers per round, so a G-qubit group takes ceil(G/2) rounds with
+//    one LDS exchange between rounds instead of one per qubit;
+//  * the round touching the matrix side reads or writes 4 x 4 blocks of
+//    consecutive columns (16- or 32-byte accesses); the round touching the
+//    outcome side maps consecutive threads to consecutive outcome indices.
+//
+// Rounds (bits are the group-local qubit bit positions, 0 = least
+// significant; a round holds two bits per thread and applies the per-qubit
+// contraction to the listed ones):
+//   G=3: {0,1} ops 0,1 | {1,2} op 2
+//   G=4: {0,1} ops 0,1 | {2,3} ops 2,3
+//   G=5: {0,1} ops 0,1 | {2,3} op 2 | {3,4} ops 3,4
+//   G=6: {0,1} ops 0,1 | {2,3} ops 2,3 | {4,5} ops 4,5
+// The forward map runs the rounds in this order (matrix side first), the
+// adjoint in reverse (outcome side first).
+#include "qst_device.h"
+#include "qst_kernels.h"
+#include "qst_povm_ops.h"
+
+namespace qst {
+
+namespace {
+
+template <int G>
+struct Rounds;
+template <>
+struct Rounds<3> {
+  static constexpr int n = 2;
+  static constexpr int bA[2] = {0, 1}, bB[2] = {1, 2};
+  static constexpr bool opA[2] = {true, false}, opB[2] = {true, true};
+};
+template <>
+struct Rounds<4> {
+  static constexpr int n = 2;
+  static constexpr int bA[2] = {0, 2}, bB[2] = {1, 3};
+  static constexpr bool opA[2] = {true, true}, opB[2] = {true, true};
+};
+template <>
+struct Rounds<5> {
+  static constexpr int n = 3;
+  static constexpr int bA[3] = {0, 2, 3}, bB[3] = {1, 3, 4};
+  static constexpr bool opA[3] = {true, true, true}, opB[3] = {true, false, true};
+};
+template <>
+struct Rounds<6> {
+  static constexpr int n = 3;
+  static constexpr int bA[3] = {0, 2, 4}, bB[3] = {1, 3, 5};
+  static constexpr bool opA[3] = {true, true, true}, opB[3] = {true, true, true};
+};
+
+// Fixed bits of a round: the G-2 bit positions other than (bA, bB), listed
+// in increasing order, each contributing an (r, c) pair.  Enumeration index
+// u (2(G-2) bits): bit 2i of u is c at the i-th fixed position, bit 2i+1 is
+// r there (interleaved, so for the top round u equals the outcome digits of
+// the low positions).
+template <int G>
+__device__ __forceinline__ void fixed_bits(int u, int bA, int bB, int& r, int& c) {
+  r = 0;
+  c = 0;
+  int i = 0;
+#pragma unroll
+  for (int b = 0; b < G; ++b) {
+    if (b == bA || b == bB) continue;
+    c |= ((u >> (2 * i)) & 1) << b;
+    r |= ((u >> (2 * i + 1)) & 1) << b;
+    ++i;
+  }
+}
+
+// Contract the flagged bits of a 16-value register block x[mA * 4 + mB].
+template <typename R, bool ADJ, bool TETRA>
+__device__ __forceinline__ void contract16(Cx<R> x[16], bool opA, bool opB, const ModeMatrix& A) {
+  if (opA) {
+#pragma unroll
+    for (int mB = 0; mB < 4; ++mB) {
+      Cx<R> v[4] = {x[mB], x[4 + mB], x[8 + mB], x[12 + mB]};
+      apply4<R, ADJ, TETRA>(v, A);
+      x[mB] = v[0];
+      x[4 + mB] = v[1];
+      x[8 + mB] = v[2];
+      x[12 + mB] = v[3];
+    }
+  }
+  if (opB) {
+#pragma unroll
+    for (int mA = 0; mA < 4; ++mA) apply4<R, ADJ, TETRA>(x + 4 * mA, A);
+  }
+}
+
+// (r, c) of value (mA, mB) of a round with fixed part (rf, cf).
+__device__ __forceinline__ void rc_of(int rf, int cf, int bA, int bB, int mA, int mB, int& r, int& c) {
+  r = rf | ((mA >> 1) << bA) | ((mB >> 1) << bB);
+  c = cf | ((mA & 1) << bA) | ((mB & 1) << bB);
+}
+
+// Swizzled LDS position of (r, c) in a 2^G x 2^G tile (matrix-side kernel).
+template <int G>
+__device__ __forceinline__ int swz(int r, int c) {
+  return (r << G) | (c ^ (r & ((1 << G) - 1)));
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-side pass (pass 0): rho (forward input, lower triangle) or G'
+// (adjoint output, written in full); outcome side X'[(Rhi, Chi)][kg].
+// 4^(G-2) threads per tile, 256 / 4^(G-2) tiles per workgroup.
+// ---------------------------------------------------------------------------
+template <typename R, bool ADJ, bool TETRA, int G>
+__global__ __launch_bounds__(256) void mat_pass(PassArgs a, ModeMatrix A, int64_t ntiles) {
+  constexpr int NT = 1 << (2 * (G - 2));
+  constexpr int TPW = 256 / NT;
+  constexpr int TILE = 1 << (2 * G);
+  __shared__ Cx<R> lds[TPW * TILE];
+  using RD = Rounds<G>;
+
+  const int tl = threadIdx.x / NT, t = threadIdx.x % NT;
+  const int64_t tile = int64_t(blockIdx.x) * TPW + tl;
+  const bool active = tile < ntiles;
+  int Rhi = 0, Chi = 0;
+  if (active) tri_decode(tile, Rhi, Chi);
+  const int Up = a.U - G;
+  Cx<R>* L = lds + tl * TILE;
+  const int64_t R0 = int64_t(Rhi) << G, C0 = int64_t(Chi) << G;
+  const int64_t obase = ((int64_t(Rhi) << Up) | Chi) * int64_t(TILE);
+  const int bq = t & ((1 << (G - 2)) - 1), aq = t >> (G - 2);  // 4 x 4 block (rows 4aq.., cols 4bq..)
+
+  // Fixed part of round rd: the 4 x 4 block corner for round 0 (bits 0, 1
+  // vary), otherwise the interleaved enumeration of the other bits by t.
+  auto round_fixed = [&](int rd, int& rf, int& cf) {
+    if (rd == 0) {
+      rf = 4 * aq;
+      cf = 4 * bq;
+    } else {
+      fixed_bits<G>(t, RD::bA[rd], RD::bB[rd], rf, cf);
+    }
+  };
+  // value m = mA*4 + mB of round 0 <-> block entry (ri, ci)
+  auto blk_ri = [](int m) { return (((m & 3) >> 1) << 1) | ((m >> 2) >> 1); };
+  auto blk_ci = [](int m) { return ((m & 1) << 1) | ((m >> 2) & 1); };
+
+  Cx<R> x[16];
+  if constexpr (!ADJ) {
+#pragma unroll
+    for (int rd = 0; rd < RD::n; ++rd) {
+      const int bA = RD::bA[rd], bB = RD::bB[rd];
+      int rf, cf;
+      round_fixed(rd, rf, cf);
+      if (rd == 0) {
+        Cx<R> blk[4][4];
+        if (active) {
+          const Cx<R>* M = static_cast<const Cx<R>*>(a.in);
+          const bool diag = Rhi == Chi;
+          if (diag && aq < bq) {  // block above the diagonal: conjugate of the mirror block
+#pragma unroll
+            for (int ci = 0; ci < 4; ++ci) {
+              const Cx<R>* row = M + (C0 + 4 * bq + ci) * a.ld + R0 + 4 * aq;
+#pragma unroll
+              for (int ri = 0; ri < 4; ++ri) blk[ri][ci] = Cx<R>{row[ri].re, -row[ri].im};
+            }
+          } else {
+#pragma unroll
+            for (int ri = 0; ri < 4; ++ri) {
+              const Cx<R>* row = M + (R0 + 4 * aq + ri) * a.ld + C0 + 4 * bq;
+#pragma unroll
+              for (int ci = 0; ci < 4; ++ci) blk[ri][ci] = row[ci];
+            }
+            if (diag && aq == bq) {  // diagonal block: upper entries from the lower ones
+#pragma unroll
+              for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+                for (int ci = ri + 1; ci < 4; ++ci) blk[ri][ci] = Cx<R>{blk[ci][ri].re, -blk[ci][ri].im};
+            }
+          }
+        } else {
+#pragma unroll
+          for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+            for (int ci = 0; ci < 4; ++ci) blk[ri][ci] = Cx<R>{R(0), R(0)};
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) x[m] = blk[blk_ri(m)][blk_ci(m)];
+      } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          x[m] = L[swz<G>(r, c)];
+        }
+      }
+      contract16<R, false, TETRA>(x, RD::opA[rd], RD::opB[rd], A);
+      if (rd + 1 < RD::n) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          L[swz<G>(r, c)] = x[m];
+        }
+        __syncthreads();
+      } else if (active) {
+        Cx<R>* out = static_cast<Cx<R>*>(a.out) + obase;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) out[t + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB))] = x[m];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int rd = RD::n - 1; rd >= 0; --rd) {
+      const int bA = RD::bA[rd], bB = RD::bB[rd];
+      int rf, cf;
+      round_fixed(rd, rf, cf);
+      if (rd == RD::n - 1) {
+        const Cx<R>* in = static_cast<const Cx<R>*>(a.in) + obase;
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+          x[m] = active ? in[t + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB))] : Cx<R>{R(0), R(0)};
+      } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          x[m] = L[swz<G>(r, c)];
+        }
+      }
+      contract16<R, true, TETRA>(x, RD::opA[rd], RD::opB[rd], A);
+      if (rd > 0) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          L[swz<G>(r, c)] = x[m];
+        }
+        __syncthreads();
+      } else if (active) {
+        Cx<R> blk[4][4];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) blk[blk_ri(m)][blk_ci(m)] = x[m];
+        Cx<R>* M = static_cast<Cx<R>*>(a.out);
+#pragma unroll
+        for (int ri = 0; ri < 4; ++ri) {
+          Cx<R>* row = M + (R0 + 4 * aq + ri) * a.ld + C0 + 4 * bq;
+#pragma unroll
+          for (int ci = 0; ci < 4; ++ci) row[ci] = blk[ri][ci];
+        }
+        if (Rhi != Chi) {  // mirror tile: conjugate transpose
+#pragma unroll
+          for (int ci = 0; ci < 4; ++ci) {
+            Cx<R>* row = M + (C0 + 4 * bq + ci) * a.ld + R0 + 4 * aq;
+#pragma unroll
+            for (int ri = 0; ri < 4; ++ri) row[ri] = Cx<R>{blk[ri][ci].re, -blk[ri][ci].im};
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outcome-side pass (passes 1..): matrix side is the intermediate
+// X[(Rr, Cr)][kdone] (lower triangle of the remaining bits), outcome side is
+// X'[(Rhi, Chi)][kg * kd + kdone] or, for the last pass (PSIDE), p itself
+// (forward) / g' = F - f/p (adjoint).  A workgroup covers one (Rhi, Chi) pair
+// and J consecutive kdone values; lanes run over kdone fastest.
+// ---------------------------------------------------------------------------
+template <typename R, bool ADJ, bool TETRA, int G, int J, bool PSIDE>
+__global__ __launch_bounds__(256) void kd_pass(PassArgs a, ModeMatrix A) {
+  constexpr int TILE = 1 << (2 * G);
+  constexpr int NB = TILE * J / 16;  // 16-value blocks per workgroup
+  constexpr int BPT = NB / 256;      // blocks per thread
+  static_assert(NB % 256 == 0, "tile x chunk must give whole blocks per thread");
+  __shared__ Cx<R> lds[TILE * J];
+  using RD = Rounds<G>;
+
+  const int U = a.U, Up = U - G;
+  const int64_t kd = int64_t(1) << (2 * (a.n - U));
+  const int64_t nchunks = kd / J;
+  const int64_t ch = blockIdx.x % nchunks;
+  int Rhi, Chi;
+  tri_decode(blockIdx.x / nchunks, Rhi, Chi);
+  const int64_t kd0 = ch * J;
+  const int64_t obase = ((int64_t(Rhi) << Up) | Chi) * (kd * TILE);
+  double F = 0.0;
+  if constexpr (ADJ && PSIDE) F = *a.F;
+
+#pragma unroll
+  for (int step = 0; step < RD::n; ++step) {
+    const int rd = ADJ ? RD::n - 1 - step : step;
+    const int bA = RD::bA[rd], bB = RD::bB[rd];
+    const bool first = step == 0, last = step == RD::n - 1;
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      const int j = blk % J;
+      const int u = blk / J;  // fixed-bit enumeration
+      int rf, cf;
+      fixed_bits<G>(u, bA, bB, rf, cf);
+      Cx<R> x[16];
+      if (first && !ADJ) {  // matrix side in (forward)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          const int64_t Rr = (int64_t(Rhi) << G) | r, Cr = (int64_t(Chi) << G) | c;
+          const bool mir = Rr < Cr;
+          const int64_t rr = mir ? Cr : Rr, cc = mir ? Rr : Cr;
+          Cx<R> v = static_cast<const Cx<R>*>(a.in)[((rr << U) | cc) * kd + kd0 + j];
+          if (mir) v.im = -v.im;
+          x[m] = v;
+        }
+      } else if (first) {  // outcome side in (adjoint)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
+          if constexpr (PSIDE) {
+            const int64_t k = int64_t(kg) * kd + kd0 + j;
+            const double fk = double(static_cast<const R*>(a.f)[k]);
+            double gk = F;
+            if (fk != 0.0) gk = F - fk / double(static_cast<const R*>(a.p)[k]);
+            x[m] = Cx<R>{R(gk), R(0)};
+          } else {
+            x[m] = static_cast<const Cx<R>*>(a.in)[obase + int64_t(kg) * kd + kd0 + j];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          x[m] = lds[((r << G) | c) * J + j];
+        }
+      }
+      contract16<R, ADJ, TETRA>(x, RD::opA[rd], RD::opB[rd], A);
+      if (!last) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          lds[((r << G) | c) * J + j] = x[m];
+        }
+      } else if constexpr (!ADJ) {  // outcome side out (forward)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
+          if constexpr (PSIDE) {
+            static_cast<R*>(a.out)[int64_t(kg) * kd + kd0 + j] = x[m].re;
+          } else {
+            static_cast<Cx<R>*>(a.out)[obase + int64_t(kg) * kd + kd0 + j] = x[m];
+          }
+        }
+      } else {  // matrix side out (adjoint): lower triangle only
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          const int64_t Rr = (int64_t(Rhi) << G) | r, Cr = (int64_t(Chi) << G) | c;
+          if (Rr >= Cr) static_cast<Cx<R>*>(a.out)[((Rr << U) | Cr) * kd + kd0 + j] = x[m];
+        }
+      }
+    }
+    if (!last) __syncthreads();
+  }
+}
+
+}  // namespace
+
+// Returns true and launches when a specialised kernel covers the pass.
+bool launch_pass_fast(bool adjoint, qst_prec prec, bool tetra, const PassArgs& a, const ModeMatrix& A,
+                      bool matside, bool pside, int64_t blocks, hipStream_t s, hipError_t* err) {
+  const bool f64 = prec == QST_F64;
+#define QST_MAT(R, ADJ, TET, G)                                                                   \
+  do {                                                                                            \
+    constexpr int TPW = 256 >> (2 * (G - 2));                                                     \
+    const unsigned grid = unsigned((blocks + TPW - 1) / TPW);                                     \
+    mat_pass<R, ADJ, TET, G><<<grid, 256, 0, s>>>(a, A, blocks);                                  \
+  } while (0)
+#define QST_MAT_ALL(G)                                                                            \
+  do {                                                                                            \
+    if (f64) {                                                                                    \
+      if (adjoint) { if (tetra) QST_MAT(double, true, true, G); else QST_MAT(double, true, false, G); } \
+      else { if (tetra) QST_MAT(double, false, true, G); else QST_MAT(double, false, false, G); }  \
+    } else {                                                                                      \
+      if (adjoint) { if (tetra) QST_MAT(float, true, true, G); else QST_MAT(float, true, false, G); } \
+      else { if (tetra) QST_MAT(float, false, true, G); else QST_MAT(float, false, false, G); }    \
+    }                                                                                             \
+  } while (0)
+  if (matside && !pside && a.J == 1 && a.g >= 4 && a.g <= 6) {
+    if (a.g == 4) QST_MAT_ALL(4);
+    else if (a.g == 5) QST_MAT_ALL(5);
+    else QST_MAT_ALL(6);
+    *err = hipGetLastError();
+    return true;
+  }
+#undef QST_MAT_ALL
+#undef QST_MAT
+#define QST_KD(R, ADJ, TET, G, J, P) kd_pass<R, ADJ, TET, G, J, P><<<unsigned(blocks), 256, 0, s>>>(a, A)
+#define QST_KD_P(R, ADJ, TET, G, J)                                                               \
+  do {                                                                                            \
+    if (pside) QST_KD(R, ADJ, TET, G, J, true); else QST_KD(R, ADJ, TET, G, J, false);          \
+  } while (0)
+#define QST_KD_ALL(R, G, J)                                                                       \
+  do {                                                                                            \
+    if (adjoint) { if (tetra) QST_KD_P(R, true, true, G, J); else QST_KD_P(R, true, false, G, J); } \
+    else { if (tetra) QST_KD_P(R, false, true, G, J); else QST_KD_P(R, false, false, G, J); }      \
+  } while (0)
+  if (!matside) {
+    const int g = a.g, J = a.J;
+    bool ok = true;
+    if (f64) {
+      if (g == 5 && J == 4) QST_KD_ALL(double, 5, 4);
+      else if (g == 4 && J == 16) QST_KD_ALL(double, 4, 16);
+      else if (g == 3 && J == 64) QST_KD_ALL(double, 3, 64);
+      else ok = false;
+    } else {
+      if (g == 5 && J == 8) QST_KD_ALL(float, 5, 8);
+      else if (g == 4 && J == 32) QST_KD_ALL(float, 4, 32);
+      else if (g == 3 && J == 64) QST_KD_ALL(float, 3, 64);
+      else ok = false;
+    }
+    if (ok) {
+      *err = hipGetLastError();
+      return true;
+    }
+  }
+#undef QST_KD_ALL
+#undef QST_KD_P
+#undef QST_KD
+  return false;
+}
+
+}  // namespace qst

@@ -23,16 +23,24 @@ __global__ __launch_bounds__(256) void tau_partial_kernel(const Cx<R>* __restric
   const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
   const int64_t beg = int64_t(blockIdx.x) * chunk;
   const int64_t end = beg + chunk < total ? beg + chunk : total;
+  // Four strided elements per thread in flight; per-thread order fixed.
   double acc = 0.0;
-  for (int64_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-    const int64_t r = e >> n, c = e & (d - 1);
-    const Cx<R> v = T[r * ld + c];
-    double x = double(v.re), y = double(v.im);
-    if constexpr (ROUND) {
-      x = double(bf16_value(float(v.re)));
-      y = double(bf16_value(float(v.im)));
+  for (int64_t e0 = beg + threadIdx.x; e0 < end; e0 += 4 * int64_t(blockDim.x)) {
+    Cx<R> v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = e0 + u * int64_t(blockDim.x);
+      v[u] = e < end ? T[(e >> n) * ld + (e & (d - 1))] : Cx<R>{R(0), R(0)};
     }
-    acc += x * x + y * y;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double x = double(v[u].re), y = double(v[u].im);
+      if constexpr (ROUND) {
+        x = double(bf16_value(float(v[u].re)));
+        y = double(bf16_value(float(v[u].im)));
+      }
+      acc += x * x + y * y;
+    }
   }
   const double s = block_sum256(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -60,20 +68,32 @@ __global__ __launch_bounds__(256) void nll_partial_kernel(const R* __restrict__ 
   const int64_t chunk = (D + nb - 1) / nb;
   const int64_t beg = int64_t(blockIdx.x) * chunk;
   const int64_t end = beg + chunk < D ? beg + chunk : D;
+  // Four strided elements per thread in flight; per-thread order fixed.
   double L = 0.0, F = 0.0, bad0 = 0.0, bad1 = 0.0;
-  for (int64_t k = beg + threadIdx.x; k < end; k += blockDim.x) {
-    const double fk = double(f[k]);
-    F += fk;
-    if constexpr (WITH_P) {
-      const double pk = double(p[k]);
-      if (fk != 0.0) {
-        if (pk > 0.0) {
-          L -= fk * log(pk);
-        } else {
-          bad0 += 1.0;
+  for (int64_t k0 = beg + threadIdx.x; k0 < end; k0 += 4 * int64_t(blockDim.x)) {
+    R fv[4], pv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u * int64_t(blockDim.x);
+      const bool in = k < end;
+      fv[u] = in ? f[k] : R(0);
+      if constexpr (WITH_P) pv[u] = in ? p[k] : R(1);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double fk = double(fv[u]);
+      F += fk;
+      if constexpr (WITH_P) {
+        const double pk = double(pv[u]);
+        if (fk != 0.0) {
+          if (pk > 0.0) {
+            L -= fk * log(pk);
+          } else {
+            bad0 += 1.0;
+          }
         }
+        if (pk != pk || fk != fk) bad1 += 1.0;
       }
-      if (pk != pk || fk != fk) bad1 += 1.0;
     }
   }
   double s = block_sum256(L, red);
@@ -129,7 +149,7 @@ hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* p
   } else {
     tau_partial_kernel<float, true><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
   }
-  finish_sums_kernel<<<1, 256, 0, s>>>(partials, nb, 1, tau_dev);
+  if (tau_dev) finish_sums_kernel<<<1, 256, 0, s>>>(partials, nb, 1, tau_dev);
   return hipGetLastError();
 }
 

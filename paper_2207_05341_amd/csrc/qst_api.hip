@@ -21,6 +21,17 @@ qst_status hip_fail(hipError_t e, const char* what) {
   return fail(QST_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// tau and rho = T T^dagger / tau.  For d >= 64 the product kernel folds the
+// tau partial sums itself (and stores tau); below that a finishing kernel
+// produces tau first.
+hipError_t run_state_map(qst_prec prec, const void* T, int64_t ldT, void* rho, int64_t ldr, int n,
+                         double* partials, double* tau_dev, void* sk, hipStream_t s) {
+  const bool fold = n >= 6;
+  hipError_t e = launch_tau(prec, T, ldT, n, partials, fold ? nullptr : tau_dev, s);
+  if (e != hipSuccess) return e;
+  return launch_herk(prec, T, ldT, rho, ldr, n, fold ? partials : nullptr, tau_dev, sk, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -38,10 +49,8 @@ qst_status qst_state_map(int n, qst_prec prec, const void* T, int64_t ldT, void*
   if (T == rho) return fail(QST_ERR_INVALID_ARG, "rho must not alias T");
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* partials = reinterpret_cast<double*>(ws_at(ws, L.partials));
-  hipError_t e = launch_tau(prec, T, ldT, n, partials, tau_dev, s);
-  if (e != hipSuccess) return hip_fail(e, "tau reduction");
-  e = launch_herk(prec, T, ldT, rho, ld_rho, n, tau_dev, s);
-  if (e != hipSuccess) return hip_fail(e, "T T^dagger");
+  hipError_t e = run_state_map(prec, T, ldT, rho, ld_rho, n, partials, tau_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "state map");
   clear_error();
   return QST_OK;
 }
@@ -84,8 +93,9 @@ qst_status qst_nll(int n, qst_prec prec, const void* p, const void* f, double* n
 }
 
 qst_status qst_nll_backward(int n, qst_prec prec, const void* T, int64_t ldT, const void* f, const void* p,
-                            const double* tau_dev, const double* povm_host, const double* upstream_dev,
-                            void* gradT, int64_t ldG, void* ws, size_t ws_bytes, void* stream) {
+                            const double* tau_dev, const double* nll_dev, const double* povm_host,
+                            const double* upstream_dev, void* gradT, int64_t ldG, void* ws, size_t ws_bytes,
+                            void* stream) {
   std::string msg;
   qst_status st;
   if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
@@ -111,24 +121,24 @@ qst_status qst_nll_backward(int n, qst_prec prec, const void* T, int64_t ldT, co
   if (recompute) {
     // rho and p are rebuilt from T here; rho lives in the G' slot.
     double* tau_ws = scalars + 1;
-    e = launch_tau(prec, T, ldT, n, partials, tau_ws, s);
-    if (e != hipSuccess) return hip_fail(e, "tau reduction (recompute)");
-    e = launch_herk(prec, T, ldT, ws_at(ws, L.rho), d, n, tau_ws, s);
-    if (e != hipSuccess) return hip_fail(e, "T T^dagger (recompute)");
+    e = run_state_map(prec, T, ldT, ws_at(ws, L.rho), d, n, partials, tau_ws, L.has_sk ? ws_at(ws, L.sk) : nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "state map (recompute)");
     e = launch_povm(false, prec, pl, W, tetra, ws_at(ws, L.rho), d, ws_at(ws, L.p), nullptr, nullptr,
                     ws_at(ws, L.inter0), ws_at(ws, L.inter1), s);
     if (e != hipSuccess) return hip_fail(e, "POVM map (recompute)");
     p = ws_at(ws, L.p);
     tau_dev = tau_ws;
   }
-  double* F_dev = scalars;
-  e = launch_fsum(prec, f, n, partials, F_dev, s);
-  if (e != hipSuccess) return hip_fail(e, "F reduction");
+  const double* F_dev = nll_dev ? nll_dev + 1 : scalars;
+  if (!nll_dev) {
+    e = launch_fsum(prec, f, n, partials, scalars, s);
+    if (e != hipSuccess) return hip_fail(e, "F reduction");
+  }
   void* G = ws_at(ws, L.gmat);
   e = launch_povm(true, prec, pl, V, tetra, G, d, const_cast<void*>(p), f, F_dev, ws_at(ws, L.inter0),
                   ws_at(ws, L.inter1), s);
   if (e != hipSuccess) return hip_fail(e, "adjoint POVM map");
-  e = launch_hemm(prec, G, d, T, ldT, gradT, ldG, n, tau_dev, upstream_dev, s);
+  e = launch_hemm(prec, G, d, T, ldT, gradT, ldG, n, tau_dev, upstream_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "G' T");
   clear_error();
   return QST_OK;

@@ -25,18 +25,23 @@ class ProfScope {
   hipStream_t s_;
 };
 
-// tau = sum |T_ij|^2 (FP64; over bf16-rounded T for QST_BF16GEMM).
+// tau = sum |T_ij|^2 (FP64; over bf16-rounded T for QST_BF16GEMM): the
+// kReduceBlocks partial sums, and, if tau_dev is not NULL, their total.
 hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
                       double* tau_dev, hipStream_t s);
 
-// rho = T T^dagger / *tau_dev, written in full.
+// rho = T T^dagger / tau, written in full.  tau comes from tau_partials (the
+// partial sums of launch_tau; the kernel also stores the total at tau_dev)
+// or, when tau_partials is NULL, from *tau_dev.  sk_partial: stream-K
+// partial-tile area of stream_k_partial_bytes(prec) bytes, or NULL (then one
+// workgroup per tile).
 hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int64_t ldr, int n,
-                       const double* tau_dev, hipStream_t s);
+                       const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s);
 
 // out = (upstream ? *upstream : 1) * 2 / *tau_dev * G T.
 hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T, int64_t ldt,
                        void* out, int64_t ldo, int n, const double* tau_dev,
-                       const double* upstream_dev, hipStream_t s);
+                       const double* upstream_dev, void* sk_partial, hipStream_t s);
 
 // Forward (adjoint=false): mat = rho (lower triangle read) -> pvec.
 // Adjoint (adjoint=true): g' = F - f/p from (pvec, fvec, F_dev) -> mat = G'
@@ -44,7 +49,8 @@ hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T,
 // complex; tetra selects the tetrahedral fast form (mode_matrix unused).
 hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const double* mode_matrix,
                        bool tetra, const void* mat, int64_t ld, void* pvec, const void* fvec,
-                       const double* F_dev, void* inter0, void* inter1, hipStream_t s);
+                       const double* F_dev, void* inter0, void* inter1, hipStream_t s,
+                       bool use_fast = true);
 
 // nll[0] = L, nll[1] = F, bad[0..1] counts (bad may be NULL).
 hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double* partials,

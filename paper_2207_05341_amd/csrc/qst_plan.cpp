@@ -37,7 +37,7 @@ PovmPlan make_povm_plan(int n, qst_prec prec) {
     } else {
       const int64_t kd = int64_t(1) << (2 * (n - U));
       int64_t J = int64_t(65536) / ((int64_t(1) << (2 * pl.g[j])) * int64_t(cb));
-      if (J > 16) J = 16;
+      if (J > 64) J = 64;
       if (J > kd) J = kd;
       if (J < 1) J = 1;
       pl.J[j] = int(J);
@@ -67,8 +67,15 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
     off = align_up(off + bytes);
     return at;
   };
+  const bool sk = n >= kStreamKMinQubits;
   switch (op) {
     case QST_OP_STATE_MAP:
+      w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
+      if (sk) {
+        w.sk = take(stream_k_partial_bytes(prec));
+        w.has_sk = true;
+      }
+      break;
     case QST_OP_NLL:
       w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
       break;
@@ -85,6 +92,10 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
       if (recompute) {
         w.rho = w.gmat;  // rho is dead once p exists; G' reuses its storage
         w.p = take(D * rb);
+      }
+      if (sk) {
+        w.sk = take(stream_k_partial_bytes(prec));
+        w.has_sk = true;
       }
       break;
     default:

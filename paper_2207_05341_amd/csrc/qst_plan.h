@@ -48,12 +48,22 @@ struct WsLayout {
   size_t gmat = 0;       // G' (d x d complex), backward only
   size_t rho = 0;        // rho (d x d complex), recompute mode only
   size_t p = 0;          // p (4^N real), recompute mode only
+  size_t sk = 0;         // stream-K partial tiles (0 = not used)
+  bool has_sk = false;
 };
 
 WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute);
 
 constexpr int kReduceBlocks = 1024;  // stage-1 blocks of every FP64 reduction
 constexpr int kReduceThreads = 256;
+
+// Stream-K scheduling of the complex products: at most this many
+// workgroups, each leaving at most two partial 64 x 64 complex tiles.
+constexpr int kStreamKMaxGrid = 1024;
+constexpr int kStreamKMinQubits = 10;  // smaller products always run one tile per workgroup
+inline size_t stream_k_partial_bytes(qst_prec p) {
+  return size_t(kStreamKMaxGrid) * 2 * (2 * 64 * 64) * (p == QST_F64 ? 8 : 4);
+}
 
 // Argument validation.  Each returns QST_OK or an error status and fills msg.
 qst_status check_common(int n, int prec, std::string& msg);

@@ -150,8 +150,8 @@ def test_backward_validation(L):
 
     def call(**kw):
         a = dict(args, **kw)
-        return L.qst_nll_backward(n, 0, a["T"], a["ldT"], a["f"], a["p"], a["tau"], a["povm"], a["up"], a["G"],
-                                  a["ldG"], W, kw.get("ws", ws), None)
+        return L.qst_nll_backward(n, 0, a["T"], a["ldT"], a["f"], a["p"], a["tau"], None, a["povm"], a["up"],
+                                  a["G"], a["ldG"], W, kw.get("ws", ws), None)
 
     assert call(T=None) == lib_mod.QST_ERR_INVALID_ARG
     assert call(f=None) == lib_mod.QST_ERR_INVALID_ARG

@@ -45,14 +45,15 @@ def say(*a):
     print(*a, flush=True)
 
 
-def run_chain(T, f, prec, recompute=False, povm=None):
+def run_chain(T, f, prec, recompute=False, povm=None, f_from_forward=True):
     """Forward and backward through the C ABI; returns numpy (rho, tau, p, L, grad)."""
     Tg = to_dev(T.astype(ctype(prec)))
     fg = to_dev(f.astype(rtype(prec)))
     rho, tau = qst.state_map(Tg, prec)
     p = qst.povm_probs(rho, prec, povm)
     out, bad = qst.nll(p, fg, prec)
-    grad = qst.nll_backward(Tg, fg, None if recompute else p, None if recompute else tau, prec, povm)
+    grad = qst.nll_backward(Tg, fg, None if recompute else p, None if recompute else tau, prec, povm,
+                            nll_out=out if f_from_forward else None)
     torch.cuda.synchronize()
     return host(rho), float(tau.item()), host(p).astype(np.float64), float(out[0].item()), host(grad), host(bad)
 
@@ -79,7 +80,7 @@ def bf16_round(x):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("n", [1, 3, 5, 6, 7, 9])
+@pytest.mark.parametrize("n", [1, 3, 5, 6, 7, 9, 10])
 def test_state_map(n, prec):
     say(f"state_map n={n} prec={prec}")
     g = S.rng(2000 + n)
@@ -242,7 +243,9 @@ def test_recompute_equals_stored_and_determinism(prec):
     a = run_chain(T, f, prec, recompute=False)
     b = run_chain(T, f, prec, recompute=True)
     c = run_chain(T, f, prec, recompute=False)
+    e = run_chain(T, f, prec, recompute=False, f_from_forward=False)
     assert np.array_equal(a[4], b[4])  # gradient bitwise identical
+    assert np.array_equal(a[4], e[4])  # F from the forward NLL == F reduced in the backward
     for x, y in zip(a, c):
         if isinstance(x, np.ndarray):
             assert np.array_equal(x, y)
