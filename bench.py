@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--n", type=int, default=11)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precision paths")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     return ap.parse_args()
 
 
@@ -95,6 +96,56 @@ def time_steps(qst, T, f, prec, steps, warmup, profile):
         _lib.profile_enable(False)
         kern = _lib.profile_report(reset=True)
     return (t1 - t0) / steps, kern
+
+
+def batched(qst, prec, dev, reps=20):
+    """Batched form: 1024 instances, N uniform on {3..8} (seed 9), Ginibre T,
+    Porter-Thomas stand-in frequencies from 10^5 shots each.  One graph
+    replay of the persistent launch vs 1024 separate single-instance call
+    sequences (state map, POVM map, NLL, backward) through the same C ABI."""
+    import numpy as np
+    import torch
+
+    import synth as S
+
+    g = S.rng(9)
+    ns = [int(x) for x in S.batch_qubit_counts(g, 1024, 3, 8)]
+    ct = np.complex128 if prec == "f64" else np.complex64
+    rt = np.float64 if prec == "f64" else np.float32
+    Ts, fs = [], []
+    for n in ns:
+        d = 1 << n
+        Ts.append(S.ginibre(g, d).astype(ct))
+        fs.append(S.multinomial_freqs(g, 100_000, S.porter_thomas_probs(g, 4 ** n, 0.1)).astype(rt))
+    plan = qst.BatchPlan(ns, prec)
+    T_all, f_all = plan.pack(Ts, fs, dev)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan.run(T_all, f_all, use_graph=True)  # tunes, captures
+        side.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(side)
+        for _ in range(reps):
+            plan.run(T_all, f_all, use_graph=True)
+        ev1.record(side)
+    side.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / reps
+    # separate launches
+    Tg = [torch.from_numpy(T).to(dev) for T in Ts]
+    fg = [torch.from_numpy(f).to(dev) for f in fs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for T, f in zip(Tg, fg):
+        step(qst, T, f, prec)
+    torch.cuda.synchronize()
+    sep_ms = 1e3 * (time.perf_counter() - t0)
+    info = plan.info()
+    plan.close()
+    flops = sum(4.0 * (1 << n) ** 2 * ((1 << n) + 1) + 8.0 * (1 << n) ** 3 for n in ns)
+    return {"instances": len(ns), "n_range": [3, 8], "precision": prec,
+            "graph_ms_per_batch": graph_ms, "instances_per_s": len(ns) / (graph_ms * 1e-3),
+            "separate_launches_ms": sep_ms, "speedup_vs_separate": sep_ms / graph_ms,
+            "tflops": flops / (graph_ms * 1e-3) / 1e12, "tuned": info}
 
 
 def cpu_baseline(T, f, prec):
@@ -204,6 +255,7 @@ def main():
             paths[prec] = {"evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
                            "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()}}
 
+    batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
 
     line = {
@@ -228,6 +280,7 @@ def main():
         "kernels_us": {k: round(v, 2) for k, v in sorted(kern_us.items())},
         "povm_pass_gbs": {k: round(v, 1) for k, v in povm_gbs.items()},
         "paths": paths,
+        "batched": batch,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

@@ -182,6 +182,47 @@ qst_status qst_profile_enable(int on);
  */
 size_t qst_profile_report(char* buf, size_t len, int reset);
 
+/*
+ * Batched form: many independent instances of mixed qubit counts, forward
+ * and adjoint of every instance in one persistent launch (optionally replayed
+ * as a captured HIP graph).  Instance i has N_i qubits (1 <= N_i <= 8),
+ * d_i = 2^N_i.  Buffers are packed in instance order:
+ *   T_all    complex, instance i's d_i x d_i row-major T (ld = d_i) at
+ *            complex offset t_off[i];  grad_all: same layout, written;
+ *   f_all    real, instance i's 4^N_i frequencies at real offset f_off[i];
+ *   nll_out  double [count][2]: (L_i, F_i), written;
+ *   bad_out  uint64 [count][2]: the counters of qst_nll, or NULL.
+ * t_off and f_off (count + 1 entries each) come from qst_batch_offsets.
+ * The plan owns device memory (descriptor table, work counter, per-workgroup
+ * scratch) and, in graph mode, a HIP graph, until qst_batch_plan_destroy.
+ * On its first run the plan times its candidate launch shapes (grid size,
+ * instance order) on the given buffers and keeps the fastest; with a cache
+ * file (tune_cache, else the QST_TUNE_CACHE environment variable; NULL/unset
+ * = no cache) the choice is appended there and reused by later plans with
+ * the same precision, POVM kind, qubit-count histogram and device.
+ * A plan must not be run concurrently on two streams.
+ */
+typedef struct qst_batch_plan qst_batch_plan;
+
+qst_status qst_batch_plan_create(const int* n_qubits_host, int count, qst_prec prec,
+                                 const double* povm_host, const char* tune_cache,
+                                 qst_batch_plan** plan);
+
+qst_status qst_batch_offsets(const qst_batch_plan* plan, int64_t* t_off_host, int64_t* f_off_host);
+
+/* use_graph != 0 captures (once per buffer set and stream) and replays a HIP
+ * graph; stream must then be non-NULL. */
+qst_status qst_batch_run(qst_batch_plan* plan, const void* T_all, const void* f_all,
+                         double* nll_out, unsigned long long* bad_out, void* grad_all,
+                         int use_graph, void* stream);
+
+/* The tuned launch shape: grid (workgroups), sorted_order (1 = largest
+ * instances first), tuned_ms (time of one batch when tuned). */
+qst_status qst_batch_info(const qst_batch_plan* plan, int* grid, int* sorted_order,
+                          double* tuned_ms);
+
+void qst_batch_plan_destroy(qst_batch_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

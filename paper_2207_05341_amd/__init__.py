@@ -195,3 +195,79 @@ def likelihood(T: torch.Tensor, f: torch.Tensor, prec=None, recompute: bool | No
     if recompute is None:
         recompute = _qubits(T.shape[-1]) >= 12
     return LikelihoodFn.apply(T, f, prec, recompute, povm)
+
+
+class BatchPlan:
+    """Many independent instances (1 <= N_i <= 8) in one persistent launch
+    (qst_batch_* in include/qst.h).  Inputs and outputs are packed tensors:
+    T_all / grad_all hold the d_i x d_i matrices back to back (complex), f_all
+    the 4^N_i frequencies back to back (real); offsets() gives the starts."""
+
+    def __init__(self, n_qubits, prec="f32", povm=None, tune_cache: str | None = None):
+        self.n = [int(x) for x in n_qubits]
+        self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        arr = (ctypes.c_int * len(self.n))(*self.n)
+        handle = ctypes.c_void_p()
+        cache = tune_cache.encode() if tune_cache else None
+        self._handle = None
+        _lib.check(_lib.lib().qst_batch_plan_create(arr, len(self.n), self.prec, _povm_arg(povm), cache,
+                                                    ctypes.byref(handle)), "qst_batch_plan_create")
+        self._handle = handle
+        t_off = (ctypes.c_int64 * (len(self.n) + 1))()
+        f_off = (ctypes.c_int64 * (len(self.n) + 1))()
+        _lib.check(_lib.lib().qst_batch_offsets(self._handle, t_off, f_off), "qst_batch_offsets")
+        self.t_off = list(t_off)
+        self.f_off = list(f_off)
+
+    def offsets(self):
+        return self.t_off, self.f_off
+
+    def pack(self, mats, vecs, device):
+        """Pack per-instance T (d x d) and f (4^N) into the plan's layout."""
+        cd, rd = complex_dtype(self.prec), real_dtype(self.prec)
+        T_all = torch.empty(self.t_off[-1], dtype=cd, device=device)
+        f_all = torch.empty(self.f_off[-1], dtype=rd, device=device)
+        for i, (m, v) in enumerate(zip(mats, vecs)):
+            T_all[self.t_off[i]:self.t_off[i + 1]] = torch.as_tensor(m).reshape(-1).to(cd)
+            f_all[self.f_off[i]:self.f_off[i + 1]] = torch.as_tensor(v).reshape(-1).to(rd)
+        return T_all, f_all
+
+    def run(self, T_all: torch.Tensor, f_all: torch.Tensor, use_graph: bool = True, out=None):
+        """Forward and adjoint of every instance: returns (nll [count, 2] with
+        (L_i, F_i), grad_all packed like T_all, bad [count, 2])."""
+        cd, rd = complex_dtype(self.prec), real_dtype(self.prec)
+        if T_all.dtype != cd or f_all.dtype != rd or not T_all.is_cuda or not f_all.is_cuda:
+            raise TypeError(f"T_all must be {cd} and f_all {rd}, on the GPU")
+        if T_all.numel() != self.t_off[-1] or f_all.numel() != self.f_off[-1]:
+            raise ValueError("packed sizes do not match the plan")
+        if not (T_all.is_contiguous() and f_all.is_contiguous()):
+            raise ValueError("packed buffers must be contiguous")
+        if out is None:
+            nll_out = torch.empty((len(self.n), 2), dtype=torch.float64, device=T_all.device)
+            bad = torch.empty((len(self.n), 2), dtype=torch.int64, device=T_all.device)
+            grad = torch.empty_like(T_all)
+        else:
+            nll_out, bad, grad = out
+        stream = torch.cuda.current_stream(T_all.device)
+        use_graph = bool(use_graph) and stream.cuda_stream != 0
+        _lib.check(_lib.lib().qst_batch_run(self._handle, T_all.data_ptr(), f_all.data_ptr(), nll_out.data_ptr(),
+                                            bad.data_ptr(), grad.data_ptr(), 1 if use_graph else 0,
+                                            _stream(T_all.device)), "qst_batch_run")
+        return nll_out, grad, bad
+
+    def info(self):
+        grid, so, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _lib.check(_lib.lib().qst_batch_info(self._handle, ctypes.byref(grid), ctypes.byref(so), ctypes.byref(ms)),
+                   "qst_batch_info")
+        return {"grid": grid.value, "sorted_order": bool(so.value), "tuned_ms": ms.value}
+
+    def close(self):
+        if self._handle is not None:
+            _lib.lib().qst_batch_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

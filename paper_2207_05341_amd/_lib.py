@@ -28,6 +28,11 @@ SIGNATURES = {
     "qst_version": (ctypes.c_char_p, []),
     "qst_profile_enable": (_int, [_int]),
     "qst_profile_report": (_sz, [ctypes.c_char_p, _sz, _int]),
+    "qst_batch_plan_create": (_int, [_vp, _int, _int, _vp, ctypes.c_char_p, ctypes.POINTER(_vp)]),
+    "qst_batch_offsets": (_int, [_vp, _vp, _vp]),
+    "qst_batch_run": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
+    "qst_batch_info": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]),
+    "qst_batch_plan_destroy": (None, [_vp]),
 }
 
 _lib = None

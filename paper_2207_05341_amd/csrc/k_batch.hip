@@ -1,0 +1,645 @@
+// Batched form: many independent tomography instances of mixed qubit counts
+// (N = 1..8) -- forward and adjoint of each -- in ONE persistent launch.
+//
+// A grid of CUs x occupancy workgroups pulls instance indices from an integer
+// work counter, in descending cost order (largest d first, a greedy longest-
+// processing-time schedule).  One workgroup carries one instance through
+// every step of the path:
+//   tau (FP64 block reduction) -> T T^dagger / tau (MFMA tiles of the product
+//   kernels, or per-entry loops below d = 64) -> POVM passes -> L, F (FP64
+//   block reduction) -> cotangent + adjoint passes -> (2/tau) G' T,
+// keeping rho / G', the POVM intermediate and p in a per-workgroup scratch
+// region.  Every reduction has a fixed order, so results do not depend on
+// which workgroup takes which instance.
+//
+// The host plan (qst_batch_plan_*) owns the descriptor table, the work
+// counter, the scratch and an optional HIP graph of (counter reset + kernel),
+// and picks the grid size and instance order with a small autotuner whose
+// choices can be cached in a text file.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "qst_gemm_tiles.h"
+#include "qst_kernels.h"
+#include "qst_plan.h"
+#include "qst_povm_generic.h"
+
+namespace qst {
+
+namespace {
+
+constexpr int kBatchMaxQubits = 8;
+
+struct BatchItem {
+  int n;
+  int pad;
+  int64_t t_off;  // complex elements into T_all / grad_all
+  int64_t f_off;  // reals into f_all
+};
+
+struct BatchPlanTable {
+  int passes[kBatchMaxQubits + 1];
+  int g[kBatchMaxQubits + 1][4];
+  int U[kBatchMaxQubits + 1][4];
+  int J[kBatchMaxQubits + 1][4];
+};
+
+struct BatchArgs {
+  const BatchItem* items;
+  const int* order;
+  int count;
+  int* counter;
+  const void* T_all;
+  const void* f_all;
+  double* nll_out;              // [count][2]
+  unsigned long long* bad_out;  // [count][2] or NULL
+  void* grad_all;
+  unsigned char* scratch;
+  int64_t stride;  // bytes of scratch per workgroup
+  int nmax;
+  BatchPlanTable plan;
+  ModeMatrix W, V;
+};
+
+__global__ void reset_counter_kernel(int* c) { *c = 0; }
+
+// Block-wide FP64 sum (fixed order), result broadcast to every thread.
+__device__ double block_sum_bcast(double v, double* red4, double* slot) {
+  const double s = block_sum256(v, red4);
+  if (threadIdx.x == 0) *slot = s;
+  __syncthreads();
+  const double r = *slot;
+  __syncthreads();
+  return r;
+}
+
+template <class PH, class PM, typename R, bool TETRA, bool BF16>
+__global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
+  // One 64 KiB LDS pool serves, one stage at a time, the product panels, the
+  // POVM pass buffer and the reduction scratch (red, slot, s_idx).
+  __shared__ __align__(16) unsigned char pool[65536];
+  double* const red = reinterpret_cast<double*>(pool);
+  double* const slotp = red + 4;
+  int* const s_idx_p = reinterpret_cast<int*>(red + 5);
+  const int t = threadIdx.x;
+  const int64_t dmax = int64_t(1) << b.nmax, Dmax = dmax * dmax;
+  unsigned char* scr = b.scratch + int64_t(blockIdx.x) * b.stride;
+  Cx<R>* rho = reinterpret_cast<Cx<R>*>(scr);            // rho, then G'
+  Cx<R>* inter = rho + Dmax;                             // POVM intermediate
+  R* pvec = reinterpret_cast<R*>(inter + Dmax);          // p
+  double* Fdev = reinterpret_cast<double*>(pvec + Dmax);  // F for the cotangent
+
+  for (;;) {
+    if (t == 0) *s_idx_p = atomicAdd(b.counter, 1);
+    __syncthreads();
+    const int idx = *s_idx_p;
+    __syncthreads();
+    if (idx >= b.count) break;
+    const int j = b.order[idx];
+    const BatchItem it = b.items[j];
+    const int n = it.n;
+    const int d = 1 << n;
+    const int64_t D = int64_t(d) * d;
+    const Cx<R>* T = static_cast<const Cx<R>*>(b.T_all) + it.t_off;
+    const R* f = static_cast<const R*>(b.f_all) + it.f_off;
+    Cx<R>* grad = static_cast<Cx<R>*>(b.grad_all) + it.t_off;
+
+    // 1. tau = sum |T|^2 (FP64, over bf16-rounded T for the BF16 path)
+    double acc = 0.0;
+    for (int64_t e = t; e < D; e += 256) {
+      const Cx<R> v = T[e];
+      double x = double(v.re), y = double(v.im);
+      if constexpr (BF16) {
+        x = double(bf16_value(float(v.re)));
+        y = double(bf16_value(float(v.im)));
+      }
+      acc += x * x + y * y;
+    }
+    const double tau = block_sum_bcast(acc, red, slotp);
+
+    // 2. rho = T T^dagger / tau
+    if (d >= 64) {
+      gemm::GemmArgs g{};
+      g.A = T;
+      g.lda = d;
+      g.B = T;
+      g.ldb = d;
+      g.C = rho;
+      g.ldc = d;
+      g.d = d;
+      g.kIters = d / PH::KP;
+      const int tiles = d / 64;
+      for (int tile = 0; tile < tiles * (tiles + 1) / 2; ++tile) {
+        int tr, tc;
+        tri_decode(tile, tr, tc);
+        typename PH::acc_t aR[2][2], aI[2][2];
+        gemm::zero_acc<PH>(aR, aI);
+        PH::run(g, *reinterpret_cast<typename PH::Smem*>(pool), tr, tc, 0, g.kIters, aR, aI);
+        gemm::epilogue<PH>(g, tr, tc, aR, aI, 1.0 / tau);
+      }
+    } else {
+      for (int64_t e = t; e < D; e += 256) {
+        const int r = int(e >> n), c = int(e & (d - 1));
+        R sr = 0, si = 0;
+        for (int k = 0; k < d; ++k) {
+          Cx<R> x = T[int64_t(r) * d + k], y = T[int64_t(c) * d + k];
+          if constexpr (BF16) {
+            x = {R(bf16_value(float(x.re))), R(bf16_value(float(x.im)))};
+            y = {R(bf16_value(float(y.re))), R(bf16_value(float(y.im)))};
+          }
+          sr += x.re * y.re + x.im * y.im;
+          si += x.im * y.re - x.re * y.im;
+        }
+        rho[e] = Cx<R>{R(sr / tau), R(si / tau)};
+      }
+    }
+    __syncthreads();
+
+    // 3. POVM map: rho -> p
+    Cx<R>* buf = reinterpret_cast<Cx<R>*>(pool);
+    const int P = b.plan.passes[n];
+    for (int pj = 0; pj < P; ++pj) {
+      PassArgs a{};
+      a.n = n;
+      a.U = b.plan.U[n][pj];
+      a.g = b.plan.g[n][pj];
+      a.J = b.plan.J[n][pj];
+      a.ld = d;
+      const bool ms = pj == 0, ps = pj == P - 1;
+      a.in = ms ? static_cast<const void*>(rho) : static_cast<const void*>(inter);
+      a.out = ps ? static_cast<void*>(pvec) : static_cast<void*>(inter);
+      const int Up = a.U - a.g;
+      const int64_t side = int64_t(1) << Up;
+      const int64_t blocks = side * (side + 1) / 2 * ((int64_t(1) << (2 * (n - a.U))) / a.J);
+      for (int64_t vb = 0; vb < blocks; ++vb) {
+        if (ms && ps) generic_pass::fwd_pass_body<R, TETRA, true, true>(a, b.W, vb, buf);
+        else if (ms) generic_pass::fwd_pass_body<R, TETRA, true, false>(a, b.W, vb, buf);
+        else if (ps) generic_pass::fwd_pass_body<R, TETRA, false, true>(a, b.W, vb, buf);
+        else generic_pass::fwd_pass_body<R, TETRA, false, false>(a, b.W, vb, buf);
+        __syncthreads();
+      }
+    }
+
+    // 4. L, F (FP64), counters
+    double L = 0.0, F = 0.0, bad0 = 0.0, bad1 = 0.0;
+    for (int64_t k = t; k < D; k += 256) {
+      const double fk = double(f[k]), pk = double(pvec[k]);
+      F += fk;
+      if (fk != 0.0) {
+        if (pk > 0.0) L -= fk * log(pk);
+        else bad0 += 1.0;
+      }
+      if (pk != pk || fk != fk) bad1 += 1.0;
+    }
+    L = block_sum_bcast(L, red, slotp);
+    F = block_sum_bcast(F, red, slotp);
+    bad0 = block_sum_bcast(bad0, red, slotp);
+    bad1 = block_sum_bcast(bad1, red, slotp);
+    if (t == 0) {
+      double Lo = L;
+      if (F != F || bad1 > 0.0) Lo = __builtin_nan("");
+      else if (bad0 > 0.0) Lo = __builtin_inf();
+      b.nll_out[2 * j] = Lo;
+      b.nll_out[2 * j + 1] = F;
+      if (b.bad_out) {
+        b.bad_out[2 * j] = (unsigned long long)bad0;
+        b.bad_out[2 * j + 1] = (unsigned long long)bad1;
+      }
+      *Fdev = F;
+    }
+    __syncthreads();
+
+    // 5. cotangent + adjoint map: (p, f) -> G' (in the rho slot)
+    for (int pj = P - 1; pj >= 0; --pj) {
+      PassArgs a{};
+      a.n = n;
+      a.U = b.plan.U[n][pj];
+      a.g = b.plan.g[n][pj];
+      a.J = b.plan.J[n][pj];
+      a.ld = d;
+      a.p = pvec;
+      a.f = f;
+      a.F = Fdev;
+      const bool ms = pj == 0, ps = pj == P - 1;
+      a.in = ps ? nullptr : static_cast<const void*>(inter);
+      a.out = ms ? static_cast<void*>(rho) : static_cast<void*>(inter);
+      const int Up = a.U - a.g;
+      const int64_t side = int64_t(1) << Up;
+      const int64_t blocks = side * (side + 1) / 2 * ((int64_t(1) << (2 * (n - a.U))) / a.J);
+      for (int64_t vb = 0; vb < blocks; ++vb) {
+        if (ms && ps) generic_pass::adj_pass_body<R, TETRA, true, true>(a, b.V, vb, buf);
+        else if (ms) generic_pass::adj_pass_body<R, TETRA, true, false>(a, b.V, vb, buf);
+        else if (ps) generic_pass::adj_pass_body<R, TETRA, false, true>(a, b.V, vb, buf);
+        else generic_pass::adj_pass_body<R, TETRA, false, false>(a, b.V, vb, buf);
+        __syncthreads();
+      }
+    }
+
+    // 6. grad = (2/tau) G' T
+    const double scale = 2.0 / tau;
+    if (d >= 64) {
+      gemm::GemmArgs g{};
+      g.A = rho;
+      g.lda = d;
+      g.B = T;
+      g.ldb = d;
+      g.C = grad;
+      g.ldc = d;
+      g.d = d;
+      g.kIters = d / PM::KP;
+      const int tiles = d / 64;
+      for (int tile = 0; tile < tiles * tiles; ++tile) {
+        const int tr = tile / tiles, tc = tile % tiles;
+        typename PM::acc_t aR[2][2], aI[2][2];
+        gemm::zero_acc<PM>(aR, aI);
+        PM::run(g, *reinterpret_cast<typename PM::Smem*>(pool), tr, tc, 0, g.kIters, aR, aI);
+        gemm::epilogue<PM>(g, tr, tc, aR, aI, scale);
+      }
+    } else {
+      for (int64_t e = t; e < D; e += 256) {
+        const int r = int(e >> n), c = int(e & (d - 1));
+        R sr = 0, si = 0;
+        for (int k = 0; k < d; ++k) {
+          const Cx<R> x = rho[int64_t(r) * d + k], y = T[int64_t(k) * d + c];
+          if constexpr (BF16) {
+            const float ahr = bf16_value(float(x.re)), ahi = bf16_value(float(x.im));
+            const float alr = bf16_value(float(x.re) - ahr), ali = bf16_value(float(x.im) - ahi);
+            const float bhr = bf16_value(float(y.re)), bhi = bf16_value(float(y.im));
+            const float blr = bf16_value(float(y.re) - bhr), bli = bf16_value(float(y.im) - bhi);
+            sr += (ahr * bhr - ahi * bhi) + (ahr * blr - ahi * bli) + (alr * bhr - ali * bhi);
+            si += (ahr * bhi + ahi * bhr) + (ahr * bli + ahi * blr) + (alr * bhi + ali * bhr);
+          } else {
+            sr += x.re * y.re - x.im * y.im;
+            si += x.re * y.im + x.im * y.re;
+          }
+        }
+        grad[e] = Cx<R>{R(sr * scale), R(si * scale)};
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename R, bool TETRA, bool BF16>
+struct BatchKernelOf;
+template <bool TETRA>
+struct BatchKernelOf<double, TETRA, false> {
+  static void* fn() {
+    return reinterpret_cast<void*>(
+        &batch_kernel<gemm::CxPolicy<double, true>, gemm::CxPolicy<double, false>, double, TETRA, false>);
+  }
+};
+template <bool TETRA>
+struct BatchKernelOf<float, TETRA, false> {
+  static void* fn() {
+    return reinterpret_cast<void*>(
+        &batch_kernel<gemm::CxPolicy<float, true>, gemm::CxPolicy<float, false>, float, TETRA, false>);
+  }
+};
+template <bool TETRA>
+struct BatchKernelOf<float, TETRA, true> {
+  static void* fn() {
+    return reinterpret_cast<void*>(
+        &batch_kernel<gemm::HerkBf16Policy, gemm::HemmBf16x3Policy, float, TETRA, true>);
+  }
+};
+
+template <class PH, class PM, typename R, bool BF16>
+hipError_t launch_batch_t(bool tetra, const BatchArgs& a, int grid, hipStream_t s) {
+  if (tetra) batch_kernel<PH, PM, R, true, BF16><<<unsigned(grid), 256, 0, s>>>(a);
+  else batch_kernel<PH, PM, R, false, BF16><<<unsigned(grid), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_kernel(qst_prec prec, bool tetra, const BatchArgs& a, int grid, hipStream_t s) {
+  using namespace gemm;
+  if (prec == QST_F64) return launch_batch_t<CxPolicy<double, true>, CxPolicy<double, false>, double, false>(tetra, a, grid, s);
+  if (prec == QST_F32) return launch_batch_t<CxPolicy<float, true>, CxPolicy<float, false>, float, false>(tetra, a, grid, s);
+  return launch_batch_t<HerkBf16Policy, HemmBf16x3Policy, float, true>(tetra, a, grid, s);
+}
+
+int batch_occupancy(qst_prec prec) {
+  void* fn = prec == QST_F64 ? BatchKernelOf<double, true, false>::fn()
+             : prec == QST_F32 ? BatchKernelOf<float, true, false>::fn()
+                               : BatchKernelOf<float, true, true>::fn();
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), 256, 0) != hipSuccess ||
+      n <= 0)
+    n = 1;
+  return n;
+}
+
+}  // namespace
+
+}  // namespace qst
+
+// ---------------------------------------------------------------------------
+// Host plan
+// ---------------------------------------------------------------------------
+struct qst_batch_plan {
+  int count = 0;
+  qst_prec prec = QST_F32;
+  bool tetra = true;
+  int nmax = 0;
+  int device = 0;
+  std::vector<int> n;
+  std::vector<int64_t> t_off, f_off;  // count + 1 entries
+  qst::BatchArgs args{};
+  qst::BatchItem* d_items = nullptr;
+  int* d_order = nullptr;
+  int* d_order_natural = nullptr;
+  int* d_counter = nullptr;
+  unsigned char* d_scratch = nullptr;
+  int cus = 256;
+  int occ = 1;
+  // tuning
+  std::string cache_path, key;
+  bool tuned = false;
+  int grid = 0;
+  bool sorted_order = true;
+  double tuned_ms = 0.0;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* g_T = nullptr;
+  const void* g_f = nullptr;
+  void* g_nll = nullptr;
+  void* g_bad = nullptr;
+  void* g_grad = nullptr;
+  hipStream_t g_stream = nullptr;
+  int g_grid = 0;
+  bool g_sorted = true;
+};
+
+namespace qst {
+qst_status fail_status(qst_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+}  // namespace qst
+
+namespace {
+
+std::string device_name(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  return std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+void free_plan(qst_batch_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_order) (void)hipFree(p->d_order);
+  if (p->d_order_natural) (void)hipFree(p->d_order_natural);
+  if (p->d_counter) (void)hipFree(p->d_counter);
+  if (p->d_scratch) (void)hipFree(p->d_scratch);
+  delete p;
+}
+
+bool read_cache(qst_batch_plan* p) {
+  if (p->cache_path.empty()) return false;
+  std::ifstream in(p->cache_path);
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string key;
+    int grid = 0, sorted = 1;
+    double ms = 0;
+    if (ls >> key >> grid >> sorted >> ms && key == p->key && grid > 0) {
+      p->grid = std::min(grid, p->cus * p->occ);
+      p->sorted_order = sorted != 0;
+      p->tuned_ms = ms;
+      p->tuned = true;
+    }
+  }
+  return p->tuned;
+}
+
+void write_cache(const qst_batch_plan* p) {
+  if (p->cache_path.empty()) return;
+  std::ofstream out(p->cache_path, std::ios::app);
+  out << p->key << " " << p->grid << " " << (p->sorted_order ? 1 : 0) << " " << p->tuned_ms << "\n";
+}
+
+hipError_t enqueue(qst_batch_plan* p, int grid, bool sorted, hipStream_t s) {
+  qst::BatchArgs a = p->args;
+  a.order = sorted ? p->d_order : p->d_order_natural;
+  qst::reset_counter_kernel<<<1, 1, 0, s>>>(p->d_counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return qst::launch_batch_kernel(p->prec, p->tetra, a, grid, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+qst_status qst_batch_plan_create(const int* n_qubits, int count, qst_prec prec, const double* povm_host,
+                                 const char* tune_cache, qst_batch_plan** out) {
+  std::string msg;
+  if (!out) return qst::fail_status(QST_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!n_qubits || count <= 0) return qst::fail_status(QST_ERR_INVALID_ARG, "empty batch");
+  if (!qst::prec_valid(prec)) return qst::fail_status(QST_ERR_INVALID_ARG, "unknown precision");
+  if (qst::check_povm(povm_host, msg) != QST_OK) return qst::fail_status(QST_ERR_INVALID_ARG, msg);
+  for (int i = 0; i < count; ++i) {
+    if (n_qubits[i] < 1 || n_qubits[i] > qst::kBatchMaxQubits)
+      return qst::fail_status(QST_ERR_INVALID_ARG, "batched instances need 1 <= N <= 8 (instance " +
+                                                       std::to_string(i) + " has N=" + std::to_string(n_qubits[i]) + ")");
+  }
+  qst_batch_plan* p = new qst_batch_plan();
+  p->count = count;
+  p->prec = prec;
+  p->tetra = povm_host == nullptr;
+  p->n.assign(n_qubits, n_qubits + count);
+  p->t_off.assign(count + 1, 0);
+  p->f_off.assign(count + 1, 0);
+  std::vector<qst::BatchItem> items(count);
+  for (int i = 0; i < count; ++i) {
+    const int64_t D = int64_t(1) << (2 * p->n[i]);
+    p->nmax = std::max(p->nmax, p->n[i]);
+    items[i] = qst::BatchItem{p->n[i], 0, p->t_off[i], p->f_off[i]};
+    p->t_off[i + 1] = p->t_off[i] + D;
+    p->f_off[i + 1] = p->f_off[i] + D;
+  }
+  // descending cost (N), ties by index: greedy longest-processing-time order
+  std::vector<int> order(count), natural(count);
+  for (int i = 0; i < count; ++i) order[i] = natural[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->n[a] > p->n[b]; });
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return qst::fail_status(QST_ERR_HIP, std::string("device query: ") + hipGetErrorString(e));
+  }
+  p->occ = std::max(1, qst::batch_occupancy(prec));
+  const int64_t dmax = int64_t(1) << p->nmax, Dmax = dmax * dmax;
+  const size_t cb = qst::complex_bytes(prec), rb = qst::real_bytes(prec);
+  const int64_t stride = int64_t((2 * Dmax * cb + Dmax * rb + 64 + 255) / 256 * 256);
+  const int max_grid = p->cus * p->occ;
+  e = hipMalloc(&p->d_items, sizeof(qst::BatchItem) * count);
+  if (e == hipSuccess) e = hipMalloc(&p->d_order, sizeof(int) * count);
+  if (e == hipSuccess) e = hipMalloc(&p->d_order_natural, sizeof(int) * count);
+  if (e == hipSuccess) e = hipMalloc(&p->d_counter, 256);
+  if (e == hipSuccess) e = hipMalloc(&p->d_scratch, size_t(stride) * max_grid);
+  if (e == hipSuccess) e = hipMemcpy(p->d_items, items.data(), sizeof(qst::BatchItem) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_order_natural, natural.data(), sizeof(int) * count, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return qst::fail_status(QST_ERR_HIP, std::string("batch plan allocation: ") + hipGetErrorString(e));
+  }
+  qst::BatchArgs& a = p->args;
+  a.items = p->d_items;
+  a.count = count;
+  a.counter = p->d_counter;
+  a.scratch = p->d_scratch;
+  a.stride = stride;
+  a.nmax = p->nmax;
+  for (int m = 1; m <= qst::kBatchMaxQubits; ++m) {
+    const qst::PovmPlan pl = qst::make_povm_plan(m, prec);
+    a.plan.passes[m] = pl.passes;
+    for (int j = 0; j < 4; ++j) {
+      a.plan.g[m][j] = pl.g[j];
+      a.plan.U[m][j] = pl.U[j];
+      a.plan.J[m][j] = pl.J[j];
+    }
+  }
+  double W[32], V[32];
+  qst::povm_mode_matrices(povm_host, W, V);
+  for (int i = 0; i < 32; ++i) {
+    a.W.a[i] = W[i];
+    a.V.a[i] = V[i];
+  }
+  // tuning key: precision, histogram of qubit counts, device
+  int hist[qst::kBatchMaxQubits + 1] = {0};
+  for (int i = 0; i < count; ++i) ++hist[p->n[i]];
+  std::ostringstream key;
+  key << "prec" << int(prec) << (p->tetra ? "-tetra" : "-povm") << "-n";
+  for (int m = 1; m <= qst::kBatchMaxQubits; ++m) key << (m > 1 ? "." : "") << hist[m];
+  key << "-" << device_name(p->device);
+  p->key = key.str();
+  std::string path = tune_cache ? tune_cache : "";
+  if (path.empty()) {
+    const char* env = std::getenv("QST_TUNE_CACHE");
+    if (env) path = env;
+  }
+  p->cache_path = path;
+  p->grid = max_grid;
+  read_cache(p);
+  *out = p;
+  qst::clear_error();
+  return QST_OK;
+}
+
+qst_status qst_batch_offsets(const qst_batch_plan* p, int64_t* t_offsets, int64_t* f_offsets) {
+  if (!p || !t_offsets || !f_offsets) return qst::fail_status(QST_ERR_INVALID_ARG, "NULL argument");
+  std::copy(p->t_off.begin(), p->t_off.end(), t_offsets);
+  std::copy(p->f_off.begin(), p->f_off.end(), f_offsets);
+  return QST_OK;
+}
+
+qst_status qst_batch_run(qst_batch_plan* p, const void* T_all, const void* f_all, double* nll_out,
+                         unsigned long long* bad_out, void* grad_all, int use_graph, void* stream) {
+  if (!p) return qst::fail_status(QST_ERR_INVALID_ARG, "plan is NULL");
+  if (!T_all || !f_all || !nll_out || !grad_all) return qst::fail_status(QST_ERR_INVALID_ARG, "NULL buffer");
+  if (T_all == grad_all) return qst::fail_status(QST_ERR_INVALID_ARG, "grad_all must not alias T_all");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (use_graph && !s) return qst::fail_status(QST_ERR_INVALID_ARG, "graph mode needs a non-null stream");
+  p->args.T_all = T_all;
+  p->args.f_all = f_all;
+  p->args.nll_out = nll_out;
+  p->args.bad_out = bad_out;
+  p->args.grad_all = grad_all;
+  hipError_t e;
+  if (!p->tuned) {
+    // autotune: grid (CUs x {1..occupancy}) x order (cost-sorted, natural)
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    double best = 1e30;
+    int best_grid = p->grid;
+    bool best_sorted = true;
+    for (int m = 1; m <= p->occ && e == hipSuccess; ++m) {
+      for (int so = 1; so >= 0 && e == hipSuccess; --so) {
+        const int grid = p->cus * m;
+        e = enqueue(p, grid, so != 0, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = enqueue(p, grid, so != 0, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && ms / 3.0 < best) {
+          best = ms / 3.0;
+          best_grid = grid;
+          best_sorted = so != 0;
+        }
+      }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return qst::fail_status(QST_ERR_HIP, std::string("batch tuning: ") + hipGetErrorString(e));
+    p->grid = best_grid;
+    p->sorted_order = best_sorted;
+    p->tuned_ms = best;
+    p->tuned = true;
+    write_cache(p);
+  }
+  if (!use_graph) {
+    e = enqueue(p, p->grid, p->sorted_order, s);
+    if (e != hipSuccess) return qst::fail_status(QST_ERR_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+    qst::clear_error();
+    return QST_OK;
+  }
+  const bool stale = !p->exec || p->g_T != T_all || p->g_f != f_all || p->g_nll != nll_out || p->g_bad != bad_out ||
+                     p->g_grad != grad_all || p->g_stream != s || p->g_grid != p->grid ||
+                     p->g_sorted != p->sorted_order;
+  if (stale) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t e1 = enqueue(p, p->grid, p->sorted_order, s);
+      e = hipStreamEndCapture(s, &p->graph);
+      if (e == hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return qst::fail_status(QST_ERR_HIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+    p->g_T = T_all;
+    p->g_f = f_all;
+    p->g_nll = nll_out;
+    p->g_bad = bad_out;
+    p->g_grad = grad_all;
+    p->g_stream = s;
+    p->g_grid = p->grid;
+    p->g_sorted = p->sorted_order;
+  }
+  e = hipGraphLaunch(p->exec, s);
+  if (e != hipSuccess) return qst::fail_status(QST_ERR_HIP, std::string("batch graph launch: ") + hipGetErrorString(e));
+  qst::clear_error();
+  return QST_OK;
+}
+
+qst_status qst_batch_info(const qst_batch_plan* p, int* grid, int* sorted_order, double* tuned_ms) {
+  if (!p) return qst::fail_status(QST_ERR_INVALID_ARG, "plan is NULL");
+  if (grid) *grid = p->grid;
+  if (sorted_order) *sorted_order = p->sorted_order ? 1 : 0;
+  if (tuned_ms) *tuned_ms = p->tuned_ms;
+  return QST_OK;
+}
+
+void qst_batch_plan_destroy(qst_batch_plan* p) { free_plan(p); }
+
+}  // extern "C"

@@ -25,6 +25,7 @@
 #include <algorithm>
 
 #include "qst_device.h"
+#include "qst_gemm_tiles.h"
 #include "qst_kernels.h"
 #include "qst_plan.h"
 
@@ -32,413 +33,7 @@ namespace qst {
 
 namespace {
 
-constexpr int BM = 64;    // output tile (complex)
-constexpr int PADC = 1;   // LDS row padding (complex elements), fp32/fp64 panels
-constexpr int PADH = 8;   // LDS row padding (bf16 elements), bf16 panels
-constexpr int TILE = BM * BM;
-
-struct GemmArgs {
-  const void* A;
-  int64_t lda;
-  const void* B;
-  int64_t ldb;
-  void* C;
-  int64_t ldc;
-  int d;
-  const double* tau;
-  const double* up;
-  int ntiles;     // output tiles
-  int kIters;     // K panels per tile
-  int64_t iters;  // ntiles * kIters
-  void* partial;  // stream-K partial accumulators [P][2][2 * TILE] (acc scalar)
-  const double* tau_part;  // HERK: FP64 partial sums of tau (kReduceBlocks), or NULL to read *tau
-  double* tau_out;         // HERK with tau_part: where workgroup 0 stores tau
-};
-
-// ---------------------------------------------------------------------------
-// Policies: one K-panel loop per (precision, product) with a common
-// accumulator shape acc[2][2] re/im, 4 values per lane.
-// ---------------------------------------------------------------------------
-template <typename R, bool HERK>
-struct CxPolicy {
-  typedef R scalar;
-  typedef typename Mfma<R>::acc acc_t;
-  static constexpr int KP = 16;  // complex K per panel
-  static constexpr bool kHerk = HERK;
-  static constexpr bool kStreamK = true;
-  struct Smem {
-    Cx<R> As[KP][BM + PADC];
-    Cx<R> Bs[KP][BM + PADC];
-  };
-  static __device__ __forceinline__ int row(int q, int v) { return Mfma<R>::row(q, v); }
-
-  static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
-                                             acc_t (&aR)[2][2], acc_t (&aI)[2][2]) {
-    const Cx<R>* A = static_cast<const Cx<R>*>(g.A);
-    const Cx<R>* B = static_cast<const Cx<R>*>(g.B);
-    const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
-    const int t = threadIdx.x;
-    const int lane = t & 63, w = t >> 6;
-    const int wr = w >> 1, wc = w & 1;
-    const int li = lane & 15, lk = lane >> 4;
-    const int a_row = t >> 2, a_k = (t & 3) * 4;   // A panel: 64 rows x 16 k
-    const int hb_k = t >> 4, hb_n = (t & 15) * 4;  // HEMM B panel: 16 k x 64 n
-    const Cx<R>* Ap = A + (R0 + a_row) * g.lda + a_k;
-    const Cx<R>* Bp = HERK ? (B + (C0 + a_row) * g.ldb + a_k) : (B + int64_t(hb_k) * g.ldb + C0 + hb_n);
-    // register prefetch of the next panel (written out, not via a lambda:
-    // captured arrays would be kept in scratch memory)
-    // (held as native 2-vectors: an aligned struct array would go to scratch)
-    typedef R v2 __attribute__((ext_vector_type(2)));
-    const v2* Av = reinterpret_cast<const v2*>(Ap);
-    const v2* Bv = reinterpret_cast<const v2*>(Bp);
-    v2 ra[4], rb[4];
-#define QST_LOAD_PANEL(kp)                                                   \
-  do {                                                                       \
-    const int k0_ = (kp) * KP;                                               \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) ra[i] = Av[k0_ + i];       \
-    if constexpr (HERK) {                                                    \
-      _Pragma("unroll") for (int i = 0; i < 4; ++i) rb[i] = Bv[k0_ + i];     \
-    } else {                                                                 \
-      _Pragma("unroll") for (int i = 0; i < 4; ++i) rb[i] = Bv[int64_t(k0_) * g.ldb + i]; \
-    }                                                                        \
-  } while (0)
-    QST_LOAD_PANEL(kb);
-    for (int kp = kb; kp < ke; ++kp) {
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sm.As[a_k + i][a_row] = Cx<R>{ra[i].x, ra[i].y};
-      if constexpr (HERK) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sm.Bs[a_k + i][a_row] = Cx<R>{rb[i].x, rb[i].y};
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sm.Bs[hb_k][hb_n + i] = Cx<R>{rb[i].x, rb[i].y};
-      }
-      __syncthreads();
-      if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
-#undef QST_LOAD_PANEL
-#pragma unroll
-      for (int ks = 0; ks < KP / 4; ++ks) {
-        const int kk = ks * 4 + lk;
-        Cx<R> a[2], b[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = sm.As[kk][wr * 32 + i * 16 + li];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = sm.Bs[kk][wc * 32 + j * 16 + li];
-        // eight independent accumulator chains, each advanced once per sweep
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            aR[i][j] = Mfma<R>::step(a[i].re, b[j].re, aR[i][j]);
-            aI[i][j] = Mfma<R>::step(HERK ? a[i].im : a[i].re, HERK ? b[j].re : b[j].im, aI[i][j]);
-          }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            // HERK: re += ai bi, im -= ar bi;  HEMM: re -= ai bi, im += ai br
-            aR[i][j] = Mfma<R>::step(HERK ? a[i].im : -a[i].im, b[j].im, aR[i][j]);
-            aI[i][j] = Mfma<R>::step(HERK ? -a[i].re : a[i].im, HERK ? b[j].im : b[j].re, aI[i][j]);
-          }
-      }
-    }
-  }
-};
-
-// T T^dagger with T rounded to bf16 (RNE), fp32 accumulate.
-struct HerkBf16Policy {
-  typedef float scalar;
-  typedef f4 acc_t;
-  static constexpr int KP = 32;  // one MFMA K step
-  static constexpr bool kHerk = true;
-  static constexpr bool kStreamK = false;  // load-bound: splitting K only adds partial traffic
-  struct Smem {
-    uint16_t Ar[BM][KP + PADH], Ai[BM][KP + PADH], Br[BM][KP + PADH], Bi[BM][KP + PADH];
-  };
-  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
-
-  static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
-                                             acc_t (&aR)[2][2], acc_t (&aI)[2][2]) {
-    const Cx<float>* T = static_cast<const Cx<float>*>(g.A);
-    const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
-    const int t = threadIdx.x;
-    const int lane = t & 63, w = t >> 6;
-    const int wr = w >> 1, wc = w & 1;
-    const int li = lane & 15, lq = lane >> 4;
-    const int row = t >> 2, kq = (t & 3) * 8;  // 64 rows x 32 k, 8 complex per thread
-    const Cx<float>* Ap = T + (R0 + row) * g.lda + kq;
-    const Cx<float>* Bp = T + (C0 + row) * g.lda + kq;
-    Cx<float> ra[8], rb[8];
-#define QST_LOAD_PANEL(kp)                                 \
-  do {                                                     \
-    const int k0_ = (kp) * KP;                             \
-    _Pragma("unroll") for (int i = 0; i < 8; ++i) {        \
-      ra[i] = Ap[k0_ + i];                                 \
-      rb[i] = Bp[k0_ + i];                                 \
-    }                                                      \
-  } while (0)
-    QST_LOAD_PANEL(kb);
-    for (int kp = kb; kp < ke; ++kp) {
-      __syncthreads();
-      {
-        u16x8 xr, xi, yr, yi;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          xr[i] = bf16_bits(ra[i].re);
-          xi[i] = bf16_bits(ra[i].im);
-          yr[i] = bf16_bits(rb[i].re);
-          yi[i] = bf16_bits(rb[i].im);
-        }
-        *reinterpret_cast<u16x8*>(&sm.Ar[row][kq]) = xr;
-        *reinterpret_cast<u16x8*>(&sm.Ai[row][kq]) = xi;
-        *reinterpret_cast<u16x8*>(&sm.Br[row][kq]) = yr;
-        *reinterpret_cast<u16x8*>(&sm.Bi[row][kq]) = yi;
-      }
-      __syncthreads();
-      if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
-#undef QST_LOAD_PANEL
-      u16x8 a_r[2], a_i[2], b_r[2], b_i[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a_r[i] = *reinterpret_cast<const u16x8*>(&sm.Ar[wr * 32 + i * 16 + li][lq * 8]);
-        a_i[i] = *reinterpret_cast<const u16x8*>(&sm.Ai[wr * 32 + i * 16 + li][lq * 8]);
-        b_r[i] = *reinterpret_cast<const u16x8*>(&sm.Br[wc * 32 + i * 16 + li][lq * 8]);
-        b_i[i] = *reinterpret_cast<const u16x8*>(&sm.Bi[wc * 32 + i * 16 + li][lq * 8]);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          aR[i][j] = mfma_bf16(a_r[i], b_r[j], aR[i][j]);
-          aI[i][j] = mfma_bf16(a_i[i], b_r[j], aI[i][j]);
-        }
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const u16x8 na = bf16_neg(a_r[i]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          aR[i][j] = mfma_bf16(a_i[i], b_i[j], aR[i][j]);
-          aI[i][j] = mfma_bf16(na, b_i[j], aI[i][j]);
-        }
-      }
-    }
-  }
-};
-
-// G' T with split-bf16 operands: x = hi + lo, hi = bf16(x), lo = bf16(x - hi);
-// the product keeps hi*hi + hi*lo + lo*hi (lo*lo is below fp32 rounding).
-struct HemmBf16x3Policy {
-  typedef float scalar;
-  typedef f4 acc_t;
-  static constexpr int KP = 32;
-  static constexpr bool kHerk = false;
-  static constexpr bool kStreamK = true;
-  struct Smem {
-    uint16_t As[4][BM][KP + PADH];  // re_hi, im_hi, re_lo, im_lo
-    uint16_t Bt[4][BM][KP + PADH];  // transposed: [n][k]
-  };
-  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
-
-  static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
-                                             acc_t (&aR)[2][2], acc_t (&aI)[2][2]) {
-    const Cx<float>* G = static_cast<const Cx<float>*>(g.A);
-    const Cx<float>* T = static_cast<const Cx<float>*>(g.B);
-    const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
-    const int t = threadIdx.x;
-    const int lane = t & 63, w = t >> 6;
-    const int wr = w >> 1, wc = w & 1;
-    const int li = lane & 15, lq = lane >> 4;
-    const int a_row = t >> 2, a_k = (t & 3) * 8;  // A panel: 64 rows x 32 k
-    const int b_k = t >> 3, b_n = (t & 7) * 8;    // B panel: 32 k x 64 n
-    const Cx<float>* Ap = G + (R0 + a_row) * g.lda + a_k;
-    const Cx<float>* Bp = T + int64_t(b_k) * g.ldb + C0 + b_n;
-    Cx<float> ra[8], rb[8];
-#define QST_LOAD_PANEL(kp)                                 \
-  do {                                                     \
-    const int k0_ = (kp) * KP;                             \
-    _Pragma("unroll") for (int i = 0; i < 8; ++i) {        \
-      ra[i] = Ap[k0_ + i];                                 \
-      rb[i] = Bp[int64_t(k0_) * g.ldb + i];                \
-    }                                                      \
-  } while (0)
-    QST_LOAD_PANEL(kb);
-    for (int kp = kb; kp < ke; ++kp) {
-      __syncthreads();
-      {
-        u16x8 h0, h1, l0, l1;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const uint16_t hr = bf16_bits(ra[i].re), hm = bf16_bits(ra[i].im);
-          h0[i] = hr;
-          h1[i] = hm;
-          l0[i] = bf16_bits(ra[i].re - __uint_as_float(uint32_t(hr) << 16));
-          l1[i] = bf16_bits(ra[i].im - __uint_as_float(uint32_t(hm) << 16));
-        }
-        *reinterpret_cast<u16x8*>(&sm.As[0][a_row][a_k]) = h0;
-        *reinterpret_cast<u16x8*>(&sm.As[1][a_row][a_k]) = h1;
-        *reinterpret_cast<u16x8*>(&sm.As[2][a_row][a_k]) = l0;
-        *reinterpret_cast<u16x8*>(&sm.As[3][a_row][a_k]) = l1;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const uint16_t hr = bf16_bits(rb[i].re), hm = bf16_bits(rb[i].im);
-          sm.Bt[0][b_n + i][b_k] = hr;
-          sm.Bt[1][b_n + i][b_k] = hm;
-          sm.Bt[2][b_n + i][b_k] = bf16_bits(rb[i].re - __uint_as_float(uint32_t(hr) << 16));
-          sm.Bt[3][b_n + i][b_k] = bf16_bits(rb[i].im - __uint_as_float(uint32_t(hm) << 16));
-        }
-      }
-      __syncthreads();
-      if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
-#undef QST_LOAD_PANEL
-      u16x8 a[2][4], b[2][4];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
-          a[i][pl] = *reinterpret_cast<const u16x8*>(&sm.As[pl][wr * 32 + i * 16 + li][lq * 8]);
-          b[i][pl] = *reinterpret_cast<const u16x8*>(&sm.Bt[pl][wc * 32 + i * 16 + li][lq * 8]);
-        }
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const u16x8 nih = bf16_neg(a[i][1]), nil = bf16_neg(a[i][3]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          // complex: re = ar br - ai bi, im = ar bi + ai br;  hi*hi, hi*lo, lo*hi
-          aR[i][j] = mfma_bf16(a[i][0], b[j][0], aR[i][j]);
-          aR[i][j] = mfma_bf16(nih, b[j][1], aR[i][j]);
-          aI[i][j] = mfma_bf16(a[i][0], b[j][1], aI[i][j]);
-          aI[i][j] = mfma_bf16(a[i][1], b[j][0], aI[i][j]);
-          aR[i][j] = mfma_bf16(a[i][0], b[j][2], aR[i][j]);
-          aR[i][j] = mfma_bf16(nih, b[j][3], aR[i][j]);
-          aI[i][j] = mfma_bf16(a[i][0], b[j][3], aI[i][j]);
-          aI[i][j] = mfma_bf16(a[i][1], b[j][2], aI[i][j]);
-          aR[i][j] = mfma_bf16(a[i][2], b[j][0], aR[i][j]);
-          aR[i][j] = mfma_bf16(nil, b[j][1], aR[i][j]);
-          aI[i][j] = mfma_bf16(a[i][2], b[j][1], aI[i][j]);
-          aI[i][j] = mfma_bf16(a[i][3], b[j][0], aI[i][j]);
-        }
-      }
-    }
-  }
-};
-
-// ---------------------------------------------------------------------------
-// Shared tile plumbing
-// ---------------------------------------------------------------------------
-template <class P>
-__device__ __forceinline__ void tile_coords(const GemmArgs& g, int tile, int& tr, int& tc) {
-  if constexpr (P::kHerk) {
-    tri_decode(tile, tr, tc);
-  } else {
-    const int tiles = g.d / BM;
-    tr = tile / tiles;
-    tc = tile % tiles;
-  }
-}
-
-template <class P>
-__device__ __forceinline__ void zero_acc(typename P::acc_t (&aR)[2][2], typename P::acc_t (&aI)[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      aR[i][j] = typename P::acc_t{0, 0, 0, 0};
-      aI[i][j] = typename P::acc_t{0, 0, 0, 0};
-    }
-}
-
-// Output scale, evaluated by every workgroup at its start: 1/tau for
-// T T^dagger, s * 2/tau for G' T.  With tau partials, tau is their sum in a
-// fixed order (bitwise the same in every workgroup), and workgroup 0 stores it.
-template <class P>
-__device__ double tile_scale(const GemmArgs& g) {
-  double tau;
-  if (g.tau_part) {
-    __shared__ double red[4];
-    __shared__ double bcast;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < kReduceBlocks; b += blockDim.x) acc += g.tau_part[b];
-    const double sum = block_sum256(acc, red);
-    if (threadIdx.x == 0) {
-      bcast = sum;
-      if (blockIdx.x == 0 && g.tau_out) *g.tau_out = sum;
-    }
-    __syncthreads();
-    tau = bcast;
-  } else {
-    tau = *g.tau;
-  }
-  if constexpr (P::kHerk) {
-    return 1.0 / tau;
-  } else {
-    double s = 2.0 / tau;
-    if (g.up) s *= *g.up;
-    return s;
-  }
-}
-
-template <class P>
-__device__ __forceinline__ void epilogue(const GemmArgs& g, int tr, int tc, typename P::acc_t (&aR)[2][2],
-                                         typename P::acc_t (&aI)[2][2], double scale) {
-  typedef typename P::scalar R;
-  Cx<R>* C = static_cast<Cx<R>*>(g.C);
-  const R sc = R(scale);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w >> 1, wc = w & 1, li = lane & 15, lq = lane >> 4;
-  const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t col = C0 + wc * 32 + j * 16 + li;
-      const int64_t rbase = R0 + wr * 32 + i * 16;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = rbase + P::row(lq, v);
-        C[row * g.ldc + col] = Cx<R>{aR[i][j][v] * sc, aI[i][j][v] * sc};
-        if (P::kHerk && tr != tc) C[col * g.ldc + row] = Cx<R>{aR[i][j][v] * sc, -aI[i][j][v] * sc};
-      }
-    }
-  }
-}
-
-// Partial accumulators of one tile segment, stored per lane in the MFMA
-// layout: element ((((w*2 + i)*2 + j)*2 + part)*4 + v)*64 + lane.
-template <class P>
-__device__ __forceinline__ typename P::scalar* partial_slot(const GemmArgs& g, int wg, int which) {
-  return static_cast<typename P::scalar*>(g.partial) + (int64_t(wg) * 2 + which) * int64_t(2 * TILE);
-}
-
-template <class P>
-__device__ __forceinline__ void store_partial(typename P::scalar* dst, typename P::acc_t (&aR)[2][2],
-                                              typename P::acc_t (&aI)[2][2]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        dst[((((w * 2 + i) * 2 + j) * 2 + 0) * 4 + v) * 64 + lane] = aR[i][j][v];
-        dst[((((w * 2 + i) * 2 + j) * 2 + 1) * 4 + v) * 64 + lane] = aI[i][j][v];
-      }
-}
-
-template <class P>
-__device__ __forceinline__ void add_partial(const typename P::scalar* src, typename P::acc_t (&aR)[2][2],
-                                            typename P::acc_t (&aI)[2][2]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        aR[i][j][v] += src[((((w * 2 + i) * 2 + j) * 2 + 0) * 4 + v) * 64 + lane];
-        aI[i][j][v] += src[((((w * 2 + i) * 2 + j) * 2 + 1) * 4 + v) * 64 + lane];
-      }
-}
+using namespace gemm;
 
 // First iteration owned by stream-K workgroup w of P.
 __device__ __forceinline__ int64_t sk_start(int64_t w, int64_t P, int64_t iters) { return (w * iters) / P; }

@@ -1,0 +1,156 @@
+"""Batched form (many instances of mixed qubit counts in one persistent launch)
+against the FP64 oracle, per instance, and against the single-instance path.
+
+Workload: 1024 instances, N_i uniform on {3..8} (seed 9), Ginibre T_i, target
+per instance a depolarised Haar pure state with q ~ U(0,1), 10^5 multinomial
+shots each.  Tolerances as in test_gpu_parity (relative: FP64 1e-12, FP32
+1e-5, BF16 2e-3 on L; gradient by Frobenius norm).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+from workloads import rel_fro
+
+torch = pytest.importorskip("torch")
+qst = pytest.importorskip("paper_2207_05341_amd")
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3}
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def make_batch(count, seed, lo=3, hi=8, shots=100_000):
+    g = S.rng(seed)
+    ns = S.batch_qubit_counts(g, count, lo, hi)
+    Ts, fs = [], []
+    for n in ns:
+        d = 1 << int(n)
+        T = S.ginibre(g, d)
+        psi = S.haar_vector(g, d)
+        q = float(g.uniform())
+        f = S.multinomial_freqs(g, shots, O.probs_real(S.depolarised_pure(psi, q)))
+        Ts.append(T)
+        fs.append(f)
+    return [int(n) for n in ns], Ts, fs
+
+
+def oracle_one(T, f):
+    rho, tau = O.state_map(T)
+    n = O.n_qubits_of(T.shape[0])
+    p = O.probs_real(rho)
+    L = O.nll_vec(p, f)
+    grad = (2.0 / tau) * (O.adjoint(O.cotangent(p, f), n) @ T)
+    return L, grad
+
+
+@pytest.fixture(scope="module")
+def batch1024():
+    say("building 1024 batched instances (seed 9) and their oracle results")
+    ns, Ts, fs = make_batch(1024, 9)
+    ref = [oracle_one(T, f) for T, f in zip(Ts, fs)]
+    return ns, Ts, fs, ref
+
+
+def quantize(Ts, fs, prec):
+    ct = np.complex128 if prec == "f64" else np.complex64
+    rt = np.float64 if prec == "f64" else np.float32
+    return [T.astype(ct) for T in Ts], [f.astype(rt) for f in fs]
+
+
+def unpack(plan, grad_all):
+    g = grad_all.cpu().numpy()
+    return [g[plan.t_off[i]:plan.t_off[i + 1]].reshape(1 << plan.n[i], 1 << plan.n[i]) for i in range(len(plan.n))]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64", "bf16"])
+def test_batch_1024_against_oracle(batch1024, prec):
+    ns, Ts, fs, ref = batch1024
+    say(f"batched 1024 instances, {prec}")
+    Tq, fq = quantize(Ts, fs, prec)
+    plan = qst.BatchPlan(ns, prec)
+    T_all, f_all = plan.pack(Tq, fq, DEV)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        nll, grad, bad = plan.run(T_all, f_all, use_graph=True)
+    side.synchronize()
+    say(f"  tuned launch shape {plan.info()}")
+    nll = nll.cpu().numpy()
+    grads = unpack(plan, grad)
+    assert (bad.cpu().numpy() == 0).all()
+    worst_L = worst_g = 0.0
+    check = range(len(ns)) if prec == "f32" else range(0, len(ns), 8)
+    for i in check:
+        if prec == "f64":
+            L_ref, g_ref = ref[i]
+        else:
+            L_ref, g_ref = oracle_one(Tq[i].astype(np.complex128), fq[i].astype(np.float64))
+        worst_L = max(worst_L, abs(nll[i, 0] - L_ref) / abs(L_ref))
+        worst_g = max(worst_g, rel_fro(grads[i], g_ref))
+        assert abs(nll[i, 1] - fq[i].astype(np.float64).sum()) <= 1e-9
+    say(f"  worst relative L error {worst_L:.3e}, worst gradient error {worst_g:.3e}")
+    assert worst_L <= TOL[prec] and worst_g <= TOL[prec]
+    plan.close()
+
+
+def test_batch_graph_replay_equals_eager_and_single_path(batch1024):
+    """Graph replays (several, with eager work between them) are bitwise equal
+    to an eager launch; the batch agrees with the single-instance C-ABI path."""
+    ns, Ts, fs, _ = batch1024
+    say("batched graph replay vs eager vs single-instance path (f32)")
+    sel = list(range(0, 1024, 4))
+    ns_s = [ns[i] for i in sel]
+    Tq, fq = quantize([Ts[i] for i in sel], [fs[i] for i in sel], "f32")
+    plan = qst.BatchPlan(ns_s, "f32")
+    T_all, f_all = plan.pack(Tq, fq, DEV)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ref_nll, ref_grad, _ = plan.run(T_all, f_all, use_graph=False)
+        ref_nll, ref_grad = ref_nll.clone(), ref_grad.clone()
+        for rep in range(3):
+            nll, grad, _ = plan.run(T_all, f_all, use_graph=True)
+            side.synchronize()
+            assert torch.equal(nll, ref_nll) and torch.equal(grad, ref_grad), rep
+            # unrelated eager work between replays
+            _ = (T_all * 2).sum()
+    side.synchronize()
+    grads = unpack(plan, ref_grad)
+    for k in range(0, len(sel), 16):
+        Tg = torch.from_numpy(Tq[k]).to(DEV)
+        fg = torch.from_numpy(fq[k]).to(DEV)
+        rho, tau = qst.state_map(Tg, "f32")
+        p = qst.povm_probs(rho, "f32")
+        out, _ = qst.nll(p, fg, "f32")
+        g1 = qst.nll_backward(Tg, fg, p, tau, "f32", nll_out=out).cpu().numpy()
+        assert abs(out[0].item() - ref_nll[k, 0].item()) <= 1e-5 * abs(out[0].item())
+        assert rel_fro(grads[k], g1) <= 1e-5
+    plan.close()
+
+
+def test_batch_small_n_and_general_povm():
+    """Instances down to N = 1, and a non-tetrahedral POVM (generic kernels)."""
+    say("batched small N and general POVM (f64)")
+    ns, Ts, fs = make_batch(40, 31, lo=1, hi=6, shots=2000)
+    g = S.rng(32)
+    U, _ = np.linalg.qr(S.ginibre(g, 2))
+    M = np.array([U @ m @ U.conj().T for m in O.tetrahedral_povm()])
+    plan = qst.BatchPlan(ns, "f64", povm=M)
+    T_all, f_all = plan.pack(Ts, fs, DEV)
+    nll, grad, _ = plan.run(T_all, f_all, use_graph=False)
+    torch.cuda.synchronize()
+    grads = unpack(plan, grad)
+    nll = nll.cpu().numpy()
+    for i in range(len(ns)):
+        rho, tau = O.state_map(Ts[i])
+        p = O.probs_real(rho, M) if ns[i] > 5 else O.probs_kron(rho, M).real.copy()
+        L = O.nll_vec(p, fs[i])
+        gr = (2.0 / tau) * (O.adjoint(O.cotangent(p, fs[i]), ns[i], M) @ Ts[i])
+        assert abs(nll[i, 0] - L) <= 1e-12 * abs(L)
+        assert rel_fro(grads[i], gr) <= 1e-12
+    plan.close()
