@@ -65,11 +65,13 @@ typedef enum {
   /* complex64 T and rho, float32 p and f; FP32 MFMA products with FP32
    * accumulation; tau and the log-likelihood sum in FP64. */
   QST_F32 = 1,
-  /* complex64 storage as QST_F32.  T T^dagger takes T rounded to bfloat16
-   * (round-to-nearest-even) on the BF16 MFMA with FP32 accumulation, and tau
-   * is the FP64 sum over that same rounded T.  The gradient product G' T
-   * uses split bfloat16 operands (hi + lo, three products) so that the
-   * gradient keeps ~1e-4 relative accuracy. */
+  /* complex64 storage as QST_F32.  For d >= 256, T T^dagger takes T rounded
+   * to bfloat16 (round-to-nearest-even) on the BF16 MFMA with FP32
+   * accumulation; for d <= 128 T is split into bfloat16 hi + lo (three
+   * products), because plain rounding there moves the gradient by more than
+   * 2e-3 relative.  tau is the FP64 sum over the same represented T.  The
+   * gradient product G' T always uses split bfloat16 operands (hi + lo,
+   * three products). */
   QST_BF16GEMM = 2
 } qst_prec;
 

@@ -116,15 +116,41 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
       const Cx<R> v = T[e];
       double x = double(v.re), y = double(v.im);
       if constexpr (BF16) {
-        x = double(bf16_value(float(v.re)));
-        y = double(bf16_value(float(v.im)));
+        const float hr = bf16_value(float(v.re)), hi = bf16_value(float(v.im));
+        if (d <= kBf16SplitMaxDim) {  // split bf16 hi + lo
+          x = double(hr + bf16_value(float(v.re) - hr));
+          y = double(hi + bf16_value(float(v.im) - hi));
+        } else {
+          x = double(hr);
+          y = double(hi);
+        }
       }
       acc += x * x + y * y;
     }
     const double tau = block_sum_bcast(acc, red, slotp);
 
     // 2. rho = T T^dagger / tau
-    if (d >= 64) {
+    if (BF16 && d >= 64 && d <= kBf16SplitMaxDim) {
+      gemm::GemmArgs g{};
+      g.A = T;
+      g.lda = d;
+      g.B = T;
+      g.ldb = d;
+      g.C = rho;
+      g.ldc = d;
+      g.d = d;
+      g.kIters = d / gemm::HerkBf16x3Policy::KP;
+      const int tiles = d / 64;
+      for (int tile = 0; tile < tiles * (tiles + 1) / 2; ++tile) {
+        int tr, tc;
+        tri_decode(tile, tr, tc);
+        f4 aR[2][2], aI[2][2];
+        gemm::zero_acc<gemm::HerkBf16x3Policy>(aR, aI);
+        gemm::HerkBf16x3Policy::run(g, *reinterpret_cast<gemm::HerkBf16x3Policy::Smem*>(pool), tr, tc, 0,
+                                    g.kIters, aR, aI);
+        gemm::epilogue<gemm::HerkBf16x3Policy>(g, tr, tc, aR, aI, 1.0 / tau);
+      }
+    } else if (d >= 64) {
       gemm::GemmArgs g{};
       g.A = T;
       g.lda = d;
@@ -148,13 +174,18 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
         const int r = int(e >> n), c = int(e & (d - 1));
         R sr = 0, si = 0;
         for (int k = 0; k < d; ++k) {
-          Cx<R> x = T[int64_t(r) * d + k], y = T[int64_t(c) * d + k];
-          if constexpr (BF16) {
-            x = {R(bf16_value(float(x.re))), R(bf16_value(float(x.im)))};
-            y = {R(bf16_value(float(y.re))), R(bf16_value(float(y.im)))};
+          const Cx<R> x = T[int64_t(r) * d + k], y = T[int64_t(c) * d + k];
+          if constexpr (BF16) {  // d < 64: split bf16 x 3
+            const float ahr = bf16_value(float(x.re)), ahi = bf16_value(float(x.im));
+            const float alr = bf16_value(float(x.re) - ahr), ali = bf16_value(float(x.im) - ahi);
+            const float bhr = bf16_value(float(y.re)), bhi = bf16_value(float(y.im));
+            const float blr = bf16_value(float(y.re) - bhr), bli = bf16_value(float(y.im) - bhi);
+            sr += (ahr * bhr + ahi * bhi) + (ahr * blr + ahi * bli) + (alr * bhr + ali * bhi);
+            si += (ahi * bhr - ahr * bhi) + (ahi * blr - ahr * bli) + (ali * bhr - alr * bhi);
+          } else {
+            sr += x.re * y.re + x.im * y.im;
+            si += x.im * y.re - x.re * y.im;
           }
-          sr += x.re * y.re + x.im * y.im;
-          si += x.im * y.re - x.re * y.im;
         }
         rho[e] = Cx<R>{R(sr / tau), R(si / tau)};
       }

@@ -114,12 +114,17 @@ __global__ void herk_small_kernel(const Cx<R>* __restrict__ T, int64_t ldt, Cx<R
   R sr = 0, si = 0;
   for (int k = 0; k < d; ++k) {
     Cx<R> a = T[int64_t(i) * ldt + k], b = T[int64_t(j) * ldt + k];
-    if constexpr (BF16) {
-      a = {R(bf16_value(float(a.re))), R(bf16_value(float(a.im)))};
-      b = {R(bf16_value(float(b.re))), R(bf16_value(float(b.im)))};
+    if constexpr (BF16) {  // d < 64: split bf16 x 3, as the d <= 128 tiles
+      const float ahr = bf16_value(float(a.re)), ahi = bf16_value(float(a.im));
+      const float alr = bf16_value(float(a.re) - ahr), ali = bf16_value(float(a.im) - ahi);
+      const float bhr = bf16_value(float(b.re)), bhi = bf16_value(float(b.im));
+      const float blr = bf16_value(float(b.re) - bhr), bli = bf16_value(float(b.im) - bhi);
+      sr += (ahr * bhr + ahi * bhi) + (ahr * blr + ahi * bli) + (alr * bhr + ali * bhi);
+      si += (ahi * bhr - ahr * bhi) + (ahi * blr - ahr * bli) + (ali * bhr - alr * bhi);
+    } else {
+      sr += a.re * b.re + a.im * b.im;
+      si += a.im * b.re - a.re * b.im;
     }
-    sr += a.re * b.re + a.im * b.im;
-    si += a.im * b.re - a.re * b.im;
   }
   const double inv = 1.0 / *tau_dev;
   C[int64_t(i) * ldc + j] = Cx<R>{R(sr * inv), R(si * inv)};
@@ -239,6 +244,7 @@ hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int
   g.tau_out = tau_partials ? tau_dev : nullptr;
   if (prec == QST_F64) return run_gemm<CxPolicy<double, true>>(g, s);
   if (prec == QST_F32) return run_gemm<CxPolicy<float, true>>(g, s);
+  if (d <= kBf16SplitMaxDim) return run_gemm<HerkBf16x3Policy>(g, s);
   return run_gemm<HerkBf16Policy>(g, s);
 }
 

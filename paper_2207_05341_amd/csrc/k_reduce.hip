@@ -14,7 +14,8 @@ namespace qst {
 
 namespace {
 
-template <typename R, bool ROUND>
+// ROUND: 0 = T as given, 1 = bf16(T), 2 = bf16 hi + lo of T (exact in fp32).
+template <typename R, int ROUND>
 __global__ __launch_bounds__(256) void tau_partial_kernel(const Cx<R>* __restrict__ T, int64_t ld,
                                                           int n, double* __restrict__ partials) {
   __shared__ double red[4];
@@ -23,21 +24,27 @@ __global__ __launch_bounds__(256) void tau_partial_kernel(const Cx<R>* __restric
   const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
   const int64_t beg = int64_t(blockIdx.x) * chunk;
   const int64_t end = beg + chunk < total ? beg + chunk : total;
-  // Four strided elements per thread in flight; per-thread order fixed.
+  // Up to 16 strided elements per thread are loaded before any arithmetic
+  // (all loads in flight at once); the per-thread summation order is fixed.
+  constexpr int U = 16;
   double acc = 0.0;
-  for (int64_t e0 = beg + threadIdx.x; e0 < end; e0 += 4 * int64_t(blockDim.x)) {
-    Cx<R> v[4];
+  for (int64_t e0 = beg + threadIdx.x; e0 < end; e0 += U * int64_t(blockDim.x)) {
+    Cx<R> v[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + u * int64_t(blockDim.x);
       v[u] = e < end ? T[(e >> n) * ld + (e & (d - 1))] : Cx<R>{R(0), R(0)};
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       double x = double(v[u].re), y = double(v[u].im);
-      if constexpr (ROUND) {
+      if constexpr (ROUND == 1) {
         x = double(bf16_value(float(v[u].re)));
         y = double(bf16_value(float(v[u].im)));
+      } else if constexpr (ROUND == 2) {
+        const float hr = bf16_value(float(v[u].re)), hi = bf16_value(float(v[u].im));
+        x = double(hr + bf16_value(float(v[u].re) - hr));
+        y = double(hi + bf16_value(float(v[u].im) - hi));
       }
       acc += x * x + y * y;
     }
@@ -68,19 +75,20 @@ __global__ __launch_bounds__(256) void nll_partial_kernel(const R* __restrict__ 
   const int64_t chunk = (D + nb - 1) / nb;
   const int64_t beg = int64_t(blockIdx.x) * chunk;
   const int64_t end = beg + chunk < D ? beg + chunk : D;
-  // Four strided elements per thread in flight; per-thread order fixed.
+  // Up to 16 strided elements per thread loaded before any arithmetic.
+  constexpr int U = 16;
   double L = 0.0, F = 0.0, bad0 = 0.0, bad1 = 0.0;
-  for (int64_t k0 = beg + threadIdx.x; k0 < end; k0 += 4 * int64_t(blockDim.x)) {
-    R fv[4], pv[4];
+  for (int64_t k0 = beg + threadIdx.x; k0 < end; k0 += U * int64_t(blockDim.x)) {
+    R fv[U], pv[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int64_t k = k0 + u * int64_t(blockDim.x);
       const bool in = k < end;
       fv[u] = in ? f[k] : R(0);
       if constexpr (WITH_P) pv[u] = in ? p[k] : R(1);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const double fk = double(fv[u]);
       F += fk;
       if constexpr (WITH_P) {
@@ -143,11 +151,13 @@ hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* p
   const int nb = kReduceBlocks;
   ProfScope prof("tau_reduce", s);
   if (prec == QST_F64) {
-    tau_partial_kernel<double, false><<<nb, 256, 0, s>>>(static_cast<const Cx<double>*>(T), ld, n, partials);
+    tau_partial_kernel<double, 0><<<nb, 256, 0, s>>>(static_cast<const Cx<double>*>(T), ld, n, partials);
   } else if (prec == QST_F32) {
-    tau_partial_kernel<float, false><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
+    tau_partial_kernel<float, 0><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
+  } else if ((int64_t(1) << n) <= kBf16SplitMaxDim) {
+    tau_partial_kernel<float, 2><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
   } else {
-    tau_partial_kernel<float, true><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
+    tau_partial_kernel<float, 1><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
   }
   if (tau_dev) finish_sums_kernel<<<1, 256, 0, s>>>(partials, nb, 1, tau_dev);
   return hipGetLastError();

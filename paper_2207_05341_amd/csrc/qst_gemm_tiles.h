@@ -203,6 +203,98 @@ struct HerkBf16Policy {
   }
 };
 
+// T T^dagger with T split into bf16 hi + lo (three products: hi hi^dagger +
+// hi lo^dagger + lo hi^dagger), fp32 accumulate.  Used for small d, where the
+// rounding of plain bf16 T moves the gradient by more than the BF16 bar.
+struct HerkBf16x3Policy {
+  typedef float scalar;
+  typedef f4 acc_t;
+  static constexpr int KP = 32;
+  static constexpr bool kHerk = true;
+  static constexpr bool kStreamK = false;
+  struct Smem {
+    uint16_t A[4][BM][KP + PADH];  // re_hi, im_hi, re_lo, im_lo of the row block
+    uint16_t B[4][BM][KP + PADH];  // same for the column block
+  };
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+
+  static __device__ __forceinline__ void split_store(uint16_t (*P)[BM][KP + PADH], int row, int kq,
+                                                     const Cx<float> (&v)[8]) {
+    u16x8 h0, h1, l0, l1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint16_t hr = bf16_bits(v[i].re), hm = bf16_bits(v[i].im);
+      h0[i] = hr;
+      h1[i] = hm;
+      l0[i] = bf16_bits(v[i].re - __uint_as_float(uint32_t(hr) << 16));
+      l1[i] = bf16_bits(v[i].im - __uint_as_float(uint32_t(hm) << 16));
+    }
+    *reinterpret_cast<u16x8*>(&P[0][row][kq]) = h0;
+    *reinterpret_cast<u16x8*>(&P[1][row][kq]) = h1;
+    *reinterpret_cast<u16x8*>(&P[2][row][kq]) = l0;
+    *reinterpret_cast<u16x8*>(&P[3][row][kq]) = l1;
+  }
+
+  static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
+                                             acc_t (&aR)[2][2], acc_t (&aI)[2][2]) {
+    const Cx<float>* T = static_cast<const Cx<float>*>(g.A);
+    const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int li = lane & 15, lq = lane >> 4;
+    const int row = t >> 2, kq = (t & 3) * 8;
+    const Cx<float>* Ap = T + (R0 + row) * g.lda + kq;
+    const Cx<float>* Bp = T + (C0 + row) * g.lda + kq;
+    Cx<float> ra[8], rb[8];
+#define QST_LOAD_PANEL(kp)                                 \
+  do {                                                     \
+    const int k0_ = (kp) * KP;                             \
+    _Pragma("unroll") for (int i = 0; i < 8; ++i) {        \
+      ra[i] = Ap[k0_ + i];                                 \
+      rb[i] = Bp[k0_ + i];                                 \
+    }                                                      \
+  } while (0)
+    QST_LOAD_PANEL(kb);
+    for (int kp = kb; kp < ke; ++kp) {
+      __syncthreads();
+      split_store(sm.A, row, kq, ra);
+      split_store(sm.B, row, kq, rb);
+      __syncthreads();
+      if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
+#undef QST_LOAD_PANEL
+      u16x8 a[2][4], b[2][4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+          a[i][pl] = *reinterpret_cast<const u16x8*>(&sm.A[pl][wr * 32 + i * 16 + li][lq * 8]);
+          b[i][pl] = *reinterpret_cast<const u16x8*>(&sm.B[pl][wc * 32 + i * 16 + li][lq * 8]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const u16x8 nrh = bf16_neg(a[i][0]), nrl = bf16_neg(a[i][2]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          // A B^dagger: re = ar br + ai bi, im = ai br - ar bi;  hi*hi, hi*lo, lo*hi
+          aR[i][j] = mfma_bf16(a[i][0], b[j][0], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[i][1], b[j][0], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[i][1], b[j][1], aR[i][j]);
+          aI[i][j] = mfma_bf16(nrh, b[j][1], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[i][0], b[j][2], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[i][1], b[j][2], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[i][1], b[j][3], aR[i][j]);
+          aI[i][j] = mfma_bf16(nrh, b[j][3], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[i][2], b[j][0], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[i][3], b[j][0], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[i][3], b[j][1], aR[i][j]);
+          aI[i][j] = mfma_bf16(nrl, b[j][1], aI[i][j]);
+        }
+      }
+    }
+  }
+};
+
 // G' T with split-bf16 operands: x = hi + lo, hi = bf16(x), lo = bf16(x - hi);
 // the product keeps hi*hi + hi*lo + lo*hi (lo*lo is below fp32 rounding).
 struct HemmBf16x3Policy {

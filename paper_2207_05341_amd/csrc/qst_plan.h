@@ -60,7 +60,13 @@ constexpr int kReduceThreads = 256;
 // Stream-K scheduling of the complex products: at most this many
 // workgroups, each leaving at most two partial 64 x 64 complex tiles.
 constexpr int kStreamKMaxGrid = 1024;
-constexpr int kStreamKMinQubits = 10;  // smaller products always run one tile per workgroup
+constexpr int kStreamKMinQubits = 10;
+
+// BF16 path: T T^dagger uses plain bf16 T for d > this, split bf16 hi + lo
+// (three products) up to it, where plain rounding of T moves the gradient by
+// more than 2e-3 relative (measured with the FP64 oracle: up to 4.3e-3 at
+// d = 8, 2.9e-3 at d = 64, 1.4e-3 at d = 128, 7.1e-4 at d = 256).
+constexpr int kBf16SplitMaxDim = 128;  // smaller products always run one tile per workgroup
 inline size_t stream_k_partial_bytes(qst_prec p) {
   return size_t(kStreamKMaxGrid) * 2 * (2 * 64 * 64) * (p == QST_F64 ? 8 : 4);
 }

@@ -74,6 +74,13 @@ def bf16_round(x):
     return re + 1j * im
 
 
+def bf16_split(x):
+    """hi + lo with hi = bf16(x), lo = bf16(x - hi) (x given in fp32)."""
+    x = x.astype(np.complex64).astype(np.complex128)
+    hi = bf16_round(x)
+    return hi + bf16_round((x - hi).astype(np.complex64).astype(np.complex128))
+
+
 # ---------------------------------------------------------------------------
 # Per-step parity at sizes the oracle finishes in seconds (several tiles,
 # several passes, single-tile and small-matrix paths)
@@ -90,8 +97,10 @@ def test_state_map(n, prec):
     rho, tau = host(rho), float(tau.item())
     want_rho, want_tau = O.state_map(T)
     if prec == "bf16":
-        # tau is the FP64 sum over the same bf16-rounded T that the product uses
-        assert abs(tau - O.trace_tt(bf16_round(T))) <= 1e-12 * tau
+        # tau is the FP64 sum over the same represented T that the product
+        # uses: bf16(T) for d >= 256, bf16 hi + lo below
+        rep = bf16_round(T) if d >= 256 else bf16_split(T)
+        assert abs(tau - O.trace_tt(rep)) <= 1e-12 * tau
     else:
         assert abs(tau - want_tau) <= 1e-12 * want_tau
     assert rel_max(rho, want_rho) <= TOL[prec]
