@@ -33,6 +33,35 @@ METRIC = "likelihood fwd+bwd evals/sec at N=11 on 1 GPU; % HBM/MFMA peak; max|Δ
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 PEAK_HBM_GBS = 8000.0
 
+# Memory traffic per launch of the dominant kernels: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (separate runs, KiB per dispatch), each scaled by what the same
+# counter reads for one plain 256 MiB device copy in the same run.  A figure
+# holds only for the kernel sources it was measured on (SHA-256 over the
+# files below, in order); otherwise the reported traffic is null.
+TRAFFIC_SOURCES = ["paper_2207_05341_amd/csrc/k_gemm.hip", "paper_2207_05341_amd/csrc/qst_gemm_tiles.h",
+                   "paper_2207_05341_amd/csrc/qst_device.h"]
+TRAFFIC = {
+    # N = 11, d = 2048: 179275.1 KiB fetched x 1.9998 + 32768.0 KiB written x 1.0000
+    "hemm_f32": {"bytes": 400.67e6, "sources_sha256": "7cc62a7a4ee5ca513c32b2af99837a4f26d9b6d374a593038ab239cf46911961"},
+}
+
+
+def sources_sha256(paths):
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_of(kernel):
+    rec = TRAFFIC.get(kernel)
+    if not rec or rec["sources_sha256"] != sources_sha256(TRAFFIC_SOURCES):
+        return None
+    return rec["bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -44,6 +73,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precision paths")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy (torch.neg) of this many MiB first, as the "
+                         "reference dispatch for scaling memory-traffic counters")
     return ap.parse_args()
 
 
@@ -75,7 +107,11 @@ def step(qst, T, f, prec):
     return p, out, grad
 
 
-def time_steps(qst, T, f, prec, steps, warmup, profile):
+def time_steps(qst, T, f, prec, steps, warmup, only=None, timed=True):
+    """Run warmup + steps; with `only`, the library times that kernel scope
+    (HIP events on its launch stream) inside the same steps; `only=""` times
+    every scope (each bracketing event costs queue time, so that loop is a
+    breakdown, not the throughput figure)."""
     import torch
 
     from paper_2207_05341_amd import _lib
@@ -83,16 +119,16 @@ def time_steps(qst, T, f, prec, steps, warmup, profile):
     for _ in range(warmup):
         step(qst, T, f, prec)
     torch.cuda.synchronize()
-    if profile:
+    if only is not None:
         _lib.profile_report(reset=True)
-        _lib.profile_enable(True)
+        _lib.profile_enable(True, only or None)
     t0 = time.perf_counter()
     for _ in range(steps):
         step(qst, T, f, prec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern = {}
-    if profile:
+    if only is not None:
         _lib.profile_enable(False)
         kern = _lib.profile_report(reset=True)
     return (t1 - t0) / steps, kern
@@ -199,13 +235,22 @@ def main():
     dev = torch.device("cuda:0")
     n, d = args.n, 1 << args.n
     T_np, f_np = make_inputs(n)
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     # accuracy against the FP64 path on the same GPU
     T64, f64 = to_prec(T_np, f_np, "f64", dev)
     p64, out64, g64 = step(qst, T64, f64, "f64")
     torch.cuda.synchronize()
 
-    def measure(prec, steps, warmup, profile):
+    def measure(prec, steps, warmup):
+        """Accuracy against the FP64 path; a per-kernel breakdown loop (every
+        scope timed); then the timed loop, in which only the dominant kernel
+        is bracketed by events."""
         T, f = to_prec(T_np, f_np, prec, dev)
         p, out, grad = step(qst, T, f, prec)
         torch.cuda.synchronize()
@@ -215,24 +260,44 @@ def main():
             "grad_rel": float(torch.linalg.vector_norm(grad.to(torch.complex128) - g64)
                               / torch.linalg.vector_norm(g64)),
         }
-        sec, kern = time_steps(qst, T, f, prec, steps, warmup, profile)
-        return sec, kern, acc
+        # breakdown: list the scopes once, then time each one alone (events
+        # bracketing every scope would add their queue time to each other)
+        _, names = time_steps(qst, T, f, prec, 1, 1, only="")
+        breakdown = {}
+        for name in names:
+            breakdown.update(time_steps(qst, T, f, prec, max(5, steps // 5), 0, only=name)[1])
+        dom = max(breakdown, key=lambda k: breakdown[k][1] / breakdown[k][0])
+        sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom)
+        return sec, breakdown, dom, kdom, acc
 
-    sec, kern, acc = measure(args.prec, args.steps, args.warmup, True)
+    sec, kern, dom, kdom, acc = measure(args.prec, args.steps, args.warmup)
     kern_us = {k: 1e3 * ms / calls for k, (calls, ms) in kern.items()}
 
-    # roofline of the dominant kernel (largest share of the step)
-    dom = max(kern, key=lambda k: kern[k][1]) if kern else None
+    # roofline of the dominant kernel (largest share of the step), its
+    # duration from the events of the timed loop
     roofline = None
-    if dom:
-        avg_s = kern_us[dom] * 1e-6
+    if dom in kdom:
+        avg_s = kdom[dom][1] * 1e-3 / kdom[dom][0]
         if dom.startswith("hemm") or dom.startswith("herk"):
-            flops = 8.0 * d ** 3 if dom.startswith("hemm") else 4.0 * d * d * (d + 1)
-            peak_key = "bf16" if dom.endswith(("bf16", "bf16x3")) else ("f64" if dom.endswith("f64") else "f32")
+            # flops counted at 8 per complex multiply-add (4 d^2 (d+1) for the
+            # Hermitian T T^dagger, 8 d^3 for G' T); the fp32/fp64 products
+            # run the 3M form (3 real products per complex product: 6 flops
+            # per complex multiply-add executed), the bf16 gradient product
+            # three split products of 4 real products each (24 d^3 executed)
+            herk = dom.startswith("herk")
+            flops = 4.0 * d * d * (d + 1) if herk else 8.0 * d ** 3
+            bf16 = dom.endswith(("bf16", "bf16x3"))
+            peak_key = "bf16" if bf16 else ("f64" if dom.endswith("f64") else "f32")
+            executed = flops * (0.75 if not bf16 else (1.0 if herk else 3.0))
             ach = flops / avg_s / 1e12
             roofline = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[peak_key],
-                        "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[peak_key], "traffic": None,
-                        "algorithmic_per_launch": f"{flops:.4g} flop ({'8d^3' if dom.startswith('hemm') else '4d^2(d+1)'}, d={d})"}
+                        "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[peak_key], "traffic": traffic_of(dom),
+                        "algorithmic_per_launch": f"{flops:.4g} flop ({'4d^2(d+1)' if herk else '8d^3'}, d={d}, "
+                                                  "8 flop per complex multiply-add)",
+                        "executed_mfma_frac": executed / avg_s / 1e12 / PEAK_TFLOPS[peak_key],
+                        "note": "complex products in the 3M form: 6 real flop executed per complex "
+                                "multiply-add, counted at 8" if not bf16 else
+                                "bf16 split operands: three products per complex product"}
     # POVM passes: achieved GB/s from algorithmic bytes (lower triangle read, see DESIGN)
     cb = 16 if args.prec == "f64" else 8
     rb = 8 if args.prec == "f64" else 4
@@ -251,7 +316,7 @@ def main():
         for prec in ("f64", "f32", "bf16"):
             if prec == args.prec:
                 continue
-            s2, k2, a2 = measure(prec, max(10, args.steps // 2), 3, True)
+            s2, k2, _, _, a2 = measure(prec, max(10, args.steps // 2), 3)
             paths[prec] = {"evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
                            "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()}}
 

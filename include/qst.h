@@ -169,16 +169,21 @@ const char* qst_last_error(void);
 const char* qst_version(void);
 
 /*
- * Kernel timing for measurement tools.  While enabled (on != 0), every
- * kernel the library launches is bracketed by two hipEvents recorded on its
- * launch stream.  Disabled by default; do not enable it while a stream is
- * being captured into a HIP graph.
+ * Kernel timing for measurement tools.  While enabled (on != 0), each timed
+ * kernel scope (one launch, or a short fixed sequence such as a product and
+ * its stream-K fix-up, under one name: "hemm_f32", "povm_fwd_p0", ...) is
+ * bracketed by two timing-only hipEvents recorded on its launch stream.
+ * only == NULL or "" times every scope; otherwise only the scope of that
+ * name.  Each event costs several microseconds of queue time between
+ * kernels, so a throughput measurement should time only the scope it
+ * reports.  Disabled by default; do not enable it while a stream is being
+ * captured into a HIP graph.
  */
-qst_status qst_profile_enable(int on);
+qst_status qst_profile_enable(int on, const char* only);
 
 /*
  * Waits for the recorded events and writes one line "name calls total_ms"
- * per kernel name seen since the last reset into buf (NUL-terminated,
+ * per timed scope name seen since the last reset into buf (NUL-terminated,
  * truncated to len).  Returns the size needed including the NUL.  reset != 0
  * clears the totals afterwards.
  */

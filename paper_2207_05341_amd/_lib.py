@@ -26,7 +26,7 @@ SIGNATURES = {
     "qst_status_string": (ctypes.c_char_p, [_int]),
     "qst_last_error": (ctypes.c_char_p, []),
     "qst_version": (ctypes.c_char_p, []),
-    "qst_profile_enable": (_int, [_int]),
+    "qst_profile_enable": (_int, [_int, ctypes.c_char_p]),
     "qst_profile_report": (_sz, [ctypes.c_char_p, _sz, _int]),
     "qst_batch_plan_create": (_int, [_vp, _int, _int, _vp, ctypes.c_char_p, ctypes.POINTER(_vp)]),
     "qst_batch_offsets": (_int, [_vp, _vp, _vp]),
@@ -74,8 +74,9 @@ def workspace_bytes(n: int, prec: int, op: int) -> int:
     return int(lib().qst_workspace_bytes(n, prec, op))
 
 
-def profile_enable(on: bool) -> None:
-    check(lib().qst_profile_enable(1 if on else 0), "qst_profile_enable")
+def profile_enable(on: bool, only: str | None = None) -> None:
+    """Time every library kernel scope, or only the scope named `only`."""
+    check(lib().qst_profile_enable(1 if on else 0, only.encode() if only else None), "qst_profile_enable")
 
 
 def profile_report(reset: bool = True) -> dict[str, tuple[int, float]]:

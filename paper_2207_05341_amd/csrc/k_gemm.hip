@@ -40,7 +40,7 @@ __device__ __forceinline__ int64_t sk_start(int64_t w, int64_t P, int64_t iters)
 
 // One tile per workgroup.
 template <class P>
-__global__ __launch_bounds__(256) void gemm_dp_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, P::kMinWaves) void gemm_dp_kernel(GemmArgs g) {
   __shared__ typename P::Smem sm;
   typename P::acc_t aR[2][2], aI[2][2];
   const double scale = tile_scale<P>(g);
@@ -53,10 +53,12 @@ __global__ __launch_bounds__(256) void gemm_dp_kernel(GemmArgs g) {
 
 // Stream-K: workgroup w owns iterations [start(w), start(w+1)).
 template <class P>
-__global__ __launch_bounds__(256) void gemm_sk_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, P::kMinWaves) void gemm_sk_kernel(GemmArgs g) {
   __shared__ typename P::Smem sm;
   typename P::acc_t aR[2][2], aI[2][2];
-  const int64_t Pn = gridDim.x, w = blockIdx.x;
+  // logical workgroup index: consecutive segments (the two halves of a cut
+  // tile, neighbouring tiles sharing panels) run on one XCD
+  const int64_t Pn = gridDim.x, w = xcd_order(blockIdx.x, gridDim.x);
   const double scale = tile_scale<P>(g);
   int64_t it = sk_start(w, Pn, g.iters);
   const int64_t end = sk_start(w + 1, Pn, g.iters);

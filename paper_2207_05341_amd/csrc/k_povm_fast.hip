@@ -281,9 +281,12 @@ __global__ __launch_bounds__(256) void kd_pass(PassArgs a, ModeMatrix A) {
   const int U = a.U, Up = U - G;
   const int64_t kd = int64_t(1) << (2 * (a.n - U));
   const int64_t nchunks = kd / J;
-  const int64_t ch = blockIdx.x % nchunks;
+  // J consecutive outcomes are 32..128 bytes; the chunks sharing a cache
+  // line must run on the same XCD (see xcd_order)
+  const int64_t lb = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t ch = lb % nchunks;
   int Rhi, Chi;
-  tri_decode(blockIdx.x / nchunks, Rhi, Chi);
+  tri_decode(lb / nchunks, Rhi, Chi);
   const int64_t kd0 = ch * J;
   const int64_t obase = ((int64_t(Rhi) << Up) | Chi) * (kd * TILE);
   double F = 0.0;

@@ -88,6 +88,19 @@ __device__ __forceinline__ double block_sum256(double v, double* lds4) {
   return s;
 }
 
+// Workgroups of a launch are handed to the 8 XCDs in turn (workgroup b to
+// XCD b % 8), and each XCD has its own L2.  xcd_order renumbers them so that
+// each XCD runs one contiguous range of logical indices; logical neighbours,
+// which share cache lines and operand panels, then share an L2.  It is a
+// bijection on [0, grid) for every grid size, so correctness never depends
+// on the hardware's actual placement.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t grid) {
+  constexpr int64_t kXcds = 8;
+  const int64_t per = grid / kXcds, rem = grid % kXcds;
+  const int64_t x = b % kXcds, q = b / kXcds;
+  return x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
+}
+
 // Lower-triangular tile index t -> (R, C) with R >= C, t = R(R+1)/2 + C.
 __device__ __forceinline__ void tri_decode(int64_t t, int& R, int& C) {
   int r = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);

@@ -36,12 +36,20 @@ struct GemmArgs {
 // Policies: one K-panel loop per (precision, product) with a common
 // accumulator shape acc[2][2] re/im, 4 values per lane.
 // ---------------------------------------------------------------------------
-template <typename R, bool HERK>
+// M3: three real products per complex product instead of four (Gauss):
+// P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); re = P1 - P2,
+// im = P3 - P1 - P2.  A quarter fewer MFMAs; the rounding error stays of the
+// same order (a few units of eps * sqrt(K) * |A| |B|).  The combination is
+// linear, so each K segment (stream-K) combines its own sums.
+template <typename R, bool HERK, bool M3 = true>
 struct CxPolicy {
   typedef R scalar;
   typedef typename Mfma<R>::acc acc_t;
   static constexpr int KP = 16;  // complex K per panel
   static constexpr bool kHerk = HERK;
+  // waves per SIMD the register allocation must allow (fp64 3M: 2, which
+  // caps a lane at 256 registers; it would take 260 unconstrained)
+  static constexpr int kMinWaves = 2;
   static constexpr bool kStreamK = true;
   struct Smem {
     Cx<R> As[KP][BM + PADC];
@@ -79,6 +87,16 @@ struct CxPolicy {
       _Pragma("unroll") for (int i = 0; i < 4; ++i) rb[i] = Bv[int64_t(k0_) * g.ldb + i]; \
     }                                                                        \
   } while (0)
+    // 3M sums (unused by the four-product form).  HERK uses P2' = Ai Bi'
+    // with B' = T rows (B = conj B'^T): re = P1 + P2', im = P3 - P1 + P2',
+    // P3 = (Ar + Ai)(Br' - Bi').
+    acc_t p1[2][2], p2[2][2], p3[2][2];
+    if constexpr (M3) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = acc_t{0, 0, 0, 0};
+    }
     QST_LOAD_PANEL(kb);
     for (int kp = kb; kp < ke; ++kp) {
       __syncthreads();
@@ -102,29 +120,66 @@ struct CxPolicy {
         for (int i = 0; i < 2; ++i) a[i] = sm.As[kk][wr * 32 + i * 16 + li];
 #pragma unroll
         for (int j = 0; j < 2; ++j) b[j] = sm.Bs[kk][wc * 32 + j * 16 + li];
-        // eight independent accumulator chains, each advanced once per sweep
+        if constexpr (M3) {
+          R as[2], bs[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < 2; ++i) as[i] = a[i].re + a[i].im;
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            aR[i][j] = Mfma<R>::step(a[i].re, b[j].re, aR[i][j]);
-            aI[i][j] = Mfma<R>::step(HERK ? a[i].im : a[i].re, HERK ? b[j].re : b[j].im, aI[i][j]);
-          }
+          for (int j = 0; j < 2; ++j) bs[j] = HERK ? b[j].re - b[j].im : b[j].re + b[j].im;
+          // twelve independent accumulator chains
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            // HERK: re += ai bi, im -= ar bi;  HEMM: re -= ai bi, im += ai br
-            aR[i][j] = Mfma<R>::step(HERK ? a[i].im : -a[i].im, b[j].im, aR[i][j]);
-            aI[i][j] = Mfma<R>::step(HERK ? -a[i].re : a[i].im, HERK ? b[j].im : b[j].re, aI[i][j]);
-          }
+            for (int j = 0; j < 2; ++j) p1[i][j] = Mfma<R>::step(a[i].re, b[j].re, p1[i][j]);
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) p2[i][j] = Mfma<R>::step(a[i].im, b[j].im, p2[i][j]);
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) p3[i][j] = Mfma<R>::step(as[i], bs[j], p3[i][j]);
+        } else {
+          // eight independent accumulator chains, each advanced once per sweep
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              aR[i][j] = Mfma<R>::step(a[i].re, b[j].re, aR[i][j]);
+              aI[i][j] = Mfma<R>::step(HERK ? a[i].im : a[i].re, HERK ? b[j].re : b[j].im, aI[i][j]);
+            }
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              // HERK: re += ai bi, im -= ar bi;  HEMM: re -= ai bi, im += ai br
+              aR[i][j] = Mfma<R>::step(HERK ? a[i].im : -a[i].im, b[j].im, aR[i][j]);
+              aI[i][j] = Mfma<R>::step(HERK ? -a[i].re : a[i].im, HERK ? b[j].im : b[j].re, aI[i][j]);
+            }
+        }
       }
+    }
+    if constexpr (M3) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          // callers pass zeroed accumulators: assign rather than add
+          if constexpr (HERK) {
+            aR[i][j] = p1[i][j] + p2[i][j];
+            aI[i][j] = (p3[i][j] - p1[i][j]) + p2[i][j];
+          } else {
+            aR[i][j] = p1[i][j] - p2[i][j];
+            aI[i][j] = (p3[i][j] - p1[i][j]) - p2[i][j];
+          }
+        }
     }
   }
 };
 
 // T T^dagger with T rounded to bf16 (RNE), fp32 accumulate.
 struct HerkBf16Policy {
+  static constexpr int kMinWaves = 1;
   typedef float scalar;
   typedef f4 acc_t;
   static constexpr int KP = 32;  // one MFMA K step
@@ -207,6 +262,7 @@ struct HerkBf16Policy {
 // hi lo^dagger + lo hi^dagger), fp32 accumulate.  Used for small d, where the
 // rounding of plain bf16 T moves the gradient by more than the BF16 bar.
 struct HerkBf16x3Policy {
+  static constexpr int kMinWaves = 1;
   typedef float scalar;
   typedef f4 acc_t;
   static constexpr int KP = 32;
@@ -298,6 +354,7 @@ struct HerkBf16x3Policy {
 // G' T with split-bf16 operands: x = hi + lo, hi = bf16(x), lo = bf16(x - hi);
 // the product keeps hi*hi + hi*lo + lo*hi (lo*lo is below fp32 rounding).
 struct HemmBf16x3Policy {
+  static constexpr int kMinWaves = 1;
   typedef float scalar;
   typedef f4 acc_t;
   static constexpr int KP = 32;

@@ -1,5 +1,6 @@
-// Optional per-kernel timing: when enabled, each kernel launch of the library
-// is bracketed by two hipEvents recorded on its launch stream.  The report
+// Optional per-kernel timing: when enabled, each timed scope of the library
+// (one kernel, or a fixed short sequence under one name) is bracketed by two
+// hipEvents recorded on its launch stream.  The report
 // waits for the events and sums the elapsed times per kernel name.
 #include <cstdio>
 #include <map>
@@ -21,6 +22,7 @@ struct Pending {
 struct State {
   std::mutex mu;
   bool enabled = false;
+  std::string only;  // empty: every scope
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<long long, double>> totals;  // calls, ms
@@ -38,7 +40,9 @@ hipEvent_t take_event(State& st) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing-only events: no system-scope fence (cache write-back and
+  // invalidate) when they complete
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -48,6 +52,7 @@ ProfScope::ProfScope(const char* name, hipStream_t s) : s_(s) {
   State& st = state();
   std::lock_guard<std::mutex> lock(st.mu);
   if (!st.enabled) return;
+  if (!st.only.empty() && st.only != name) return;
   hipEvent_t a = take_event(st), b = take_event(st);
   if (!a || !b) return;
   if (hipEventRecord(a, s) != hipSuccess) return;
@@ -66,10 +71,11 @@ ProfScope::~ProfScope() {
 
 extern "C" {
 
-qst_status qst_profile_enable(int on) {
+qst_status qst_profile_enable(int on, const char* only) {
   qst::State& st = qst::state();
   std::lock_guard<std::mutex> lock(st.mu);
   st.enabled = on != 0;
+  st.only = only ? only : "";
   return QST_OK;
 }
 

@@ -38,9 +38,9 @@ def gpu_fidelity_lowrank(T, W, tw):
     (T^dagger W)^dagger (T^dagger W) / (tau tw) (the oracle's low-rank form)."""
     X = T.conj().transpose(0, 1).contiguous() @ W
     tau = float((T.real.double() ** 2).sum() + (T.imag.double() ** 2).sum())
-    M = (X.conj().transpose(0, 1).contiguous() @ X).to(torch.complex128) / (tau * tw)
-    w = torch.linalg.eigvalsh((M + M.conj().transpose(0, 1)) / 2).clamp(min=0)
-    return float(torch.sqrt(w).sum() ** 2)
+    M = (X.conj().transpose(0, 1).contiguous() @ X).cpu().numpy().astype(np.complex128) / (tau * tw)
+    w = np.clip(np.linalg.eigvalsh((M + M.conj().T) / 2), 0.0, None)
+    return float(np.sqrt(w).sum() ** 2)
 
 
 def train_gpu(T0, f, steps, prec, recompute=True):
