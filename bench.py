@@ -3,8 +3,12 @@
 
 One step = the whole hot path on one batch of synthetic input, inputs resident
 in HBM before timing starts:
-    qst_state_map (tau, T T^dagger)  ->  qst_povm_probs (4^11 outcomes)
-    ->  qst_nll  ->  qst_nll_backward (F, cotangent + adjoint POVM map, G' T).
+    qst_likelihood (tau, T T^dagger, POVM map over 4^11 outcomes, NLL,
+    cotangent, adjoint POVM map -> G'; the last POVM pass, the NLL terms, the
+    cotangent and the first adjoint pass fused, p never stored)
+    ->  qst_grad_product (2/tau G' T).
+The same step as four separate calls with p stored (qst_state_map,
+qst_povm_probs, qst_nll, qst_nll_backward) is reported alongside.
 
 Workload (N = 11): T 2048 x 2048 complex Ginibre (seed 6); frequencies from
 10^7 multinomial shots of a Porter-Thomas stand-in distribution of a
@@ -99,15 +103,22 @@ def to_prec(T, f, prec, dev):
             torch.from_numpy(np.ascontiguousarray(f.astype(rt))).to(dev))
 
 
-def step(qst, T, f, prec):
+def step(qst, T, f, prec, fused=True):
+    """One pass of the whole path.  fused: qst_likelihood (tau, rho, p, L, F and
+    G' in one call; p never stored) then qst_grad_product.  Otherwise the four
+    separate calls with p stored between them."""
+    if fused:
+        out, tau, G, _ = qst.likelihood_forward(T, f, prec)
+        grad = qst.grad_product(G, T, tau, prec)
+        return out, grad
     rho, tau = qst.state_map(T, prec)
     p = qst.povm_probs(rho, prec)
     out, _ = qst.nll(p, f, prec)
     grad = qst.nll_backward(T, f, p, tau, prec, nll_out=out)
-    return p, out, grad
+    return out, grad
 
 
-def time_steps(qst, T, f, prec, steps, warmup, only=None, timed=True):
+def time_steps(qst, T, f, prec, steps, warmup, only=None, fused=True):
     """Run warmup + steps; with `only`, the library times that kernel scope
     (HIP events on its launch stream) inside the same steps; `only=""` times
     every scope (each bracketing event costs queue time, so that loop is a
@@ -117,14 +128,14 @@ def time_steps(qst, T, f, prec, steps, warmup, only=None, timed=True):
     from paper_2207_05341_amd import _lib
 
     for _ in range(warmup):
-        step(qst, T, f, prec)
+        step(qst, T, f, prec, fused)
     torch.cuda.synchronize()
     if only is not None:
         _lib.profile_report(reset=True)
         _lib.profile_enable(True, only or None)
     t0 = time.perf_counter()
     for _ in range(steps):
-        step(qst, T, f, prec)
+        step(qst, T, f, prec, fused)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern = {}
@@ -138,7 +149,7 @@ def batched(qst, prec, dev, reps=20):
     """Batched form: 1024 instances, N uniform on {3..8} (seed 9), Ginibre T,
     Porter-Thomas stand-in frequencies from 10^5 shots each.  One graph
     replay of the persistent launch vs 1024 separate single-instance call
-    sequences (state map, POVM map, NLL, backward) through the same C ABI."""
+    sequences (qst_likelihood + qst_grad_product) through the same C ABI."""
     import numpy as np
     import torch
 
@@ -244,15 +255,21 @@ def main():
 
     # accuracy against the FP64 path on the same GPU
     T64, f64 = to_prec(T_np, f_np, "f64", dev)
-    p64, out64, g64 = step(qst, T64, f64, "f64")
+    out64, g64 = step(qst, T64, f64, "f64")
+    rho64, _ = qst.state_map(T64, "f64")
+    p64 = qst.povm_probs(rho64, "f64")
+    del rho64
     torch.cuda.synchronize()
 
-    def measure(prec, steps, warmup):
-        """Accuracy against the FP64 path; a per-kernel breakdown loop (every
-        scope timed); then the timed loop, in which only the dominant kernel
-        is bracketed by events."""
+    def measure(prec, steps, warmup, fused=True):
+        """Accuracy against the FP64 path; a per-kernel breakdown loop (each
+        scope timed alone); then the timed loop, in which only the dominant
+        kernel is bracketed by events."""
         T, f = to_prec(T_np, f_np, prec, dev)
-        p, out, grad = step(qst, T, f, prec)
+        out, grad = step(qst, T, f, prec, fused)
+        rho, _ = qst.state_map(T, prec)
+        p = qst.povm_probs(rho, prec)  # the forward map alone, for max|dp|
+        del rho
         torch.cuda.synchronize()
         acc = {
             "max_dp_rel": float((p.double() - p64).abs().max() / p64.abs().max()),
@@ -260,14 +277,15 @@ def main():
             "grad_rel": float(torch.linalg.vector_norm(grad.to(torch.complex128) - g64)
                               / torch.linalg.vector_norm(g64)),
         }
+        del p
         # breakdown: list the scopes once, then time each one alone (events
         # bracketing every scope would add their queue time to each other)
-        _, names = time_steps(qst, T, f, prec, 1, 1, only="")
+        _, names = time_steps(qst, T, f, prec, 1, 1, only="", fused=fused)
         breakdown = {}
         for name in names:
-            breakdown.update(time_steps(qst, T, f, prec, max(5, steps // 5), 0, only=name)[1])
+            breakdown.update(time_steps(qst, T, f, prec, max(5, steps // 5), 0, only=name, fused=fused)[1])
         dom = max(breakdown, key=lambda k: breakdown[k][1] / breakdown[k][0])
-        sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom)
+        sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom, fused=fused)
         return sec, breakdown, dom, kdom, acc
 
     sec, kern, dom, kdom, acc = measure(args.prec, args.steps, args.warmup)
@@ -298,16 +316,19 @@ def main():
                         "note": "complex products in the 3M form: 6 real flop executed per complex "
                                 "multiply-add, counted at 8" if not bf16 else
                                 "bf16 split operands: three products per complex product"}
-    # POVM passes: achieved GB/s from algorithmic bytes (lower triangle read, see DESIGN)
+    # POVM passes: achieved GB/s from algorithmic bytes.  N = 11 plan: pass 0
+    # contracts qubits 6..11 of rho (lower triangle read) into X[(r, c)][kd]
+    # with (r, c) the 528 lower pairs of the 5 remaining qubits and kd 4^6
+    # digits; the fused pass reads X and f and writes the adjoint
+    # intermediate in place; adjoint pass 0 writes G' in full.
     cb = 16 if args.prec == "f64" else 8
     rb = 8 if args.prec == "f64" else 4
-    tiles = (d // 64) * (d // 64 + 1) // 2
+    pairs, kd = 32 * 33 // 2, 4 ** 6
     tri = d * (d + 1) // 2
     povm_bytes = {
-        "povm_fwd_p0": tri * cb + tiles * 4096 * cb,
-        "povm_fwd_p1": tiles * 4096 * cb + 4 ** n * rb,
-        "povm_adj_p1": 2 * 4 ** n * rb + tiles * 4096 * cb,
-        "povm_adj_p0": tiles * 4096 * cb + d * d * cb,
+        "povm_fwd_p0": tri * cb + pairs * kd * cb,
+        "povm_fused": 2 * pairs * kd * cb + 4 ** n * rb,
+        "povm_adj_p0": pairs * kd * cb + d * d * cb,
     }
     povm_gbs = {k: v / (kern_us[k] * 1e-6) / 1e9 for k, v in povm_bytes.items() if k in kern_us} if n == 11 else {}
 
@@ -319,6 +340,11 @@ def main():
             s2, k2, _, _, a2 = measure(prec, max(10, args.steps // 2), 3)
             paths[prec] = {"evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
                            "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()}}
+        s2, k2, _, _, a2 = measure(args.prec, max(10, args.steps // 2), 3, fused=False)
+        paths[args.prec + "_separate_calls"] = {
+            "evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
+            "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()},
+            "note": "qst_state_map, qst_povm_probs, qst_nll, qst_nll_backward with p stored"}
 
     batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
@@ -337,7 +363,8 @@ def main():
         "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": f"N={n} single state: T {d}x{d} complex Ginibre, {4 ** n} tetrahedral-POVM "
-                               f"outcomes, f from 10^7 multinomial shots; stored-p forward+adjoint",
+                               f"outcomes, f from 10^7 multinomial shots; forward+adjoint as qst_likelihood + "
+                               f"qst_grad_product (p not stored)",
                    "n_qubits": n, "precision": args.prec, "parallelism": "none (1 GPU)"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -79,7 +79,9 @@ typedef enum {
   QST_OP_STATE_MAP = 0,
   QST_OP_POVM_PROBS = 1,
   QST_OP_NLL = 2,
-  QST_OP_NLL_BACKWARD = 3
+  QST_OP_NLL_BACKWARD = 3,
+  QST_OP_LIKELIHOOD = 4,
+  QST_OP_GRAD_PRODUCT = 5
 } qst_op;
 
 /*
@@ -153,6 +155,48 @@ qst_status qst_nll_backward(int n_qubits, qst_prec prec, const void* T, int64_t 
                             const double* nll_dev, const double* povm_host,
                             const double* upstream_dev, void* gradT, int64_t ldG, void* ws,
                             size_t ws_bytes, void* stream);
+
+/*
+ * Likelihood and the adjoint matrix in one call (the chain of Eq. MLE_T with
+ * rho = T T^dagger / tau):
+ *   tau and rho = T T^dagger / tau          (as qst_state_map),
+ *   p_k = Tr(rho M_k) for all k             (as qst_povm_probs),
+ *   L = -sum_{f_k != 0} f_k ln p_k, F = sum f, counters (as qst_nll),
+ *   and, when G is not NULL, G' = sum_k (F - f_k/p_k) M_k (the matrix that
+ *   qst_nll_backward multiplies by T).
+ * rho and p stay in the workspace.  For N >= 7 the last stage of the POVM
+ * map, the NLL terms, the cotangent and the first stage of the adjoint map
+ * run as one kernel per block of outcomes, so p is never written to memory
+ * (F is summed beforehand, alongside tau).
+ *   T        [in]  d x d complex, row stride ldT, device.
+ *   f        [in]  4^N reals, device.
+ *   povm_host[in]  as in qst_povm_probs.
+ *   tau_dev  [out] one double, device (input of qst_grad_product).
+ *   nll_dev  [out] two doubles, device: L and F (as qst_nll).
+ *   bad_dev  [out] two uint64, device, or NULL (as qst_nll).
+ *   G        [out] d x d complex, row stride ldG, device, written in full;
+ *                  or NULL for the value alone.  Must not overlap T.
+ * Summation orders are fixed: results are bitwise reproducible.
+ */
+qst_status qst_likelihood(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* f,
+                          const double* povm_host, double* tau_dev, double* nll_dev,
+                          unsigned long long* bad_dev, void* G, int64_t ldG, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/*
+ * Gradient product, the last step of the adjoint (Eq. MLE_T):
+ *   gradT = s * (2 / tau) * G' T,  s = *upstream_dev (1 if upstream_dev is NULL),
+ * for G' and tau from qst_likelihood (same T).
+ *   G        [in]  d x d complex, row stride ldG, device.
+ *   T        [in]  d x d complex, row stride ldT, device.
+ *   tau_dev  [in]  one double, device.
+ *   upstream_dev[in] one double, device, or NULL.
+ *   gradT    [out] d x d complex, row stride ld_grad, device; must overlap
+ *                  neither G nor T.
+ */
+qst_status qst_grad_product(int n_qubits, qst_prec prec, const void* G, int64_t ldG, const void* T,
+                            int64_t ldT, const double* tau_dev, const double* upstream_dev,
+                            void* gradT, int64_t ld_grad, void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace in bytes needed by op (a qst_op) at (n_qubits, prec); 0 for an
  * invalid request. */

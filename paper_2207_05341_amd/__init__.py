@@ -14,11 +14,13 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_NLL, QST_OP_NLL_BACKWARD,
-                   QST_OP_POVM_PROBS, QST_OP_STATE_MAP, QstError, workspace_bytes)
+from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
+                   QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS, QST_OP_STATE_MAP, QstError,
+                   workspace_bytes)
 
 __all__ = [
-    "PRECISIONS", "state_map", "povm_probs", "nll", "nll_backward", "likelihood", "LikelihoodFn",
+    "PRECISIONS", "state_map", "povm_probs", "nll", "nll_backward", "likelihood_forward", "grad_product",
+    "likelihood", "LikelihoodFn",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
 
@@ -144,9 +146,8 @@ def nll_backward(T: torch.Tensor, f: torch.Tensor, p: torch.Tensor | None, tau: 
         _vector(p, "p", n, real_dtype(pr))
         if tau is None:
             raise ValueError("tau is required when p is given")
-    for name, t in (("tau", tau), ("upstream", upstream)):
-        if t is not None and (t.dtype != torch.float64 or t.numel() != 1 or not t.is_cuda):
-            raise ValueError(f"{name} must be a one-element float64 GPU tensor")
+    _scalar(tau, "tau")
+    _scalar(upstream, "upstream")
     if nll_out is not None and (nll_out.dtype != torch.float64 or nll_out.numel() != 2 or not nll_out.is_cuda
                                 or not nll_out.is_contiguous()):
         raise ValueError("nll_out must be the contiguous two-element float64 GPU tensor returned by nll()")
@@ -158,21 +159,70 @@ def nll_backward(T: torch.Tensor, f: torch.Tensor, p: torch.Tensor | None, tau: 
     return grad
 
 
+def _scalar(t, name):
+    if t is not None and (t.dtype != torch.float64 or t.numel() != 1 or not t.is_cuda):
+        raise ValueError(f"{name} must be a one-element float64 GPU tensor")
+
+
+def likelihood_forward(T: torch.Tensor, f: torch.Tensor, prec=None, povm=None, with_grad_matrix: bool = True):
+    """One library call for L and the adjoint matrix: returns (out, tau, G, bad)
+    with out = [L, F] (float64), tau (0-dim float64), G = G' = sum_k (F -
+    f_k/p_k) M_k as a d x d matrix of T's dtype (None when with_grad_matrix is
+    False) and bad = [f>0 with p<=0, NaN] counts.  rho and p never leave the
+    library's workspace."""
+    n, ld = _matrix(T, "T")
+    pr = _prec(T.dtype, prec)
+    _vector(f, "f", n, real_dtype(pr))
+    out = torch.empty(2, dtype=torch.float64, device=T.device)
+    bad = torch.empty(2, dtype=torch.int64, device=T.device)
+    tau = torch.empty((), dtype=torch.float64, device=T.device)
+    G = torch.empty(T.shape, dtype=T.dtype, device=T.device) if with_grad_matrix else None
+    ws, nb = _workspace(n, pr, QST_OP_LIKELIHOOD, T.device)
+    _lib.check(_lib.lib().qst_likelihood(n, pr, T.data_ptr(), ld, f.data_ptr(), _povm_arg(povm), tau.data_ptr(),
+                                         out.data_ptr(), bad.data_ptr(), _ptr(G), 0 if G is None else G.stride(0),
+                                         _ptr(ws), nb, _stream(T.device)), "qst_likelihood")
+    return out, tau, G, bad
+
+
+def grad_product(G: torch.Tensor, T: torch.Tensor, tau: torch.Tensor, prec=None,
+                 upstream: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dRe T + i dL/dIm T = (2 s / tau) G' T, s = *upstream (1 if None)."""
+    n, ldt = _matrix(T, "T")
+    n2, ldg = _matrix(G, "G")
+    if n2 != n or G.dtype != T.dtype:
+        raise ValueError("G must match T in size and dtype")
+    pr = _prec(T.dtype, prec)
+    _scalar(tau, "tau")
+    _scalar(upstream, "upstream")
+    grad = torch.empty(T.shape, dtype=T.dtype, device=T.device)
+    ws, nb = _workspace(n, pr, QST_OP_GRAD_PRODUCT, T.device)
+    _lib.check(_lib.lib().qst_grad_product(n, pr, G.data_ptr(), ldg, T.data_ptr(), ldt, tau.data_ptr(),
+                                           _ptr(upstream), grad.data_ptr(), grad.stride(0), _ptr(ws), nb,
+                                           _stream(T.device)), "qst_grad_product")
+    return grad
+
+
 class LikelihoodFn(torch.autograd.Function):
     """L(T) = -sum_k f_k ln Tr(M_k T T^dagger / Tr(T T^dagger)) with the
-    hand-written adjoint.  recompute=True keeps only T, f and tau for the
-    backward pass (rho and p are rebuilt there)."""
+    hand-written adjoint.  Modes:
+      "fused"     forward = qst_likelihood (L and G'), backward = qst_grad_product;
+                  kept between them: T, G' and tau (nothing of length 4^N);
+      "stored"    forward keeps p; backward = qst_nll_backward(p);
+      "recompute" forward keeps T, f, tau; backward rebuilds rho and p."""
 
     @staticmethod
-    def forward(ctx, T, f, prec, recompute, povm):
+    def forward(ctx, T, f, prec, mode, povm):
+        ctx.prec, ctx.povm, ctx.mode = prec, povm, mode
+        if mode == "fused":
+            need = ctx.needs_input_grad[0]
+            out, tau, G, _ = likelihood_forward(T, f, prec, povm, with_grad_matrix=need)
+            ctx.save_for_backward(T, G, tau)
+            return out[0].clone()
         rho, tau = state_map(T, prec)
         p = povm_probs(rho, prec, povm)
         del rho
         out, _ = nll(p, f, _prec(T.dtype, prec))
-        ctx.prec = prec
-        ctx.povm = povm
-        ctx.recompute = bool(recompute)
-        if ctx.recompute:
+        if mode == "recompute":
             ctx.save_for_backward(T, f, tau, out)
         else:
             ctx.save_for_backward(T, f, tau, out, p)
@@ -180,21 +230,28 @@ class LikelihoodFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
+        up = g.detach().to(torch.float64).reshape(1).contiguous()
+        if ctx.mode == "fused":
+            T, G, tau = ctx.saved_tensors
+            return grad_product(G, T, tau, ctx.prec, up), None, None, None, None
         saved = ctx.saved_tensors
         T, f, tau, out = saved[0], saved[1], saved[2], saved[3]
-        p = None if ctx.recompute else saved[4]
-        up = g.detach().to(torch.float64).reshape(1).contiguous()
+        p = None if ctx.mode == "recompute" else saved[4]
         grad = nll_backward(T, f, p, None if p is None else tau, ctx.prec, ctx.povm, up, out)
         return grad, None, None, None, None
 
 
-def likelihood(T: torch.Tensor, f: torch.Tensor, prec=None, recompute: bool | None = None, povm=None):
-    """Differentiable negative log-likelihood (0-dim float64 tensor).  By
-    default the probability vector is recomputed in the backward pass at
-    N >= 12 and kept from the forward pass below that."""
-    if recompute is None:
-        recompute = _qubits(T.shape[-1]) >= 12
-    return LikelihoodFn.apply(T, f, prec, recompute, povm)
+def likelihood(T: torch.Tensor, f: torch.Tensor, prec=None, recompute: bool | None = None, povm=None,
+               mode: str | None = None):
+    """Differentiable negative log-likelihood (0-dim float64 tensor).
+
+    mode: "fused" (default), "stored" or "recompute" (see LikelihoodFn).
+    recompute=True / False select "recompute" / "stored" when mode is None."""
+    if mode is None:
+        mode = "fused" if recompute is None else ("recompute" if recompute else "stored")
+    if mode not in ("fused", "stored", "recompute"):
+        raise ValueError(f"unknown mode {mode!r}")
+    return LikelihoodFn.apply(T, f, prec, mode, povm)
 
 
 class BatchPlan:

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
       const double fk = double(f[k]), pk = double(pvec[k]);
       F += fk;
       if (fk != 0.0) {
-        if (pk > 0.0) L -= fk * log(pk);
+        if (pk > 0.0) L -= fk * ln_prob(pvec[k]);
         else bad0 += 1.0;
       }
       if (pk != pk || fk != fk) bad1 += 1.0;

@@ -116,4 +116,62 @@ hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const do
   return hipSuccess;
 }
 
+hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W, const double* V, bool tetra,
+                             const void* rho, int64_t ld_rho, const void* fvec, const double* Fpart, void* G,
+                             int64_t ldG, void* inter0, void* inter1, double* part, double* nll_dev,
+                             unsigned long long* bad_dev, hipStream_t s) {
+  static const char* kFwd[4] = {"povm_fwd_p0", "povm_fwd_p1", "povm_fwd_p2", "povm_fwd_p3"};
+  static const char* kAdj[4] = {"povm_adj_p0", "povm_adj_p1", "povm_adj_p2", "povm_adj_p3"};
+  ModeMatrix Af, Aa;
+  for (int i = 0; i < 32; ++i) {
+    Af.a[i] = W[i];
+    Aa.a[i] = V[i];
+  }
+  void* bufs[2] = {inter0, inter1};
+  const int P = pl.passes;
+  auto args = [&](int j) {
+    PassArgs a{};
+    a.n = pl.n;
+    a.U = pl.U[j];
+    a.g = pl.g[j];
+    a.J = pl.J[j];
+    return a;
+  };
+  hipError_t e = hipSuccess;
+  for (int j = 0; j + 1 < P; ++j) {
+    PassArgs a = args(j);
+    a.in = j == 0 ? rho : bufs[(j - 1) & 1];
+    a.out = bufs[j & 1];
+    a.ld = ld_rho;
+    ProfScope prof(kFwd[j], s);
+    if (!launch_pass_fast(false, prec, tetra, a, Af, j == 0, false, povm_pass_blocks(pl, j), s, &e))
+      return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+  }
+  {
+    PassArgs a = args(P - 1);
+    a.in = a.out = bufs[(P - 2) & 1];
+    a.f = fvec;
+    a.Fpart = Fpart;
+    a.part = part;
+    const int64_t nb = povm_pass_blocks(pl, P - 1);
+    ProfScope prof("povm_fused", s);
+    if (!launch_fused_fast(prec, tetra, a, Af, Aa, nb, s, &e)) return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+    if ((e = launch_likelihood_finish(part, int(nb), Fpart, nll_dev, bad_dev, s)) != hipSuccess) return e;
+  }
+  if (!G) return hipSuccess;
+  for (int j = P - 2; j >= 0; --j) {
+    PassArgs a = args(j);
+    a.in = bufs[j & 1];
+    a.out = j == 0 ? G : bufs[(j - 1) & 1];
+    a.ld = ldG;
+    ProfScope prof(kAdj[j], s);
+    if (!launch_pass_fast(true, prec, tetra, a, Aa, j == 0, false, povm_pass_blocks(pl, j), s, &e))
+      return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace qst

@@ -323,10 +323,7 @@ __global__ __launch_bounds__(256) void kd_pass(PassArgs a, ModeMatrix A) {
           const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
           if constexpr (PSIDE) {
             const int64_t k = int64_t(kg) * kd + kd0 + j;
-            const double fk = double(static_cast<const R*>(a.f)[k]);
-            double gk = F;
-            if (fk != 0.0) gk = F - fk / double(static_cast<const R*>(a.p)[k]);
-            x[m] = Cx<R>{R(gk), R(0)};
+            x[m] = Cx<R>{cotangent(F, static_cast<const R*>(a.f)[k], static_cast<const R*>(a.p)[k]), R(0)};
           } else {
             x[m] = static_cast<const Cx<R>*>(a.in)[obase + int64_t(kg) * kd + kd0 + j];
           }
@@ -371,7 +368,182 @@ __global__ __launch_bounds__(256) void kd_pass(PassArgs a, ModeMatrix A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Last pass fused with the likelihood.  The last pass has a single (R, C)
+// pair (all remaining qubits are contracted), so a workgroup owns J
+// consecutive kdone values of the whole 2^G x 2^G block.  It runs the forward
+// rounds (p for 16 outcomes per register block after the last round), the
+// NLL terms and the cotangent g'_k = F - f_k / p_k in registers (F from the
+// partial sums of the tau kernel, summed in the same fixed order by every
+// workgroup), then the adjoint rounds in reverse, starting from the same
+// registers (the adjoint's first round is the forward's last round).  Reads X
+// and writes Y = adjoint intermediate at the same addresses (in place: every
+// address a workgroup writes is one it alone has read, and all its reads
+// precede its first write by a barrier).
+// ---------------------------------------------------------------------------
+template <typename R, bool TETRA, int G, int J>
+__global__ __launch_bounds__(256, 2) void kd_fused_pass(PassArgs a, ModeMatrix Af, ModeMatrix Aa) {
+  constexpr int TILE = 1 << (2 * G);
+  constexpr int NB = TILE * J / 16;
+  constexpr int BPT = NB / 256;
+  static_assert(NB % 256 == 0, "tile x chunk must give whole blocks per thread");
+  __shared__ Cx<R> lds[TILE * J];
+  __shared__ double red[4];
+  using RD = Rounds<G>;
+  static_assert(RD::n >= 2, "the fused pass needs a round to exchange between");
+
+  const int U = a.U;  // == G
+  const int64_t kd = int64_t(1) << (2 * (a.n - U));
+  const int64_t lb = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t kd0 = lb * J;
+  Cx<R>* X = static_cast<Cx<R>*>(a.out);  // in place: a.in == a.out
+  const R* f = static_cast<const R*>(a.f);
+  __shared__ double Fsh;
+  {
+    const double Fsum = sum_partials256(a.Fpart, kReduceBlocks, red);
+    if (threadIdx.x == 0) Fsh = Fsum;
+    __syncthreads();
+  }
+  const double F = Fsh;
+  double L = 0.0, bad0 = 0.0, bad1 = 0.0;
+
+  // forward rounds; the last one continues into the cotangent and the
+  // adjoint of the same round
+#pragma unroll
+  for (int rd = 0; rd < RD::n; ++rd) {
+    const int bA = RD::bA[rd], bB = RD::bB[rd];
+    const bool first = rd == 0, last = rd == RD::n - 1;
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      const int j = blk % J;
+      const int u = blk / J;
+      int rf, cf;
+      fixed_bits<G>(u, bA, bB, rf, cf);
+      Cx<R> x[16];
+      if (first) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          const bool mir = r < c;
+          const int rr = mir ? c : r, cc = mir ? r : c;
+          Cx<R> v = X[((int64_t(rr) << U) | cc) * kd + kd0 + j];
+          if (mir) v.im = -v.im;
+          x[m] = v;
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          x[m] = lds[((r << G) | c) * J + j];
+        }
+      }
+      contract16<R, false, TETRA>(x, RD::opA[rd], RD::opB[rd], Af);
+      if (last) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
+          const R fr = f[int64_t(kg) * kd + kd0 + j], pr = x[m].re;
+          const double fk = double(fr), pk = double(pr);
+          if (fk != 0.0) {
+            if (pk > 0.0) {
+              L -= fk * ln_prob(pr);
+            } else {
+              bad0 += 1.0;
+            }
+          }
+          if (pk != pk || fk != fk) bad1 += 1.0;
+          x[m] = Cx<R>{cotangent(F, fr, pr), R(0)};
+        }
+        contract16<R, true, TETRA>(x, RD::opA[rd], RD::opB[rd], Aa);
+      }
+      // the exchange positions of this block are this thread's alone in the
+      // round, so the adjoint values can replace the forward ones directly
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        int r, c;
+        rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+        lds[((r << G) | c) * J + j] = x[m];
+      }
+    }
+    __syncthreads();
+  }
+  // remaining adjoint rounds, last forward round excluded
+#pragma unroll
+  for (int rd = RD::n - 2; rd >= 0; --rd) {
+    const int bA = RD::bA[rd], bB = RD::bB[rd];
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      const int j = blk % J;
+      const int u = blk / J;
+      int rf, cf;
+      fixed_bits<G>(u, bA, bB, rf, cf);
+      Cx<R> x[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        int r, c;
+        rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+        x[m] = lds[((r << G) | c) * J + j];
+      }
+      contract16<R, true, TETRA>(x, RD::opA[rd], RD::opB[rd], Aa);
+      if (rd > 0) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          lds[((r << G) | c) * J + j] = x[m];
+        }
+      } else {  // matrix side out: lower triangle only
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          if (r >= c) X[((int64_t(r) << U) | c) * kd + kd0 + j] = x[m];
+        }
+      }
+    }
+    if (rd > 0) __syncthreads();
+  }
+  // per-workgroup partial sums in a fixed order, slot = logical index
+  const int64_t nb = gridDim.x;
+  double v = block_sum256(L, red);
+  if (threadIdx.x == 0) a.part[lb] = v;
+  v = block_sum256(bad0, red);
+  if (threadIdx.x == 0) a.part[2 * nb + lb] = v;
+  v = block_sum256(bad1, red);
+  if (threadIdx.x == 0) a.part[3 * nb + lb] = v;
+}
+
 }  // namespace
+
+// Fused last pass; false when no specialised form covers (g, J).
+bool launch_fused_fast(qst_prec prec, bool tetra, const PassArgs& a, const ModeMatrix& Af,
+                       const ModeMatrix& Aa, int64_t blocks, hipStream_t s, hipError_t* err) {
+  const unsigned grid = unsigned(blocks);
+#define QST_FU(R, G, J)                                                              \
+  do {                                                                               \
+    if (tetra) kd_fused_pass<R, true, G, J><<<grid, 256, 0, s>>>(a, Af, Aa);         \
+    else kd_fused_pass<R, false, G, J><<<grid, 256, 0, s>>>(a, Af, Aa);              \
+  } while (0)
+  const int g = a.g, J = a.J;
+  if (prec == QST_F64) {
+    if (g == 5 && J == 4) QST_FU(double, 5, 4);
+    else if (g == 4 && J == 16) QST_FU(double, 4, 16);
+    else if (g == 3 && J == 64) QST_FU(double, 3, 64);
+    else return false;
+  } else {
+    if (g == 5 && J == 8) QST_FU(float, 5, 8);
+    else if (g == 4 && J == 32) QST_FU(float, 4, 32);
+    else if (g == 3 && J == 64) QST_FU(float, 3, 64);
+    else return false;
+  }
+#undef QST_FU
+  *err = hipGetLastError();
+  return true;
+}
 
 // Returns true and launches when a specialised kernel covers the pass.
 bool launch_pass_fast(bool adjoint, qst_prec prec, bool tetra, const PassArgs& a, const ModeMatrix& A,

@@ -15,9 +15,12 @@ namespace qst {
 namespace {
 
 // ROUND: 0 = T as given, 1 = bf16(T), 2 = bf16 hi + lo of T (exact in fp32).
-template <typename R, int ROUND>
+// WITH_F: also F = sum f over the same element range (f has 4^N = d^2
+// entries, element e of T and f alike), partials[nb + b].
+template <typename R, int ROUND, bool WITH_F = false>
 __global__ __launch_bounds__(256) void tau_partial_kernel(const Cx<R>* __restrict__ T, int64_t ld,
-                                                          int n, double* __restrict__ partials) {
+                                                          int n, double* __restrict__ partials,
+                                                          const R* __restrict__ f = nullptr) {
   __shared__ double red[4];
   const int64_t d = int64_t(1) << n;
   const int64_t total = d * d;
@@ -27,13 +30,19 @@ __global__ __launch_bounds__(256) void tau_partial_kernel(const Cx<R>* __restric
   // Up to 16 strided elements per thread are loaded before any arithmetic
   // (all loads in flight at once); the per-thread summation order is fixed.
   constexpr int U = 16;
-  double acc = 0.0;
+  double acc = 0.0, accf = 0.0;
   for (int64_t e0 = beg + threadIdx.x; e0 < end; e0 += U * int64_t(blockDim.x)) {
     Cx<R> v[U];
+    R fv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + u * int64_t(blockDim.x);
       v[u] = e < end ? T[(e >> n) * ld + (e & (d - 1))] : Cx<R>{R(0), R(0)};
+      if constexpr (WITH_F) fv[u] = e < end ? f[e] : R(0);
+    }
+    if constexpr (WITH_F) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) accf += double(fv[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -51,6 +60,10 @@ __global__ __launch_bounds__(256) void tau_partial_kernel(const Cx<R>* __restric
   }
   const double s = block_sum256(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if constexpr (WITH_F) {
+    const double sf = block_sum256(accf, red);
+    if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = sf;
+  }
 }
 
 // One 256-thread block: out[i] = sum_b partials[i*nb + b] for i < nsum.
@@ -95,7 +108,7 @@ __global__ __launch_bounds__(256) void nll_partial_kernel(const R* __restrict__ 
         const double pk = double(pv[u]);
         if (fk != 0.0) {
           if (pk > 0.0) {
-            L -= fk * log(pk);
+            L -= fk * ln_prob(pv[u]);
           } else {
             bad0 += 1.0;
           }
@@ -144,20 +157,62 @@ __global__ __launch_bounds__(256) void nll_finish_kernel(const double* __restric
   }
 }
 
+// Stage 2 of qst_likelihood's NLL: L and the counters from the fused pass's
+// partials [4][nb] (slot 1 unused), F from the kReduceBlocks F partials of
+// the tau kernel, summed exactly as the fused pass sums them.
+__global__ __launch_bounds__(256) void likelihood_finish_kernel(const double* __restrict__ part, int nb,
+                                                                const double* __restrict__ Fpart,
+                                                                double* __restrict__ nll,
+                                                                unsigned long long* __restrict__ bad) {
+  __shared__ double red[4];
+  double sums[4];
+  for (int i = 0; i < 4; ++i) {
+    if (i == 1) {
+      sums[1] = sum_partials256(Fpart, kReduceBlocks, red);
+      continue;
+    }
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[int64_t(i) * nb + b];
+    sums[i] = block_sum256(acc, red);
+  }
+  if (threadIdx.x == 0) {
+    double L = sums[0];
+    if (sums[1] != sums[1] || sums[3] > 0.0) {
+      L = __builtin_nan("");
+    } else if (sums[2] > 0.0) {
+      L = __builtin_inf();
+    }
+    nll[0] = L;
+    nll[1] = sums[1];
+    if (bad) {
+      bad[0] = (unsigned long long)sums[2];
+      bad[1] = (unsigned long long)sums[3];
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
-                      double* tau_dev, hipStream_t s) {
+                      double* tau_dev, hipStream_t s, const void* f) {
   const int nb = kReduceBlocks;
   ProfScope prof("tau_reduce", s);
+  const Cx<double>* T64 = static_cast<const Cx<double>*>(T);
+  const Cx<float>* T32 = static_cast<const Cx<float>*>(T);
+  const double* f64 = static_cast<const double*>(f);
+  const float* f32 = static_cast<const float*>(f);
   if (prec == QST_F64) {
-    tau_partial_kernel<double, 0><<<nb, 256, 0, s>>>(static_cast<const Cx<double>*>(T), ld, n, partials);
+    if (f) tau_partial_kernel<double, 0, true><<<nb, 256, 0, s>>>(T64, ld, n, partials, f64);
+    else tau_partial_kernel<double, 0><<<nb, 256, 0, s>>>(T64, ld, n, partials);
   } else if (prec == QST_F32) {
-    tau_partial_kernel<float, 0><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
+    if (f) tau_partial_kernel<float, 0, true><<<nb, 256, 0, s>>>(T32, ld, n, partials, f32);
+    else tau_partial_kernel<float, 0><<<nb, 256, 0, s>>>(T32, ld, n, partials);
   } else if ((int64_t(1) << n) <= kBf16SplitMaxDim) {
-    tau_partial_kernel<float, 2><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
+    if (f) tau_partial_kernel<float, 2, true><<<nb, 256, 0, s>>>(T32, ld, n, partials, f32);
+    else tau_partial_kernel<float, 2><<<nb, 256, 0, s>>>(T32, ld, n, partials);
   } else {
-    tau_partial_kernel<float, 1><<<nb, 256, 0, s>>>(static_cast<const Cx<float>*>(T), ld, n, partials);
+    if (f) tau_partial_kernel<float, 1, true><<<nb, 256, 0, s>>>(T32, ld, n, partials, f32);
+    else tau_partial_kernel<float, 1><<<nb, 256, 0, s>>>(T32, ld, n, partials);
   }
   if (tau_dev) finish_sums_kernel<<<1, 256, 0, s>>>(partials, nb, 1, tau_dev);
   return hipGetLastError();
@@ -176,6 +231,12 @@ hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double
                                                        static_cast<const float*>(f), D, partials);
   }
   nll_finish_kernel<<<1, 256, 0, s>>>(partials, nb, nll_dev, bad_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_likelihood_finish(const double* part, int nb, const double* Fpart, double* nll_dev,
+                                   unsigned long long* bad_dev, hipStream_t s) {
+  likelihood_finish_kernel<<<1, 256, 0, s>>>(part, nb, Fpart, nll_dev, bad_dev);
   return hipGetLastError();
 }
 

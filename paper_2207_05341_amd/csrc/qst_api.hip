@@ -24,10 +24,12 @@ qst_status hip_fail(hipError_t e, const char* what) {
 // tau and rho = T T^dagger / tau.  For d >= 64 the product kernel folds the
 // tau partial sums itself (and stores tau); below that a finishing kernel
 // produces tau first.
+// With f, the tau kernel also leaves the partial sums of F = sum f at
+// partials + kReduceBlocks.
 hipError_t run_state_map(qst_prec prec, const void* T, int64_t ldT, void* rho, int64_t ldr, int n,
-                         double* partials, double* tau_dev, void* sk, hipStream_t s) {
+                         double* partials, double* tau_dev, void* sk, hipStream_t s, const void* f = nullptr) {
   const bool fold = n >= 6;
-  hipError_t e = launch_tau(prec, T, ldT, n, partials, fold ? nullptr : tau_dev, s);
+  hipError_t e = launch_tau(prec, T, ldT, n, partials, fold ? nullptr : tau_dev, s, f);
   if (e != hipSuccess) return e;
   return launch_herk(prec, T, ldT, rho, ldr, n, fold ? partials : nullptr, tau_dev, sk, s);
 }
@@ -139,6 +141,74 @@ qst_status qst_nll_backward(int n, qst_prec prec, const void* T, int64_t ldT, co
                   ws_at(ws, L.inter1), s);
   if (e != hipSuccess) return hip_fail(e, "adjoint POVM map");
   e = launch_hemm(prec, G, d, T, ldT, gradT, ldG, n, tau_dev, upstream_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "G' T");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_likelihood(int n, qst_prec prec, const void* T, int64_t ldT, const void* f,
+                          const double* povm_host, double* tau_dev, double* nll_dev,
+                          unsigned long long* bad_dev, void* G, int64_t ldG, void* ws, size_t ws_bytes,
+                          void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(f, "f", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(tau_dev, "tau_dev", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(nll_dev, "nll_dev", msg)) != QST_OK) return fail(st, msg);
+  if (G && (st = check_matrix(G, ldG, n, "G", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_povm(povm_host, msg)) != QST_OK) return fail(st, msg);
+  if (G == T) return fail(QST_ERR_INVALID_ARG, "G must not alias T");
+  const WsLayout L = workspace_layout(n, prec, QST_OP_LIKELIHOOD, false);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* partials = reinterpret_cast<double*>(ws_at(ws, L.partials));
+  double W[32], V[32];
+  povm_mode_matrices(povm_host, W, V);
+  const bool tetra = povm_host == nullptr;
+  const PovmPlan pl = make_povm_plan(n, prec);
+  const int64_t d = int64_t(1) << n;
+  void* rho = ws_at(ws, L.rho);
+  const bool fused = fused_likelihood(pl, prec);
+  hipError_t e = run_state_map(prec, T, ldT, rho, d, n, partials, tau_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s,
+                               fused ? f : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "state map");
+  if (fused) {
+    e = launch_povm_fused(prec, pl, W, V, tetra, rho, d, f, partials + kReduceBlocks, G, ldG, ws_at(ws, L.inter0),
+                          ws_at(ws, L.inter1), reinterpret_cast<double*>(ws_at(ws, L.fpart)), nll_dev, bad_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "fused POVM / likelihood passes");
+  } else {
+    void* p = ws_at(ws, L.p);
+    e = launch_povm(false, prec, pl, W, tetra, rho, d, p, nullptr, nullptr, ws_at(ws, L.inter0), ws_at(ws, L.inter1), s);
+    if (e != hipSuccess) return hip_fail(e, "POVM map");
+    e = launch_nll(prec, p, f, n, partials, nll_dev, bad_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "NLL reduction");
+    if (G) {
+      e = launch_povm(true, prec, pl, V, tetra, G, ldG, p, f, nll_dev + 1, ws_at(ws, L.inter0), ws_at(ws, L.inter1), s);
+      if (e != hipSuccess) return hip_fail(e, "adjoint POVM map");
+    }
+  }
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_grad_product(int n, qst_prec prec, const void* G, int64_t ldG, const void* T, int64_t ldT,
+                            const double* tau_dev, const double* upstream_dev, void* gradT, int64_t ld_grad,
+                            void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(G, ldG, n, "G", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(gradT, ld_grad, n, "gradT", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(tau_dev, "tau_dev", msg)) != QST_OK) return fail(st, msg);
+  if (gradT == T || gradT == G) return fail(QST_ERR_INVALID_ARG, "gradT must not alias G or T");
+  const WsLayout L = workspace_layout(n, prec, QST_OP_GRAD_PRODUCT, false);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+  hipError_t e = launch_hemm(prec, G, ldG, T, ldT, gradT, ld_grad, n, tau_dev, upstream_dev,
+                             L.has_sk ? ws_at(ws, L.sk) : nullptr, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "G' T");
   clear_error();
   return QST_OK;

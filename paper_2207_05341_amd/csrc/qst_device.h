@@ -110,4 +110,24 @@ __device__ __forceinline__ void tri_decode(int64_t t, int& R, int& C) {
   C = int(t - int64_t(r) * (r + 1) / 2);
 }
 
+// Sum of nb FP64 partials in a fixed order by a 256-thread block (strided
+// per thread, then block_sum256); result valid in thread 0.
+__device__ __forceinline__ double sum_partials256(const double* part, int nb, double* lds4) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
+  return block_sum256(acc, lds4);
+}
+
+// Per-outcome arithmetic of the likelihood in the storage precision of p
+// and f: ln p_k (the sum over k is accumulated in FP64 on every path) and
+// the cotangent g'_k = F - f_k / p_k (F where f_k = 0).  FP64 storage: FP64
+// throughout.  FP32 storage: the logarithm and the quotient in FP32 (about
+// one ulp each, the size of the rounding of p itself).
+__device__ __forceinline__ double ln_prob(double p) { return log(p); }
+__device__ __forceinline__ double ln_prob(float p) { return double(logf(p)); }
+__device__ __forceinline__ double cotangent(double F, double f, double p) { return f != 0.0 ? F - f / p : F; }
+__device__ __forceinline__ float cotangent(double F, float f, float p) {
+  return f != 0.0f ? float(F) - f / p : float(F);
+}
+
 }  // namespace qst

@@ -26,9 +26,11 @@ class ProfScope {
 };
 
 // tau = sum |T_ij|^2 (FP64; over bf16-rounded T for QST_BF16GEMM): the
-// kReduceBlocks partial sums, and, if tau_dev is not NULL, their total.
+// kReduceBlocks partial sums, and, if tau_dev is not NULL, their total.  With
+// f (4^N reals), also the kReduceBlocks partial sums of F = sum f at
+// partials + kReduceBlocks.
 hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
-                      double* tau_dev, hipStream_t s);
+                      double* tau_dev, hipStream_t s, const void* f = nullptr);
 
 // rho = T T^dagger / tau, written in full.  tau comes from tau_partials (the
 // partial sums of launch_tau; the kernel also stores the total at tau_dev)
@@ -57,6 +59,20 @@ hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double
                       double* nll_dev, unsigned long long* bad_dev, hipStream_t s);
 
 // *F_dev = sum f.
+// Stage 2 of qst_likelihood's NLL: L and counters from the fused pass's
+// partials [4][nb]; F from the kReduceBlocks F partials of launch_tau.
+hipError_t launch_likelihood_finish(const double* part, int nb, const double* Fpart, double* nll_dev,
+                                   unsigned long long* bad_dev, hipStream_t s);
+
+// The POVM part of qst_likelihood when fused_likelihood(pl, prec): forward
+// passes 0..P-2, the fused last pass (+ NLL finish into nll_dev / bad_dev),
+// and, if G is not NULL, the adjoint passes P-2..0.  part: FP64 partials
+// [4][blocks of the last pass]; Fpart: the kReduceBlocks F partials.
+hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W, const double* V, bool tetra,
+                             const void* rho, int64_t ld_rho, const void* fvec, const double* Fpart, void* G,
+                             int64_t ldG, void* inter0, void* inter1, double* part, double* nll_dev,
+                             unsigned long long* bad_dev, hipStream_t s);
+
 hipError_t launch_fsum(qst_prec prec, const void* f, int n, double* partials, double* F_dev,
                        hipStream_t s);
 

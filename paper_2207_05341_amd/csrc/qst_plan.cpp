@@ -55,6 +55,21 @@ int64_t povm_pass_blocks(const PovmPlan& pl, int j) {
   return pairs * (kd / pl.J[j]);
 }
 
+bool fast_pass_available(const PovmPlan& pl, int j, qst_prec prec) {
+  if (j < 0 || j >= pl.passes) return false;
+  const int g = pl.g[j], J = pl.J[j];
+  if (j == 0) return pl.passes >= 2 && J == 1 && g >= 4 && g <= 6;
+  if (prec == QST_F64) return (g == 5 && J == 4) || (g == 4 && J == 16) || (g == 3 && J == 64);
+  return (g == 5 && J == 8) || (g == 4 && J == 32) || (g == 3 && J == 64);
+}
+
+bool fused_likelihood(const PovmPlan& pl, qst_prec prec) {
+  if (pl.passes < 2) return false;
+  for (int j = 0; j < pl.passes; ++j)
+    if (!fast_pass_available(pl, j, prec)) return false;
+  return true;
+}
+
 WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
   WsLayout w;
   const size_t cb = complex_bytes(prec), rb = real_bytes(prec);
@@ -93,6 +108,26 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
         w.rho = w.gmat;  // rho is dead once p exists; G' reuses its storage
         w.p = take(D * rb);
       }
+      if (sk) {
+        w.sk = take(stream_k_partial_bytes(prec));
+        w.has_sk = true;
+      }
+      break;
+    case QST_OP_LIKELIHOOD: {
+      const bool fused = fused_likelihood(pl, prec);
+      w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
+      if (fused) w.fpart = take(size_t(povm_pass_blocks(pl, pl.passes - 1)) * 4 * sizeof(double));
+      w.rho = take(D * cb);
+      if (pl.passes >= 2) w.inter0 = take(D * cb);
+      if (pl.passes >= 3) w.inter1 = take(D * cb);
+      if (!fused) w.p = take(D * rb);
+      if (sk) {
+        w.sk = take(stream_k_partial_bytes(prec));
+        w.has_sk = true;
+      }
+      break;
+    }
+    case QST_OP_GRAD_PRODUCT:
       if (sk) {
         w.sk = take(stream_k_partial_bytes(prec));
         w.has_sk = true;
@@ -215,7 +250,7 @@ extern "C" {
 size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op) {
   std::string msg;
   if (qst::check_common(n_qubits, prec, msg) != QST_OK) return 0;
-  if (op < QST_OP_STATE_MAP || op > QST_OP_NLL_BACKWARD) return 0;
+  if (op < QST_OP_STATE_MAP || op > QST_OP_GRAD_PRODUCT) return 0;
   return qst::workspace_layout(n_qubits, prec, op, /*recompute=*/true).total;
 }
 

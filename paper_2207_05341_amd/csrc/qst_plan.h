@@ -38,6 +38,16 @@ PovmPlan make_povm_plan(int n, qst_prec prec);
 // chunks).
 int64_t povm_pass_blocks(const PovmPlan& pl, int j);
 
+// Whether pass j has a specialised kernel (k_povm_fast.hip): matrix-side
+// passes with g in 4..6; outcome-side passes with (g, J) in
+// {(5,4), (4,16), (3,64)} for FP64 and {(5,8), (4,32), (3,64)} otherwise.
+bool fast_pass_available(const PovmPlan& pl, int j, qst_prec prec);
+
+// Whether the likelihood call fuses the last POVM pass with the NLL, the
+// cotangent and the first adjoint pass: at least two passes, all of them
+// specialised.
+bool fused_likelihood(const PovmPlan& pl, qst_prec prec);
+
 // Workspace layout (byte offsets) for each op; see the .cpp for the rules.
 struct WsLayout {
   size_t total = 0;
@@ -49,6 +59,7 @@ struct WsLayout {
   size_t rho = 0;        // rho (d x d complex), recompute mode only
   size_t p = 0;          // p (4^N real), recompute mode only
   size_t sk = 0;         // stream-K partial tiles (0 = not used)
+  size_t fpart = 0;      // fused likelihood pass: FP64 partials [4][blocks]
   bool has_sk = false;
 };
 

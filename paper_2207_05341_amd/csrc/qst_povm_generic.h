@@ -129,12 +129,9 @@ __device__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
     deinterleave(kg, g, r, c);
     Cx<R> v;
     if constexpr (PSIDE) {
-      // cotangent g'_k = F - f_k / p_k (F where f_k = 0), in FP64
+      // cotangent g'_k = F - f_k / p_k (F where f_k = 0)
       const int64_t k = int64_t(kg) * kd + kd0 + j;
-      const double fk = double(static_cast<const R*>(a.f)[k]);
-      double gk = F;
-      if (fk != 0.0) gk = F - fk / double(static_cast<const R*>(a.p)[k]);
-      v = {R(gk), R(0)};
+      v = {cotangent(F, static_cast<const R*>(a.f)[k], static_cast<const R*>(a.p)[k]), R(0)};
     } else {
       const int64_t base = ((int64_t(Rhi) << Up) | Chi) * (kd * tile);
       v = static_cast<const Cx<R>*>(a.in)[base + int64_t(kg) * kd + kd0 + j];

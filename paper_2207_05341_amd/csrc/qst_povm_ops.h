@@ -22,12 +22,14 @@ struct ModeMatrix {
 };
 
 struct PassArgs {
-  const void* in;   // forward: rho or intermediate; adjoint: intermediate
-  void* out;        // forward: intermediate or p; adjoint: intermediate or G'
-  const void* p;    // adjoint, last pass: probabilities
-  const void* f;    // adjoint, last pass: frequencies
-  const double* F;  // adjoint, last pass: F = sum f
-  int64_t ld;       // row stride of the matrix (rho or G')
+  const void* in;       // forward: rho or intermediate; adjoint: intermediate
+  void* out;            // forward: intermediate or p; adjoint: intermediate or G'
+  const void* p;        // adjoint, last pass: probabilities
+  const void* f;        // adjoint / fused last pass: frequencies
+  const double* F;      // adjoint, last pass: F = sum f
+  const double* Fpart;  // fused last pass: kReduceBlocks FP64 partial sums of F = sum f
+  double* part;         // fused last pass: FP64 partials [4][blocks] (L, -, bad0, bad1)
+  int64_t ld;           // row stride of the matrix (rho or G')
   int n, U, g, J;
 };
 
@@ -103,5 +105,11 @@ __device__ __forceinline__ void apply4(Cx<R> x[4], const ModeMatrix& A) {
 // false (launching nothing) otherwise.
 bool launch_pass_fast(bool adjoint, qst_prec prec, bool tetra, const PassArgs& a, const ModeMatrix& A,
                       bool matside, bool pside, int64_t blocks, hipStream_t s, hipError_t* err);
+
+// Fused last pass of qst_likelihood (forward + NLL terms + cotangent
+// g' = F - f/p + adjoint), in place on a.out; partial sums to a.part.  Returns false (and
+// launches nothing) when no specialised form covers (g, J).
+bool launch_fused_fast(qst_prec prec, bool tetra, const PassArgs& a, const ModeMatrix& Af,
+                       const ModeMatrix& Aa, int64_t blocks, hipStream_t s, hipError_t* err);
 
 }  // namespace qst

@@ -64,6 +64,12 @@ def test_workspace_sizes(L):
         for prec in (0, 1, 2):
             assert ws(n, prec, lib_mod.QST_OP_STATE_MAP) > 0
             assert ws(n, prec, lib_mod.QST_OP_NLL_BACKWARD) >= ws(n, prec, lib_mod.QST_OP_POVM_PROBS)
+            # likelihood keeps rho and the POVM intermediates in the workspace
+            cb = 16 if prec == 0 else 8
+            assert ws(n, prec, lib_mod.QST_OP_LIKELIHOOD) >= cb * 4 ** n + ws(n, prec, lib_mod.QST_OP_POVM_PROBS)
+            # the gradient product needs only stream-K partials (N >= 10)
+            assert (ws(n, prec, lib_mod.QST_OP_GRAD_PRODUCT) > 0) == (n >= 10)
+    assert ws(5, 0, 6) == 0
 
 
 def _err(L):
@@ -161,6 +167,50 @@ def test_backward_validation(L):
     assert call(tau=None) == lib_mod.QST_ERR_INVALID_ARG and "tau_dev" in _err(L)
     assert call(G=FAKE) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
     assert call(ws=1024) == lib_mod.QST_ERR_WORKSPACE
+
+
+def test_likelihood_validation(L):
+    n, d = 8, 256
+    ws = lib_mod.workspace_bytes(n, 1, lib_mod.QST_OP_LIKELIHOOD)
+    W = ctypes.c_void_p(0x30000)
+    G = ctypes.c_void_p(0x40000)
+    args = dict(T=FAKE, ldT=d, f=FAKE2, povm=None, tau=FAKE, nll=FAKE2, bad=None, G=G, ldG=d, ws=ws)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return L.qst_likelihood(n, 1, a["T"], a["ldT"], a["f"], a["povm"], a["tau"], a["nll"], a["bad"], a["G"],
+                                a["ldG"], W, a["ws"], None)
+
+    assert call(T=None) == lib_mod.QST_ERR_INVALID_ARG and "T is NULL" in _err(L)
+    assert call(f=None) == lib_mod.QST_ERR_INVALID_ARG and "f is NULL" in _err(L)
+    assert call(tau=None) == lib_mod.QST_ERR_INVALID_ARG and "tau_dev" in _err(L)
+    assert call(nll=None) == lib_mod.QST_ERR_INVALID_ARG and "nll_dev" in _err(L)
+    assert call(ldT=d - 1) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(ldG=d - 1) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(G=FAKE) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
+    assert call(ws=ws - 1) == lib_mod.QST_ERR_WORKSPACE
+    bad = _tetra_flat()
+    bad[0] += 0.01
+    assert call(povm=_povm_array(bad)) == lib_mod.QST_ERR_INVALID_ARG and "identity" in _err(L)
+
+
+def test_grad_product_validation(L):
+    n, d = 10, 1024
+    ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_GRAD_PRODUCT)
+    W = ctypes.c_void_p(0x30000)
+    out = ctypes.c_void_p(0x50000)
+
+    def call(G=FAKE2, ldG=d, T=FAKE, ldT=d, tau=FAKE, grad=out, ldg=d, nb=ws):
+        return L.qst_grad_product(n, 0, G, ldG, T, ldT, tau, None, grad, ldg, W, nb, None)
+
+    assert call(G=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(T=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(grad=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(tau=None) == lib_mod.QST_ERR_INVALID_ARG and "tau_dev" in _err(L)
+    assert call(ldg=5) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(grad=FAKE) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
+    assert call(grad=FAKE2) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
 
 
 def test_plan_unit_builds_without_hip(tmp_path):

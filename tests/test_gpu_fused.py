@@ -1,0 +1,235 @@
+"""qst_likelihood (L, F, tau and G' in one call; for N >= 7 the last POVM pass,
+the NLL terms, the cotangent and the first adjoint pass run as one kernel and
+p is never stored) and qst_grad_product, through the C ABI, against the FP64
+oracle and against the separate-call path.
+
+Tolerances as in test_gpu_parity (relative): FP64 1e-12, FP32 1e-5, BF16 2e-3.
+  L: |dL| / |L|,  G' and grad: ||d||_F / ||.||_F
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+from workloads import config3, depolarised_case, rel_fro
+
+torch = pytest.importorskip("torch")
+qst = pytest.importorskip("paper_2207_05341_amd")
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3}
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def ctype(prec):
+    return np.complex128 if prec == "f64" else np.complex64
+
+
+def rtype(prec):
+    return np.float64 if prec == "f64" else np.float32
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def run_fused(T, f, prec, povm=None, upstream=None):
+    Tg, fg = to_dev(T.astype(ctype(prec))), to_dev(f.astype(rtype(prec)))
+    out, tau, G, bad = qst.likelihood_forward(Tg, fg, prec, povm)
+    up = None if upstream is None else torch.tensor([upstream], dtype=torch.float64, device=DEV)
+    grad = qst.grad_product(G, Tg, tau, prec, up)
+    torch.cuda.synchronize()
+    return (float(out[0].item()), float(out[1].item()), float(tau.item()), host(G), host(grad), host(bad))
+
+
+def run_separate(T, f, prec, povm=None):
+    Tg, fg = to_dev(T.astype(ctype(prec))), to_dev(f.astype(rtype(prec)))
+    rho, tau = qst.state_map(Tg, prec)
+    p = qst.povm_probs(rho, prec, povm)
+    out, _ = qst.nll(p, fg, prec)
+    grad = qst.nll_backward(Tg, fg, p, tau, prec, povm, nll_out=out)
+    torch.cuda.synchronize()
+    return float(out[0].item()), host(grad)
+
+
+def oracle(T, f, povm=None):
+    rho, tau = O.state_map(T)
+    n = O.n_qubits_of(T.shape[0])
+    p = O.probs_real(rho, povm)
+    L = O.nll_vec(p, f)
+    G = O.adjoint(O.cotangent(p, f), n, povm)
+    return L, tau, G, (2.0 / tau) * (G @ T)
+
+
+def check(T, f, prec, povm=None, upstream=None):
+    Tq = T.astype(ctype(prec)).astype(np.complex128)
+    fq = f.astype(rtype(prec)).astype(np.float64)
+    L, F, tau, G, grad, bad = run_fused(T, f, prec, povm, upstream)
+    wL, wtau, wG, wgrad = oracle(Tq, fq, povm)
+    s = 1.0 if upstream is None else upstream
+    errs = {"L": abs(L - wL) / abs(wL), "G": rel_fro(G, wG), "grad": rel_fro(grad, s * wgrad)}
+    say(f"  errors {errs}")
+    for k, v in errs.items():
+        assert v <= TOL[prec], (k, v)
+    assert abs(F - math.fsum(fq.tolist())) <= 1e-12 * max(1.0, abs(F))
+    if prec != "bf16":
+        assert abs(tau - wtau) <= 1e-12 * wtau
+    assert bad.tolist() == [0, 0]
+    return L, grad
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n", [1, 4, 6, 7, 8, 9, 10])
+def test_fused_against_oracle(n, prec):
+    """N <= 6: one POVM pass (the library runs the separate kernels); N >= 7:
+    the fused last pass (2-pass plans; FP32 and FP64 chunk shapes differ)."""
+    say(f"fused likelihood n={n} prec={prec}")
+    T, f, _ = depolarised_case(n, 3000 + n, 0.1, 20 * 4 ** n)
+    check(T, f, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n", [7, 9])
+def test_fused_equals_separate_calls(n, prec):
+    say(f"fused vs separate calls n={n} prec={prec}")
+    T, f, _ = depolarised_case(n, 3100 + n, 0.05, 10 ** 6)
+    L, _, _, _, grad, _ = run_fused(T, f, prec)
+    L2, grad2 = run_separate(T, f, prec)
+    # p agrees to rounding (the two kernels may contract products into FMAs
+    # differently) and L is summed over a different block partition
+    assert abs(L - L2) <= (1e-13 if prec == "f64" else 1e-7) * abs(L2)
+    assert rel_fro(grad, grad2) <= {"f64": 1e-12, "f32": 1e-6, "bf16": 1e-5}[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_general_povm(prec):
+    say(f"fused, rotated tetrahedron POVM, n=8 prec={prec}")
+    g = S.rng(3200)
+    U, _ = np.linalg.qr(S.ginibre(g, 2))
+    M = np.array([U @ m @ U.conj().T for m in O.tetrahedral_povm()])
+    T, f, _ = depolarised_case(8, 3210, 0.2, 10 ** 6)
+    check(T, f, prec, povm=M)
+
+
+def test_fused_leading_dimensions_and_upstream():
+    say("fused: padded T and G, upstream scale")
+    n, d = 7, 128
+    T, f, _ = depolarised_case(n, 3300, 0.1, 10 ** 5)
+    bigT = np.zeros((d, d + 40), dtype=np.complex128)
+    bigT[:, :d] = T
+    Tg = to_dev(bigT)[:, :d]
+    fg = to_dev(f)
+    Gbig = torch.full((d, d + 24), float("nan"), dtype=torch.complex128, device=DEV)
+    G = Gbig[:, :d]
+    out = torch.empty(2, dtype=torch.float64, device=DEV)
+    bad = torch.empty(2, dtype=torch.int64, device=DEV)
+    tau = torch.empty((), dtype=torch.float64, device=DEV)
+    lib = qst._lib.lib()
+    nb = qst.workspace_bytes(n, qst.QST_F64, qst._lib.QST_OP_LIKELIHOOD)
+    ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    s = torch.cuda.current_stream().cuda_stream
+    qst._lib.check(lib.qst_likelihood(n, qst.QST_F64, Tg.data_ptr(), Tg.stride(0), fg.data_ptr(), None,
+                                      tau.data_ptr(), out.data_ptr(), bad.data_ptr(), G.data_ptr(), G.stride(0),
+                                      ws.data_ptr(), nb, s), "qst_likelihood")
+    up = torch.tensor([-2.5], dtype=torch.float64, device=DEV)
+    grad = qst.grad_product(G, Tg, tau, "f64", up)
+    torch.cuda.synchronize()
+    wL, _, wG, wgrad = oracle(T, f)
+    assert abs(out[0].item() - wL) <= 1e-12 * abs(wL)
+    assert rel_fro(host(G), wG) <= 1e-12
+    assert rel_fro(host(grad), -2.5 * wgrad) <= 1e-12
+    assert torch.isnan(Gbig[:, d:]).all()  # padding untouched
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_edge_cases(prec):
+    say(f"fused edge cases prec={prec}")
+    n = 7
+    T, f, _ = depolarised_case(n, 3400, 0.1, 10 ** 5)
+    # f = 0 everywhere: L = 0, F = 0, G' = 0, gradient 0
+    L, F, _, G, grad, bad = run_fused(T, np.zeros_like(f), prec)
+    assert L == 0.0 and F == 0.0 and not np.any(G) and not np.any(grad) and bad.tolist() == [0, 0]
+    # a NaN frequency: L = NaN and counted
+    f2 = f.copy()
+    f2[77] = np.nan
+    L, _, _, _, _, bad = run_fused(T, f2, prec)
+    assert math.isnan(L) and bad[1] == 1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_fused_determinism(prec):
+    say(f"fused determinism prec={prec}")
+    T, f, _ = depolarised_case(10, 3500, 0.05, 10 ** 6)
+    a = run_fused(T, f, prec)
+    b = run_fused(T, f, prec)
+    for x, y in zip(a, b):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+def test_autograd_modes_agree():
+    say("autograd: fused, stored, recompute")
+    T, f, _ = depolarised_case(8, 3600, 0.1, 10 ** 6)
+    res = {}
+    for mode in ("fused", "stored", "recompute"):
+        Tg = to_dev(T).requires_grad_(True)
+        L = qst.likelihood(Tg, to_dev(f), mode=mode)
+        (0.5 * L).backward()
+        res[mode] = (L.item(), host(Tg.grad))
+    wL, _, _, wgrad = oracle(T, f)
+    for mode, (L, g) in res.items():
+        assert abs(L - wL) <= 1e-12 * abs(wL), mode
+        assert rel_fro(g, 0.5 * wgrad) <= 1e-12, mode
+    # forward only (no gradient needed): the value alone
+    with torch.no_grad():
+        L = qst.likelihood(to_dev(T), to_dev(f), mode="fused")
+    assert abs(L.item() - wL) <= 1e-12 * abs(wL)
+
+
+@pytest.fixture(scope="module")
+def n11():
+    say("building N=11 inputs and FP64 oracle results")
+    T, f, _ = config3(0.05)
+    return T, f
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_fused_n11(n11, prec):
+    say(f"fused N=11 {prec}")
+    T, f = n11
+    check(T, f, prec)
+
+
+def test_fused_n12_f32_against_recompute():
+    """N = 12 (3-pass plan, fused last pass of 4 qubits): against the
+    separate-call path with rho and p recomputed in the backward."""
+    say("fused N=12 f32 vs recompute path")
+    g = S.rng(3700)
+    T = S.ginibre(g, 4096).astype(np.complex64)
+    f = S.porter_thomas_probs(g, 4 ** 12, 0.05).astype(np.float32)
+    Tg, fg = to_dev(T), to_dev(f)
+    out, tau, G, bad = qst.likelihood_forward(Tg, fg, "f32")
+    grad = qst.grad_product(G, Tg, tau, "f32")
+    rho, tau2 = qst.state_map(Tg, "f32")
+    p = qst.povm_probs(rho, "f32")
+    del rho
+    out2, _ = qst.nll(p, fg, "f32")
+    del p
+    grad2 = qst.nll_backward(Tg, fg, None, None, "f32", nll_out=out2)
+    torch.cuda.synchronize()
+    assert abs(out[0].item() - out2[0].item()) <= 1e-7 * abs(out2[0].item())
+    assert host(bad).tolist() == [0, 0]
+    err = float(torch.linalg.vector_norm((grad - grad2).to(torch.complex128)) /
+                torch.linalg.vector_norm(grad2.to(torch.complex128)))
+    say(f"  grad rel diff {err:.2e}")
+    assert err <= 1e-6

@@ -170,7 +170,8 @@ def test_nll_and_edge_cases(prec):
     f = S.multinomial_freqs(g, 3000, p.astype(np.float64)).astype(rtype(prec))
     out, bad = qst.nll(to_dev(p), to_dev(f), prec)
     want = O.nll_vec(p.astype(np.float64), f.astype(np.float64))
-    assert abs(out[0].item() - want) <= 1e-13 * abs(want)
+    # FP32 storage: each ln p_k is taken in FP32 (within 2 ulp), the sum in FP64
+    assert abs(out[0].item() - want) <= (1e-13 if prec == "f64" else 3e-7) * abs(want)
     assert abs(out[1].item() - math.fsum(f.astype(np.float64).tolist())) <= 1e-13
     assert host(bad).tolist() == [0, 0]
     # f = 0 everywhere: L = 0, F = 0
