@@ -43,14 +43,14 @@ def gpu_fidelity_lowrank(T, W, tw):
     return float(np.sqrt(w).sum() ** 2)
 
 
-def train_gpu(T0, f, steps, prec, recompute=True):
+def train_gpu(T0, f, steps, prec, mode="recompute"):
     T = torch.nn.Parameter(torch.from_numpy(T0).to(DEV))
     fg = torch.from_numpy(f).to(DEV)
     opt = torch.optim.Adam([T], lr=LR, betas=BETAS, eps=EPS)
     losses = []
     for _ in range(steps):
         opt.zero_grad(set_to_none=True)
-        L = qst.likelihood(T, fg, prec, recompute=recompute)
+        L = qst.likelihood(T, fg, prec, mode=mode)
         L.backward()
         opt.step()
         losses.append(L.detach())
@@ -64,7 +64,7 @@ def test_training_trajectory_n6_f64():
     T0 = S.ginibre(g, d)
     W = S.ginibre(g, d, 4)
     f = S.multinomial_freqs(g, 100_000, O.probs_real(O.state_map(W)[0]))
-    Tg, losses = train_gpu(T0, f, 200, "f64", recompute=True)
+    Tg, losses = train_gpu(T0, f, 200, "f64", mode="recompute")
     To, lo = O.adam_train(T0, f, steps=200, lr=LR, betas=BETAS, eps=EPS)
     Tg = Tg.cpu().numpy()
     dl = max(abs(a - b) / abs(b) for a, b in zip(losses, lo))
@@ -75,8 +75,8 @@ def test_training_trajectory_n6_f64():
     assert losses[-1] < losses[0]
 
 
-def test_training_n12_f32_recompute():
-    say("training N=12 FP32, 200 Adam steps with recompute")
+def test_training_n12_f32():
+    say("training N=12 FP32, 200 Adam steps, recompute and fused modes")
     g = S.rng(10)
     n, d = 12, 4096
     T0 = S.ginibre(g, d).astype(np.complex64)
@@ -88,40 +88,45 @@ def test_training_n12_f32_recompute():
     del p0
     Wg = torch.from_numpy(W.astype(np.complex64)).to(DEV)
     tw = float(np.sum(np.abs(W) ** 2))
-    torch.cuda.synchronize()
-    torch.cuda.reset_peak_memory_stats()
-    free0, total = torch.cuda.mem_get_info()
 
     # 2 steps, compared with the oracle's FP64 Adam after 2 steps
-    T2, l2 = train_gpu(T0, f, 2, "f32", recompute=True)
+    T2, l2 = train_gpu(T0, f, 2, "f32", mode="recompute")
     f2 = gpu_fidelity_lowrank(T2, Wg, tw)
-    say(f"  GPU after 2 steps: losses {l2}, fidelity {f2:.8f}")
+    T2b, l2b = train_gpu(T0, f, 2, "f32", mode="fused")
+    f2b = gpu_fidelity_lowrank(T2b, Wg, tw)
+    say(f"  GPU after 2 steps: recompute losses {l2} fidelity {f2:.8f}; fused losses {l2b} fidelity {f2b:.8f}")
     t0 = time.perf_counter()
     To, lo = O.adam_train(T0.astype(np.complex128), f.astype(np.float64), steps=2, lr=LR, betas=BETAS, eps=EPS)
     fo = O.fidelity_q_lowrank(O.state_map(To)[0], W)
     say(f"  oracle after 2 steps ({time.perf_counter() - t0:.0f} s): losses {lo}, fidelity {fo:.8f}")
-    for a, b in zip(l2, lo):
-        assert abs(a - b) / abs(b) <= 1e-5
-    assert abs(f2 - fo) <= 1e-5
+    for ls in (l2, l2b):
+        for a, b in zip(ls, lo):
+            assert abs(a - b) / abs(b) <= 1e-5
+    assert abs(f2 - fo) <= 1e-5 and abs(f2b - fo) <= 1e-5
 
-    # 200 steps, timed
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    T200, l200 = train_gpu(T0, f, 200, "f32", recompute=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    f200 = gpu_fidelity_lowrank(T200, Wg, tw)
-    peak = torch.cuda.max_memory_allocated()
-    free1, _ = torch.cuda.mem_get_info()
-    f0 = gpu_fidelity_lowrank(torch.from_numpy(T0).to(DEV), Wg, tw)
-    rec = {"config": "N=12 FP32 training, 200 Adam steps, recompute in backward",
-           "steps_per_s": 200 / dt, "ms_per_step": 1e3 * dt / 200,
-           "peak_torch_allocated_GiB": peak / 2 ** 30, "device_used_GiB": (total - free1) / 2 ** 30,
-           "loss_first": l200[0], "loss_last": l200[-1], "fidelity_start": f0, "fidelity_final": f200,
-           "fidelity_after_2_gpu": f2, "fidelity_after_2_oracle": fo}
+    # 200 steps, timed, in both modes: rho and p recomputed in the backward,
+    # and the fused call (p never stored; G' kept between forward and backward)
+    rec = {"config": "N=12 FP32 training, 200 Adam steps (lr 1e-2), target rank-8 Ginibre, 10^8 shots",
+           "fidelity_after_2_gpu_recompute": f2, "fidelity_after_2_gpu_fused": f2b,
+           "fidelity_after_2_oracle": fo,
+           "fidelity_start": gpu_fidelity_lowrank(torch.from_numpy(T0).to(DEV), Wg, tw)}
+    for mode in ("recompute", "fused"):
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        T200, l200 = train_gpu(T0, f, 200, "f32", mode=mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        free1, total = torch.cuda.mem_get_info()
+        rec[mode] = {"steps_per_s": 200 / dt, "ms_per_step": 1e3 * dt / 200,
+                     "peak_torch_allocated_GiB": torch.cuda.max_memory_allocated() / 2 ** 30,
+                     "device_used_GiB": (total - free1) / 2 ** 30,
+                     "loss_first": l200[0], "loss_last": l200[-1],
+                     "fidelity_final": gpu_fidelity_lowrank(T200, Wg, tw)}
+        assert all(math.isfinite(x) for x in l200)
+        assert l200[-1] < l200[0] and rec[mode]["fidelity_final"] > rec["fidelity_start"]
+        del T200
     say("  " + json.dumps(rec))
     if os.path.isdir("gpurun_out"):
         with open(os.path.join("gpurun_out", "config5_training.json"), "w") as fh:
             json.dump(rec, fh)
-    assert all(math.isfinite(x) for x in l200)
-    assert l200[-1] < l200[0] and f200 > f0
