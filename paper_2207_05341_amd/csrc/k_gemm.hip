@@ -51,40 +51,50 @@ __global__ __launch_bounds__(256, P::kMinWaves) void gemm_dp_kernel(GemmArgs g) 
   epilogue<P>(g, tr, tc, aR, aI, scale);
 }
 
-// Stream-K: workgroup w owns iterations [start(w), start(w+1)).
+// Hybrid schedule: workgroup w first computes the whole tiles w, w + P,
+// w + 2P, ... below dp_tiles, then owns the stream-K iterations
+// [start(w), start(w+1)) of the K panels of the remaining tiles.
 template <class P>
 __global__ __launch_bounds__(256, P::kMinWaves) void gemm_sk_kernel(GemmArgs g) {
   __shared__ typename P::Smem sm;
   typename P::acc_t aR[2][2], aI[2][2];
-  // logical workgroup index: consecutive segments (the two halves of a cut
-  // tile, neighbouring tiles sharing panels) run on one XCD
+  // logical workgroup index: consecutive tiles and consecutive segments
+  // (neighbours sharing panels) run on one XCD
   const int64_t Pn = gridDim.x, w = xcd_order(blockIdx.x, gridDim.x);
   const double scale = tile_scale<P>(g);
+  for (int64_t t = w; t < g.dp_tiles; t += Pn) {
+    int tr, tc;
+    tile_coords<P>(g, int(t), tr, tc);
+    zero_acc<P>(aR, aI);
+    P::run(g, sm, tr, tc, 0, g.kIters, aR, aI);
+    epilogue<P>(g, tr, tc, aR, aI, scale);
+  }
   int64_t it = sk_start(w, Pn, g.iters);
   const int64_t end = sk_start(w + 1, Pn, g.iters);
-  const int first_tile = int(it / g.kIters);
+  const int first_rel = int(it / g.kIters);
   while (it < end) {
-    const int tile = int(it / g.kIters);
+    const int rel = int(it / g.kIters);
     const int kb = int(it % g.kIters);
     const int ke = int(min(int64_t(g.kIters), int64_t(kb) + (end - it)));
     int tr, tc;
-    tile_coords<P>(g, tile, tr, tc);
+    tile_coords<P>(g, g.dp_tiles + rel, tr, tc);
     zero_acc<P>(aR, aI);
     P::run(g, sm, tr, tc, kb, ke, aR, aI);
     if (kb == 0 && ke == g.kIters) {
       epilogue<P>(g, tr, tc, aR, aI, scale);
     } else {
-      store_partial<P>(partial_slot<P>(g, int(w), tile == first_tile ? 0 : 1), aR, aI);
+      store_partial<P>(partial_slot<P>(g, int(w), rel == first_rel ? 0 : 1), aR, aI);
     }
     it += ke - kb;
   }
 }
 
-// Sum the partial segments of every tile that stream-K cut, in K order.
+// Sum the partial segments of every stream-K tile that was cut, in K order.
+// Workgroup b handles tile dp_tiles + b.
 template <class P>
 __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g, int Pn) {
-  const int tile = blockIdx.x;
-  const int64_t kb = int64_t(tile) * g.kIters, kl = kb + g.kIters - 1;
+  const int rel = blockIdx.x;
+  const int64_t kb = int64_t(rel) * g.kIters, kl = kb + g.kIters - 1;
   // workgroups owning the first and the last iteration of the tile
   int64_t wlo = (kb * Pn) / g.iters;
   while (wlo + 1 < Pn && sk_start(wlo + 1, Pn, g.iters) <= kb) ++wlo;
@@ -97,11 +107,11 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g, int Pn) {
   typename P::acc_t aR[2][2], aI[2][2];
   zero_acc<P>(aR, aI);
   for (int64_t w = wlo; w <= whi; ++w) {
-    const int first_tile = int(sk_start(w, Pn, g.iters) / g.kIters);
-    add_partial<P>(partial_slot<P>(g, int(w), tile == first_tile ? 0 : 1), aR, aI);
+    const int first_rel = int(sk_start(w, Pn, g.iters) / g.kIters);
+    add_partial<P>(partial_slot<P>(g, int(w), rel == first_rel ? 0 : 1), aR, aI);
   }
   int tr, tc;
-  tile_coords<P>(g, tile, tr, tc);
+  tile_coords<P>(g, g.dp_tiles + rel, tr, tc);
   epilogue<P>(g, tr, tc, aR, aI, scale);
 }
 
@@ -189,16 +199,30 @@ hipError_t run_gemm(GemmArgs g, hipStream_t s) {
   g.kIters = g.d / P::KP;
   g.iters = int64_t(g.ntiles) * g.kIters;
   const int cus = device_cus();
+  g.dp_tiles = 0;
   bool sk = P::kStreamK && g.partial != nullptr && g.ntiles % cus != 0;
   int64_t Pn = 0;
   if (sk) {
-    const int64_t min_iters = 32;  // at least 32 K panels per stream-K workgroup
     const int occ = std::min(sk_occupancy<P>(), 4);
-    Pn = std::min<int64_t>(int64_t(kStreamKMaxGrid), std::min<int64_t>(int64_t(cus) * occ, g.iters / min_iters));
-    Pn = (Pn / cus) * cus;  // whole waves of workgroups over the compute units
-    sk = Pn >= cus;
+    // Whole tiles first when every one of the (CUs x occupancy) workgroups
+    // gets at least one: those tiles need no partials.  With fewer tiles
+    // than that, lowering the workgroups per CU to make tiles whole costs
+    // more (measured at N = 11: 528 tiles at 2 per CU, T T^dagger 245 ->
+    // 283 us) than the partials it saves, so every tile is split instead.
+    if (g.ntiles / cus >= occ) {
+      Pn = int64_t(cus) * occ;
+      g.dp_tiles = int((g.ntiles / Pn) * Pn);
+    } else {
+      const int64_t min_iters = 32;  // at least 32 K panels per stream-K workgroup
+      Pn = std::min<int64_t>(int64_t(kStreamKMaxGrid), std::min<int64_t>(int64_t(cus) * occ, g.iters / min_iters));
+      Pn = (Pn / cus) * cus;  // whole waves of workgroups over the compute units
+    }
+    sk = Pn >= cus && Pn <= kStreamKMaxGrid;
+    g.iters = int64_t(g.ntiles - g.dp_tiles) * g.kIters;
   }
   if (!sk) {
+    g.dp_tiles = 0;
+    g.iters = int64_t(g.ntiles) * g.kIters;
     gemm_dp_kernel<P><<<unsigned(g.ntiles), 256, 0, s>>>(g);
     return hipGetLastError();
   }
@@ -207,7 +231,7 @@ hipError_t run_gemm(GemmArgs g, hipStream_t s) {
   if (e != hipSuccess) return e;
   GemmArgs gf = g;
   gf.tau_out = nullptr;
-  gemm_fixup_kernel<P><<<unsigned(g.ntiles), 256, 0, s>>>(gf, int(Pn));
+  gemm_fixup_kernel<P><<<unsigned(g.ntiles - g.dp_tiles), 256, 0, s>>>(gf, int(Pn));
   return hipGetLastError();
 }
 

@@ -102,10 +102,21 @@ __device__ __forceinline__ void rc_of(int rf, int cf, int bA, int bB, int mA, in
   c = cf | ((mA & 1) << bA) | ((mB & 1) << bB);
 }
 
-// Swizzled LDS position of (r, c) in a 2^G x 2^G tile (matrix-side kernel).
+// Swizzled LDS position of (r, c) in a 2^G x 2^G tile (matrix-side kernel):
+// c' = c ^ ((c >> A) & 3) ^ ((r & MR) << B), a bijection in c for every r.
+// The constants spread each round's 16-lane groups over distinct banks: in
+// round 0 a group varies c's high bits (the 4 x 4 block corners), in later
+// rounds the low bits of r and of c.  Chosen by a 32-bank model of the
+// three rounds (the model reproduces the measured conflict rates), in LDS
+// cycles per ideal: G=6 1.0 (fp32) / 1.33 (fp64), G=5 1.33 / 1.0,
+// G=4 2.0 / 2.0, against 2.7..4.0 for a plain c ^ r.
 template <int G>
 __device__ __forceinline__ int swz(int r, int c) {
-  return (r << G) | (c ^ (r & ((1 << G) - 1)));
+  constexpr int A = G == 6 ? 4 : (G == 5 ? 3 : 2);
+  constexpr int B = G == 4 ? 1 : 2;
+  constexpr int MR = G == 4 ? 7 : 3;
+  constexpr int M = (1 << G) - 1;
+  return (r << G) | (c ^ ((c >> A) & 3) ^ (((r & MR) << B) & M));
 }
 
 // ---------------------------------------------------------------------------
@@ -406,6 +417,23 @@ __global__ __launch_bounds__(256, 2) void kd_fused_pass(PassArgs a, ModeMatrix A
   }
   const double F = Fsh;
   double L = 0.0, bad0 = 0.0, bad1 = 0.0;
+  // f for the outcomes of the last round, loaded now so that it arrives
+  // while the forward rounds run
+  R fpre[BPT][16];
+  {
+    constexpr int rl = RD::n - 1;
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      const int j = blk % J;
+      const int u = blk / J;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int kg = u + ((m >> 2) << (2 * RD::bA[rl])) + ((m & 3) << (2 * RD::bB[rl]));
+        fpre[bi][m] = f[int64_t(kg) * kd + kd0 + j];
+      }
+    }
+  }
 
   // forward rounds; the last one continues into the cotangent and the
   // adjoint of the same round
@@ -444,8 +472,7 @@ __global__ __launch_bounds__(256, 2) void kd_fused_pass(PassArgs a, ModeMatrix A
       if (last) {
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
-          const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
-          const R fr = f[int64_t(kg) * kd + kd0 + j], pr = x[m].re;
+          const R fr = fpre[bi][m], pr = x[m].re;
           const double fk = double(fr), pk = double(pr);
           if (fk != 0.0) {
             if (pk > 0.0) {

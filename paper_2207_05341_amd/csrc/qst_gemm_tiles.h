@@ -26,7 +26,8 @@ struct GemmArgs {
   const double* up;
   int ntiles;     // output tiles
   int kIters;     // K panels per tile
-  int64_t iters;  // ntiles * kIters
+  int64_t iters;  // stream-K: K panels of the tiles from dp_tiles on
+  int dp_tiles;   // stream-K: tiles [0, dp_tiles) are computed whole, one per workgroup and round
   void* partial;  // stream-K partial accumulators [P][2][2 * TILE] (acc scalar)
   const double* tau_part;  // HERK: FP64 partial sums of tau (kReduceBlocks), or NULL to read *tau
   double* tau_out;         // HERK with tau_part: where workgroup 0 stores tau
