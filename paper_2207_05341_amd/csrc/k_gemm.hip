@@ -38,61 +38,81 @@ using namespace gemm;
 // First iteration owned by stream-K workgroup w of P.
 __device__ __forceinline__ int64_t sk_start(int64_t w, int64_t P, int64_t iters) { return (w * iters) / P; }
 
+// Tile output: rho / G' T, or with X0G = g (4..6) the first POVM pass over
+// g qubits of a T T^dagger tile.
+template <class P, int X0G>
+__device__ __forceinline__ void finish_tile(const GemmArgs& g, int tr, int tc, typename P::acc_t (&aR)[2][2],
+                                            typename P::acc_t (&aI)[2][2], double scale, void* lds) {
+  if constexpr (X0G != 0) {
+    x0_tile<P, X0G>(g, tr, tc, aR, aI, scale, static_cast<Cx<typename P::scalar>*>(lds));
+  } else {
+    epilogue<P>(g, tr, tc, aR, aI, scale);
+  }
+}
+
 // One tile per workgroup.
-template <class P>
+template <class P, int X0G>
 __global__ __launch_bounds__(256, P::kMinWaves) void gemm_dp_kernel(GemmArgs g) {
-  __shared__ typename P::Smem sm;
+  __shared__ __align__(16) unsigned char smem[smem_bytes<P, X0G != 0>()];
+  auto& sm = *reinterpret_cast<typename P::Smem*>(smem);
   typename P::acc_t aR[2][2], aI[2][2];
   const double scale = tile_scale<P>(g);
   int tr, tc;
   tile_coords<P>(g, blockIdx.x, tr, tc);
   zero_acc<P>(aR, aI);
   P::run(g, sm, tr, tc, 0, g.kIters, aR, aI);
-  epilogue<P>(g, tr, tc, aR, aI, scale);
+  finish_tile<P, X0G>(g, tr, tc, aR, aI, scale, smem);
 }
 
 // Hybrid schedule: workgroup w first computes the whole tiles w, w + P,
 // w + 2P, ... below dp_tiles, then owns the stream-K iterations
 // [start(w), start(w+1)) of the K panels of the remaining tiles.
-template <class P>
+template <class P, int X0G>
 __global__ __launch_bounds__(256, P::kMinWaves) void gemm_sk_kernel(GemmArgs g) {
-  __shared__ typename P::Smem sm;
+  __shared__ __align__(16) unsigned char smem[smem_bytes<P, X0G != 0>()];
+  auto& sm = *reinterpret_cast<typename P::Smem*>(smem);
   typename P::acc_t aR[2][2], aI[2][2];
   // logical workgroup index: consecutive tiles and consecutive segments
   // (neighbours sharing panels) run on one XCD
   const int64_t Pn = gridDim.x, w = xcd_order(blockIdx.x, gridDim.x);
   const double scale = tile_scale<P>(g);
-  for (int64_t t = w; t < g.dp_tiles; t += Pn) {
-    int tr, tc;
-    tile_coords<P>(g, int(t), tr, tc);
-    zero_acc<P>(aR, aI);
-    P::run(g, sm, tr, tc, 0, g.kIters, aR, aI);
-    epilogue<P>(g, tr, tc, aR, aI, scale);
-  }
+  // one loop over the work items (whole tiles, then the stream-K slice), so
+  // that the tile epilogue is instantiated once
+  int64_t t = w;
   int64_t it = sk_start(w, Pn, g.iters);
   const int64_t end = sk_start(w + 1, Pn, g.iters);
   const int first_rel = int(it / g.kIters);
-  while (it < end) {
-    const int rel = int(it / g.kIters);
-    const int kb = int(it % g.kIters);
-    const int ke = int(min(int64_t(g.kIters), int64_t(kb) + (end - it)));
+  while (t < g.dp_tiles || it < end) {
+    int tile, kb, ke, rel = 0;
+    if (t < g.dp_tiles) {
+      tile = int(t);
+      kb = 0;
+      ke = g.kIters;
+      t += Pn;
+    } else {
+      rel = int(it / g.kIters);
+      kb = int(it % g.kIters);
+      ke = int(min(int64_t(g.kIters), int64_t(kb) + (end - it)));
+      tile = g.dp_tiles + rel;
+      it += ke - kb;
+    }
     int tr, tc;
-    tile_coords<P>(g, g.dp_tiles + rel, tr, tc);
+    tile_coords<P>(g, tile, tr, tc);
     zero_acc<P>(aR, aI);
     P::run(g, sm, tr, tc, kb, ke, aR, aI);
     if (kb == 0 && ke == g.kIters) {
-      epilogue<P>(g, tr, tc, aR, aI, scale);
+      finish_tile<P, X0G>(g, tr, tc, aR, aI, scale, smem);
     } else {
       store_partial<P>(partial_slot<P>(g, int(w), rel == first_rel ? 0 : 1), aR, aI);
     }
-    it += ke - kb;
   }
 }
 
 // Sum the partial segments of every stream-K tile that was cut, in K order.
 // Workgroup b handles tile dp_tiles + b.
-template <class P>
+template <class P, int X0G>
 __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g, int Pn) {
+  __shared__ __align__(16) unsigned char smem[X0G ? smem_bytes<P, X0G != 0>() : 16];
   const int rel = blockIdx.x;
   const int64_t kb = int64_t(rel) * g.kIters, kl = kb + g.kIters - 1;
   // workgroups owning the first and the last iteration of the tile
@@ -112,7 +132,7 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g, int Pn) {
   }
   int tr, tc;
   tile_coords<P>(g, g.dp_tiles + rel, tr, tc);
-  epilogue<P>(g, tr, tc, aR, aI, scale);
+  finish_tile<P, X0G>(g, tr, tc, aR, aI, scale, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,64 +202,106 @@ int device_cus() {
   return cached[dev];
 }
 
-// Workgroups of gemm_sk_kernel<P> resident per CU (queried once per process).
-template <class P>
+// Workgroups of gemm_sk_kernel<P, X0G> resident per CU (queried once per process).
+template <class P, int X0G>
 int sk_occupancy() {
   static int occ = 0;
   if (occ == 0) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_sk_kernel<P>, 256, 0) != hipSuccess || n <= 0) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_sk_kernel<P, X0G>, 256, 0) != hipSuccess || n <= 0) n = 1;
     occ = n;
   }
   return occ;
 }
 
-template <class P>
+// Stream-K grid for a given resident-workgroup count per CU; sets
+// g.dp_tiles and g.iters.  Returns 0 when stream-K does not apply.
+inline int64_t sk_grid(GemmArgs& g, int cus, int occ) {
+  int64_t Pn = 0;
+  g.dp_tiles = 0;
+  // Whole tiles first when every one of the (CUs x occupancy) workgroups
+  // gets at least one: those tiles need no partials.  With fewer tiles than
+  // that, lowering the workgroups per CU to make tiles whole costs more
+  // (measured at N = 11: 528 tiles at 2 per CU, T T^dagger 245 -> 283 us)
+  // than the partials it saves, so every tile is split instead.
+  if (g.ntiles / cus >= occ) {
+    Pn = int64_t(cus) * occ;
+    g.dp_tiles = int((g.ntiles / Pn) * Pn);
+  } else {
+    const int64_t min_iters = 32;  // at least 32 K panels per stream-K workgroup
+    Pn = std::min<int64_t>(int64_t(kStreamKMaxGrid),
+                           std::min<int64_t>(int64_t(cus) * occ, int64_t(g.ntiles) * g.kIters / min_iters));
+    Pn = (Pn / cus) * cus;  // whole waves of workgroups over the compute units
+  }
+  if (Pn < cus || Pn > kStreamKMaxGrid) {
+    g.dp_tiles = 0;
+    return 0;
+  }
+  g.iters = int64_t(g.ntiles - g.dp_tiles) * g.kIters;
+  return Pn;
+}
+
+template <class P, int X0G = 0>
 hipError_t run_gemm(GemmArgs g, hipStream_t s) {
   g.kIters = g.d / P::KP;
   g.iters = int64_t(g.ntiles) * g.kIters;
   const int cus = device_cus();
   g.dp_tiles = 0;
   bool sk = P::kStreamK && g.partial != nullptr && g.ntiles % cus != 0;
+  if (sk && X0G != 0) {
+    // The POVM epilogue raises the register use of the stream-K kernel.
+    // When no workgroup of the plain kernel's grid can finish a whole tile
+    // (no data-parallel tiles, every slice shorter than a tile), all tiles
+    // are finished by the fix-up: run the plain stream-K kernel (its
+    // epilogue is then never reached) and the POVM fix-up.
+    GemmArgs gp = g;
+    const int64_t Pn = sk_grid(gp, cus, std::min(sk_occupancy<P, 0>(), 4));
+    if (Pn > 0 && gp.dp_tiles == 0 && (gp.iters + Pn - 1) / Pn < gp.kIters) {
+      gemm_sk_kernel<P, 0><<<unsigned(Pn), 256, 0, s>>>(gp);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      GemmArgs gf = gp;
+      gf.tau_out = nullptr;
+      gemm_fixup_kernel<P, X0G><<<unsigned(gp.ntiles), 256, 0, s>>>(gf, int(Pn));
+      return hipGetLastError();
+    }
+  }
   int64_t Pn = 0;
   if (sk) {
-    const int occ = std::min(sk_occupancy<P>(), 4);
-    // Whole tiles first when every one of the (CUs x occupancy) workgroups
-    // gets at least one: those tiles need no partials.  With fewer tiles
-    // than that, lowering the workgroups per CU to make tiles whole costs
-    // more (measured at N = 11: 528 tiles at 2 per CU, T T^dagger 245 ->
-    // 283 us) than the partials it saves, so every tile is split instead.
-    if (g.ntiles / cus >= occ) {
-      Pn = int64_t(cus) * occ;
-      g.dp_tiles = int((g.ntiles / Pn) * Pn);
-    } else {
-      const int64_t min_iters = 32;  // at least 32 K panels per stream-K workgroup
-      Pn = std::min<int64_t>(int64_t(kStreamKMaxGrid), std::min<int64_t>(int64_t(cus) * occ, g.iters / min_iters));
-      Pn = (Pn / cus) * cus;  // whole waves of workgroups over the compute units
-    }
-    sk = Pn >= cus && Pn <= kStreamKMaxGrid;
-    g.iters = int64_t(g.ntiles - g.dp_tiles) * g.kIters;
+    const int occ = std::min(sk_occupancy<P, X0G>(), 4);
+    Pn = sk_grid(g, cus, occ);
+    sk = Pn > 0;
   }
   if (!sk) {
     g.dp_tiles = 0;
     g.iters = int64_t(g.ntiles) * g.kIters;
-    gemm_dp_kernel<P><<<unsigned(g.ntiles), 256, 0, s>>>(g);
+    gemm_dp_kernel<P, X0G><<<unsigned(g.ntiles), 256, 0, s>>>(g);
     return hipGetLastError();
   }
-  gemm_sk_kernel<P><<<unsigned(Pn), 256, 0, s>>>(g);
+  gemm_sk_kernel<P, X0G><<<unsigned(Pn), 256, 0, s>>>(g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   GemmArgs gf = g;
   gf.tau_out = nullptr;
-  gemm_fixup_kernel<P><<<unsigned(g.ntiles - g.dp_tiles), 256, 0, s>>>(gf, int(Pn));
+  gemm_fixup_kernel<P, X0G><<<unsigned(g.ntiles - g.dp_tiles), 256, 0, s>>>(gf, int(Pn));
   return hipGetLastError();
+}
+
+template <int G>
+hipError_t run_herk_x0(qst_prec prec, int d, const GemmArgs& g, hipStream_t s) {
+  if (prec == QST_F64) return run_gemm<CxPolicy<double, true>, G>(g, s);
+  if (prec == QST_F32) return run_gemm<CxPolicy<float, true>, G>(g, s);
+  if (d <= kBf16SplitMaxDim) return run_gemm<HerkBf16x3Policy, G>(g, s);
+  return run_gemm<HerkBf16Policy, G>(g, s);
 }
 
 }  // namespace
 
 hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int64_t ldr, int n,
-                       const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s) {
+                       const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s,
+                       const Pass0Out* x0) {
   const int d = 1 << n;
+  if (x0 && (d < BM || x0->g < 4 || x0->g > 6 || !x0->tetra)) return hipErrorInvalidValue;
   ProfScope prof(d < BM ? "herk_small" : (prec == QST_F64 ? "herk_f64" : prec == QST_F32 ? "herk_f32" : "herk_bf16"), s);
   if (d < BM) {
     if (prec == QST_F64)
@@ -268,6 +330,13 @@ hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int
   g.partial = sk_partial;
   g.tau_part = tau_partials;
   g.tau_out = tau_partials ? tau_dev : nullptr;
+  if (x0) {
+    g.x0 = x0->X;
+    g.x0g = x0->g;
+    g.x0up = n - x0->g;
+    return x0->g == 6 ? run_herk_x0<6>(prec, d, g, s) : x0->g == 5 ? run_herk_x0<5>(prec, d, g, s)
+                                                         : run_herk_x0<4>(prec, d, g, s);
+  }
   if (prec == QST_F64) return run_gemm<CxPolicy<double, true>>(g, s);
   if (prec == QST_F32) return run_gemm<CxPolicy<float, true>>(g, s);
   if (d <= kBf16SplitMaxDim) return run_gemm<HerkBf16x3Policy>(g, s);

@@ -119,7 +119,7 @@ hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const do
 hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W, const double* V, bool tetra,
                              const void* rho, int64_t ld_rho, const void* fvec, const double* Fpart, void* G,
                              int64_t ldG, void* inter0, void* inter1, double* part, double* nll_dev,
-                             unsigned long long* bad_dev, hipStream_t s) {
+                             unsigned long long* bad_dev, bool pass0_done, hipStream_t s) {
   static const char* kFwd[4] = {"povm_fwd_p0", "povm_fwd_p1", "povm_fwd_p2", "povm_fwd_p3"};
   static const char* kAdj[4] = {"povm_adj_p0", "povm_adj_p1", "povm_adj_p2", "povm_adj_p3"};
   ModeMatrix Af, Aa;
@@ -138,7 +138,7 @@ hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W,
     return a;
   };
   hipError_t e = hipSuccess;
-  for (int j = 0; j + 1 < P; ++j) {
+  for (int j = pass0_done ? 1 : 0; j + 1 < P; ++j) {
     PassArgs a = args(j);
     a.in = j == 0 ? rho : bufs[(j - 1) & 1];
     a.out = bufs[j & 1];

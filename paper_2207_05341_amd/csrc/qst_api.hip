@@ -26,12 +26,15 @@ qst_status hip_fail(hipError_t e, const char* what) {
 // produces tau first.
 // With f, the tau kernel also leaves the partial sums of F = sum f at
 // partials + kReduceBlocks.
+// With x0, the first POVM pass is applied to rho's tiles in the product
+// kernel and rho itself is not written.
 hipError_t run_state_map(qst_prec prec, const void* T, int64_t ldT, void* rho, int64_t ldr, int n,
-                         double* partials, double* tau_dev, void* sk, hipStream_t s, const void* f = nullptr) {
+                         double* partials, double* tau_dev, void* sk, hipStream_t s, const void* f = nullptr,
+                         const Pass0Out* x0 = nullptr) {
   const bool fold = n >= 6;
   hipError_t e = launch_tau(prec, T, ldT, n, partials, fold ? nullptr : tau_dev, s, f);
   if (e != hipSuccess) return e;
-  return launch_herk(prec, T, ldT, rho, ldr, n, fold ? partials : nullptr, tau_dev, sk, s);
+  return launch_herk(prec, T, ldT, rho, ldr, n, fold ? partials : nullptr, tau_dev, sk, s, x0);
 }
 
 }  // namespace
@@ -172,12 +175,18 @@ qst_status qst_likelihood(int n, qst_prec prec, const void* T, int64_t ldT, cons
   const int64_t d = int64_t(1) << n;
   void* rho = ws_at(ws, L.rho);
   const bool fused = fused_likelihood(pl, prec);
+  // tetrahedral POVM: the first pass runs in the epilogue of T T^dagger, so
+  // rho is never written (the tile sizes of pass 0 divide the 64 x 64
+  // product tiles for every fused plan)
+  const bool x0 = fused && tetra && d >= 64 && pl.g[0] >= 4 && pl.g[0] <= 6;
+  const Pass0Out p0{ws_at(ws, L.inter0), pl.g[0], true};
   hipError_t e = run_state_map(prec, T, ldT, rho, d, n, partials, tau_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s,
-                               fused ? f : nullptr);
+                               fused ? f : nullptr, x0 ? &p0 : nullptr);
   if (e != hipSuccess) return hip_fail(e, "state map");
   if (fused) {
     e = launch_povm_fused(prec, pl, W, V, tetra, rho, d, f, partials + kReduceBlocks, G, ldG, ws_at(ws, L.inter0),
-                          ws_at(ws, L.inter1), reinterpret_cast<double*>(ws_at(ws, L.fpart)), nll_dev, bad_dev, s);
+                          ws_at(ws, L.inter1), reinterpret_cast<double*>(ws_at(ws, L.fpart)), nll_dev, bad_dev, x0,
+                          s);
     if (e != hipSuccess) return hip_fail(e, "fused POVM / likelihood passes");
   } else {
     void* p = ws_at(ws, L.p);

@@ -5,6 +5,7 @@
 
 #include "qst_device.h"
 #include "qst_plan.h"
+#include "qst_povm_rounds.h"
 
 namespace qst {
 namespace gemm {
@@ -31,6 +32,14 @@ struct GemmArgs {
   void* partial;  // stream-K partial accumulators [P][2][2 * TILE] (acc scalar)
   const double* tau_part;  // HERK: FP64 partial sums of tau (kReduceBlocks), or NULL to read *tau
   double* tau_out;         // HERK with tau_part: where workgroup 0 stores tau
+  // HERK with the first POVM pass in the epilogue (kernels instantiated with
+  // X0; tetrahedral POVM): a finished tile of rho is not stored; the pass
+  // over its x0g lowest qubits is applied to each of its 2^x0g x 2^x0g
+  // sub-tiles and the lower ones go to x0 (the pass output X[(R, C)][k],
+  // (R, C) over the x0up remaining qubits).
+  void* x0;
+  int x0g;
+  int x0up;
 };
 
 // ---------------------------------------------------------------------------
@@ -528,6 +537,58 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int tr, int tc, type
       }
     }
   }
+}
+
+// The tetrahedral fast form reads no mode matrix; this one only fills the
+// parameter.
+static __constant__ ModeMatrix kTetraNoMatrix = {};
+
+// First POVM pass applied to a finished T T^dagger tile (see GemmArgs::x0).
+// lds: BM x BM complex values of the workgroup's shared memory (aliasing the
+// panel buffers, which the caller no longer reads).
+template <class P, int G>
+__device__ __forceinline__ void x0_tile(const GemmArgs& g, int tr, int tc, typename P::acc_t (&aR)[2][2],
+                                        typename P::acc_t (&aI)[2][2], double scale,
+                                        Cx<typename P::scalar>* lds) {
+  typedef typename P::scalar R;
+  constexpr int S = BM >> G;             // sub-tiles per side
+  constexpr int TG = 1 << (2 * G);       // values per sub-tile
+  constexpr int NT = 1 << (2 * (G - 2)); // threads per sub-tile
+  constexpr int M = (1 << G) - 1;
+  const R sc = R(scale);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1, li = lane & 15, lq = lane >> 4;
+  __syncthreads();  // every wave is done with the panel buffers
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = wc * 32 + j * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr * 32 + i * 16 + P::row(lq, v);
+        lds[((r >> G) * S + (c >> G)) * TG + swz<G>(r & M, c & M)] = Cx<R>{aR[i][j][v] * sc, aI[i][j][v] * sc};
+      }
+    }
+  __syncthreads();
+  const int tl = threadIdx.x / NT, t = threadIdx.x % NT;
+  const int64_t Rhi = int64_t(tr) * S + tl / S, Chi = int64_t(tc) * S + tl % S;
+  Cx<R>* L = lds + tl * TG;
+  const int bq = t & ((1 << (G - 2)) - 1), aq = t >> (G - 2);
+  Cx<R> x[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) x[m] = L[swz<G>(4 * aq + blk_ri(m), 4 * bq + blk_ci(m))];
+  Cx<R>* out = Rhi >= Chi ? static_cast<Cx<R>*>(g.x0) + ((Rhi << g.x0up) | Chi) * int64_t(TG) : nullptr;
+  mat_fwd_rounds<R, true, G>(x, L, t, kTetraNoMatrix, out);
+}
+
+// Shared memory of a product kernel: the policy's panel buffers, and with
+// X0 at least one BM x BM complex tile for the POVM epilogue.
+template <class P, bool X0>
+constexpr size_t smem_bytes() {
+  return (X0 && size_t(BM) * BM * sizeof(Cx<typename P::scalar>) > sizeof(typename P::Smem))
+             ? size_t(BM) * BM * sizeof(Cx<typename P::scalar>)
+             : sizeof(typename P::Smem);
 }
 
 // Partial accumulators of one tile segment, stored per lane in the MFMA

@@ -37,8 +37,17 @@ hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* p
 // or, when tau_partials is NULL, from *tau_dev.  sk_partial: stream-K
 // partial-tile area of stream_k_partial_bytes(prec) bytes, or NULL (then one
 // workgroup per tile).
+// First product-POVM pass folded into T T^dagger (tetrahedral POVM, d >= 64):
+// instead of rho, each finished tile's pass over the g lowest qubits
+// (4 <= g <= 6) is written to X (the pass-0 output of the plan).
+struct Pass0Out {
+  void* X;
+  int g;
+  bool tetra;  // must be true
+};
 hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int64_t ldr, int n,
-                       const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s);
+                       const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s,
+                       const Pass0Out* x0 = nullptr);
 
 // out = (upstream ? *upstream : 1) * 2 / *tau_dev * G T.
 hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T, int64_t ldt,
@@ -65,13 +74,14 @@ hipError_t launch_likelihood_finish(const double* part, int nb, const double* Fp
                                    unsigned long long* bad_dev, hipStream_t s);
 
 // The POVM part of qst_likelihood when fused_likelihood(pl, prec): forward
-// passes 0..P-2, the fused last pass (+ NLL finish into nll_dev / bad_dev),
-// and, if G is not NULL, the adjoint passes P-2..0.  part: FP64 partials
-// [4][blocks of the last pass]; Fpart: the kReduceBlocks F partials.
+// passes 0..P-2 (from pass 1 when pass0_done: its output is already in
+// inter0), the fused last pass (+ NLL finish into nll_dev / bad_dev), and, if
+// G is not NULL, the adjoint passes P-2..0.  part: FP64 partials [4][blocks
+// of the last pass]; Fpart: the kReduceBlocks F partials.
 hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W, const double* V, bool tetra,
                              const void* rho, int64_t ld_rho, const void* fvec, const double* Fpart, void* G,
                              int64_t ldG, void* inter0, void* inter1, double* part, double* nll_dev,
-                             unsigned long long* bad_dev, hipStream_t s);
+                             unsigned long long* bad_dev, bool pass0_done, hipStream_t s);
 
 hipError_t launch_fsum(qst_prec prec, const void* f, int n, double* partials, double* F_dev,
                        hipStream_t s);
