@@ -121,13 +121,18 @@ __device__ __forceinline__ double sum_partials256(const double* part, int nb, do
 // Per-outcome arithmetic of the likelihood in the storage precision of p
 // and f: ln p_k (the sum over k is accumulated in FP64 on every path) and
 // the cotangent g'_k = F - f_k / p_k (F where f_k = 0).  FP64 storage: FP64
-// throughout.  FP32 storage: the logarithm and the quotient in FP32 (about
-// one ulp each, the size of the rounding of p itself).
+// throughout.  FP32 storage: the hardware base-2 logarithm times ln 2 and
+// the hardware reciprocal (about one ulp each, the size of the rounding of
+// p itself; p is a probability, far from the denormal range the hardware
+// flushes, except where it is 0 or negative, which the callers treat
+// apart).
 __device__ __forceinline__ double ln_prob(double p) { return log(p); }
-__device__ __forceinline__ double ln_prob(float p) { return double(logf(p)); }
+__device__ __forceinline__ double ln_prob(float p) {
+  return double(__builtin_amdgcn_logf(p) * 0.693147180559945309f);
+}
 __device__ __forceinline__ double cotangent(double F, double f, double p) { return f != 0.0 ? F - f / p : F; }
 __device__ __forceinline__ float cotangent(double F, float f, float p) {
-  return f != 0.0f ? float(F) - f / p : float(F);
+  return f != 0.0f ? float(F) - f * __builtin_amdgcn_rcpf(p) : float(F);
 }
 
 }  // namespace qst
