@@ -190,6 +190,42 @@ def probs_real(rho: np.ndarray, povm: np.ndarray | None = None, check: bool = Tr
     return pc.real.copy()
 
 
+def outcome_digits(k: int, n: int, K: int = 4) -> tuple:
+    """(k_1..k_N) of the flat outcome index k = sum_i k_i K^(N-i)."""
+    out = []
+    for _ in range(n):
+        out.append(k % K)
+        k //= K
+    return tuple(reversed(out))
+
+
+def probs_at(W: np.ndarray, outcomes, povm: np.ndarray | None = None) -> np.ndarray:
+    """p_k = Tr(M_k rho) for the listed outcomes only (each a tuple k_1..k_N),
+    rho = W W^dagger / Tr(W W^dagger) with W a d x r factor (Born rule,
+    Sec. 2.1; product POVM, Sec. 3.3).  Uses Tr(M_k W W^dagger) =
+    Tr(W^dagger M_k W): M_k = M_{k_1} (x) ... (x) M_{k_N} is applied to the
+    row index of W one qubit at a time (qubit 1 = the most significant row
+    bit), O(N d r) work per outcome, so single outcomes of the largest states
+    can be evaluated without forming rho or the full map."""
+    povm = tetrahedral_povm() if povm is None else np.asarray(povm, dtype=np.complex128)
+    a = np.asarray(W, dtype=np.complex128)
+    if a.ndim == 1:
+        a = a[:, None]
+    d, r = a.shape
+    n = n_qubits_of(d)
+    tau = trace_tt(a)
+    base = a.reshape((2,) * n + (r,))
+    out = []
+    for ks in outcomes:
+        if len(ks) != n:
+            raise ValueError("outcome tuple length differs from the qubit count")
+        x = base
+        for i, kq in enumerate(ks):
+            x = np.moveaxis(np.tensordot(povm[kq], x, axes=([1], [i])), 0, i)
+        out.append(np.vdot(base, x).real)  # sum conj(W) * (M_k W)
+    return np.asarray(out, dtype=np.float64) / tau
+
+
 # ----------------------------------------------------------------------------
 # Adjoint of the POVM map: G = sum_k g_k M_k
 # ----------------------------------------------------------------------------

@@ -90,6 +90,17 @@ def porter_thomas_probs(g: np.random.Generator, n_outcomes: int, q: float) -> np
     return (1.0 - q) * (w / w.sum()) + q / n_outcomes
 
 
+def thin_factor_square(g: np.random.Generator, d: int, r: int) -> tuple[np.ndarray, np.ndarray]:
+    """(T, W): W a d x r Ginibre factor and T = W Q^dagger, d x d, with Q a
+    d x r matrix of orthonormal columns (QR of a Ginibre matrix), so that
+    T T^dagger = W W^dagger exactly in exact arithmetic.  Every entry of T is
+    generic (no zero rows or columns), while single outcome probabilities of
+    T T^dagger / Tr can be evaluated from the thin W."""
+    W = ginibre(g, d, r)
+    Q, _ = np.linalg.qr(ginibre(g, d, r))
+    return W @ Q.conj().T, W
+
+
 def unit_directions(g: np.random.Generator, d: int, count: int) -> list[np.ndarray]:
     """``count`` complex Ginibre d x d directions with unit Frobenius norm."""
     out = []

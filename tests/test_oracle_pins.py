@@ -105,6 +105,54 @@ def test_product_state_closed_form(n):
         assert np.max(np.abs(O.probs_kron(rho).real - want)) <= 1e-15
 
 
+def pure_qubit(r):
+    """Ket with Bloch vector r (|r| = 1): (cos(t/2), e^{i f} sin(t/2))."""
+    t = math.acos(max(-1.0, min(1.0, r[2])))
+    f = math.atan2(r[1], r[0])
+    return np.array([math.cos(t / 2), complex(math.cos(f), math.sin(f)) * math.sin(t / 2)])
+
+
+@pytest.mark.parametrize("n", [1, 3, 13])
+def test_probs_at_product_state_closed_form(n):
+    """Single outcomes from a rank-1 factor: W = (x)_i |psi_i>, pure qubits
+    with distinct Bloch vectors (r_y != 0), gives p_k = prod_i (1 + s_{k_i}.r_i)/4
+    at any N, N = 13 (8192 rows) included."""
+    g = S.rng(250 + n)
+    r = g.standard_normal((n, 3))
+    r = r / np.linalg.norm(r, axis=1, keepdims=True)
+    assert np.all(np.abs(r[:, 1]) > 1e-3)
+    W = np.ones(1, dtype=np.complex128)
+    for ri in r:
+        W = np.kron(W, pure_qubit(ri))
+    D = 4 ** n
+    ks = list(range(D)) if D <= 64 else [0, D - 1] + [int(k) for k in g.integers(0, D, 62)]
+    outs = [O.outcome_digits(k, n) for k in ks]
+    want = np.array([np.prod([(1.0 + O.TETRA_S[o[i]] @ r[i]) / 4.0 for i in range(n)]) for o in outs])
+    got = O.probs_at(W, outs)
+    assert np.max(np.abs(got - want)) <= 1e-14 * np.max(want)
+
+
+@pytest.mark.parametrize("n", [1, 3, 5])
+@pytest.mark.parametrize("rank", [1, 3, None])
+def test_probs_at_equals_full_map(n, rank):
+    """probs_at(W) = the full product map of rho = W W^dagger / Tr at every
+    outcome, for thin and square factors, tetrahedral and rotated POVMs;
+    the outcome digits follow k = sum_i k_i 4^(N-i)."""
+    g = S.rng(260 + 10 * n + (rank or 0))
+    d = 1 << n
+    W = S.ginibre(g, d, rank or d)
+    rho, _ = O.state_map(W)
+    U, _ = np.linalg.qr(S.ginibre(g, 2))
+    rot = np.array([U @ m @ U.conj().T for m in O.tetrahedral_povm()])
+    for povm in (None, rot):
+        full = O.probs_real(rho, povm)
+        outs = [O.outcome_digits(k, n) for k in range(4 ** n)]
+        got = O.probs_at(W, outs, povm)
+        assert np.max(np.abs(got - full)) <= 1e-14 * np.max(full)
+    assert O.outcome_digits(4 ** n - 1, n) == (3,) * n
+    assert O.outcome_digits(1, n)[-1] == 1 and O.outcome_digits(4 ** (n - 1), n)[0] == 1
+
+
 def test_eq_ps_literal_pairing_is_transposed():
     """Reading of Eq. PS: pairing b_i (the (0,1) entry of M_i) with the
     (0,1) block B computes Tr(M^T rho), which flips s_y.  The Born rule pairs
