@@ -19,17 +19,33 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 // --------------------------------------------------------------------------
-// bfloat16 round-to-nearest-even of a float, returned as the 16-bit pattern
-// and as the float it represents.  Finite inputs only (the state-map inputs
-// are finite; NaN payloads are not preserved).
+// bfloat16 round-to-nearest-even of a float (gfx950's FP32 -> BF16
+// conversion instruction in the default rounding mode), as the 16-bit
+// pattern and as the float it represents; bf16x8 converts eight floats with
+// four packed conversions.  The split x = hi + lo takes hi = bf16(x) and
+// lo = bf16(x - hi) (x - hi is exact in FP32).
 // --------------------------------------------------------------------------
-__device__ __forceinline__ uint16_t bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ float bf16_value(float x) { return float((__bf16)x); }
+__device__ __forceinline__ float bf16_to_float(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+__device__ __forceinline__ uint32_t bf16x2_bits(float a, float b) {
+  const bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
 }
-__device__ __forceinline__ float bf16_value(float x) {
-  return __uint_as_float(uint32_t(bf16_bits(x)) << 16);
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u16x8 bf16x8(const float (&v)[8]) {
+  const u32x4 w = {bf16x2_bits(v[0], v[1]), bf16x2_bits(v[2], v[3]), bf16x2_bits(v[4], v[5]),
+                   bf16x2_bits(v[6], v[7])};
+  return __builtin_bit_cast(u16x8, w);
+}
+// hi and lo planes of eight values
+__device__ __forceinline__ void bf16x8_split(const float (&v)[8], u16x8& hi, u16x8& lo) {
+  hi = bf16x8(v);
+  float r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = v[i] - bf16_to_float(hi[i]);
+  lo = bf16x8(r);
 }
 
 // --------------------------------------------------------------------------

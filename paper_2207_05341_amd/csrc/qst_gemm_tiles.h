@@ -224,18 +224,18 @@ struct HerkBf16Policy {
     for (int kp = kb; kp < ke; ++kp) {
       __syncthreads();
       {
-        u16x8 xr, xi, yr, yi;
+        float xr[8], xi[8], yr[8], yi[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          xr[i] = bf16_bits(ra[i].re);
-          xi[i] = bf16_bits(ra[i].im);
-          yr[i] = bf16_bits(rb[i].re);
-          yi[i] = bf16_bits(rb[i].im);
+          xr[i] = ra[i].re;
+          xi[i] = ra[i].im;
+          yr[i] = rb[i].re;
+          yi[i] = rb[i].im;
         }
-        *reinterpret_cast<u16x8*>(&sm.Ar[row][kq]) = xr;
-        *reinterpret_cast<u16x8*>(&sm.Ai[row][kq]) = xi;
-        *reinterpret_cast<u16x8*>(&sm.Br[row][kq]) = yr;
-        *reinterpret_cast<u16x8*>(&sm.Bi[row][kq]) = yi;
+        *reinterpret_cast<u16x8*>(&sm.Ar[row][kq]) = bf16x8(xr);
+        *reinterpret_cast<u16x8*>(&sm.Ai[row][kq]) = bf16x8(xi);
+        *reinterpret_cast<u16x8*>(&sm.Br[row][kq]) = bf16x8(yr);
+        *reinterpret_cast<u16x8*>(&sm.Bi[row][kq]) = bf16x8(yi);
       }
       __syncthreads();
       if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
@@ -268,6 +268,25 @@ struct HerkBf16Policy {
   }
 };
 
+// Eight consecutive complex values -> their re_hi, im_hi, re_lo, im_lo
+// bf16 planes at P[plane][row][k0..k0+7] (16-byte stores).
+template <int LD>
+__device__ __forceinline__ void split_store_planes(uint16_t (*P)[BM][LD], int row, int k0, const Cx<float> (&v)[8]) {
+  float re[8], im[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    re[i] = v[i].re;
+    im[i] = v[i].im;
+  }
+  u16x8 h0, h1, l0, l1;
+  bf16x8_split(re, h0, l0);
+  bf16x8_split(im, h1, l1);
+  *reinterpret_cast<u16x8*>(&P[0][row][k0]) = h0;
+  *reinterpret_cast<u16x8*>(&P[1][row][k0]) = h1;
+  *reinterpret_cast<u16x8*>(&P[2][row][k0]) = l0;
+  *reinterpret_cast<u16x8*>(&P[3][row][k0]) = l1;
+}
+
 // T T^dagger with T split into bf16 hi + lo (three products: hi hi^dagger +
 // hi lo^dagger + lo hi^dagger), fp32 accumulate.  Used for small d, where the
 // rounding of plain bf16 T moves the gradient by more than the BF16 bar.
@@ -286,19 +305,7 @@ struct HerkBf16x3Policy {
 
   static __device__ __forceinline__ void split_store(uint16_t (*P)[BM][KP + PADH], int row, int kq,
                                                      const Cx<float> (&v)[8]) {
-    u16x8 h0, h1, l0, l1;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const uint16_t hr = bf16_bits(v[i].re), hm = bf16_bits(v[i].im);
-      h0[i] = hr;
-      h1[i] = hm;
-      l0[i] = bf16_bits(v[i].re - __uint_as_float(uint32_t(hr) << 16));
-      l1[i] = bf16_bits(v[i].im - __uint_as_float(uint32_t(hm) << 16));
-    }
-    *reinterpret_cast<u16x8*>(&P[0][row][kq]) = h0;
-    *reinterpret_cast<u16x8*>(&P[1][row][kq]) = h1;
-    *reinterpret_cast<u16x8*>(&P[2][row][kq]) = l0;
-    *reinterpret_cast<u16x8*>(&P[3][row][kq]) = l1;
+    split_store_planes(P, row, kq, v);
   }
 
   static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
@@ -385,8 +392,8 @@ struct HemmBf16x3Policy {
     const int lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
     const int li = lane & 15, lq = lane >> 4;
-    const int a_row = t >> 2, a_k = (t & 3) * 8;  // A panel: 64 rows x 32 k
-    const int b_k = t >> 3, b_n = (t & 7) * 8;    // B panel: 32 k x 64 n
+    const int a_row = t >> 2, a_k = (t & 3) * 8;  // A panel: 64 rows x 32 k, 8 consecutive k per thread
+    const int b_n = t & 63, b_k = (t >> 6) * 8;   // B panel: 32 k x 64 n, 8 consecutive k of one column
     const Cx<float>* Ap = G + (R0 + a_row) * g.lda + a_k;
     const Cx<float>* Bp = T + int64_t(b_k) * g.ldb + C0 + b_n;
     Cx<float> ra[8], rb[8];
@@ -395,35 +402,14 @@ struct HemmBf16x3Policy {
     const int k0_ = (kp) * KP;                             \
     _Pragma("unroll") for (int i = 0; i < 8; ++i) {        \
       ra[i] = Ap[k0_ + i];                                 \
-      rb[i] = Bp[int64_t(k0_) * g.ldb + i];                \
+      rb[i] = Bp[int64_t(k0_ + i) * g.ldb];                \
     }                                                      \
   } while (0)
     QST_LOAD_PANEL(kb);
     for (int kp = kb; kp < ke; ++kp) {
       __syncthreads();
-      {
-        u16x8 h0, h1, l0, l1;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const uint16_t hr = bf16_bits(ra[i].re), hm = bf16_bits(ra[i].im);
-          h0[i] = hr;
-          h1[i] = hm;
-          l0[i] = bf16_bits(ra[i].re - __uint_as_float(uint32_t(hr) << 16));
-          l1[i] = bf16_bits(ra[i].im - __uint_as_float(uint32_t(hm) << 16));
-        }
-        *reinterpret_cast<u16x8*>(&sm.As[0][a_row][a_k]) = h0;
-        *reinterpret_cast<u16x8*>(&sm.As[1][a_row][a_k]) = h1;
-        *reinterpret_cast<u16x8*>(&sm.As[2][a_row][a_k]) = l0;
-        *reinterpret_cast<u16x8*>(&sm.As[3][a_row][a_k]) = l1;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const uint16_t hr = bf16_bits(rb[i].re), hm = bf16_bits(rb[i].im);
-          sm.Bt[0][b_n + i][b_k] = hr;
-          sm.Bt[1][b_n + i][b_k] = hm;
-          sm.Bt[2][b_n + i][b_k] = bf16_bits(rb[i].re - __uint_as_float(uint32_t(hr) << 16));
-          sm.Bt[3][b_n + i][b_k] = bf16_bits(rb[i].im - __uint_as_float(uint32_t(hm) << 16));
-        }
-      }
+      split_store_planes(sm.As, a_row, a_k, ra);
+      split_store_planes(sm.Bt, b_n, b_k, rb);
       __syncthreads();
       if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
 #undef QST_LOAD_PANEL
