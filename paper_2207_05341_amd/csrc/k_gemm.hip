@@ -288,10 +288,11 @@ hipError_t run_gemm(GemmArgs g, hipStream_t s) {
 }
 
 template <int G>
-hipError_t run_herk_x0(qst_prec prec, int d, const GemmArgs& g, hipStream_t s) {
+hipError_t run_herk_x0(qst_prec prec, int d, const GemmArgs& g, hipStream_t s, bool planes) {
   if (prec == QST_F64) return run_gemm<CxPolicy<double, true>, G>(g, s);
   if (prec == QST_F32) return run_gemm<CxPolicy<float, true>, G>(g, s);
   if (d <= kBf16SplitMaxDim) return run_gemm<HerkBf16x3Policy, G>(g, s);
+  if (planes) return run_gemm<HerkBf16PlanesPolicy, G>(g, s);
   return run_gemm<HerkBf16Policy, G>(g, s);
 }
 
@@ -299,7 +300,7 @@ hipError_t run_herk_x0(qst_prec prec, int d, const GemmArgs& g, hipStream_t s) {
 
 hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int64_t ldr, int n,
                        const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s,
-                       const Pass0Out* x0) {
+                       const Pass0Out* x0, const void* planes) {
   const int d = 1 << n;
   if (x0 && (d < BM || x0->g < 4 || x0->g > 6 || !x0->tetra)) return hipErrorInvalidValue;
   ProfScope prof(d < BM ? "herk_small" : (prec == QST_F64 ? "herk_f64" : prec == QST_F32 ? "herk_f32" : "herk_bf16"), s);
@@ -330,16 +331,25 @@ hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int
   g.partial = sk_partial;
   g.tau_part = tau_partials;
   g.tau_out = tau_partials ? tau_dev : nullptr;
+  const bool use_planes = prec == QST_BF16GEMM && d > kBf16SplitMaxDim && planes;
+  if (use_planes) {  // operands: bf16 planes of T, row stride d
+    g.A = planes;
+    g.lda = d;
+    g.B = planes;
+    g.ldb = d;
+  }
   if (x0) {
     g.x0 = x0->X;
     g.x0g = x0->g;
     g.x0up = n - x0->g;
-    return x0->g == 6 ? run_herk_x0<6>(prec, d, g, s) : x0->g == 5 ? run_herk_x0<5>(prec, d, g, s)
-                                                         : run_herk_x0<4>(prec, d, g, s);
+    return x0->g == 6 ? run_herk_x0<6>(prec, d, g, s, use_planes)
+           : x0->g == 5 ? run_herk_x0<5>(prec, d, g, s, use_planes)
+                        : run_herk_x0<4>(prec, d, g, s, use_planes);
   }
   if (prec == QST_F64) return run_gemm<CxPolicy<double, true>>(g, s);
   if (prec == QST_F32) return run_gemm<CxPolicy<float, true>>(g, s);
   if (d <= kBf16SplitMaxDim) return run_gemm<HerkBf16x3Policy>(g, s);
+  if (use_planes) return run_gemm<HerkBf16PlanesPolicy>(g, s);
   return run_gemm<HerkBf16Policy>(g, s);
 }
 

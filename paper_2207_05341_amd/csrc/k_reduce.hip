@@ -66,6 +66,70 @@ __global__ __launch_bounds__(256) void tau_partial_kernel(const Cx<R>* __restric
   }
 }
 
+// BF16 path with planes: the partial sums of tau_partial_kernel<float, 1,
+// WITH_F> over the same per-block element ranges, and bf16(T) stored as a
+// re plane and an im plane (d x d row-major each: element e = r d + c at
+// planes[e] and planes[d^2 + e]), the operands of the bf16 product.  Each
+// thread takes 8 consecutive elements of a row at a time (16-byte plane
+// stores); needs the block range to be a multiple of 8 (d^2 / kReduceBlocks
+// for d >= 256).
+template <bool WITH_F>
+__global__ __launch_bounds__(256) void tau_planes_kernel(const Cx<float>* __restrict__ T, int64_t ld, int n,
+                                                         double* __restrict__ partials,
+                                                         const float* __restrict__ f,
+                                                         uint16_t* __restrict__ planes) {
+  __shared__ double red[4];
+  const int64_t d = int64_t(1) << n;
+  const int64_t total = d * d;
+  const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t beg = int64_t(blockIdx.x) * chunk;
+  const int64_t end = beg + chunk < total ? beg + chunk : total;
+  constexpr int U = 2;
+  double acc = 0.0, accf = 0.0;
+  for (int64_t e0 = beg + 8 * int64_t(threadIdx.x); e0 < end; e0 += 8 * U * int64_t(blockDim.x)) {
+    Cx<float> v[U][8];
+    float fv[U][8];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + u * 8 * int64_t(blockDim.x);
+      const bool in = e < end;
+      const Cx<float>* src = T + (e >> n) * ld + (e & (d - 1));
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        v[u][i] = in ? src[i] : Cx<float>{0.f, 0.f};
+        if constexpr (WITH_F) fv[u][i] = in ? f[e + i] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + u * 8 * int64_t(blockDim.x);
+      float re[8], im[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        re[i] = v[u][i].re;
+        im[i] = v[u][i].im;
+      }
+      const u16x8 hr = bf16x8(re), hi = bf16x8(im);
+      if (e < end) {
+        *reinterpret_cast<u16x8*>(planes + e) = hr;
+        *reinterpret_cast<u16x8*>(planes + total + e) = hi;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double x = double(bf16_to_float(hr[i])), y = double(bf16_to_float(hi[i]));
+        acc += x * x + y * y;
+        if constexpr (WITH_F) accf += double(fv[u][i]);
+      }
+    }
+  }
+  const double s = block_sum256(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if constexpr (WITH_F) {
+    const double sf = block_sum256(accf, red);
+    if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = sf;
+  }
+}
+
 // One 256-thread block: out[i] = sum_b partials[i*nb + b] for i < nsum.
 __global__ __launch_bounds__(256) void finish_sums_kernel(const double* __restrict__ partials, int nb,
                                                           int nsum, double* __restrict__ out) {
@@ -194,7 +258,7 @@ __global__ __launch_bounds__(256) void likelihood_finish_kernel(const double* __
 }  // namespace
 
 hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
-                      double* tau_dev, hipStream_t s, const void* f) {
+                      double* tau_dev, hipStream_t s, const void* f, void* planes) {
   const int nb = kReduceBlocks;
   ProfScope prof("tau_reduce", s);
   const Cx<double>* T64 = static_cast<const Cx<double>*>(T);
@@ -211,7 +275,10 @@ hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* p
     if (f) tau_partial_kernel<float, 2, true><<<nb, 256, 0, s>>>(T32, ld, n, partials, f32);
     else tau_partial_kernel<float, 2><<<nb, 256, 0, s>>>(T32, ld, n, partials);
   } else {
-    if (f) tau_partial_kernel<float, 1, true><<<nb, 256, 0, s>>>(T32, ld, n, partials, f32);
+    uint16_t* pl = static_cast<uint16_t*>(planes);
+    if (pl && f) tau_planes_kernel<true><<<nb, 256, 0, s>>>(T32, ld, n, partials, f32, pl);
+    else if (pl) tau_planes_kernel<false><<<nb, 256, 0, s>>>(T32, ld, n, partials, nullptr, pl);
+    else if (f) tau_partial_kernel<float, 1, true><<<nb, 256, 0, s>>>(T32, ld, n, partials, f32);
     else tau_partial_kernel<float, 1><<<nb, 256, 0, s>>>(T32, ld, n, partials);
   }
   if (tau_dev) finish_sums_kernel<<<1, 256, 0, s>>>(partials, nb, 1, tau_dev);

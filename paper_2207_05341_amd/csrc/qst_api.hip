@@ -28,13 +28,15 @@ qst_status hip_fail(hipError_t e, const char* what) {
 // partials + kReduceBlocks.
 // With x0, the first POVM pass is applied to rho's tiles in the product
 // kernel and rho itself is not written.
+// planes: workspace for the bf16 planes of T (BF16 path, d >
+// kBf16SplitMaxDim), or NULL.
 hipError_t run_state_map(qst_prec prec, const void* T, int64_t ldT, void* rho, int64_t ldr, int n,
                          double* partials, double* tau_dev, void* sk, hipStream_t s, const void* f = nullptr,
-                         const Pass0Out* x0 = nullptr) {
+                         const Pass0Out* x0 = nullptr, void* planes = nullptr) {
   const bool fold = n >= 6;
-  hipError_t e = launch_tau(prec, T, ldT, n, partials, fold ? nullptr : tau_dev, s, f);
+  hipError_t e = launch_tau(prec, T, ldT, n, partials, fold ? nullptr : tau_dev, s, f, planes);
   if (e != hipSuccess) return e;
-  return launch_herk(prec, T, ldT, rho, ldr, n, fold ? partials : nullptr, tau_dev, sk, s, x0);
+  return launch_herk(prec, T, ldT, rho, ldr, n, fold ? partials : nullptr, tau_dev, sk, s, x0, planes);
 }
 
 }  // namespace
@@ -54,7 +56,8 @@ qst_status qst_state_map(int n, qst_prec prec, const void* T, int64_t ldT, void*
   if (T == rho) return fail(QST_ERR_INVALID_ARG, "rho must not alias T");
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* partials = reinterpret_cast<double*>(ws_at(ws, L.partials));
-  hipError_t e = run_state_map(prec, T, ldT, rho, ld_rho, n, partials, tau_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s);
+  hipError_t e = run_state_map(prec, T, ldT, rho, ld_rho, n, partials, tau_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s,
+                               nullptr, nullptr, L.has_planes ? ws_at(ws, L.planes) : nullptr);
   if (e != hipSuccess) return hip_fail(e, "state map");
   clear_error();
   return QST_OK;
@@ -126,7 +129,8 @@ qst_status qst_nll_backward(int n, qst_prec prec, const void* T, int64_t ldT, co
   if (recompute) {
     // rho and p are rebuilt from T here; rho lives in the G' slot.
     double* tau_ws = scalars + 1;
-    e = run_state_map(prec, T, ldT, ws_at(ws, L.rho), d, n, partials, tau_ws, L.has_sk ? ws_at(ws, L.sk) : nullptr, s);
+    e = run_state_map(prec, T, ldT, ws_at(ws, L.rho), d, n, partials, tau_ws, L.has_sk ? ws_at(ws, L.sk) : nullptr, s,
+                      nullptr, nullptr, L.has_planes ? ws_at(ws, L.planes) : nullptr);
     if (e != hipSuccess) return hip_fail(e, "state map (recompute)");
     e = launch_povm(false, prec, pl, W, tetra, ws_at(ws, L.rho), d, ws_at(ws, L.p), nullptr, nullptr,
                     ws_at(ws, L.inter0), ws_at(ws, L.inter1), s);
@@ -181,7 +185,7 @@ qst_status qst_likelihood(int n, qst_prec prec, const void* T, int64_t ldT, cons
   const bool x0 = fused && tetra && d >= 64 && pl.g[0] >= 4 && pl.g[0] <= 6;
   const Pass0Out p0{ws_at(ws, L.inter0), pl.g[0], true};
   hipError_t e = run_state_map(prec, T, ldT, rho, d, n, partials, tau_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s,
-                               fused ? f : nullptr, x0 ? &p0 : nullptr);
+                               fused ? f : nullptr, x0 ? &p0 : nullptr, L.has_planes ? ws_at(ws, L.planes) : nullptr);
   if (e != hipSuccess) return hip_fail(e, "state map");
   if (fused) {
     e = launch_povm_fused(prec, pl, W, V, tetra, rho, d, f, partials + kReduceBlocks, G, ldG, ws_at(ws, L.inter0),

@@ -268,6 +268,88 @@ struct HerkBf16Policy {
   }
 };
 
+// T T^dagger from bf16 planes of T (a re plane and an im plane, d x d
+// row-major each, g.A = the re plane, g.lda = d; written by the tau kernel):
+// no conversion inside the product and half the operand bytes of fp32 T.
+// Panels of 64 k (two MFMA K steps between barriers), fp32 accumulate.
+struct HerkBf16PlanesPolicy {
+  static constexpr int kMinWaves = 1;
+  typedef float scalar;
+  typedef f4 acc_t;
+  static constexpr int KP = 64;
+  static constexpr bool kHerk = true;
+  static constexpr bool kStreamK = false;
+  struct Smem {
+    uint16_t Ar[BM][KP + PADH], Ai[BM][KP + PADH], Br[BM][KP + PADH], Bi[BM][KP + PADH];
+  };
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+
+  static __device__ __forceinline__ void run(const GemmArgs& g, Smem& sm, int tr, int tc, int kb, int ke,
+                                             acc_t (&aR)[2][2], acc_t (&aI)[2][2]) {
+    const uint16_t* Pr = static_cast<const uint16_t*>(g.A);
+    const uint16_t* Pi = Pr + int64_t(g.d) * g.d;
+    const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int li = lane & 15, lq = lane >> 4;
+    const int row = t >> 2, kq = (t & 3) * 16;  // 64 rows x 64 k per plane, 16 k per thread
+    const int64_t oa = (R0 + row) * g.lda + kq, ob = (C0 + row) * g.lda + kq;
+    u16x8 xr[2], xi[2], yr[2], yi[2];
+#define QST_LOAD_PANEL(kp)                                                   \
+  do {                                                                       \
+    const int64_t k0_ = int64_t(kp) * KP;                                    \
+    _Pragma("unroll") for (int h = 0; h < 2; ++h) {                          \
+      xr[h] = *reinterpret_cast<const u16x8*>(Pr + oa + k0_ + 8 * h);        \
+      xi[h] = *reinterpret_cast<const u16x8*>(Pi + oa + k0_ + 8 * h);        \
+      yr[h] = *reinterpret_cast<const u16x8*>(Pr + ob + k0_ + 8 * h);        \
+      yi[h] = *reinterpret_cast<const u16x8*>(Pi + ob + k0_ + 8 * h);        \
+    }                                                                        \
+  } while (0)
+    QST_LOAD_PANEL(kb);
+    for (int kp = kb; kp < ke; ++kp) {
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        *reinterpret_cast<u16x8*>(&sm.Ar[row][kq + 8 * h]) = xr[h];
+        *reinterpret_cast<u16x8*>(&sm.Ai[row][kq + 8 * h]) = xi[h];
+        *reinterpret_cast<u16x8*>(&sm.Br[row][kq + 8 * h]) = yr[h];
+        *reinterpret_cast<u16x8*>(&sm.Bi[row][kq + 8 * h]) = yi[h];
+      }
+      __syncthreads();
+      if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
+#undef QST_LOAD_PANEL
+#pragma unroll
+      for (int ks = 0; ks < KP / 32; ++ks) {
+        u16x8 a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a_r[i] = *reinterpret_cast<const u16x8*>(&sm.Ar[wr * 32 + i * 16 + li][ks * 32 + lq * 8]);
+          a_i[i] = *reinterpret_cast<const u16x8*>(&sm.Ai[wr * 32 + i * 16 + li][ks * 32 + lq * 8]);
+          b_r[i] = *reinterpret_cast<const u16x8*>(&sm.Br[wc * 32 + i * 16 + li][ks * 32 + lq * 8]);
+          b_i[i] = *reinterpret_cast<const u16x8*>(&sm.Bi[wc * 32 + i * 16 + li][ks * 32 + lq * 8]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            aR[i][j] = mfma_bf16(a_r[i], b_r[j], aR[i][j]);
+            aI[i][j] = mfma_bf16(a_i[i], b_r[j], aI[i][j]);
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const u16x8 na = bf16_neg(a_r[i]);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            aR[i][j] = mfma_bf16(a_i[i], b_i[j], aR[i][j]);
+            aI[i][j] = mfma_bf16(na, b_i[j], aI[i][j]);
+          }
+        }
+      }
+    }
+  }
+};
+
 // Eight consecutive complex values -> their re_hi, im_hi, re_lo, im_lo
 // bf16 planes at P[plane][row][k0..k0+7] (16-byte stores).
 template <int LD>

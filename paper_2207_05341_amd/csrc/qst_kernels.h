@@ -28,9 +28,11 @@ class ProfScope {
 // tau = sum |T_ij|^2 (FP64; over bf16-rounded T for QST_BF16GEMM): the
 // kReduceBlocks partial sums, and, if tau_dev is not NULL, their total.  With
 // f (4^N reals), also the kReduceBlocks partial sums of F = sum f at
-// partials + kReduceBlocks.
+// partials + kReduceBlocks.  planes (QST_BF16GEMM with d > kBf16SplitMaxDim,
+// else ignored; may be NULL): receives bf16(T) as re and im planes (d x d
+// row-major each, 4 d^2 bytes), the operands launch_herk takes.
 hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
-                      double* tau_dev, hipStream_t s, const void* f = nullptr);
+                      double* tau_dev, hipStream_t s, const void* f = nullptr, void* planes = nullptr);
 
 // rho = T T^dagger / tau, written in full.  tau comes from tau_partials (the
 // partial sums of launch_tau; the kernel also stores the total at tau_dev)
@@ -45,9 +47,11 @@ struct Pass0Out {
   int g;
   bool tetra;  // must be true
 };
+// planes: the bf16 planes of T written by launch_tau (BF16 path, d >
+// kBf16SplitMaxDim), or NULL to round T inside the product.
 hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int64_t ldr, int n,
                        const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s,
-                       const Pass0Out* x0 = nullptr);
+                       const Pass0Out* x0 = nullptr, const void* planes = nullptr);
 
 // out = (upstream ? *upstream : 1) * 2 / *tau_dev * G T.
 hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T, int64_t ldt,

@@ -83,9 +83,15 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
     return at;
   };
   const bool sk = n >= kStreamKMinQubits;
+  const bool planes = prec == QST_BF16GEMM && d > size_t(kBf16SplitMaxDim);
+  auto take_planes = [&]() {
+    w.planes = take(2 * D * sizeof(uint16_t));
+    w.has_planes = true;
+  };
   switch (op) {
     case QST_OP_STATE_MAP:
       w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
+      if (planes) take_planes();
       if (sk) {
         w.sk = take(stream_k_partial_bytes(prec));
         w.has_sk = true;
@@ -107,6 +113,7 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
       if (recompute) {
         w.rho = w.gmat;  // rho is dead once p exists; G' reuses its storage
         w.p = take(D * rb);
+        if (planes) take_planes();
       }
       if (sk) {
         w.sk = take(stream_k_partial_bytes(prec));
@@ -121,6 +128,7 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
       if (pl.passes >= 2) w.inter0 = take(D * cb);
       if (pl.passes >= 3) w.inter1 = take(D * cb);
       if (!fused) w.p = take(D * rb);
+      if (planes) take_planes();
       if (sk) {
         w.sk = take(stream_k_partial_bytes(prec));
         w.has_sk = true;

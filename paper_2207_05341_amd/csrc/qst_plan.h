@@ -60,7 +60,9 @@ struct WsLayout {
   size_t p = 0;          // p (4^N real), recompute mode only
   size_t sk = 0;         // stream-K partial tiles (0 = not used)
   size_t fpart = 0;      // fused likelihood pass: FP64 partials [4][blocks]
+  size_t planes = 0;     // BF16 path, d > kBf16SplitMaxDim: bf16(T) as re and im planes, d x d each
   bool has_sk = false;
+  bool has_planes = false;
 };
 
 WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute);
