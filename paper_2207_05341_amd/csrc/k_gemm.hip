@@ -353,9 +353,169 @@ hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int
   return run_gemm<HerkBf16Policy>(g, s);
 }
 
+namespace {
+
+// Operand planes of the split-bf16 product, x = hi + lo with hi = bf16(x)
+// and lo = bf16(x - hi), for the real and imaginary parts of a d x d complex
+// matrix M (leading dimension ld): P[pl][d][d] with pl = re_hi, im_hi,
+// re_lo, im_lo; element (r, c) at P[pl][r d + c], or at P[pl][c d + r] with
+// TRANSPOSE (through a 64 x 64 LDS tile).  One 64 x 64 tile per workgroup;
+// each thread converts two runs of 8 consecutive elements (16-byte stores).
+template <bool TRANSPOSE>
+__global__ __launch_bounds__(256) void split_planes_kernel(const Cx<float>* __restrict__ M, int64_t ld, int d,
+                                                           uint16_t* __restrict__ P) {
+  __shared__ Cx<float> tile[TRANSPOSE ? 64 : 1][65];
+  const int tiles = d / 64;
+  const int64_t r0 = int64_t(blockIdx.x / tiles) * 64, c0 = int64_t(blockIdx.x % tiles) * 64;
+  const int64_t dd = int64_t(d) * d;
+  const int t = threadIdx.x, rr = t >> 3, cc = (t & 7) * 8;
+  auto emit = [&](const Cx<float> (&v)[8], int64_t at) {
+    float re[8], im[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      re[i] = v[i].re;
+      im[i] = v[i].im;
+    }
+    u16x8 rh, rl, ih, il;
+    bf16x8_split(re, rh, rl);
+    bf16x8_split(im, ih, il);
+    *reinterpret_cast<u16x8*>(P + at) = rh;
+    *reinterpret_cast<u16x8*>(P + dd + at) = ih;
+    *reinterpret_cast<u16x8*>(P + 2 * dd + at) = rl;
+    *reinterpret_cast<u16x8*>(P + 3 * dd + at) = il;
+  };
+  Cx<float> v[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const Cx<float>* src = M + (r0 + rr + 32 * h) * ld + c0 + cc;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[h][i] = src[i];
+  }
+  if constexpr (!TRANSPOSE) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) emit(v[h], (r0 + rr + 32 * h) * d + c0 + cc);
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) tile[rr + 32 * h][cc + i] = v[h][i];
+    __syncthreads();
+    // transposed run: column c of the tile, rows cc .. cc + 7
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = rr + 32 * h;
+      Cx<float> u[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[i] = tile[cc + i][c];
+      emit(u, (c0 + c) * d + r0 + cc);
+    }
+  }
+}
+
+// G' T on the BF16 path for d >= 1024 from the split planes (g.A: planes of
+// G', g.B: planes of T^T, both with row stride d): 128 x 128 complex output
+// tiles, 512 threads in 8 waves of 64 x 32, panels of 32 k; per panel the
+// three products hi hi + hi lo + lo hi of each real product (12 MFMAs per
+// 16 x 16 block).  Per MFMA a 128 x 128 tile moves half the operand bytes of
+// a 64 x 64 one, which is what bounds the bf16 form.  Tiles are numbered so
+// that each XCD's contiguous range of workgroups covers blocks of 4 x 8
+// tiles (4 row panels of G', 8 column panels of T).  Needs d / 128 divisible
+// by 8.
+constexpr int kWideBM = 128;
+__global__ __launch_bounds__(512) void hemm_bf16_wide_kernel(GemmArgs g) {
+  constexpr int KP = 32, LD = KP + PADH;
+  __shared__ uint16_t As[4][kWideBM][LD];  // re_hi, im_hi, re_lo, im_lo of G' rows
+  __shared__ uint16_t Bt[4][kWideBM][LD];  // the same of T columns: [n][k]
+  const uint16_t* A = static_cast<const uint16_t*>(g.A);
+  const uint16_t* B = static_cast<const uint16_t*>(g.B);
+  const int64_t dd = int64_t(g.d) * g.d;
+  const int ts = g.d / kWideBM;
+  const int lb = int(xcd_order(blockIdx.x, gridDim.x));
+  const int grp = lb / 32, within = lb % 32;
+  const int tr = (grp / (ts / 8)) * 4 + within / 8;
+  const int tc = (grp % (ts / 8)) * 8 + within % 8;
+  const int64_t R0 = int64_t(tr) * kWideBM, C0 = int64_t(tc) * kWideBM;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 2, wc = w & 3;  // rows wr * 64 .., columns wc * 32 ..
+  const int li = lane & 15, lq = lane >> 4;
+  const int row = t >> 2, kq = (t & 3) * 8;  // 128 rows x 32 k per plane, 8 k per thread
+  const int64_t oa = (R0 + row) * g.lda + kq, ob = (C0 + row) * g.ldb + kq;
+  u16x8 xa[4], xb[4];
+  f4 aR[4][2], aI[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) aR[i][j] = aI[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto load = [&](int kp) {
+    const int64_t k0 = int64_t(kp) * KP;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      xa[pl] = *reinterpret_cast<const u16x8*>(A + pl * dd + oa + k0);
+      xb[pl] = *reinterpret_cast<const u16x8*>(B + pl * dd + ob + k0);
+    }
+  };
+  const int kIters = g.d / KP;
+  load(0);
+  for (int kp = 0; kp < kIters; ++kp) {
+    __syncthreads();
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      *reinterpret_cast<u16x8*>(&As[pl][row][kq]) = xa[pl];
+      *reinterpret_cast<u16x8*>(&Bt[pl][row][kq]) = xb[pl];
+    }
+    __syncthreads();
+    if (kp + 1 < kIters) load(kp + 1);
+    u16x8 b[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) b[j][pl] = *reinterpret_cast<const u16x8*>(&Bt[pl][wc * 32 + j * 16 + li][lq * 8]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      u16x8 a[4];
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const u16x8*>(&As[pl][wr * 64 + i * 16 + li][lq * 8]);
+      const u16x8 nih = bf16_neg(a[1]), nil = bf16_neg(a[3]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // complex: re = ar br - ai bi, im = ar bi + ai br;  hi*hi, hi*lo, lo*hi
+        aR[i][j] = mfma_bf16(a[0], b[j][0], aR[i][j]);
+        aR[i][j] = mfma_bf16(nih, b[j][1], aR[i][j]);
+        aI[i][j] = mfma_bf16(a[0], b[j][1], aI[i][j]);
+        aI[i][j] = mfma_bf16(a[1], b[j][0], aI[i][j]);
+        aR[i][j] = mfma_bf16(a[0], b[j][2], aR[i][j]);
+        aR[i][j] = mfma_bf16(nih, b[j][3], aR[i][j]);
+        aI[i][j] = mfma_bf16(a[0], b[j][3], aI[i][j]);
+        aI[i][j] = mfma_bf16(a[1], b[j][2], aI[i][j]);
+        aR[i][j] = mfma_bf16(a[2], b[j][0], aR[i][j]);
+        aR[i][j] = mfma_bf16(nil, b[j][1], aR[i][j]);
+        aI[i][j] = mfma_bf16(a[2], b[j][1], aI[i][j]);
+        aI[i][j] = mfma_bf16(a[3], b[j][0], aI[i][j]);
+      }
+    }
+  }
+  double scale = 2.0 / *g.tau;
+  if (g.up) scale *= *g.up;
+  const float sc = float(scale);
+  Cx<float>* C = static_cast<Cx<float>*>(g.C);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t col = C0 + wc * 32 + j * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = R0 + wr * 64 + i * 16 + 4 * lq + v;
+        C[r * g.ldc + col] = Cx<float>{aR[i][j][v] * sc, aI[i][j][v] * sc};
+      }
+    }
+}
+
+}  // namespace
+
 hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T, int64_t ldt, void* out,
                        int64_t ldo, int n, const double* tau_dev, const double* upstream_dev,
-                       void* sk_partial, hipStream_t s) {
+                       void* sk_partial, hipStream_t s, void* planes) {
   const int d = 1 << n;
   ProfScope prof(d < BM ? "hemm_small" : (prec == QST_F64 ? "hemm_f64" : prec == QST_F32 ? "hemm_f32" : "hemm_bf16x3"), s);
   if (d < BM) {
@@ -393,6 +553,19 @@ hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T,
   g.tau_out = nullptr;
   if (prec == QST_F64) return run_gemm<CxPolicy<double, false>>(g, s);
   if (prec == QST_F32) return run_gemm<CxPolicy<float, false>>(g, s);
+  if (planes && d % (8 * kWideBM) == 0) {
+    uint16_t* pg = static_cast<uint16_t*>(planes);
+    uint16_t* pt = pg + 4 * int64_t(d) * d;
+    split_planes_kernel<false><<<unsigned(tiles * tiles), 256, 0, s>>>(static_cast<const Cx<float>*>(G), ldg, d, pg);
+    split_planes_kernel<true><<<unsigned(tiles * tiles), 256, 0, s>>>(static_cast<const Cx<float>*>(T), ldt, d, pt);
+    g.A = pg;
+    g.lda = d;
+    g.B = pt;
+    g.ldb = d;
+    const int wt = d / kWideBM;
+    hemm_bf16_wide_kernel<<<unsigned(wt * wt), 512, 0, s>>>(g);
+    return hipGetLastError();
+  }
   return run_gemm<HemmBf16x3Policy>(g, s);
 }
 

@@ -147,7 +147,8 @@ qst_status qst_nll_backward(int n, qst_prec prec, const void* T, int64_t ldT, co
   e = launch_povm(true, prec, pl, V, tetra, G, d, const_cast<void*>(p), f, F_dev, ws_at(ws, L.inter0),
                   ws_at(ws, L.inter1), s);
   if (e != hipSuccess) return hip_fail(e, "adjoint POVM map");
-  e = launch_hemm(prec, G, d, T, ldT, gradT, ldG, n, tau_dev, upstream_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s);
+  e = launch_hemm(prec, G, d, T, ldT, gradT, ldG, n, tau_dev, upstream_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s,
+                  L.has_planes ? ws_at(ws, L.planes) : nullptr);
   if (e != hipSuccess) return hip_fail(e, "G' T");
   clear_error();
   return QST_OK;
@@ -221,7 +222,8 @@ qst_status qst_grad_product(int n, qst_prec prec, const void* G, int64_t ldG, co
   const WsLayout L = workspace_layout(n, prec, QST_OP_GRAD_PRODUCT, false);
   if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
   hipError_t e = launch_hemm(prec, G, ldG, T, ldT, gradT, ld_grad, n, tau_dev, upstream_dev,
-                             L.has_sk ? ws_at(ws, L.sk) : nullptr, static_cast<hipStream_t>(stream));
+                             L.has_sk ? ws_at(ws, L.sk) : nullptr, static_cast<hipStream_t>(stream),
+                             L.has_planes ? ws_at(ws, L.planes) : nullptr);
   if (e != hipSuccess) return hip_fail(e, "G' T");
   clear_error();
   return QST_OK;

@@ -53,10 +53,12 @@ hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int
                        const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s,
                        const Pass0Out* x0 = nullptr, const void* planes = nullptr);
 
-// out = (upstream ? *upstream : 1) * 2 / *tau_dev * G T.
+// out = (upstream ? *upstream : 1) * 2 / *tau_dev * G T.  planes (BF16 path,
+// used for d >= 1024; may be NULL): 16 d^2 bytes for the split-bf16 planes
+// of G and of T^T, which the 128 x 128-tile product reads.
 hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T, int64_t ldt,
                        void* out, int64_t ldo, int n, const double* tau_dev,
-                       const double* upstream_dev, void* sk_partial, hipStream_t s);
+                       const double* upstream_dev, void* sk_partial, hipStream_t s, void* planes = nullptr);
 
 // Forward (adjoint=false): mat = rho (lower triangle read) -> pvec.
 // Adjoint (adjoint=true): g' = F - f/p from (pvec, fvec, F_dev) -> mat = G'

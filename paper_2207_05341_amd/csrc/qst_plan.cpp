@@ -84,14 +84,15 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
   };
   const bool sk = n >= kStreamKMinQubits;
   const bool planes = prec == QST_BF16GEMM && d > size_t(kBf16SplitMaxDim);
-  auto take_planes = [&]() {
-    w.planes = take(2 * D * sizeof(uint16_t));
+  const bool hemm_planes = prec == QST_BF16GEMM && d >= 1024;
+  auto take_planes = [&](size_t count) {  // count planes of d x d bf16
+    w.planes = take(count * D * sizeof(uint16_t));
     w.has_planes = true;
   };
   switch (op) {
     case QST_OP_STATE_MAP:
       w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
-      if (planes) take_planes();
+      if (planes) take_planes(2);
       if (sk) {
         w.sk = take(stream_k_partial_bytes(prec));
         w.has_sk = true;
@@ -113,8 +114,11 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
       if (recompute) {
         w.rho = w.gmat;  // rho is dead once p exists; G' reuses its storage
         w.p = take(D * rb);
-        if (planes) take_planes();
       }
+      if (hemm_planes)
+        take_planes(8);  // also holds T's two planes of the recomputed state map
+      else if (recompute && planes)
+        take_planes(2);
       if (sk) {
         w.sk = take(stream_k_partial_bytes(prec));
         w.has_sk = true;
@@ -128,7 +132,7 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
       if (pl.passes >= 2) w.inter0 = take(D * cb);
       if (pl.passes >= 3) w.inter1 = take(D * cb);
       if (!fused) w.p = take(D * rb);
-      if (planes) take_planes();
+      if (planes) take_planes(2);
       if (sk) {
         w.sk = take(stream_k_partial_bytes(prec));
         w.has_sk = true;
@@ -136,6 +140,7 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
       break;
     }
     case QST_OP_GRAD_PRODUCT:
+      if (hemm_planes) take_planes(8);
       if (sk) {
         w.sk = take(stream_k_partial_bytes(prec));
         w.has_sk = true;

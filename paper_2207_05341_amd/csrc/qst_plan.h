@@ -60,7 +60,8 @@ struct WsLayout {
   size_t p = 0;          // p (4^N real), recompute mode only
   size_t sk = 0;         // stream-K partial tiles (0 = not used)
   size_t fpart = 0;      // fused likelihood pass: FP64 partials [4][blocks]
-  size_t planes = 0;     // BF16 path, d > kBf16SplitMaxDim: bf16(T) as re and im planes, d x d each
+  size_t planes = 0;     // BF16 path: bf16(T) as re and im planes for T T^dagger (d > kBf16SplitMaxDim,
+                         // 4 d^2 bytes); split planes of G' and T^T for G' T (d >= 1024, 16 d^2 bytes)
   bool has_sk = false;
   bool has_planes = false;
 };

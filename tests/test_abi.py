@@ -67,8 +67,15 @@ def test_workspace_sizes(L):
             # likelihood keeps rho and the POVM intermediates in the workspace
             cb = 16 if prec == 0 else 8
             assert ws(n, prec, lib_mod.QST_OP_LIKELIHOOD) >= cb * 4 ** n + ws(n, prec, lib_mod.QST_OP_POVM_PROBS)
-            # the gradient product needs only stream-K partials (N >= 10)
-            assert (ws(n, prec, lib_mod.QST_OP_GRAD_PRODUCT) > 0) == (n >= 10)
+            # the gradient product needs stream-K partials (N >= 10) and, on
+            # the BF16 path, the split planes of G' and T^T (16 d^2 bytes)
+            gp = ws(n, prec, lib_mod.QST_OP_GRAD_PRODUCT)
+            assert (gp > 0) == (n >= 10)
+            if prec == 2 and n >= 10:
+                assert gp >= 16 * 4 ** n
+            # BF16 state map from N = 8: bf16 planes of T (4 d^2 bytes)
+            if prec == 2 and n >= 8:
+                assert ws(n, prec, lib_mod.QST_OP_STATE_MAP) >= 4 * 4 ** n
     assert ws(5, 0, 6) == 0
 
 
