@@ -414,16 +414,16 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const Cx<float>* __re
 
 // G' T on the BF16 path for d >= 1024 from the split planes (g.A: planes of
 // G', g.B: planes of T^T, both with row stride d): 128 x 128 complex output
-// tiles, 512 threads in 8 waves of 64 x 32, panels of 32 k; per panel the
-// three products hi hi + hi lo + lo hi of each real product (12 MFMAs per
-// 16 x 16 block).  Per MFMA a 128 x 128 tile moves half the operand bytes of
+// tiles, 512 threads in 8 waves of 64 x 32, panels of 64 k (147 KB of LDS,
+// one workgroup per CU); per K step of 32 the three products hi hi + hi lo +
+// lo hi of each real product (12 MFMAs per 16 x 16 block).  Per MFMA a 128 x 128 tile moves half the operand bytes of
 // a 64 x 64 one, which is what bounds the bf16 form.  Tiles are numbered so
 // that each XCD's contiguous range of workgroups covers blocks of 4 x 8
 // tiles (4 row panels of G', 8 column panels of T).  Needs d / 128 divisible
 // by 8.
 constexpr int kWideBM = 128;
 __global__ __launch_bounds__(512) void hemm_bf16_wide_kernel(GemmArgs g) {
-  constexpr int KP = 32, LD = KP + PADH;
+  constexpr int KP = 64, LD = KP + PADH;   // two MFMA K steps per panel
   __shared__ uint16_t As[4][kWideBM][LD];  // re_hi, im_hi, re_lo, im_lo of G' rows
   __shared__ uint16_t Bt[4][kWideBM][LD];  // the same of T columns: [n][k]
   const uint16_t* A = static_cast<const uint16_t*>(g.A);
@@ -438,9 +438,9 @@ __global__ __launch_bounds__(512) void hemm_bf16_wide_kernel(GemmArgs g) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 2, wc = w & 3;  // rows wr * 64 .., columns wc * 32 ..
   const int li = lane & 15, lq = lane >> 4;
-  const int row = t >> 2, kq = (t & 3) * 8;  // 128 rows x 32 k per plane, 8 k per thread
+  const int row = t >> 2, kq = (t & 3) * 16;  // 128 rows x 64 k per plane, 16 k per thread
   const int64_t oa = (R0 + row) * g.lda + kq, ob = (C0 + row) * g.ldb + kq;
-  u16x8 xa[4], xb[4];
+  u16x8 xa[4][2], xb[4][2];
   f4 aR[4][2], aI[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -449,48 +449,56 @@ __global__ __launch_bounds__(512) void hemm_bf16_wide_kernel(GemmArgs g) {
   auto load = [&](int kp) {
     const int64_t k0 = int64_t(kp) * KP;
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) {
-      xa[pl] = *reinterpret_cast<const u16x8*>(A + pl * dd + oa + k0);
-      xb[pl] = *reinterpret_cast<const u16x8*>(B + pl * dd + ob + k0);
-    }
+    for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        xa[pl][h] = *reinterpret_cast<const u16x8*>(A + pl * dd + oa + k0 + 8 * h);
+        xb[pl][h] = *reinterpret_cast<const u16x8*>(B + pl * dd + ob + k0 + 8 * h);
+      }
   };
   const int kIters = g.d / KP;
   load(0);
   for (int kp = 0; kp < kIters; ++kp) {
     __syncthreads();
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) {
-      *reinterpret_cast<u16x8*>(&As[pl][row][kq]) = xa[pl];
-      *reinterpret_cast<u16x8*>(&Bt[pl][row][kq]) = xb[pl];
-    }
+    for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        *reinterpret_cast<u16x8*>(&As[pl][row][kq + 8 * h]) = xa[pl][h];
+        *reinterpret_cast<u16x8*>(&Bt[pl][row][kq + 8 * h]) = xb[pl][h];
+      }
     __syncthreads();
     if (kp + 1 < kIters) load(kp + 1);
-    u16x8 b[2][4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int ks = 0; ks < KP / 32; ++ks) {
+      const int kk = ks * 32 + lq * 8;
+      u16x8 b[2][4];
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) b[j][pl] = *reinterpret_cast<const u16x8*>(&Bt[pl][wc * 32 + j * 16 + li][lq * 8]);
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      u16x8 a[4];
+        for (int pl = 0; pl < 4; ++pl) b[j][pl] = *reinterpret_cast<const u16x8*>(&Bt[pl][wc * 32 + j * 16 + li][kk]);
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const u16x8*>(&As[pl][wr * 64 + i * 16 + li][lq * 8]);
-      const u16x8 nih = bf16_neg(a[1]), nil = bf16_neg(a[3]);
+      for (int i = 0; i < 4; ++i) {
+        u16x8 a[4];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        // complex: re = ar br - ai bi, im = ar bi + ai br;  hi*hi, hi*lo, lo*hi
-        aR[i][j] = mfma_bf16(a[0], b[j][0], aR[i][j]);
-        aR[i][j] = mfma_bf16(nih, b[j][1], aR[i][j]);
-        aI[i][j] = mfma_bf16(a[0], b[j][1], aI[i][j]);
-        aI[i][j] = mfma_bf16(a[1], b[j][0], aI[i][j]);
-        aR[i][j] = mfma_bf16(a[0], b[j][2], aR[i][j]);
-        aR[i][j] = mfma_bf16(nih, b[j][3], aR[i][j]);
-        aI[i][j] = mfma_bf16(a[0], b[j][3], aI[i][j]);
-        aI[i][j] = mfma_bf16(a[1], b[j][2], aI[i][j]);
-        aR[i][j] = mfma_bf16(a[2], b[j][0], aR[i][j]);
-        aR[i][j] = mfma_bf16(nil, b[j][1], aR[i][j]);
-        aI[i][j] = mfma_bf16(a[2], b[j][1], aI[i][j]);
-        aI[i][j] = mfma_bf16(a[3], b[j][0], aI[i][j]);
+        for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const u16x8*>(&As[pl][wr * 64 + i * 16 + li][kk]);
+        const u16x8 nih = bf16_neg(a[1]), nil = bf16_neg(a[3]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          // complex: re = ar br - ai bi, im = ar bi + ai br;  hi*hi, hi*lo, lo*hi
+          aR[i][j] = mfma_bf16(a[0], b[j][0], aR[i][j]);
+          aR[i][j] = mfma_bf16(nih, b[j][1], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[0], b[j][1], aI[i][j]);
+          aI[i][j] = mfma_bf16(a[1], b[j][0], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[0], b[j][2], aR[i][j]);
+          aR[i][j] = mfma_bf16(nih, b[j][3], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[0], b[j][3], aI[i][j]);
+          aI[i][j] = mfma_bf16(a[1], b[j][2], aI[i][j]);
+          aR[i][j] = mfma_bf16(a[2], b[j][0], aR[i][j]);
+          aR[i][j] = mfma_bf16(nil, b[j][1], aR[i][j]);
+          aI[i][j] = mfma_bf16(a[2], b[j][1], aI[i][j]);
+          aI[i][j] = mfma_bf16(a[3], b[j][0], aI[i][j]);
+        }
       }
     }
   }
