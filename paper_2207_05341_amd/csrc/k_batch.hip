@@ -79,6 +79,12 @@ __device__ double block_sum_bcast(double v, double* red4, double* slot) {
   return r;
 }
 
+// Product tiles of the batched kernel.
+template <typename R>
+using BatchHerk = gemm::CxPolicy<R, true>;
+template <typename R>
+using BatchHemm = gemm::CxPolicy<R, false>;
+
 template <class PH, class PM, typename R, bool TETRA, bool BF16>
 __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
   // One 64 KiB LDS pool serves, one stage at a time, the product panels, the
@@ -111,21 +117,33 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
     Cx<R>* grad = static_cast<Cx<R>*>(b.grad_all) + it.t_off;
 
     // 1. tau = sum |T|^2 (FP64, over bf16-rounded T for the BF16 path)
+    // (kBatch loads per thread in flight, unconditional: indices past the
+    // end are clamped and their values dropped)
+    constexpr int kBatch = 4;
     double acc = 0.0;
-    for (int64_t e = t; e < D; e += 256) {
-      const Cx<R> v = T[e];
-      double x = double(v.re), y = double(v.im);
-      if constexpr (BF16) {
-        const float hr = bf16_value(float(v.re)), hi = bf16_value(float(v.im));
-        if (d <= kBf16SplitMaxDim) {  // split bf16 hi + lo
-          x = double(hr + bf16_value(float(v.re) - hr));
-          y = double(hi + bf16_value(float(v.im) - hi));
-        } else {
-          x = double(hr);
-          y = double(hi);
-        }
+    for (int64_t e0 = 0; e0 < D; e0 += kBatch * 256) {
+      Cx<R> v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int64_t e = e0 + u * 256 + t;
+        v[u] = T[e < D ? e : D - 1];
       }
-      acc += x * x + y * y;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        if (e0 + u * 256 + t >= D) continue;
+        double x = double(v[u].re), y = double(v[u].im);
+        if constexpr (BF16) {
+          const float hr = bf16_value(float(v[u].re)), hi = bf16_value(float(v[u].im));
+          if (d <= kBf16SplitMaxDim) {  // split bf16 hi + lo
+            x = double(hr + bf16_value(float(v[u].re) - hr));
+            y = double(hi + bf16_value(float(v[u].im) - hi));
+          } else {
+            x = double(hr);
+            y = double(hi);
+          }
+        }
+        acc += x * x + y * y;
+      }
     }
     const double tau = block_sum_bcast(acc, red, slotp);
 
@@ -192,8 +210,9 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
     }
     __syncthreads();
 
-    // 3. POVM map: rho -> p
+    // 3. POVM map: rho -> p, as many pass blocks at a time as the pool holds
     Cx<R>* buf = reinterpret_cast<Cx<R>*>(pool);
+    constexpr int kPoolValues = int(sizeof(pool) / sizeof(Cx<R>));
     const int P = b.plan.passes[n];
     for (int pj = 0; pj < P; ++pj) {
       PassArgs a{};
@@ -208,25 +227,39 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
       const int Up = a.U - a.g;
       const int64_t side = int64_t(1) << Up;
       const int64_t blocks = side * (side + 1) / 2 * ((int64_t(1) << (2 * (n - a.U))) / a.J);
-      for (int64_t vb = 0; vb < blocks; ++vb) {
-        if (ms && ps) generic_pass::fwd_pass_body<R, TETRA, true, true>(a, b.W, vb, buf);
-        else if (ms) generic_pass::fwd_pass_body<R, TETRA, true, false>(a, b.W, vb, buf);
-        else if (ps) generic_pass::fwd_pass_body<R, TETRA, false, true>(a, b.W, vb, buf);
-        else generic_pass::fwd_pass_body<R, TETRA, false, false>(a, b.W, vb, buf);
+      const int per = kPoolValues / ((1 << (2 * a.g)) * a.J);  // blocks the LDS pool holds
+      for (int64_t vb = 0; vb < blocks; vb += per) {
+        const int nb = int(blocks - vb < per ? blocks - vb : per);
+        if (ms && ps) generic_pass::fwd_pass_body<R, TETRA, true, true>(a, b.W, vb, buf, nb);
+        else if (ms) generic_pass::fwd_pass_body<R, TETRA, true, false>(a, b.W, vb, buf, nb);
+        else if (ps) generic_pass::fwd_pass_body<R, TETRA, false, true>(a, b.W, vb, buf, nb);
+        else generic_pass::fwd_pass_body<R, TETRA, false, false>(a, b.W, vb, buf, nb);
         __syncthreads();
       }
     }
 
     // 4. L, F (FP64), counters
     double L = 0.0, F = 0.0, bad0 = 0.0, bad1 = 0.0;
-    for (int64_t k = t; k < D; k += 256) {
-      const double fk = double(f[k]), pk = double(pvec[k]);
-      F += fk;
-      if (fk != 0.0) {
-        if (pk > 0.0) L -= fk * ln_prob(pvec[k]);
-        else bad0 += 1.0;
+    for (int64_t k0 = 0; k0 < D; k0 += kBatch * 256) {
+      R fv[kBatch], pv[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int64_t k = k0 + u * 256 + t;
+        const int64_t kc = k < D ? k : D - 1;
+        fv[u] = f[kc];
+        pv[u] = pvec[kc];
       }
-      if (pk != pk || fk != fk) bad1 += 1.0;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        if (k0 + u * 256 + t >= D) continue;
+        const double fk = double(fv[u]), pk = double(pv[u]);
+        F += fk;
+        if (fk != 0.0) {
+          if (pk > 0.0) L -= fk * ln_prob(pv[u]);
+          else bad0 += 1.0;
+        }
+        if (pk != pk || fk != fk) bad1 += 1.0;
+      }
     }
     L = block_sum_bcast(L, red, slotp);
     F = block_sum_bcast(F, red, slotp);
@@ -263,11 +296,13 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
       const int Up = a.U - a.g;
       const int64_t side = int64_t(1) << Up;
       const int64_t blocks = side * (side + 1) / 2 * ((int64_t(1) << (2 * (n - a.U))) / a.J);
-      for (int64_t vb = 0; vb < blocks; ++vb) {
-        if (ms && ps) generic_pass::adj_pass_body<R, TETRA, true, true>(a, b.V, vb, buf);
-        else if (ms) generic_pass::adj_pass_body<R, TETRA, true, false>(a, b.V, vb, buf);
-        else if (ps) generic_pass::adj_pass_body<R, TETRA, false, true>(a, b.V, vb, buf);
-        else generic_pass::adj_pass_body<R, TETRA, false, false>(a, b.V, vb, buf);
+      const int per = kPoolValues / ((1 << (2 * a.g)) * a.J);
+      for (int64_t vb = 0; vb < blocks; vb += per) {
+        const int nb = int(blocks - vb < per ? blocks - vb : per);
+        if (ms && ps) generic_pass::adj_pass_body<R, TETRA, true, true>(a, b.V, vb, buf, nb);
+        else if (ms) generic_pass::adj_pass_body<R, TETRA, true, false>(a, b.V, vb, buf, nb);
+        else if (ps) generic_pass::adj_pass_body<R, TETRA, false, true>(a, b.V, vb, buf, nb);
+        else generic_pass::adj_pass_body<R, TETRA, false, false>(a, b.V, vb, buf, nb);
         __syncthreads();
       }
     }
@@ -323,14 +358,14 @@ template <bool TETRA>
 struct BatchKernelOf<double, TETRA, false> {
   static void* fn() {
     return reinterpret_cast<void*>(
-        &batch_kernel<gemm::CxPolicy<double, true>, gemm::CxPolicy<double, false>, double, TETRA, false>);
+        &batch_kernel<BatchHerk<double>, BatchHemm<double>, double, TETRA, false>);
   }
 };
 template <bool TETRA>
 struct BatchKernelOf<float, TETRA, false> {
   static void* fn() {
     return reinterpret_cast<void*>(
-        &batch_kernel<gemm::CxPolicy<float, true>, gemm::CxPolicy<float, false>, float, TETRA, false>);
+        &batch_kernel<BatchHerk<float>, BatchHemm<float>, float, TETRA, false>);
   }
 };
 template <bool TETRA>
@@ -350,8 +385,8 @@ hipError_t launch_batch_t(bool tetra, const BatchArgs& a, int grid, hipStream_t 
 
 hipError_t launch_batch_kernel(qst_prec prec, bool tetra, const BatchArgs& a, int grid, hipStream_t s) {
   using namespace gemm;
-  if (prec == QST_F64) return launch_batch_t<CxPolicy<double, true>, CxPolicy<double, false>, double, false>(tetra, a, grid, s);
-  if (prec == QST_F32) return launch_batch_t<CxPolicy<float, true>, CxPolicy<float, false>, float, false>(tetra, a, grid, s);
+  if (prec == QST_F64) return launch_batch_t<BatchHerk<double>, BatchHemm<double>, double, false>(tetra, a, grid, s);
+  if (prec == QST_F32) return launch_batch_t<BatchHerk<float>, BatchHemm<float>, float, false>(tetra, a, grid, s);
   return launch_batch_t<HerkBf16Policy, HemmBf16x3Policy, float, true>(tetra, a, grid, s);
 }
 

@@ -27,14 +27,20 @@ __device__ __forceinline__ void deinterleave(int k, int g, int& r, int& c) {
   }
 }
 
-// In-place contraction of the g qubit axes held in LDS.
+// In-place contraction of the g qubit axes held in LDS, for nb consecutive
+// blocks of 4^g * J values each.
 template <typename R, bool ADJ, bool TETRA>
-__device__ __forceinline__ void contract_group(Cx<R>* buf, int g, int J, const ModeMatrix& A) {
-  const int groups = (1 << (2 * (g - 1))) * J;
+__device__ __forceinline__ void contract_group(Cx<R>* buf, int g, int J, const ModeMatrix& A, int nb = 1) {
+  // every extent is a power of two: divisions are shifts
+  const int lgJ = __builtin_ctz(unsigned(J));
+  const int lgP = 2 * (g - 1) + lgJ;  // groups of four per block
+  const int groups = nb << lgP;
   for (int b = 0; b < g; ++b) {
-    for (int h = threadIdx.x; h < groups; h += blockDim.x) {
-      const int j = h % J;
-      const int rc = h / J;
+    for (int h0 = threadIdx.x; h0 < groups; h0 += blockDim.x) {
+      Cx<R>* blk = buf + ((h0 >> lgP) << (lgP + 2));
+      const int h = h0 & ((1 << lgP) - 1);
+      const int j = h & (J - 1);
+      const int rc = h >> lgJ;
       const int c0 = ins0(rc & ((1 << (g - 1)) - 1), b);
       const int r0 = ins0(rc >> (g - 1), b);
       int pos[4];
@@ -45,57 +51,98 @@ __device__ __forceinline__ void contract_group(Cx<R>* buf, int g, int J, const M
       }
       Cx<R> x[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) x[m] = buf[pos[m]];
+      for (int m = 0; m < 4; ++m) x[m] = blk[pos[m]];
       apply4<R, ADJ, TETRA>(x, A);
 #pragma unroll
-      for (int m = 0; m < 4; ++m) buf[pos[m]] = x[m];
+      for (int m = 0; m < 4; ++m) blk[pos[m]] = x[m];
     }
     __syncthreads();
   }
 }
 
-// One workgroup's share (virtual block bid) of a forward pass; buf holds
-// 4^g * J complex values of LDS.
+// Block bid of a pass: its (Rhi, Chi) tile pair and first outcome chunk.
+// Pair indices below 2^22 use a single-precision square root (exact after
+// the integer corrections), larger ones the general decode.
+// lgC = log2 of the chunks per pair, lgJ = log2 J.
+__device__ __forceinline__ void block_coords(int64_t bid, int lgC, int lgJ, int& Rhi, int& Chi, int64_t& kd0) {
+  const int64_t pr = bid >> lgC;
+  if (pr < (int64_t(1) << 22)) {
+    const int q = int(pr);
+    int r = int((sqrtf(8.0f * float(q) + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > q) --r;
+    while ((r + 1) * (r + 2) / 2 <= q) ++r;
+    Rhi = r;
+    Chi = q - r * (r + 1) / 2;
+  } else {
+    tri_decode(pr, Rhi, Chi);
+  }
+  kd0 = (bid & ((int64_t(1) << lgC) - 1)) << lgJ;
+}
+
+// Element loops load kLoadBatch values per thread before storing any, so
+// that that many memory round trips overlap (one workgroup alone on a CU
+// has nothing else to hide them behind).  The loads are unconditional: an
+// index past the end is clamped to the last element and its value dropped
+// (a load under a branch is waited for where the branch rejoins).
+constexpr int kLoadBatch = 4;
+
+// One workgroup's share of a forward pass: the nb consecutive virtual
+// blocks bid0 .. bid0 + nb - 1; buf holds nb * 4^g * J complex values of
+// LDS.
 template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
-__device__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid, Cx<R>* buf) {
+__device__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
   const int g = a.g, J = a.J, U = a.U, n = a.n;
   const int Up = U - g;
   const int64_t kd = int64_t(1) << (2 * (n - U));
-  const int64_t nchunks = kd / J;
-  const int64_t ch = bid % nchunks;
-  int Rhi, Chi;
-  tri_decode(bid / nchunks, Rhi, Chi);
-  const int64_t kd0 = ch * J;
   const int tile = 1 << (2 * g);
   const int elems = tile * J;
   const int gm = (1 << g) - 1;
+  // every extent is a power of two: divisions are shifts
+  const int lgJ = __builtin_ctz(unsigned(J));
+  const int lgE = 2 * g + lgJ;
+  const int lgC = 2 * (n - U) - lgJ;  // chunks of J outcome digits per pair
 
   const Cx<R>* in = static_cast<const Cx<R>*>(a.in);
-  for (int e = threadIdx.x; e < elems; e += blockDim.x) {
-    const int j = e % J;
-    const int rc = e / J;
-    const int c = rc & gm, r = rc >> g;
-    const int64_t Rr = (int64_t(Rhi) << g) | r, Cr = (int64_t(Chi) << g) | c;
-    const bool mirror = Rr < Cr;
-    const int64_t rr = mirror ? Cr : Rr, cc = mirror ? Rr : Cr;
-    Cx<R> v;
-    if constexpr (MATSIDE) {
-      v = in[rr * a.ld + cc];
-    } else {
-      v = in[((rr << U) | cc) * kd + kd0 + j];
+  const int total = elems * nb;
+  for (int base = 0; base < total; base += kLoadBatch * int(blockDim.x)) {
+    R vr[kLoadBatch], vi[kLoadBatch];  // scalar arrays stay in registers
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e0 = base + u * int(blockDim.x) + int(threadIdx.x);
+      const int ec = e0 < total ? e0 : total - 1;
+      const int e = ec & (elems - 1);
+      int Rhi, Chi;
+      int64_t kd0;
+      block_coords(bid0 + (ec >> lgE), lgC, lgJ, Rhi, Chi, kd0);
+      const int j = e & (J - 1);
+      const int rc = e >> lgJ;
+      const int c = rc & gm, r = rc >> g;
+      const int64_t Rr = (int64_t(Rhi) << g) | r, Cr = (int64_t(Chi) << g) | c;
+      const bool mirror = Rr < Cr;
+      const int64_t rr = mirror ? Cr : Rr, cc = mirror ? Rr : Cr;
+      const Cx<R> v = MATSIDE ? in[rr * a.ld + cc] : in[((rr << U) | cc) * kd + kd0 + j];
+      vr[u] = v.re;
+      vi[u] = mirror ? -v.im : v.im;
     }
-    if (mirror) v.im = -v.im;
-    buf[e] = v;
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e0 = base + u * int(blockDim.x) + int(threadIdx.x);
+      if (e0 < total) buf[e0] = Cx<R>{vr[u], vi[u]};
+    }
   }
   __syncthreads();
-  contract_group<R, false, TETRA>(buf, g, J, A);
+  contract_group<R, false, TETRA>(buf, g, J, A, nb);
 
-  for (int e = threadIdx.x; e < elems; e += blockDim.x) {
-    const int j = e % J;
-    const int kg = e / J;
+  for (int e0 = threadIdx.x; e0 < elems * nb; e0 += blockDim.x) {
+    const int e = e0 & (elems - 1);
+    int Rhi, Chi;
+    int64_t kd0;
+    block_coords(bid0 + (e0 >> lgE), lgC, lgJ, Rhi, Chi, kd0);
+    const int j = e & (J - 1);
+    const int kg = e >> lgJ;
     int r, c;
     deinterleave(kg, g, r, c);
-    const Cx<R> v = buf[((r << g) | c) * J + j];
+    const Cx<R> v = buf[(e0 - e) + ((r << g) | c) * J + j];
     if constexpr (PSIDE) {
       static_cast<R*>(a.out)[int64_t(kg) * kd + kd0 + j] = v.re;
     } else {
@@ -105,50 +152,74 @@ __device__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
   }
 }
 
-// One workgroup's share (virtual block bid) of an adjoint pass.
+// One workgroup's share of an adjoint pass: the nb consecutive virtual
+// blocks bid0 .. bid0 + nb - 1 (buf as for the forward pass).
 template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
-__device__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid, Cx<R>* buf) {
+__device__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
   const int g = a.g, J = a.J, U = a.U, n = a.n;
   const int Up = U - g;
   const int64_t kd = int64_t(1) << (2 * (n - U));
-  const int64_t nchunks = kd / J;
-  const int64_t ch = bid % nchunks;
-  int Rhi, Chi;
-  tri_decode(bid / nchunks, Rhi, Chi);
-  const int64_t kd0 = ch * J;
   const int tile = 1 << (2 * g);
   const int elems = tile * J;
   const int gm = (1 << g) - 1;
+  // every extent is a power of two: divisions are shifts
+  const int lgJ = __builtin_ctz(unsigned(J));
+  const int lgE = 2 * g + lgJ;
+  const int lgC = 2 * (n - U) - lgJ;  // chunks of J outcome digits per pair
 
   double F = 0.0;
   if constexpr (PSIDE) F = *a.F;
-  for (int e = threadIdx.x; e < elems; e += blockDim.x) {
-    const int j = e % J;
-    const int kg = e / J;
-    int r, c;
-    deinterleave(kg, g, r, c);
-    Cx<R> v;
-    if constexpr (PSIDE) {
-      // cotangent g'_k = F - f_k / p_k (F where f_k = 0)
-      const int64_t k = int64_t(kg) * kd + kd0 + j;
-      v = {cotangent(F, static_cast<const R*>(a.f)[k], static_cast<const R*>(a.p)[k]), R(0)};
-    } else {
-      const int64_t base = ((int64_t(Rhi) << Up) | Chi) * (kd * tile);
-      v = static_cast<const Cx<R>*>(a.in)[base + int64_t(kg) * kd + kd0 + j];
+  const int total = elems * nb;
+  for (int base0 = 0; base0 < total; base0 += kLoadBatch * int(blockDim.x)) {
+    R vr[kLoadBatch], vi[kLoadBatch];  // PSIDE: f_k and p_k
+    int dst[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e0 = base0 + u * int(blockDim.x) + int(threadIdx.x);
+      const int ec = e0 < total ? e0 : total - 1;
+      const int e = ec & (elems - 1);
+      int Rhi, Chi;
+      int64_t kd0;
+      block_coords(bid0 + (ec >> lgE), lgC, lgJ, Rhi, Chi, kd0);
+      const int j = e & (J - 1);
+      const int kg = e >> lgJ;
+      int r, c;
+      deinterleave(kg, g, r, c);
+      dst[u] = e0 < total ? (ec - e) + ((r << g) | c) * J + j : -1;
+      if constexpr (PSIDE) {
+        const int64_t k = int64_t(kg) * kd + kd0 + j;
+        vr[u] = static_cast<const R*>(a.f)[k];
+        vi[u] = static_cast<const R*>(a.p)[k];
+      } else {
+        const int64_t base = ((int64_t(Rhi) << Up) | Chi) * (kd * tile);
+        const Cx<R> v = static_cast<const Cx<R>*>(a.in)[base + int64_t(kg) * kd + kd0 + j];
+        vr[u] = v.re;
+        vi[u] = v.im;
+      }
     }
-    buf[((r << g) | c) * J + j] = v;
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      if (dst[u] < 0) continue;
+      // cotangent g'_k = F - f_k / p_k (F where f_k = 0)
+      if constexpr (PSIDE) buf[dst[u]] = Cx<R>{cotangent(F, vr[u], vi[u]), R(0)};
+      else buf[dst[u]] = Cx<R>{vr[u], vi[u]};
+    }
   }
   __syncthreads();
-  contract_group<R, true, TETRA>(buf, g, J, A);
+  contract_group<R, true, TETRA>(buf, g, J, A, nb);
 
   Cx<R>* out = static_cast<Cx<R>*>(a.out);
-  for (int e = threadIdx.x; e < elems; e += blockDim.x) {
-    const int j = e % J;
-    const int rc = e / J;
+  for (int e0 = threadIdx.x; e0 < elems * nb; e0 += blockDim.x) {
+    const int e = e0 & (elems - 1);
+    int Rhi, Chi;
+    int64_t kd0;
+    block_coords(bid0 + (e0 >> lgE), lgC, lgJ, Rhi, Chi, kd0);
+    const int j = e & (J - 1);
+    const int rc = e >> lgJ;
     const int c = rc & gm, r = rc >> g;
     const int64_t Rr = (int64_t(Rhi) << g) | r, Cr = (int64_t(Chi) << g) | c;
     if (Rr < Cr) continue;  // upper triangle: the conjugate of a stored entry
-    const Cx<R> v = buf[e];
+    const Cx<R> v = buf[e0];
     if constexpr (MATSIDE) {
       out[Rr * a.ld + Cr] = v;
       if (Rr != Cr) out[Cr * a.ld + Rr] = Cx<R>{v.re, -v.im};
