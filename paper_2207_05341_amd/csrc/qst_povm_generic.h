@@ -86,11 +86,51 @@ __device__ __forceinline__ void block_coords(int64_t bid, int lgC, int lgJ, int&
 // (a load under a branch is waited for where the branch rejoins).
 constexpr int kLoadBatch = 4;
 
-// One workgroup's share of a forward pass: the nb consecutive virtual
-// blocks bid0 .. bid0 + nb - 1; buf holds nb * 4^g * J complex values of
-// LDS.
-template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
-__device__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
+// Coordinates of the blocks an element loop visits, in increasing order.
+// UNI (4^g J a multiple of the workgroup size, so every thread of an
+// iteration is in the same block): a cursor in scalar registers steps
+// through the blocks -- chunks of a pair, then the pairs (Rhi, Chi) row by
+// row over the lower triangle -- without division or square root.
+// Otherwise each element decodes its own block.
+template <bool UNI>
+struct BlockWalk {
+  int64_t b, ch;
+  int R, C, lgC, lgJ;
+  __device__ __forceinline__ BlockWalk(int64_t bid0, int lgC_, int lgJ_) : b(bid0), ch(0), R(0), C(0), lgC(lgC_), lgJ(lgJ_) {
+    if constexpr (UNI) {
+      int64_t kd0;
+      block_coords(bid0, lgC, lgJ, R, C, kd0);
+      ch = kd0 >> lgJ;
+    }
+  }
+  // Block of element e0 (given relative to the call's first block bid0).
+  __device__ __forceinline__ void at(int64_t bid0, int blk, int& Rhi, int& Chi, int64_t& kd0) {
+    if constexpr (UNI) {
+      const int64_t bid = bid0 + __builtin_amdgcn_readfirstlane(blk);
+      while (b < bid) {
+        ++b;
+        if (++ch == (int64_t(1) << lgC)) {
+          ch = 0;
+          if (C < R) {
+            ++C;
+          } else {
+            ++R;
+            C = 0;
+          }
+        }
+      }
+      Rhi = R;
+      Chi = C;
+      kd0 = ch << lgJ;
+    } else {
+      block_coords(bid0 + blk, lgC, lgJ, Rhi, Chi, kd0);
+    }
+  }
+};
+
+// Forward pass over the blocks bid0 .. bid0 + nb - 1 (see fwd_pass_body).
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE, bool UNI>
+__device__ __forceinline__ void fwd_pass_impl(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb) {
   const int g = a.g, J = a.J, U = a.U, n = a.n;
   const int Up = U - g;
   const int64_t kd = int64_t(1) << (2 * (n - U));
@@ -104,6 +144,7 @@ __device__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
 
   const Cx<R>* in = static_cast<const Cx<R>*>(a.in);
   const int total = elems * nb;
+  BlockWalk<UNI> walk(bid0, lgC, lgJ);
   for (int base = 0; base < total; base += kLoadBatch * int(blockDim.x)) {
     R vr[kLoadBatch], vi[kLoadBatch];  // scalar arrays stay in registers
 #pragma unroll
@@ -113,7 +154,7 @@ __device__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
       const int e = ec & (elems - 1);
       int Rhi, Chi;
       int64_t kd0;
-      block_coords(bid0 + (ec >> lgE), lgC, lgJ, Rhi, Chi, kd0);
+      walk.at(bid0, ec >> lgE, Rhi, Chi, kd0);
       const int j = e & (J - 1);
       const int rc = e >> lgJ;
       const int c = rc & gm, r = rc >> g;
@@ -133,11 +174,12 @@ __device__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
   __syncthreads();
   contract_group<R, false, TETRA>(buf, g, J, A, nb);
 
+  BlockWalk<UNI> walk2(bid0, lgC, lgJ);
   for (int e0 = threadIdx.x; e0 < elems * nb; e0 += blockDim.x) {
     const int e = e0 & (elems - 1);
     int Rhi, Chi;
     int64_t kd0;
-    block_coords(bid0 + (e0 >> lgE), lgC, lgJ, Rhi, Chi, kd0);
+    walk2.at(bid0, e0 >> lgE, Rhi, Chi, kd0);
     const int j = e & (J - 1);
     const int kg = e >> lgJ;
     int r, c;
@@ -152,10 +194,9 @@ __device__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
   }
 }
 
-// One workgroup's share of an adjoint pass: the nb consecutive virtual
-// blocks bid0 .. bid0 + nb - 1 (buf as for the forward pass).
-template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
-__device__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
+// Adjoint pass over the blocks bid0 .. bid0 + nb - 1 (see adj_pass_body).
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE, bool UNI>
+__device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb) {
   const int g = a.g, J = a.J, U = a.U, n = a.n;
   const int Up = U - g;
   const int64_t kd = int64_t(1) << (2 * (n - U));
@@ -170,6 +211,7 @@ __device__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
   double F = 0.0;
   if constexpr (PSIDE) F = *a.F;
   const int total = elems * nb;
+  BlockWalk<UNI> walk(bid0, lgC, lgJ);
   for (int base0 = 0; base0 < total; base0 += kLoadBatch * int(blockDim.x)) {
     R vr[kLoadBatch], vi[kLoadBatch];  // PSIDE: f_k and p_k
     int dst[kLoadBatch];
@@ -180,7 +222,7 @@ __device__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
       const int e = ec & (elems - 1);
       int Rhi, Chi;
       int64_t kd0;
-      block_coords(bid0 + (ec >> lgE), lgC, lgJ, Rhi, Chi, kd0);
+      walk.at(bid0, ec >> lgE, Rhi, Chi, kd0);
       const int j = e & (J - 1);
       const int kg = e >> lgJ;
       int r, c;
@@ -209,11 +251,12 @@ __device__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
   contract_group<R, true, TETRA>(buf, g, J, A, nb);
 
   Cx<R>* out = static_cast<Cx<R>*>(a.out);
+  BlockWalk<UNI> walk2(bid0, lgC, lgJ);
   for (int e0 = threadIdx.x; e0 < elems * nb; e0 += blockDim.x) {
     const int e = e0 & (elems - 1);
     int Rhi, Chi;
     int64_t kd0;
-    block_coords(bid0 + (e0 >> lgE), lgC, lgJ, Rhi, Chi, kd0);
+    walk2.at(bid0, e0 >> lgE, Rhi, Chi, kd0);
     const int j = e & (J - 1);
     const int rc = e >> lgJ;
     const int c = rc & gm, r = rc >> g;
@@ -227,6 +270,25 @@ __device__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bi
       out[((Rr << U) | Cr) * kd + kd0 + j] = v;
     }
   }
+}
+
+// One workgroup's share of a forward / adjoint pass: the nb consecutive
+// virtual blocks bid0 .. bid0 + nb - 1; buf holds nb * 4^g * J complex
+// values of LDS.  The block walk runs on the scalar unit whenever a block
+// is a whole number of workgroup-wide iterations.
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
+__device__ __forceinline__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
+  if ((((1 << (2 * a.g)) * a.J) & (int(blockDim.x) - 1)) == 0)
+    fwd_pass_impl<R, TETRA, MATSIDE, PSIDE, true>(a, A, bid0, buf, nb);
+  else
+    fwd_pass_impl<R, TETRA, MATSIDE, PSIDE, false>(a, A, bid0, buf, nb);
+}
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
+__device__ __forceinline__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
+  if ((((1 << (2 * a.g)) * a.J) & (int(blockDim.x) - 1)) == 0)
+    adj_pass_impl<R, TETRA, MATSIDE, PSIDE, true>(a, A, bid0, buf, nb);
+  else
+    adj_pass_impl<R, TETRA, MATSIDE, PSIDE, false>(a, A, bid0, buf, nb);
 }
 
 }  // namespace generic_pass
