@@ -90,6 +90,9 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
   // One 64 KiB LDS pool serves, one stage at a time, the product panels, the
   // POVM pass buffer and the reduction scratch (red, slot, s_idx).
   __shared__ __align__(16) unsigned char pool[65536];
+  static_assert(sizeof(typename PH::Smem) <= sizeof(pool) && sizeof(typename PM::Smem) <= sizeof(pool) &&
+                    sizeof(gemm::HerkBf16x3Policy::Smem) <= sizeof(pool),
+                "product panels exceed the LDS pool");
   double* const red = reinterpret_cast<double*>(pool);
   double* const slotp = red + 4;
   int* const s_idx_p = reinterpret_cast<int*>(red + 5);

@@ -122,14 +122,28 @@ struct CxPolicy {
       __syncthreads();
       if (kp + 1 < ke) QST_LOAD_PANEL(kp + 1);
 #undef QST_LOAD_PANEL
+      // operands of the next K step are read from LDS before the MFMAs of
+      // the current one, so the LDS latency overlaps them
+      Cx<R> an[2], bn[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) an[i] = sm.As[lk][wr * 32 + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bn[j] = sm.Bs[lk][wc * 32 + j * 16 + li];
 #pragma unroll
       for (int ks = 0; ks < KP / 4; ++ks) {
-        const int kk = ks * 4 + lk;
         Cx<R> a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = sm.As[kk][wr * 32 + i * 16 + li];
+        for (int i = 0; i < 2; ++i) a[i] = an[i];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = sm.Bs[kk][wc * 32 + j * 16 + li];
+        for (int j = 0; j < 2; ++j) b[j] = bn[j];
+        if (ks + 1 < KP / 4) {
+          const int kn = (ks + 1) * 4 + lk;
+#pragma unroll
+          for (int i = 0; i < 2; ++i) an[i] = sm.As[kn][wr * 32 + i * 16 + li];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) bn[j] = sm.Bs[kn][wc * 32 + j * 16 + li];
+          __builtin_amdgcn_sched_barrier(0);  // keep these reads ahead of the MFMAs below
+        }
         if constexpr (M3) {
           R as[2], bs[2];
 #pragma unroll
