@@ -69,10 +69,19 @@ struct BatchArgs {
 
 __global__ void reset_counter_kernel(int* c) { *c = 0; }
 
-// Block-wide FP64 sum (fixed order), result broadcast to every thread.
-__device__ double block_sum_bcast(double v, double* red4, double* slot) {
-  const double s = block_sum256(v, red4);
-  if (threadIdx.x == 0) *slot = s;
+// Block-wide FP64 sum over NW waves (wave trees, then the wave sums in
+// order), result broadcast to every thread.
+template <int NW>
+__device__ double block_sum_bcast(double v, double* redw, double* slot) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) redw[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = redw[0];
+    for (int i = 1; i < NW; ++i) s += redw[i];
+    *slot = s;
+  }
   __syncthreads();
   const double r = *slot;
   __syncthreads();
@@ -85,17 +94,26 @@ using BatchHerk = gemm::CxPolicy<R, true>;
 template <typename R>
 using BatchHemm = gemm::CxPolicy<R, false>;
 
-template <class PH, class PM, typename R, bool TETRA, bool BF16>
-__global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
+// THREADS = 256 x SUB: the element loops use every thread; the product
+// stages run SUB tiles at a time, one per 256-thread group, each with its own
+// panel buffers.  Every group makes the same number of tile calls (a tile
+// list is padded to a multiple of SUB; a padding call recomputes tile 0 and
+// stores nothing), so the barriers inside the tile code stay matched.
+template <class PH, class PM, typename R, bool TETRA, bool BF16, int THREADS>
+__global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
+  constexpr int SUB = THREADS / 256, NW = THREADS / 64;
   // One 64 KiB LDS pool serves, one stage at a time, the product panels, the
   // POVM pass buffer and the reduction scratch (red, slot, s_idx).
   __shared__ __align__(16) unsigned char pool[65536];
   static_assert(sizeof(typename PH::Smem) <= sizeof(pool) && sizeof(typename PM::Smem) <= sizeof(pool) &&
                     sizeof(gemm::HerkBf16x3Policy::Smem) <= sizeof(pool),
                 "product panels exceed the LDS pool");
+  static_assert(SUB * sizeof(typename PH::Smem) <= sizeof(pool) && SUB * sizeof(typename PM::Smem) <= sizeof(pool),
+                "one set of panel buffers per 256-thread group must fit the pool");
   double* const red = reinterpret_cast<double*>(pool);
-  double* const slotp = red + 4;
-  int* const s_idx_p = reinterpret_cast<int*>(red + 5);
+  double* const slotp = red + NW;
+  int* const s_idx_p = reinterpret_cast<int*>(red + NW + 1);
+  const int sub = threadIdx.x >> 8;
   const int t = threadIdx.x;
   const int64_t dmax = int64_t(1) << b.nmax, Dmax = dmax * dmax;
   unsigned char* scr = b.scratch + int64_t(blockIdx.x) * b.stride;
@@ -124,16 +142,16 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
     // end are clamped and their values dropped)
     constexpr int kBatch = 4;
     double acc = 0.0;
-    for (int64_t e0 = 0; e0 < D; e0 += kBatch * 256) {
+    for (int64_t e0 = 0; e0 < D; e0 += kBatch * THREADS) {
       Cx<R> v[kBatch];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const int64_t e = e0 + u * 256 + t;
+        const int64_t e = e0 + u * THREADS + t;
         v[u] = T[e < D ? e : D - 1];
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        if (e0 + u * 256 + t >= D) continue;
+        if (e0 + u * THREADS + t >= D) continue;
         double x = double(v[u].re), y = double(v[u].im);
         if constexpr (BF16) {
           const float hr = bf16_value(float(v[u].re)), hi = bf16_value(float(v[u].im));
@@ -148,7 +166,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
         acc += x * x + y * y;
       }
     }
-    const double tau = block_sum_bcast(acc, red, slotp);
+    const double tau = block_sum_bcast<NW>(acc, red, slotp);
 
     // 2. rho = T T^dagger / tau
     if (BF16 && d >= 64 && d <= kBf16SplitMaxDim) {
@@ -181,17 +199,19 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
       g.ldc = d;
       g.d = d;
       g.kIters = d / PH::KP;
-      const int tiles = d / 64;
-      for (int tile = 0; tile < tiles * (tiles + 1) / 2; ++tile) {
+      const int tiles = d / 64, ntl = tiles * (tiles + 1) / 2;
+      auto& sm = reinterpret_cast<typename PH::Smem*>(pool)[sub];
+      for (int t0 = 0; t0 < ntl; t0 += SUB) {
+        const int tile = t0 + sub;
         int tr, tc;
-        tri_decode(tile, tr, tc);
+        tri_decode(tile < ntl ? tile : 0, tr, tc);
         typename PH::acc_t aR[2][2], aI[2][2];
         gemm::zero_acc<PH>(aR, aI);
-        PH::run(g, *reinterpret_cast<typename PH::Smem*>(pool), tr, tc, 0, g.kIters, aR, aI);
-        gemm::epilogue<PH>(g, tr, tc, aR, aI, 1.0 / tau);
+        PH::run(g, sm, tr, tc, 0, g.kIters, aR, aI);
+        if (tile < ntl) gemm::epilogue<PH>(g, tr, tc, aR, aI, 1.0 / tau);
       }
     } else {
-      for (int64_t e = t; e < D; e += 256) {
+      for (int64_t e = t; e < D; e += THREADS) {
         const int r = int(e >> n), c = int(e & (d - 1));
         R sr = 0, si = 0;
         for (int k = 0; k < d; ++k) {
@@ -243,18 +263,18 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
 
     // 4. L, F (FP64), counters
     double L = 0.0, F = 0.0, bad0 = 0.0, bad1 = 0.0;
-    for (int64_t k0 = 0; k0 < D; k0 += kBatch * 256) {
+    for (int64_t k0 = 0; k0 < D; k0 += kBatch * THREADS) {
       R fv[kBatch], pv[kBatch];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const int64_t k = k0 + u * 256 + t;
+        const int64_t k = k0 + u * THREADS + t;
         const int64_t kc = k < D ? k : D - 1;
         fv[u] = f[kc];
         pv[u] = pvec[kc];
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        if (k0 + u * 256 + t >= D) continue;
+        if (k0 + u * THREADS + t >= D) continue;
         const double fk = double(fv[u]), pk = double(pv[u]);
         F += fk;
         if (fk != 0.0) {
@@ -264,10 +284,10 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
         if (pk != pk || fk != fk) bad1 += 1.0;
       }
     }
-    L = block_sum_bcast(L, red, slotp);
-    F = block_sum_bcast(F, red, slotp);
-    bad0 = block_sum_bcast(bad0, red, slotp);
-    bad1 = block_sum_bcast(bad1, red, slotp);
+    L = block_sum_bcast<NW>(L, red, slotp);
+    F = block_sum_bcast<NW>(F, red, slotp);
+    bad0 = block_sum_bcast<NW>(bad0, red, slotp);
+    bad1 = block_sum_bcast<NW>(bad1, red, slotp);
     if (t == 0) {
       double Lo = L;
       if (F != F || bad1 > 0.0) Lo = __builtin_nan("");
@@ -322,16 +342,18 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
       g.ldc = d;
       g.d = d;
       g.kIters = d / PM::KP;
-      const int tiles = d / 64;
-      for (int tile = 0; tile < tiles * tiles; ++tile) {
-        const int tr = tile / tiles, tc = tile % tiles;
+      const int tiles = d / 64, ntl = tiles * tiles;
+      auto& sm = reinterpret_cast<typename PM::Smem*>(pool)[sub];
+      for (int t0 = 0; t0 < ntl; t0 += SUB) {
+        const int tile = t0 + sub, tl = tile < ntl ? tile : 0;
+        const int tr = tl / tiles, tc = tl % tiles;
         typename PM::acc_t aR[2][2], aI[2][2];
         gemm::zero_acc<PM>(aR, aI);
-        PM::run(g, *reinterpret_cast<typename PM::Smem*>(pool), tr, tc, 0, g.kIters, aR, aI);
-        gemm::epilogue<PM>(g, tr, tc, aR, aI, scale);
+        PM::run(g, sm, tr, tc, 0, g.kIters, aR, aI);
+        if (tile < ntl) gemm::epilogue<PM>(g, tr, tc, aR, aI, scale);
       }
     } else {
-      for (int64_t e = t; e < D; e += 256) {
+      for (int64_t e = t; e < D; e += THREADS) {
         const int r = int(e >> n), c = int(e & (d - 1));
         R sr = 0, si = 0;
         for (int k = 0; k < d; ++k) {
@@ -355,34 +377,40 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs b) {
   }
 }
 
+// Workgroup size of the batched kernel: 512 (two tile groups) for FP32,
+// whose registers allow two waves per SIMD; 256 for FP64 and BF16.
+template <typename R, bool BF16>
+constexpr int kBatchThreads = (sizeof(R) == 4 && !BF16) ? 512 : 256;
+
 template <typename R, bool TETRA, bool BF16>
 struct BatchKernelOf;
 template <bool TETRA>
 struct BatchKernelOf<double, TETRA, false> {
   static void* fn() {
     return reinterpret_cast<void*>(
-        &batch_kernel<BatchHerk<double>, BatchHemm<double>, double, TETRA, false>);
+        &batch_kernel<BatchHerk<double>, BatchHemm<double>, double, TETRA, false, kBatchThreads<double, false>>);
   }
 };
 template <bool TETRA>
 struct BatchKernelOf<float, TETRA, false> {
   static void* fn() {
     return reinterpret_cast<void*>(
-        &batch_kernel<BatchHerk<float>, BatchHemm<float>, float, TETRA, false>);
+        &batch_kernel<BatchHerk<float>, BatchHemm<float>, float, TETRA, false, kBatchThreads<float, false>>);
   }
 };
 template <bool TETRA>
 struct BatchKernelOf<float, TETRA, true> {
   static void* fn() {
     return reinterpret_cast<void*>(
-        &batch_kernel<gemm::HerkBf16Policy, gemm::HemmBf16x3Policy, float, TETRA, true>);
+        &batch_kernel<gemm::HerkBf16Policy, gemm::HemmBf16x3Policy, float, TETRA, true, kBatchThreads<float, true>>);
   }
 };
 
 template <class PH, class PM, typename R, bool BF16>
 hipError_t launch_batch_t(bool tetra, const BatchArgs& a, int grid, hipStream_t s) {
-  if (tetra) batch_kernel<PH, PM, R, true, BF16><<<unsigned(grid), 256, 0, s>>>(a);
-  else batch_kernel<PH, PM, R, false, BF16><<<unsigned(grid), 256, 0, s>>>(a);
+  constexpr int NT = kBatchThreads<R, BF16>;
+  if (tetra) batch_kernel<PH, PM, R, true, BF16, NT><<<unsigned(grid), NT, 0, s>>>(a);
+  else batch_kernel<PH, PM, R, false, BF16, NT><<<unsigned(grid), NT, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -397,8 +425,11 @@ int batch_occupancy(qst_prec prec) {
   void* fn = prec == QST_F64 ? BatchKernelOf<double, true, false>::fn()
              : prec == QST_F32 ? BatchKernelOf<float, true, false>::fn()
                                : BatchKernelOf<float, true, true>::fn();
+  const int threads = prec == QST_F64 ? kBatchThreads<double, false>
+                      : prec == QST_F32 ? kBatchThreads<float, false>
+                                        : kBatchThreads<float, true>;
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), 256, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), threads, 0) != hipSuccess ||
       n <= 0)
     n = 1;
   return n;

@@ -72,7 +72,7 @@ struct CxPolicy {
     const Cx<R>* A = static_cast<const Cx<R>*>(g.A);
     const Cx<R>* B = static_cast<const Cx<R>*>(g.B);
     const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x & 255;  // index in the 256-thread group computing the tile
     const int lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
     const int li = lane & 15, lk = lane >> 4;
@@ -602,7 +602,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int tr, int tc, type
   typedef typename P::scalar R;
   Cx<R>* C = static_cast<Cx<R>*>(g.C);
   const R sc = R(scale);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = (threadIdx.x & 255) >> 6;  // 256-thread group
   const int wr = w >> 1, wc = w & 1, li = lane & 15, lq = lane >> 4;
   const int64_t R0 = int64_t(tr) * BM, C0 = int64_t(tc) * BM;
 #pragma unroll

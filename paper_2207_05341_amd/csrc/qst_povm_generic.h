@@ -87,8 +87,8 @@ __device__ __forceinline__ void block_coords(int64_t bid, int lgC, int lgJ, int&
 constexpr int kLoadBatch = 4;
 
 // Coordinates of the blocks an element loop visits, in increasing order.
-// UNI (4^g J a multiple of the workgroup size, so every thread of an
-// iteration is in the same block): a cursor in scalar registers steps
+// UNI (4^g J a multiple of 64, so the 64 lanes of a wave are in the same
+// block in every iteration): a per-wave cursor in scalar registers steps
 // through the blocks -- chunks of a pair, then the pairs (Rhi, Chi) row by
 // row over the lower triangle -- without division or square root.
 // Otherwise each element decodes its own block.
@@ -275,17 +275,17 @@ __device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatri
 // One workgroup's share of a forward / adjoint pass: the nb consecutive
 // virtual blocks bid0 .. bid0 + nb - 1; buf holds nb * 4^g * J complex
 // values of LDS.  The block walk runs on the scalar unit whenever a block
-// is a whole number of workgroup-wide iterations.
+// is a whole number of waves.
 template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
 __device__ __forceinline__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
-  if ((((1 << (2 * a.g)) * a.J) & (int(blockDim.x) - 1)) == 0)
+  if ((((1 << (2 * a.g)) * a.J) & 63) == 0)
     fwd_pass_impl<R, TETRA, MATSIDE, PSIDE, true>(a, A, bid0, buf, nb);
   else
     fwd_pass_impl<R, TETRA, MATSIDE, PSIDE, false>(a, A, bid0, buf, nb);
 }
 template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
 __device__ __forceinline__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
-  if ((((1 << (2 * a.g)) * a.J) & (int(blockDim.x) - 1)) == 0)
+  if ((((1 << (2 * a.g)) * a.J) & 63) == 0)
     adj_pass_impl<R, TETRA, MATSIDE, PSIDE, true>(a, A, bid0, buf, nb);
   else
     adj_pass_impl<R, TETRA, MATSIDE, PSIDE, false>(a, A, bid0, buf, nb);
