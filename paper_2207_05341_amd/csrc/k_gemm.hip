@@ -23,6 +23,7 @@
 // accumulators in the workspace (at most two per workgroup), and a fix-up
 // kernel adds them in K order -- no atomics, so results are deterministic.
 #include <algorithm>
+#include <cmath>
 
 #include "qst_device.h"
 #include "qst_gemm_tiles.h"
@@ -108,28 +109,77 @@ __global__ __launch_bounds__(256, P::kMinWaves) void gemm_sk_kernel(GemmArgs g) 
   }
 }
 
-// Sum the partial segments of every stream-K tile that was cut, in K order.
-// Workgroup b handles tile dp_tiles + b.
-template <class P, int X0G>
-__global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g, int Pn) {
-  __shared__ __align__(16) unsigned char smem[X0G ? smem_bytes<P, X0G != 0>() : 16];
-  const int rel = blockIdx.x;
+// Stream-K workgroups owning the first and the last K panel of tile
+// dp_tiles + rel.
+__device__ __forceinline__ void tile_owners(const GemmArgs& g, int64_t Pn, int rel, int64_t& wlo, int64_t& whi) {
   const int64_t kb = int64_t(rel) * g.kIters, kl = kb + g.kIters - 1;
-  // workgroups owning the first and the last iteration of the tile
-  int64_t wlo = (kb * Pn) / g.iters;
+  wlo = (kb * Pn) / g.iters;
   while (wlo + 1 < Pn && sk_start(wlo + 1, Pn, g.iters) <= kb) ++wlo;
   while (wlo > 0 && sk_start(wlo, Pn, g.iters) > kb) --wlo;
-  int64_t whi = (kl * Pn) / g.iters;
+  whi = (kl * Pn) / g.iters;
   while (whi + 1 < Pn && sk_start(whi + 1, Pn, g.iters) <= kl) ++whi;
   while (whi > 0 && sk_start(whi, Pn, g.iters) > kl) --whi;
+}
+
+// Partial of workgroup w for tile dp_tiles + rel.
+template <class P>
+__device__ __forceinline__ typename P::scalar* tile_partial(const GemmArgs& g, int64_t Pn, int64_t w, int rel) {
+  const int first_rel = int(sk_start(w, Pn, g.iters) / g.kIters);
+  return partial_slot<P>(g, int(w), rel == first_rel ? 0 : 1);
+}
+
+// Sum the partials of workgroups [lo, hi] for tile dp_tiles + rel in
+// workgroup order, four per memory round trip.
+template <class P>
+__device__ __forceinline__ void sum_partials(const GemmArgs& g, int64_t Pn, int rel, int64_t lo, int64_t hi,
+                                             int64_t step, typename P::acc_t (&aR)[2][2],
+                                             typename P::acc_t (&aI)[2][2]) {
+  int64_t w = lo;
+  for (; w + 3 * step <= hi; w += 4 * step) {
+    const typename P::scalar* const src[4] = {tile_partial<P>(g, Pn, w, rel), tile_partial<P>(g, Pn, w + step, rel),
+                                              tile_partial<P>(g, Pn, w + 2 * step, rel),
+                                              tile_partial<P>(g, Pn, w + 3 * step, rel)};
+    add_partials<P, 4>(src, aR, aI);
+  }
+  for (; w <= hi; w += step) add_partial<P>(tile_partial<P>(g, Pn, w, rel), aR, aI);
+}
+
+// First level of the fix-up for tiles cut into many segments: workgroup
+// (rel, c) sums the partials of the stream-K workgroups wlo + c*chunk ..
+// wlo + (c+1)*chunk - 1 of tile dp_tiles + rel (in order) into the first
+// one's partial, so that the fix-up adds one partial per chunk.  A
+// workgroup reads and writes only the partials of its own chunk.  (Slicing
+// each partial over several workgroups, one 16-byte vector per thread and
+// all partials of a chunk in flight at once, measured slower: 20 us against
+// 13 us for the 16 tiles of FP64 at N = 11.)
+template <class P>
+__global__ __launch_bounds__(256) void gemm_chunk_sum_kernel(GemmArgs g, int Pn, int chunk, int groups) {
+  const int rel = blockIdx.x / groups, c = blockIdx.x % groups;
+  int64_t wlo, whi;
+  tile_owners(g, Pn, rel, wlo, whi);
+  const int64_t lo = wlo + int64_t(c) * chunk;
+  const int64_t hi = min(whi, lo + chunk - 1);
+  if (lo >= hi) return;  // empty chunk, or a single partial already in place
+  typename P::acc_t aR[2][2], aI[2][2];
+  zero_acc<P>(aR, aI);
+  sum_partials<P>(g, Pn, rel, lo, hi, 1, aR, aI);
+  store_partial<P>(tile_partial<P>(g, Pn, lo, rel), aR, aI);
+}
+
+// Sum the partial segments of every stream-K tile that was cut, in K order
+// (with chunk > 1, the chunk sums left by gemm_chunk_sum_kernel).
+// Workgroup b handles tile dp_tiles + b.
+template <class P, int X0G>
+__global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g, int Pn, int chunk) {
+  __shared__ __align__(16) unsigned char smem[X0G ? smem_bytes<P, X0G != 0>() : 16];
+  const int rel = blockIdx.x;
+  int64_t wlo, whi;
+  tile_owners(g, Pn, rel, wlo, whi);
   if (wlo == whi) return;  // whole tile inside one workgroup: already written
   const double scale = tile_scale<P>(g);
   typename P::acc_t aR[2][2], aI[2][2];
   zero_acc<P>(aR, aI);
-  for (int64_t w = wlo; w <= whi; ++w) {
-    const int first_rel = int(sk_start(w, Pn, g.iters) / g.kIters);
-    add_partial<P>(partial_slot<P>(g, int(w), rel == first_rel ? 0 : 1), aR, aI);
-  }
+  sum_partials<P>(g, Pn, rel, wlo, whi, chunk, aR, aI);
   int tr, tc;
   tile_coords<P>(g, g.dp_tiles + rel, tr, tc);
   finish_tile<P, X0G>(g, tr, tc, aR, aI, scale, smem);
@@ -238,7 +288,37 @@ inline int64_t sk_grid(GemmArgs& g, int cus, int occ) {
     return 0;
   }
   g.iters = int64_t(g.ntiles - g.dp_tiles) * g.kIters;
+  if (g.iters < Pn) {  // every stream-K workgroup must own at least one K panel
+    g.dp_tiles = 0;
+    g.iters = int64_t(g.ntiles) * g.kIters;
+    return 0;
+  }
   return Pn;
+}
+
+// Fix-up of the tiles dp_tiles.. cut by the stream-K kernel of Pn
+// workgroups.  A tile cut into many segments (32 for the one wave of 16
+// leftover tiles in FP64 at N = 11) would leave one workgroup reading them
+// all (45 us for FP64 at N = 11); above 8 segments they are first summed
+// in chunks of about sqrt(segments) by gemm_chunk_sum_kernel (13 + 18 us).
+template <class P, int X0G>
+hipError_t launch_fixup(const GemmArgs& g, int64_t Pn, hipStream_t s) {
+  const int64_t sk_tiles = g.ntiles - g.dp_tiles;
+  // workgroups sharing one tile: at most ceil(kIters / min panels per workgroup) + 1
+  const int64_t per_wg = g.iters / Pn;
+  const int64_t parts = std::min<int64_t>(Pn, (g.kIters + per_wg - 1) / per_wg + 1);
+  int chunk = 1;
+  if (parts > 8) {
+    chunk = int(std::lround(std::sqrt(double(parts))));
+    const int groups = int((parts + chunk - 1) / chunk);
+    gemm_chunk_sum_kernel<P><<<unsigned(sk_tiles * groups), 256, 0, s>>>(g, int(Pn), chunk, groups);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  GemmArgs gf = g;
+  gf.tau_out = nullptr;
+  gemm_fixup_kernel<P, X0G><<<unsigned(sk_tiles), 256, 0, s>>>(gf, int(Pn), chunk);
+  return hipGetLastError();
 }
 
 template <class P, int X0G = 0>
@@ -260,10 +340,7 @@ hipError_t run_gemm(GemmArgs g, hipStream_t s) {
       gemm_sk_kernel<P, 0><<<unsigned(Pn), 256, 0, s>>>(gp);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
-      GemmArgs gf = gp;
-      gf.tau_out = nullptr;
-      gemm_fixup_kernel<P, X0G><<<unsigned(gp.ntiles), 256, 0, s>>>(gf, int(Pn));
-      return hipGetLastError();
+      return launch_fixup<P, X0G>(gp, Pn, s);
     }
   }
   int64_t Pn = 0;
@@ -281,10 +358,7 @@ hipError_t run_gemm(GemmArgs g, hipStream_t s) {
   gemm_sk_kernel<P, X0G><<<unsigned(Pn), 256, 0, s>>>(g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  GemmArgs gf = g;
-  gf.tau_out = nullptr;
-  gemm_fixup_kernel<P, X0G><<<unsigned(g.ntiles - g.dp_tiles), 256, 0, s>>>(gf, int(Pn));
-  return hipGetLastError();
+  return launch_fixup<P, X0G>(g, Pn, s);
 }
 
 template <int G>

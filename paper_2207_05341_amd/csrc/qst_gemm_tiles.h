@@ -695,6 +695,38 @@ __device__ __forceinline__ void store_partial(typename P::scalar* dst, typename 
       }
 }
 
+// NB partial tiles at once: all NB are loaded before any is added (one
+// memory round trip for the group), then added in the order src[0], src[1], ...
+template <class P, int NB>
+__device__ __forceinline__ void add_partials(const typename P::scalar* const (&src)[NB],
+                                             typename P::acc_t (&aR)[2][2], typename P::acc_t (&aI)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  typename P::acc_t bR[NB][2][2], bI[NB][2][2];
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int o = (((w * 2 + i) * 2 + j) * 2 * 4 + v) * 64 + lane;
+          bR[q][i][j][v] = src[q][o];
+          bI[q][i][j][v] = src[q][o + 4 * 64];
+        }
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          aR[i][j][v] += bR[q][i][j][v];
+          aI[i][j][v] += bI[q][i][j][v];
+        }
+}
+
 template <class P>
 __device__ __forceinline__ void add_partial(const typename P::scalar* src, typename P::acc_t (&aR)[2][2],
                                             typename P::acc_t (&aI)[2][2]) {
