@@ -28,6 +28,7 @@
 #include "qst_gemm_tiles.h"
 #include "qst_kernels.h"
 #include "qst_plan.h"
+#include "qst_povm_fast.h"
 #include "qst_povm_generic.h"
 
 namespace qst {
@@ -99,12 +100,129 @@ using BatchHemm = gemm::CxPolicy<R, false>;
 // panel buffers.  Every group makes the same number of tile calls (a tile
 // list is padded to a multiple of SUB; a padding call recomputes tile 0 and
 // stores nothing), so the barriers inside the tile code stay matched.
+// Barrier after one call of a POVM pass.  Between calls of the same pass
+// (more to come) only the LDS buffer is reused: the call's global stores
+// go to a different array than the pass reads, so they need not complete
+// before the next call's loads start (no fence, just the barrier).  After
+// a pass's last call, or when a pass reads the array it writes, the full
+// barrier makes the stores visible to the whole workgroup.
+__device__ __forceinline__ void pass_call_barrier(const PassArgs& a, bool more) {
+  if (more && a.in != a.out)
+    __builtin_amdgcn_s_barrier();
+  else
+    __syncthreads();
+}
+
+// Which register-round form covers an instance's POVM plan: 4 (pass 0 over
+// 4 qubits, pass 1 over 4 with J = 32 / 16 for FP32 / FP64, N = 8), 3 (4 then
+// 3 with J = 64, N = 7), or 0 (the generic passes).
+__device__ __forceinline__ int fast_plan(const BatchPlanTable& pl, int n, bool f64) {
+  if (pl.passes[n] != 2 || pl.g[n][0] != 4 || pl.J[n][0] != 1) return 0;
+  if (pl.g[n][1] == 4 && pl.J[n][1] == (f64 ? 16 : 32)) return 4;
+  if (pl.g[n][1] == 3 && pl.J[n][1] == 64) return 3;
+  return 0;
+}
+
+// Pass args of pass pj of instance n.
+__device__ __forceinline__ PassArgs pass_args(const BatchPlanTable& pl, int n, int pj) {
+  PassArgs a{};
+  a.n = n;
+  a.U = pl.U[n][pj];
+  a.g = pl.g[n][pj];
+  a.J = pl.J[n][pj];
+  a.ld = 1 << n;
+  return a;
+}
+
+// The SUB 256-thread groups of the workgroup take calls sub, sub + SUB, ...
+// of a pass; the call count is rounded up to a multiple of SUB (a padding
+// call stores nothing), so every group meets the same barriers.  The
+// barrier after each call protects the group's LDS area for the next call;
+// the last one also makes the pass's stores visible to the next pass.
+template <typename R, bool ADJ, bool TETRA, int G1, int J1, int SUB, int POOL>
+__device__ __forceinline__ void fast_pass_pair(const BatchArgs& b, int n, Cx<R>* rho, Cx<R>* inter, R* pvec,
+                                               const R* f, const double* Fdev, unsigned char* pool, int sub,
+                                               unsigned tid) {
+  constexpr int TPW = 256 >> 4;  // tiles of pass 0 (G = 4) per 256 threads
+  typedef Cx<R> Mat4Lds[TPW << 8];
+  typedef Cx<R> KdLds[J1 << (2 * G1)];
+  static_assert(SUB * sizeof(Mat4Lds) <= size_t(POOL) && SUB * sizeof(KdLds) <= size_t(POOL),
+                "one pass buffer per 256-thread group must fit the pool");
+  const ModeMatrix& A = ADJ ? b.V : b.W;
+  PassArgs a0 = pass_args(b.plan, n, 0), a1 = pass_args(b.plan, n, 1);
+  const int64_t side0 = int64_t(1) << (a0.U - 4);
+  const int64_t tiles0 = side0 * (side0 + 1) / 2;
+  const int64_t calls0 = (tiles0 + TPW - 1) / TPW;
+  const int64_t calls1 = (int64_t(1) << (2 * (n - a1.U))) / J1;  // one (R, C) pair: the chunks
+  Mat4Lds& L0 = reinterpret_cast<Mat4Lds*>(pool)[sub];
+  KdLds& L1 = reinterpret_cast<KdLds*>(pool)[sub];
+  const int64_t end0 = (calls0 + SUB - 1) / SUB * SUB, end1 = (calls1 + SUB - 1) / SUB * SUB;
+  if constexpr (!ADJ) {
+    a0.in = rho;
+    a0.out = inter;
+    a1.in = inter;
+    a1.out = pvec;
+    for (int64_t c = sub; c < end0; c += SUB) {
+      unsigned tv = tid;
+      asm volatile("" : "+v"(tv));
+      fast_pass::mat_pass_body<R, false, TETRA, 4>(a0, A, tiles0, c, tv, L0);
+      __syncthreads();
+    }
+    for (int64_t c = sub; c < end1; c += SUB) {
+      unsigned tv = tid;
+      asm volatile("" : "+v"(tv));
+      fast_pass::kd_pass_body<R, false, TETRA, G1, J1, true>(a1, A, c < calls1 ? c : calls1 - 1, tv, L1, c < calls1);
+      __syncthreads();
+    }
+  } else {
+    a1.in = nullptr;
+    a1.out = inter;
+    a1.p = pvec;
+    a1.f = f;
+    a1.F = Fdev;
+    a0.in = inter;
+    a0.out = rho;
+    for (int64_t c = sub; c < end1; c += SUB) {
+      unsigned tv = tid;
+      asm volatile("" : "+v"(tv));
+      fast_pass::kd_pass_body<R, true, TETRA, G1, J1, true>(a1, A, c < calls1 ? c : calls1 - 1, tv, L1, c < calls1);
+      __syncthreads();
+    }
+    for (int64_t c = sub; c < end0; c += SUB) {
+      unsigned tv = tid;
+      asm volatile("" : "+v"(tv));
+      fast_pass::mat_pass_body<R, true, TETRA, 4>(a0, A, tiles0, c, tv, L0);
+      __syncthreads();
+    }
+  }
+}
+
+template <typename R, bool TETRA, bool ADJ, int SUB, int POOL>
+__device__ __forceinline__ void fast_passes(const BatchArgs& b, int n, int form, Cx<R>* rho, Cx<R>* inter, R* pvec,
+                                            const R* f, const double* Fdev, unsigned char* pool, int sub,
+                                            unsigned tid) {
+  constexpr int J4 = sizeof(R) == 8 ? 16 : 32;
+  if (form == 4)
+    fast_pass_pair<R, ADJ, TETRA, 4, J4, SUB, POOL>(b, n, rho, inter, pvec, f, Fdev, pool, sub, tid);
+  else
+    fast_pass_pair<R, ADJ, TETRA, 3, 64, SUB, POOL>(b, n, rho, inter, pvec, f, Fdev, pool, sub, tid);
+}
+
+template <bool BF16>
+constexpr int kBatchPoolBytes = BF16 ? 65536 : 131072;
+
 template <class PH, class PM, typename R, bool TETRA, bool BF16, int THREADS>
 __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
   constexpr int SUB = THREADS / 256, NW = THREADS / 64;
-  // One 64 KiB LDS pool serves, one stage at a time, the product panels, the
-  // POVM pass buffer and the reduction scratch (red, slot, s_idx).
-  __shared__ __align__(16) unsigned char pool[65536];
+  // POVM element loops: values loaded per thread before any is stored, as
+  // many as the registers allow (FP32 at 512 threads: 16; FP64: 8)
+  constexpr int kPassLoads = THREADS == 512 ? 16 : (sizeof(R) == 8 ? 8 : generic_pass::kLoadBatch);
+  // One LDS pool serves, one stage at a time, the product panels, the POVM
+  // pass buffer and the reduction scratch (red, slot, s_idx).  Where the
+  // registers already hold the kernel to one workgroup per CU (FP32 at 512
+  // threads, FP64) it takes 128 KiB, so a POVM pass needs half the calls;
+  // BF16 keeps 64 KiB and two workgroups per CU.
+  __shared__ __align__(16) unsigned char pool[kBatchPoolBytes<BF16>];
   static_assert(sizeof(typename PH::Smem) <= sizeof(pool) && sizeof(typename PM::Smem) <= sizeof(pool) &&
                     sizeof(gemm::HerkBf16x3Policy::Smem) <= sizeof(pool),
                 "product panels exceed the LDS pool");
@@ -237,6 +355,14 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
     Cx<R>* buf = reinterpret_cast<Cx<R>*>(pool);
     constexpr int kPoolValues = int(sizeof(pool) / sizeof(Cx<R>));
     const int P = b.plan.passes[n];
+    // the two-pass plans of N = 7, 8 run the register-round passes (for the
+    // tetrahedral POVM in FP32 and FP64: with the general 4 x 4 form, or
+    // beside the BF16 products, they would cost registers -- spills, or the
+    // second BF16 workgroup per CU)
+    const int fastp = (TETRA && !BF16) ? fast_plan(b.plan, n, sizeof(R) == 8) : 0;
+    if (fastp) {
+      fast_passes<R, TETRA, false, SUB, int(sizeof(pool))>(b, n, fastp, rho, inter, pvec, f, Fdev, pool, sub, t & 255);
+    } else
     for (int pj = 0; pj < P; ++pj) {
       PassArgs a{};
       a.n = n;
@@ -253,11 +379,11 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
       const int per = kPoolValues / ((1 << (2 * a.g)) * a.J);  // blocks the LDS pool holds
       for (int64_t vb = 0; vb < blocks; vb += per) {
         const int nb = int(blocks - vb < per ? blocks - vb : per);
-        if (ms && ps) generic_pass::fwd_pass_body<R, TETRA, true, true>(a, b.W, vb, buf, nb);
-        else if (ms) generic_pass::fwd_pass_body<R, TETRA, true, false>(a, b.W, vb, buf, nb);
-        else if (ps) generic_pass::fwd_pass_body<R, TETRA, false, true>(a, b.W, vb, buf, nb);
-        else generic_pass::fwd_pass_body<R, TETRA, false, false>(a, b.W, vb, buf, nb);
-        __syncthreads();
+        if (ms && ps) generic_pass::fwd_pass_body<R, TETRA, true, true, kPassLoads>(a, b.W, vb, buf, nb);
+        else if (ms) generic_pass::fwd_pass_body<R, TETRA, true, false, kPassLoads>(a, b.W, vb, buf, nb);
+        else if (ps) generic_pass::fwd_pass_body<R, TETRA, false, true, kPassLoads>(a, b.W, vb, buf, nb);
+        else generic_pass::fwd_pass_body<R, TETRA, false, false, kPassLoads>(a, b.W, vb, buf, nb);
+        pass_call_barrier(a, vb + per < blocks);
       }
     }
 
@@ -303,6 +429,9 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
     __syncthreads();
 
     // 5. cotangent + adjoint map: (p, f) -> G' (in the rho slot)
+    if (fastp) {
+      fast_passes<R, TETRA, true, SUB, int(sizeof(pool))>(b, n, fastp, rho, inter, pvec, f, Fdev, pool, sub, t & 255);
+    } else
     for (int pj = P - 1; pj >= 0; --pj) {
       PassArgs a{};
       a.n = n;
@@ -322,11 +451,11 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
       const int per = kPoolValues / ((1 << (2 * a.g)) * a.J);
       for (int64_t vb = 0; vb < blocks; vb += per) {
         const int nb = int(blocks - vb < per ? blocks - vb : per);
-        if (ms && ps) generic_pass::adj_pass_body<R, TETRA, true, true>(a, b.V, vb, buf, nb);
-        else if (ms) generic_pass::adj_pass_body<R, TETRA, true, false>(a, b.V, vb, buf, nb);
-        else if (ps) generic_pass::adj_pass_body<R, TETRA, false, true>(a, b.V, vb, buf, nb);
-        else generic_pass::adj_pass_body<R, TETRA, false, false>(a, b.V, vb, buf, nb);
-        __syncthreads();
+        if (ms && ps) generic_pass::adj_pass_body<R, TETRA, true, true, kPassLoads>(a, b.V, vb, buf, nb);
+        else if (ms) generic_pass::adj_pass_body<R, TETRA, true, false, kPassLoads>(a, b.V, vb, buf, nb);
+        else if (ps) generic_pass::adj_pass_body<R, TETRA, false, true, kPassLoads>(a, b.V, vb, buf, nb);
+        else generic_pass::adj_pass_body<R, TETRA, false, false, kPassLoads>(a, b.V, vb, buf, nb);
+        pass_call_barrier(a, vb + per < blocks);
       }
     }
 

@@ -1,0 +1,250 @@
+// Bodies of the specialised product-POVM passes (see k_povm_fast.hip for
+// the round structure), as device functions over a logical block and a
+// 256-thread group, so that the pass kernels and the batched persistent
+// kernel run the same code.  Every thread of the calling workgroup must
+// make the same calls: the bodies contain barriers.
+#pragma once
+
+#include "qst_device.h"
+#include "qst_povm_ops.h"
+#include "qst_povm_rounds.h"
+
+namespace qst {
+namespace fast_pass {
+
+// ---------------------------------------------------------------------------
+// Matrix-side pass (pass 0): rho (forward input, lower triangle) or G'
+// (adjoint output, written in full); outcome side X'[(Rhi, Chi)][kg].
+// 4^(G-2) threads per tile, 256 / 4^(G-2) tiles per 256 threads: the
+// call with index wb (thread tid of 256) covers tiles wb * TPW ..; tiles
+// past ntiles load nothing and store nothing.  lds holds TPW * 4^G values.
+// ---------------------------------------------------------------------------
+template <typename R, bool ADJ, bool TETRA, int G>
+__device__ __forceinline__ void mat_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t ntiles, int64_t wb,
+                                              unsigned tid, Cx<R> (&lds)[(256 >> (2 * (G - 2))) << (2 * G)]) {
+  constexpr int NT = 1 << (2 * (G - 2));
+  constexpr int TPW = 256 / NT;
+  constexpr int TILE = 1 << (2 * G);
+  using RD = Rounds<G>;
+  __builtin_assume(tid < 256);
+
+  const int tl = tid / NT, t = tid % NT;
+  const int64_t tile = wb * TPW + tl;
+  const bool active = tile < ntiles;
+  int Rhi = 0, Chi = 0;
+  if (active) tri_decode(tile, Rhi, Chi);
+  const int Up = a.U - G;
+  Cx<R>* L = lds + tl * TILE;
+  const int64_t R0 = int64_t(Rhi) << G, C0 = int64_t(Chi) << G;
+  const int64_t obase = ((int64_t(Rhi) << Up) | Chi) * int64_t(TILE);
+  const int bq = t & ((1 << (G - 2)) - 1), aq = t >> (G - 2);  // 4 x 4 block (rows 4aq.., cols 4bq..)
+
+  // Fixed part of round rd: the 4 x 4 block corner for round 0 (bits 0, 1
+  // vary), otherwise the interleaved enumeration of the other bits by t.
+  auto round_fixed = [&](int rd, int& rf, int& cf) {
+    if (rd == 0) {
+      rf = 4 * aq;
+      cf = 4 * bq;
+    } else {
+      fixed_bits<G>(t, RD::bA[rd], RD::bB[rd], rf, cf);
+    }
+  };
+
+  Cx<R> x[16];
+  if constexpr (!ADJ) {
+    Cx<R> blk[4][4];
+    if (active) {
+      const Cx<R>* M = static_cast<const Cx<R>*>(a.in);
+      const bool diag = Rhi == Chi;
+      if (diag && aq < bq) {  // block above the diagonal: conjugate of the mirror block
+#pragma unroll
+        for (int ci = 0; ci < 4; ++ci) {
+          const Cx<R>* row = M + (C0 + 4 * bq + ci) * a.ld + R0 + 4 * aq;
+#pragma unroll
+          for (int ri = 0; ri < 4; ++ri) blk[ri][ci] = Cx<R>{row[ri].re, -row[ri].im};
+        }
+      } else {
+#pragma unroll
+        for (int ri = 0; ri < 4; ++ri) {
+          const Cx<R>* row = M + (R0 + 4 * aq + ri) * a.ld + C0 + 4 * bq;
+#pragma unroll
+          for (int ci = 0; ci < 4; ++ci) blk[ri][ci] = row[ci];
+        }
+        if (diag && aq == bq) {  // diagonal block: upper entries from the lower ones
+#pragma unroll
+          for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+            for (int ci = ri + 1; ci < 4; ++ci) blk[ri][ci] = Cx<R>{blk[ci][ri].re, -blk[ci][ri].im};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+        for (int ci = 0; ci < 4; ++ci) blk[ri][ci] = Cx<R>{R(0), R(0)};
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) x[m] = blk[blk_ri(m)][blk_ci(m)];
+    mat_fwd_rounds<R, TETRA, G>(x, L, t, A, active ? static_cast<Cx<R>*>(a.out) + obase : nullptr);
+  } else {
+#pragma unroll
+    for (int rd = RD::n - 1; rd >= 0; --rd) {
+      const int bA = RD::bA[rd], bB = RD::bB[rd];
+      int rf, cf;
+      round_fixed(rd, rf, cf);
+      if (rd == RD::n - 1) {
+        const Cx<R>* in = static_cast<const Cx<R>*>(a.in) + obase;
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+          x[m] = active ? in[t + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB))] : Cx<R>{R(0), R(0)};
+      } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          x[m] = L[swz<G>(r, c)];
+        }
+      }
+      contract16<R, true, TETRA>(x, RD::opA[rd], RD::opB[rd], A);
+      if (rd > 0) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          L[swz<G>(r, c)] = x[m];
+        }
+        __syncthreads();
+      } else if (active) {
+        Cx<R> blk[4][4];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) blk[blk_ri(m)][blk_ci(m)] = x[m];
+        Cx<R>* M = static_cast<Cx<R>*>(a.out);
+#pragma unroll
+        for (int ri = 0; ri < 4; ++ri) {
+          Cx<R>* row = M + (R0 + 4 * aq + ri) * a.ld + C0 + 4 * bq;
+#pragma unroll
+          for (int ci = 0; ci < 4; ++ci) row[ci] = blk[ri][ci];
+        }
+        if (Rhi != Chi) {  // mirror tile: conjugate transpose
+#pragma unroll
+          for (int ci = 0; ci < 4; ++ci) {
+            Cx<R>* row = M + (C0 + 4 * bq + ci) * a.ld + R0 + 4 * aq;
+#pragma unroll
+            for (int ri = 0; ri < 4; ++ri) row[ri] = Cx<R>{blk[ri][ci].re, -blk[ri][ci].im};
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outcome-side pass (passes 1..): matrix side is the intermediate
+// X[(Rr, Cr)][kdone] (lower triangle of the remaining bits), outcome side is
+// X'[(Rhi, Chi)][kg * kd + kdone] or, for the last pass (PSIDE), p itself
+// (forward) / g' = F - f/p (adjoint).  A workgroup covers one (Rhi, Chi) pair
+// and J consecutive kdone values; lanes run over kdone fastest.  Logical
+// block lb, thread tid of 256; lds holds 4^G * J values; inactive (a
+// padding call): the same loads, rounds and barriers, no stores.
+// ---------------------------------------------------------------------------
+template <typename R, bool ADJ, bool TETRA, int G, int J, bool PSIDE>
+__device__ __forceinline__ void kd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t lb, unsigned tid,
+                                             Cx<R> (&lds)[J << (2 * G)], bool active) {
+  constexpr int TILE = 1 << (2 * G);
+  constexpr int NB = TILE * J / 16;  // 16-value blocks per workgroup
+  constexpr int BPT = NB / 256;      // blocks per thread
+  static_assert(NB % 256 == 0, "tile x chunk must give whole blocks per thread");
+  using RD = Rounds<G>;
+  __builtin_assume(tid < 256);
+
+  const int U = a.U, Up = U - G;
+  const int64_t kd = int64_t(1) << (2 * (a.n - U));
+  const int64_t nchunks = kd / J;
+  const int64_t ch = lb % nchunks;
+  int Rhi, Chi;
+  tri_decode(lb / nchunks, Rhi, Chi);
+  const int64_t kd0 = ch * J;
+  const int64_t obase = ((int64_t(Rhi) << Up) | Chi) * (kd * TILE);
+  double F = 0.0;
+  if constexpr (ADJ && PSIDE) F = *a.F;
+
+#pragma unroll
+  for (int step = 0; step < RD::n; ++step) {
+    const int rd = ADJ ? RD::n - 1 - step : step;
+    const int bA = RD::bA[rd], bB = RD::bB[rd];
+    const bool first = step == 0, last = step == RD::n - 1;
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = tid + 256 * bi;
+      const int j = blk % J;
+      const int u = blk / J;  // fixed-bit enumeration
+      int rf, cf;
+      fixed_bits<G>(u, bA, bB, rf, cf);
+      Cx<R> x[16];
+      if (first && !ADJ) {  // matrix side in (forward)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          const int64_t Rr = (int64_t(Rhi) << G) | r, Cr = (int64_t(Chi) << G) | c;
+          const bool mir = Rr < Cr;
+          const int64_t rr = mir ? Cr : Rr, cc = mir ? Rr : Cr;
+          Cx<R> v = static_cast<const Cx<R>*>(a.in)[((rr << U) | cc) * kd + kd0 + j];
+          if (mir) v.im = -v.im;
+          x[m] = v;
+        }
+      } else if (first) {  // outcome side in (adjoint)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
+          if constexpr (PSIDE) {
+            const int64_t k = int64_t(kg) * kd + kd0 + j;
+            x[m] = Cx<R>{cotangent(F, static_cast<const R*>(a.f)[k], static_cast<const R*>(a.p)[k]), R(0)};
+          } else {
+            x[m] = static_cast<const Cx<R>*>(a.in)[obase + int64_t(kg) * kd + kd0 + j];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          x[m] = lds[((r << G) | c) * J + j];
+        }
+      }
+      contract16<R, ADJ, TETRA>(x, RD::opA[rd], RD::opB[rd], A);
+      if (!last) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          lds[((r << G) | c) * J + j] = x[m];
+        }
+      } else if (!active) {
+        // padding call of the batched form: same loads and rounds, no stores
+      } else if constexpr (!ADJ) {  // outcome side out (forward)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
+          if constexpr (PSIDE) {
+            static_cast<R*>(a.out)[int64_t(kg) * kd + kd0 + j] = x[m].re;
+          } else {
+            static_cast<Cx<R>*>(a.out)[obase + int64_t(kg) * kd + kd0 + j] = x[m];
+          }
+        }
+      } else {  // matrix side out (adjoint): lower triangle only
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          const int64_t Rr = (int64_t(Rhi) << G) | r, Cr = (int64_t(Chi) << G) | c;
+          if (Rr >= Cr) static_cast<Cx<R>*>(a.out)[((Rr << U) | Cr) * kd + kd0 + j] = x[m];
+        }
+      }
+    }
+    if (!last) __syncthreads();
+  }
+}
+
+}  // namespace fast_pass
+}  // namespace qst

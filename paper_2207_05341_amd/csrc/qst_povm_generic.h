@@ -129,7 +129,7 @@ struct BlockWalk {
 };
 
 // Forward pass over the blocks bid0 .. bid0 + nb - 1 (see fwd_pass_body).
-template <typename R, bool TETRA, bool MATSIDE, bool PSIDE, bool UNI>
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE, bool UNI, int LB>
 __device__ __forceinline__ void fwd_pass_impl(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb) {
   const int g = a.g, J = a.J, U = a.U, n = a.n;
   const int Up = U - g;
@@ -145,10 +145,10 @@ __device__ __forceinline__ void fwd_pass_impl(const PassArgs& a, const ModeMatri
   const Cx<R>* in = static_cast<const Cx<R>*>(a.in);
   const int total = elems * nb;
   BlockWalk<UNI> walk(bid0, lgC, lgJ);
-  for (int base = 0; base < total; base += kLoadBatch * int(blockDim.x)) {
-    R vr[kLoadBatch], vi[kLoadBatch];  // scalar arrays stay in registers
+  for (int base = 0; base < total; base += LB * int(blockDim.x)) {
+    R vr[LB], vi[LB];  // scalar arrays stay in registers
 #pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
+    for (int u = 0; u < LB; ++u) {
       const int e0 = base + u * int(blockDim.x) + int(threadIdx.x);
       const int ec = e0 < total ? e0 : total - 1;
       const int e = ec & (elems - 1);
@@ -166,7 +166,7 @@ __device__ __forceinline__ void fwd_pass_impl(const PassArgs& a, const ModeMatri
       vi[u] = mirror ? -v.im : v.im;
     }
 #pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
+    for (int u = 0; u < LB; ++u) {
       const int e0 = base + u * int(blockDim.x) + int(threadIdx.x);
       if (e0 < total) buf[e0] = Cx<R>{vr[u], vi[u]};
     }
@@ -195,7 +195,7 @@ __device__ __forceinline__ void fwd_pass_impl(const PassArgs& a, const ModeMatri
 }
 
 // Adjoint pass over the blocks bid0 .. bid0 + nb - 1 (see adj_pass_body).
-template <typename R, bool TETRA, bool MATSIDE, bool PSIDE, bool UNI>
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE, bool UNI, int LB>
 __device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb) {
   const int g = a.g, J = a.J, U = a.U, n = a.n;
   const int Up = U - g;
@@ -212,11 +212,11 @@ __device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatri
   if constexpr (PSIDE) F = *a.F;
   const int total = elems * nb;
   BlockWalk<UNI> walk(bid0, lgC, lgJ);
-  for (int base0 = 0; base0 < total; base0 += kLoadBatch * int(blockDim.x)) {
-    R vr[kLoadBatch], vi[kLoadBatch];  // PSIDE: f_k and p_k
-    int dst[kLoadBatch];
+  for (int base0 = 0; base0 < total; base0 += LB * int(blockDim.x)) {
+    R vr[LB], vi[LB];  // PSIDE: f_k and p_k
+    int dst[LB];
 #pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
+    for (int u = 0; u < LB; ++u) {
       const int e0 = base0 + u * int(blockDim.x) + int(threadIdx.x);
       const int ec = e0 < total ? e0 : total - 1;
       const int e = ec & (elems - 1);
@@ -240,7 +240,7 @@ __device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatri
       }
     }
 #pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
+    for (int u = 0; u < LB; ++u) {
       if (dst[u] < 0) continue;
       // cotangent g'_k = F - f_k / p_k (F where f_k = 0)
       if constexpr (PSIDE) buf[dst[u]] = Cx<R>{cotangent(F, vr[u], vi[u]), R(0)};
@@ -276,19 +276,21 @@ __device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatri
 // virtual blocks bid0 .. bid0 + nb - 1; buf holds nb * 4^g * J complex
 // values of LDS.  The block walk runs on the scalar unit whenever a block
 // is a whole number of waves.
-template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
+// LB: values loaded per thread before any is stored (kLoadBatch, or more
+// where the caller's register budget allows).
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE, int LB = kLoadBatch>
 __device__ __forceinline__ void fwd_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
   if ((((1 << (2 * a.g)) * a.J) & 63) == 0)
-    fwd_pass_impl<R, TETRA, MATSIDE, PSIDE, true>(a, A, bid0, buf, nb);
+    fwd_pass_impl<R, TETRA, MATSIDE, PSIDE, true, LB>(a, A, bid0, buf, nb);
   else
-    fwd_pass_impl<R, TETRA, MATSIDE, PSIDE, false>(a, A, bid0, buf, nb);
+    fwd_pass_impl<R, TETRA, MATSIDE, PSIDE, false, LB>(a, A, bid0, buf, nb);
 }
-template <typename R, bool TETRA, bool MATSIDE, bool PSIDE>
+template <typename R, bool TETRA, bool MATSIDE, bool PSIDE, int LB = kLoadBatch>
 __device__ __forceinline__ void adj_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t bid0, Cx<R>* buf, int nb = 1) {
   if ((((1 << (2 * a.g)) * a.J) & 63) == 0)
-    adj_pass_impl<R, TETRA, MATSIDE, PSIDE, true>(a, A, bid0, buf, nb);
+    adj_pass_impl<R, TETRA, MATSIDE, PSIDE, true, LB>(a, A, bid0, buf, nb);
   else
-    adj_pass_impl<R, TETRA, MATSIDE, PSIDE, false>(a, A, bid0, buf, nb);
+    adj_pass_impl<R, TETRA, MATSIDE, PSIDE, false, LB>(a, A, bid0, buf, nb);
 }
 
 }  // namespace generic_pass
