@@ -134,78 +134,71 @@ __device__ __forceinline__ PassArgs pass_args(const BatchPlanTable& pl, int n, i
   return a;
 }
 
-// The SUB 256-thread groups of the workgroup take calls sub, sub + SUB, ...
-// of a pass; the call count is rounded up to a multiple of SUB (a padding
-// call stores nothing), so every group meets the same barriers.  The
-// barrier after each call protects the group's LDS area for the next call;
-// the last one also makes the pass's stores visible to the next pass.
-template <typename R, bool ADJ, bool TETRA, int G1, int J1, int SUB, int POOL>
-__device__ __forceinline__ void fast_pass_pair(const BatchArgs& b, int n, Cx<R>* rho, Cx<R>* inter, R* pvec,
-                                               const R* f, const double* Fdev, unsigned char* pool, int sub,
-                                               unsigned tid) {
+// Register-round passes of the two-pass plans.  The SUB 256-thread groups
+// of the workgroup take calls sub, sub + SUB, ... of a pass; the call count
+// is rounded up to a multiple of SUB (a padding call stores and counts
+// nothing), so every group meets the same barriers.  The barrier after
+// each call protects the group's LDS area for the next call; the last one
+// also makes the pass's stores visible to the next stage.  (The empty asm
+// keeps the compiler from hoisting the thread-index arithmetic of the
+// unrolled pass bodies out of the call loop, which kept it all live in
+// registers across the calls and spilled.)
+//
+// Pass 0 over 4 qubits: rho -> X (forward) or Y -> G' (adjoint).
+template <typename R, bool ADJ, bool TETRA, int SUB, int POOL>
+__device__ __forceinline__ void fast_pass0(const BatchArgs& b, int n, Cx<R>* rho, Cx<R>* inter, unsigned char* pool,
+                                           int sub, unsigned tid) {
   constexpr int TPW = 256 >> 4;  // tiles of pass 0 (G = 4) per 256 threads
-  typedef Cx<R> Mat4Lds[TPW << 8];
-  typedef Cx<R> KdLds[J1 << (2 * G1)];
-  static_assert(SUB * sizeof(Mat4Lds) <= size_t(POOL) && SUB * sizeof(KdLds) <= size_t(POOL),
-                "one pass buffer per 256-thread group must fit the pool");
-  const ModeMatrix& A = ADJ ? b.V : b.W;
-  PassArgs a0 = pass_args(b.plan, n, 0), a1 = pass_args(b.plan, n, 1);
-  const int64_t side0 = int64_t(1) << (a0.U - 4);
-  const int64_t tiles0 = side0 * (side0 + 1) / 2;
-  const int64_t calls0 = (tiles0 + TPW - 1) / TPW;
-  const int64_t calls1 = (int64_t(1) << (2 * (n - a1.U))) / J1;  // one (R, C) pair: the chunks
-  Mat4Lds& L0 = reinterpret_cast<Mat4Lds*>(pool)[sub];
-  KdLds& L1 = reinterpret_cast<KdLds*>(pool)[sub];
-  const int64_t end0 = (calls0 + SUB - 1) / SUB * SUB, end1 = (calls1 + SUB - 1) / SUB * SUB;
-  if constexpr (!ADJ) {
-    a0.in = rho;
-    a0.out = inter;
-    a1.in = inter;
-    a1.out = pvec;
-    for (int64_t c = sub; c < end0; c += SUB) {
-      unsigned tv = tid;
-      asm volatile("" : "+v"(tv));
-      fast_pass::mat_pass_body<R, false, TETRA, 4>(a0, A, tiles0, c, tv, L0);
-      __syncthreads();
-    }
-    for (int64_t c = sub; c < end1; c += SUB) {
-      unsigned tv = tid;
-      asm volatile("" : "+v"(tv));
-      fast_pass::kd_pass_body<R, false, TETRA, G1, J1, true>(a1, A, c < calls1 ? c : calls1 - 1, tv, L1, c < calls1);
-      __syncthreads();
-    }
-  } else {
-    a1.in = nullptr;
-    a1.out = inter;
-    a1.p = pvec;
-    a1.f = f;
-    a1.F = Fdev;
-    a0.in = inter;
-    a0.out = rho;
-    for (int64_t c = sub; c < end1; c += SUB) {
-      unsigned tv = tid;
-      asm volatile("" : "+v"(tv));
-      fast_pass::kd_pass_body<R, true, TETRA, G1, J1, true>(a1, A, c < calls1 ? c : calls1 - 1, tv, L1, c < calls1);
-      __syncthreads();
-    }
-    for (int64_t c = sub; c < end0; c += SUB) {
-      unsigned tv = tid;
-      asm volatile("" : "+v"(tv));
-      fast_pass::mat_pass_body<R, true, TETRA, 4>(a0, A, tiles0, c, tv, L0);
-      __syncthreads();
-    }
+  typedef Cx<R> Lds[TPW << 8];
+  static_assert(SUB * sizeof(Lds) <= size_t(POOL), "one pass buffer per 256-thread group must fit the pool");
+  PassArgs a = pass_args(b.plan, n, 0);
+  a.in = ADJ ? inter : rho;
+  a.out = ADJ ? rho : inter;
+  const int64_t side = int64_t(1) << (a.U - 4);
+  const int64_t tiles = side * (side + 1) / 2;
+  const int64_t calls = (tiles + TPW - 1) / TPW;
+  Lds& L = reinterpret_cast<Lds*>(pool)[sub];
+  for (int64_t c = sub; c < (calls + SUB - 1) / SUB * SUB; c += SUB) {
+    unsigned tv = tid;
+    asm volatile("" : "+v"(tv));
+    fast_pass::mat_pass_body<R, ADJ, TETRA, 4>(a, ADJ ? b.V : b.W, tiles, c, tv, L);
+    __syncthreads();
   }
 }
 
-template <typename R, bool TETRA, bool ADJ, int SUB, int POOL>
-__device__ __forceinline__ void fast_passes(const BatchArgs& b, int n, int form, Cx<R>* rho, Cx<R>* inter, R* pvec,
-                                            const R* f, const double* Fdev, unsigned char* pool, int sub,
-                                            unsigned tid) {
+// Last pass fused with the likelihood (G1 qubits, chunks of J1): X -> p in
+// registers -> NLL terms (added to L, bad0, bad1) and the cotangent
+// F - f/p -> adjoint rounds -> Y, in place of X.
+template <typename R, bool TETRA, int G1, int J1, int SUB, int POOL>
+__device__ __forceinline__ void fast_fused(const BatchArgs& b, int n, Cx<R>* inter, const R* f, double F,
+                                           unsigned char* pool, int sub, unsigned tid, double& L, double& bad0,
+                                           double& bad1) {
+  typedef Cx<R> Lds[J1 << (2 * G1)];
+  static_assert(SUB * sizeof(Lds) <= size_t(POOL), "one pass buffer per 256-thread group must fit the pool");
+  PassArgs a = pass_args(b.plan, n, 1);
+  a.in = inter;
+  a.out = inter;
+  a.f = f;
+  const int64_t calls = (int64_t(1) << (2 * (n - a.U))) / J1;  // one (R, C) pair: the chunks
+  Lds& Lb = reinterpret_cast<Lds*>(pool)[sub];
+  for (int64_t c = sub; c < (calls + SUB - 1) / SUB * SUB; c += SUB) {
+    unsigned tv = tid;
+    asm volatile("" : "+v"(tv));
+    fast_pass::kd_fused_body<R, TETRA, G1, J1>(a, b.W, b.V, c < calls ? c : calls - 1, tv, Lb, c < calls, F, L, bad0,
+                                               bad1);
+    __syncthreads();
+  }
+}
+
+template <typename R, bool TETRA, int SUB, int POOL>
+__device__ __forceinline__ void fast_fused_form(const BatchArgs& b, int n, int form, Cx<R>* inter, const R* f,
+                                                double F, unsigned char* pool, int sub, unsigned tid, double& L,
+                                                double& bad0, double& bad1) {
   constexpr int J4 = sizeof(R) == 8 ? 16 : 32;
   if (form == 4)
-    fast_pass_pair<R, ADJ, TETRA, 4, J4, SUB, POOL>(b, n, rho, inter, pvec, f, Fdev, pool, sub, tid);
+    fast_fused<R, TETRA, 4, J4, SUB, POOL>(b, n, inter, f, F, pool, sub, tid, L, bad0, bad1);
   else
-    fast_pass_pair<R, ADJ, TETRA, 3, 64, SUB, POOL>(b, n, rho, inter, pvec, f, Fdev, pool, sub, tid);
+    fast_fused<R, TETRA, 3, 64, SUB, POOL>(b, n, inter, f, F, pool, sub, tid, L, bad0, bad1);
 }
 
 template <bool BF16>
@@ -257,19 +250,31 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
 
     // 1. tau = sum |T|^2 (FP64, over bf16-rounded T for the BF16 path)
     // (kBatch loads per thread in flight, unconditional: indices past the
-    // end are clamped and their values dropped)
-    constexpr int kBatch = 4;
-    double acc = 0.0;
+    // end are clamped and their values dropped; 16 for FP32 at 512 threads,
+    // whose registers allow it)
+    // The sum of f (D = 4^n values, as many as T has) is taken in the same
+    // loop, in the order of the likelihood stage's own sum: the fused last
+    // pass needs F for the cotangent before any probability exists.
+    constexpr int kBatch = (THREADS == 512 && sizeof(R) == 4) ? 16 : 4;
+    // the two-pass plans of N = 7, 8 run the register-round passes, with the
+    // last pass fused with the likelihood (for the tetrahedral POVM in FP32
+    // and FP64: with the general 4 x 4 form, or beside the BF16 products,
+    // they would cost registers -- spills, or the second BF16 workgroup per CU)
+    const int fastp = (TETRA && !BF16) ? fast_plan(b.plan, n, sizeof(R) == 8) : 0;
+    double acc = 0.0, facc = 0.0;
     for (int64_t e0 = 0; e0 < D; e0 += kBatch * THREADS) {
       Cx<R> v[kBatch];
+      R fv[kBatch];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const int64_t e = e0 + u * THREADS + t;
         v[u] = T[e < D ? e : D - 1];
+        fv[u] = f[e < D ? e : D - 1];
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         if (e0 + u * THREADS + t >= D) continue;
+        facc += double(fv[u]);
         double x = double(v[u].re), y = double(v[u].im);
         if constexpr (BF16) {
           const float hr = bf16_value(float(v[u].re)), hi = bf16_value(float(v[u].im));
@@ -285,6 +290,7 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
       }
     }
     const double tau = block_sum_bcast<NW>(acc, red, slotp);
+    const double Fsum = block_sum_bcast<NW>(facc, red, slotp);
 
     // 2. rho = T T^dagger / tau
     if (BF16 && d >= 64 && d <= kBf16SplitMaxDim) {
@@ -355,13 +361,13 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
     Cx<R>* buf = reinterpret_cast<Cx<R>*>(pool);
     constexpr int kPoolValues = int(sizeof(pool) / sizeof(Cx<R>));
     const int P = b.plan.passes[n];
-    // the two-pass plans of N = 7, 8 run the register-round passes (for the
-    // tetrahedral POVM in FP32 and FP64: with the general 4 x 4 form, or
-    // beside the BF16 products, they would cost registers -- spills, or the
-    // second BF16 workgroup per CU)
-    const int fastp = (TETRA && !BF16) ? fast_plan(b.plan, n, sizeof(R) == 8) : 0;
+    // (two-pass plans of N = 7, 8: pass 0, then the last pass fused with
+    // the likelihood and the first adjoint pass; p is never stored)
+    double L = 0.0, F = 0.0, bad0 = 0.0, bad1 = 0.0;
     if (fastp) {
-      fast_passes<R, TETRA, false, SUB, int(sizeof(pool))>(b, n, fastp, rho, inter, pvec, f, Fdev, pool, sub, t & 255);
+      fast_pass0<R, false, TETRA, SUB, int(sizeof(pool))>(b, n, rho, inter, pool, sub, t & 255);
+      fast_fused_form<R, TETRA, SUB, int(sizeof(pool))>(b, n, fastp, inter, f, Fsum, pool, sub, t & 255, L, bad0,
+                                                       bad1);
     } else
     for (int pj = 0; pj < P; ++pj) {
       PassArgs a{};
@@ -388,7 +394,8 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
     }
 
     // 4. L, F (FP64), counters
-    double L = 0.0, F = 0.0, bad0 = 0.0, bad1 = 0.0;
+    if (fastp) F = Fsum;
+    else
     for (int64_t k0 = 0; k0 < D; k0 += kBatch * THREADS) {
       R fv[kBatch], pv[kBatch];
 #pragma unroll
@@ -411,7 +418,7 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
       }
     }
     L = block_sum_bcast<NW>(L, red, slotp);
-    F = block_sum_bcast<NW>(F, red, slotp);
+    if (!fastp) F = block_sum_bcast<NW>(F, red, slotp);
     bad0 = block_sum_bcast<NW>(bad0, red, slotp);
     bad1 = block_sum_bcast<NW>(bad1, red, slotp);
     if (t == 0) {
@@ -428,9 +435,10 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
     }
     __syncthreads();
 
-    // 5. cotangent + adjoint map: (p, f) -> G' (in the rho slot)
+    // 5. cotangent + adjoint map: (p, f) -> G' (in the rho slot); in the
+    // fused form only the adjoint pass 0 is left: Y -> G'
     if (fastp) {
-      fast_passes<R, TETRA, true, SUB, int(sizeof(pool))>(b, n, fastp, rho, inter, pvec, f, Fdev, pool, sub, t & 255);
+      fast_pass0<R, true, TETRA, SUB, int(sizeof(pool))>(b, n, rho, inter, pool, sub, t & 255);
     } else
     for (int pj = P - 1; pj >= 0; --pj) {
       PassArgs a{};

@@ -246,5 +246,148 @@ __device__ __forceinline__ void kd_pass_body(const PassArgs& a, const ModeMatrix
   }
 }
 
+// Fused last pass (the kd_fused_pass kernel of k_povm_fast.hip): chunk lb
+// of J outcome positions, thread tid of 256, lds of 4^G * J values.  F is
+// the sum of f; the NLL terms and the bad-entry counts of the chunk are
+// added to L, bad0, bad1.  Reads X = a.out and writes the adjoint
+// intermediate in place.  Inactive (a padding call): the same loads,
+// rounds and barriers, nothing stored or counted.
+template <typename R, bool TETRA, int G, int J>
+__device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatrix& Af, const ModeMatrix& Aa, int64_t lb,
+                                              unsigned tid, Cx<R> (&lds)[J << (2 * G)], bool active, double F,
+                                              double& L, double& bad0, double& bad1) {
+  constexpr int TILE = 1 << (2 * G);
+  constexpr int NB = TILE * J / 16;
+  constexpr int BPT = NB / 256;
+  static_assert(NB % 256 == 0, "tile x chunk must give whole blocks per thread");
+  using RD = Rounds<G>;
+  static_assert(RD::n >= 2, "the fused pass needs a round to exchange between");
+  __builtin_assume(tid < 256);
+
+  const int U = a.U;  // == G
+  const int64_t kd = int64_t(1) << (2 * (a.n - U));
+  const int64_t kd0 = lb * J;
+  Cx<R>* X = static_cast<Cx<R>*>(a.out);  // in place: a.in == a.out
+  const R* f = static_cast<const R*>(a.f);
+  // f for the outcomes of the last round, loaded now so that it arrives
+  // while the forward rounds run
+  R fpre[BPT][16];
+  {
+    constexpr int rl = RD::n - 1;
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = tid + 256 * bi;
+      const int j = blk % J;
+      const int u = blk / J;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int kg = u + ((m >> 2) << (2 * RD::bA[rl])) + ((m & 3) << (2 * RD::bB[rl]));
+        fpre[bi][m] = f[int64_t(kg) * kd + kd0 + j];
+      }
+    }
+  }
+
+  // forward rounds; the last one continues into the cotangent and the
+  // adjoint of the same round
+#pragma unroll
+  for (int rd = 0; rd < RD::n; ++rd) {
+    const int bA = RD::bA[rd], bB = RD::bB[rd];
+    const bool first = rd == 0, last = rd == RD::n - 1;
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = tid + 256 * bi;
+      const int j = blk % J;
+      const int u = blk / J;
+      int rf, cf;
+      fixed_bits<G>(u, bA, bB, rf, cf);
+      Cx<R> x[16];
+      if (first) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          const bool mir = r < c;
+          const int rr = mir ? c : r, cc = mir ? r : c;
+          Cx<R> v = X[((int64_t(rr) << U) | cc) * kd + kd0 + j];
+          if (mir) v.im = -v.im;
+          x[m] = v;
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          x[m] = lds[((r << G) | c) * J + j];
+        }
+      }
+      contract16<R, false, TETRA>(x, RD::opA[rd], RD::opB[rd], Af);
+      if (last) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const R fr = fpre[bi][m], pr = x[m].re;
+          const double fk = active ? double(fr) : 0.0, pk = double(pr);
+          if (fk != 0.0) {
+            if (pk > 0.0) {
+              L -= fk * ln_prob(pr);
+            } else {
+              bad0 += 1.0;
+            }
+          }
+          if (active && (pk != pk || fk != fk)) bad1 += 1.0;
+          x[m] = Cx<R>{cotangent(F, fr, pr), R(0)};
+        }
+        contract16<R, true, TETRA>(x, RD::opA[rd], RD::opB[rd], Aa);
+      }
+      // the exchange positions of this block are this thread's alone in the
+      // round, so the adjoint values can replace the forward ones directly
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        int r, c;
+        rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+        lds[((r << G) | c) * J + j] = x[m];
+      }
+    }
+    __syncthreads();
+  }
+  // remaining adjoint rounds, last forward round excluded
+#pragma unroll
+  for (int rd = RD::n - 2; rd >= 0; --rd) {
+    const int bA = RD::bA[rd], bB = RD::bB[rd];
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = tid + 256 * bi;
+      const int j = blk % J;
+      const int u = blk / J;
+      int rf, cf;
+      fixed_bits<G>(u, bA, bB, rf, cf);
+      Cx<R> x[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        int r, c;
+        rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+        x[m] = lds[((r << G) | c) * J + j];
+      }
+      contract16<R, true, TETRA>(x, RD::opA[rd], RD::opB[rd], Aa);
+      if (rd > 0) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          lds[((r << G) | c) * J + j] = x[m];
+        }
+      } else if (active) {  // matrix side out: lower triangle only
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          int r, c;
+          rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
+          if (r >= c) X[((int64_t(r) << U) | c) * kd + kd0 + j] = x[m];
+        }
+      }
+    }
+    if (rd > 0) __syncthreads();
+  }
+}
+
+
 }  // namespace fast_pass
 }  // namespace qst
