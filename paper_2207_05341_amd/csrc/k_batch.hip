@@ -89,11 +89,12 @@ __device__ double block_sum_bcast(double v, double* redw, double* slot) {
   return r;
 }
 
-// Product tiles of the batched kernel.
+// Product tiles of the batched kernel: two LDS panel buffers, since the
+// 256-thread groups of a workgroup meet at every barrier.
 template <typename R>
-using BatchHerk = gemm::CxPolicy<R, true>;
+using BatchHerk = gemm::CxPolicy<R, true, true, true>;
 template <typename R>
-using BatchHemm = gemm::CxPolicy<R, false>;
+using BatchHemm = gemm::CxPolicy<R, false, true, true>;
 
 // THREADS = 256 x SUB: the element loops use every thread; the product
 // stages run SUB tiles at a time, one per 256-thread group, each with its own
