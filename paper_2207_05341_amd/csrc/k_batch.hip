@@ -96,22 +96,20 @@ using BatchHerk = gemm::CxPolicy<R, true, true, true>;
 template <typename R>
 using BatchHemm = gemm::CxPolicy<R, false, true, true>;
 
-// THREADS = 256 x SUB: the element loops use every thread; the product
-// stages run SUB tiles at a time, one per 256-thread group, each with its own
-// panel buffers.  Every group makes the same number of tile calls (a tile
-// list is padded to a multiple of SUB; a padding call recomputes tile 0 and
-// stores nothing), so the barriers inside the tile code stay matched.
-// Barrier after one call of a POVM pass.  Between calls of the same pass
-// (more to come) only the LDS buffer is reused: the call's global stores
-// go to a different array than the pass reads, so they need not complete
-// before the next call's loads start (no fence, just the barrier).  After
-// a pass's last call, or when a pass reads the array it writes, the full
-// barrier makes the stores visible to the whole workgroup.
+// Barrier after one call of a generic POVM pass.  Between calls of a pass
+// that reads another array than it writes, only the LDS buffer is reused:
+// fences that order LDS accesses alone (the call's global stores need not
+// complete before the next call starts).  After the last call, or when a
+// pass reads the array it writes, the full barrier makes the stores
+// visible to the whole workgroup.
 __device__ __forceinline__ void pass_call_barrier(const PassArgs& a, bool more) {
-  if (more && a.in != a.out)
+  if (more && a.in != a.out) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
-  else
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  } else {
     __syncthreads();
+  }
 }
 
 // Which register-round form covers an instance's POVM plan: 4 (pass 0 over
@@ -205,6 +203,11 @@ __device__ __forceinline__ void fast_fused_form(const BatchArgs& b, int n, int f
 template <bool BF16>
 constexpr int kBatchPoolBytes = BF16 ? 65536 : 131072;
 
+// THREADS = 256 x SUB: the element loops use every thread; the product
+// stages run SUB tiles at a time, one per 256-thread group, each with its own
+// panel buffers.  Every group makes the same number of tile calls (a tile
+// list is padded to a multiple of SUB; a padding call recomputes tile 0 and
+// stores nothing), so the barriers inside the tile code stay matched.
 template <class PH, class PM, typename R, bool TETRA, bool BF16, int THREADS>
 __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
   constexpr int SUB = THREADS / 256, NW = THREADS / 64;
