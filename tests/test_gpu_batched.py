@@ -134,9 +134,11 @@ def test_batch_graph_replay_equals_eager_and_single_path(batch1024):
 
 
 def test_batch_small_n_and_general_povm():
-    """Instances down to N = 1, and a non-tetrahedral POVM (generic kernels)."""
+    """Instances from N = 1 to 8 with a non-tetrahedral POVM: the generic
+    pass kernels, also for the two-pass plans of N = 7, 8 (which run the
+    register-round passes for the tetrahedral POVM)."""
     say("batched small N and general POVM (f64)")
-    ns, Ts, fs = make_batch(40, 31, lo=1, hi=6, shots=2000)
+    ns, Ts, fs = make_batch(40, 31, lo=1, hi=8, shots=2000)
     g = S.rng(32)
     U, _ = np.linalg.qr(S.ginibre(g, 2))
     M = np.array([U @ m @ U.conj().T for m in O.tetrahedral_povm()])
