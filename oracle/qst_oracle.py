@@ -10,6 +10,9 @@ What it computes, written from the paper (Wang, Cheng, Li, Chen,
 * state map   rho = T T^dagger / Tr(T T^dagger)
               (Sec. 2.2.1 Eq. T_matrix; Sec. 3.2 Eq. unified_DP and Eq. abs_P
               at P = 2 -- see the reading of T^dagger T vs T T^dagger below)
+* modes       the pre-maps of Chol_H (Hermitian part, Sec. 2.2.2 and
+              Eq. unified_DP) and Chol_Delta (lower triangle, Eq. T_matrix),
+              and the P-order absolute projection (Eq. abs_P) by eigh
 * Born rule   p_k = Tr(M_k rho)                  (Sec. 2.1, Born rule)
 * product POVM M_k = M_{k_1} (x) ... (x) M_{k_N}   (Sec. 3.3)
 * tetrahedral single-qubit POVM M_a = (I + s_a . sigma)/4   (Sec. 4.1 setup)
@@ -107,6 +110,45 @@ def state_map(T: np.ndarray) -> tuple[np.ndarray, float]:
     tau = trace_tt(a)
     rho = (a @ a.conj().T) / tau
     return rho, tau
+
+
+# State-map modes applied to the network output before the state map.
+# Chol_Delta (Sec. 2.2.1 Eq. T_matrix): T lower triangular.  Chol_H (Sec. 3.2
+# Eq. unified_DP, the paper's default): T Hermitian, made so by the Hermitian
+# part (X + X^dagger)/2 (Sec. 2.2.2, the remark on non-Hermitian matrices).
+# Both are orthogonal projections for the real inner product Re Tr(A^dagger
+# B), hence self-adjoint: the same map sends dL/dT' back to dL/dT.
+# ----------------------------------------------------------------------------
+
+def hermitian_part(X: np.ndarray) -> np.ndarray:
+    """(X + X^dagger) / 2."""
+    a = np.asarray(X, dtype=np.complex128)
+    return (a + a.conj().T) / 2.0
+
+
+def lower_part(X: np.ndarray) -> np.ndarray:
+    """Lower triangle of X (row >= column), strict upper part zero."""
+    return np.tril(np.asarray(X, dtype=np.complex128))
+
+
+def premap(X: np.ndarray, mode: str) -> np.ndarray:
+    """The pre-map of a state-map mode: 'plain' (identity), 'hermitian'
+    (Chol_H) or 'lower' (Chol_Delta)."""
+    if mode == "plain":
+        return np.asarray(X, dtype=np.complex128)
+    if mode == "hermitian":
+        return hermitian_part(X)
+    if mode == "lower":
+        return lower_part(X)
+    raise ValueError(mode)
+
+
+def abs_projection(H: np.ndarray, P: float) -> np.ndarray:
+    """P-order absolute projection of a Hermitian H = Q Lambda Q^dagger
+    (Sec. 3.2 Eq. abs_P): Q |Lambda|^P Q^dagger / Tr |Lambda|^P."""
+    lam, Q = np.linalg.eigh(np.asarray(H, dtype=np.complex128))
+    w = np.abs(lam) ** P
+    return (Q * (w / math.fsum(w.tolist()))) @ Q.conj().T
 
 
 # ----------------------------------------------------------------------------
@@ -320,6 +362,14 @@ def grad_T(T: np.ndarray, f: np.ndarray, povm: np.ndarray | None = None):
 
 def loss_of_T(T: np.ndarray, f: np.ndarray, povm: np.ndarray | None = None) -> float:
     return likelihood(T, f, povm)[0]
+
+
+def grad_T_mode(T: np.ndarray, f: np.ndarray, mode: str, povm: np.ndarray | None = None):
+    """Gradient through a state-map mode: L(premap(T)); the pre-map is
+    self-adjoint, so dL/dT = premap(dL/dT' at T' = premap(T)).
+    Returns (grad, L)."""
+    g, L = grad_T(premap(T, mode), f, povm)
+    return premap(g, mode), L
 
 
 # ----------------------------------------------------------------------------

@@ -431,3 +431,80 @@ def test_adam_matches_torch():
         opt.step()
     np.testing.assert_allclose(P.detach().numpy(), Tn, atol=1e-13)
     assert losses[-1] < losses[0]
+
+
+# --------------------------------------------------------------------------
+# State-map modes (Sec. 2.2.1 Eq. T_matrix; Sec. 2.2.2; Sec. 3.2
+# Eq. unified_DP, Eq. abs_P)
+# --------------------------------------------------------------------------
+
+def re_inner(A, B):
+    """Re Tr(A^dagger B), written out entrywise."""
+    return float(np.sum(A.real * B.real + A.imag * B.imag))
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_premaps_are_orthogonal_projections(n):
+    """Hermitian part and lower triangle: their images are Hermitian /
+    lower-triangular matrices, they fix those, they are idempotent, and they
+    are self-adjoint for Re Tr(A^dagger B) (so they also map dL/dT' back)."""
+    g = S.rng(1300 + n)
+    d = 1 << n
+    X, Y = S.ginibre(g, d), S.ginibre(g, d)
+    H = O.hermitian_part(X)
+    for r in range(d):
+        for c in range(d):
+            # entrywise definition: (X_rc + conj(X_cr)) / 2
+            want = (X[r, c] + np.conj(X[c, r])) / 2
+            assert H[r, c] == want
+    assert np.array_equal(H, H.conj().T)
+    assert np.array_equal(O.hermitian_part(H), H)
+    Lo = O.lower_part(X)
+    for r in range(d):
+        for c in range(d):
+            assert Lo[r, c] == (X[r, c] if c <= r else 0)
+    assert np.array_equal(O.lower_part(Lo), Lo)
+    for mode in ("hermitian", "lower"):
+        a = re_inner(O.premap(X, mode), Y)
+        b = re_inner(X, O.premap(Y, mode))
+        assert abs(a - b) <= 1e-13 * (abs(a) + 1.0)
+    assert np.array_equal(O.premap(X, "plain"), X)
+
+
+def test_abs_projection_closed_form_and_cholh():
+    """Eq. abs_P on a diagonal H is diag(|lambda|^P) / sum |lambda|^P; for a
+    Hermitian T, P = 2 is Eq. unified_DP: T T^dagger / Tr(T T^dagger)
+    (the library eigensolver against a plain product)."""
+    lam = np.array([2.0, -0.5, 0.0, -3.0])
+    for P in (0.5, 1.0, 2.0, 3.5):
+        w = np.abs(lam) ** P
+        np.testing.assert_allclose(O.abs_projection(np.diag(lam), P), np.diag(w / w.sum()), atol=1e-15)
+    g = S.rng(1310)
+    for n in (2, 4):
+        H = O.hermitian_part(S.ginibre(g, 1 << n))
+        rho, _ = O.state_map(H)
+        np.testing.assert_allclose(O.abs_projection(H, 2.0), rho, atol=1e-14)
+        R = O.abs_projection(H, 1.3)
+        assert abs(np.trace(R).real - 1.0) <= 1e-13
+        assert np.min(np.linalg.eigvalsh(R)) >= -1e-14
+
+
+@pytest.mark.parametrize("mode", ["hermitian", "lower"])
+def test_mode_gradient_central_differences(mode):
+    """L(premap(T)) by central differences on random complex directions
+    against Re<grad_T_mode, E>; the gradient lies in the mode's image."""
+    g = S.rng(1320 + len(mode))
+    n, d = 3, 8
+    T = S.ginibre(g, d)
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 5000, O.probs_real(S.depolarised_pure(psi, 0.2)))
+    grad, L = O.grad_T_mode(T, f, mode)
+    assert L == O.loss_of_T(O.premap(T, mode), f)
+    h = 1e-5 * np.linalg.norm(T)
+    for E in S.unit_directions(g, d, 6):
+        fd = (O.loss_of_T(O.premap(T + h * E, mode), f) - O.loss_of_T(O.premap(T - h * E, mode), f)) / (2 * h)
+        assert abs(fd - re_inner(grad, E)) <= 1e-6 * np.linalg.norm(grad) + 1e-12
+    if mode == "hermitian":
+        assert np.max(np.abs(grad - grad.conj().T)) <= 1e-15 * np.max(np.abs(grad)) * 10
+    else:
+        assert np.all(np.triu(grad, 1) == 0)
