@@ -195,6 +195,48 @@ def batched(qst, prec, dev, reps=20):
             "tflops": flops / (graph_ms * 1e-3) / 1e12, "tuned": info}
 
 
+def state_maps(qst, T, f, prec, reps=50):
+    """The paper's two decomposition modes at the bench size: the pre-map
+    kernels alone (achieved GB/s from algorithmic bytes: the Hermitian part
+    reads and writes d^2 complex values, the lower triangle reads the lower
+    d(d+1)/2 and writes d^2) and one fwd+bwd step through each mode (pre-map,
+    qst_likelihood, qst_grad_product, pre-map of the gradient)."""
+    import torch
+
+    d = T.shape[0]
+    cb = T.element_size()
+    Y = torch.empty_like(T)
+    out = {}
+    for mode, nbytes in (("hermitian", 2 * d * d * cb), ("lower", (d * (d + 1) // 2 + d * d) * cb)):
+        for _ in range(3):
+            qst.state_premap(T, mode, prec, out=Y)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            qst.state_premap(T, mode, prec, out=Y)
+        ev1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * ev0.elapsed_time(ev1) / reps
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out[mode + "_premap"] = {"us": round(us, 2), "GB_s": round(gbs, 1), "hbm_frac": round(gbs / 8000.0, 3)}
+
+    def mode_step(mode):
+        Tp = qst.state_premap(T, mode, prec)
+        o, tau, G, _ = qst.likelihood_forward(Tp, f, prec)
+        return o, qst.state_premap(qst.grad_product(G, Tp, tau, prec), mode, prec)
+
+    for mode, key in (("hermitian", "chol_h"), ("lower", "chol_delta")):
+        for _ in range(3):
+            mode_step(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mode_step(mode)
+        torch.cuda.synchronize()
+        out[key + "_evals_per_s"] = round(reps / (time.perf_counter() - t0), 1)
+    return out
+
+
 def cpu_baseline(T, f, prec):
     """FP64 oracle on a bounded sample: full forward + adjoint evaluations of
     the same N = 11 workload (the measured precision's T and f widened)."""
@@ -346,6 +388,9 @@ def main():
             "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()},
             "note": "qst_state_map, qst_povm_probs, qst_nll, qst_nll_backward with p stored"}
 
+    Tm, fm = to_prec(T_np, f_np, args.prec, dev)
+    modes = state_maps(qst, Tm, fm, args.prec)
+    del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
 
@@ -372,6 +417,7 @@ def main():
         "kernels_us": {k: round(v, 2) for k, v in sorted(kern_us.items())},
         "povm_pass_gbs": {k: round(v, 1) for k, v in povm_gbs.items()},
         "paths": paths,
+        "state_maps": modes,
         "batched": batch,
         "device": torch.cuda.get_device_name(0),
     }

@@ -198,6 +198,33 @@ qst_status qst_grad_product(int n_qubits, qst_prec prec, const void* G, int64_t 
                             int64_t ldT, const double* tau_dev, const double* upstream_dev,
                             void* gradT, int64_t ld_grad, void* ws, size_t ws_bytes, void* stream);
 
+typedef enum {
+  /* Y = (X + X^dagger) / 2: the Hermitian part.  Applied to T before the
+   * state map it gives Chol_H, the paper's default map (Sec. 3.2
+   * Eq. unified_DP, equal to Eq. abs_P at P = 2); the Hermitian part of a
+   * non-Hermitian matrix is the remark of Sec. 2.2.2. */
+  QST_PREMAP_HERMITIAN = 1,
+  /* Y = X on and below the diagonal (row >= column), 0 above: Chol_Delta,
+   * the Cholesky-form decomposition with a lower-triangular T (Sec. 2.2.1
+   * Eq. T_matrix). */
+  QST_PREMAP_LOWER = 2
+} qst_premap;
+
+/*
+ * Pre-map of a state-map mode, Y = P(X), with P one of qst_premap.  Both
+ * maps are orthogonal projections for the real inner product Re Tr(A^dagger
+ * B), hence self-adjoint: the same call maps dL/dT' (the gradient of the
+ * other calls, taken at T' = P(T)) to dL/dT.
+ *   mode     [in]  QST_PREMAP_HERMITIAN or QST_PREMAP_LOWER.
+ *   X        [in]  d x d complex, row stride ldX, device.
+ *   Y        [out] d x d complex, row stride ldY, device.  Y == X (with
+ *                  ldY == ldX) works in place; otherwise Y must not overlap X.
+ * Elementwise: the result is bitwise the definition's ((x + conj y) * 0.5 in
+ * the storage precision; a copy or a zero).  No workspace.
+ */
+qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X, int64_t ldX, void* Y,
+                            int64_t ldY, void* stream);
+
 /* Workspace in bytes needed by op (a qst_op) at (n_qubits, prec); 0 for an
  * invalid request. */
 size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op);

@@ -15,12 +15,12 @@ import torch
 
 from . import _lib
 from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
-                   QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS, QST_OP_STATE_MAP, QstError,
-                   workspace_bytes)
+                   QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS, QST_OP_STATE_MAP, QST_PREMAP_HERMITIAN,
+                   QST_PREMAP_LOWER, QstError, workspace_bytes)
 
 __all__ = [
-    "PRECISIONS", "state_map", "povm_probs", "nll", "nll_backward", "likelihood_forward", "grad_product",
-    "likelihood", "LikelihoodFn",
+    "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
+    "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
 
@@ -94,6 +94,43 @@ def _povm_arg(povm):
     m = torch.as_tensor(povm).to(torch.complex128).reshape(4, 2, 2)
     flat = torch.view_as_real(m.contiguous()).reshape(-1).tolist()
     return (ctypes.c_double * 32)(*flat)
+
+
+#: State-map modes: the pre-map applied to T before rho = T' T'^dagger / Tr.
+#: "plain" (none), "hermitian" (Chol_H: (T + T^dagger)/2, the paper's
+#: default), "lower" (Chol_Delta: lower triangle of T).
+STATE_MAPS = {"plain": 0, "hermitian": QST_PREMAP_HERMITIAN, "lower": QST_PREMAP_LOWER}
+
+
+def state_premap(X: torch.Tensor, mode: str, prec=None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Y = P(X) for the pre-map of a state-map mode ("hermitian" or "lower");
+    out=X works in place.  P is self-adjoint, so it also maps dL/dT' to dL/dT."""
+    if mode not in ("hermitian", "lower"):
+        raise ValueError(f"unknown pre-map {mode!r}")
+    n, ld = _matrix(X, "X")
+    p = _prec(X.dtype, prec)
+    if out is None:
+        out = torch.empty(X.shape, dtype=X.dtype, device=X.device)
+    else:
+        n2, _ = _matrix(out, "out")
+        if n2 != n or out.dtype != X.dtype:
+            raise ValueError("out must match X in size and dtype")
+    _lib.check(_lib.lib().qst_state_premap(n, p, STATE_MAPS[mode], X.data_ptr(), ld, out.data_ptr(), out.stride(0),
+                                           _stream(X.device)), "qst_state_premap")
+    return out
+
+
+class StatePremapFn(torch.autograd.Function):
+    """T' = P(T) with backward dL/dT = P(dL/dT') (P self-adjoint)."""
+
+    @staticmethod
+    def forward(ctx, T, mode, prec):
+        ctx.mode, ctx.prec = mode, prec
+        return state_premap(T, mode, prec)
+
+    @staticmethod
+    def backward(ctx, g):
+        return state_premap(g.contiguous(), ctx.mode, ctx.prec), None, None
 
 
 def state_map(T: torch.Tensor, prec=None):
@@ -242,15 +279,21 @@ class LikelihoodFn(torch.autograd.Function):
 
 
 def likelihood(T: torch.Tensor, f: torch.Tensor, prec=None, recompute: bool | None = None, povm=None,
-               mode: str | None = None):
+               mode: str | None = None, state_map: str = "plain"):
     """Differentiable negative log-likelihood (0-dim float64 tensor).
 
     mode: "fused" (default), "stored" or "recompute" (see LikelihoodFn).
-    recompute=True / False select "recompute" / "stored" when mode is None."""
+    recompute=True / False select "recompute" / "stored" when mode is None.
+    state_map: "plain" (rho from T), "hermitian" (Chol_H) or "lower"
+    (Chol_Delta): rho from the pre-mapped T (see STATE_MAPS)."""
     if mode is None:
         mode = "fused" if recompute is None else ("recompute" if recompute else "stored")
     if mode not in ("fused", "stored", "recompute"):
         raise ValueError(f"unknown mode {mode!r}")
+    if state_map not in STATE_MAPS:
+        raise ValueError(f"unknown state map {state_map!r}")
+    if state_map != "plain":
+        T = StatePremapFn.apply(T, state_map, prec)
     return LikelihoodFn.apply(T, f, prec, mode, povm)
 
 

@@ -15,6 +15,7 @@ QST_F64, QST_F32, QST_BF16GEMM = 0, 1, 2
 QST_OP_STATE_MAP, QST_OP_POVM_PROBS, QST_OP_NLL, QST_OP_NLL_BACKWARD = 0, 1, 2, 3
 QST_OP_LIKELIHOOD, QST_OP_GRAD_PRODUCT = 4, 5
 QST_MAX_QUBITS = 13
+QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER = 1, 2
 
 #: Every symbol include/qst.h declares, with (restype, argtypes).
 _vp, _i64, _sz, _int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int
@@ -25,6 +26,7 @@ SIGNATURES = {
     "qst_nll_backward": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_likelihood": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_grad_product": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
+    "qst_state_premap": (_int, [_int, _int, _int, _vp, _i64, _vp, _i64, _vp]),
     "qst_workspace_bytes": (_sz, [_int, _int, _int]),
     "qst_status_string": (ctypes.c_char_p, [_int]),
     "qst_last_error": (ctypes.c_char_p, []),

@@ -63,6 +63,20 @@ qst_status qst_state_map(int n, qst_prec prec, const void* T, int64_t ldT, void*
   return QST_OK;
 }
 
+qst_status qst_state_premap(int n, qst_prec prec, int mode, const void* X, int64_t ldX, void* Y, int64_t ldY,
+                            void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(X, ldX, n, "X", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(Y, ldY, n, "Y", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_premap(mode, X, ldX, Y, ldY, msg)) != QST_OK) return fail(st, msg);
+  hipError_t e = launch_premap(prec, mode, X, ldX, Y, ldY, n, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "state pre-map");
+  clear_error();
+  return QST_OK;
+}
+
 qst_status qst_povm_probs(int n, qst_prec prec, const void* rho, int64_t ld_rho, const double* povm_host,
                           void* p, void* ws, size_t ws_bytes, void* stream) {
   std::string msg;

@@ -31,6 +31,10 @@ class ProfScope {
 // partials + kReduceBlocks.  planes (QST_BF16GEMM with d > kBf16SplitMaxDim,
 // else ignored; may be NULL): receives bf16(T) as re and im planes (d x d
 // row-major each, 4 d^2 bytes), the operands launch_herk takes.
+// State-map pre-map (qst_premap mode) of a d x d complex matrix; Y may be X.
+hipError_t launch_premap(qst_prec prec, int mode, const void* X, int64_t ldx, void* Y, int64_t ldy, int n,
+                         hipStream_t s);
+
 hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* partials,
                       double* tau_dev, hipStream_t s, const void* f = nullptr, void* planes = nullptr);
 

@@ -225,6 +225,18 @@ qst_status check_povm(const double* M, std::string& msg) {
   return QST_OK;
 }
 
+qst_status check_premap(int mode, const void* X, int64_t ldX, const void* Y, int64_t ldY, std::string& msg) {
+  if (mode != QST_PREMAP_HERMITIAN && mode != QST_PREMAP_LOWER) {
+    msg = "unknown pre-map mode " + std::to_string(mode);
+    return QST_ERR_INVALID_ARG;
+  }
+  if (X == Y && ldX != ldY) {
+    msg = "in place (Y == X) needs ldY == ldX";
+    return QST_ERR_INVALID_ARG;
+  }
+  return QST_OK;
+}
+
 void povm_mode_matrices(const double* M, double W[32], double V[32]) {
   // Tetrahedral POVM of Sec. 4.1: M_a = (I + s_a . sigma)/4, s_a = (+-1,+-1,+-1)/sqrt(3).
   double tet[32];

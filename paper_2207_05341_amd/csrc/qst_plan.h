@@ -91,6 +91,8 @@ qst_status check_matrix(const void* ptr, int64_t ld, int n, const char* name, st
 qst_status check_ptr(const void* ptr, const char* name, std::string& msg);
 qst_status check_ws(const void* ws, size_t ws_bytes, size_t need, std::string& msg);
 qst_status check_povm(const double* povm_host, std::string& msg);
+// Mode and in-place rule of qst_state_premap (Y == X needs ldY == ldX).
+qst_status check_premap(int mode, const void* X, int64_t ldX, const void* Y, int64_t ldY, std::string& msg);
 
 // Per-thread last-error message.
 void set_error(const std::string& msg);

@@ -220,6 +220,23 @@ def test_grad_product_validation(L):
     assert call(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
 
 
+def test_premap_validation(L):
+    H, Lo = lib_mod.QST_PREMAP_HERMITIAN, lib_mod.QST_PREMAP_LOWER
+
+    def call(n=4, prec=0, mode=H, X=FAKE, ldX=16, Y=FAKE2, ldY=16):
+        return L.qst_state_premap(n, prec, mode, X, ldX, Y, ldY, None)
+
+    assert call(n=0) == lib_mod.QST_ERR_INVALID_ARG and "n_qubits" in _err(L)
+    assert call(prec=7) == lib_mod.QST_ERR_INVALID_ARG and "precision" in _err(L)
+    assert call(mode=0) == lib_mod.QST_ERR_INVALID_ARG and "mode" in _err(L)
+    assert call(mode=3) == lib_mod.QST_ERR_INVALID_ARG and "mode" in _err(L)
+    assert call(mode=Lo, X=None) == lib_mod.QST_ERR_INVALID_ARG and "X is NULL" in _err(L)
+    assert call(Y=None) == lib_mod.QST_ERR_INVALID_ARG and "Y is NULL" in _err(L)
+    assert call(ldX=15) == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
+    assert call(ldY=8) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(Y=FAKE, ldY=32) == lib_mod.QST_ERR_INVALID_ARG and "in place" in _err(L)
+
+
 def test_plan_unit_builds_without_hip(tmp_path):
     """The validation / planning unit is HIP-free: it compiles with g++."""
     src = os.path.join(ROOT, "paper_2207_05341_amd", "csrc", "qst_plan.cpp")
