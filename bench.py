@@ -237,6 +237,39 @@ def state_maps(qst, T, f, prec, reps=50):
     return out
 
 
+def fidelities(qst, T, prec, reps=20):
+    """Fidelity calls at the bench size: F_q against a rank-8 target (as in
+    the training workload; three launches, reading T once) and F_c between
+    two 4^N probability vectors.  Achieved GB/s from algorithmic bytes."""
+    import numpy as np
+    import torch
+
+    import synth as S
+
+    d = T.shape[0]
+    g = S.rng(11)
+    ct = np.complex128 if prec == "f64" else np.complex64
+    W = torch.from_numpy(S.ginibre(g, d, 8).astype(ct)).to(T.device)
+    rt = torch.float64 if prec == "f64" else torch.float32
+    pa = torch.from_numpy(S.porter_thomas_probs(g, d * d, 0.1)).to(T.device, rt)
+    pb = torch.from_numpy(S.porter_thomas_probs(g, d * d, 0.2)).to(T.device, rt)
+    out = {}
+    for key, fn, nbytes in (("lowrank_r8", lambda: qst.fidelity_lowrank(T, W, prec), (d * d + 8 * d) * T.element_size()),
+                            ("classical", lambda: qst.fidelity_classical(pa, pb, prec), 2 * d * d * pa.element_size())):
+        for _ in range(3):
+            fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * ev0.elapsed_time(ev1) / reps
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out[key] = {"us": round(us, 2), "GB_s": round(gbs, 1), "hbm_frac": round(gbs / 8000.0, 3)}
+    return out
+
+
 def cpu_baseline(T, f, prec):
     """FP64 oracle on a bounded sample: full forward + adjoint evaluations of
     the same N = 11 workload (the measured precision's T and f widened)."""
@@ -390,6 +423,7 @@ def main():
 
     Tm, fm = to_prec(T_np, f_np, args.prec, dev)
     modes = state_maps(qst, Tm, fm, args.prec)
+    fids = fidelities(qst, Tm, args.prec)
     del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
@@ -418,6 +452,7 @@ def main():
         "povm_pass_gbs": {k: round(v, 1) for k, v in povm_gbs.items()},
         "paths": paths,
         "state_maps": modes,
+        "fidelity": fids,
         "batched": batch,
         "device": torch.cuda.get_device_name(0),
     }

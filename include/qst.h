@@ -50,6 +50,7 @@ extern "C" {
 #endif
 
 #define QST_MAX_QUBITS 13
+#define QST_FIDELITY_MAX_RANK 32
 
 typedef enum {
   QST_OK = 0,
@@ -81,7 +82,8 @@ typedef enum {
   QST_OP_NLL = 2,
   QST_OP_NLL_BACKWARD = 3,
   QST_OP_LIKELIHOOD = 4,
-  QST_OP_GRAD_PRODUCT = 5
+  QST_OP_GRAD_PRODUCT = 5,
+  QST_OP_FIDELITY = 6
 } qst_op;
 
 /*
@@ -224,6 +226,36 @@ typedef enum {
  */
 qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X, int64_t ldX, void* Y,
                             int64_t ldY, void* stream);
+
+/*
+ * Quantum fidelity against a target of low rank r (Sec. 2.3 Eq. F_QF):
+ *   F_q = (Tr sqrt(sqrt(rho_hat) rho sqrt(rho_hat)))^2,
+ *   rho_hat = T T^dagger / Tr(T T^dagger)   (the state map of T),
+ *   rho     = W W^dagger / Tr(W W^dagger)   (the target, W d x r).
+ * sqrt(rho_hat) rho sqrt(rho_hat) and the r x r matrix
+ * C = (W^dagger T)(W^dagger T)^dagger / (Tr(T T^dagger) Tr(W W^dagger))
+ * have the same nonzero eigenvalues, so F_q = (sum_i sqrt(lambda_i(C)))^2
+ * from an r x r Hermitian eigensolve (cyclic Jacobi in FP64; negative
+ * rounding-level eigenvalues read as 0).  A pure target psi is r = 1:
+ * F_q = |psi^dagger T|^2 / (Tr(T T^dagger) |psi|^2).  Sums in FP64, fixed
+ * order (bitwise reproducible).
+ *   T      [in]  d x d complex, row stride ldT, device (pass the pre-mapped
+ *                T' of a state-map mode).
+ *   W      [in]  d x r complex, row stride ldW >= r (row i holds W_i0 ..
+ *                W_i,r-1), device.  1 <= r <= QST_FIDELITY_MAX_RANK.
+ *   F_dev  [out] one double, device.
+ */
+qst_status qst_fidelity_lowrank(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* W,
+                                int64_t ldW, int r, double* F_dev, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Classical fidelity (Sec. 2.3 Eq. F_CF): F_c = (sum_k sqrt(p_hat_k p_k))^2
+ * with negative entries read as 0, summed in FP64 in a fixed order.
+ *   p_hat, p [in]  4^N reals each, device.
+ *   F_dev    [out] one double, device.
+ */
+qst_status qst_fidelity_classical(int n_qubits, qst_prec prec, const void* p_hat, const void* p, double* F_dev,
+                                  void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace in bytes needed by op (a qst_op) at (n_qubits, prec); 0 for an
  * invalid request. */

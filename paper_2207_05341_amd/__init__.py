@@ -15,12 +15,13 @@ import torch
 
 from . import _lib
 from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
-                   QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS, QST_OP_STATE_MAP, QST_PREMAP_HERMITIAN,
-                   QST_PREMAP_LOWER, QstError, workspace_bytes)
+                   QST_FIDELITY_MAX_RANK, QST_OP_FIDELITY, QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS,
+                   QST_OP_STATE_MAP, QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER, QstError, workspace_bytes)
 
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
-    "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn",
+    "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "fidelity_lowrank",
+    "fidelity_classical",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
 
@@ -237,6 +238,36 @@ def grad_product(G: torch.Tensor, T: torch.Tensor, tau: torch.Tensor, prec=None,
                                            _ptr(upstream), grad.data_ptr(), grad.stride(0), _ptr(ws), nb,
                                            _stream(T.device)), "qst_grad_product")
     return grad
+
+
+def fidelity_lowrank(T: torch.Tensor, W: torch.Tensor, prec=None) -> torch.Tensor:
+    """F_q(T T^dagger / Tr, W W^dagger / Tr) for a d x r target factor W
+    (r <= QST_FIDELITY_MAX_RANK; a pure state is a d x 1 W), as a 0-dim
+    float64 device tensor."""
+    n, ld = _matrix(T, "T")
+    if W.dim() != 2 or W.shape[0] != T.shape[0] or W.dtype != T.dtype or not W.is_cuda or W.stride(1) != 1:
+        raise ValueError("W must be a d x r row-major GPU matrix of T's dtype")
+    r = W.shape[1]
+    pr = _prec(T.dtype, prec)
+    F = torch.empty((), dtype=torch.float64, device=T.device)
+    ws, nb = _workspace(n, pr, QST_OP_FIDELITY, T.device)
+    _lib.check(_lib.lib().qst_fidelity_lowrank(n, pr, T.data_ptr(), ld, W.data_ptr(), W.stride(0), r, F.data_ptr(),
+                                               _ptr(ws), nb, _stream(T.device)), "qst_fidelity_lowrank")
+    return F
+
+
+def fidelity_classical(p_hat: torch.Tensor, p: torch.Tensor, prec=None) -> torch.Tensor:
+    """F_c = (sum_k sqrt(p_hat_k p_k))^2 as a 0-dim float64 device tensor."""
+    n = (p.numel().bit_length() - 1) // 2
+    pr = QST_F64 if (prec is None and p.dtype == torch.float64) else (
+        QST_F32 if prec is None else (PRECISIONS[prec] if isinstance(prec, str) else int(prec)))
+    _vector(p_hat, "p_hat", n, real_dtype(pr))
+    _vector(p, "p", n, real_dtype(pr))
+    F = torch.empty((), dtype=torch.float64, device=p.device)
+    ws, nb = _workspace(n, pr, QST_OP_FIDELITY, p.device)
+    _lib.check(_lib.lib().qst_fidelity_classical(n, pr, p_hat.data_ptr(), p.data_ptr(), F.data_ptr(), _ptr(ws), nb,
+                                                 _stream(p.device)), "qst_fidelity_classical")
+    return F
 
 
 class LikelihoodFn(torch.autograd.Function):

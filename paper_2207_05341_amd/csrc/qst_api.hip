@@ -77,6 +77,42 @@ qst_status qst_state_premap(int n, qst_prec prec, int mode, const void* X, int64
   return QST_OK;
 }
 
+qst_status qst_fidelity_lowrank(int n, qst_prec prec, const void* T, int64_t ldT, const void* W, int64_t ldW, int r,
+                                double* F_dev, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(W, "W", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(F_dev, "F_dev", msg)) != QST_OK) return fail(st, msg);
+  if (r < 1 || r > QST_FIDELITY_MAX_RANK)
+    return fail(QST_ERR_INVALID_ARG, "rank r=" + std::to_string(r) + " outside [1, " +
+                                         std::to_string(QST_FIDELITY_MAX_RANK) + "]");
+  if (ldW < r) return fail(QST_ERR_INVALID_ARG, "ldW (" + std::to_string(ldW) + ") is smaller than r");
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_FIDELITY, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  hipError_t e = launch_fidelity_lowrank(prec, T, ldT, W, ldW, r, n, ws, F_dev, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "fidelity");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_fidelity_classical(int n, qst_prec prec, const void* p_hat, const void* p, double* F_dev, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(p_hat, "p_hat", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(p, "p", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(F_dev, "F_dev", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_FIDELITY, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  hipError_t e = launch_fidelity_classical(prec, p_hat, p, n, ws, F_dev, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "classical fidelity");
+  clear_error();
+  return QST_OK;
+}
+
 qst_status qst_povm_probs(int n, qst_prec prec, const void* rho, int64_t ld_rho, const double* povm_host,
                           void* p, void* ws, size_t ws_bytes, void* stream) {
   std::string msg;

@@ -31,6 +31,12 @@ class ProfScope {
 // partials + kReduceBlocks.  planes (QST_BF16GEMM with d > kBf16SplitMaxDim,
 // else ignored; may be NULL): receives bf16(T) as re and im planes (d x d
 // row-major each, 4 d^2 bytes), the operands launch_herk takes.
+// Fidelities (workspace laid out by fidelity_layout).
+hipError_t launch_fidelity_lowrank(qst_prec prec, const void* T, int64_t ldT, const void* W, int64_t ldW, int r,
+                                   int n, void* ws, double* F, hipStream_t s);
+hipError_t launch_fidelity_classical(qst_prec prec, const void* ph, const void* p, int n, void* ws, double* F,
+                                     hipStream_t s);
+
 // State-map pre-map (qst_premap mode) of a d x d complex matrix; Y may be X.
 hipError_t launch_premap(qst_prec prec, int mode, const void* X, int64_t ldx, void* Y, int64_t ldy, int n,
                          hipStream_t s);

@@ -70,6 +70,26 @@ bool fused_likelihood(const PovmPlan& pl, qst_prec prec) {
   return true;
 }
 
+FidelityLayout fidelity_layout(int n) {
+  FidelityLayout f;
+  const size_t d = size_t(1) << n;
+  f.nrb = d >= 64 ? 16 : 1;
+  const size_t ncb = d < 64 ? 1 : d / 64;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  f.mpart = take(size_t(f.nrb) * kFidelityMaxRank * d * 2 * sizeof(double));
+  f.mrow = take(size_t(kFidelityMaxRank) * d * 2 * sizeof(double));
+  f.gram = take(size_t(kFidelityMaxRank) * kFidelityMaxRank * 2 * sizeof(double));
+  f.taup = take(ncb * f.nrb * sizeof(double));
+  f.cpart = take(size_t(kReduceBlocks) * sizeof(double));
+  f.total = off;
+  return f;
+}
+
 WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
   WsLayout w;
   const size_t cb = complex_bytes(prec), rb = real_bytes(prec);
@@ -145,6 +165,9 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
         w.sk = take(stream_k_partial_bytes(prec));
         w.has_sk = true;
       }
+      break;
+    case QST_OP_FIDELITY:
+      off = fidelity_layout(n).total;
       break;
     default:
       return WsLayout{};
@@ -275,7 +298,7 @@ extern "C" {
 size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op) {
   std::string msg;
   if (qst::check_common(n_qubits, prec, msg) != QST_OK) return 0;
-  if (op < QST_OP_STATE_MAP || op > QST_OP_GRAD_PRODUCT) return 0;
+  if (op < QST_OP_STATE_MAP || op > QST_OP_FIDELITY) return 0;
   return qst::workspace_layout(n_qubits, prec, op, /*recompute=*/true).total;
 }
 

@@ -85,6 +85,17 @@ inline size_t stream_k_partial_bytes(qst_prec p) {
   return size_t(kStreamKMaxGrid) * 2 * (2 * 64 * 64) * (p == QST_F64 ? 8 : 4);
 }
 
+// Fidelity workspace (qst_fidelity_lowrank / qst_fidelity_classical):
+// W^dagger T partial sums over nrb row blocks and their total M (complex
+// FP64, sized for the largest rank), the r x r Gram matrix, per-workgroup |T|^2 partials and the
+// classical-fidelity partials.
+constexpr int kFidelityMaxRank = QST_FIDELITY_MAX_RANK;
+struct FidelityLayout {
+  int nrb = 1;
+  size_t mpart = 0, mrow = 0, gram = 0, taup = 0, cpart = 0, total = 0;
+};
+FidelityLayout fidelity_layout(int n);
+
 // Argument validation.  Each returns QST_OK or an error status and fills msg.
 qst_status check_common(int n, int prec, std::string& msg);
 qst_status check_matrix(const void* ptr, int64_t ld, int n, const char* name, std::string& msg);

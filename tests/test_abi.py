@@ -76,7 +76,11 @@ def test_workspace_sizes(L):
             # BF16 state map from N = 8: bf16 planes of T (4 d^2 bytes)
             if prec == 2 and n >= 8:
                 assert ws(n, prec, lib_mod.QST_OP_STATE_MAP) >= 4 * 4 ** n
-    assert ws(5, 0, 6) == 0
+    assert ws(5, 0, 7) == 0
+    # fidelity: the W^dagger T partials of 16 row blocks at the largest rank
+    for n in (2, 6, 11):
+        d = 1 << n
+        assert ws(n, 0, lib_mod.QST_OP_FIDELITY) >= (16 if d >= 64 else 1) * lib_mod.QST_FIDELITY_MAX_RANK * d * 16
 
 
 def _err(L):
@@ -235,6 +239,34 @@ def test_premap_validation(L):
     assert call(ldX=15) == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
     assert call(ldY=8) == lib_mod.QST_ERR_INVALID_ARG
     assert call(Y=FAKE, ldY=32) == lib_mod.QST_ERR_INVALID_ARG and "in place" in _err(L)
+
+
+def test_fidelity_validation(L):
+    n, d = 6, 64
+    ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_FIDELITY)
+    W = ctypes.c_void_p(0x30000)
+    F = ctypes.c_void_p(0x40000)
+
+    def low(T=FAKE, ldT=d, Wt=FAKE2, ldW=4, r=4, Fd=F, nb=ws, n=n):
+        return L.qst_fidelity_lowrank(n, 0, T, ldT, Wt, ldW, r, Fd, W, nb, None)
+
+    assert low(n=0) == lib_mod.QST_ERR_INVALID_ARG
+    assert low(T=None) == lib_mod.QST_ERR_INVALID_ARG and "T is NULL" in _err(L)
+    assert low(ldT=d - 1) == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
+    assert low(Wt=None) == lib_mod.QST_ERR_INVALID_ARG and "W is NULL" in _err(L)
+    assert low(Fd=None) == lib_mod.QST_ERR_INVALID_ARG and "F_dev" in _err(L)
+    assert low(r=0) == lib_mod.QST_ERR_INVALID_ARG and "rank" in _err(L)
+    assert low(r=lib_mod.QST_FIDELITY_MAX_RANK + 1, ldW=64) == lib_mod.QST_ERR_INVALID_ARG and "rank" in _err(L)
+    assert low(ldW=3) == lib_mod.QST_ERR_INVALID_ARG and "ldW" in _err(L)
+    assert low(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
+
+    def cls(ph=FAKE, p=FAKE2, Fd=F, nb=ws):
+        return L.qst_fidelity_classical(n, 0, ph, p, Fd, W, nb, None)
+
+    assert cls(ph=None) == lib_mod.QST_ERR_INVALID_ARG and "p_hat" in _err(L)
+    assert cls(p=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert cls(Fd=None) == lib_mod.QST_ERR_INVALID_ARG and "F_dev" in _err(L)
+    assert cls(nb=0) == lib_mod.QST_ERR_WORKSPACE
 
 
 def test_plan_unit_builds_without_hip(tmp_path):

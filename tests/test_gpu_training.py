@@ -33,14 +33,11 @@ def say(*a):
     print(*a, flush=True)
 
 
-def gpu_fidelity_lowrank(T, W, tw):
-    """F_q(T T^dagger / tau, W W^dagger / tw) via the r x r matrix
-    (T^dagger W)^dagger (T^dagger W) / (tau tw) (the oracle's low-rank form)."""
-    X = T.conj().transpose(0, 1).contiguous() @ W
-    tau = float((T.real.double() ** 2).sum() + (T.imag.double() ** 2).sum())
-    M = (X.conj().transpose(0, 1).contiguous() @ X).cpu().numpy().astype(np.complex128) / (tau * tw)
-    w = np.clip(np.linalg.eigvalsh((M + M.conj().T) / 2), 0.0, None)
-    return float(np.sqrt(w).sum() ** 2)
+def gpu_fidelity_lowrank(T, W):
+    """F_q(T T^dagger / tau, W W^dagger / tw) by the library
+    (qst_fidelity_lowrank, checked against the oracle in
+    test_gpu_fidelity.py)."""
+    return float(qst.fidelity_lowrank(T.contiguous(), W).item())
 
 
 def train_gpu(T0, f, steps, prec, mode="recompute"):
@@ -87,13 +84,12 @@ def test_training_n12_f32():
     f = S.multinomial_freqs(g, 100_000_000, p0).astype(np.float32)
     del p0
     Wg = torch.from_numpy(W.astype(np.complex64)).to(DEV)
-    tw = float(np.sum(np.abs(W) ** 2))
 
     # 2 steps, compared with the oracle's FP64 Adam after 2 steps
     T2, l2 = train_gpu(T0, f, 2, "f32", mode="recompute")
-    f2 = gpu_fidelity_lowrank(T2, Wg, tw)
+    f2 = gpu_fidelity_lowrank(T2, Wg)
     T2b, l2b = train_gpu(T0, f, 2, "f32", mode="fused")
-    f2b = gpu_fidelity_lowrank(T2b, Wg, tw)
+    f2b = gpu_fidelity_lowrank(T2b, Wg)
     say(f"  GPU after 2 steps: recompute losses {l2} fidelity {f2:.8f}; fused losses {l2b} fidelity {f2b:.8f}")
     t0 = time.perf_counter()
     To, lo = O.adam_train(T0.astype(np.complex128), f.astype(np.float64), steps=2, lr=LR, betas=BETAS, eps=EPS)
@@ -109,7 +105,7 @@ def test_training_n12_f32():
     rec = {"config": "N=12 FP32 training, 200 Adam steps (lr 1e-2), target rank-8 Ginibre, 10^8 shots",
            "fidelity_after_2_gpu_recompute": f2, "fidelity_after_2_gpu_fused": f2b,
            "fidelity_after_2_oracle": fo,
-           "fidelity_start": gpu_fidelity_lowrank(torch.from_numpy(T0).to(DEV), Wg, tw)}
+           "fidelity_start": gpu_fidelity_lowrank(torch.from_numpy(T0).to(DEV), Wg)}
     for mode in ("recompute", "fused"):
         torch.cuda.synchronize()
         torch.cuda.reset_peak_memory_stats()
@@ -122,7 +118,7 @@ def test_training_n12_f32():
                      "peak_torch_allocated_GiB": torch.cuda.max_memory_allocated() / 2 ** 30,
                      "device_used_GiB": (total - free1) / 2 ** 30,
                      "loss_first": l200[0], "loss_last": l200[-1],
-                     "fidelity_final": gpu_fidelity_lowrank(T200, Wg, tw)}
+                     "fidelity_final": gpu_fidelity_lowrank(T200, Wg)}
         assert all(math.isfinite(x) for x in l200)
         assert l200[-1] < l200[0] and rec[mode]["fidelity_final"] > rec["fidelity_start"]
         del T200
