@@ -13,6 +13,8 @@ What it computes, written from the paper (Wang, Cheng, Li, Chen,
 * modes       the pre-maps of Chol_H (Hermitian part, Sec. 2.2.2 and
               Eq. unified_DP) and Chol_Delta (lower triangle, Eq. T_matrix),
               and the P-order absolute projection (Eq. abs_P) by eigh
+* network     the 3-layer FNN of Sec. 3.1 (4^N -> 2N -> 4^N) filling the
+              Hermitian T, and its backward
 * Born rule   p_k = Tr(M_k rho)                  (Sec. 2.1, Born rule)
 * product POVM M_k = M_{k_1} (x) ... (x) M_{k_N}   (Sec. 3.3)
 * tetrahedral single-qubit POVM M_a = (I + s_a . sigma)/4   (Sec. 4.1 setup)
@@ -149,6 +151,59 @@ def abs_projection(H: np.ndarray, P: float) -> np.ndarray:
     lam, Q = np.linalg.eigh(np.asarray(H, dtype=np.complex128))
     w = np.abs(lam) ** P
     return (Q * (w / math.fsum(w.tolist()))) @ Q.conj().T
+
+
+# ----------------------------------------------------------------------------
+# The mapping network (Sec. 3.1): a 3-layer FNN from the measured
+# distribution x (K^N = 4^N inputs) through 2N hidden units with a leaky
+# ReLU to 4^N real outputs, which fill the Hermitian T of Chol_H.
+# Readings: negative slope 0.01; outputs y as a real d x d matrix Y (row
+# major) fill T with T_ij = Y_ij + i Y_ji below the diagonal, its conjugate
+# above, T_ii = Y_ii (a bijection of R^(d^2) onto Hermitian matrices).
+# ----------------------------------------------------------------------------
+
+LEAKY_SLOPE = 0.01
+
+
+def leaky_relu(v: np.ndarray) -> np.ndarray:
+    v = np.asarray(v, dtype=np.float64)
+    return np.where(v > 0, v, LEAKY_SLOPE * v)
+
+
+def fnn_fill(y: np.ndarray, d: int) -> np.ndarray:
+    """Hermitian T from the 4^N outputs (reading above)."""
+    Y = np.asarray(y, dtype=np.float64).reshape(d, d)
+    L = np.tril(Y, -1)
+    U = np.triu(Y, 1)
+    return (L + L.T) + 1j * (U.T - U) + np.diag(np.diag(Y))
+
+
+def fnn_unfill(G: np.ndarray) -> np.ndarray:
+    """Adjoint of fnn_fill for Re Tr(A^dagger B): dL/dy from dL/dT
+    (PyTorch convention dL/dRe T + i dL/dIm T), as a flat 4^N vector."""
+    G = np.asarray(G, dtype=np.complex128)
+    S = G.real + G.real.T
+    A = G.imag.T - G.imag
+    return (np.tril(S, -1) + np.triu(A, 1) + np.diag(np.diag(G.real))).ravel()
+
+
+def fnn_forward(W1, b1, W2, b2, x):
+    """h_pre = W1 x + b1, h = leaky(h_pre), y = W2 h + b2, T = fill(y).
+    W1 is 2N x 4^N, W2 is 4^N x 2N.  Returns (T, h_pre, y)."""
+    h_pre = np.asarray(W1, dtype=np.float64) @ np.asarray(x, dtype=np.float64) + np.asarray(b1, dtype=np.float64)
+    y = np.asarray(W2, dtype=np.float64) @ leaky_relu(h_pre) + np.asarray(b2, dtype=np.float64)
+    d = int(round(math.sqrt(y.size)))
+    return fnn_fill(y, d), h_pre, y
+
+
+def fnn_backward(W2, x, h_pre, G):
+    """Gradients of L(T(W1, b1, W2, b2)) from G = dL/dT: returns
+    (dW1, db1, dW2, db2)."""
+    gy = fnn_unfill(G)
+    h = leaky_relu(h_pre)
+    dh = np.asarray(W2, dtype=np.float64).T @ gy
+    dh_pre = dh * np.where(np.asarray(h_pre) > 0, 1.0, LEAKY_SLOPE)
+    return np.outer(dh_pre, np.asarray(x, dtype=np.float64)), dh_pre, np.outer(gy, h), gy
 
 
 # ----------------------------------------------------------------------------

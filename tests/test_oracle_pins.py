@@ -508,3 +508,67 @@ def test_mode_gradient_central_differences(mode):
         assert np.max(np.abs(grad - grad.conj().T)) <= 1e-15 * np.max(np.abs(grad)) * 10
     else:
         assert np.all(np.triu(grad, 1) == 0)
+
+
+# --------------------------------------------------------------------------
+# Mapping network (Sec. 3.1)
+# --------------------------------------------------------------------------
+
+def test_fnn_fill_definition_and_adjoint():
+    """fill: entrywise T_ij = Y_ij + i Y_ji (i > j), conjugate above, Y_ii on
+    the diagonal; Hermitian; a bijection (Y recovered from T); unfill is its
+    adjoint for Re Tr(A^dagger B)."""
+    g = S.rng(1400)
+    d = 8
+    y = g.standard_normal(d * d)
+    Y = y.reshape(d, d)
+    T = O.fnn_fill(y, d)
+    for i in range(d):
+        for j in range(d):
+            if i > j:
+                assert T[i, j] == Y[i, j] + 1j * Y[j, i]
+            elif i < j:
+                assert T[i, j] == Y[j, i] - 1j * Y[i, j]
+            else:
+                assert T[i, j] == Y[i, i]
+    assert np.array_equal(T, T.conj().T)
+    rec = np.tril(T.real) + np.triu(-T.imag, 1)  # Y from T
+    assert np.array_equal(rec, Y)
+    G = S.ginibre(g, d)
+    a = float(np.sum(T.real * G.real + T.imag * G.imag))
+    b = float(np.dot(y, O.fnn_unfill(G)))
+    assert abs(a - b) <= 1e-13 * (abs(a) + 1.0)
+
+
+def test_fnn_backward_central_differences():
+    """L(fill(FNN(W1, b1, W2, b2; x))) by central differences along random
+    directions in each parameter against the oracle's backward."""
+    g = S.rng(1410)
+    n, d = 2, 4
+    D, H = 4 ** n, 2 * n
+    x = S.porter_thomas_probs(g, D, 0.2)
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 4000, O.probs_real(S.depolarised_pure(psi, 0.2)))
+    W1, b1 = g.standard_normal((H, D)), g.standard_normal(H)
+    W2, b2 = g.standard_normal((D, H)) / 3, g.standard_normal(D) / 3
+    params = [W1, b1, W2, b2]
+
+    def loss(ps):
+        T, _, _ = O.fnn_forward(*ps, x)
+        return O.loss_of_T(T, f)
+
+    T, h_pre, _ = O.fnn_forward(W1, b1, W2, b2, x)
+    assert np.all(np.abs(h_pre) > 1e-3)  # away from the kink
+    G, _ = O.grad_T(T, f)
+    grads = O.fnn_backward(W2, x, h_pre, G)
+    for k in range(4):
+        for _ in range(3):
+            E = g.standard_normal(params[k].shape)
+            E /= np.linalg.norm(E)
+            h = 1e-6
+            plus = [p + (h * E if i == k else 0) for i, p in enumerate(params)]
+            minus = [p - (h * E if i == k else 0) for i, p in enumerate(params)]
+            fd = (loss(plus) - loss(minus)) / (2 * h)
+            an = float(np.sum(grads[k] * E))
+            assert abs(fd - an) <= 1e-6 * max(1.0, np.linalg.norm(grads[k])), (k, fd, an)
+    assert np.array_equal(O.leaky_relu(np.array([-2.0, 0.0, 3.0])), np.array([-0.02, 0.0, 3.0]))
