@@ -270,6 +270,69 @@ def fidelities(qst, T, prec, reps=20):
     return out
 
 
+def network(qst, f, prec, reps=10):
+    """The mapping network of Sec. 3.1 at the bench size (4^N -> 2N -> 4^N,
+    184.5M parameters at N = 11): forward and backward kernel time with
+    achieved GB/s from algorithmic bytes (each weight matrix streamed once
+    per pass; the backward also writes both weight gradients), and one whole
+    NN-QST training step (network, fused likelihood, backward, the paper's
+    Rprop at lr 1e-3 from torch) per second."""
+    import torch
+
+    d = 1 << ((f.numel().bit_length() - 1) // 2)
+    n = d.bit_length() - 1
+    D, H = d * d, 2 * n
+    rt = torch.float64 if prec == "f64" else torch.float32
+    rb = 8 if prec == "f64" else 4
+    net = qst.MappingNetwork(n, dtype=rt, device=f.device, generator=torch.Generator().manual_seed(12))
+    x = (f.double() / f.double().sum()).to(rt)
+    P = (net.W1.detach(), net.b1.detach(), net.W2.detach(), net.b2.detach())
+    T, h_pre = qst.fnn_forward(*P, x, prec)
+    out, tau, G, _ = qst.likelihood_forward(T, f, prec)
+    grad = qst.grad_product(G, T, tau, prec)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return 1e3 * ev0.elapsed_time(ev1) / reps
+
+    fwd_us = timed(lambda: qst.fnn_forward(*P, x, prec))
+    bwd_us = timed(lambda: qst.fnn_backward(P[2], x, h_pre, grad, prec))
+    fwd_bytes = (2 * H * D + 2 * D) * rb + D * 2 * rb  # W1, W2, x, b2 read; T written
+    bwd_bytes = (H * D + D) * rb + D * 2 * rb + (2 * H * D + D) * rb  # W2, x, G read; dW2, dW1, db2 written
+    opt = torch.optim.Rprop(net.parameters(), lr=1e-3)
+
+    def train_step():
+        opt.zero_grad(set_to_none=True)
+        L = qst.likelihood(net(x, prec), f, prec)
+        L.backward()
+        opt.step()
+
+    for _ in range(2):
+        train_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        train_step()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / reps
+    del net, opt, T, G, grad
+    return {"parameters": 2 * H * D + H + D,
+            "forward_us": round(fwd_us, 1), "forward_GB_s": round(fwd_bytes / (fwd_us * 1e-6) / 1e9, 1),
+            "forward_hbm_frac": round(fwd_bytes / (fwd_us * 1e-6) / 8e12, 3),
+            "backward_us": round(bwd_us, 1), "backward_GB_s": round(bwd_bytes / (bwd_us * 1e-6) / 1e9, 1),
+            "backward_hbm_frac": round(bwd_bytes / (bwd_us * 1e-6) / 8e12, 3),
+            "nnqst_train_steps_per_s": round(1.0 / step_s, 1),
+            "note": "train step = network forward, qst_likelihood, qst_grad_product, network backward, "
+                    "torch Rprop (lr 1e-3) over all parameters"}
+
+
 def cpu_baseline(T, f, prec):
     """FP64 oracle on a bounded sample: full forward + adjoint evaluations of
     the same N = 11 workload (the measured precision's T and f widened)."""
@@ -424,6 +487,7 @@ def main():
     Tm, fm = to_prec(T_np, f_np, args.prec, dev)
     modes = state_maps(qst, Tm, fm, args.prec)
     fids = fidelities(qst, Tm, args.prec)
+    net = network(qst, fm, args.prec)
     del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
@@ -453,6 +517,7 @@ def main():
         "paths": paths,
         "state_maps": modes,
         "fidelity": fids,
+        "network": net,
         "batched": batch,
         "device": torch.cuda.get_device_name(0),
     }

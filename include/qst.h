@@ -83,7 +83,8 @@ typedef enum {
   QST_OP_NLL_BACKWARD = 3,
   QST_OP_LIKELIHOOD = 4,
   QST_OP_GRAD_PRODUCT = 5,
-  QST_OP_FIDELITY = 6
+  QST_OP_FIDELITY = 6,
+  QST_OP_FNN = 7
 } qst_op;
 
 /*
@@ -256,6 +257,41 @@ qst_status qst_fidelity_lowrank(int n_qubits, qst_prec prec, const void* T, int6
  */
 qst_status qst_fidelity_classical(int n_qubits, qst_prec prec, const void* p_hat, const void* p, double* F_dev,
                                   void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The mapping network (Sec. 3.1): a 3-layer feed-forward network from the
+ * measured distribution x (4^N inputs) through H = 2N hidden units with a
+ * leaky ReLU (negative slope 0.01) to 4^N real outputs y that fill the
+ * Hermitian T of Chol_H:
+ *   h_pre = W1 x + b1,  y = W2 leaky(h_pre) + b2,  Y = y as a d x d real
+ *   matrix (row major),  T_ij = Y_ij + i Y_ji (i > j),  T_ij = Y_ji - i Y_ij
+ *   (i < j),  T_ii = Y_ii  (a bijection of R^(d^2) onto Hermitian matrices).
+ * Real arrays are float64 for QST_F64, float32 otherwise.
+ *   W1 [in]  H x 4^N, row major;  b1 [in] H;  W2 [in] 4^N x H, row major;
+ *   b2 [in]  4^N;  x [in] 4^N; all device.
+ *   h_pre [out] H reals, device (input of qst_fnn_backward).
+ *   T     [out] d x d complex, row stride ldT, device.
+ * Sums in FP64 in a fixed order (bitwise reproducible).
+ */
+qst_status qst_fnn_forward(int n_qubits, qst_prec prec, const void* W1, const void* b1, const void* W2,
+                           const void* b2, const void* x, void* h_pre, void* T, int64_t ldT, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/*
+ * Backward of qst_fnn_forward: from G = dL/dT (the gradient convention of
+ * qst_nll_backward, dL/dRe T + i dL/dIm T; only its action on Hermitian
+ * directions matters), the gradients of L with respect to the parameters:
+ *   dL/dy = fill^*(G):  Re G_ij + Re G_ji (i > j),  Im G_ji - Im G_ij
+ *           (i < j),  Re G_ii;
+ *   dW2 = dL/dy leaky(h_pre)^T,  db2 = dL/dy,
+ *   db1 = (W2^T dL/dy) * leaky'(h_pre),  dW1 = db1 x^T.
+ *   W2, x, h_pre [in] as in the forward call;  G [in] d x d complex, row
+ *   stride ldG;  dW1 [out] H x 4^N;  db1 [out] H;  dW2 [out] 4^N x H;
+ *   db2 [out] 4^N; all device.
+ */
+qst_status qst_fnn_backward(int n_qubits, qst_prec prec, const void* W2, const void* x, const void* h_pre,
+                            const void* G, int64_t ldG, void* dW1, void* db1, void* dW2, void* db2, void* ws,
+                            size_t ws_bytes, void* stream);
 
 /* Workspace in bytes needed by op (a qst_op) at (n_qubits, prec); 0 for an
  * invalid request. */

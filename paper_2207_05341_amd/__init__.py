@@ -15,13 +15,13 @@ import torch
 
 from . import _lib
 from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
-                   QST_FIDELITY_MAX_RANK, QST_OP_FIDELITY, QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS,
+                   QST_FIDELITY_MAX_RANK, QST_OP_FIDELITY, QST_OP_FNN, QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS,
                    QST_OP_STATE_MAP, QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER, QstError, workspace_bytes)
 
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
     "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "fidelity_lowrank",
-    "fidelity_classical",
+    "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
 
@@ -268,6 +268,98 @@ def fidelity_classical(p_hat: torch.Tensor, p: torch.Tensor, prec=None) -> torch
     _lib.check(_lib.lib().qst_fidelity_classical(n, pr, p_hat.data_ptr(), p.data_ptr(), F.data_ptr(), _ptr(ws), nb,
                                                  _stream(p.device)), "qst_fidelity_classical")
     return F
+
+
+def _fnn_args(W2: torch.Tensor, x: torch.Tensor):
+    D = x.numel()
+    n = (D.bit_length() - 1) // 2
+    if 4 ** n != D or not 1 <= n <= QST_MAX_QUBITS:
+        raise ValueError(f"x must have 4^N entries, got {D}")
+    return n, D, 2 * n
+
+
+def _check_real(t: torch.Tensor, name: str, shape, dtype):
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous GPU {dtype} tensor of shape {tuple(shape)}")
+
+
+def fnn_forward(W1, b1, W2, b2, x, prec=None):
+    """The mapping network (Sec. 3.1): returns (T, h_pre) with T the d x d
+    Hermitian matrix filled from the 4^N outputs and h_pre the 2N hidden
+    pre-activations (input of fnn_backward)."""
+    n, D, H = _fnn_args(W2, x)
+    rt = x.dtype
+    for t, name, shape in ((W1, "W1", (H, D)), (b1, "b1", (H,)), (W2, "W2", (D, H)), (b2, "b2", (D,)), (x, "x", (D,))):
+        _check_real(t, name, shape, rt)
+    pr = QST_F64 if rt == torch.float64 else (QST_F32 if prec is None else _prec(torch.complex64, prec))
+    d = 1 << n
+    T = torch.empty((d, d), dtype=torch.complex128 if rt == torch.float64 else torch.complex64, device=x.device)
+    h_pre = torch.empty(H, dtype=rt, device=x.device)
+    ws, nb = _workspace(n, pr, QST_OP_FNN, x.device)
+    _lib.check(_lib.lib().qst_fnn_forward(n, pr, W1.data_ptr(), b1.data_ptr(), W2.data_ptr(), b2.data_ptr(),
+                                          x.data_ptr(), h_pre.data_ptr(), T.data_ptr(), T.stride(0), _ptr(ws), nb,
+                                          _stream(x.device)), "qst_fnn_forward")
+    return T, h_pre
+
+
+def fnn_backward(W2, x, h_pre, G, prec=None):
+    """Parameter gradients (dW1, db1, dW2, db2) from G = dL/dT."""
+    n, D, H = _fnn_args(W2, x)
+    rt = x.dtype
+    _check_real(W2, "W2", (D, H), rt)
+    _check_real(h_pre, "h_pre", (H,), rt)
+    n2, ldg = _matrix(G, "G")
+    if n2 != n:
+        raise ValueError("G must be d x d")
+    pr = QST_F64 if rt == torch.float64 else (QST_F32 if prec is None else _prec(torch.complex64, prec))
+    dW1 = torch.empty((H, D), dtype=rt, device=x.device)
+    db1 = torch.empty(H, dtype=rt, device=x.device)
+    dW2 = torch.empty((D, H), dtype=rt, device=x.device)
+    db2 = torch.empty(D, dtype=rt, device=x.device)
+    ws, nb = _workspace(n, pr, QST_OP_FNN, x.device)
+    _lib.check(_lib.lib().qst_fnn_backward(n, pr, W2.data_ptr(), x.data_ptr(), h_pre.data_ptr(), G.data_ptr(), ldg,
+                                           dW1.data_ptr(), db1.data_ptr(), dW2.data_ptr(), db2.data_ptr(), _ptr(ws),
+                                           nb, _stream(x.device)), "qst_fnn_backward")
+    return dW1, db1, dW2, db2
+
+
+class FnnFn(torch.autograd.Function):
+    """T = fill(W2 leaky(W1 x + b1) + b2) with the library's backward."""
+
+    @staticmethod
+    def forward(ctx, W1, b1, W2, b2, x, prec):
+        T, h_pre = fnn_forward(W1, b1, W2, b2, x, prec)
+        ctx.save_for_backward(W2, x, h_pre)
+        ctx.prec = prec
+        return T
+
+    @staticmethod
+    def backward(ctx, g):
+        W2, x, h_pre = ctx.saved_tensors
+        dW1, db1, dW2, db2 = fnn_backward(W2, x, h_pre, g.contiguous(), ctx.prec)
+        return dW1, db1, dW2, db2, None, None
+
+
+class MappingNetwork(torch.nn.Module):
+    """The 3-layer network of Sec. 3.1 for N qubits: 4^N inputs (the
+    measured distribution), 2N hidden units (leaky ReLU), 4^N outputs filling
+    the Hermitian T.  Parameters start uniform in +-1/sqrt(fan_in), the
+    usual initialisation of a linear layer."""
+
+    def __init__(self, n_qubits: int, dtype=torch.float32, device="cuda", generator=None):
+        super().__init__()
+        D, H = 4 ** n_qubits, 2 * n_qubits
+
+        def uni(shape, fan_in):
+            b = 1.0 / fan_in ** 0.5
+            return torch.nn.Parameter((torch.rand(shape, generator=generator, dtype=torch.float64) * 2 - 1).mul(b)
+                                      .to(device=device, dtype=dtype))
+
+        self.W1, self.b1 = uni((H, D), D), uni((H,), D)
+        self.W2, self.b2 = uni((D, H), H), uni((D,), H)
+
+    def forward(self, x, prec=None):
+        return FnnFn.apply(self.W1, self.b1, self.W2, self.b2, x, prec)
 
 
 class LikelihoodFn(torch.autograd.Function):

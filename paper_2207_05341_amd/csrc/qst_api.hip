@@ -77,6 +77,45 @@ qst_status qst_state_premap(int n, qst_prec prec, int mode, const void* X, int64
   return QST_OK;
 }
 
+qst_status qst_fnn_forward(int n, qst_prec prec, const void* W1, const void* b1, const void* W2, const void* b2,
+                           const void* x, void* h_pre, void* T, int64_t ldT, void* ws, size_t ws_bytes,
+                           void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  const void* ins[] = {W1, b1, W2, b2, x, h_pre};
+  const char* names[] = {"W1", "b1", "W2", "b2", "x", "h_pre"};
+  for (int i = 0; i < 6; ++i)
+    if ((st = check_ptr(ins[i], names[i], msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_FNN, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  hipError_t e = launch_fnn_forward(prec, n, W1, b1, W2, b2, x, h_pre, T, ldT, ws, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "network forward");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_fnn_backward(int n, qst_prec prec, const void* W2, const void* x, const void* h_pre, const void* G,
+                            int64_t ldG, void* dW1, void* db1, void* dW2, void* db2, void* ws, size_t ws_bytes,
+                            void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  const void* ptrs[] = {W2, x, h_pre, dW1, db1, dW2, db2};
+  const char* names[] = {"W2", "x", "h_pre", "dW1", "db1", "dW2", "db2"};
+  for (int i = 0; i < 7; ++i)
+    if ((st = check_ptr(ptrs[i], names[i], msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(G, ldG, n, "G", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_FNN, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  hipError_t e = launch_fnn_backward(prec, n, W2, x, h_pre, G, ldG, dW1, db1, dW2, db2, ws,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "network backward");
+  clear_error();
+  return QST_OK;
+}
+
 qst_status qst_fidelity_lowrank(int n, qst_prec prec, const void* T, int64_t ldT, const void* W, int64_t ldW, int r,
                                 double* F_dev, void* ws, size_t ws_bytes, void* stream) {
   std::string msg;

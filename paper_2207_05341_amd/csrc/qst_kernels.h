@@ -31,6 +31,12 @@ class ProfScope {
 // partials + kReduceBlocks.  planes (QST_BF16GEMM with d > kBf16SplitMaxDim,
 // else ignored; may be NULL): receives bf16(T) as re and im planes (d x d
 // row-major each, 4 d^2 bytes), the operands launch_herk takes.
+// Mapping network (workspace laid out by fnn_layout).
+hipError_t launch_fnn_forward(qst_prec prec, int n, const void* W1, const void* b1, const void* W2, const void* b2,
+                              const void* x, void* h_pre, void* T, int64_t ldT, void* ws, hipStream_t s);
+hipError_t launch_fnn_backward(qst_prec prec, int n, const void* W2, const void* x, const void* h_pre, const void* G,
+                               int64_t ldG, void* dW1, void* db1, void* dW2, void* db2, void* ws, hipStream_t s);
+
 // Fidelities (workspace laid out by fidelity_layout).
 hipError_t launch_fidelity_lowrank(qst_prec prec, const void* T, int64_t ldT, const void* W, int64_t ldW, int r,
                                    int n, void* ws, double* F, hipStream_t s);

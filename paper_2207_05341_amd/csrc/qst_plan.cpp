@@ -90,6 +90,23 @@ FidelityLayout fidelity_layout(int n) {
   return f;
 }
 
+FnnLayout fnn_layout(int n, size_t real_bytes) {
+  FnnLayout f;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t H = size_t(2) * n;
+  f.part = take(size_t(kFnnBlocks) * H * sizeof(double));
+  f.hvec = take(H * sizeof(double));
+  f.dhvec = take(H * sizeof(double));
+  f.yvec = take((size_t(1) << (2 * n)) * real_bytes);
+  f.total = off;
+  return f;
+}
+
 WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
   WsLayout w;
   const size_t cb = complex_bytes(prec), rb = real_bytes(prec);
@@ -168,6 +185,9 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
       break;
     case QST_OP_FIDELITY:
       off = fidelity_layout(n).total;
+      break;
+    case QST_OP_FNN:
+      off = fnn_layout(n, rb).total;
       break;
     default:
       return WsLayout{};
@@ -298,7 +318,7 @@ extern "C" {
 size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op) {
   std::string msg;
   if (qst::check_common(n_qubits, prec, msg) != QST_OK) return 0;
-  if (op < QST_OP_STATE_MAP || op > QST_OP_FIDELITY) return 0;
+  if (op < QST_OP_STATE_MAP || op > QST_OP_FNN) return 0;
   return qst::workspace_layout(n_qubits, prec, op, /*recompute=*/true).total;
 }
 

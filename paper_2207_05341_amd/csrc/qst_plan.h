@@ -96,6 +96,16 @@ struct FidelityLayout {
 };
 FidelityLayout fidelity_layout(int n);
 
+// Mapping network workspace: FP64 block partials of the two H-wide sums,
+// h and dL/dh_pre (FP64), and the 4^N outputs y (or dL/dy) in storage
+// precision.
+constexpr int kFnnMaxHidden = 2 * QST_MAX_QUBITS;
+constexpr int kFnnBlocks = 1024;
+struct FnnLayout {
+  size_t part = 0, hvec = 0, dhvec = 0, yvec = 0, total = 0;
+};
+FnnLayout fnn_layout(int n, size_t real_bytes);
+
 // Argument validation.  Each returns QST_OK or an error status and fills msg.
 qst_status check_common(int n, int prec, std::string& msg);
 qst_status check_matrix(const void* ptr, int64_t ld, int n, const char* name, std::string& msg);

@@ -76,7 +76,7 @@ def test_workspace_sizes(L):
             # BF16 state map from N = 8: bf16 planes of T (4 d^2 bytes)
             if prec == 2 and n >= 8:
                 assert ws(n, prec, lib_mod.QST_OP_STATE_MAP) >= 4 * 4 ** n
-    assert ws(5, 0, 7) == 0
+    assert ws(5, 0, 8) == 0
     # fidelity: the W^dagger T partials of 16 row blocks at the largest rank
     for n in (2, 6, 11):
         d = 1 << n
@@ -267,6 +267,34 @@ def test_fidelity_validation(L):
     assert cls(p=None) == lib_mod.QST_ERR_INVALID_ARG
     assert cls(Fd=None) == lib_mod.QST_ERR_INVALID_ARG and "F_dev" in _err(L)
     assert cls(nb=0) == lib_mod.QST_ERR_WORKSPACE
+
+
+def test_fnn_validation(L):
+    n, d = 4, 16
+    ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_FNN)
+    assert ws >= 1024 * 8 * 8 + 4 ** n * 8
+    W = ctypes.c_void_p(0x30000)
+    P = [ctypes.c_void_p(0x100000 * (i + 1)) for i in range(8)]
+
+    def fwd(i=None, T=FAKE, ldT=d, nb=ws):
+        a = [p if k != i else None for k, p in enumerate(P[:6])]
+        return L.qst_fnn_forward(n, 0, *a, T, ldT, W, nb, None)
+
+    for i, name in enumerate(["W1", "b1", "W2", "b2", "x", "h_pre"]):
+        assert fwd(i) == lib_mod.QST_ERR_INVALID_ARG and f"{name} is NULL" in _err(L)
+    assert fwd(T=None) == lib_mod.QST_ERR_INVALID_ARG and "T is NULL" in _err(L)
+    assert fwd(ldT=d - 1) == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
+    assert fwd(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
+
+    def bwd(i=None, G=FAKE, ldG=d, nb=ws):
+        a = [p if k != i else None for k, p in enumerate(P[:7])]
+        return L.qst_fnn_backward(n, 0, a[0], a[1], a[2], G, ldG, a[3], a[4], a[5], a[6], W, nb, None)
+
+    for i, name in enumerate(["W2", "x", "h_pre", "dW1", "db1", "dW2", "db2"]):
+        assert bwd(i) == lib_mod.QST_ERR_INVALID_ARG and f"{name} is NULL" in _err(L)
+    assert bwd(G=None) == lib_mod.QST_ERR_INVALID_ARG and "G is NULL" in _err(L)
+    assert bwd(ldG=3) == lib_mod.QST_ERR_INVALID_ARG
+    assert bwd(nb=0) == lib_mod.QST_ERR_WORKSPACE
 
 
 def test_plan_unit_builds_without_hip(tmp_path):

@@ -1,0 +1,130 @@
+"""The mapping network of Sec. 3.1 through the C ABI (qst_fnn_forward,
+qst_fnn_backward) and through autograd, against the oracle's fnn_forward /
+fnn_backward (pinned by the fill definition, its adjoint identity and
+central differences through the whole loss).
+
+* forward (T, h_pre) and backward (dW1, db1, dW2, db2 for a random dL/dT)
+  at N = 1 .. 8 in both precisions; bitwise repeats;
+* the whole NN-QST chain, network -> T -> likelihood, differentiated by
+  autograd, against the oracle chain at N = 4 (FP64) and N = 8 (FP32);
+* a short Rprop run (the paper's optimiser, lr 1e-3) lowers the loss.
+
+Tolerances: FP64 1e-12, FP32 1e-5 (relative; Frobenius for matrices).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+from workloads import rel_fro
+
+torch = pytest.importorskip("torch")
+qst = pytest.importorskip("paper_2207_05341_amd")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def params(g, n, rt):
+    D, H = 4 ** n, 2 * n
+    W1 = (g.uniform(-1, 1, (H, D)) / np.sqrt(D)).astype(rt)
+    b1 = (g.uniform(-1, 1, H) / np.sqrt(D)).astype(rt)
+    W2 = (g.uniform(-1, 1, (D, H)) / np.sqrt(H)).astype(rt)
+    b2 = (g.uniform(-1, 1, D) / np.sqrt(H)).astype(rt)
+    return W1, b1, W2, b2
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 2, 4, 6, 8])
+def test_fnn_against_oracle(prec, n):
+    say(f"network N={n} {prec}")
+    rt = np.float64 if prec == "f64" else np.float32
+    ct = np.complex128 if prec == "f64" else np.complex64
+    g = S.rng(7500 + n)
+    W1, b1, W2, b2 = params(g, n, rt)
+    x = S.porter_thomas_probs(g, 4 ** n, 0.1).astype(rt)
+    G = S.ginibre(g, 1 << n).astype(ct)
+    T_w, hp_w, _ = O.fnn_forward(W1, b1, W2, b2, x)
+    grads_w = O.fnn_backward(W2, x, hp_w, G.astype(np.complex128))
+    Wg = [dev(a) for a in (W1, b1, W2, b2)]
+    xg = dev(x)
+    T, h_pre = qst.fnn_forward(*Wg, xg, prec)
+    grads = qst.fnn_backward(Wg[2], xg, h_pre, dev(G), prec)
+    T2, h_pre2 = qst.fnn_forward(*Wg, xg, prec)
+    grads2 = qst.fnn_backward(Wg[2], xg, h_pre2, dev(G), prec)
+    torch.cuda.synchronize()
+    Tn = T.cpu().numpy()
+    assert np.array_equal(Tn, Tn.conj().T)
+    errs = {"T": rel_fro(Tn, T_w), "h_pre": rel_fro(h_pre.cpu().numpy(), hp_w)}
+    for name, a, w in zip(("dW1", "db1", "dW2", "db2"), grads, grads_w):
+        errs[name] = rel_fro(a.cpu().numpy(), w)
+    say(f"  {errs}")
+    for k, v in errs.items():
+        assert v <= TOL[prec], (k, v)
+    assert torch.equal(T, T2) and all(torch.equal(a, b) for a, b in zip(grads, grads2))
+
+
+@pytest.mark.parametrize("prec,n", [("f64", 4), ("f32", 8)])
+def test_network_chain_through_autograd(prec, n):
+    """MappingNetwork -> T -> likelihood: autograd's parameter gradients
+    against the oracle's chain (grad_T at the network's T, then
+    fnn_backward)."""
+    say(f"network + likelihood N={n} {prec}")
+    rt = torch.float64 if prec == "f64" else torch.float32
+    gen = torch.Generator().manual_seed(7600 + n)
+    net = qst.MappingNetwork(n, dtype=rt, device=DEV, generator=gen)
+    g = S.rng(7610 + n)
+    d = 1 << n
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))
+    fr = f.astype(np.float64 if prec == "f64" else np.float32)
+    x = (fr / fr.sum()).astype(fr.dtype)
+    fg, xg = dev(fr), dev(x)
+    T = net(xg, prec)
+    L = qst.likelihood(T, fg, prec)
+    L.backward()
+    torch.cuda.synchronize()
+    P = [p.detach().cpu().numpy().astype(np.float64) for p in (net.W1, net.b1, net.W2, net.b2)]
+    xw, fw = x.astype(np.float64), fr.astype(np.float64)
+    T_w, hp_w, _ = O.fnn_forward(*P, xw)
+    G_w, L_w = O.grad_T(T_w, fw)
+    grads_w = O.fnn_backward(P[2], xw, hp_w, G_w)
+    eL = abs(float(L.item()) - L_w) / abs(L_w)
+    errs = {"L": eL}
+    for name, p, w in zip(("dW1", "db1", "dW2", "db2"), (net.W1, net.b1, net.W2, net.b2), grads_w):
+        errs[name] = rel_fro(p.grad.cpu().numpy(), w)
+    say(f"  {errs}")
+    for k, v in errs.items():
+        assert v <= TOL[prec], (k, v)
+
+
+def test_rprop_lowers_the_loss():
+    """The paper's optimiser (Rprop, lr 1e-3) on the network at N = 4."""
+    n, d = 4, 16
+    gen = torch.Generator().manual_seed(7700)
+    net = qst.MappingNetwork(n, dtype=torch.float64, device=DEV, generator=gen)
+    g = S.rng(7701)
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))
+    fg = dev(f)
+    xg = dev(f / f.sum())
+    opt = torch.optim.Rprop(net.parameters(), lr=1e-3)
+    losses = []
+    for _ in range(30):
+        opt.zero_grad(set_to_none=True)
+        L = qst.likelihood(net(xg), fg, "f64")
+        L.backward()
+        opt.step()
+        losses.append(float(L.item()))
+    say(f"  Rprop losses {losses[0]:.6f} -> {losses[-1]:.6f}")
+    assert losses[-1] < losses[0]
