@@ -276,7 +276,7 @@ def network(qst, f, prec, reps=10):
     achieved GB/s from algorithmic bytes (each weight matrix streamed once
     per pass; the backward also writes both weight gradients), and one whole
     NN-QST training step (network, fused likelihood, backward, the paper's
-    Rprop at lr 1e-3 from torch) per second."""
+    Rprop at lr 1e-3 by qst_rprop_step) per second."""
     import torch
 
     d = 1 << ((f.numel().bit_length() - 1) // 2)
@@ -306,7 +306,7 @@ def network(qst, f, prec, reps=10):
     bwd_us = timed(lambda: qst.fnn_backward(P[2], x, h_pre, grad, prec))
     fwd_bytes = (2 * H * D + 2 * D) * rb + D * 2 * rb  # W1, W2, x, b2 read; T written
     bwd_bytes = (H * D + D) * rb + D * 2 * rb + (2 * H * D + D) * rb  # W2, x, G read; dW2, dW1, db2 written
-    opt = torch.optim.Rprop(net.parameters(), lr=1e-3)
+    opt = qst.Rprop(net.parameters(), lr=1e-3)
 
     def train_step():
         opt.zero_grad(set_to_none=True)
@@ -330,7 +330,7 @@ def network(qst, f, prec, reps=10):
             "backward_hbm_frac": round(bwd_bytes / (bwd_us * 1e-6) / 8e12, 3),
             "nnqst_train_steps_per_s": round(1.0 / step_s, 1),
             "note": "train step = network forward, qst_likelihood, qst_grad_product, network backward, "
-                    "torch Rprop (lr 1e-3) over all parameters"}
+                    "Rprop (lr 1e-3, qst_rprop_step) over all parameters"}
 
 
 def cpu_baseline(T, f, prec):

@@ -293,6 +293,21 @@ qst_status qst_fnn_backward(int n_qubits, qst_prec prec, const void* W2, const v
                             const void* G, int64_t ldG, void* dW1, void* db1, void* dW2, void* db2, void* ws,
                             size_t ws_bytes, void* stream);
 
+/*
+ * One Rprop step (the optimiser of the paper's setup, Sec. 4.1; the
+ * iRprop- rule): for each of count entries,
+ *   s = sign(grad) sign(prev),
+ *   step <- clamp(step * (s > 0 ? eta_plus : s < 0 ? eta_minus : 1),
+ *                 step_min, step_max),
+ *   g' = (s < 0 ? 0 : grad),  param <- param - sign(g') step,  prev <- g'.
+ * param, prev, step [in/out] and grad [in]: count reals each (float64 for
+ * QST_F64, float32 otherwise), device; the caller starts with prev = 0 and
+ * step = the learning rate.  Requires 0 < eta_minus < 1 < eta_plus and
+ * 0 < step_min <= step_max.  count = 0 does nothing.
+ */
+qst_status qst_rprop_step(int64_t count, qst_prec prec, void* param, const void* grad, void* prev, void* step,
+                          double eta_minus, double eta_plus, double step_min, double step_max, void* stream);
+
 /* Workspace in bytes needed by op (a qst_op) at (n_qubits, prec); 0 for an
  * invalid request. */
 size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op);

@@ -206,6 +206,21 @@ def fnn_backward(W2, x, h_pre, G):
     return np.outer(dh_pre, np.asarray(x, dtype=np.float64)), dh_pre, np.outer(gy, h), gy
 
 
+def rprop_step(w, g, prev, step, etas=(0.5, 1.2), step_sizes=(1e-6, 50.0)):
+    """One Rprop step, the optimiser of the paper's setup (Sec. 4.1), in the
+    iRprop- form: where g and the previous gradient agree in sign the step
+    grows by eta+, where they disagree it shrinks by eta- and that entry is
+    not moved (its stored gradient becomes 0); steps are kept within
+    step_sizes; w moves by -sign(g) step.  Returns (w, prev, step)."""
+    w, g = np.asarray(w, dtype=np.float64), np.asarray(g, dtype=np.float64)
+    prev, step = np.asarray(prev, dtype=np.float64), np.asarray(step, dtype=np.float64)
+    s = np.sign(g) * np.sign(prev)
+    factor = np.where(s > 0, etas[1], np.where(s < 0, etas[0], 1.0))
+    step = np.clip(step * factor, step_sizes[0], step_sizes[1])
+    g = np.where(s < 0, 0.0, g)
+    return w - np.sign(g) * step, g, step
+
+
 # ----------------------------------------------------------------------------
 # Product-structured POVM probabilities (Sec. 2.1 Born rule; Sec. 3.3)
 # ----------------------------------------------------------------------------

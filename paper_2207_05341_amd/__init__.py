@@ -21,7 +21,7 @@ from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_GRAD_P
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
     "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "fidelity_lowrank",
-    "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork",
+    "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
 
@@ -360,6 +360,37 @@ class MappingNetwork(torch.nn.Module):
 
     def forward(self, x, prec=None):
         return FnnFn.apply(self.W1, self.b1, self.W2, self.b2, x, prec)
+
+
+class Rprop(torch.optim.Optimizer):
+    """Rprop (iRprop-, the optimiser of the paper's setup) with each tensor's
+    step done by one library call (qst_rprop_step): param, grad, previous
+    gradient and step size streamed once."""
+
+    def __init__(self, params, lr=1e-3, etas=(0.5, 1.2), step_sizes=(1e-6, 50.0)):
+        super().__init__(params, dict(lr=lr, etas=etas, step_sizes=step_sizes))
+
+    @torch.no_grad()
+    def step(self, closure=None):
+        loss = closure() if closure is not None else None
+        for group in self.param_groups:
+            em, ep = group["etas"]
+            smin, smax = group["step_sizes"]
+            for p in group["params"]:
+                if p.grad is None:
+                    continue
+                if p.dtype not in (torch.float32, torch.float64) or not p.is_cuda or not p.is_contiguous():
+                    raise ValueError("Rprop takes contiguous float32 / float64 GPU parameters")
+                st = self.state[p]
+                if not st:
+                    st["prev"] = torch.zeros_like(p)
+                    st["step"] = torch.full_like(p, group["lr"])
+                g = p.grad.contiguous()
+                pr = QST_F64 if p.dtype == torch.float64 else QST_F32
+                _lib.check(_lib.lib().qst_rprop_step(p.numel(), pr, p.data_ptr(), g.data_ptr(), st["prev"].data_ptr(),
+                                                     st["step"].data_ptr(), em, ep, smin, smax, _stream(p.device)),
+                           "qst_rprop_step")
+        return loss
 
 
 class LikelihoodFn(torch.autograd.Function):

@@ -30,6 +30,8 @@ SIGNATURES = {
     "qst_state_premap": (_int, [_int, _int, _int, _vp, _i64, _vp, _i64, _vp]),
     "qst_fnn_forward": (_int, [_int, _int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_fnn_backward": (_int, [_int, _int, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qst_rprop_step": (_int, [_i64, _int, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, _vp]),
     "qst_fidelity_lowrank": (_int, [_int, _int, _vp, _i64, _vp, _i64, _int, _vp, _vp, _sz, _vp]),
     "qst_fidelity_classical": (_int, [_int, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qst_workspace_bytes": (_sz, [_int, _int, _int]),

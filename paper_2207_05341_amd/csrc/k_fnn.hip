@@ -280,6 +280,28 @@ __global__ __launch_bounds__(256) void fnn_l1_back_kernel(const R* __restrict__ 
   for (int j = 0; j < H; ++j) dW1[int64_t(j) * D + c] = R(ds[j] * xv);
 }
 
+// One Rprop step per entry (iRprop-): s = sign(g) sign(prev); the step
+// grows by eta+ where s > 0, shrinks by eta- where s < 0 (and that entry's
+// gradient is dropped), and is clamped; param moves by -sign(g') step.
+template <typename R>
+__global__ __launch_bounds__(256) void rprop_kernel(R* __restrict__ w, const R* __restrict__ g, R* __restrict__ prev,
+                                                    R* __restrict__ step, int64_t count, R eta_minus, R eta_plus,
+                                                    R smin, R smax) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += int64_t(gridDim.x) * 256) {
+    const R gi = g[i], pi = prev[i];
+    const int s = ((gi > R(0)) - (gi < R(0))) * ((pi > R(0)) - (pi < R(0)));
+    R st = step[i];
+    if (s > 0) st = st * eta_plus;
+    else if (s < 0) st = st * eta_minus;
+    st = st < smin ? smin : (st > smax ? smax : st);
+    const R gg = s < 0 ? R(0) : gi;
+    const R sg = R((gg > R(0)) - (gg < R(0)));
+    w[i] = w[i] - sg * st;
+    prev[i] = gg;
+    step[i] = st;
+  }
+}
+
 template <typename R>
 hipError_t run_fnn_forward(int n, const void* W1, const void* b1, const void* W2, const void* b2, const void* x,
                            void* h_pre, void* T, int64_t ldT, void* ws, hipStream_t s) {
@@ -341,6 +363,22 @@ hipError_t launch_fnn_forward(qst_prec prec, int n, const void* W1, const void* 
                               const void* x, void* h_pre, void* T, int64_t ldT, void* ws, hipStream_t s) {
   if (prec == QST_F64) return run_fnn_forward<double>(n, W1, b1, W2, b2, x, h_pre, T, ldT, ws, s);
   return run_fnn_forward<float>(n, W1, b1, W2, b2, x, h_pre, T, ldT, ws, s);
+}
+
+hipError_t launch_rprop(qst_prec prec, int64_t count, void* w, const void* g, void* prev, void* step, double eta_minus,
+                        double eta_plus, double smin, double smax, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const int64_t blocks = (count + 255) / 256;
+  const unsigned grid = unsigned(blocks < 8192 ? blocks : 8192);
+  if (prec == QST_F64)
+    rprop_kernel<double><<<grid, 256, 0, s>>>(static_cast<double*>(w), static_cast<const double*>(g),
+                                              static_cast<double*>(prev), static_cast<double*>(step), count, eta_minus,
+                                              eta_plus, smin, smax);
+  else
+    rprop_kernel<float><<<grid, 256, 0, s>>>(static_cast<float*>(w), static_cast<const float*>(g),
+                                             static_cast<float*>(prev), static_cast<float*>(step), count,
+                                             float(eta_minus), float(eta_plus), float(smin), float(smax));
+  return hipGetLastError();
 }
 
 hipError_t launch_fnn_backward(qst_prec prec, int n, const void* W2, const void* x, const void* h_pre, const void* G,

@@ -116,6 +116,29 @@ qst_status qst_fnn_backward(int n, qst_prec prec, const void* W2, const void* x,
   return QST_OK;
 }
 
+qst_status qst_rprop_step(int64_t count, qst_prec prec, void* param, const void* grad, void* prev, void* step,
+                          double eta_minus, double eta_plus, double step_min, double step_max, void* stream) {
+  std::string msg;
+  if (!prec_valid(prec)) return fail(QST_ERR_INVALID_ARG, "unknown precision " + std::to_string(prec));
+  if (count < 0) return fail(QST_ERR_INVALID_ARG, "count is negative");
+  if (!(eta_minus > 0.0 && eta_minus < 1.0 && eta_plus > 1.0))
+    return fail(QST_ERR_INVALID_ARG, "Rprop factors need 0 < eta_minus < 1 < eta_plus");
+  if (!(step_min > 0.0 && step_min <= step_max))
+    return fail(QST_ERR_INVALID_ARG, "Rprop step bounds need 0 < step_min <= step_max");
+  if (count > 0) {
+    qst_status st;
+    const void* ptrs[] = {param, grad, prev, step};
+    const char* names[] = {"param", "grad", "prev", "step"};
+    for (int i = 0; i < 4; ++i)
+      if ((st = check_ptr(ptrs[i], names[i], msg)) != QST_OK) return fail(st, msg);
+  }
+  hipError_t e = launch_rprop(prec, count, param, grad, prev, step, eta_minus, eta_plus, step_min, step_max,
+                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "Rprop step");
+  clear_error();
+  return QST_OK;
+}
+
 qst_status qst_fidelity_lowrank(int n, qst_prec prec, const void* T, int64_t ldT, const void* W, int64_t ldW, int r,
                                 double* F_dev, void* ws, size_t ws_bytes, void* stream) {
   std::string msg;

@@ -37,6 +37,10 @@ hipError_t launch_fnn_forward(qst_prec prec, int n, const void* W1, const void* 
 hipError_t launch_fnn_backward(qst_prec prec, int n, const void* W2, const void* x, const void* h_pre, const void* G,
                                int64_t ldG, void* dW1, void* db1, void* dW2, void* db2, void* ws, hipStream_t s);
 
+// One Rprop step over count entries.
+hipError_t launch_rprop(qst_prec prec, int64_t count, void* w, const void* g, void* prev, void* step, double eta_minus,
+                        double eta_plus, double smin, double smax, hipStream_t s);
+
 // Fidelities (workspace laid out by fidelity_layout).
 hipError_t launch_fidelity_lowrank(qst_prec prec, const void* T, int64_t ldT, const void* W, int64_t ldW, int r,
                                    int n, void* ws, double* F, hipStream_t s);

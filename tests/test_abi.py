@@ -297,6 +297,23 @@ def test_fnn_validation(L):
     assert bwd(nb=0) == lib_mod.QST_ERR_WORKSPACE
 
 
+def test_rprop_validation(L):
+    def call(count=8, prec=0, p=FAKE, g=FAKE2, pr=FAKE, st=FAKE2, em=0.5, ep=1.2, smin=1e-6, smax=50.0):
+        return L.qst_rprop_step(count, prec, p, g, pr, st, em, ep, smin, smax, None)
+
+    assert call(count=-1) == lib_mod.QST_ERR_INVALID_ARG and "negative" in _err(L)
+    assert call(prec=9) == lib_mod.QST_ERR_INVALID_ARG and "precision" in _err(L)
+    assert call(em=1.0) == lib_mod.QST_ERR_INVALID_ARG and "eta" in _err(L)
+    assert call(ep=1.0) == lib_mod.QST_ERR_INVALID_ARG and "eta" in _err(L)
+    assert call(smin=0.0) == lib_mod.QST_ERR_INVALID_ARG and "step" in _err(L)
+    assert call(smin=2.0, smax=1.0) == lib_mod.QST_ERR_INVALID_ARG
+    for k, name in enumerate(["param", "grad", "prev", "step"]):
+        args = dict(p=FAKE, g=FAKE2, pr=FAKE, st=FAKE2)
+        args[["p", "g", "pr", "st"][k]] = None
+        assert call(**args) == lib_mod.QST_ERR_INVALID_ARG and f"{name} is NULL" in _err(L)
+    assert call(count=0, p=None, g=None, pr=None, st=None) == lib_mod.QST_OK  # nothing to do
+
+
 def test_plan_unit_builds_without_hip(tmp_path):
     """The validation / planning unit is HIP-free: it compiles with g++."""
     src = os.path.join(ROOT, "paper_2207_05341_amd", "csrc", "qst_plan.cpp")

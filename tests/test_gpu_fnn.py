@@ -108,6 +108,33 @@ def test_network_chain_through_autograd(prec, n):
         assert v <= TOL[prec], (k, v)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rprop_step_against_oracle(prec):
+    """qst_rprop_step over six steps (sign agreements, disagreements and
+    zero gradients) against the oracle's rule, and the Rprop class against
+    torch.optim.Rprop on the same parameters."""
+    rt = np.float64 if prec == "f64" else np.float32
+    g = S.rng(7800)
+    count = 100_003  # not a multiple of the block
+    w0 = g.standard_normal(count).astype(rt)
+    p = torch.nn.Parameter(dev(w0.copy()))
+    q = torch.nn.Parameter(dev(w0.copy()))
+    ours, ref = qst.Rprop([p], lr=1e-3), torch.optim.Rprop([q], lr=1e-3)
+    w, prev, step = w0.astype(np.float64), np.zeros(count), np.full(count, rt(1e-3), dtype=np.float64)
+    for k in range(6):
+        grad = (g.standard_normal(count) * (1 if k % 2 else -1)).astype(rt)
+        grad[k::7] = 0
+        p.grad, q.grad = dev(grad.copy()), dev(grad.copy())
+        ours.step()
+        ref.step()
+        w, prev, step = O.rprop_step(w, grad.astype(np.float64), prev, step)
+    torch.cuda.synchronize()
+    got = p.detach().cpu().numpy()
+    tol = 1e-14 if prec == "f64" else 1e-6
+    assert np.max(np.abs(got - w)) <= tol * np.max(np.abs(w))
+    assert np.max(np.abs(got - q.detach().cpu().numpy())) <= tol * np.max(np.abs(w))
+
+
 def test_rprop_lowers_the_loss():
     """The paper's optimiser (Rprop, lr 1e-3) on the network at N = 4."""
     n, d = 4, 16
@@ -118,7 +145,7 @@ def test_rprop_lowers_the_loss():
     f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))
     fg = dev(f)
     xg = dev(f / f.sum())
-    opt = torch.optim.Rprop(net.parameters(), lr=1e-3)
+    opt = qst.Rprop(net.parameters(), lr=1e-3)
     losses = []
     for _ in range(30):
         opt.zero_grad(set_to_none=True)

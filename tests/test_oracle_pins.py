@@ -572,3 +572,27 @@ def test_fnn_backward_central_differences():
             an = float(np.sum(grads[k] * E))
             assert abs(fd - an) <= 1e-6 * max(1.0, np.linalg.norm(grads[k])), (k, fd, an)
     assert np.array_equal(O.leaky_relu(np.array([-2.0, 0.0, 3.0])), np.array([-0.02, 0.0, 3.0]))
+
+
+def test_rprop_step_matches_the_library_optimiser():
+    """The oracle's Rprop against torch.optim.Rprop (CPU, float64) over a
+    few steps with sign changes, and the rule's special cases by hand."""
+    torch = pytest.importorskip("torch")
+    g = S.rng(1500)
+    w0 = g.standard_normal(50)
+    p = torch.nn.Parameter(torch.from_numpy(w0.copy()))
+    opt = torch.optim.Rprop([p], lr=1e-3)
+    w, prev, step = w0.copy(), np.zeros(50), np.full(50, 1e-3)
+    for k in range(6):
+        grad = g.standard_normal(50) * (1 if k % 2 else -1)
+        grad[:5] = 0.0
+        p.grad = torch.from_numpy(grad.copy())
+        opt.step()
+        w, prev, step = O.rprop_step(w, grad, prev, step)
+        np.testing.assert_allclose(p.detach().numpy(), w, rtol=0, atol=1e-15)
+    # by hand: agreement grows the step, disagreement shrinks it and holds w
+    w1, pr1, st1 = O.rprop_step(np.array([1.0, 1.0, 1.0]), np.array([2.0, -2.0, 3.0]),
+                                np.array([1.0, 1.0, 0.0]), np.array([0.1, 0.1, 0.1]))
+    np.testing.assert_allclose(st1, [0.12, 0.05, 0.1])
+    np.testing.assert_allclose(w1, [0.88, 1.0, 0.9])
+    np.testing.assert_allclose(pr1, [2.0, 0.0, 3.0])
