@@ -7,7 +7,8 @@ central differences through the whole loss).
   at N = 1 .. 8 in both precisions; bitwise repeats;
 * the whole NN-QST chain, network -> T -> likelihood, differentiated by
   autograd, against the oracle chain at N = 4 (FP64) and N = 8 (FP32);
-* a short Rprop run (the paper's optimiser, lr 1e-3) lowers the loss.
+* the Rprop step against the oracle and torch's Rprop; a short run lowers the
+  loss; ten steps of the whole method against the oracle at N = 5.
 
 Tolerances: FP64 1e-12, FP32 1e-5 (relative; Frobenius for matrices).
 """
@@ -155,3 +156,38 @@ def test_rprop_lowers_the_loss():
         losses.append(float(L.item()))
     say(f"  Rprop losses {losses[0]:.6f} -> {losses[-1]:.6f}")
     assert losses[-1] < losses[0]
+
+
+def test_nnqst_trajectory_against_oracle():
+    """Ten steps of the whole method at N = 5 in FP64 -- network, likelihood,
+    backward, Rprop -- against the same steps by the oracle from the same
+    initial parameters: losses and final parameters."""
+    n, d = 5, 32
+    gen = torch.Generator().manual_seed(7900)
+    net = qst.MappingNetwork(n, dtype=torch.float64, device=DEV, generator=gen)
+    g = S.rng(7901)
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))
+    x = f / f.sum()
+    fg, xg = dev(f), dev(x)
+    P = [p.detach().cpu().numpy().copy() for p in (net.W1, net.b1, net.W2, net.b2)]
+    prev = [np.zeros_like(p) for p in P]
+    step = [np.full_like(p, 1e-3) for p in P]
+    opt = qst.Rprop(net.parameters(), lr=1e-3)
+    worst = 0.0
+    for _ in range(10):
+        opt.zero_grad(set_to_none=True)
+        L = qst.likelihood(net(xg), fg, "f64")
+        L.backward()
+        opt.step()
+        T, h_pre, _ = O.fnn_forward(*P, x)
+        G, L_w = O.grad_T(T, f)
+        grads = O.fnn_backward(P[2], x, h_pre, G)
+        for k in range(4):
+            P[k], prev[k], step[k] = O.rprop_step(P[k], grads[k], prev[k], step[k])
+        worst = max(worst, abs(float(L.item()) - L_w) / abs(L_w))
+    torch.cuda.synchronize()
+    say(f"  worst loss difference {worst:.2e}")
+    assert worst <= 1e-12
+    for p, w in zip((net.W1, net.b1, net.W2, net.b2), P):
+        assert rel_fro(p.detach().cpu().numpy(), w) <= 1e-12
