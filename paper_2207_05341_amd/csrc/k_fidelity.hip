@@ -7,7 +7,8 @@
 // matrix C = M M^dagger / (tau tw), M = W^dagger T (r x d), so
 // F_q = (sum_i sqrt(lambda_i(C)))^2.  Four launches:
 //   1. fid_partial_kernel: M over row blocks of T (FP64 sums; also the
-//      partial sums of |T|^2 for tau) -- reads T once per 16 target columns;
+//      partial sums of |T|^2 for tau) -- reads T once per 8 or 16 target
+//      columns;
 //   2. fid_mreduce_kernel: M from the row-block sums, in order;
 //   3. fid_gram_kernel: C_ab = sum_j M_aj conj(M_bj), one workgroup per pair;
 //   4. fid_jacobi_kernel: tau, tw, C / (tau tw), parallel cyclic Jacobi
@@ -25,7 +26,6 @@ namespace qst {
 
 namespace {
 
-constexpr int kAChunk = 16;  // target columns per pass over T
 constexpr int kRowChunk = 64;
 constexpr int kRowGroup = 8;
 
@@ -36,16 +36,17 @@ struct Zd {
 // Workgroup (cb, rb): columns cb*64 .. +63 of T (fewer when d < 64), rows
 // rb*RB .. (rb+1)*RB - 1.  Thread t: column c = t & 63, row quarter
 // q = t >> 6 (rows i0 + q, i0 + q + 4, ... of each 64-row chunk).  For each
-// chunk of 16 target columns a0.., W's rows of the chunk are staged in LDS
+// chunk of AC target columns a0.., W's rows of the chunk are staged in LDS
 // and every thread adds conj(W_ia) T_ij over its rows; the quarters are
 // summed in order and P[rb][a][j] written.  In the first pass the thread
 // also sums |T_ij|^2 (tau), written per workgroup to taup[rb * ncb + cb].
-template <typename R>
+// AC target columns per pass over T (8 for ranks up to 8, else 16).
+template <typename R, int AC>
 __global__ __launch_bounds__(256) void fid_partial_kernel(const Cx<R>* __restrict__ T, int64_t ldT,
                                                           const Cx<R>* __restrict__ W, int64_t ldW, int r, int d,
                                                           int RB, Zd* __restrict__ P, double* __restrict__ taup) {
-  __shared__ Zd wl[kRowChunk][kAChunk];
-  __shared__ Zd red[3][64][kAChunk];
+  __shared__ Zd wl[kRowChunk][AC];
+  __shared__ Zd red[3][64][AC];
   __shared__ double rtau[4];
   const int ncb = d < 64 ? 1 : d / 64;
   const int cb = blockIdx.x % ncb, rb = blockIdx.x / ncb;
@@ -55,14 +56,14 @@ __global__ __launch_bounds__(256) void fid_partial_kernel(const Cx<R>* __restric
   const int64_t r0 = int64_t(rb) * RB;
   const int chunk = RB < kRowChunk ? RB : kRowChunk;
   double tsum = 0.0;
-  for (int a0 = 0; a0 < r; a0 += kAChunk) {
-    Zd acc[kAChunk];
+  for (int a0 = 0; a0 < r; a0 += AC) {
+    Zd acc[AC];
 #pragma unroll
-    for (int a = 0; a < kAChunk; ++a) acc[a] = Zd{0.0, 0.0};
+    for (int a = 0; a < AC; ++a) acc[a] = Zd{0.0, 0.0};
     for (int i0 = 0; i0 < RB; i0 += chunk) {
       __syncthreads();  // the previous chunk's W is no longer read
-      for (int e = t; e < chunk * kAChunk; e += 256) {
-        const int ii = e / kAChunk, a = e % kAChunk;
+      for (int e = t; e < chunk * AC; e += 256) {
+        const int ii = e / AC, a = e % AC;
         Cx<R> w{R(0), R(0)};
         if (a0 + a < r) w = W[(r0 + i0 + ii) * ldW + a0 + a];
         wl[ii][a] = Zd{double(w.re), double(w.im)};
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void fid_partial_kernel(const Cx<R>* __restric
             const double xr = double(xg[u].re), xi = double(xg[u].im);
             if (a0 == 0) tsum += xr * xr + xi * xi;
 #pragma unroll
-            for (int a = 0; a < kAChunk; ++a) {
+            for (int a = 0; a < AC; ++a) {
               const double wr = wl[ii][a].re, wi = wl[ii][a].im;
               // conj(w) x
               acc[a].re += wr * xr + wi * xi;
@@ -99,12 +100,12 @@ __global__ __launch_bounds__(256) void fid_partial_kernel(const Cx<R>* __restric
     __syncthreads();
     if (q > 0) {
 #pragma unroll
-      for (int a = 0; a < kAChunk; ++a) red[q - 1][c][a] = acc[a];
+      for (int a = 0; a < AC; ++a) red[q - 1][c][a] = acc[a];
     }
     __syncthreads();
     if (q == 0 && col) {
 #pragma unroll
-      for (int a = 0; a < kAChunk; ++a) {
+      for (int a = 0; a < AC; ++a) {
         Zd s = acc[a];
         for (int k = 0; k < 3; ++k) {
           s.re += red[k][c][a].re;
@@ -271,14 +272,12 @@ __global__ __launch_bounds__(256) void fid_jacobi_kernel(const double* __restric
         if (q < 0) continue;
         const double cs = rot[k][0], sn = rot[k][1], er = rot[k][2], ei = rot[k][3];
         const Zd rp_ = C[p][j], rq = C[q][j];
-        // cs rp - sn e rq ;  sn conj(e) rp + cs rq
-        C[p][j] = Zd{cs * rp_.re - sn * (er * rq.re - ei * rq.im), cs * rp_.im - sn * (er * rq.im + ei * rq.re)};
-        C[q][j] = Zd{sn * (er * rp_.re + ei * rp_.im) + cs * rq.re, sn * (er * rp_.im - ei * rp_.re) + cs * rq.im};
-      }
-      __syncthreads();
-      if (t < np && pq[t][1] >= 0) {
-        C[pq[t][0]][pq[t][1]] = Zd{0.0, 0.0};
-        C[pq[t][1]][pq[t][0]] = Zd{0.0, 0.0};
+        // cs rp - sn e rq ;  sn conj(e) rp + cs rq; the rotated pair's own
+        // off-diagonal entries are zero by construction and stored as such
+        C[p][j] = j == q ? Zd{0.0, 0.0}
+                         : Zd{cs * rp_.re - sn * (er * rq.re - ei * rq.im), cs * rp_.im - sn * (er * rq.im + ei * rq.re)};
+        C[q][j] = j == p ? Zd{0.0, 0.0}
+                         : Zd{sn * (er * rp_.re + ei * rp_.im) + cs * rq.re, sn * (er * rp_.im - ei * rp_.re) + cs * rq.im};
       }
       __syncthreads();
     }
@@ -334,9 +333,14 @@ hipError_t run_fidelity_lowrank(const void* T, int64_t ldT, const void* W, int64
   Zd* C = reinterpret_cast<Zd*>(base + fl.gram);
   double* taup = reinterpret_cast<double*>(base + fl.taup);
   const int ncb = d < 64 ? 1 : d / 64;
-  fid_partial_kernel<R><<<unsigned(ncb * fl.nrb), 256, 0, s>>>(static_cast<const Cx<R>*>(T), ldT,
-                                                               static_cast<const Cx<R>*>(W), ldW, r, d, d / fl.nrb,
-                                                               P, taup);
+  if (r <= 8)
+    fid_partial_kernel<R, 8><<<unsigned(ncb * fl.nrb), 256, 0, s>>>(static_cast<const Cx<R>*>(T), ldT,
+                                                                    static_cast<const Cx<R>*>(W), ldW, r, d,
+                                                                    d / fl.nrb, P, taup);
+  else
+    fid_partial_kernel<R, 16><<<unsigned(ncb * fl.nrb), 256, 0, s>>>(static_cast<const Cx<R>*>(T), ldT,
+                                                                     static_cast<const Cx<R>*>(W), ldW, r, d,
+                                                                     d / fl.nrb, P, taup);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   Zd* M = reinterpret_cast<Zd*>(base + fl.mrow);
