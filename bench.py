@@ -323,14 +323,67 @@ def network(qst, f, prec, reps=10):
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / reps
     del net, opt, T, G, grad
+    conv = convergence(qst, n, prec, f.device)
     return {"parameters": 2 * H * D + H + D,
             "forward_us": round(fwd_us, 1), "forward_GB_s": round(fwd_bytes / (fwd_us * 1e-6) / 1e9, 1),
             "forward_hbm_frac": round(fwd_bytes / (fwd_us * 1e-6) / 8e12, 3),
             "backward_us": round(bwd_us, 1), "backward_GB_s": round(bwd_bytes / (bwd_us * 1e-6) / 1e9, 1),
             "backward_hbm_frac": round(bwd_bytes / (bwd_us * 1e-6) / 8e12, 3),
             "nnqst_train_steps_per_s": round(1.0 / step_s, 1),
+            "nnqst_1000_steps": conv,
             "note": "train step = network forward, qst_likelihood, qst_grad_product, network backward, "
                     "Rprop (lr 1e-3, qst_rprop_step) over all parameters"}
+
+
+def convergence(qst, n, prec, dev, steps=1000):
+    """NN-QST as the paper runs it: a fresh network trained by Rprop (lr
+    1e-3) for 1000 steps on frequencies of 10^7 shots of a Haar-random pure
+    state (p computed by the library from T0 = [psi 0 ... 0]); wall time,
+    and F_q of the network's state against the target after the run."""
+    import numpy as np
+    import torch
+
+    import synth as S
+
+    d = 1 << n
+    g = S.rng(13)
+    psi = S.haar_vector(g, d)
+    ct = np.complex128 if prec == "f64" else np.complex64
+    T0 = np.zeros((d, d), dtype=ct)
+    T0[:, 0] = psi
+    rho0, _ = qst.state_map(torch.from_numpy(T0).to(dev), prec)
+    p0 = qst.povm_probs(rho0, prec).double().cpu().numpy()
+    del rho0
+    p0 = np.clip(p0, 0.0, None)
+    f_np = S.multinomial_freqs(g, 10_000_000, p0 / p0.sum())
+    rt = torch.float64 if prec == "f64" else torch.float32
+    f = torch.from_numpy(f_np).to(dev, rt)
+    x = (f.double() / f.double().sum()).to(rt)
+    net = qst.MappingNetwork(n, dtype=rt, device=dev, generator=torch.Generator().manual_seed(14))
+    opt = qst.Rprop(net.parameters(), lr=1e-3)
+    W = torch.from_numpy(psi.astype(ct).reshape(d, 1)).to(dev)
+    with torch.no_grad():
+        f_start = float(qst.fidelity_lowrank(net(x, prec).contiguous(), W, prec).item())
+    trace = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        opt.zero_grad(set_to_none=True)
+        L = qst.likelihood(net(x, prec), f, prec)
+        L.backward()
+        opt.step()
+        if k % 100 == 0:
+            with torch.no_grad():
+                trace.append(qst.fidelity_lowrank(net(x, prec).contiguous(), W, prec))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    trace = [round(float(t.item()), 6) for t in trace]
+    out = {"seconds": round(wall, 2), "loss_last": float(L.item()), "fidelity_start": round(f_start, 6),
+           "fidelity_every_100_steps": trace,
+           "target": "Haar-random pure state, 10^7 shots; F_q of the network's rho against it",
+           "note": "wall time includes the ten fidelity evaluations"}
+    del net, opt, f, x
+    return out
 
 
 def cpu_baseline(T, f, prec):
