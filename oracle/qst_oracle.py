@@ -12,7 +12,8 @@ What it computes, written from the paper (Wang, Cheng, Li, Chen,
               at P = 2 -- see the reading of T^dagger T vs T T^dagger below)
 * modes       the pre-maps of Chol_H (Hermitian part, Sec. 2.2.2 and
               Eq. unified_DP) and Chol_Delta (lower triangle, Eq. T_matrix),
-              and the P-order absolute projection (Eq. abs_P) by eigh
+              and the P-order absolute projection (Eq. abs_P) by eigh, with
+              the absolute map A = Q |Lambda|^(P/2) Q^dagger and its adjoint
 * network     the 3-layer FNN of Sec. 3.1 (4^N -> 2N -> 4^N) filling the
               Hermitian T, and its backward
 * Born rule   p_k = Tr(M_k rho)                  (Sec. 2.1, Born rule)
@@ -151,6 +152,54 @@ def abs_projection(H: np.ndarray, P: float) -> np.ndarray:
     lam, Q = np.linalg.eigh(np.asarray(H, dtype=np.complex128))
     w = np.abs(lam) ** P
     return (Q * (w / math.fsum(w.tolist()))) @ Q.conj().T
+
+
+def abs_map(T: np.ndarray, P: float):
+    """P-order absolute map of Sec. 3.2: for the Hermitian part H = Q Lambda
+    Q^dagger of T, A = Q |Lambda|^(P/2) Q^dagger.  A is Hermitian and
+    positive semidefinite, so A A^dagger / Tr(A A^dagger) = Q |Lambda|^P
+    Q^dagger / Tr |Lambda|^P: the P-order absolute projection (Eq. abs_P)
+    computed by the library's state map.  Returns (A, Q, lam)."""
+    lam, Q = np.linalg.eigh(hermitian_part(T))
+    return (Q * np.abs(lam) ** (P / 2.0)) @ Q.conj().T, Q, lam
+
+
+def abs_divided_differences(lam: np.ndarray, P: float) -> np.ndarray:
+    """Gamma_ij = (g(l_i) - g(l_j)) / (l_i - l_j) for g(l) = |l|^(P/2), and
+    g'(l_i) = (P/2) sign(l_i) |l_i|^(P/2 - 1) where l_i = l_j (0 at l = 0,
+    the one-sided derivatives there being infinite or of opposite signs)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    a = P / 2.0
+    g = np.abs(lam) ** a
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dg = np.where(lam == 0.0, 0.0, a * np.sign(lam) * np.abs(lam) ** (a - 1.0))
+        num = g[:, None] - g[None, :]
+        den = lam[:, None] - lam[None, :]
+        gam = np.where(den == 0.0, 0.0, num / np.where(den == 0.0, 1.0, den))
+    ties = den == 0.0
+    gam[ties] = np.broadcast_to(dg[:, None], gam.shape)[ties]
+    return gam
+
+
+def abs_map_backward(Q: np.ndarray, lam: np.ndarray, P: float, GA: np.ndarray) -> np.ndarray:
+    """dL/dT from dL/dA (both dL/dRe + i dL/dIm) through A = g(H), H the
+    Hermitian part of T: the first-order change of a spectral function of a
+    Hermitian matrix is Q (Gamma o (Q^dagger dH Q)) Q^dagger (Gamma the
+    divided differences of g on the eigenvalues), which is self-adjoint, as
+    is the Hermitian part; so dL/dT = Q (Gamma o (Q^dagger S Q)) Q^dagger
+    with S = (GA + GA^dagger) / 2."""
+    Q = np.asarray(Q, dtype=np.complex128)
+    S = hermitian_part(GA)
+    M = Q.conj().T @ S @ Q
+    return Q @ (abs_divided_differences(lam, P) * M) @ Q.conj().T
+
+
+def grad_T_abs(T: np.ndarray, f: np.ndarray, P: float, povm: np.ndarray | None = None):
+    """Gradient of L(rho) with rho the P-order absolute projection of T:
+    dL/dA at A = abs_map(T, P), then abs_map_backward.  Returns (grad, L)."""
+    A, Q, lam = abs_map(T, P)
+    gA, L = grad_T(A, f, povm)
+    return abs_map_backward(Q, lam, P, gA), L
 
 
 # ----------------------------------------------------------------------------

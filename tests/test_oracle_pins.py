@@ -489,6 +489,98 @@ def test_abs_projection_closed_form_and_cholh():
         assert np.min(np.linalg.eigvalsh(R)) >= -1e-14
 
 
+def test_abs_map_closed_forms():
+    """The absolute map A = Q |Lambda|^(P/2) Q^dagger of the Hermitian part H
+    against forms that need no eigendecomposition: P = 0 gives I, P = 4
+    gives H H, and A = (H H)^(P/4) by scipy's fractional matrix power
+    (Schur-Pade) and its square root; A A^dagger / Tr is Eq. abs_P."""
+    g = S.rng(1330)
+    for n in (1, 3, 5):
+        d = 1 << n
+        T = S.ginibre(g, d)
+        H = O.hermitian_part(T)
+        HH = H @ H
+        np.testing.assert_allclose(O.abs_map(T, 0.0)[0], np.eye(d), atol=1e-12)
+        np.testing.assert_allclose(O.abs_map(T, 4.0)[0], HH, atol=1e-12 * np.abs(HH).max())
+        np.testing.assert_allclose(O.abs_map(T, 2.0)[0], scipy.linalg.sqrtm(HH), atol=1e-10 * np.abs(H).max())
+        for P in (0.5, 1.0, 1.5, 3.0):
+            A, Q, lam = O.abs_map(T, P)
+            want = scipy.linalg.fractional_matrix_power(HH, P / 4.0)
+            assert np.abs(A - want).max() <= 1e-9 * np.abs(want).max(), P
+            np.testing.assert_allclose(A, A.conj().T, atol=1e-13 * np.abs(A).max())
+            rho = A @ A.conj().T / np.trace(A @ A.conj().T).real
+            np.testing.assert_allclose(rho, O.abs_projection(H, P), atol=1e-13)
+            np.testing.assert_allclose((Q * lam) @ Q.conj().T, H, atol=1e-13 * np.abs(H).max())
+
+
+def test_abs_divided_differences():
+    """Gamma for g = |l|^(P/2): P = 4 gives l_i + l_j (ties included), P = 2
+    with the signs of l_i, l_j equal gives their common sign and with
+    opposite signs (|l_i| - |l_j|)/(l_i - l_j); ties take g'."""
+    lam = np.array([-2.0, -0.5, 0.25, 0.25, 3.0])
+    np.testing.assert_allclose(O.abs_divided_differences(lam, 4.0), lam[:, None] + lam[None, :], atol=1e-15)
+    G2 = O.abs_divided_differences(lam, 2.0)
+    for i in range(5):
+        for j in range(5):
+            if np.sign(lam[i]) == np.sign(lam[j]):
+                assert G2[i, j] == np.sign(lam[i])
+            else:
+                assert abs(G2[i, j] - (abs(lam[i]) - abs(lam[j])) / (lam[i] - lam[j])) <= 1e-15
+    G1 = O.abs_divided_differences(lam, 1.0)
+    assert abs(G1[2, 3] - 0.5 * 0.25 ** -0.5) <= 1e-15 and abs(G1[1, 1] + 0.5 * 0.5 ** -0.5) <= 1e-15
+
+
+def test_abs_map_backward_p4_closed_form():
+    """At P = 4, A = H H, so dL/dT = S H + H S (S the Hermitian part of
+    dL/dA) with no eigendecomposition."""
+    g = S.rng(1340)
+    for n in (2, 4):
+        d = 1 << n
+        T, GA = S.ginibre(g, d), S.ginibre(g, d)
+        A, Q, lam = O.abs_map(T, 4.0)
+        H, Sg = O.hermitian_part(T), O.hermitian_part(GA)
+        want = Sg @ H + H @ Sg
+        np.testing.assert_allclose(O.abs_map_backward(Q, lam, 4.0, GA), want, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("P", [0.5, 1.0, 1.5, 2.0, 3.0])
+def test_abs_map_backward_central_differences(P):
+    """phi(T) = Re<W, A(T)> by central differences on random complex
+    directions E against Re<abs_map_backward(W), E>."""
+    g = S.rng(1350 + int(4 * P))
+    d = 8
+    T, W = S.ginibre(g, d), S.ginibre(g, d)
+    A, Q, lam = O.abs_map(T, P)
+    grad = O.abs_map_backward(Q, lam, P, W)
+    h = 1e-6
+    for _ in range(4):
+        E = S.ginibre(g, d)
+        fp = np.vdot(W, O.abs_map(T + h * E, P)[0]).real
+        fm = np.vdot(W, O.abs_map(T - h * E, P)[0]).real
+        fd, an = (fp - fm) / (2 * h), np.vdot(grad, E).real
+        assert abs(fd - an) <= 1e-6 * (abs(an) + np.abs(grad).max()), (P, fd, an)
+
+
+def test_abs_likelihood_gradient_central_differences():
+    """L of the P-order absolute projection (P = 1.5) through the whole
+    likelihood: grad_T_abs against central differences."""
+    g = S.rng(1360)
+    n, d, P = 3, 8, 1.5
+    T = S.ginibre(g, d)
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 5000, O.probs_real(S.depolarised_pure(psi, 0.2)))
+    grad, L = O.grad_T_abs(T, f, P)
+    rho = O.abs_projection(O.hermitian_part(T), P)
+    assert abs(L - O.nll(O.probs_real(rho), f)) <= 1e-12 * abs(L)
+    h = 1e-6
+    for _ in range(4):
+        E = S.ginibre(g, d)
+        Lp = O.loss_of_T(O.abs_map(T + h * E, P)[0], f)
+        Lm = O.loss_of_T(O.abs_map(T - h * E, P)[0], f)
+        fd, an = (Lp - Lm) / (2 * h), np.vdot(grad, E).real
+        assert abs(fd - an) <= 1e-6 * (abs(an) + np.abs(grad).max())
+
+
 @pytest.mark.parametrize("mode", ["hermitian", "lower"])
 def test_mode_gradient_central_differences(mode):
     """L(premap(T)) by central differences on random complex directions
