@@ -84,7 +84,8 @@ typedef enum {
   QST_OP_LIKELIHOOD = 4,
   QST_OP_GRAD_PRODUCT = 5,
   QST_OP_FIDELITY = 6,
-  QST_OP_FNN = 7
+  QST_OP_FNN = 7,
+  QST_OP_ABS_MAP = 8
 } qst_op;
 
 /*
@@ -227,6 +228,53 @@ typedef enum {
  */
 qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X, int64_t ldX, void* Y,
                             int64_t ldY, void* stream);
+
+/*
+ * P-order absolute map (Sec. 3.2 Eq. abs_P and the map A(T)_P before it).
+ * With H = (T + T^dagger) / 2 = Q Lambda Q^dagger,
+ *   A = Q |Lambda|^(P/2) Q^dagger,
+ * Hermitian positive semidefinite, so that the state map of A (qst_state_map,
+ * qst_likelihood) gives rho = Q |Lambda|^P Q^dagger / Tr |Lambda|^P, the
+ * P-order absolute projection; P = 2 is Chol_H (Eq. unified_DP).
+ * The eigendecomposition is a cyclic two-sided Jacobi method in FP64 on the
+ * device, whatever prec; the call synchronises the stream once per sweep
+ * (it reads the off-diagonal norm on the host to stop).
+ *   P      [in]  finite, >= 0.
+ *   T      [in]  d x d complex (prec's storage type), row stride ldT, device.
+ *   A      [out] d x d complex (prec's storage type), row stride ldA, device.
+ *                A == T with ldA == ldT works in place.
+ *   Q      [out] d x d complex FP64 (interleaved re, im), row-major, row
+ *                stride d, device: the eigenvectors of H as columns.
+ *   lam    [out] d doubles, device: the eigenvalues of H, lam[i] belonging to
+ *                column i of Q (no particular order).
+ *   sweeps [out] host int, may be NULL: the Jacobi sweeps taken.
+ * Q and lam are what qst_abs_map_backward needs.  Q must not overlap T, A or
+ * lam.  Workspace: qst_workspace_bytes(N, prec, QST_OP_ABS_MAP) (three
+ * d x d FP64 complex buffers).  Returns QST_ERR_INVALID_ARG when H is not
+ * finite (the off-diagonal norm is not finite) or the sweeps do not
+ * converge.
+ */
+qst_status qst_abs_map(int n_qubits, qst_prec prec, double P, const void* T, int64_t ldT, void* A, int64_t ldA,
+                       void* Q, double* lam, int* sweeps, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of qst_abs_map: dL/dT from dL/dA (both the gradient convention of
+ * qst_grad_product, dL/dRe X + i dL/dIm X).  With S = (dL/dA + dL/dA^dagger)/2
+ * and Gamma_ij the divided differences (g(l_i) - g(l_j)) / (l_i - l_j) of
+ * g(l) = |l|^(P/2) (g'(l_i) where l_i = l_j, 0 at l = 0),
+ *   dL/dT = Q (Gamma o (Q^dagger S Q)) Q^dagger,
+ * the first-order change of a spectral function, composed with the
+ * Hermitian part (both self-adjoint).  Four complex products in FP64.
+ *   P, Q, lam  [in] as given to / returned by qst_abs_map.
+ *   GA     [in]  d x d complex (prec's storage type), row stride ldGA.
+ *   GT     [out] d x d complex (prec's storage type), row stride ldGT.  GT may
+ *                be GA (with ldGT == ldGA); it must not overlap Q or lam.
+ * Workspace: qst_workspace_bytes(N, prec, QST_OP_ABS_MAP).  No
+ * synchronisation.
+ */
+qst_status qst_abs_map_backward(int n_qubits, qst_prec prec, double P, const void* Q, const double* lam,
+                                const void* GA, int64_t ldGA, void* GT, int64_t ldGT, void* ws, size_t ws_bytes,
+                                void* stream);
 
 /*
  * Quantum fidelity against a target of low rank r (Sec. 2.3 Eq. F_QF):

@@ -14,13 +14,14 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
+from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MAP, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
                    QST_FIDELITY_MAX_RANK, QST_OP_FIDELITY, QST_OP_FNN, QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS,
                    QST_OP_STATE_MAP, QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER, QstError, workspace_bytes)
 
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
-    "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "fidelity_lowrank",
+    "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
+    "abs_map_backward", "AbsMapFn", "fidelity_lowrank",
     "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
@@ -99,8 +100,9 @@ def _povm_arg(povm):
 
 #: State-map modes: the pre-map applied to T before rho = T' T'^dagger / Tr.
 #: "plain" (none), "hermitian" (Chol_H: (T + T^dagger)/2, the paper's
-#: default), "lower" (Chol_Delta: lower triangle of T).
-STATE_MAPS = {"plain": 0, "hermitian": QST_PREMAP_HERMITIAN, "lower": QST_PREMAP_LOWER}
+#: default), "lower" (Chol_Delta: lower triangle of T), "abs" (the P-order
+#: absolute map, T' = Q |Lambda|^(P/2) Q^dagger of the Hermitian part).
+STATE_MAPS = {"plain": 0, "hermitian": QST_PREMAP_HERMITIAN, "lower": QST_PREMAP_LOWER, "abs": -1}
 
 
 def state_premap(X: torch.Tensor, mode: str, prec=None, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -119,6 +121,66 @@ def state_premap(X: torch.Tensor, mode: str, prec=None, out: torch.Tensor | None
     _lib.check(_lib.lib().qst_state_premap(n, p, STATE_MAPS[mode], X.data_ptr(), ld, out.data_ptr(), out.stride(0),
                                            _stream(X.device)), "qst_state_premap")
     return out
+
+
+def abs_map(T: torch.Tensor, P: float, prec=None, out: torch.Tensor | None = None):
+    """A = Q |Lambda|^(P/2) Q^dagger for the Hermitian part of T (qst_abs_map;
+    the state map of A is the P-order absolute projection).  Returns
+    (A, Q, lam, sweeps): Q d x d complex128, lam d float64, both on T's
+    device, and the Jacobi sweeps taken.  Synchronises the stream."""
+    n, ld = _matrix(T, "T")
+    p = _prec(T.dtype, prec)
+    d = 1 << n
+    if out is None:
+        out = torch.empty((d, d), dtype=T.dtype, device=T.device)
+    else:
+        n2, _ = _matrix(out, "out")
+        if n2 != n or out.dtype != T.dtype:
+            raise ValueError("out must match T in size and dtype")
+    Q = torch.empty((d, d), dtype=torch.complex128, device=T.device)
+    lam = torch.empty(d, dtype=torch.float64, device=T.device)
+    sweeps = ctypes.c_int(-1)
+    ws, nb = _workspace(n, p, QST_OP_ABS_MAP, T.device)
+    _lib.check(_lib.lib().qst_abs_map(n, p, float(P), T.data_ptr(), ld, out.data_ptr(), out.stride(0), Q.data_ptr(),
+                                      lam.data_ptr(), ctypes.byref(sweeps), _ptr(ws), nb, _stream(T.device)),
+               "qst_abs_map")
+    return out, Q, lam, sweeps.value
+
+
+def abs_map_backward(Q: torch.Tensor, lam: torch.Tensor, P: float, GA: torch.Tensor, prec=None,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dT from dL/dA through the absolute map (qst_abs_map_backward)."""
+    n, ld = _matrix(GA, "GA")
+    p = _prec(GA.dtype, prec)
+    d = 1 << n
+    if Q.shape != (d, d) or Q.dtype != torch.complex128 or not Q.is_contiguous() or Q.device != GA.device:
+        raise ValueError("Q must be the d x d complex128 matrix returned by abs_map")
+    if lam.shape != (d,) or lam.dtype != torch.float64 or not lam.is_contiguous() or lam.device != GA.device:
+        raise ValueError("lam must be the d float64 eigenvalues returned by abs_map")
+    if out is None:
+        out = torch.empty((d, d), dtype=GA.dtype, device=GA.device)
+    ws, nb = _workspace(n, p, QST_OP_ABS_MAP, GA.device)
+    _lib.check(_lib.lib().qst_abs_map_backward(n, p, float(P), Q.data_ptr(), lam.data_ptr(), GA.data_ptr(), ld,
+                                               out.data_ptr(), out.stride(0), _ptr(ws), nb, _stream(GA.device)),
+               "qst_abs_map_backward")
+    return out
+
+
+class AbsMapFn(torch.autograd.Function):
+    """T' = Q |Lambda|^(P/2) Q^dagger of the Hermitian part of T, backward by
+    qst_abs_map_backward (saves Q and the eigenvalues)."""
+
+    @staticmethod
+    def forward(ctx, T, P, prec):
+        A, Q, lam, _ = abs_map(T, P, prec)
+        ctx.P, ctx.prec = P, prec
+        ctx.save_for_backward(Q, lam)
+        return A
+
+    @staticmethod
+    def backward(ctx, g):
+        Q, lam = ctx.saved_tensors
+        return abs_map_backward(Q, lam, ctx.P, g.contiguous(), ctx.prec), None, None
 
 
 class StatePremapFn(torch.autograd.Function):
@@ -433,20 +495,23 @@ class LikelihoodFn(torch.autograd.Function):
 
 
 def likelihood(T: torch.Tensor, f: torch.Tensor, prec=None, recompute: bool | None = None, povm=None,
-               mode: str | None = None, state_map: str = "plain"):
+               mode: str | None = None, state_map: str = "plain", P: float = 2.0):
     """Differentiable negative log-likelihood (0-dim float64 tensor).
 
     mode: "fused" (default), "stored" or "recompute" (see LikelihoodFn).
     recompute=True / False select "recompute" / "stored" when mode is None.
-    state_map: "plain" (rho from T), "hermitian" (Chol_H) or "lower"
-    (Chol_Delta): rho from the pre-mapped T (see STATE_MAPS)."""
+    state_map: "plain" (rho from T), "hermitian" (Chol_H), "lower"
+    (Chol_Delta) or "abs" (the P-order absolute projection of Eq. abs_P,
+    order P): rho from the pre-mapped T (see STATE_MAPS)."""
     if mode is None:
         mode = "fused" if recompute is None else ("recompute" if recompute else "stored")
     if mode not in ("fused", "stored", "recompute"):
         raise ValueError(f"unknown mode {mode!r}")
     if state_map not in STATE_MAPS:
         raise ValueError(f"unknown state map {state_map!r}")
-    if state_map != "plain":
+    if state_map == "abs":
+        T = AbsMapFn.apply(T, P, prec)
+    elif state_map != "plain":
         T = StatePremapFn.apply(T, state_map, prec)
     return LikelihoodFn.apply(T, f, prec, mode, povm)
 

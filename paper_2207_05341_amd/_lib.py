@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqst.so")
 QST_OK, QST_ERR_INVALID_ARG, QST_ERR_UNSUPPORTED, QST_ERR_WORKSPACE, QST_ERR_HIP = range(5)
 QST_F64, QST_F32, QST_BF16GEMM = 0, 1, 2
 QST_OP_STATE_MAP, QST_OP_POVM_PROBS, QST_OP_NLL, QST_OP_NLL_BACKWARD = 0, 1, 2, 3
-QST_OP_LIKELIHOOD, QST_OP_GRAD_PRODUCT, QST_OP_FIDELITY, QST_OP_FNN = 4, 5, 6, 7
+QST_OP_LIKELIHOOD, QST_OP_GRAD_PRODUCT, QST_OP_FIDELITY, QST_OP_FNN, QST_OP_ABS_MAP = 4, 5, 6, 7, 8
 QST_FIDELITY_MAX_RANK = 32
 QST_MAX_QUBITS = 13
 QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER = 1, 2
@@ -28,6 +28,8 @@ SIGNATURES = {
     "qst_likelihood": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_grad_product": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_state_premap": (_int, [_int, _int, _int, _vp, _i64, _vp, _i64, _vp]),
+    "qst_abs_map": (_int, [_int, _int, ctypes.c_double, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qst_abs_map_backward": (_int, [_int, _int, ctypes.c_double, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "qst_fnn_forward": (_int, [_int, _int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_fnn_backward": (_int, [_int, _int, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qst_rprop_step": (_int, [_i64, _int, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,

@@ -1,0 +1,403 @@
+// The P-order absolute map of Sec. 3.2 (Eq. abs_P) and its adjoint.
+//
+// Forward: H = (T + T^dagger) / 2 in FP64, H = Q Lambda Q^dagger by a
+// cyclic two-sided Jacobi method, and A = Q |Lambda|^(P/2) Q^dagger =
+// U U^dagger with U = Q |Lambda|^(P/4) (one complex product on MFMA).  The
+// likelihood path's state map of A, A A^dagger / Tr(A A^dagger) =
+// Q |Lambda|^P Q^dagger / Tr |Lambda|^P, is then the P-order absolute
+// projection.
+//
+// Jacobi: the d indices are paired by the round-robin (circle) schedule, in
+// which round t of d - 1 pairs every index once: pair 0 is (0, 1 + t) and
+// pair k > 0 is (1 + (k + t) mod (d-1), 1 + (d-1-k+t) mod (d-1)).  All d/2
+// rotations of a round are computed from the matrix before the round and
+// applied together, A <- J^dagger A J with J block diagonal over the pairs:
+// the workgroup of pair (p, q) rewrites rows p and q, each 2 x 2 block of
+// them (columns (r, s) of another pair) as J_pq^dagger B J_rs, reading from
+// one buffer and writing the other.  The rows of V^T (V the product of the
+// rotations, Q at the end) are rotated in place.  The rotation of a pair
+// zeroes its off-diagonal entry exactly: with c = |c| e^(i phi) the phase
+// diag(1, e^(-i phi)) makes the 2 x 2 block real symmetric and the classical
+// rotation angle (tangent t of the smaller root of t^2 + 2 zeta t - 1 = 0,
+// zeta = (b - a) / (2 |c|)) diagonalises it.  After each sweep (d - 1
+// rounds) the host reads the off-diagonal norm; sweeps stop when it is
+// below 1e-14 of ||H||_F, or below 1e-10 of it and no longer falling by
+// half (the rounding floor), which Jacobi's quadratic convergence reaches
+// in a few sweeps.
+//
+// Adjoint: for a spectral function A = g(H), g(l) = |l|^(P/2), the
+// first-order change is Q (Gamma o (Q^dagger dH Q)) Q^dagger with Gamma the
+// divided differences of g on the eigenvalues (g' on ties); both it and
+// the Hermitian part are self-adjoint, so dL/dT = Q (Gamma o (Q^dagger S Q))
+// Q^dagger with S = (dL/dA + dL/dA^dagger) / 2: four complex products.
+//
+// Everything runs in FP64 whatever the storage precision of T, A and the
+// gradients: the eigensolver's rounding enters A through g, whose slope is
+// unbounded near 0 for P < 2.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "qst_device.h"
+#include "qst_kernels.h"
+
+namespace qst {
+
+namespace {
+
+using C64 = Cx<double>;
+
+constexpr int kTB = 32;          // tile side of the transposes
+constexpr int kMaxSweeps = 40;   // Jacobi sweeps before giving up (non-finite input)
+
+__device__ __forceinline__ C64 cmul(C64 a, C64 b) { return C64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ C64 cscale(C64 a, double s) { return C64{a.re * s, a.im * s}; }
+__device__ __forceinline__ C64 csub(C64 a, C64 b) { return C64{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ C64 cadd(C64 a, C64 b) { return C64{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ double cnorm(C64 a) { return a.re * a.re + a.im * a.im; }
+
+// J = [[cs, sn], [-sn ph, cs ph]], ph = e^(-i phi); shift = t |c| (the
+// diagonal becomes a - shift, b + shift).
+struct Rot {
+  double cs, sn;
+  C64 ph;
+  double shift;
+};
+
+__device__ __forceinline__ Rot make_rot(double a, double b, C64 c) {
+  Rot r{1.0, 0.0, C64{1.0, 0.0}, 0.0};
+  const double ac = hypot(c.re, c.im);
+  if (ac == 0.0) return r;
+  const double z = (b - a) / (2.0 * ac);
+  const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+  r.cs = 1.0 / sqrt(1.0 + t * t);
+  r.sn = r.cs * t;
+  r.ph = C64{c.re / ac, -c.im / ac};
+  r.shift = t * ac;
+  return r;
+}
+
+__device__ __forceinline__ void pair_at(int k, int t, int m, int& p, int& q) {
+  if (k == 0) {
+    p = 0;
+    q = 1 + t;
+  } else {
+    p = 1 + (k + t) % m;
+    q = 1 + (m - k + t) % m;
+  }
+}
+
+__device__ __forceinline__ Rot rot_of(const C64* A, int d, int p, int q) {
+  return make_rot(A[int64_t(p) * d + p].re, A[int64_t(q) * d + q].re, A[int64_t(p) * d + q]);
+}
+
+// One round t: workgroup k rewrites rows p, q of pair k (Ain -> Aout) and
+// rotates rows p, q of Vt; part[2k], part[2k+1] receive the squared
+// off-diagonal and diagonal entries of the new rows.
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const C64* __restrict__ Ain, C64* __restrict__ Aout,
+                                                           C64* __restrict__ Vt, int d, int t,
+                                                           double* __restrict__ part) {
+  __shared__ double lds4[4];
+  const int m = d - 1, half = d >> 1;
+  const int k = blockIdx.x;
+  int p, q;
+  pair_at(k, t, m, p, q);
+  const Rot J = rot_of(Ain, d, p, q);
+  const C64 phc{J.ph.re, -J.ph.im};
+  const C64* rp = Ain + int64_t(p) * d;
+  const C64* rq = Ain + int64_t(q) * d;
+  C64* wp = Aout + int64_t(p) * d;
+  C64* wq = Aout + int64_t(q) * d;
+  double off = 0.0, dia = 0.0;
+  for (int R = threadIdx.x; R < half; R += 256) {
+    int r, s;
+    pair_at(R, t, m, r, s);
+    if (R == k) {
+      const double a = rp[p].re - J.shift, b = rq[q].re + J.shift;
+      wp[p] = C64{a, 0.0};
+      wq[q] = C64{b, 0.0};
+      wp[q] = C64{0.0, 0.0};
+      wq[p] = C64{0.0, 0.0};
+      dia += a * a + b * b;
+      continue;
+    }
+    const Rot K = rot_of(Ain, d, r, s);
+    const C64 xpr = rp[r], xps = rp[s], xqr = rq[r], xqs = rq[s];
+    // right: [u, v] J_rs = [u cs - v sn ph, u sn + v cs ph]
+    const C64 vp = cmul(xps, K.ph), vq = cmul(xqs, K.ph);
+    const C64 ypr = csub(cscale(xpr, K.cs), cscale(vp, K.sn)), yps = cadd(cscale(xpr, K.sn), cscale(vp, K.cs));
+    const C64 yqr = csub(cscale(xqr, K.cs), cscale(vq, K.sn)), yqs = cadd(cscale(xqr, K.sn), cscale(vq, K.cs));
+    // left: J_pq^dagger = [[cs, -sn conj(ph)], [sn, cs conj(ph)]]
+    const C64 ur = cmul(phc, yqr), us = cmul(phc, yqs);
+    const C64 zpr = csub(cscale(ypr, J.cs), cscale(ur, J.sn)), zqr = cadd(cscale(ypr, J.sn), cscale(ur, J.cs));
+    const C64 zps = csub(cscale(yps, J.cs), cscale(us, J.sn)), zqs = cadd(cscale(yps, J.sn), cscale(us, J.cs));
+    wp[r] = zpr;
+    wp[s] = zps;
+    wq[r] = zqr;
+    wq[s] = zqs;
+    off += cnorm(zpr) + cnorm(zps) + cnorm(zqr) + cnorm(zqs);
+  }
+  C64* vpr = Vt + int64_t(p) * d;
+  C64* vqr = Vt + int64_t(q) * d;
+  for (int c = threadIdx.x; c < d; c += 256) {
+    const C64 u = vpr[c], v = cmul(vqr[c], J.ph);
+    vpr[c] = csub(cscale(u, J.cs), cscale(v, J.sn));
+    vqr[c] = cadd(cscale(u, J.sn), cscale(v, J.cs));
+  }
+  off = block_sum256(off, lds4);
+  dia = block_sum256(dia, lds4);
+  if (threadIdx.x == 0) {
+    part[2 * k] = off;
+    part[2 * k + 1] = dia;
+  }
+}
+
+// out[0] = sum of part[2k] (off-diagonal), out[1] = sum of part[2k+1], in a
+// fixed order.
+__global__ __launch_bounds__(256) void jacobi_norms_kernel(const double* __restrict__ part, int half,
+                                                           double* __restrict__ out) {
+  __shared__ double lds4[4];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < half; k += 256) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  a = block_sum256(a, lds4);
+  b = block_sum256(b, lds4);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+__global__ __launch_bounds__(256) void identity_kernel(C64* __restrict__ X, int n) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= (int64_t(1) << (2 * n))) return;
+  const int64_t r = e >> n, c = e & ((int64_t(1) << n) - 1);
+  X[e] = C64{r == c ? 1.0 : 0.0, 0.0};
+}
+
+__global__ void set_scalar_kernel(double* x, double v) { *x = v; }
+
+// lam[i] = A[i][i] (real), sc[i] = |lam[i]|^(P/4).
+__global__ __launch_bounds__(256) void spectrum_kernel(const C64* __restrict__ A, int d, double P,
+                                                       double* __restrict__ lam, double* __restrict__ sc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= d) return;
+  const double l = A[int64_t(i) * d + i].re;
+  lam[i] = l;
+  sc[i] = pow(fabs(l), 0.25 * P);
+}
+
+// Y[i][j] = op(X[j][i]) * (scale ? scale[j] : 1), op = conj or identity;
+// tiles B x B (B = min(d, 32)) staged through LDS.
+__global__ __launch_bounds__(256) void transpose64_kernel(const C64* __restrict__ X, int64_t ldx,
+                                                          C64* __restrict__ Y, int64_t ldy, int lgB, int conj,
+                                                          const double* __restrict__ scale) {
+  __shared__ C64 a[kTB][kTB + 1];
+  const int B = 1 << lgB;
+  const int I = blockIdx.x, Jt = blockIdx.y;  // Y tile (I, Jt) from X tile (Jt, I)
+  const int64_t xr0 = int64_t(Jt) << lgB, xc0 = int64_t(I) << lgB;
+  const int elems = B * B;
+  for (int e = threadIdx.x; e < elems; e += 256) {
+    const int r = e >> lgB, c = e & (B - 1);
+    a[r][c] = X[(xr0 + r) * ldx + xc0 + c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < elems; e += 256) {
+    const int r = e >> lgB, c = e & (B - 1);
+    C64 v = a[c][r];  // X[xr0 + c][xc0 + r] = X[j][i] for i = xc0 + r, j = xr0 + c
+    if (conj) v.im = -v.im;
+    if (scale) v = cscale(v, scale[xr0 + c]);
+    Y[(xc0 + r) * ldy + xr0 + c] = v;
+  }
+}
+
+// Y[j][i] = conj(X[j][i]) * scale[j] (elementwise, d x d contiguous).
+__global__ __launch_bounds__(256) void conj_rows_kernel(const C64* __restrict__ X, C64* __restrict__ Y, int n,
+                                                        const double* __restrict__ scale) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= (int64_t(1) << (2 * n))) return;
+  const double s = scale[e >> n];
+  const C64 v = X[e];
+  Y[e] = C64{v.re * s, -v.im * s};
+}
+
+// S = (X + X^dagger) / 2 in FP64 (d x d contiguous) from X in storage type
+// R, over the tile pairs (I, J), I >= J, of B x B tiles.
+template <typename R>
+__global__ __launch_bounds__(256) void herm_to64_kernel(const Cx<R>* __restrict__ X, int64_t ldx, int lgB,
+                                                        C64* __restrict__ S, int64_t lds) {
+  __shared__ C64 a[kTB][kTB + 1], b[kTB][kTB + 1];
+  const int B = 1 << lgB;
+  int I, J;
+  tri_decode(blockIdx.x, I, J);
+  const int64_t r0 = int64_t(I) << lgB, c0 = int64_t(J) << lgB;
+  const int elems = B * B;
+  for (int e = threadIdx.x; e < elems; e += 256) {
+    const int r = e >> lgB, c = e & (B - 1);
+    const Cx<R> x = X[(r0 + r) * ldx + c0 + c], y = X[(c0 + r) * ldx + r0 + c];
+    a[r][c] = C64{double(x.re), double(x.im)};
+    b[r][c] = C64{double(y.re), double(y.im)};
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < elems; e += 256) {
+    const int r = e >> lgB, c = e & (B - 1);
+    const C64 x = a[r][c], y = b[c][r];
+    S[(r0 + r) * lds + c0 + c] = C64{0.5 * (x.re + y.re), 0.5 * (x.im - y.im)};
+    if (I != J) {
+      const C64 u = b[r][c], v = a[c][r];
+      S[(c0 + r) * lds + r0 + c] = C64{0.5 * (u.re + v.re), 0.5 * (u.im - v.im)};
+    }
+  }
+}
+
+// Divided difference of g(l) = |l|^a at (x, y): g' on ties (0 at l = 0); for
+// x, y of one sign, |x|^a - |y|^a = |y|^a expm1(a log1p((|x| - |y|) / |y|)),
+// free of cancellation when x and y are close.
+__device__ __forceinline__ double divided_difference(double x, double y, double a) {
+  if (x == y) return x == 0.0 ? 0.0 : (x > 0.0 ? a : -a) * pow(fabs(x), a - 1.0);
+  if ((x > 0.0 && y > 0.0) || (x < 0.0 && y < 0.0)) {
+    const double ax = fabs(x), ay = fabs(y), dd = ax - ay;
+    const double v = pow(ay, a) * expm1(a * log1p(dd / ay)) / dd;
+    return x > 0.0 ? v : -v;
+  }
+  return (pow(fabs(x), a) - pow(fabs(y), a)) / (x - y);
+}
+
+__global__ __launch_bounds__(256) void divided_diff_kernel(C64* __restrict__ M, const double* __restrict__ lam,
+                                                           int n, double a) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= (int64_t(1) << (2 * n))) return;
+  const double g = divided_difference(lam[e >> n], lam[e & ((int64_t(1) << n) - 1)], a);
+  M[e] = cscale(M[e], g);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void from64_kernel(const C64* __restrict__ X, int n, Cx<R>* __restrict__ Y,
+                                                     int64_t ldy) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= (int64_t(1) << (2 * n))) return;
+  const int64_t r = e >> n, c = e & ((int64_t(1) << n) - 1);
+  Y[r * ldy + c] = Cx<R>{R(X[e].re), R(X[e].im)};
+}
+
+struct Bufs {
+  C64 *b0, *b1, *b2;
+  double *part, *scal;
+  void* sk;
+};
+
+Bufs carve(int n, void* ws) {
+  const AbsMapLayout L = absmap_layout(n);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  return Bufs{reinterpret_cast<C64*>(w + L.b0), reinterpret_cast<C64*>(w + L.b1), reinterpret_cast<C64*>(w + L.b2),
+              reinterpret_cast<double*>(w + L.part), reinterpret_cast<double*>(w + L.scal),
+              L.sk_bytes ? static_cast<void*>(w + L.sk) : nullptr};
+}
+
+unsigned elem_blocks(int n) { return unsigned(((int64_t(1) << (2 * n)) + 255) / 256); }
+
+hipError_t herm_to64(qst_prec prec, const void* X, int64_t ldx, C64* S, int n, hipStream_t s) {
+  const int lgB = n < 5 ? n : 5;
+  const int64_t m = int64_t(1) << (n - lgB);
+  const unsigned blocks = unsigned(m * (m + 1) / 2);
+  const int64_t d = int64_t(1) << n;
+  if (prec == QST_F64)
+    herm_to64_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const Cx<double>*>(X), ldx, lgB, S, d);
+  else
+    herm_to64_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const Cx<float>*>(X), ldx, lgB, S, d);
+  return hipGetLastError();
+}
+
+hipError_t transpose64(const C64* X, int64_t ldx, C64* Y, int64_t ldy, int n, bool conj, const double* scale,
+                       hipStream_t s) {
+  const int lgB = n < 5 ? n : 5;
+  const unsigned m = 1u << (n - lgB);
+  transpose64_kernel<<<dim3(m, m), 256, 0, s>>>(X, ldx, Y, ldy, lgB, conj ? 1 : 0, scale);
+  return hipGetLastError();
+}
+
+// C = X Y (d x d, FP64, contiguous operands) on the library's complex
+// product: its scale 2 up / tau is 1 with tau = 2 (scal[0]) and no up.
+hipError_t product64(const C64* X, const C64* Y, void* C, int64_t ldc, int n, const Bufs& b, hipStream_t s) {
+  const int64_t d = int64_t(1) << n;
+  return launch_hemm(QST_F64, X, d, Y, d, C, ldc, n, b.scal, nullptr, b.sk, s, nullptr);
+}
+
+hipError_t store_out(qst_prec prec, const C64* X, void* Y, int64_t ldy, int n, hipStream_t s) {
+  if (prec == QST_F64) return hipSuccess;
+  from64_kernel<float><<<elem_blocks(n), 256, 0, s>>>(X, n, static_cast<Cx<float>*>(Y), ldy);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, void* A, int64_t ldA,
+                          void* Q, double* lam, void* ws, hipStream_t s, int* sweeps) {
+  *sweeps = -1;
+  const int d = 1 << n, half = d >> 1;
+  const Bufs b = carve(n, ws);
+  hipError_t e;
+  ProfScope prof("abs_map", s);
+  if ((e = herm_to64(prec, T, ldT, b.b0, n, s)) != hipSuccess) return e;
+  identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
+  set_scalar_kernel<<<1, 1, 0, s>>>(b.scal, 2.0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  C64 *cur = b.b0, *nxt = b.b1;
+  double prev = HUGE_VAL, host[2];
+  for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
+    for (int t = 0; t < d - 1; ++t) {
+      jacobi_round_kernel<<<half, 256, 0, s>>>(cur, nxt, b.b2, d, t, b.part);
+      C64* x = cur;
+      cur = nxt;
+      nxt = x;
+    }
+    jacobi_norms_kernel<<<1, 256, 0, s>>>(b.part, half, b.scal + 2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(host, b.scal + 2, sizeof(host), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const double off = host[0], tot = host[0] + host[1];
+    if (!std::isfinite(off) || !std::isfinite(tot)) return hipSuccess;  // sweeps stays -1
+    const double r = tot > 0.0 ? std::sqrt(off / tot) : 0.0;
+    if (r <= 1e-14 || (r <= 1e-10 && r > 0.5 * prev)) {
+      *sweeps = sweep;
+      break;
+    }
+    prev = r;
+  }
+  if (*sweeps < 0) return hipSuccess;
+  // cur holds Lambda on its diagonal, b.b2 = V^T; the other buffer is free.
+  double* sc = b.part;  // |lam|^(P/4), d values
+  spectrum_kernel<<<(d + 255) / 256, 256, 0, s>>>(cur, d, P, lam, sc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = transpose64(b.b2, d, static_cast<C64*>(Q), d, n, false, nullptr, s)) != hipSuccess) return e;
+  if ((e = transpose64(b.b2, d, nxt, d, n, false, sc, s)) != hipSuccess) return e;  // U = Q diag(sc)
+  conj_rows_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, cur, n, sc);                 // U^dagger
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  C64* out64 = prec == QST_F64 ? static_cast<C64*>(A) : b.b2;
+  if ((e = product64(nxt, cur, out64, prec == QST_F64 ? ldA : d, n, b, s)) != hipSuccess) return e;
+  return store_out(prec, out64, A, ldA, n, s);
+}
+
+hipError_t launch_abs_map_backward(qst_prec prec, int n, double P, const void* Q, const double* lam, const void* GA,
+                                   int64_t ldGA, void* GT, int64_t ldGT, void* ws, hipStream_t s) {
+  const int d = 1 << n;
+  const Bufs b = carve(n, ws);
+  const C64* q = static_cast<const C64*>(Q);
+  hipError_t e;
+  ProfScope prof("abs_map_backward", s);
+  set_scalar_kernel<<<1, 1, 0, s>>>(b.scal, 2.0);
+  if ((e = herm_to64(prec, GA, ldGA, b.b0, n, s)) != hipSuccess) return e;       // S
+  if ((e = transpose64(q, d, b.b1, d, n, true, nullptr, s)) != hipSuccess) return e;  // Q^dagger
+  if ((e = product64(b.b0, q, b.b2, d, n, b, s)) != hipSuccess) return e;        // S Q
+  if ((e = product64(b.b1, b.b2, b.b0, d, n, b, s)) != hipSuccess) return e;     // M = Q^dagger S Q
+  divided_diff_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b0, lam, n, 0.5 * P);     // Gamma o M
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = product64(q, b.b0, b.b2, d, n, b, s)) != hipSuccess) return e;        // Q (Gamma o M)
+  C64* out64 = prec == QST_F64 ? static_cast<C64*>(GT) : b.b0;
+  if ((e = product64(b.b2, b.b1, out64, prec == QST_F64 ? ldGT : d, n, b, s)) != hipSuccess) return e;
+  return store_out(prec, out64, GT, ldGT, n, s);
+}
+
+}  // namespace qst

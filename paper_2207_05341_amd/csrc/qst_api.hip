@@ -77,6 +77,50 @@ qst_status qst_state_premap(int n, qst_prec prec, int mode, const void* X, int64
   return QST_OK;
 }
 
+qst_status qst_abs_map(int n, qst_prec prec, double P, const void* T, int64_t ldT, void* A, int64_t ldA, void* Q,
+                       double* lam, int* sweeps, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(A, ldA, n, "A", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(Q, "Q", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(lam, "lam", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_abs_order(P, msg)) != QST_OK) return fail(st, msg);
+  if (A == T && ldA != ldT) return fail(QST_ERR_INVALID_ARG, "in place (A == T) needs ldA == ldT");
+  if (Q == T || Q == A || Q == static_cast<void*>(lam)) return fail(QST_ERR_INVALID_ARG, "Q must not alias T, A or lam");
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_ABS_MAP, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  int taken = -1;
+  hipError_t e = launch_abs_map(prec, n, P, T, ldT, A, ldA, Q, lam, ws, static_cast<hipStream_t>(stream), &taken);
+  if (e != hipSuccess) return hip_fail(e, "absolute map");
+  if (sweeps) *sweeps = taken;
+  if (taken < 0)
+    return fail(QST_ERR_INVALID_ARG, "absolute map: the Jacobi sweeps did not converge (is T finite?)");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_abs_map_backward(int n, qst_prec prec, double P, const void* Q, const double* lam, const void* GA,
+                                int64_t ldGA, void* GT, int64_t ldGT, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(Q, "Q", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(lam, "lam", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(GA, ldGA, n, "GA", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(GT, ldGT, n, "GT", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_abs_order(P, msg)) != QST_OK) return fail(st, msg);
+  if (GT == GA && ldGT != ldGA) return fail(QST_ERR_INVALID_ARG, "in place (GT == GA) needs ldGT == ldGA");
+  if (GT == Q || GT == static_cast<const void*>(lam)) return fail(QST_ERR_INVALID_ARG, "GT must not alias Q or lam");
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_ABS_MAP, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  hipError_t e = launch_abs_map_backward(prec, n, P, Q, lam, GA, ldGA, GT, ldGT, ws, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "absolute map adjoint");
+  clear_error();
+  return QST_OK;
+}
+
 qst_status qst_fnn_forward(int n, qst_prec prec, const void* W1, const void* b1, const void* W2, const void* b2,
                            const void* x, void* h_pre, void* T, int64_t ldT, void* ws, size_t ws_bytes,
                            void* stream) {

@@ -47,6 +47,15 @@ hipError_t launch_fidelity_lowrank(qst_prec prec, const void* T, int64_t ldT, co
 hipError_t launch_fidelity_classical(qst_prec prec, const void* ph, const void* p, int n, void* ws, double* F,
                                      hipStream_t s);
 
+// P-order absolute map and its adjoint (workspace laid out by
+// absmap_layout).  launch_abs_map synchronises s once per Jacobi sweep and
+// sets *sweeps to the sweeps taken, or -1 when the off-diagonal norm is not
+// finite or does not converge.
+hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, void* A, int64_t ldA,
+                          void* Q, double* lam, void* ws, hipStream_t s, int* sweeps);
+hipError_t launch_abs_map_backward(qst_prec prec, int n, double P, const void* Q, const double* lam, const void* GA,
+                                   int64_t ldGA, void* GT, int64_t ldGT, void* ws, hipStream_t s);
+
 // State-map pre-map (qst_premap mode) of a d x d complex matrix; Y may be X.
 hipError_t launch_premap(qst_prec prec, int mode, const void* X, int64_t ldx, void* Y, int64_t ldy, int n,
                          hipStream_t s);

@@ -107,6 +107,28 @@ FnnLayout fnn_layout(int n, size_t real_bytes) {
   return f;
 }
 
+AbsMapLayout absmap_layout(int n) {
+  AbsMapLayout a;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t d = size_t(1) << n;
+  a.b0 = take(d * d * 16);
+  a.b1 = take(d * d * 16);
+  a.b2 = take(d * d * 16);
+  a.part = take(d * sizeof(double));
+  a.scal = take(8 * sizeof(double));
+  if (n >= kStreamKMinQubits) {
+    a.sk_bytes = stream_k_partial_bytes(QST_F64);
+    a.sk = take(a.sk_bytes);
+  }
+  a.total = off;
+  return a;
+}
+
 WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
   WsLayout w;
   const size_t cb = complex_bytes(prec), rb = real_bytes(prec);
@@ -189,6 +211,9 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
     case QST_OP_FNN:
       off = fnn_layout(n, rb).total;
       break;
+    case QST_OP_ABS_MAP:
+      off = absmap_layout(n).total;
+      break;
     default:
       return WsLayout{};
   }
@@ -268,6 +293,14 @@ qst_status check_povm(const double* M, std::string& msg) {
   return QST_OK;
 }
 
+qst_status check_abs_order(double P, std::string& msg) {
+  if (!std::isfinite(P) || P < 0.0) {
+    msg = "absolute-map order P=" + std::to_string(P) + " is not a finite number >= 0";
+    return QST_ERR_INVALID_ARG;
+  }
+  return QST_OK;
+}
+
 qst_status check_premap(int mode, const void* X, int64_t ldX, const void* Y, int64_t ldY, std::string& msg) {
   if (mode != QST_PREMAP_HERMITIAN && mode != QST_PREMAP_LOWER) {
     msg = "unknown pre-map mode " + std::to_string(mode);
@@ -318,7 +351,7 @@ extern "C" {
 size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op) {
   std::string msg;
   if (qst::check_common(n_qubits, prec, msg) != QST_OK) return 0;
-  if (op < QST_OP_STATE_MAP || op > QST_OP_FNN) return 0;
+  if (op < QST_OP_STATE_MAP || op > QST_OP_ABS_MAP) return 0;
   return qst::workspace_layout(n_qubits, prec, op, /*recompute=*/true).total;
 }
 

@@ -48,6 +48,16 @@ bool fast_pass_available(const PovmPlan& pl, int j, qst_prec prec);
 // specialised.
 bool fused_likelihood(const PovmPlan& pl, qst_prec prec);
 
+// Absolute-map workspace (qst_abs_map, qst_abs_map_backward): three d x d
+// complex FP64 buffers, d FP64 values (Jacobi norm partials, then
+// |lambda|^(P/4)), a few FP64 scalars and the FP64 stream-K partial tiles of
+// the complex products (N >= kStreamKMinQubits).
+struct AbsMapLayout {
+  size_t b0 = 0, b1 = 0, b2 = 0, part = 0, scal = 0, sk = 0, sk_bytes = 0, total = 0;
+};
+AbsMapLayout absmap_layout(int n);
+qst_status check_abs_order(double P, std::string& msg);  // P finite and >= 0
+
 // Workspace layout (byte offsets) for each op; see the .cpp for the rules.
 struct WsLayout {
   size_t total = 0;

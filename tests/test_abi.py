@@ -76,7 +76,11 @@ def test_workspace_sizes(L):
             # BF16 state map from N = 8: bf16 planes of T (4 d^2 bytes)
             if prec == 2 and n >= 8:
                 assert ws(n, prec, lib_mod.QST_OP_STATE_MAP) >= 4 * 4 ** n
-    assert ws(5, 0, 8) == 0
+    assert ws(5, 0, 9) == 0
+    # absolute map: three d x d complex FP64 buffers, any storage precision
+    for n in (1, 6, 12):
+        for prec in (0, 1, 2):
+            assert ws(n, prec, lib_mod.QST_OP_ABS_MAP) >= 3 * 16 * 4 ** n
     # fidelity: the W^dagger T partials of 16 row blocks at the largest rank
     for n in (2, 6, 11):
         d = 1 << n
@@ -239,6 +243,41 @@ def test_premap_validation(L):
     assert call(ldX=15) == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
     assert call(ldY=8) == lib_mod.QST_ERR_INVALID_ARG
     assert call(Y=FAKE, ldY=32) == lib_mod.QST_ERR_INVALID_ARG and "in place" in _err(L)
+
+
+def test_abs_map_validation(L):
+    n, d = 4, 16
+    ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_ABS_MAP)
+    W = ctypes.c_void_p(0x30000)
+    Q, lam = ctypes.c_void_p(0x40000), ctypes.c_void_p(0x50000)
+
+    def fwd(n=n, prec=0, P=1.5, T=FAKE, ldT=d, A=FAKE2, ldA=d, Qp=Q, lp=lam, nb=ws):
+        return L.qst_abs_map(n, prec, P, T, ldT, A, ldA, Qp, lp, None, W, nb, None)
+
+    assert fwd(n=0) == lib_mod.QST_ERR_INVALID_ARG and "n_qubits" in _err(L)
+    assert fwd(prec=9) == lib_mod.QST_ERR_INVALID_ARG and "precision" in _err(L)
+    assert fwd(T=None) == lib_mod.QST_ERR_INVALID_ARG and "T is NULL" in _err(L)
+    assert fwd(A=None) == lib_mod.QST_ERR_INVALID_ARG and "A is NULL" in _err(L)
+    assert fwd(ldA=d - 1) == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
+    assert fwd(Qp=None) == lib_mod.QST_ERR_INVALID_ARG and "Q is NULL" in _err(L)
+    assert fwd(lp=None) == lib_mod.QST_ERR_INVALID_ARG and "lam is NULL" in _err(L)
+    for bad in (-0.5, float("nan"), float("inf")):
+        assert fwd(P=bad) == lib_mod.QST_ERR_INVALID_ARG and "order P" in _err(L)
+    assert fwd(A=FAKE, ldA=d + 1) == lib_mod.QST_ERR_INVALID_ARG and "in place" in _err(L)
+    assert fwd(Qp=FAKE2) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
+    assert fwd(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
+
+    def bwd(P=1.5, Qp=Q, lp=lam, GA=FAKE, ldGA=d, GT=FAKE2, ldGT=d, nb=ws):
+        return L.qst_abs_map_backward(n, 0, P, Qp, lp, GA, ldGA, GT, ldGT, W, nb, None)
+
+    assert bwd(Qp=None) == lib_mod.QST_ERR_INVALID_ARG and "Q is NULL" in _err(L)
+    assert bwd(lp=None) == lib_mod.QST_ERR_INVALID_ARG and "lam is NULL" in _err(L)
+    assert bwd(GA=None) == lib_mod.QST_ERR_INVALID_ARG and "GA is NULL" in _err(L)
+    assert bwd(ldGT=3) == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
+    assert bwd(P=-1.0) == lib_mod.QST_ERR_INVALID_ARG and "order P" in _err(L)
+    assert bwd(GT=FAKE, ldGT=d + 2) == lib_mod.QST_ERR_INVALID_ARG and "in place" in _err(L)
+    assert bwd(GT=Q) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
+    assert bwd(nb=0) == lib_mod.QST_ERR_WORKSPACE
 
 
 def test_fidelity_validation(L):

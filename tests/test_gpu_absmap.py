@@ -1,0 +1,188 @@
+"""The P-order absolute map of Sec. 3.2 (Eq. abs_P) through the C ABI
+(qst_abs_map, qst_abs_map_backward) and through autograd, against the
+oracle's abs_map / abs_map_backward / grad_T_abs (pinned by closed forms at
+P = 0 and P = 4, scipy's fractional matrix powers and central differences).
+
+* A = Q |Lambda|^(P/2) Q^dagger of the Hermitian part at N = 1 .. 8 and 10
+  for P in {0.5, 1, 1.5, 2, 3, 4} (the paper's orders), both precisions,
+  padded leading dimensions; the eigenpairs: Q unitary, Q Lambda Q^dagger =
+  H, the spectrum against numpy's; bitwise repeats;
+* dL/dT from a random dL/dA against the oracle's adjoint (independent of
+  the eigenvector phases and order, which differ between the two);
+* closed forms: P = 0 gives I, P = 4 gives H H; P = 2 through the whole
+  likelihood equals the library's Chol_H mode; a diagonal T takes one sweep
+  and returns its diagonal;
+* the whole chain T -> A -> likelihood differentiated by autograd against
+  the oracle's grad_T_abs.
+
+Tolerances: FP64 1e-12, FP32 1e-5 (relative Frobenius; the eigensolver and
+the products run in FP64 on both paths, FP32 only rounds the storage).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+from workloads import rel_fro
+
+torch = pytest.importorskip("torch")
+qst = pytest.importorskip("paper_2207_05341_amd")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-12, "f32": 1e-5}
+ORDERS = (0.5, 1.0, 1.5, 2.0, 3.0, 4.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def ctype(prec):
+    return np.complex128 if prec == "f64" else np.complex64
+
+
+def dev_matrix(X, pad=0):
+    rows, cols = X.shape
+    tdt = torch.complex128 if X.dtype == np.complex128 else torch.complex64
+    buf = torch.zeros((rows, cols + pad), dtype=tdt, device=DEV)
+    buf[:, :cols] = torch.from_numpy(X)
+    return buf[:, :cols]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 8])
+def test_abs_map_against_oracle(prec, n):
+    d = 1 << n
+    g = S.rng(8100 + n)
+    T = S.ginibre(g, d).astype(ctype(prec))
+    T64 = T.astype(np.complex128)
+    H = O.hermitian_part(T64)
+    Tg = dev_matrix(T, pad=3 if n % 2 else 0)
+    lam_w = np.linalg.eigvalsh(H)
+    for P in ORDERS:
+        t0 = time.perf_counter()
+        A, Q, lam, sweeps = qst.abs_map(Tg, P, prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        A_w = O.abs_map(T64, P)[0]
+        An, Qn, ln = A.cpu().numpy(), Q.cpu().numpy(), lam.cpu().numpy()
+        e = rel_fro(An, A_w)
+        say(f"N={n} {prec} P={P}: sweeps {sweeps}, {1e3 * dt:.1f} ms, A rel err {e:.2e}")
+        assert e <= TOL[prec], (P, e)
+        assert np.abs(Qn.conj().T @ Qn - np.eye(d)).max() <= 1e-13 * d
+        assert rel_fro((Qn * ln) @ Qn.conj().T, H) <= 1e-13
+        assert np.abs(np.sort(ln) - lam_w).max() <= 1e-13 * np.abs(lam_w).max()
+    A2 = qst.abs_map(Tg, 1.5, prec)[0]
+    A3 = qst.abs_map(Tg, 1.5, prec)[0]
+    assert torch.equal(A2, A3)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 3, 6, 8])
+def test_abs_map_backward_against_oracle(prec, n):
+    d = 1 << n
+    g = S.rng(8200 + n)
+    T = S.ginibre(g, d).astype(ctype(prec))
+    GA = S.ginibre(g, d).astype(ctype(prec))
+    T64, GA64 = T.astype(np.complex128), GA.astype(np.complex128)
+    _, Qw, lw = O.abs_map(T64, 1.0)
+    Tg, GAg = dev_matrix(T), dev_matrix(GA, pad=5)
+    for P in ORDERS:
+        _, Q, lam, _ = qst.abs_map(Tg, P, prec)
+        GT = qst.abs_map_backward(Q, lam, P, GAg, prec)
+        GT2 = qst.abs_map_backward(Q, lam, P, GAg, prec)
+        torch.cuda.synchronize()
+        want = O.abs_map_backward(Qw, lw, P, GA64)
+        e = rel_fro(GT.cpu().numpy(), want)
+        say(f"N={n} {prec} P={P}: dL/dT rel err {e:.2e}")
+        assert e <= TOL[prec], (P, e)
+        assert torch.equal(GT, GT2)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_abs_map_closed_forms(prec):
+    """P = 0: A = I; P = 4: A = H H; a diagonal T: one sweep, lam = its
+    real diagonal."""
+    g = S.rng(8300)
+    n, d = 7, 128
+    T = S.ginibre(g, d).astype(ctype(prec))
+    H = O.hermitian_part(T.astype(np.complex128))
+    Tg = dev_matrix(T)
+    A0 = qst.abs_map(Tg, 0.0, prec)[0].cpu().numpy()
+    assert np.abs(A0 - np.eye(d)).max() <= 10 * TOL[prec]
+    A4 = qst.abs_map(Tg, 4.0, prec)[0].cpu().numpy()
+    assert rel_fro(A4, H @ H) <= TOL[prec]
+    D = np.diag(g.standard_normal(d) + 1j * g.standard_normal(d)).astype(ctype(prec))
+    A, Q, lam, sweeps = qst.abs_map(dev_matrix(D), 2.0, prec)
+    assert sweeps == 1
+    assert np.array_equal(lam.cpu().numpy(), np.diag(D).real.astype(np.float64))
+    assert rel_fro(A.cpu().numpy(), np.diag(np.abs(np.diag(D).real)).astype(np.complex128)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec,n,P", [("f64", 4, 1.5), ("f64", 5, 0.5), ("f32", 7, 3.0), ("f32", 8, 1.0)])
+def test_abs_likelihood_through_autograd(prec, n, P):
+    """T -> A (AbsMapFn) -> likelihood: L and autograd's dL/dT against the
+    oracle's grad_T_abs."""
+    d = 1 << n
+    g = S.rng(8400 + n)
+    T = S.ginibre(g, d).astype(ctype(prec))
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))
+    rt = torch.float64 if prec == "f64" else torch.float32
+    Tg = torch.from_numpy(T).to(DEV).requires_grad_(True)
+    fg = torch.from_numpy(f).to(DEV, rt)
+    L = qst.likelihood(Tg, fg, prec, state_map="abs", P=P)
+    L.backward()
+    torch.cuda.synchronize()
+    grad_w, L_w = O.grad_T_abs(T.astype(np.complex128), f, P)
+    eL = abs(float(L.item()) - L_w) / abs(L_w)
+    eg = rel_fro(Tg.grad.cpu().numpy(), grad_w)
+    say(f"N={n} {prec} P={P}: L rel err {eL:.2e}, grad rel err {eg:.2e}")
+    assert eL <= TOL[prec] and eg <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_abs_p2_equals_chol_h(prec):
+    """Eq. abs_P at P = 2 is Chol_H: the library's two routes agree in L
+    and dL/dT."""
+    n, d = 6, 64
+    g = S.rng(8500)
+    T = S.ginibre(g, d).astype(ctype(prec))
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))
+    rt = torch.float64 if prec == "f64" else torch.float32
+    fg = torch.from_numpy(f).to(DEV, rt)
+    out = {}
+    for mode in ("abs", "hermitian"):
+        Tg = torch.from_numpy(T).to(DEV).requires_grad_(True)
+        L = qst.likelihood(Tg, fg, prec, state_map=mode, P=2.0)
+        L.backward()
+        out[mode] = (float(L.item()), Tg.grad.cpu().numpy())
+    (La, ga), (Lh, gh) = out["abs"], out["hermitian"]
+    assert abs(La - Lh) <= TOL[prec] * abs(Lh)
+    assert rel_fro(ga, gh) <= (TOL[prec] if prec == "f64" else 1e-4)
+
+
+def test_abs_map_n10_against_oracle():
+    """N = 10 (the paper's size for the comparison of maps), FP32 storage,
+    P = 1.5: A and dL/dT against the oracle (the products on MFMA tiles with
+    the stream-K schedule)."""
+    n, d, P = 10, 1024, 1.5
+    g = S.rng(8600)
+    T = S.ginibre(g, d).astype(np.complex64)
+    GA = S.ginibre(g, d).astype(np.complex64)
+    T64 = T.astype(np.complex128)
+    t0 = time.perf_counter()
+    A, Q, lam, sweeps = qst.abs_map(dev_matrix(T), P, "f32")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    A_w, Qw, lw = O.abs_map(T64, P)
+    e = rel_fro(A.cpu().numpy(), A_w)
+    GT = qst.abs_map_backward(Q, lam, P, dev_matrix(GA), "f32")
+    eg = rel_fro(GT.cpu().numpy(), O.abs_map_backward(Qw, lw, P, GA.astype(np.complex128)))
+    say(f"N=10 f32 P={P}: sweeps {sweeps}, {dt:.2f} s, A rel err {e:.2e}, dL/dT rel err {eg:.2e}")
+    assert e <= 1e-5 and eg <= 1e-5
