@@ -270,6 +270,71 @@ def fidelities(qst, T, prec, reps=20):
     return out
 
 
+def abs_projection(qst, prec, dev, n=10, P=1.5, reps=5):
+    """The P-order absolute projection (Eq. abs_P) at N = 10, the size at
+    which the paper compares the state maps (P = 1.5, one of its orders):
+    qst_abs_map (the FP64 Jacobi eigensolver, then A = Q |Lambda|^(P/2)
+    Q^dagger) with its sweeps, the time per Jacobi round and its achieved
+    GB/s from algorithmic bytes (a round reads and writes every element of A
+    and of V^T once: 64 d^2 bytes), qst_abs_map_backward, and one whole step
+    through the map (abs map, likelihood, gradient, adjoint of the map)."""
+    import numpy as np
+    import torch
+
+    import synth as S
+
+    d = 1 << n
+    g = S.rng(21)
+    ct = np.complex128 if prec == "f64" else np.complex64
+    rt = torch.float64 if prec == "f64" else torch.float32
+    T = torch.from_numpy(S.ginibre(g, d).astype(ct)).to(dev)
+    GA = torch.from_numpy(S.ginibre(g, d).astype(ct)).to(dev)
+    f = torch.from_numpy(S.multinomial_freqs(g, 10_000_000, S.porter_thomas_probs(g, 4 ** n, 0.1))).to(dev, rt)
+    qst.abs_map(T, P, prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A, Q, lam, sweeps = qst.abs_map(T, P, prec)
+    torch.cuda.synchronize()
+    fwd_s = time.perf_counter() - t0
+    qst.abs_map_backward(Q, lam, P, GA, prec)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        qst.abs_map_backward(Q, lam, P, GA, prec)
+    ev1.record()
+    torch.cuda.synchronize()
+    bwd_ms = ev0.elapsed_time(ev1) / reps
+    rounds = sweeps * (d - 1)
+    round_us = 1e6 * fwd_s / rounds
+    gbs = 64.0 * d * d / (round_us * 1e-6) / 1e9
+    Tg = T.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = qst.likelihood(Tg, f, prec, state_map="abs", P=P)
+    L.backward()
+    torch.cuda.synchronize()
+    step_s = time.perf_counter() - t0
+    # a training loop's pattern: T moved by 1e-3 of its scale since the last
+    # step, the eigensolver warm-started from the last step's eigenvectors
+    proj = qst.AbsProjection(P, prec)
+    proj(T)
+    Tw = (T + 1e-3 * GA).requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = qst.likelihood(proj(Tw), f, prec)
+    L.backward()
+    torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t0
+    warm_sweeps = proj.sweeps
+    del A, Q, lam, T, GA, Tg, Tw, proj
+    return {"n_qubits": n, "P": P, "forward_ms": round(1e3 * fwd_s, 1), "sweeps": sweeps,
+            "round_us": round(round_us, 2), "round_GB_s": round(gbs, 1), "round_hbm_frac": round(gbs / 8000.0, 3),
+            "backward_ms": round(bwd_ms, 3), "step_ms": round(1e3 * step_s, 1),
+            "warm_step_ms": round(1e3 * warm_s, 1), "warm_sweeps": warm_sweeps,
+            "note": "forward wall time (synchronises once per sweep) divided over its rounds; warm step: T moved "
+                    "by 1e-3, eigensolver started from the previous eigenvectors (AbsProjection)"}
+
+
 def network(qst, f, prec, reps=10):
     """The mapping network of Sec. 3.1 at the bench size (4^N -> 2N -> 4^N,
     184.5M parameters at N = 11): forward and backward kernel time with
@@ -541,6 +606,7 @@ def main():
     modes = state_maps(qst, Tm, fm, args.prec)
     fids = fidelities(qst, Tm, args.prec)
     net = network(qst, fm, args.prec)
+    absp = abs_projection(qst, args.prec, fm.device)
     del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
@@ -569,6 +635,7 @@ def main():
         "povm_pass_gbs": {k: round(v, 1) for k, v in povm_gbs.items()},
         "paths": paths,
         "state_maps": modes,
+        "abs_projection": absp,
         "fidelity": fids,
         "network": net,
         "batched": batch,

@@ -241,6 +241,12 @@ qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X
  * (it reads the off-diagonal norm on the host to stop).
  *   P      [in]  finite, >= 0.
  *   T      [in]  d x d complex (prec's storage type), row stride ldT, device.
+ *   Q0     [in]  NULL, or a warm start: a unitary d x d complex FP64 matrix
+ *                laid out as Q (normally the Q of an earlier call on a
+ *                nearby T, e.g. the previous training step); the sweeps then
+ *                run on Q0^dagger H Q0, which takes fewer of them.  The
+ *                result does not depend on Q0 beyond rounding as long as Q0
+ *                is unitary.  Q0 may be Q; it must not overlap T, A or lam.
  *   A      [out] d x d complex (prec's storage type), row stride ldA, device.
  *                A == T with ldA == ldT works in place.
  *   Q      [out] d x d complex FP64 (interleaved re, im), row-major, row
@@ -254,8 +260,8 @@ qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X
  * finite (the off-diagonal norm is not finite) or the sweeps do not
  * converge.
  */
-qst_status qst_abs_map(int n_qubits, qst_prec prec, double P, const void* T, int64_t ldT, void* A, int64_t ldA,
-                       void* Q, double* lam, int* sweeps, void* ws, size_t ws_bytes, void* stream);
+qst_status qst_abs_map(int n_qubits, qst_prec prec, double P, const void* T, int64_t ldT, const void* Q0, void* A,
+                       int64_t ldA, void* Q, double* lam, int* sweeps, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Adjoint of qst_abs_map: dL/dT from dL/dA (both the gradient convention of

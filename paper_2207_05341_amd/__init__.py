@@ -21,7 +21,7 @@ from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MA
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
     "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
-    "abs_map_backward", "AbsMapFn", "fidelity_lowrank",
+    "abs_map_backward", "AbsMapFn", "AbsProjection", "fidelity_lowrank",
     "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
@@ -123,14 +123,18 @@ def state_premap(X: torch.Tensor, mode: str, prec=None, out: torch.Tensor | None
     return out
 
 
-def abs_map(T: torch.Tensor, P: float, prec=None, out: torch.Tensor | None = None):
+def abs_map(T: torch.Tensor, P: float, prec=None, out: torch.Tensor | None = None, Q0: torch.Tensor | None = None):
     """A = Q |Lambda|^(P/2) Q^dagger for the Hermitian part of T (qst_abs_map;
     the state map of A is the P-order absolute projection).  Returns
     (A, Q, lam, sweeps): Q d x d complex128, lam d float64, both on T's
-    device, and the Jacobi sweeps taken.  Synchronises the stream."""
+    device, and the Jacobi sweeps taken.  Q0: optional warm start (a unitary
+    Q from an earlier call on a nearby T).  Synchronises the stream."""
     n, ld = _matrix(T, "T")
     p = _prec(T.dtype, prec)
     d = 1 << n
+    if Q0 is not None and (Q0.shape != (d, d) or Q0.dtype != torch.complex128 or not Q0.is_contiguous()
+                           or Q0.device != T.device):
+        raise ValueError("Q0 must be a d x d contiguous complex128 matrix on T's device")
     if out is None:
         out = torch.empty((d, d), dtype=T.dtype, device=T.device)
     else:
@@ -141,9 +145,9 @@ def abs_map(T: torch.Tensor, P: float, prec=None, out: torch.Tensor | None = Non
     lam = torch.empty(d, dtype=torch.float64, device=T.device)
     sweeps = ctypes.c_int(-1)
     ws, nb = _workspace(n, p, QST_OP_ABS_MAP, T.device)
-    _lib.check(_lib.lib().qst_abs_map(n, p, float(P), T.data_ptr(), ld, out.data_ptr(), out.stride(0), Q.data_ptr(),
-                                      lam.data_ptr(), ctypes.byref(sweeps), _ptr(ws), nb, _stream(T.device)),
-               "qst_abs_map")
+    _lib.check(_lib.lib().qst_abs_map(n, p, float(P), T.data_ptr(), ld, _ptr(Q0), out.data_ptr(), out.stride(0),
+                                      Q.data_ptr(), lam.data_ptr(), ctypes.byref(sweeps), _ptr(ws), nb,
+                                      _stream(T.device)), "qst_abs_map")
     return out, Q, lam, sweeps.value
 
 
@@ -168,11 +172,16 @@ def abs_map_backward(Q: torch.Tensor, lam: torch.Tensor, P: float, GA: torch.Ten
 
 class AbsMapFn(torch.autograd.Function):
     """T' = Q |Lambda|^(P/2) Q^dagger of the Hermitian part of T, backward by
-    qst_abs_map_backward (saves Q and the eigenvalues)."""
+    qst_abs_map_backward (saves Q and the eigenvalues).  state: None, or a
+    dict whose "Q" (if present) warm-starts the eigensolver and receives
+    this call's Q and sweeps."""
 
     @staticmethod
-    def forward(ctx, T, P, prec):
-        A, Q, lam, _ = abs_map(T, P, prec)
+    def forward(ctx, T, P, prec, state=None):
+        Q0 = None if state is None else state.get("Q")
+        A, Q, lam, sweeps = abs_map(T, P, prec, Q0=Q0)
+        if state is not None:
+            state["Q"], state["sweeps"] = Q, sweeps
         ctx.P, ctx.prec = P, prec
         ctx.save_for_backward(Q, lam)
         return A
@@ -180,7 +189,27 @@ class AbsMapFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         Q, lam = ctx.saved_tensors
-        return abs_map_backward(Q, lam, ctx.P, g.contiguous(), ctx.prec), None, None
+        return abs_map_backward(Q, lam, ctx.P, g.contiguous(), ctx.prec), None, None, None
+
+
+class AbsProjection:
+    """The P-order absolute map for a training loop: each call returns
+    T' = Q |Lambda|^(P/2) Q^dagger (differentiable) and keeps Q to warm-start
+    the next call's eigensolver.  Use as likelihood(proj(T), f)."""
+
+    def __init__(self, P: float, prec=None):
+        self.P, self.prec = float(P), prec
+        self.state: dict = {}
+
+    def __call__(self, T: torch.Tensor) -> torch.Tensor:
+        Q = self.state.get("Q")
+        if Q is not None and (Q.shape != (T.shape[0], T.shape[0]) or Q.device != T.device):
+            self.state = {}
+        return AbsMapFn.apply(T, self.P, self.prec, self.state)
+
+    @property
+    def sweeps(self) -> int | None:
+        return self.state.get("sweeps")
 
 
 class StatePremapFn(torch.autograd.Function):
@@ -510,7 +539,7 @@ def likelihood(T: torch.Tensor, f: torch.Tensor, prec=None, recompute: bool | No
     if state_map not in STATE_MAPS:
         raise ValueError(f"unknown state map {state_map!r}")
     if state_map == "abs":
-        T = AbsMapFn.apply(T, P, prec)
+        T = AbsMapFn.apply(T, P, prec, None)
     elif state_map != "plain":
         T = StatePremapFn.apply(T, state_map, prec)
     return LikelihoodFn.apply(T, f, prec, mode, povm)

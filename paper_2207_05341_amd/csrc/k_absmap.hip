@@ -31,6 +31,11 @@
 // the Hermitian part are self-adjoint, so dL/dT = Q (Gamma o (Q^dagger S Q))
 // Q^dagger with S = (dL/dA + dL/dA^dagger) / 2: four complex products.
 //
+// A warm start from the eigenvectors Q0 of a nearby matrix (the previous
+// step of a training loop) runs the sweeps on Q0^dagger H Q0, nearly
+// diagonal, with V starting at Q0: two more products, and the sweeps drop to
+// the quadratically convergent tail.
+//
 // Everything runs in FP64 whatever the storage precision of T, A and the
 // gradients: the eigensolver's rounding enters A through g, whose slope is
 // unbounded near 0 for P < 2.
@@ -333,17 +338,26 @@ hipError_t store_out(qst_prec prec, const C64* X, void* Y, int64_t ldy, int n, h
 
 }  // namespace
 
-hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, void* A, int64_t ldA,
-                          void* Q, double* lam, void* ws, hipStream_t s, int* sweeps) {
+hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, const void* Q0, void* A,
+                          int64_t ldA, void* Q, double* lam, void* ws, hipStream_t s, int* sweeps) {
   *sweeps = -1;
   const int d = 1 << n, half = d >> 1;
   const Bufs b = carve(n, ws);
   hipError_t e;
   ProfScope prof("abs_map", s);
-  if ((e = herm_to64(prec, T, ldT, b.b0, n, s)) != hipSuccess) return e;
-  identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
   set_scalar_kernel<<<1, 1, 0, s>>>(b.scal, 2.0);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = herm_to64(prec, T, ldT, b.b0, n, s)) != hipSuccess) return e;
+  if (Q0) {
+    // Warm start from a unitary Q0: Jacobi on Q0^dagger H Q0 with V = Q0.
+    const C64* q0 = static_cast<const C64*>(Q0);
+    if ((e = transpose64(q0, d, b.b1, d, n, true, nullptr, s)) != hipSuccess) return e;  // Q0^dagger
+    if ((e = product64(b.b0, q0, b.b2, d, n, b, s)) != hipSuccess) return e;               // H Q0
+    if ((e = product64(b.b1, b.b2, b.b0, d, n, b, s)) != hipSuccess) return e;             // Q0^dagger H Q0
+    if ((e = transpose64(q0, d, b.b2, d, n, false, nullptr, s)) != hipSuccess) return e;  // V^T = Q0^T
+  } else {
+    identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   C64 *cur = b.b0, *nxt = b.b1;
   double prev = HUGE_VAL, host[2];
   for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {

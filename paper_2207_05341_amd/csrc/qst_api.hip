@@ -77,8 +77,8 @@ qst_status qst_state_premap(int n, qst_prec prec, int mode, const void* X, int64
   return QST_OK;
 }
 
-qst_status qst_abs_map(int n, qst_prec prec, double P, const void* T, int64_t ldT, void* A, int64_t ldA, void* Q,
-                       double* lam, int* sweeps, void* ws, size_t ws_bytes, void* stream) {
+qst_status qst_abs_map(int n, qst_prec prec, double P, const void* T, int64_t ldT, const void* Q0, void* A,
+                       int64_t ldA, void* Q, double* lam, int* sweeps, void* ws, size_t ws_bytes, void* stream) {
   std::string msg;
   qst_status st;
   if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
@@ -89,10 +89,12 @@ qst_status qst_abs_map(int n, qst_prec prec, double P, const void* T, int64_t ld
   if ((st = check_abs_order(P, msg)) != QST_OK) return fail(st, msg);
   if (A == T && ldA != ldT) return fail(QST_ERR_INVALID_ARG, "in place (A == T) needs ldA == ldT");
   if (Q == T || Q == A || Q == static_cast<void*>(lam)) return fail(QST_ERR_INVALID_ARG, "Q must not alias T, A or lam");
+  if (Q0 && (Q0 == T || Q0 == A || Q0 == static_cast<const void*>(lam)))
+    return fail(QST_ERR_INVALID_ARG, "Q0 must not alias T, A or lam");
   if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_ABS_MAP, false).total, msg)) != QST_OK)
     return fail(st, msg);
   int taken = -1;
-  hipError_t e = launch_abs_map(prec, n, P, T, ldT, A, ldA, Q, lam, ws, static_cast<hipStream_t>(stream), &taken);
+  hipError_t e = launch_abs_map(prec, n, P, T, ldT, Q0, A, ldA, Q, lam, ws, static_cast<hipStream_t>(stream), &taken);
   if (e != hipSuccess) return hip_fail(e, "absolute map");
   if (sweeps) *sweeps = taken;
   if (taken < 0)

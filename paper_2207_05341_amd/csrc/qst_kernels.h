@@ -51,8 +51,8 @@ hipError_t launch_fidelity_classical(qst_prec prec, const void* ph, const void* 
 // absmap_layout).  launch_abs_map synchronises s once per Jacobi sweep and
 // sets *sweeps to the sweeps taken, or -1 when the off-diagonal norm is not
 // finite or does not converge.
-hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, void* A, int64_t ldA,
-                          void* Q, double* lam, void* ws, hipStream_t s, int* sweeps);
+hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, const void* Q0, void* A,
+                          int64_t ldA, void* Q, double* lam, void* ws, hipStream_t s, int* sweeps);
 hipError_t launch_abs_map_backward(qst_prec prec, int n, double P, const void* Q, const double* lam, const void* GA,
                                    int64_t ldGA, void* GT, int64_t ldGT, void* ws, hipStream_t s);
 

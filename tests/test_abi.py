@@ -251,8 +251,8 @@ def test_abs_map_validation(L):
     W = ctypes.c_void_p(0x30000)
     Q, lam = ctypes.c_void_p(0x40000), ctypes.c_void_p(0x50000)
 
-    def fwd(n=n, prec=0, P=1.5, T=FAKE, ldT=d, A=FAKE2, ldA=d, Qp=Q, lp=lam, nb=ws):
-        return L.qst_abs_map(n, prec, P, T, ldT, A, ldA, Qp, lp, None, W, nb, None)
+    def fwd(n=n, prec=0, P=1.5, T=FAKE, ldT=d, Q0=None, A=FAKE2, ldA=d, Qp=Q, lp=lam, nb=ws):
+        return L.qst_abs_map(n, prec, P, T, ldT, Q0, A, ldA, Qp, lp, None, W, nb, None)
 
     assert fwd(n=0) == lib_mod.QST_ERR_INVALID_ARG and "n_qubits" in _err(L)
     assert fwd(prec=9) == lib_mod.QST_ERR_INVALID_ARG and "precision" in _err(L)
@@ -265,6 +265,7 @@ def test_abs_map_validation(L):
         assert fwd(P=bad) == lib_mod.QST_ERR_INVALID_ARG and "order P" in _err(L)
     assert fwd(A=FAKE, ldA=d + 1) == lib_mod.QST_ERR_INVALID_ARG and "in place" in _err(L)
     assert fwd(Qp=FAKE2) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
+    assert fwd(Q0=FAKE) == lib_mod.QST_ERR_INVALID_ARG and "Q0 must not alias" in _err(L)
     assert fwd(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
 
     def bwd(P=1.5, Qp=Q, lp=lam, GA=FAKE, ldGA=d, GT=FAKE2, ldGT=d, nb=ws):

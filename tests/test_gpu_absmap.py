@@ -186,3 +186,45 @@ def test_abs_map_n10_against_oracle():
     eg = rel_fro(GT.cpu().numpy(), O.abs_map_backward(Qw, lw, P, GA.astype(np.complex128)))
     say(f"N=10 f32 P={P}: sweeps {sweeps}, {dt:.2f} s, A rel err {e:.2e}, dL/dT rel err {eg:.2e}")
     assert e <= 1e-5 and eg <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_abs_map_warm_start(prec):
+    """Warm start from the eigenvectors of a nearby matrix: the same A and
+    dL/dT as a cold start (to the tolerance), in fewer sweeps; AbsProjection
+    over a drifting T (a training loop's pattern) against cold-start calls."""
+    n, d, P = 7, 128, 1.5
+    g = S.rng(8700)
+    T1 = S.ginibre(g, d)
+    E = S.ginibre(g, d)
+    T2 = (T1 + 1e-3 * E).astype(ctype(prec))
+    _, Q1, _, _ = qst.abs_map(dev_matrix(T1.astype(ctype(prec))), P, prec)
+    A_c, Q_c, lam_c, sw_c = qst.abs_map(dev_matrix(T2), P, prec)
+    A_w, Q_w, lam_w, sw_w = qst.abs_map(dev_matrix(T2), P, prec, Q0=Q1)
+    say(f"{prec}: cold {sw_c} sweeps, warm {sw_w} sweeps")
+    assert sw_w < sw_c
+    A_o = O.abs_map(T2.astype(np.complex128), P)[0]
+    assert rel_fro(A_w.cpu().numpy(), A_o) <= TOL[prec]
+    assert rel_fro(A_w.cpu().numpy(), A_c.cpu().numpy()) <= TOL[prec]
+    GA = dev_matrix(S.ginibre(g, d).astype(ctype(prec)))
+    G_c = qst.abs_map_backward(Q_c, lam_c, P, GA, prec).cpu().numpy()
+    G_w = qst.abs_map_backward(Q_w, lam_w, P, GA, prec).cpu().numpy()
+    assert rel_fro(G_w, G_c) <= TOL[prec]
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))
+    rt = torch.float64 if prec == "f64" else torch.float32
+    fg = torch.from_numpy(f).to(DEV, rt)
+    proj = qst.AbsProjection(P, prec)
+    for k in range(4):
+        Tk = (T1 + (1e-3 * k) * E).astype(ctype(prec))
+        out = []
+        for warm in (True, False):
+            Tg = torch.from_numpy(Tk).to(DEV).requires_grad_(True)
+            L = qst.likelihood(proj(Tg), fg, prec) if warm else qst.likelihood(Tg, fg, prec, state_map="abs", P=P)
+            L.backward()
+            out.append((float(L.item()), Tg.grad.cpu().numpy()))
+        (Lw, gw), (Lc, gc) = out
+        say(f"  step {k}: warm sweeps {proj.sweeps}, L {Lw:.12f} vs {Lc:.12f}")
+        assert abs(Lw - Lc) <= TOL[prec] * abs(Lc) and rel_fro(gw, gc) <= 10 * TOL[prec]
+        if k:
+            assert proj.sweeps < sw_c
