@@ -96,15 +96,20 @@ __device__ __forceinline__ Rot rot_of(const C64* A, int d, int p, int q) {
   return make_rot(A[int64_t(p) * d + p].re, A[int64_t(q) * d + q].re, A[int64_t(p) * d + q]);
 }
 
-// One round t: workgroup k rewrites rows p, q of pair k (Ain -> Aout) and
-// rotates rows p, q of Vt; part[2k], part[2k+1] receive the squared
-// off-diagonal and diagonal entries of the new rows.
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const C64* __restrict__ Ain, C64* __restrict__ Aout,
-                                                           C64* __restrict__ Vt, int d, int t,
-                                                           double* __restrict__ part) {
-  __shared__ double lds4[4];
+// One round t: workgroup (k, c) rewrites the column pairs [128c, 128c + 128)
+// of rows p, q of pair k (Ain -> Aout), one column pair per thread, and
+// rotates columns [2 * 128c, 2 * 128c + 256) of rows p, q of Vt (every
+// element of both is touched by exactly one workgroup of the round);
+// part[2i], part[2i+1] (i = k * chunks + c) receive the squared off-diagonal
+// and diagonal entries it wrote.
+constexpr int kRoundThreads = 128;
+
+__global__ __launch_bounds__(kRoundThreads) void jacobi_round_kernel(const C64* __restrict__ Ain,
+                                                                     C64* __restrict__ Aout, C64* __restrict__ Vt,
+                                                                     int d, int t, double* __restrict__ part) {
+  __shared__ double red[2][kRoundThreads / 64];
   const int m = d - 1, half = d >> 1;
-  const int k = blockIdx.x;
+  const int k = blockIdx.x, c = blockIdx.y;
   int p, q;
   pair_at(k, t, m, p, q);
   const Rot J = rot_of(Ain, d, p, q);
@@ -114,7 +119,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const C64* __restrict
   C64* wp = Aout + int64_t(p) * d;
   C64* wq = Aout + int64_t(q) * d;
   double off = 0.0, dia = 0.0;
-  for (int R = threadIdx.x; R < half; R += 256) {
+  const int R = c * kRoundThreads + int(threadIdx.x);
+  if (R < half) {
     int r, s;
     pair_at(R, t, m, r, s);
     if (R == k) {
@@ -123,47 +129,55 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const C64* __restrict
       wq[q] = C64{b, 0.0};
       wp[q] = C64{0.0, 0.0};
       wq[p] = C64{0.0, 0.0};
-      dia += a * a + b * b;
-      continue;
+      dia = a * a + b * b;
+    } else {
+      const Rot K = rot_of(Ain, d, r, s);
+      const C64 xpr = rp[r], xps = rp[s], xqr = rq[r], xqs = rq[s];
+      // right: [u, v] J_rs = [u cs - v sn ph, u sn + v cs ph]
+      const C64 vp = cmul(xps, K.ph), vq = cmul(xqs, K.ph);
+      const C64 ypr = csub(cscale(xpr, K.cs), cscale(vp, K.sn)), yps = cadd(cscale(xpr, K.sn), cscale(vp, K.cs));
+      const C64 yqr = csub(cscale(xqr, K.cs), cscale(vq, K.sn)), yqs = cadd(cscale(xqr, K.sn), cscale(vq, K.cs));
+      // left: J_pq^dagger = [[cs, -sn conj(ph)], [sn, cs conj(ph)]]
+      const C64 ur = cmul(phc, yqr), us = cmul(phc, yqs);
+      const C64 zpr = csub(cscale(ypr, J.cs), cscale(ur, J.sn)), zqr = cadd(cscale(ypr, J.sn), cscale(ur, J.cs));
+      const C64 zps = csub(cscale(yps, J.cs), cscale(us, J.sn)), zqs = cadd(cscale(yps, J.sn), cscale(us, J.cs));
+      wp[r] = zpr;
+      wp[s] = zps;
+      wq[r] = zqr;
+      wq[s] = zqs;
+      off = cnorm(zpr) + cnorm(zps) + cnorm(zqr) + cnorm(zqs);
     }
-    const Rot K = rot_of(Ain, d, r, s);
-    const C64 xpr = rp[r], xps = rp[s], xqr = rq[r], xqs = rq[s];
-    // right: [u, v] J_rs = [u cs - v sn ph, u sn + v cs ph]
-    const C64 vp = cmul(xps, K.ph), vq = cmul(xqs, K.ph);
-    const C64 ypr = csub(cscale(xpr, K.cs), cscale(vp, K.sn)), yps = cadd(cscale(xpr, K.sn), cscale(vp, K.cs));
-    const C64 yqr = csub(cscale(xqr, K.cs), cscale(vq, K.sn)), yqs = cadd(cscale(xqr, K.sn), cscale(vq, K.cs));
-    // left: J_pq^dagger = [[cs, -sn conj(ph)], [sn, cs conj(ph)]]
-    const C64 ur = cmul(phc, yqr), us = cmul(phc, yqs);
-    const C64 zpr = csub(cscale(ypr, J.cs), cscale(ur, J.sn)), zqr = cadd(cscale(ypr, J.sn), cscale(ur, J.cs));
-    const C64 zps = csub(cscale(yps, J.cs), cscale(us, J.sn)), zqs = cadd(cscale(yps, J.sn), cscale(us, J.cs));
-    wp[r] = zpr;
-    wp[s] = zps;
-    wq[r] = zqr;
-    wq[s] = zqs;
-    off += cnorm(zpr) + cnorm(zps) + cnorm(zqr) + cnorm(zqs);
   }
   C64* vpr = Vt + int64_t(p) * d;
   C64* vqr = Vt + int64_t(q) * d;
-  for (int c = threadIdx.x; c < d; c += 256) {
-    const C64 u = vpr[c], v = cmul(vqr[c], J.ph);
-    vpr[c] = csub(cscale(u, J.cs), cscale(v, J.sn));
-    vqr[c] = cadd(cscale(u, J.sn), cscale(v, J.cs));
+  const int c0 = 2 * kRoundThreads * c, c1 = min(d, c0 + 2 * kRoundThreads);
+  for (int col = c0 + int(threadIdx.x); col < c1; col += kRoundThreads) {
+    const C64 u = vpr[col], v = cmul(vqr[col], J.ph);
+    vpr[col] = csub(cscale(u, J.cs), cscale(v, J.sn));
+    vqr[col] = cadd(cscale(u, J.sn), cscale(v, J.cs));
   }
-  off = block_sum256(off, lds4);
-  dia = block_sum256(dia, lds4);
+  off = wave_sum(off);
+  dia = wave_sum(dia);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = off;
+    red[1][w] = dia;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    part[2 * k] = off;
-    part[2 * k + 1] = dia;
+    const int i = k * int(gridDim.y) + c;
+    part[2 * i] = red[0][0] + red[0][1];
+    part[2 * i + 1] = red[1][0] + red[1][1];
   }
 }
 
-// out[0] = sum of part[2k] (off-diagonal), out[1] = sum of part[2k+1], in a
-// fixed order.
-__global__ __launch_bounds__(256) void jacobi_norms_kernel(const double* __restrict__ part, int half,
+// out[0] = sum of part[2i] (off-diagonal), out[1] = sum of part[2i+1] over
+// the round's workgroups i, in a fixed order.
+__global__ __launch_bounds__(256) void jacobi_norms_kernel(const double* __restrict__ part, int count,
                                                            double* __restrict__ out) {
   __shared__ double lds4[4];
   double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < half; k += 256) {
+  for (int k = threadIdx.x; k < count; k += 256) {
     a += part[2 * k];
     b += part[2 * k + 1];
   }
@@ -358,16 +372,17 @@ hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t
     identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  const int chunks = (half + kRoundThreads - 1) / kRoundThreads;
   C64 *cur = b.b0, *nxt = b.b1;
   double prev = HUGE_VAL, host[2];
   for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
     for (int t = 0; t < d - 1; ++t) {
-      jacobi_round_kernel<<<half, 256, 0, s>>>(cur, nxt, b.b2, d, t, b.part);
+      jacobi_round_kernel<<<dim3(half, chunks), kRoundThreads, 0, s>>>(cur, nxt, b.b2, d, t, b.part);
       C64* x = cur;
       cur = nxt;
       nxt = x;
     }
-    jacobi_norms_kernel<<<1, 256, 0, s>>>(b.part, half, b.scal + 2);
+    jacobi_norms_kernel<<<1, 256, 0, s>>>(b.part, half * chunks, b.scal + 2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(host, b.scal + 2, sizeof(host), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;

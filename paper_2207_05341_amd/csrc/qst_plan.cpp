@@ -3,6 +3,7 @@
 // run on machines without a GPU.
 #include "qst_plan.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -119,7 +120,10 @@ AbsMapLayout absmap_layout(int n) {
   a.b0 = take(d * d * 16);
   a.b1 = take(d * d * 16);
   a.b2 = take(d * d * 16);
-  a.part = take(d * sizeof(double));
+  // two partials per workgroup of a Jacobi round: d/2 pairs x ceil(d/256)
+  // column chunks (at least d values: |lambda|^(P/4) reuses the area)
+  const size_t chunks = (d / 2 + 127) / 128;
+  a.part = take(std::max(d, d * chunks) * sizeof(double));
   a.scal = take(8 * sizeof(double));
   if (n >= kStreamKMinQubits) {
     a.sk_bytes = stream_k_partial_bytes(QST_F64);
