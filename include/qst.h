@@ -283,6 +283,31 @@ qst_status qst_abs_map_backward(int n_qubits, qst_prec prec, double P, const voi
                                 void* stream);
 
 /*
+ * Quantum fidelity against a general target (Sec. 2.3 Eq. F_QF, computed
+ * with one eigendecomposition as Eq. fq_decom does):
+ *   F_q = (Tr sqrt(sqrt(rho_hat) rho sqrt(rho_hat)))^2,
+ *   rho_hat = T T^dagger / Tr(T T^dagger).
+ * sqrt(rho_hat) rho sqrt(rho_hat) and T^dagger rho T / Tr(T T^dagger) have
+ * the same nonzero eigenvalues (rho_hat's factor T stands in for the first
+ * decomposition of Eq. fq_decom), so F_q = (sum_i sqrt(lambda_i))^2 / tau
+ * with lambda_i the eigenvalues of T^dagger rho T (two FP64 complex
+ * products and the FP64 Jacobi eigensolver of qst_abs_map; rounding-level
+ * negative eigenvalues read as 0).  For a target of low rank prefer
+ * qst_fidelity_lowrank: here each of the d - r zero eigenvalues can add
+ * the square root of its rounding error.
+ *   T      [in]  d x d complex, row stride ldT, device.
+ *   rho    [in]  d x d complex Hermitian positive semidefinite with trace 1
+ *                (not checked), row stride ldR, device.
+ *   F_dev  [out] one double, device.
+ *   sweeps [out] host int, may be NULL: the Jacobi sweeps taken.
+ * Workspace: qst_workspace_bytes(N, prec, QST_OP_ABS_MAP).  Synchronises the
+ * stream once per sweep.  QST_ERR_INVALID_ARG when the sweeps do not
+ * converge (non-finite input).
+ */
+qst_status qst_fidelity_general(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* rho,
+                                int64_t ldR, double* F_dev, int* sweeps, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Quantum fidelity against a target of low rank r (Sec. 2.3 Eq. F_QF):
  *   F_q = (Tr sqrt(sqrt(rho_hat) rho sqrt(rho_hat)))^2,
  *   rho_hat = T T^dagger / Tr(T T^dagger)   (the state map of T),

@@ -21,7 +21,7 @@ from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MA
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
     "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
-    "abs_map_backward", "AbsMapFn", "AbsProjection", "fidelity_lowrank",
+    "abs_map_backward", "AbsMapFn", "AbsProjection", "fidelity_lowrank", "fidelity_general",
     "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
@@ -345,6 +345,25 @@ def fidelity_lowrank(T: torch.Tensor, W: torch.Tensor, prec=None) -> torch.Tenso
     _lib.check(_lib.lib().qst_fidelity_lowrank(n, pr, T.data_ptr(), ld, W.data_ptr(), W.stride(0), r, F.data_ptr(),
                                                _ptr(ws), nb, _stream(T.device)), "qst_fidelity_lowrank")
     return F
+
+
+def fidelity_general(T: torch.Tensor, rho: torch.Tensor, prec=None):
+    """F_q(T T^dagger / Tr, rho) for any target density matrix rho (d x d,
+    T's dtype) by one eigensolve of T^dagger rho T (qst_fidelity_general).
+    Returns (F as a 0-dim float64 device tensor, Jacobi sweeps).
+    Synchronises the stream."""
+    n, ld = _matrix(T, "T")
+    n2, ldr = _matrix(rho, "rho")
+    if n2 != n or rho.dtype != T.dtype:
+        raise ValueError("rho must match T in size and dtype")
+    pr = _prec(T.dtype, prec)
+    F = torch.empty((), dtype=torch.float64, device=T.device)
+    sweeps = ctypes.c_int(-1)
+    ws, nb = _workspace(n, pr, QST_OP_ABS_MAP, T.device)
+    _lib.check(_lib.lib().qst_fidelity_general(n, pr, T.data_ptr(), ld, rho.data_ptr(), ldr, F.data_ptr(),
+                                               ctypes.byref(sweeps), _ptr(ws), nb, _stream(T.device)),
+               "qst_fidelity_general")
+    return F, sweeps.value
 
 
 def fidelity_classical(p_hat: torch.Tensor, p: torch.Tensor, prec=None) -> torch.Tensor:

@@ -36,6 +36,7 @@ SIGNATURES = {
                                ctypes.c_double, _vp]),
     "qst_fidelity_lowrank": (_int, [_int, _int, _vp, _i64, _vp, _i64, _int, _vp, _vp, _sz, _vp]),
     "qst_fidelity_classical": (_int, [_int, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qst_fidelity_general": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     "qst_workspace_bytes": (_sz, [_int, _int, _int]),
     "qst_status_string": (ctypes.c_char_p, [_int]),
     "qst_last_error": (ctypes.c_char_p, []),

@@ -350,12 +350,113 @@ hipError_t store_out(qst_prec prec, const C64* X, void* Y, int64_t ldy, int n, h
   return hipGetLastError();
 }
 
+// Jacobi sweeps on *cur (ping-pong with *nxt; V^T rotated in b.b2) until
+// the stopping rule holds; on return *cur holds the diagonalised matrix and
+// *sweeps the sweeps taken, or -1 (non-finite or not converged).
+hipError_t jacobi_sweeps(const Bufs& b, int n, C64*& cur, C64*& nxt, hipStream_t s, int* sweeps) {
+  *sweeps = -1;
+  const int d = 1 << n, half = d >> 1;
+  const int chunks = (half + kRoundThreads - 1) / kRoundThreads;
+  hipError_t e;
+  double prev = HUGE_VAL, host[2];
+  for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
+    for (int t = 0; t < d - 1; ++t) {
+      jacobi_round_kernel<<<dim3(half, chunks), kRoundThreads, 0, s>>>(cur, nxt, b.b2, d, t, b.part);
+      C64* x = cur;
+      cur = nxt;
+      nxt = x;
+    }
+    jacobi_norms_kernel<<<1, 256, 0, s>>>(b.part, half * chunks, b.scal + 2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(host, b.scal + 2, sizeof(host), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const double off = host[0], tot = host[0] + host[1];
+    if (!std::isfinite(off) || !std::isfinite(tot)) return hipSuccess;
+    const double r = tot > 0.0 ? std::sqrt(off / tot) : 0.0;
+    if (r <= 1e-14 || (r <= 1e-10 && r > 0.5 * prev)) {
+      *sweeps = sweep;
+      return hipSuccess;
+    }
+    prev = r;
+  }
+  return hipSuccess;
+}
+
+// X (storage type R, row stride ldx) -> FP64, d x d contiguous.
+template <typename R>
+__global__ __launch_bounds__(256) void to64_kernel(const Cx<R>* __restrict__ X, int64_t ldx, int n,
+                                                   C64* __restrict__ Y) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= (int64_t(1) << (2 * n))) return;
+  const Cx<R> v = X[(e >> n) * ldx + (e & ((int64_t(1) << n) - 1))];
+  Y[e] = C64{double(v.re), double(v.im)};
+}
+
+hipError_t to64(qst_prec prec, const void* X, int64_t ldx, C64* Y, int n, hipStream_t s) {
+  if (prec == QST_F64)
+    to64_kernel<double><<<elem_blocks(n), 256, 0, s>>>(static_cast<const Cx<double>*>(X), ldx, n, Y);
+  else
+    to64_kernel<float><<<elem_blocks(n), 256, 0, s>>>(static_cast<const Cx<float>*>(X), ldx, n, Y);
+  return hipGetLastError();
+}
+
+// part[2b] = sum of |X_e|^2 over e = b, b + nb, ... (part[2b+1] = 0).
+__global__ __launch_bounds__(256) void sumsq_kernel(const C64* __restrict__ X, int64_t count,
+                                                    double* __restrict__ part) {
+  __shared__ double lds4[4];
+  double a = 0.0;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < count; e += int64_t(gridDim.x) * 256)
+    a += cnorm(X[e]);
+  a = block_sum256(a, lds4);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+// F = (sum_i sqrt(max(C_ii, 0)))^2 / tau over the diagonal of the
+// diagonalised C, in a fixed order (one workgroup).
+__global__ __launch_bounds__(256) void fq_finish_kernel(const C64* __restrict__ C, int d,
+                                                        const double* __restrict__ tau, double* __restrict__ F) {
+  __shared__ double lds4[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) a += sqrt(fmax(C[int64_t(i) * d + i].re, 0.0));
+  a = block_sum256(a, lds4);
+  if (threadIdx.x == 0) *F = a * a / *tau;
+}
+
 }  // namespace
+
+hipError_t launch_fidelity_general(qst_prec prec, int n, const void* T, int64_t ldT, const void* rho, int64_t ldR,
+                                   double* F, void* ws, hipStream_t s, int* sweeps) {
+  *sweeps = -1;
+  const int d = 1 << n, half = d >> 1;
+  const Bufs b = carve(n, ws);
+  hipError_t e;
+  ProfScope prof("fidelity_general", s);
+  set_scalar_kernel<<<1, 1, 0, s>>>(b.scal, 2.0);
+  if ((e = to64(prec, T, ldT, b.b0, n, s)) != hipSuccess) return e;  // T
+  const int nb = half < 256 ? half : 256;                               // 2 nb <= d partials
+  sumsq_kernel<<<nb, 256, 0, s>>>(b.b0, int64_t(d) * d, b.part);
+  jacobi_norms_kernel<<<1, 256, 0, s>>>(b.part, nb, b.scal + 4);      // tau at scal[4]
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = to64(prec, rho, ldR, b.b2, n, s)) != hipSuccess) return e;                         // rho
+  if ((e = product64(b.b2, b.b0, b.b1, d, n, b, s)) != hipSuccess) return e;                  // rho T
+  if ((e = transpose64(b.b0, d, b.b2, d, n, true, nullptr, s)) != hipSuccess) return e;      // T^dagger
+  if ((e = product64(b.b2, b.b1, b.b0, d, n, b, s)) != hipSuccess) return e;                  // C = T^dagger rho T
+  identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  C64 *cur = b.b0, *nxt = b.b1;
+  if ((e = jacobi_sweeps(b, n, cur, nxt, s, sweeps)) != hipSuccess) return e;
+  if (*sweeps < 0) return hipSuccess;
+  fq_finish_kernel<<<1, 256, 0, s>>>(cur, d, b.scal + 4, F);
+  return hipGetLastError();
+}
 
 hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, const void* Q0, void* A,
                           int64_t ldA, void* Q, double* lam, void* ws, hipStream_t s, int* sweeps) {
   *sweeps = -1;
-  const int d = 1 << n, half = d >> 1;
+  const int d = 1 << n;
   const Bufs b = carve(n, ws);
   hipError_t e;
   ProfScope prof("abs_map", s);
@@ -372,29 +473,8 @@ hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t
     identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const int chunks = (half + kRoundThreads - 1) / kRoundThreads;
   C64 *cur = b.b0, *nxt = b.b1;
-  double prev = HUGE_VAL, host[2];
-  for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
-    for (int t = 0; t < d - 1; ++t) {
-      jacobi_round_kernel<<<dim3(half, chunks), kRoundThreads, 0, s>>>(cur, nxt, b.b2, d, t, b.part);
-      C64* x = cur;
-      cur = nxt;
-      nxt = x;
-    }
-    jacobi_norms_kernel<<<1, 256, 0, s>>>(b.part, half * chunks, b.scal + 2);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(host, b.scal + 2, sizeof(host), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const double off = host[0], tot = host[0] + host[1];
-    if (!std::isfinite(off) || !std::isfinite(tot)) return hipSuccess;  // sweeps stays -1
-    const double r = tot > 0.0 ? std::sqrt(off / tot) : 0.0;
-    if (r <= 1e-14 || (r <= 1e-10 && r > 0.5 * prev)) {
-      *sweeps = sweep;
-      break;
-    }
-    prev = r;
-  }
+  if ((e = jacobi_sweeps(b, n, cur, nxt, s, sweeps)) != hipSuccess) return e;
   if (*sweeps < 0) return hipSuccess;
   // cur holds Lambda on its diagonal, b.b2 = V^T; the other buffer is free.
   double* sc = b.part;  // |lam|^(P/4), d values

@@ -103,6 +103,26 @@ qst_status qst_abs_map(int n, qst_prec prec, double P, const void* T, int64_t ld
   return QST_OK;
 }
 
+qst_status qst_fidelity_general(int n, qst_prec prec, const void* T, int64_t ldT, const void* rho, int64_t ldR,
+                                double* F_dev, int* sweeps, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(rho, ldR, n, "rho", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(F_dev, "F_dev", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_ABS_MAP, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  int taken = -1;
+  hipError_t e = launch_fidelity_general(prec, n, T, ldT, rho, ldR, F_dev, ws, static_cast<hipStream_t>(stream), &taken);
+  if (e != hipSuccess) return hip_fail(e, "general fidelity");
+  if (sweeps) *sweeps = taken;
+  if (taken < 0)
+    return fail(QST_ERR_INVALID_ARG, "general fidelity: the Jacobi sweeps did not converge (are T and rho finite?)");
+  clear_error();
+  return QST_OK;
+}
+
 qst_status qst_abs_map_backward(int n, qst_prec prec, double P, const void* Q, const double* lam, const void* GA,
                                 int64_t ldGA, void* GT, int64_t ldGT, void* ws, size_t ws_bytes, void* stream) {
   std::string msg;

@@ -53,6 +53,10 @@ hipError_t launch_fidelity_classical(qst_prec prec, const void* ph, const void* 
 // finite or does not converge.
 hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, const void* Q0, void* A,
                           int64_t ldA, void* Q, double* lam, void* ws, hipStream_t s, int* sweeps);
+// F_q against a general target rho: one eigensolve of T^dagger rho T (the
+// absolute-map workspace; synchronises s once per sweep like launch_abs_map).
+hipError_t launch_fidelity_general(qst_prec prec, int n, const void* T, int64_t ldT, const void* rho, int64_t ldR,
+                                   double* F, void* ws, hipStream_t s, int* sweeps);
 hipError_t launch_abs_map_backward(qst_prec prec, int n, double P, const void* Q, const double* lam, const void* GA,
                                    int64_t ldGA, void* GT, int64_t ldGT, void* ws, hipStream_t s);
 

@@ -281,6 +281,22 @@ def test_abs_map_validation(L):
     assert bwd(nb=0) == lib_mod.QST_ERR_WORKSPACE
 
 
+def test_fidelity_general_validation(L):
+    n, d = 5, 32
+    ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_ABS_MAP)
+    W, F = ctypes.c_void_p(0x30000), ctypes.c_void_p(0x40000)
+
+    def call(n=n, T=FAKE, ldT=d, R=FAKE2, ldR=d, Fd=F, nb=ws):
+        return L.qst_fidelity_general(n, 0, T, ldT, R, ldR, Fd, None, W, nb, None)
+
+    assert call(n=14) == lib_mod.QST_ERR_INVALID_ARG and "n_qubits" in _err(L)
+    assert call(T=None) == lib_mod.QST_ERR_INVALID_ARG and "T is NULL" in _err(L)
+    assert call(R=None) == lib_mod.QST_ERR_INVALID_ARG and "rho is NULL" in _err(L)
+    assert call(ldR=d - 1) == lib_mod.QST_ERR_INVALID_ARG and "leading dimension" in _err(L)
+    assert call(Fd=None) == lib_mod.QST_ERR_INVALID_ARG and "F_dev" in _err(L)
+    assert call(nb=ws // 2) == lib_mod.QST_ERR_WORKSPACE
+
+
 def test_fidelity_validation(L):
     n, d = 6, 64
     ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_FIDELITY)

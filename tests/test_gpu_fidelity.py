@@ -93,3 +93,31 @@ def test_fidelity_classical_against_oracle(prec, n):
     say(f"N={n} {prec}: F_c {got:.12f} oracle {want:.12f}")
     assert abs(got - want) <= TOL[prec] * want
     assert float(qst.fidelity_classical(torch.from_numpy(ph).to(DEV), torch.from_numpy(p).to(DEV), prec).item()) == got
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 3, 6, 8])
+def test_fidelity_general_against_oracle(prec, n):
+    """qst_fidelity_general (one eigensolve of T^dagger rho T, Eq. fq_decom)
+    against the oracle's F_q by two square roots (Eq. F_QF) for full-rank
+    targets: a Ginibre mixed state and the depolarised pure state of the
+    paper's noise model; F = 1 for rho = rho_hat."""
+    d = 1 << n
+    g = S.rng(7250 + n)
+    T = S.ginibre(g, d).astype(ctype(prec))
+    T64 = T.astype(np.complex128)
+    rho_hat = O.state_map(T64)[0]
+    Tg = dev_matrix(T, pad=2)
+    X = S.ginibre(g, d)
+    targets = {"ginibre": (X @ X.conj().T) / np.trace(X @ X.conj().T).real,
+               "depolarised": S.depolarised_pure(S.haar_vector(g, d), 0.3), "self": rho_hat}
+    for name, rho in targets.items():
+        r = rho.astype(ctype(prec))
+        want = O.fidelity_q(rho_hat, r.astype(np.complex128))
+        F, sweeps = qst.fidelity_general(Tg, dev_matrix(r), prec)
+        got = float(F.item())
+        say(f"N={n} {prec} {name}: F_q {got:.12f} oracle {want:.12f} ({sweeps} sweeps)")
+        tol = TOL[prec] if name != "self" else max(TOL[prec], 1e-9 * d)
+        assert abs(got - want) <= tol * want, (name, got, want)
+    F1, _ = qst.fidelity_general(Tg, dev_matrix(rho_hat.astype(ctype(prec))), prec)
+    assert abs(float(F1.item()) - 1.0) <= max(TOL[prec], 1e-9 * d)
