@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--n", type=int, default=11)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precision paths")
+    ap.add_argument("--no-long", action="store_true",
+                    help="skip the runs of many small launches (1000-step NN-QST run, absolute projection)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy (torch.neg) of this many MiB first, as the "
@@ -326,16 +328,25 @@ def abs_projection(qst, prec, dev, n=10, P=1.5, reps=5):
     torch.cuda.synchronize()
     warm_s = time.perf_counter() - t0
     warm_sweeps = proj.sweeps
-    del A, Q, lam, T, GA, Tg, Tw, proj
+    # F_q against a full-rank target (a depolarised pure state) by one
+    # eigensolve of T^dagger rho T
+    rho = torch.from_numpy(S.depolarised_pure(S.haar_vector(g, d), 0.3).astype(ct)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F, fsweeps = qst.fidelity_general(T, rho, prec)
+    float(F.item())
+    fq_s = time.perf_counter() - t0
+    del A, Q, lam, T, GA, Tg, Tw, proj, rho
     return {"n_qubits": n, "P": P, "forward_ms": round(1e3 * fwd_s, 1), "sweeps": sweeps,
             "round_us": round(round_us, 2), "round_GB_s": round(gbs, 1), "round_hbm_frac": round(gbs / 8000.0, 3),
             "backward_ms": round(bwd_ms, 3), "step_ms": round(1e3 * step_s, 1),
             "warm_step_ms": round(1e3 * warm_s, 1), "warm_sweeps": warm_sweeps,
+            "fidelity_general_ms": round(1e3 * fq_s, 1), "fidelity_general_sweeps": fsweeps,
             "note": "forward wall time (synchronises once per sweep) divided over its rounds; warm step: T moved "
                     "by 1e-3, eigensolver started from the previous eigenvectors (AbsProjection)"}
 
 
-def network(qst, f, prec, reps=10):
+def network(qst, f, prec, reps=10, long_run=True):
     """The mapping network of Sec. 3.1 at the bench size (4^N -> 2N -> 4^N,
     184.5M parameters at N = 11): forward and backward kernel time with
     achieved GB/s from algorithmic bytes (each weight matrix streamed once
@@ -388,7 +399,7 @@ def network(qst, f, prec, reps=10):
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / reps
     del net, opt, T, G, grad
-    conv = convergence(qst, n, prec, f.device)
+    conv = convergence(qst, n, prec, f.device) if long_run else None
     return {"parameters": 2 * H * D + H + D,
             "forward_us": round(fwd_us, 1), "forward_GB_s": round(fwd_bytes / (fwd_us * 1e-6) / 1e9, 1),
             "forward_hbm_frac": round(fwd_bytes / (fwd_us * 1e-6) / 8e12, 3),
@@ -605,8 +616,8 @@ def main():
     Tm, fm = to_prec(T_np, f_np, args.prec, dev)
     modes = state_maps(qst, Tm, fm, args.prec)
     fids = fidelities(qst, Tm, args.prec)
-    net = network(qst, fm, args.prec)
-    absp = abs_projection(qst, args.prec, fm.device)
+    net = network(qst, fm, args.prec, long_run=not args.no_long)
+    absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
     del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
