@@ -188,6 +188,26 @@ qst_status qst_likelihood(int n_qubits, qst_prec prec, const void* T, int64_t ld
                           size_t ws_bytes, void* stream);
 
 /*
+ * qst_likelihood plus the classical fidelity (Sec. 2.3 Eq. F_CF) of the
+ * model's distribution p_k = Tr(M_k rho) against a target distribution:
+ *   F_c = (sum_k sqrt(max(p_k, 0) max(p_target_k, 0)))^2.
+ * Where qst_likelihood fuses its last POVM pass (N >= 7 with the fused
+ * plan), the terms are formed in that pass from the p_k it holds in
+ * registers (one more read of 4^N reals, p still never stored); otherwise
+ * from the stored p.  L, F, the counters and G are those of qst_likelihood
+ * (bitwise).
+ *   p_target [in]  4^N reals (storage precision of f), device; read as
+ *                  given (not renormalised).
+ *   fc_dev   [out] one double, device.
+ * Other arguments, workspace (QST_OP_LIKELIHOOD) and errors as
+ * qst_likelihood.
+ */
+qst_status qst_likelihood_fc(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* f,
+                             const void* p_target, const double* povm_host, double* tau_dev, double* nll_dev,
+                             double* fc_dev, unsigned long long* bad_dev, void* G, int64_t ldG, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/*
  * Gradient product, the last step of the adjoint (Eq. MLE_T):
  *   gradT = s * (2 / tau) * G' T,  s = *upstream_dev (1 if upstream_dev is NULL),
  * for G' and tau from qst_likelihood (same T).

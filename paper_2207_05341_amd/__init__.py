@@ -20,7 +20,7 @@ from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MA
 
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
-    "likelihood_forward", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
+    "likelihood_forward", "likelihood_forward_fc", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
     "abs_map_backward", "AbsMapFn", "AbsProjection", "fidelity_lowrank", "fidelity_general",
     "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
@@ -311,6 +311,29 @@ def likelihood_forward(T: torch.Tensor, f: torch.Tensor, prec=None, povm=None, w
                                          out.data_ptr(), bad.data_ptr(), _ptr(G), 0 if G is None else G.stride(0),
                                          _ptr(ws), nb, _stream(T.device)), "qst_likelihood")
     return out, tau, G, bad
+
+
+def likelihood_forward_fc(T: torch.Tensor, f: torch.Tensor, p_target: torch.Tensor, prec=None, povm=None,
+                          with_grad_matrix: bool = True):
+    """likelihood_forward plus F_c = (sum_k sqrt(p_k p_target_k))^2 of the
+    model's distribution against p_target (qst_likelihood_fc; in the fused
+    last pass where the plan has one).  Returns (out, tau, G, bad, fc), fc a
+    0-dim float64 device tensor."""
+    n, ld = _matrix(T, "T")
+    pr = _prec(T.dtype, prec)
+    _vector(f, "f", n, real_dtype(pr))
+    _vector(p_target, "p_target", n, real_dtype(pr))
+    out = torch.empty(2, dtype=torch.float64, device=T.device)
+    bad = torch.empty(2, dtype=torch.int64, device=T.device)
+    tau = torch.empty((), dtype=torch.float64, device=T.device)
+    fc = torch.empty((), dtype=torch.float64, device=T.device)
+    G = torch.empty(T.shape, dtype=T.dtype, device=T.device) if with_grad_matrix else None
+    ws, nb = _workspace(n, pr, QST_OP_LIKELIHOOD, T.device)
+    _lib.check(_lib.lib().qst_likelihood_fc(n, pr, T.data_ptr(), ld, f.data_ptr(), p_target.data_ptr(),
+                                            _povm_arg(povm), tau.data_ptr(), out.data_ptr(), fc.data_ptr(),
+                                            bad.data_ptr(), _ptr(G), 0 if G is None else G.stride(0), _ptr(ws), nb,
+                                            _stream(T.device)), "qst_likelihood_fc")
+    return out, tau, G, bad, fc
 
 
 def grad_product(G: torch.Tensor, T: torch.Tensor, tau: torch.Tensor, prec=None,

@@ -353,9 +353,7 @@ hipError_t run_fidelity_lowrank(const void* T, int64_t ldT, const void* W, int64
 }
 
 template <typename R>
-hipError_t run_fidelity_classical(const void* ph, const void* p, int n, void* ws, double* F, hipStream_t s) {
-  const FidelityLayout fl = fidelity_layout(n);
-  double* part = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + fl.cpart);
+hipError_t run_fidelity_classical(const void* ph, const void* p, int n, double* part, double* F, hipStream_t s) {
   fid_classical_partial_kernel<R><<<kReduceBlocks, 256, 0, s>>>(static_cast<const R*>(ph), static_cast<const R*>(p),
                                                                 int64_t(1) << (2 * n), part);
   hipError_t e = hipGetLastError();
@@ -374,8 +372,14 @@ hipError_t launch_fidelity_lowrank(qst_prec prec, const void* T, int64_t ldT, co
 
 hipError_t launch_fidelity_classical(qst_prec prec, const void* ph, const void* p, int n, void* ws, double* F,
                                      hipStream_t s) {
-  if (prec == QST_F64) return run_fidelity_classical<double>(ph, p, n, ws, F, s);
-  return run_fidelity_classical<float>(ph, p, n, ws, F, s);
+  double* part = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + fidelity_layout(n).cpart);
+  return launch_fidelity_classical_part(prec, ph, p, n, part, F, s);
+}
+
+hipError_t launch_fidelity_classical_part(qst_prec prec, const void* ph, const void* p, int n, double* part, double* F,
+                                          hipStream_t s) {
+  if (prec == QST_F64) return run_fidelity_classical<double>(ph, p, n, part, F, s);
+  return run_fidelity_classical<float>(ph, p, n, part, F, s);
 }
 
 }  // namespace qst

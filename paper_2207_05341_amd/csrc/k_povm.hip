@@ -119,7 +119,8 @@ hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const do
 hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W, const double* V, bool tetra,
                              const void* rho, int64_t ld_rho, const void* fvec, const double* Fpart, void* G,
                              int64_t ldG, void* inter0, void* inter1, double* part, double* nll_dev,
-                             unsigned long long* bad_dev, bool pass0_done, hipStream_t s) {
+                             unsigned long long* bad_dev, bool pass0_done, hipStream_t s, const void* pt,
+                             double* fc_dev) {
   static const char* kFwd[4] = {"povm_fwd_p0", "povm_fwd_p1", "povm_fwd_p2", "povm_fwd_p3"};
   static const char* kAdj[4] = {"povm_adj_p0", "povm_adj_p1", "povm_adj_p2", "povm_adj_p3"};
   ModeMatrix Af, Aa;
@@ -154,11 +155,13 @@ hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W,
     a.f = fvec;
     a.Fpart = Fpart;
     a.part = part;
+    a.pt = pt;
     const int64_t nb = povm_pass_blocks(pl, P - 1);
     ProfScope prof("povm_fused", s);
     if (!launch_fused_fast(prec, tetra, a, Af, Aa, nb, s, &e)) return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
-    if ((e = launch_likelihood_finish(part, int(nb), Fpart, nll_dev, bad_dev, s)) != hipSuccess) return e;
+    if ((e = launch_likelihood_finish(part, int(nb), Fpart, nll_dev, bad_dev, s, pt ? fc_dev : nullptr)) != hipSuccess)
+      return e;
   }
   if (!G) return hipSuccess;
   for (int j = P - 2; j >= 0; --j) {

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void kd_pass(PassArgs a, ModeMatrix A) {
 // address a workgroup writes is one it alone has read, and all its reads
 // precede its first write by a barrier).
 // ---------------------------------------------------------------------------
-template <typename R, bool TETRA, int G, int J>
+template <typename R, bool TETRA, int G, int J, bool FC = false>
 __global__ __launch_bounds__(256, 2) void kd_fused_pass(PassArgs a, ModeMatrix Af, ModeMatrix Aa) {
   __shared__ Cx<R> lds[J << (2 * G)];
   __shared__ double red[4];
@@ -76,12 +76,16 @@ __global__ __launch_bounds__(256, 2) void kd_fused_pass(PassArgs a, ModeMatrix A
     if (threadIdx.x == 0) Fsh = Fsum;
     __syncthreads();
   }
-  double L = 0.0, bad0 = 0.0, bad1 = 0.0;
-  fast_pass::kd_fused_body<R, TETRA, G, J>(a, Af, Aa, lb, threadIdx.x, lds, true, Fsh, L, bad0, bad1);
+  double L = 0.0, bad0 = 0.0, bad1 = 0.0, fc = 0.0;
+  fast_pass::kd_fused_body<R, TETRA, G, J, FC>(a, Af, Aa, lb, threadIdx.x, lds, true, Fsh, L, bad0, bad1, &fc);
   // per-workgroup partial sums in a fixed order, slot = logical index
   const int64_t nb = gridDim.x;
   double v = block_sum256(L, red);
   if (threadIdx.x == 0) a.part[lb] = v;
+  if constexpr (FC) {
+    v = block_sum256(fc, red);
+    if (threadIdx.x == 0) a.part[nb + lb] = v;
+  }
   v = block_sum256(bad0, red);
   if (threadIdx.x == 0) a.part[2 * nb + lb] = v;
   v = block_sum256(bad1, red);
@@ -96,7 +100,9 @@ bool launch_fused_fast(qst_prec prec, bool tetra, const PassArgs& a, const ModeM
   const unsigned grid = unsigned(blocks);
 #define QST_FU(R, G, J)                                                              \
   do {                                                                               \
-    if (tetra) kd_fused_pass<R, true, G, J><<<grid, 256, 0, s>>>(a, Af, Aa);         \
+    if (a.pt && tetra) kd_fused_pass<R, true, G, J, true><<<grid, 256, 0, s>>>(a, Af, Aa);   \
+    else if (a.pt) kd_fused_pass<R, false, G, J, true><<<grid, 256, 0, s>>>(a, Af, Aa);     \
+    else if (tetra) kd_fused_pass<R, true, G, J><<<grid, 256, 0, s>>>(a, Af, Aa);    \
     else kd_fused_pass<R, false, G, J><<<grid, 256, 0, s>>>(a, Af, Aa);              \
   } while (0)
   const int g = a.g, J = a.J;

@@ -227,9 +227,16 @@ __global__ __launch_bounds__(256) void nll_finish_kernel(const double* __restric
 __global__ __launch_bounds__(256) void likelihood_finish_kernel(const double* __restrict__ part, int nb,
                                                                 const double* __restrict__ Fpart,
                                                                 double* __restrict__ nll,
-                                                                unsigned long long* __restrict__ bad) {
+                                                                unsigned long long* __restrict__ bad,
+                                                                double* __restrict__ fc) {
   __shared__ double red[4];
   double sums[4];
+  if (fc) {  // F_c = (sum of the F_c terms)^2 from slot 1
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[int64_t(nb) + b];
+    acc = block_sum256(acc, red);
+    if (threadIdx.x == 0) fc[0] = acc * acc;
+  }
   for (int i = 0; i < 4; ++i) {
     if (i == 1) {
       sums[1] = sum_partials256(Fpart, kReduceBlocks, red);
@@ -302,8 +309,8 @@ hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double
 }
 
 hipError_t launch_likelihood_finish(const double* part, int nb, const double* Fpart, double* nll_dev,
-                                   unsigned long long* bad_dev, hipStream_t s) {
-  likelihood_finish_kernel<<<1, 256, 0, s>>>(part, nb, Fpart, nll_dev, bad_dev);
+                                   unsigned long long* bad_dev, hipStream_t s, double* fc_dev) {
+  likelihood_finish_kernel<<<1, 256, 0, s>>>(part, nb, Fpart, nll_dev, bad_dev, fc_dev);
   return hipGetLastError();
 }
 

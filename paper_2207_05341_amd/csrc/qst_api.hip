@@ -39,6 +39,10 @@ hipError_t run_state_map(qst_prec prec, const void* T, int64_t ldT, void* rho, i
   return launch_herk(prec, T, ldT, rho, ldr, n, fold ? partials : nullptr, tau_dev, sk, s, x0, planes);
 }
 
+qst_status likelihood_impl(int n, qst_prec prec, const void* T, int64_t ldT, const void* f, const double* povm_host,
+                           double* tau_dev, double* nll_dev, unsigned long long* bad_dev, void* G, int64_t ldG,
+                           void* ws, size_t ws_bytes, void* stream, const void* pt, double* fc_dev);
+
 }  // namespace
 
 extern "C" {
@@ -336,6 +340,29 @@ qst_status qst_likelihood(int n, qst_prec prec, const void* T, int64_t ldT, cons
                           const double* povm_host, double* tau_dev, double* nll_dev,
                           unsigned long long* bad_dev, void* G, int64_t ldG, void* ws, size_t ws_bytes,
                           void* stream) {
+  return likelihood_impl(n, prec, T, ldT, f, povm_host, tau_dev, nll_dev, bad_dev, G, ldG, ws, ws_bytes, stream,
+                         nullptr, nullptr);
+}
+
+qst_status qst_likelihood_fc(int n, qst_prec prec, const void* T, int64_t ldT, const void* f, const void* p_target,
+                             const double* povm_host, double* tau_dev, double* nll_dev, double* fc_dev,
+                             unsigned long long* bad_dev, void* G, int64_t ldG, void* ws, size_t ws_bytes,
+                             void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_ptr(p_target, "p_target", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(fc_dev, "fc_dev", msg)) != QST_OK) return fail(st, msg);
+  return likelihood_impl(n, prec, T, ldT, f, povm_host, tau_dev, nll_dev, bad_dev, G, ldG, ws, ws_bytes, stream,
+                         p_target, fc_dev);
+}
+
+}  // extern "C"
+
+namespace {
+
+qst_status likelihood_impl(int n, qst_prec prec, const void* T, int64_t ldT, const void* f, const double* povm_host,
+                           double* tau_dev, double* nll_dev, unsigned long long* bad_dev, void* G, int64_t ldG,
+                           void* ws, size_t ws_bytes, void* stream, const void* pt, double* fc_dev) {
   std::string msg;
   qst_status st;
   if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
@@ -369,7 +396,7 @@ qst_status qst_likelihood(int n, qst_prec prec, const void* T, int64_t ldT, cons
   if (fused) {
     e = launch_povm_fused(prec, pl, W, V, tetra, rho, d, f, partials + kReduceBlocks, G, ldG, ws_at(ws, L.inter0),
                           ws_at(ws, L.inter1), reinterpret_cast<double*>(ws_at(ws, L.fpart)), nll_dev, bad_dev, x0,
-                          s);
+                          s, pt, fc_dev);
     if (e != hipSuccess) return hip_fail(e, "fused POVM / likelihood passes");
   } else {
     void* p = ws_at(ws, L.p);
@@ -377,6 +404,10 @@ qst_status qst_likelihood(int n, qst_prec prec, const void* T, int64_t ldT, cons
     if (e != hipSuccess) return hip_fail(e, "POVM map");
     e = launch_nll(prec, p, f, n, partials, nll_dev, bad_dev, s);
     if (e != hipSuccess) return hip_fail(e, "NLL reduction");
+    if (pt) {
+      e = launch_fidelity_classical_part(prec, p, pt, n, partials, fc_dev, s);
+      if (e != hipSuccess) return hip_fail(e, "classical fidelity");
+    }
     if (G) {
       e = launch_povm(true, prec, pl, V, tetra, G, ldG, p, f, nll_dev + 1, ws_at(ws, L.inter0), ws_at(ws, L.inter1), s);
       if (e != hipSuccess) return hip_fail(e, "adjoint POVM map");
@@ -385,6 +416,10 @@ qst_status qst_likelihood(int n, qst_prec prec, const void* T, int64_t ldT, cons
   clear_error();
   return QST_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 qst_status qst_grad_product(int n, qst_prec prec, const void* G, int64_t ldG, const void* T, int64_t ldT,
                             const double* tau_dev, const double* upstream_dev, void* gradT, int64_t ld_grad,

@@ -44,6 +44,9 @@ hipError_t launch_rprop(qst_prec prec, int64_t count, void* w, const void* g, vo
 // Fidelities (workspace laid out by fidelity_layout).
 hipError_t launch_fidelity_lowrank(qst_prec prec, const void* T, int64_t ldT, const void* W, int64_t ldW, int r,
                                    int n, void* ws, double* F, hipStream_t s);
+// F_c with the kReduceBlocks partials at part.
+hipError_t launch_fidelity_classical_part(qst_prec prec, const void* ph, const void* p, int n, double* part, double* F,
+                                          hipStream_t s);
 hipError_t launch_fidelity_classical(qst_prec prec, const void* ph, const void* p, int n, void* ws, double* F,
                                      hipStream_t s);
 
@@ -109,18 +112,21 @@ hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double
 // *F_dev = sum f.
 // Stage 2 of qst_likelihood's NLL: L and counters from the fused pass's
 // partials [4][nb]; F from the kReduceBlocks F partials of launch_tau.
+// With fc_dev, also F_c = (sum of the F_c terms in slot 1)^2.
 hipError_t launch_likelihood_finish(const double* part, int nb, const double* Fpart, double* nll_dev,
-                                   unsigned long long* bad_dev, hipStream_t s);
+                                   unsigned long long* bad_dev, hipStream_t s, double* fc_dev = nullptr);
 
 // The POVM part of qst_likelihood when fused_likelihood(pl, prec): forward
 // passes 0..P-2 (from pass 1 when pass0_done: its output is already in
 // inter0), the fused last pass (+ NLL finish into nll_dev / bad_dev), and, if
 // G is not NULL, the adjoint passes P-2..0.  part: FP64 partials [4][blocks
-// of the last pass]; Fpart: the kReduceBlocks F partials.
+// of the last pass]; Fpart: the kReduceBlocks F partials.  With pt (4^N
+// reals), the last pass also forms F_c against pt into fc_dev.
 hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W, const double* V, bool tetra,
                              const void* rho, int64_t ld_rho, const void* fvec, const double* Fpart, void* G,
                              int64_t ldG, void* inter0, void* inter1, double* part, double* nll_dev,
-                             unsigned long long* bad_dev, bool pass0_done, hipStream_t s);
+                             unsigned long long* bad_dev, bool pass0_done, hipStream_t s, const void* pt = nullptr,
+                             double* fc_dev = nullptr);
 
 hipError_t launch_fsum(qst_prec prec, const void* f, int n, double* partials, double* F_dev,
                        hipStream_t s);

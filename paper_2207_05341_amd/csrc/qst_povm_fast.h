@@ -251,11 +251,13 @@ __device__ __forceinline__ void kd_pass_body(const PassArgs& a, const ModeMatrix
 // the sum of f; the NLL terms and the bad-entry counts of the chunk are
 // added to L, bad0, bad1.  Reads X = a.out and writes the adjoint
 // intermediate in place.  Inactive (a padding call): the same loads,
-// rounds and barriers, nothing stored or counted.
-template <typename R, bool TETRA, int G, int J>
+// rounds and barriers, nothing stored or counted.  FC: the classical
+// fidelity terms sqrt(max(p_k, 0) max(pt_k, 0)) against a.pt are added to
+// *fc (pt read where p_k is in registers).
+template <typename R, bool TETRA, int G, int J, bool FC = false>
 __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatrix& Af, const ModeMatrix& Aa, int64_t lb,
                                               unsigned tid, Cx<R> (&lds)[J << (2 * G)], bool active, double F,
-                                              double& L, double& bad0, double& bad1) {
+                                              double& L, double& bad0, double& bad1, double* fc = nullptr) {
   constexpr int TILE = 1 << (2 * G);
   constexpr int NB = TILE * J / 16;
   constexpr int BPT = NB / 256;
@@ -334,6 +336,13 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
             }
           }
           if (active && (pk != pk || fk != fk)) bad1 += 1.0;
+          if constexpr (FC) {
+            if (active) {
+              const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
+              const double qk = double(static_cast<const R*>(a.pt)[int64_t(kg) * kd + kd0 + j]);
+              *fc += sqrt((pk > 0.0 ? pk : 0.0) * (qk > 0.0 ? qk : 0.0));
+            }
+          }
           x[m] = Cx<R>{cotangent(F, fr, pr), R(0)};
         }
         contract16<R, true, TETRA>(x, RD::opA[rd], RD::opB[rd], Aa);

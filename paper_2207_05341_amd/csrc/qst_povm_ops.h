@@ -28,7 +28,8 @@ struct PassArgs {
   const void* f;        // adjoint / fused last pass: frequencies
   const double* F;      // adjoint, last pass: F = sum f
   const double* Fpart;  // fused last pass: kReduceBlocks FP64 partial sums of F = sum f
-  double* part;         // fused last pass: FP64 partials [4][blocks] (L, -, bad0, bad1)
+  double* part;         // fused last pass: FP64 partials [4][blocks] (L, F_c terms, bad0, bad1)
+  const void* pt;       // fused last pass: target distribution of F_c, or NULL
   int64_t ld;           // row stride of the matrix (rho or G')
   int n, U, g, J;
 };

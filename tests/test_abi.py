@@ -281,6 +281,21 @@ def test_abs_map_validation(L):
     assert bwd(nb=0) == lib_mod.QST_ERR_WORKSPACE
 
 
+def test_likelihood_fc_validation(L):
+    n, d = 7, 128
+    ws = lib_mod.workspace_bytes(n, 1, lib_mod.QST_OP_LIKELIHOOD)
+    W, F = ctypes.c_void_p(0x30000), ctypes.c_void_p(0x40000)
+
+    def call(T=FAKE, f=FAKE2, pt=ctypes.c_void_p(0x50000), fc=ctypes.c_void_p(0x60000), nb=ws):
+        return L.qst_likelihood_fc(n, 1, T, d, f, pt, None, F, F, fc, None, None, 0, W, nb, None)
+
+    assert call(pt=None) == lib_mod.QST_ERR_INVALID_ARG and "p_target" in _err(L)
+    assert call(fc=None) == lib_mod.QST_ERR_INVALID_ARG and "fc_dev" in _err(L)
+    assert call(T=None) == lib_mod.QST_ERR_INVALID_ARG and "T is NULL" in _err(L)
+    assert call(f=None) == lib_mod.QST_ERR_INVALID_ARG and "f is NULL" in _err(L)
+    assert call(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
+
+
 def test_fidelity_general_validation(L):
     n, d = 5, 32
     ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_ABS_MAP)

@@ -121,3 +121,55 @@ def test_fidelity_general_against_oracle(prec, n):
         assert abs(got - want) <= tol * want, (name, got, want)
     F1, _ = qst.fidelity_general(Tg, dev_matrix(rho_hat.astype(ctype(prec))), prec)
     assert abs(float(F1.item()) - 1.0) <= max(TOL[prec], 1e-9 * d)
+
+
+@pytest.mark.parametrize("prec,n,rot", [("f64", 4, False), ("f64", 7, False), ("f32", 7, True), ("f32", 8, False),
+                                        ("f64", 8, True)])
+def test_likelihood_fc_against_oracle(prec, n, rot):
+    """qst_likelihood_fc: F_c (Eq. F_CF) of the model's distribution against
+    a target distribution, formed in the fused last pass (N >= 7; N = 4 from
+    the stored p), against the oracle's fidelity_c of the oracle's p; L, F
+    and G bitwise those of qst_likelihood.  rot: a rotated tetrahedral POVM
+    (the general-POVM form of the fused pass)."""
+    d = 1 << n
+    g = S.rng(7460 + n)
+    povm = None
+    if rot:
+        U, _ = np.linalg.qr(S.ginibre(g, 2))
+        povm = np.array([U @ m @ U.conj().T for m in O.tetrahedral_povm()])
+    T = S.ginibre(g, d).astype(ctype(prec))
+    rt = np.float64 if prec == "f64" else np.float32
+    psi = S.haar_vector(g, d)
+    f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.2), povm)).astype(rt)
+    pt = O.probs_real(S.depolarised_pure(psi, 0.1), povm).astype(rt)
+    pt[:5] = 0.0
+    p_hat = O.probs_real(O.state_map(T.astype(np.complex128))[0], povm)
+    want = O.fidelity_c(p_hat, pt.astype(np.float64))
+    Tg = torch.from_numpy(T).to(DEV)
+    fg, ptg = torch.from_numpy(f).to(DEV), torch.from_numpy(pt).to(DEV)
+    out, tau, G, bad, fc = qst.likelihood_forward_fc(Tg, fg, ptg, prec, povm)
+    out0, tau0, G0, bad0 = qst.likelihood_forward(Tg, fg, prec, povm)
+    torch.cuda.synchronize()
+    got = float(fc.item())
+    say(f"N={n} {prec} rot={rot}: F_c {got:.12f} oracle {want:.12f}")
+    assert abs(got - want) <= TOL[prec] * want
+    assert torch.equal(out, out0) and torch.equal(tau, tau0) and torch.equal(G, G0) and torch.equal(bad, bad0)
+
+
+def test_likelihood_fc_n11_equals_two_calls():
+    """N = 11, FP32: F_c from the fused pass against the library's route
+    with p stored (qst_povm_probs of qst_state_map, then
+    qst_fidelity_classical)."""
+    n, d = 11, 2048
+    g = S.rng(7470)
+    T = torch.from_numpy(S.ginibre(g, d).astype(np.complex64)).to(DEV)
+    f = torch.from_numpy(S.multinomial_freqs(g, 10_000_000, S.porter_thomas_probs(g, 4 ** n, 0.1))
+                         .astype(np.float32)).to(DEV)
+    pt = torch.from_numpy(S.porter_thomas_probs(g, 4 ** n, 0.2).astype(np.float32)).to(DEV)
+    _, _, _, _, fc = qst.likelihood_forward_fc(T, f, pt, "f32")
+    rho, _ = qst.state_map(T, "f32")
+    p = qst.povm_probs(rho, "f32")
+    F2 = qst.fidelity_classical(p, pt, "f32")
+    a, b = float(fc.item()), float(F2.item())
+    say(f"N=11 f32: F_c fused {a:.10f}, two calls {b:.10f}")
+    assert abs(a - b) <= 1e-5 * b
