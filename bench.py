@@ -239,10 +239,12 @@ def state_maps(qst, T, f, prec, reps=50):
     return out
 
 
-def fidelities(qst, T, prec, reps=20):
+def fidelities(qst, T, prec, reps=20, f=None):
     """Fidelity calls at the bench size: F_q against a rank-8 target (as in
     the training workload; three launches, reading T once) and F_c between
-    two 4^N probability vectors.  Achieved GB/s from algorithmic bytes."""
+    two 4^N probability vectors.  Achieved GB/s from algorithmic bytes.
+    With f: the likelihood forward with F_c fused into its last pass
+    (qst_likelihood_fc) against the plain forward (qst_likelihood)."""
     import numpy as np
     import torch
 
@@ -269,6 +271,22 @@ def fidelities(qst, T, prec, reps=20):
         us = 1e3 * ev0.elapsed_time(ev1) / reps
         gbs = nbytes / (us * 1e-6) / 1e9
         out[key] = {"us": round(us, 2), "GB_s": round(gbs, 1), "hbm_frac": round(gbs / 8000.0, 3)}
+    if f is not None:
+        ms = {}
+        for key, fn in (("plain", lambda: qst.likelihood_forward(T, f, prec)),
+                        ("with_fc", lambda: qst.likelihood_forward_fc(T, f, pb, prec))):
+            for _ in range(3):
+                fn()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(reps):
+                fn()
+            ev1.record()
+            torch.cuda.synchronize()
+            ms[key] = ev0.elapsed_time(ev1) / reps
+        out["classical_fused"] = {"likelihood_forward_us": round(1e3 * ms["plain"], 1),
+                                  "with_fc_us": round(1e3 * ms["with_fc"], 1),
+                                  "added_us": round(1e3 * (ms["with_fc"] - ms["plain"]), 1)}
     return out
 
 
@@ -615,7 +633,7 @@ def main():
 
     Tm, fm = to_prec(T_np, f_np, args.prec, dev)
     modes = state_maps(qst, Tm, fm, args.prec)
-    fids = fidelities(qst, Tm, args.prec)
+    fids = fidelities(qst, Tm, args.prec, f=fm)
     net = network(qst, fm, args.prec, long_run=not args.no_long)
     absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
     del Tm, fm
