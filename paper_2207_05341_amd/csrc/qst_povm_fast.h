@@ -252,8 +252,8 @@ __device__ __forceinline__ void kd_pass_body(const PassArgs& a, const ModeMatrix
 // added to L, bad0, bad1.  Reads X = a.out and writes the adjoint
 // intermediate in place.  Inactive (a padding call): the same loads,
 // rounds and barriers, nothing stored or counted.  FC: the classical
-// fidelity terms sqrt(max(p_k, 0) max(pt_k, 0)) against a.pt are added to
-// *fc (pt read where p_k is in registers).
+// fidelity terms sqrt(max(p_k, 0) max(pt_k, 0)) against a.pt (loaded with
+// f) are added to *fc, the square root in the storage precision.
 template <typename R, bool TETRA, int G, int J, bool FC = false>
 __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatrix& Af, const ModeMatrix& Aa, int64_t lb,
                                               unsigned tid, Cx<R> (&lds)[J << (2 * G)], bool active, double F,
@@ -274,6 +274,7 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
   // f for the outcomes of the last round, loaded now so that it arrives
   // while the forward rounds run
   R fpre[BPT][16];
+  R qpre[BPT][FC ? 16 : 1];  // F_c target, same positions as f
   {
     constexpr int rl = RD::n - 1;
 #pragma unroll
@@ -285,6 +286,7 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
       for (int m = 0; m < 16; ++m) {
         const int kg = u + ((m >> 2) << (2 * RD::bA[rl])) + ((m & 3) << (2 * RD::bB[rl]));
         fpre[bi][m] = f[int64_t(kg) * kd + kd0 + j];
+        if constexpr (FC) qpre[bi][m] = static_cast<const R*>(a.pt)[int64_t(kg) * kd + kd0 + j];
       }
     }
   }
@@ -337,11 +339,10 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
           }
           if (active && (pk != pk || fk != fk)) bad1 += 1.0;
           if constexpr (FC) {
-            if (active) {
-              const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
-              const double qk = double(static_cast<const R*>(a.pt)[int64_t(kg) * kd + kd0 + j]);
-              *fc += sqrt((pk > 0.0 ? pk : 0.0) * (qk > 0.0 ? qk : 0.0));
-            }
+            // the square root in the storage precision, the sum in FP64
+            const R qk = qpre[bi][m];
+            const R zero = R(0);
+            if (active) *fc += double(sqrt((pr > zero ? pr : zero) * (qk > zero ? qk : zero)));
           }
           x[m] = Cx<R>{cotangent(F, fr, pr), R(0)};
         }
