@@ -194,8 +194,10 @@ qst_status qst_likelihood(int n_qubits, qst_prec prec, const void* T, int64_t ld
  * Where qst_likelihood fuses its last POVM pass (N >= 7 with the fused
  * plan), the terms are formed in that pass from the p_k it holds in
  * registers (one more read of 4^N reals, p still never stored); otherwise
- * from the stored p.  L, F, the counters and G are those of qst_likelihood
- * (bitwise).
+ * from the stored p.  tau, F and the counters are those of qst_likelihood
+ * bitwise; L and G agree with it to rounding (the fused pass with F_c is a
+ * kernel instance of its own, and its FP64 sums may contract into FMAs
+ * differently).
  *   p_target [in]  4^N reals (storage precision of f), device; read as
  *                  given (not renormalised).
  *   fc_dev   [out] one double, device.

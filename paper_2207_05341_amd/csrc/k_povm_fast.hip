@@ -65,8 +65,10 @@ __global__ __launch_bounds__(256) void kd_pass(PassArgs a, ModeMatrix A) {
 // address a workgroup writes is one it alone has read, and all its reads
 // precede its first write by a barrier).
 // ---------------------------------------------------------------------------
+// The F_c form holds the target's values besides the rest and would spill
+// at two workgroups per CU; it runs at one.
 template <typename R, bool TETRA, int G, int J, bool FC = false>
-__global__ __launch_bounds__(256, 2) void kd_fused_pass(PassArgs a, ModeMatrix Af, ModeMatrix Aa) {
+__global__ __launch_bounds__(256, FC ? 1 : 2) void kd_fused_pass(PassArgs a, ModeMatrix Af, ModeMatrix Aa) {
   __shared__ Cx<R> lds[J << (2 * G)];
   __shared__ double red[4];
   __shared__ double Fsh;

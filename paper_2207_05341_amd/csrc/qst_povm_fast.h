@@ -252,8 +252,9 @@ __device__ __forceinline__ void kd_pass_body(const PassArgs& a, const ModeMatrix
 // added to L, bad0, bad1.  Reads X = a.out and writes the adjoint
 // intermediate in place.  Inactive (a padding call): the same loads,
 // rounds and barriers, nothing stored or counted.  FC: the classical
-// fidelity terms sqrt(max(p_k, 0) max(pt_k, 0)) against a.pt (loaded with
-// f) are added to *fc, the square root in the storage precision.
+// fidelity terms sqrt(max(p_k, 0) max(pt_k, 0)) against a.pt (loaded
+// before the last round's contraction) are added to *fc, the square root in
+// the storage precision.
 template <typename R, bool TETRA, int G, int J, bool FC = false>
 __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatrix& Af, const ModeMatrix& Aa, int64_t lb,
                                               unsigned tid, Cx<R> (&lds)[J << (2 * G)], bool active, double F,
@@ -274,7 +275,6 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
   // f for the outcomes of the last round, loaded now so that it arrives
   // while the forward rounds run
   R fpre[BPT][16];
-  R qpre[BPT][FC ? 16 : 1];  // F_c target, same positions as f
   {
     constexpr int rl = RD::n - 1;
 #pragma unroll
@@ -286,7 +286,6 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
       for (int m = 0; m < 16; ++m) {
         const int kg = u + ((m >> 2) << (2 * RD::bA[rl])) + ((m & 3) << (2 * RD::bB[rl]));
         fpre[bi][m] = f[int64_t(kg) * kd + kd0 + j];
-        if constexpr (FC) qpre[bi][m] = static_cast<const R*>(a.pt)[int64_t(kg) * kd + kd0 + j];
       }
     }
   }
@@ -324,6 +323,19 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
           x[m] = lds[((r << G) | c) * J + j];
         }
       }
+      // F_c target of this block's outcomes (last round only), loaded here
+      // so that the forward contraction covers part of its latency and only
+      // these 16 values stay live (a prefetch with f measured slower)
+      R qk[FC ? 16 : 1];
+      if constexpr (FC) {
+        if (last) {
+#pragma unroll
+          for (int m = 0; m < 16; ++m) {
+            const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
+            qk[m] = static_cast<const R*>(a.pt)[int64_t(kg) * kd + kd0 + j];
+          }
+        }
+      }
       contract16<R, false, TETRA>(x, RD::opA[rd], RD::opB[rd], Af);
       if (last) {
 #pragma unroll
@@ -340,9 +352,8 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
           if (active && (pk != pk || fk != fk)) bad1 += 1.0;
           if constexpr (FC) {
             // the square root in the storage precision, the sum in FP64
-            const R qk = qpre[bi][m];
             const R zero = R(0);
-            if (active) *fc += double(sqrt((pr > zero ? pr : zero) * (qk > zero ? qk : zero)));
+            if (active) *fc += double(sqrt((pr > zero ? pr : zero) * (qk[m] > zero ? qk[m] : zero)));
           }
           x[m] = Cx<R>{cotangent(F, fr, pr), R(0)};
         }

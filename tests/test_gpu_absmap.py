@@ -228,3 +228,23 @@ def test_abs_map_warm_start(prec):
         assert abs(Lw - Lc) <= TOL[prec] * abs(Lc) and rel_fro(gw, gc) <= 10 * TOL[prec]
         if k:
             assert proj.sweeps < sw_c
+
+
+def test_abs_map_non_finite_input_is_an_error():
+    """A NaN in T makes the off-diagonal norm non-finite after the first
+    sweep: qst_abs_map and qst_fidelity_general return QST_ERR_INVALID_ARG
+    (raised as QstError) instead of a result."""
+    d = 16
+    g = S.rng(8800)
+    T = S.ginibre(g, d)
+    T[3, 5] = np.nan
+    Tg = torch.from_numpy(T).to(DEV)
+    with pytest.raises(qst.QstError, match="did not converge"):
+        qst.abs_map(Tg, 1.5, "f64")
+    rho = torch.eye(d, dtype=torch.complex128, device=DEV) / d
+    with pytest.raises(qst.QstError, match="did not converge"):
+        qst.fidelity_general(Tg, rho, "f64")
+    # the library stays usable
+    T[3, 5] = 0.0
+    A, _, _, sweeps = qst.abs_map(torch.from_numpy(T).to(DEV), 1.5, "f64")
+    assert sweeps > 0 and rel_fro(A.cpu().numpy(), O.abs_map(T, 1.5)[0]) <= TOL["f64"]
