@@ -260,7 +260,8 @@ qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X
  * P-order absolute projection; P = 2 is Chol_H (Eq. unified_DP).
  * The eigendecomposition is a cyclic two-sided Jacobi method in FP64 on the
  * device, whatever prec; the call synchronises the stream once per sweep
- * (it reads the off-diagonal norm on the host to stop).
+ * (it reads the off-diagonal norm on the host to stop: at 1e-14 of ||H||_F
+ * for QST_F64, 1e-10 for the FP32-storage precisions).
  *   P      [in]  finite, >= 0.
  *   T      [in]  d x d complex (prec's storage type), row stride ldT, device.
  *   Q0     [in]  NULL, or a warm start: a unitary d x d complex FP64 matrix

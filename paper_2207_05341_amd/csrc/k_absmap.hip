@@ -21,9 +21,9 @@
 // rotation angle (tangent t of the smaller root of t^2 + 2 zeta t - 1 = 0,
 // zeta = (b - a) / (2 |c|)) diagonalises it.  After each sweep (d - 1
 // rounds) the host reads the off-diagonal norm; sweeps stop when it is
-// below 1e-14 of ||H||_F, or below 1e-10 of it and no longer falling by
-// half (the rounding floor), which Jacobi's quadratic convergence reaches
-// in a few sweeps.
+// below 1e-14 of ||H||_F (1e-10 for FP32 storage), or below 1e-10 of it
+// and no longer falling by half (the rounding floor), which Jacobi's
+// quadratic convergence reaches in a few sweeps.
 //
 // Adjoint: for a spectral function A = g(H), g(l) = |l|^(P/2), the
 // first-order change is Q (Gamma o (Q^dagger dH Q)) Q^dagger with Gamma the
@@ -350,10 +350,16 @@ hipError_t store_out(qst_prec prec, const C64* X, void* Y, int64_t ldy, int n, h
   return hipGetLastError();
 }
 
+// Relative off-diagonal norm at which the sweeps stop: 1e-14 for FP64
+// storage; 1e-10 for FP32 storage, whose outputs are rounded to 6e-8
+// (eigenvalue errors are second order in it, A's and the adjoint's first
+// order).
+double sweep_tol(qst_prec prec) { return prec == QST_F64 ? 1e-14 : 1e-10; }
+
 // Jacobi sweeps on *cur (ping-pong with *nxt; V^T rotated in b.b2) until
 // the stopping rule holds; on return *cur holds the diagonalised matrix and
 // *sweeps the sweeps taken, or -1 (non-finite or not converged).
-hipError_t jacobi_sweeps(const Bufs& b, int n, C64*& cur, C64*& nxt, hipStream_t s, int* sweeps) {
+hipError_t jacobi_sweeps(const Bufs& b, int n, C64*& cur, C64*& nxt, hipStream_t s, int* sweeps, double tol) {
   *sweeps = -1;
   const int d = 1 << n, half = d >> 1;
   const int chunks = (half + kRoundThreads - 1) / kRoundThreads;
@@ -373,7 +379,7 @@ hipError_t jacobi_sweeps(const Bufs& b, int n, C64*& cur, C64*& nxt, hipStream_t
     const double off = host[0], tot = host[0] + host[1];
     if (!std::isfinite(off) || !std::isfinite(tot)) return hipSuccess;
     const double r = tot > 0.0 ? std::sqrt(off / tot) : 0.0;
-    if (r <= 1e-14 || (r <= 1e-10 && r > 0.5 * prev)) {
+    if (r <= tol || (r <= 1e-10 && r > 0.5 * prev)) {
       *sweeps = sweep;
       return hipSuccess;
     }
@@ -447,7 +453,7 @@ hipError_t launch_fidelity_general(qst_prec prec, int n, const void* T, int64_t 
   identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   C64 *cur = b.b0, *nxt = b.b1;
-  if ((e = jacobi_sweeps(b, n, cur, nxt, s, sweeps)) != hipSuccess) return e;
+  if ((e = jacobi_sweeps(b, n, cur, nxt, s, sweeps, sweep_tol(prec))) != hipSuccess) return e;
   if (*sweeps < 0) return hipSuccess;
   fq_finish_kernel<<<1, 256, 0, s>>>(cur, d, b.scal + 4, F);
   return hipGetLastError();
@@ -474,7 +480,7 @@ hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   C64 *cur = b.b0, *nxt = b.b1;
-  if ((e = jacobi_sweeps(b, n, cur, nxt, s, sweeps)) != hipSuccess) return e;
+  if ((e = jacobi_sweeps(b, n, cur, nxt, s, sweeps, sweep_tol(prec))) != hipSuccess) return e;
   if (*sweeps < 0) return hipSuccess;
   // cur holds Lambda on its diagonal, b.b2 = V^T; the other buffer is free.
   double* sc = b.part;  // |lam|^(P/4), d values

@@ -74,7 +74,9 @@ def test_abs_map_against_oracle(prec, n):
         say(f"N={n} {prec} P={P}: sweeps {sweeps}, {1e3 * dt:.1f} ms, A rel err {e:.2e}")
         assert e <= TOL[prec], (P, e)
         assert np.abs(Qn.conj().T @ Qn - np.eye(d)).max() <= 1e-13 * d
-        assert rel_fro((Qn * ln) @ Qn.conj().T, H) <= 1e-13
+        # the sweeps stop at an off-diagonal norm of 1e-14 (FP64) or 1e-10
+        # (FP32 storage) of ||H||
+        assert rel_fro((Qn * ln) @ Qn.conj().T, H) <= (1e-13 if prec == "f64" else 1e-9)
         assert np.abs(np.sort(ln) - lam_w).max() <= 1e-13 * np.abs(lam_w).max()
     A2 = qst.abs_map(Tg, 1.5, prec)[0]
     A3 = qst.abs_map(Tg, 1.5, prec)[0]
