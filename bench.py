@@ -77,7 +77,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precision paths")
     ap.add_argument("--no-long", action="store_true",
-                    help="skip the runs of many small launches (1000-step NN-QST run, absolute projection)")
+                    help="skip the runs of many small launches (absolute projection)")
+    ap.add_argument("--nnqst-run", action="store_true",
+                    help="also train a fresh network for 1000 Rprop steps at N=11 (an end-to-end use of the "
+                         "library, not part of the headline measurement)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy (torch.neg) of this many MiB first, as the "
@@ -638,7 +641,7 @@ def main():
     Tm, fm = to_prec(T_np, f_np, args.prec, dev)
     modes = state_maps(qst, Tm, fm, args.prec)
     fids = fidelities(qst, Tm, args.prec, f=fm)
-    net = network(qst, fm, args.prec, long_run=not args.no_long)
+    net = network(qst, fm, args.prec, long_run=args.nnqst_run)
     absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
     del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)

@@ -44,7 +44,11 @@ Readings of the paper taken here (each also listed in the design notes):
    f_k = 0 contribute 0; a term with f_k > 0 and p_k <= 0 makes L = +inf.
 
 Parity pins: every function here is checked in ``tests/test_oracle_pins.py``
-against brute force, closed forms and invariants (no function is unpinned).
+against values that do not come from the oracle itself: brute force,
+closed forms worked out by hand, invariants and library routines.  Each
+pin is chosen so that a plausible slip (a dropped term or square, a wrong
+sign, index or operand order) fails it; F_c, for instance, is fixed by
+hand-computed values and by its factorisation over product states.
 """
 from __future__ import annotations
 

@@ -413,6 +413,47 @@ def test_fidelity_forms():
     assert abs(fq - ref) <= 1e-8
 
 
+def test_fidelity_c_closed_forms():
+    """Eq. F_CF fixed by values worked out by hand, so that dropping the
+    outer square, the square root, or the pairing of the two distributions
+    fails at least one of them:
+
+    * a point mass against the uniform distribution on 4 outcomes:
+      (sqrt(1 * 1/4))^2 = 1/4 (without the square it would be 1/2);
+    * disjoint supports give 0, equal normalised distributions give 1;
+    * p_hat = (1/2, 1/2, 0, 0), p = (1/8, 1/8, 3/8, 3/8):
+      (2 sqrt(1/16))^2 = 1/4;
+    * product states under the product POVM (Sec. 3.3): the outcome
+      distributions are products over qubits, so F_c is the product of the
+      single-qubit values, each (sum_a sqrt(p_hat_a p_a))^2 with
+      p_a = (1 + s_a . r)/4 (Sec. 4.1) -- an unsquared form gives the
+      product of their square roots instead."""
+    uni = np.full(4, 0.25)
+    assert O.fidelity_c(np.array([1.0, 0.0, 0.0, 0.0]), uni) == pytest.approx(0.25, abs=1e-15)
+    assert O.fidelity_c(np.array([0.5, 0.5, 0.0, 0.0]), np.array([0.0, 0.0, 0.5, 0.5])) == 0.0
+    assert O.fidelity_c(uni, uni) == pytest.approx(1.0, abs=1e-15)
+    assert O.fidelity_c(np.array([0.5, 0.5, 0.0, 0.0]),
+                        np.array([0.125, 0.125, 0.375, 0.375])) == pytest.approx(0.25, abs=1e-15)
+
+    g = S.rng(1410)
+    n = 3
+    ra = 0.9 * g.standard_normal((n, 3))
+    rb = 0.9 * g.standard_normal((n, 3))
+    ra /= np.maximum(1.0, np.linalg.norm(ra, axis=1, keepdims=True) / 0.9)
+    rb /= np.maximum(1.0, np.linalg.norm(rb, axis=1, keepdims=True) / 0.9)
+    per_qubit = []
+    for i in range(n):
+        pa = [(1.0 + O.TETRA_S[a] @ ra[i]) / 4.0 for a in range(4)]
+        pb = [(1.0 + O.TETRA_S[a] @ rb[i]) / 4.0 for a in range(4)]
+        per_qubit.append(sum(math.sqrt(x * y) for x, y in zip(pa, pb)) ** 2)
+    want = math.prod(per_qubit)
+    assert all(v < 0.999 for v in per_qubit)  # the square matters for every factor
+    pa = O.probs_real(kron_all([bloch_state(r) for r in ra]))
+    pb = O.probs_real(kron_all([bloch_state(r) for r in rb]))
+    assert O.fidelity_c(pa, pb) == pytest.approx(want, rel=1e-13)
+    assert abs(math.prod(math.sqrt(v) for v in per_qubit) - want) > 1e-3
+
+
 def test_adam_matches_torch():
     """The oracle's Adam loop equals torch.optim.Adam (CPU, float64) driven by
     the oracle gradient, on a complex parameter."""
