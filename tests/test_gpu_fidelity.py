@@ -124,6 +124,53 @@ def test_fidelity_general_against_oracle(prec, n):
     assert abs(float(F1.item()) - 1.0) <= max(TOL[prec], 1e-9 * d)
 
 
+@pytest.mark.parametrize("prec,n", [("f64", 10), ("f32", 10), ("f32", 11)])
+def test_fidelity_general_large_against_oracle(prec, n):
+    """qst_fidelity_general at N = 10 and 11 (its FP64 products on the
+    stream-K tiles) against the oracle's two-square-root F_q, for the
+    depolarised pure state of the paper's noise model (q = 0.1)."""
+    d = 1 << n
+    g = S.rng(7280 + n)
+    T = S.ginibre(g, d).astype(ctype(prec))
+    rho_hat = O.state_map(T.astype(np.complex128))[0]
+    rho = S.depolarised_pure(S.haar_vector(g, d), 0.1).astype(ctype(prec))
+    want = O.fidelity_q(rho_hat, rho.astype(np.complex128))
+    F, sweeps = qst.fidelity_general(dev_matrix(T), dev_matrix(rho), prec)
+    got = float(F.item())
+    say(f"N={n} {prec} depolarised q=0.1: F_q {got:.12f} oracle {want:.12f} ({sweeps} sweeps)")
+    assert abs(got - want) <= TOL[prec] * want, (got, want)
+
+
+@pytest.mark.parametrize("n,r", [(6, 1), (8, 4), (10, 1)])
+def test_fidelity_general_low_rank_targets(n, r):
+    """A pure (r = 1) or rank-r target through the general route (FP64),
+    against the exact value of the rank-r route (oracle fidelity_q_lowrank)
+    and against the library's rank-r call.
+
+    The general route takes square roots of every eigenvalue of
+    T^dagger rho T / tau, d - r of which are zero in exact arithmetic.  The
+    eigensolver leaves each of them an absolute error of at most about its
+    stopping threshold, 1e-14 of the Frobenius norm (about F_q here), so each
+    adds at most sqrt(1e-14 F) to sum sqrt(lambda) = sqrt(F): the relative
+    error of F_q is bounded by 2 (d - r) 1e-7.  The rank-r route has no such
+    term and meets 1e-12."""
+    d = 1 << n
+    g = S.rng(7290 + n)
+    T = S.ginibre(g, d)
+    rho_hat = O.state_map(T)[0]
+    W = S.ginibre(g, d, r)
+    rho, _ = O.state_map(W)
+    exact = O.fidelity_q_lowrank(rho_hat, W)
+    F, sweeps = qst.fidelity_general(dev_matrix(T), dev_matrix(rho), "f64")
+    got = float(F.item())
+    low = float(qst.fidelity_lowrank(dev_matrix(T), dev_matrix(W), "f64").item())
+    bound = 2.0 * (d - r) * 1e-7
+    say(f"N={n} r={r}: general {got:.12f}, rank-r {low:.12f}, exact {exact:.12f}; "
+        f"rel err {abs(got - exact) / exact:.2e} (bound {bound:.1e}), {sweeps} sweeps")
+    assert abs(low - exact) <= 1e-12 * exact
+    assert abs(got - exact) <= bound * exact
+
+
 @pytest.mark.parametrize("prec,n,rot", [("f64", 4, False), ("f64", 7, False), ("f32", 7, True), ("f32", 8, False),
                                         ("f64", 8, True)])
 def test_likelihood_fc_against_oracle(prec, n, rot):

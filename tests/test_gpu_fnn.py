@@ -75,7 +75,15 @@ def test_fnn_against_oracle(prec, n):
     assert torch.equal(T, T2) and all(torch.equal(a, b) for a, b in zip(grads, grads2))
 
 
-@pytest.mark.parametrize("prec,n", [("f64", 4), ("f32", 8)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fnn_n11_against_oracle(prec):
+    """The network at N = 11, the size the bench measures (4^11 inputs and
+    outputs, 22 hidden units, 184.5M parameters): T, h_pre and all four
+    parameter gradients against the oracle."""
+    test_fnn_against_oracle(prec, 11)
+
+
+@pytest.mark.parametrize("prec,n", [("f64", 4), ("f32", 8), ("f32", 11)])
 def test_network_chain_through_autograd(prec, n):
     """MappingNetwork -> T -> likelihood: autograd's parameter gradients
     against the oracle's chain (grad_T at the network's T, then

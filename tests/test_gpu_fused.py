@@ -196,18 +196,28 @@ def test_autograd_modes_agree():
     assert abs(L.item() - wL) <= 1e-12 * abs(wL)
 
 
-@pytest.fixture(scope="module")
-def n11():
-    say("building N=11 inputs and FP64 oracle results")
-    T, f, _ = config3(0.05)
+@pytest.fixture(scope="module", params=[0.0, 0.05, 0.1], ids=["q0", "q0.05", "q0.1"])
+def n11(request):
+    say(f"building N=11 inputs (q = {request.param})")
+    T, f, _ = config3(request.param)
     return T, f
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 def test_fused_n11(n11, prec):
+    """Config 3, fused call and separate-call route, each against the oracle."""
     say(f"fused N=11 {prec}")
     T, f = n11
     check(T, f, prec)
+    say(f"separate calls N=11 {prec}")
+    Tq = T.astype(ctype(prec)).astype(np.complex128)
+    fq = f.astype(rtype(prec)).astype(np.float64)
+    wL, _, _, wgrad = oracle(Tq, fq)
+    L, grad = run_separate(T, f, prec)
+    errs = {"L": abs(L - wL) / abs(wL), "grad": rel_fro(grad, wgrad)}
+    say(f"  errors {errs}")
+    for k, v in errs.items():
+        assert v <= TOL[prec], (k, v)
 
 
 def test_fused_n12_f32_against_recompute():

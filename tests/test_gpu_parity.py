@@ -318,10 +318,14 @@ def test_fd_directions_n8_f32():
 # N = 11 (4,194,304 outcomes), the measured workload, all three precisions
 # ---------------------------------------------------------------------------
 
-@pytest.fixture(scope="module")
-def n11():
-    say("building N=11 inputs and FP64 oracle results")
-    T, f, _ = config3(0.05)
+@pytest.fixture(scope="module", params=[0.0, 0.05, 0.1], ids=["q0", "q0.05", "q0.1"])
+def n11(request):
+    """Config 3 at each depolarising level: q = 0 is the pure target, with
+    about 29% of the 4^11 frequencies zero (the f_k = 0 branch of the NLL and
+    the cotangent at full size)."""
+    say(f"building N=11 inputs (q = {request.param}) and FP64 oracle results")
+    T, f, _ = config3(request.param)
+    say(f"  zero frequencies: {float(np.mean(f == 0)):.3f}")
     return T, f, oracle_chain(T, f)
 
 
