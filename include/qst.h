@@ -188,6 +188,37 @@ qst_status qst_likelihood(int n_qubits, qst_prec prec, const void* T, int64_t ld
                           size_t ws_bytes, void* stream);
 
 /*
+ * Bytes of the library's static device scratch: the workspace of
+ * qst_likelihood_noalloc, one array per GPU, held until the process ends.
+ */
+#define QST_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+
+/*
+ * qst_likelihood for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and results, bitwise, with the workspace taken from
+ * a static device array of QST_STATIC_SCRATCH_BYTES (16 MiB) instead of a
+ * workspace argument.  The call allocates nothing: no hipMalloc, no hipFree,
+ * no allocating library routine (with the library's profiler off, its
+ * default).  On its first call on a device it looks up that device's copy
+ * of the array (hipGetSymbolAddress) with that device current; the stream
+ * and every buffer must belong to the current device.
+ *   Limit: the workspace qst_likelihood would need, qst_workspace_bytes(N,
+ *   prec, QST_OP_LIKELIHOOD), must fit the array: N <= 9 in every
+ *   precision.  Larger N returns QST_ERR_WORKSPACE before anything is
+ *   launched.
+ *   Sharing: every call on one GPU uses that GPU's one array, and a call
+ *   leaves its contents behind (nothing in it needs to start at zero).
+ *   Calls that overlap on one GPU -- concurrent streams, or host threads
+ *   without ordering between their streams -- race on the array and give
+ *   undefined results; order them on one stream.
+ * Arguments and errors otherwise as qst_likelihood.
+ */
+qst_status qst_likelihood_noalloc(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* f,
+                                  const double* povm_host, double* tau_dev, double* nll_dev,
+                                  unsigned long long* bad_dev, void* G, int64_t ldG, void* stream);
+
+/*
  * qst_likelihood plus the classical fidelity (Sec. 2.3 Eq. F_CF) of the
  * model's distribution p_k = Tr(M_k rho) against a target distribution:
  *   F_c = (sum_k sqrt(max(p_k, 0) max(p_target_k, 0)))^2.

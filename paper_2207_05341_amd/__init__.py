@@ -20,7 +20,7 @@ from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MA
 
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
-    "likelihood_forward", "likelihood_forward_fc", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
+    "likelihood_forward", "likelihood_forward_noalloc", "likelihood_forward_fc", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
     "abs_map_backward", "AbsMapFn", "AbsProjection", "fidelity_lowrank", "fidelity_general",
     "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
@@ -310,6 +310,31 @@ def likelihood_forward(T: torch.Tensor, f: torch.Tensor, prec=None, povm=None, w
     _lib.check(_lib.lib().qst_likelihood(n, pr, T.data_ptr(), ld, f.data_ptr(), _povm_arg(povm), tau.data_ptr(),
                                          out.data_ptr(), bad.data_ptr(), _ptr(G), 0 if G is None else G.stride(0),
                                          _ptr(ws), nb, _stream(T.device)), "qst_likelihood")
+    return out, tau, G, bad
+
+
+def likelihood_forward_noalloc(T: torch.Tensor, f: torch.Tensor, prec=None, povm=None, G: torch.Tensor | None = None,
+                               out: torch.Tensor | None = None, tau: torch.Tensor | None = None,
+                               bad: torch.Tensor | None = None):
+    """likelihood_forward through qst_likelihood_noalloc: the library's static
+    device scratch serves as the workspace (N <= 9), so the library call
+    allocates nothing.  Output tensors may be passed in (then this wrapper
+    allocates nothing either); returns (out, tau, G, bad) as
+    likelihood_forward."""
+    n, ld = _matrix(T, "T")
+    pr = _prec(T.dtype, prec)
+    _vector(f, "f", n, real_dtype(pr))
+    out = torch.empty(2, dtype=torch.float64, device=T.device) if out is None else out
+    bad = torch.empty(2, dtype=torch.int64, device=T.device) if bad is None else bad
+    tau = torch.empty((), dtype=torch.float64, device=T.device) if tau is None else tau
+    if G is not None:
+        n2, ldg = _matrix(G, "G")
+        if n2 != n or G.dtype != T.dtype:
+            raise ValueError("G must match T in size and dtype")
+    _lib.check(_lib.lib().qst_likelihood_noalloc(n, pr, T.data_ptr(), ld, f.data_ptr(), _povm_arg(povm),
+                                                 tau.data_ptr(), out.data_ptr(), bad.data_ptr(), _ptr(G),
+                                                 0 if G is None else G.stride(0), _stream(T.device)),
+               "qst_likelihood_noalloc")
     return out, tau, G, bad
 
 

@@ -17,6 +17,7 @@ QST_OP_LIKELIHOOD, QST_OP_GRAD_PRODUCT, QST_OP_FIDELITY, QST_OP_FNN, QST_OP_ABS_
 QST_FIDELITY_MAX_RANK = 32
 QST_MAX_QUBITS = 13
 QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER = 1, 2
+QST_STATIC_SCRATCH_BYTES = 16 << 20
 
 #: Every symbol include/qst.h declares, with (restype, argtypes).
 _vp, _i64, _sz, _int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int
@@ -28,6 +29,7 @@ SIGNATURES = {
     "qst_likelihood": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_likelihood_fc": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz,
                                  _vp]),
+    "qst_likelihood_noalloc": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
     "qst_grad_product": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_state_premap": (_int, [_int, _int, _int, _vp, _i64, _vp, _i64, _vp]),
     "qst_abs_map": (_int, [_int, _int, ctypes.c_double, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),

@@ -1,6 +1,7 @@
 // extern "C" entry points of libqst: validation, workspace carving and
 // kernel dispatch for the likelihood path.  See include/qst.h for the
 // contract of each call.
+#include <mutex>
 #include <string>
 
 #include "qst_kernels.h"
@@ -357,6 +358,56 @@ qst_status qst_likelihood_fc(int n, qst_prec prec, const void* T, int64_t ldT, c
 }
 
 }  // extern "C"
+
+namespace {
+
+// The workspace of qst_likelihood_noalloc.  In host code `scratch` names a
+// host-side stand-in, not device memory: kernels get the device address
+// that hipGetSymbolAddress returns for the current device (each GPU holds
+// its own copy of the array), looked up once per device and kept here.
+__device__ __align__(256) unsigned char scratch[QST_STATIC_SCRATCH_BYTES];
+
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchMaxDevices] = {};
+
+qst_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchMaxDevices)
+    return fail(QST_ERR_UNSUPPORTED, "device ordinal " + std::to_string(dev) + " beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess)
+      return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(QST_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return QST_OK;
+}
+
+}  // namespace
+
+extern "C" qst_status qst_likelihood_noalloc(int n, qst_prec prec, const void* T, int64_t ldT, const void* f,
+                                             const double* povm_host, double* tau_dev, double* nll_dev,
+                                             unsigned long long* bad_dev, void* G, int64_t ldG, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  const size_t need = workspace_layout(n, prec, QST_OP_LIKELIHOOD, false).total;
+  if (need > QST_STATIC_SCRATCH_BYTES)
+    return fail(QST_ERR_WORKSPACE, "N=" + std::to_string(n) + " needs " + std::to_string(need) +
+                                       " bytes of workspace, more than the static scratch of " +
+                                       std::to_string(QST_STATIC_SCRATCH_BYTES) +
+                                       " bytes; use qst_likelihood with a workspace");
+  void* ws = nullptr;
+  if ((st = static_scratch(&ws)) != QST_OK) return st;
+  return likelihood_impl(n, prec, T, ldT, f, povm_host, tau_dev, nll_dev, bad_dev, G, ldG, ws,
+                         QST_STATIC_SCRATCH_BYTES, stream, nullptr, nullptr);
+}
 
 namespace {
 

@@ -209,6 +209,23 @@ def test_likelihood_validation(L):
     assert call(povm=_povm_array(bad)) == lib_mod.QST_ERR_INVALID_ARG and "identity" in _err(L)
 
 
+def test_likelihood_noalloc_limits(L):
+    """The static-scratch variant rejects, before any device call, sizes
+    whose workspace exceeds QST_STATIC_SCRATCH_BYTES (N >= 10) and invalid
+    precisions or qubit counts; N <= 9 fits in every precision."""
+    for prec in (0, 1, 2):
+        assert lib_mod.workspace_bytes(9, prec, lib_mod.QST_OP_LIKELIHOOD) <= lib_mod.QST_STATIC_SCRATCH_BYTES
+        assert lib_mod.workspace_bytes(10, prec, lib_mod.QST_OP_LIKELIHOOD) > lib_mod.QST_STATIC_SCRATCH_BYTES
+        for n in (10, 11, 13):
+            d = 1 << n
+            st = L.qst_likelihood_noalloc(n, prec, FAKE, d, FAKE2, None, FAKE, FAKE2, None, None, 0, None)
+            assert st == lib_mod.QST_ERR_WORKSPACE and "static scratch" in _err(L)
+    assert L.qst_likelihood_noalloc(0, 1, FAKE, 1, FAKE2, None, FAKE, FAKE2, None, None, 0, None) \
+        == lib_mod.QST_ERR_INVALID_ARG
+    assert L.qst_likelihood_noalloc(4, 7, FAKE, 16, FAKE2, None, FAKE, FAKE2, None, None, 0, None) \
+        == lib_mod.QST_ERR_INVALID_ARG
+
+
 def test_grad_product_validation(L):
     n, d = 10, 1024
     ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_GRAD_PRODUCT)

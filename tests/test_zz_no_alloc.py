@@ -1,0 +1,60 @@
+"""qst_likelihood_noalloc (the static-scratch variant of qst_likelihood,
+for callers that cannot allocate) against qst_likelihood on the same
+inputs: two calls in a row, the second smaller than the first, each
+compared bitwise with the workspace route and within the path's tolerance
+with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import depolarised_case, rel_fro
+
+torch = pytest.importorskip("torch")
+qst = pytest.importorskip("paper_2207_05341_amd")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_noalloc_equals_workspace_call(prec):
+    ct = np.complex128 if prec == "f64" else np.complex64
+    rt = np.float64 if prec == "f64" else np.float32
+    for n, seed in ((9, 9901), (6, 9902)):  # the second call smaller than the first
+        say(f"qst_likelihood_noalloc N={n} {prec}")
+        T, f, _ = depolarised_case(n, seed, 0.1, 100 * 4 ** n)
+        Tg, fg = dev(T.astype(ct)), dev(f.astype(rt))
+        G = torch.empty(Tg.shape, dtype=Tg.dtype, device=DEV)
+        out, tau, _, bad = qst.likelihood_forward_noalloc(Tg, fg, prec, G=G)
+        out_w, tau_w, G_w, bad_w = qst.likelihood_forward(Tg, fg, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(out, out_w) and torch.equal(tau, tau_w) and torch.equal(bad, bad_w)
+        assert torch.equal(G, G_w)
+        Tq, fq = T.astype(ct).astype(np.complex128), f.astype(rt).astype(np.float64)
+        rho, _ = O.state_map(Tq)
+        p = O.probs_real(rho)
+        wL = O.nll_vec(p, fq)
+        wG = O.adjoint(O.cotangent(p, fq), n)
+        errs = {"L": abs(float(out[0].item()) - wL) / abs(wL), "G": rel_fro(G.cpu().numpy(), wG)}
+        say(f"  errors {errs}")
+        for k, v in errs.items():
+            assert v <= TOL[prec], (k, v)
+        assert bad.cpu().tolist() == [0, 0]
+
+
+def test_noalloc_rejects_large_n():
+    n, d = 10, 1024
+    T = torch.zeros((d, d), dtype=torch.complex64, device=DEV)
+    f = torch.zeros(4 ** n, dtype=torch.float32, device=DEV)
+    with pytest.raises(qst.QstError, match="static scratch"):
+        qst.likelihood_forward_noalloc(T, f, "f32")
