@@ -16,8 +16,9 @@ depolarised random pure state (q = 0.05).
 
 Prints ONE JSON line with the throughput, the roofline of the dominant kernel
 (durations from HIP events recorded by the library on its launch stream over
-the timed region), accuracy against the FP64 path on the same GPU, the other
-precision paths, and the FP64 CPU oracle timed on a bounded sample.
+the timed region), accuracy against the FP64 oracle on the same inputs and
+against the GPU FP64 path, the other precision paths, and the FP64 CPU oracle
+timed on a bounded sample (all host threads, and one).
 """
 from __future__ import annotations
 
@@ -487,39 +488,60 @@ def convergence(qst, n, prec, dev, steps=1000):
     return out
 
 
+def _oracle_eval(O, Tq, fq):
+    """One full forward + adjoint evaluation by the oracle; returns p, L, grad."""
+    n = O.n_qubits_of(Tq.shape[0])
+    rho, tau = O.state_map(Tq)
+    p = O.probs_real(rho)
+    L = O.nll_vec(p, fq)
+    G = O.adjoint(O.cotangent(p, fq), n)
+    return p, L, (2.0 / tau) * (G @ Tq)
+
+
 def cpu_baseline(T, f, prec):
-    """FP64 oracle on a bounded sample: full forward + adjoint evaluations of
-    the same N = 11 workload (the measured precision's T and f widened)."""
+    """FP64 oracle timed on a bounded sample of the same N = 11 workload (the
+    measured precision's T and f widened to FP64): full forward + adjoint
+    evaluations, first with every BLAS thread of the host (up to 3 or
+    20 s), then with one thread (up to 2 or 25 s).  Returns the record and
+    the outputs of the first evaluation, which serve as the reference for
+    the accuracy of the GPU paths on the same inputs."""
     import numpy as np
 
     import oracle as O
 
     try:
-        from threadpoolctl import threadpool_info
-
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
     except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+        threadpool_info = threadpool_limits = None
     ct = np.complex128 if prec == "f64" else np.complex64
     rt = np.float64 if prec == "f64" else np.float32
     Tq = T.astype(ct).astype(np.complex128)
     fq = f.astype(rt).astype(np.float64)
-    n = O.n_qubits_of(Tq.shape[0])
-    evals = 0
-    t0 = time.perf_counter()
-    while True:
-        rho, tau = O.state_map(Tq)
-        p = O.probs_real(rho)
-        O.nll_vec(p, fq)
-        G = O.adjoint(O.cotangent(p, fq), n)
-        _ = (2.0 / tau) * (G @ Tq)
-        evals += 1
-        el = time.perf_counter() - t0
-        if evals >= 3 or el > 20.0:
-            break
-    return {"value": evals / el, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{evals} full forward+adjoint evaluations of the N=11 workload in FP64 numpy "
-                      f"({el:.1f} s)"}
+
+    def leg(max_evals, max_s):
+        evals, ref = 0, None
+        t0 = time.perf_counter()
+        while True:
+            out = _oracle_eval(O, Tq, fq)
+            ref = ref or out
+            evals += 1
+            el = time.perf_counter() - t0
+            if evals >= max_evals or el > max_s:
+                return evals, el, ref
+
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1]) if threadpool_info else (os.cpu_count() or 1)
+    evals, el, ref = leg(3, 20.0)
+    single = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            e1, t1, _ = leg(2, 25.0)
+        single = {"value": e1 / t1, "unit": "evals/s", "cores": 1, "kind": "oracle",
+                  "sample": f"{e1} full forward+adjoint evaluations in FP64 numpy with one BLAS thread ({t1:.1f} s)"}
+    rec = {"value": evals / el, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{evals} full forward+adjoint evaluations of the N=11 workload in FP64 numpy "
+                     f"({el:.1f} s, {threads} BLAS threads)",
+           "single_thread": single}
+    return rec, ref
 
 
 def main():
@@ -545,42 +567,43 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # accuracy against the FP64 path on the same GPU
+    # the GPU FP64 path on the unrounded inputs, for max|dp| vs FP64
     T64, f64 = to_prec(T_np, f_np, "f64", dev)
     out64, g64 = step(qst, T64, f64, "f64")
     rho64, _ = qst.state_map(T64, "f64")
     p64 = qst.povm_probs(rho64, "f64")
-    del rho64
+    del rho64, T64, f64
     torch.cuda.synchronize()
 
     def measure(prec, steps, warmup, fused=True):
-        """Accuracy against the FP64 path; a per-kernel breakdown loop (each
-        scope timed alone); then the timed loop, in which only the dominant
-        kernel is bracketed by events."""
+        """The path's outputs (for accuracy); a per-kernel breakdown (each
+        scope timed alone, in warmed loops: the events bracketing a scope
+        add their queue time to it only); then the timed loop, in which
+        only the dominant kernel is bracketed by events."""
         T, f = to_prec(T_np, f_np, prec, dev)
         out, grad = step(qst, T, f, prec, fused)
         rho, _ = qst.state_map(T, prec)
         p = qst.povm_probs(rho, prec)  # the forward map alone, for max|dp|
         del rho
         torch.cuda.synchronize()
+        res = {"p": p.double().cpu().numpy(), "L": float(out[0].item()),
+               "grad": grad.to(torch.complex128).cpu().numpy()}
         acc = {
             "max_dp_rel": float((p.double() - p64).abs().max() / p64.abs().max()),
             "L_rel": float(abs(out[0].item() - out64[0].item()) / abs(out64[0].item())),
             "grad_rel": float(torch.linalg.vector_norm(grad.to(torch.complex128) - g64)
                               / torch.linalg.vector_norm(g64)),
         }
-        del p
-        # breakdown: list the scopes once, then time each one alone (events
-        # bracketing every scope would add their queue time to each other)
+        del p, out, grad
         _, names = time_steps(qst, T, f, prec, 1, 1, only="", fused=fused)
         breakdown = {}
         for name in names:
-            breakdown.update(time_steps(qst, T, f, prec, max(5, steps // 5), 0, only=name, fused=fused)[1])
+            breakdown.update(time_steps(qst, T, f, prec, max(20, steps // 2), 3, only=name, fused=fused)[1])
         dom = max(breakdown, key=lambda k: breakdown[k][1] / breakdown[k][0])
         sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom, fused=fused)
-        return sec, breakdown, dom, kdom, acc
+        return sec, breakdown, dom, kdom, acc, res
 
-    sec, kern, dom, kdom, acc = measure(args.prec, args.steps, args.warmup)
+    sec, kern, dom, kdom, acc, res_main = measure(args.prec, args.steps, args.warmup)
     kern_us = {k: 1e3 * ms / calls for k, (calls, ms) in kern.items()}
 
     # roofline of the dominant kernel (largest share of the step), its
@@ -589,25 +612,30 @@ def main():
     if dom in kdom:
         avg_s = kdom[dom][1] * 1e-3 / kdom[dom][0]
         if dom.startswith("hemm") or dom.startswith("herk"):
-            # flops counted at 8 per complex multiply-add (4 d^2 (d+1) for the
-            # Hermitian T T^dagger, 8 d^3 for G' T); the fp32/fp64 products
-            # run the 3M form (3 real products per complex product: 6 flops
-            # per complex multiply-add executed), the bf16 gradient product
-            # three split products of 4 real products each (24 d^3 executed)
+            # Algorithmic flops of the algorithm each kernel runs: the fp32 /
+            # fp64 products use the 3M form, three real products per complex
+            # product (6 real flop per complex multiply-add): 3 d^2 (d+1) for
+            # the Hermitian T T^dagger (lower triangle), 6 d^3 for G' T.  The
+            # bf16 products use four real products per complex product (8 flop
+            # per complex multiply-add), three split products for G' T
+            # (24 d^3).  The conventional count, 8 flop per complex
+            # multiply-add (4 d^2 (d+1) and 8 d^3), is reported beside it.
             herk = dom.startswith("herk")
-            flops = 4.0 * d * d * (d + 1) if herk else 8.0 * d ** 3
+            counted = 4.0 * d * d * (d + 1) if herk else 8.0 * d ** 3
             bf16 = dom.endswith(("bf16", "bf16x3"))
             peak_key = "bf16" if bf16 else ("f64" if dom.endswith("f64") else "f32")
-            executed = flops * (0.75 if not bf16 else (1.0 if herk else 3.0))
-            ach = flops / avg_s / 1e12
+            executed = counted * (0.75 if not bf16 else (1.0 if herk else 3.0))
+            ach = executed / avg_s / 1e12
+            form = ("3 d^2(d+1)" if herk else "6 d^3") if not bf16 else ("4 d^2(d+1)" if herk else "24 d^3")
             roofline = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[peak_key],
                         "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[peak_key], "traffic": traffic_of(dom),
-                        "algorithmic_per_launch": f"{flops:.4g} flop ({'4d^2(d+1)' if herk else '8d^3'}, d={d}, "
-                                                  "8 flop per complex multiply-add)",
-                        "executed_mfma_frac": executed / avg_s / 1e12 / PEAK_TFLOPS[peak_key],
-                        "note": "complex products in the 3M form: 6 real flop executed per complex "
-                                "multiply-add, counted at 8" if not bf16 else
-                                "bf16 split operands: three products per complex product"}
+                        "algorithmic_per_launch": f"{executed:.4g} flop ({form}, d={d}: "
+                                                  + ("3M complex product, 3 real products" if not bf16 else
+                                                     "4 real products per complex product") + ")",
+                        "avg_launch_us": avg_s * 1e6, "launches": kdom[dom][0],
+                        "counted_per_launch": f"{counted:.4g} flop ({'4d^2(d+1)' if herk else '8d^3'}, "
+                                              "8 flop per complex multiply-add)",
+                        "counted_tflops": counted / avg_s / 1e12}
     # POVM passes: achieved GB/s from algorithmic bytes.  N = 11 plan: pass 0
     # contracts qubits 6..11 of rho (lower triangle read) into X[(r, c)][kd]
     # with (r, c) the 528 lower pairs of the 5 remaining qubits and kd 4^6
@@ -624,19 +652,20 @@ def main():
     }
     povm_gbs = {k: v / (kern_us[k] * 1e-6) / 1e9 for k, v in povm_bytes.items() if k in kern_us} if n == 11 else {}
 
-    paths = {}
+    paths, path_res = {}, {}
     if not args.no_variants:
         for prec in ("f64", "f32", "bf16"):
             if prec == args.prec:
                 continue
-            s2, k2, _, _, a2 = measure(prec, max(10, args.steps // 2), 3)
+            s2, k2, _, _, a2, path_res[prec] = measure(prec, max(10, args.steps // 2), 3)
             paths[prec] = {"evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
                            "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()}}
-        s2, k2, _, _, a2 = measure(args.prec, max(10, args.steps // 2), 3, fused=False)
+        s2, k2, _, _, a2, _ = measure(args.prec, max(10, args.steps // 2), 3, fused=False)
         paths[args.prec + "_separate_calls"] = {
             "evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
             "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()},
             "note": "qst_state_map, qst_povm_probs, qst_nll, qst_nll_backward with p stored"}
+    del p64, g64
 
     Tm, fm = to_prec(T_np, f_np, args.prec, dev)
     modes = state_maps(qst, Tm, fm, args.prec)
@@ -645,7 +674,35 @@ def main():
     absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
     del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(T_np, f_np, args.prec)
+    cpu, acc_oracle = None, None
+    if not args.no_cpu_baseline:
+        # the timed oracle leg also gives the reference outputs for the
+        # measured precision's inputs; the FP64 path's reference (unrounded
+        # inputs) is one more untimed evaluation when that path ran
+        import oracle as O
+
+        cpu, ref = cpu_baseline(T_np, f_np, args.prec)
+        refs = {args.prec: ref}
+        storage = {"f64": "f64", "f32": "f32", "bf16": "f32"}  # the BF16 path takes complex64 T
+        for prec in path_res:
+            if storage[prec] == storage[args.prec]:
+                refs[prec] = ref
+            elif storage[prec] == "f64":
+                refs[prec] = _oracle_eval(O, T_np.astype(np.complex128), f_np.astype(np.float64))
+            else:
+                refs[prec] = _oracle_eval(O, T_np.astype(np.complex64).astype(np.complex128),
+                                          f_np.astype(np.float32).astype(np.float64))
+
+        def vs_oracle(res, r):
+            pw, Lw, gw = r
+            return {"max_dp_rel": float(np.max(np.abs(res["p"] - pw)) / np.max(np.abs(pw))),
+                    "L_rel": abs(res["L"] - Lw) / abs(Lw),
+                    "grad_rel": float(np.linalg.norm(res["grad"] - gw) / np.linalg.norm(gw))}
+
+        acc_oracle = vs_oracle(res_main, refs[args.prec])
+        for prec, res in path_res.items():
+            paths[prec]["accuracy_vs_oracle"] = vs_oracle(res, refs[prec])
+        del refs, ref
 
     line = {
         "metric": METRIC,
@@ -666,8 +723,10 @@ def main():
                    "n_qubits": n, "precision": args.prec, "parallelism": "none (1 GPU)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "accuracy_vs_oracle": acc_oracle,
         "accuracy_vs_f64": acc,
         "kernels_us": {k: round(v, 2) for k, v in sorted(kern_us.items())},
+        "kernels_sum_us": round(sum(kern_us.values()), 1),
         "povm_pass_gbs": {k: round(v, 1) for k, v in povm_gbs.items()},
         "paths": paths,
         "state_maps": modes,

@@ -17,7 +17,9 @@ What it computes, written from the paper (Wang, Cheng, Li, Chen,
 * network     the 3-layer FNN of Sec. 3.1 (4^N -> 2N -> 4^N) filling the
               Hermitian T, and its backward
 * Born rule   p_k = Tr(M_k rho)                  (Sec. 2.1, Born rule)
-* product POVM M_k = M_{k_1} (x) ... (x) M_{k_N}   (Sec. 3.3)
+* product POVM M_k = M^(1)_{k_1} (x) ... (x) M^(N)_{k_N}   (Sec. 3.3), any
+              K-element POVM per qubit, and several such settings summed
+              in the loss (Sec. 2.1: one POVM {M^i_k} per measurement i)
 * tetrahedral single-qubit POVM M_a = (I + s_a . sigma)/4   (Sec. 4.1 setup)
 * loss        L = -sum_k f_k log p_k              (Sec. 2.1 Eq. MLE; Sec. 3.1)
 * gradient    dL/dT (PyTorch convention dL/dRe T + i dL/dIm T)
@@ -285,11 +287,30 @@ def n_qubits_of(dim: int) -> int:
     return n
 
 
-def product_element(povm: np.ndarray, ks) -> np.ndarray:
-    """M_k = M_{k_1} (x) ... (x) M_{k_N}, qubit 1 leftmost (Sec. 3.3)."""
+def per_qubit(povm, n: int) -> list:
+    """The single-qubit POVM of each qubit 1..N as a list of (K, 2, 2) arrays.
+
+    ``povm`` is None (the tetrahedral POVM on every qubit), one (K, 2, 2)
+    POVM shared by every qubit, or (N, K, 2, 2): qubit i measured with its
+    own K-element POVM M^(i) (Sec. 3.3 with a POVM per qubit; K is the same
+    on every qubit, so there are K^N outcomes)."""
+    if povm is None:
+        return [tetrahedral_povm()] * n
+    a = np.asarray(povm, dtype=np.complex128)
+    if a.ndim == 3:
+        return [a] * n
+    if a.ndim != 4 or a.shape[0] != n:
+        raise ValueError("povm must be (K, 2, 2) or (N, K, 2, 2)")
+    return [a[i] for i in range(n)]
+
+
+def product_element(povm, ks) -> np.ndarray:
+    """M_k = M^(1)_{k_1} (x) ... (x) M^(N)_{k_N}, qubit 1 leftmost (Sec. 3.3);
+    ``povm`` as in :func:`per_qubit`."""
+    mats = per_qubit(povm, len(ks))
     m = np.ones((1, 1), dtype=np.complex128)
-    for a in ks:
-        m = np.kron(m, povm[a])
+    for i, a in enumerate(ks):
+        m = np.kron(m, mats[i][a])
     return m
 
 
@@ -304,11 +325,12 @@ def probs_kron(rho: np.ndarray, povm: np.ndarray | None = None) -> np.ndarray:
     Exponential cost; intended for N <= 5.  Returns the real part; the
     imaginary part (zero for Hermitian rho) is checked by the tests.
     """
-    povm = tetrahedral_povm() if povm is None else povm
     n = n_qubits_of(rho.shape[0])
-    out = np.empty(povm.shape[0] ** n, dtype=np.complex128)
-    for idx, ks in enumerate(outcome_tuples(n, povm.shape[0])):
-        out[idx] = np.trace(product_element(povm, ks) @ rho)
+    mats = per_qubit(povm, n)
+    K = mats[0].shape[0]
+    out = np.empty(K ** n, dtype=np.complex128)
+    for idx, ks in enumerate(outcome_tuples(n, K)):
+        out[idx] = np.trace(product_element(np.array(mats), ks) @ rho)
     return out
 
 
@@ -334,12 +356,12 @@ def probs(rho: np.ndarray, povm: np.ndarray | None = None) -> np.ndarray:
     contraction per qubit over its pair index m_i = 2 r_i + c_i, with
     W[a, 2r + c] = (M_a)_{c, r} so that sum_m W[a, m] rho_m = Tr(M_a rho)
     for one qubit (Born rule).  Complex result (imaginary part ~ 0)."""
-    povm = tetrahedral_povm() if povm is None else povm
-    K = povm.shape[0]
-    W = np.transpose(povm, (0, 2, 1)).reshape(K, 4)  # W[a, 2r+c] = M_a[c, r]
     x = _pair_tensor(np.asarray(rho, dtype=np.complex128))
     n = x.ndim
+    mats = per_qubit(povm, n)
+    K = mats[0].shape[0]
     for i in range(n):
+        W = np.transpose(mats[i], (0, 2, 1)).reshape(K, 4)  # W[a, 2r+c] = M^(i)_a[c, r]
         x = np.tensordot(W, x, axes=([1], [i]))  # new axis first
         x = np.moveaxis(x, 0, i)
     return x.reshape(K ** n)
@@ -397,23 +419,24 @@ def probs_at(W: np.ndarray, outcomes, povm: np.ndarray | None = None) -> np.ndar
 
 def adjoint_kron(g: np.ndarray, n: int, povm: np.ndarray | None = None) -> np.ndarray:
     """Brute force G = sum_k g_k M_k (N <= 5)."""
-    povm = tetrahedral_povm() if povm is None else povm
+    mats = np.array(per_qubit(povm, n))
     d = 1 << n
     G = np.zeros((d, d), dtype=np.complex128)
-    for idx, ks in enumerate(outcome_tuples(n, povm.shape[0])):
-        G += g[idx] * product_element(povm, ks)
+    for idx, ks in enumerate(outcome_tuples(n, mats.shape[1])):
+        G += g[idx] * product_element(mats, ks)
     return G
 
 
 def adjoint(g: np.ndarray, n: int, povm: np.ndarray | None = None) -> np.ndarray:
     """G = sum_k g_k M_k via per-qubit contractions: G[r, c] =
-    sum_k g_k prod_i (M_{k_i})_{r_i, c_i}, i.e. V[2r + c, a] = (M_a)_{r, c}
-    applied along each qubit axis."""
-    povm = tetrahedral_povm() if povm is None else povm
-    K = povm.shape[0]
-    V = povm.reshape(K, 4).T  # V[2r+c, a] = M_a[r, c]
+    sum_k g_k prod_i (M^(i)_{k_i})_{r_i, c_i}, i.e. V[2r + c, a] =
+    (M^(i)_a)_{r, c} applied along each qubit axis i (``povm`` as in
+    :func:`per_qubit`)."""
+    mats = per_qubit(povm, n)
+    K = mats[0].shape[0]
     x = np.asarray(g, dtype=np.complex128).reshape((K,) * n)
     for i in range(n):
+        V = mats[i].reshape(K, 4).T  # V[2r+c, a] = M^(i)_a[r, c]
         x = np.tensordot(V, x, axes=([1], [i]))
         x = np.moveaxis(x, 0, i)
     return _from_pair_tensor(x)
@@ -493,6 +516,37 @@ def grad_T_mode(T: np.ndarray, f: np.ndarray, mode: str, povm: np.ndarray | None
     Returns (grad, L)."""
     g, L = grad_T(premap(T, mode), f, povm)
     return premap(g, mode), L
+
+
+def likelihood_settings(T: np.ndarray, fs, settings):
+    """Several measurement settings (Sec. 2.1: each measurement i is a POVM
+    {M^i_k} with its own frequencies): setting s is a product POVM (one
+    K-element POVM per qubit, ``settings[s]`` as in :func:`per_qubit`) with
+    frequencies fs[s] over its K^N outcomes, and the loss is the sum of the
+    settings' negative log-likelihoods, L = -sum_s sum_k f^s_k ln p^s_k.
+    Returns (L, [p_s], rho, tau)."""
+    rho, tau = state_map(T)
+    n = n_qubits_of(rho.shape[0])
+    ps, Ls = [], []
+    for f, povm in zip(fs, settings):
+        p = probs_real(rho, povm) if n > 4 else probs_kron(rho, povm).real.copy()
+        ps.append(p)
+        Ls.append(nll_vec(p, f))
+    return math.fsum(Ls), ps, rho, tau
+
+
+def grad_T_settings(T: np.ndarray, fs, settings):
+    """dL/dRe T + i dL/dIm T of :func:`likelihood_settings`: (2/tau) G' T with
+    G' = sum_s sum_k (F_s - f^s_k / p^s_k) M^s_k, F_s = sum_k f^s_k.  Each
+    setting's POVM sums to I, so the trace normalisation contributes
+    (sum_s F_s) I = sum_s sum_k F_s M^s_k.  Returns (grad, L)."""
+    L, ps, rho, tau = likelihood_settings(T, fs, settings)
+    n = n_qubits_of(rho.shape[0])
+    G = np.zeros_like(rho)
+    for f, p, povm in zip(fs, ps, settings):
+        g = cotangent(p, f)
+        G += adjoint(g, n, povm) if n > 4 else adjoint_kron(g, n, povm)
+    return (2.0 / tau) * (G @ np.asarray(T, dtype=np.complex128)), L
 
 
 # ----------------------------------------------------------------------------

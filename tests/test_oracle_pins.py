@@ -729,3 +729,134 @@ def test_rprop_step_matches_the_library_optimiser():
     np.testing.assert_allclose(st1, [0.12, 0.05, 0.1])
     np.testing.assert_allclose(w1, [0.88, 1.0, 0.9])
     np.testing.assert_allclose(pr1, [2.0, 0.0, 3.0])
+
+
+# --------------------------------------------------------------------------
+# General product POVMs: K outcomes per qubit, a POVM of its own on each
+# qubit, several settings (Sec. 3.3; Sec. 2.1, one POVM per measurement;
+# the multiple-POVM remark of the Sec. 4.1 setup)
+# --------------------------------------------------------------------------
+
+def random_povm(g, K):
+    """A random K-element qubit POVM: A_k = B_k B_k^dagger made to sum to I
+    by S^(-1/2) A_k S^(-1/2), S = sum A_k (full rank elements)."""
+    A = []
+    for _ in range(K):
+        B = g.standard_normal((2, 2)) + 1j * g.standard_normal((2, 2))
+        A.append(B @ B.conj().T)
+    w, v = np.linalg.eigh(sum(A))
+    s = (v / np.sqrt(w)) @ v.conj().T
+    return np.array([s @ a @ s for a in A])
+
+
+def tr2(M, rho):
+    """Tr(M rho) of 2 x 2 matrices, written out entry by entry."""
+    return M[0, 0] * rho[0, 0] + M[0, 1] * rho[1, 0] + M[1, 0] * rho[0, 1] + M[1, 1] * rho[1, 1]
+
+
+@pytest.mark.parametrize("n,K", [(1, 2), (2, 3), (3, 6), (4, 3), (3, 2)])
+def test_general_povm_contraction_equals_kronecker(n, K):
+    """Distinct random K-element POVMs per qubit: the per-qubit contraction
+    (probs, adjoint) against explicit Kronecker products (probs_kron,
+    adjoint_kron) on a random Hermitian matrix and a random real vector."""
+    g = S.rng(9000 + 10 * n + K)
+    povms = np.array([random_povm(g, K) for _ in range(n)])
+    for M in povms:
+        assert np.abs(M.sum(axis=0) - np.eye(2)).max() <= 1e-14
+        assert min(np.linalg.eigvalsh(m).min() for m in M) > 0
+    d = 1 << n
+    X = S.ginibre(g, d)
+    X = X + X.conj().T
+    assert np.max(np.abs(O.probs(X, povms) - O.probs_kron(X, povms))) <= 1e-13
+    y = g.standard_normal(K ** n)
+    assert np.max(np.abs(O.adjoint(y, n, povms) - O.adjoint_kron(y, n, povms))) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_general_povm_product_state_closed_form(n):
+    """rho = (x)_i rho_i with distinct Bloch vectors (r_y != 0) and a distinct
+    K = 3 POVM per qubit: p_k = prod_i Tr(M^(i)_{k_i} rho_i), each factor a
+    2 x 2 trace written out.  A wrong qubit order, outcome order, pairing of
+    M with rho, or one qubit's POVM applied to another fails it."""
+    g = S.rng(9100 + n)
+    K = 3
+    povms = np.array([random_povm(g, K) for _ in range(n)])
+    r = g.standard_normal((n, 3))
+    r = 0.9 * r / np.linalg.norm(r, axis=1, keepdims=True)
+    states = [bloch_state(ri) for ri in r]
+    rho = kron_all(states)
+    want = np.array([np.prod([tr2(povms[i][ks[i]], states[i]) for i in range(n)])
+                     for ks in itertools.product(range(K), repeat=n)]).real
+    p = O.probs_real(rho, povms)
+    assert np.max(np.abs(p - want)) <= 1e-15
+    assert abs(math.fsum(p.tolist()) - 1.0) <= 1e-14
+
+
+def test_pauli6_trine_and_basis_closed_forms():
+    """Textbook POVMs with known outcome laws:
+    * Pauli-6 (K = 6), M_{+-j} = (I +- sigma_j)/6: p = prod_i (1 +- r_{i,j})/6;
+    * trine (K = 3), M_k = (2/3)|psi_k><psi_k| with Bloch vectors
+      (sin t_k, 0, cos t_k), t_k = 2 pi k / 3: p = prod_i (1 + n_k . r_i)/3;
+    * computational basis (K = 2), M_b = |b><b|: p_k = rho_kk for any rho
+      (k read as the binary row index, qubit 1 most significant)."""
+    g = S.rng(9200)
+    n = 3
+    r = g.standard_normal((n, 3))
+    r = 0.8 * r / np.linalg.norm(r, axis=1, keepdims=True)
+    rho = kron_all([bloch_state(ri) for ri in r])
+    X, Y, Z = (np.array([[0, 1], [1, 0]], dtype=complex), np.array([[0, -1j], [1j, 0]]),
+               np.array([[1, 0], [0, -1]], dtype=complex))
+    I2 = np.eye(2, dtype=complex)
+    pauli6 = np.array([(I2 + X) / 6, (I2 - X) / 6, (I2 + Y) / 6, (I2 - Y) / 6, (I2 + Z) / 6, (I2 - Z) / 6])
+    law6 = lambda k, ri: (1 + (1 - 2 * (k % 2)) * ri[k // 2]) / 6.0  # noqa: E731
+    want = np.array([np.prod([law6(ks[i], r[i]) for i in range(n)]) for ks in itertools.product(range(6), repeat=n)])
+    assert np.max(np.abs(O.probs_real(rho, pauli6) - want)) <= 1e-15
+    ts = [2 * math.pi * k / 3 for k in range(3)]
+    trine = np.array([(2.0 / 3.0) * np.outer(v, v) for v in
+                      (np.array([math.cos(t / 2), math.sin(t / 2)], dtype=complex) for t in ts)])
+    nk = [np.array([math.sin(t), 0.0, math.cos(t)]) for t in ts]
+    want = np.array([np.prod([(1 + nk[ks[i]] @ r[i]) / 3.0 for i in range(n)])
+                     for ks in itertools.product(range(3), repeat=n)])
+    assert np.max(np.abs(O.probs_real(rho, trine) - want)) <= 1e-15
+    basis = np.array([np.diag([1.0, 0.0]), np.diag([0.0, 1.0])]).astype(complex)
+    m = 6
+    R, _ = O.state_map(S.ginibre(g, 1 << m))
+    assert np.max(np.abs(O.probs_real(R, basis) - np.diag(R).real)) <= 1e-15
+
+
+def test_general_adjoint_dot_product():
+    """<A(X), y> = Re Tr(X A^dagger(y)) for the per-qubit K = 6 map at N = 5
+    (the adjoint is the transpose of the forward contraction)."""
+    g = S.rng(9300)
+    n, K = 5, 6
+    povms = np.array([random_povm(g, K) for _ in range(n)])
+    X = S.ginibre(g, 1 << n)
+    X = X + X.conj().T
+    y = g.standard_normal(K ** n)
+    lhs = float(np.dot(O.probs(X, povms).real, y))
+    rhs = float(np.trace(X @ O.adjoint(y, n, povms)).real)
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_settings_gradient_central_differences(n):
+    """Three settings (K = 2, 3, 6, a random POVM per qubit in each) summed in
+    the loss: the gradient of grad_T_settings against central differences
+    of likelihood_settings on random complex directions, and each setting's
+    p against the single-setting route."""
+    g = S.rng(9400 + n)
+    d = 1 << n
+    T = S.ginibre(g, d)
+    settings = [np.array([random_povm(g, K) for _ in range(n)]) for K in (2, 3, 6)]
+    target, _ = O.state_map(S.ginibre(g, d, 2))
+    fs = [S.multinomial_freqs(g, 20_000, O.probs_real(target, pv)) for pv in settings]
+    grad, L = O.grad_T_settings(T, fs, settings)
+    assert L == pytest.approx(math.fsum(O.likelihood(T, f, pv)[0] for f, pv in zip(fs, settings)), rel=1e-14)
+    h = 1e-6
+    for _ in range(4):
+        E = S.ginibre(g, d)
+        E /= np.linalg.norm(E)
+        fd = (O.likelihood_settings(T + h * E, fs, settings)[0]
+              - O.likelihood_settings(T - h * E, fs, settings)[0]) / (2 * h)
+        an = float(np.sum(grad.real * E.real + grad.imag * E.imag))
+        assert abs(fd - an) <= 1e-7 * np.linalg.norm(grad)
