@@ -188,6 +188,58 @@ qst_status qst_likelihood(int n_qubits, qst_prec prec, const void* T, int64_t ld
                           size_t ws_bytes, void* stream);
 
 /*
+ * General product POVMs (Sec. 3.3 with a POVM of its own on each qubit;
+ * Sec. 2.1, one POVM per measurement setting): qubit i of setting s is
+ * measured with a K-element POVM {M^(s,i)_k}, k = 0..K-1, so a setting has
+ * K^N outcomes k = sum_i k_i K^(N-i) (qubit 1 most significant) with
+ * p^s_k = Tr(rho M^(s,1)_k1 (x) ... (x) M^(s,N)_kN).  2 <= K <= 8,
+ * K^N <= 2^30, 1 <= settings <= 64.
+ *   povm_host [in] host, settings x N x K x 2 x 2 complex (re, im),
+ *                  row-major: element k of qubit i (0-based) of setting s
+ *                  starts at double offset ((s N + i) K + k) 8 as
+ *                  M[0][0], M[0][1], M[1][0], M[1][1].  Every element must
+ *                  be Hermitian and positive semidefinite and each qubit's
+ *                  K elements must sum to I (to 1e-12), else
+ *                  QST_ERR_INVALID_ARG.
+ * Computed through the Pauli coordinates e_b = Tr(P_b1 (x) ... (x) P_bN rho)
+ * of rho (4^N reals, P = I, X, Y, Z) and the real per-qubit factors
+ * Tr(M_k P_b) / 2; FP64 arithmetic for QST_F64, FP32 otherwise.
+ * Workspace: qst_workspace_bytes_general(N, prec, K, op) with op =
+ * QST_OP_POVM_PROBS or QST_OP_LIKELIHOOD (0 for invalid arguments).
+ */
+size_t qst_workspace_bytes_general(int n_qubits, qst_prec prec, int K, int op);
+
+/*
+ * p = K^N probabilities of one general product POVM (settings = 1 layout of
+ * povm_host) from rho (d x d complex, row stride ld_rho, device; only the
+ * lower triangle is read).  p: K^N reals (storage precision), device.
+ */
+qst_status qst_povm_probs_general(int n_qubits, qst_prec prec, const void* rho, int64_t ld_rho, int K,
+                                  const double* povm_host, void* p, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The likelihood over several settings (Eq. MLE summed over the
+ * measurements of Sec. 2.1):
+ *   L = -sum_s sum_k f^s_k ln p^s_k,  rho = T T^dagger / tau,
+ * and the adjoint matrix for qst_grad_product,
+ *   G' = sum_s sum_k (F_s - f^s_k / p^s_k) M^s_k,  F_s = sum_k f^s_k
+ * (each setting's POVM sums to I, which carries the trace normalisation).
+ *   f        [in]  settings x K^N reals (storage precision), setting-major, device.
+ *   tau_dev  [out] one double, device.
+ *   nll_dev  [out] two doubles, device: L (+inf after f_k > 0 with p_k <= 0,
+ *                  NaN after a NaN) and F = sum of every f.
+ *   bad_dev  [out] two uint64 (as qst_nll, over all settings), or NULL.
+ *   G        [out] d x d complex (row stride ldG), written in full, or NULL
+ *                  for the value alone.  Must not overlap T.
+ * dL/dT then follows from qst_grad_product(G, T, tau).  Summation orders
+ * are fixed (settings in order): results are bitwise reproducible.
+ */
+qst_status qst_likelihood_general(int n_qubits, qst_prec prec, const void* T, int64_t ldT, int settings, int K,
+                                  const double* povm_host, const void* f, double* tau_dev, double* nll_dev,
+                                  unsigned long long* bad_dev, void* G, int64_t ldG, void* ws, size_t ws_bytes,
+                                  void* stream);
+
+/*
  * Bytes of the library's static device scratch: the workspace of
  * qst_likelihood_noalloc, one array per GPU, held until the process ends.
  */

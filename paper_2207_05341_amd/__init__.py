@@ -20,7 +20,8 @@ from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MA
 
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
-    "likelihood_forward", "likelihood_forward_noalloc", "likelihood_forward_fc", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
+    "likelihood_forward", "likelihood_forward_noalloc", "likelihood_forward_fc", "povm_probs_general",
+    "likelihood_forward_general", "likelihood_general", "GeneralLikelihoodFn", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
     "abs_map_backward", "AbsMapFn", "AbsProjection", "fidelity_lowrank", "fidelity_general",
     "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
@@ -588,6 +589,85 @@ class LikelihoodFn(torch.autograd.Function):
         p = None if ctx.mode == "recompute" else saved[4]
         grad = nll_backward(T, f, p, None if p is None else tau, ctx.prec, ctx.povm, up, out)
         return grad, None, None, None, None
+
+
+def _general_povm_arg(povms, n: int):
+    """(settings, K, host array) from general product POVMs: (K, 2, 2) (one
+    POVM on every qubit), (N, K, 2, 2) (a POVM per qubit) or
+    (S, N, K, 2, 2) (S settings), complex."""
+    m = torch.as_tensor(povms).to(torch.complex128)
+    if m.dim() == 3:
+        m = m.unsqueeze(0).expand(n, *m.shape)
+    if m.dim() == 4:
+        m = m.unsqueeze(0)
+    if m.dim() != 5 or m.shape[1] != n or tuple(m.shape[3:]) != (2, 2):
+        raise ValueError(f"povms must be (K, 2, 2), (N, K, 2, 2) or (S, N, K, 2, 2) with N = {n}")
+    S, K = int(m.shape[0]), int(m.shape[2])
+    flat = torch.view_as_real(m.contiguous()).reshape(-1).tolist()
+    return S, K, (ctypes.c_double * len(flat))(*flat)
+
+
+def povm_probs_general(rho: torch.Tensor, povms, prec=None) -> torch.Tensor:
+    """K^N probabilities of a product POVM with a K-element POVM per qubit
+    (qst_povm_probs_general); povms (K, 2, 2) or (N, K, 2, 2)."""
+    n, ld = _matrix(rho, "rho")
+    p = _prec(rho.dtype, prec)
+    S, K, arr = _general_povm_arg(povms, n)
+    if S != 1:
+        raise ValueError("povm_probs_general takes one setting")
+    out = torch.empty(K ** n, dtype=real_dtype(p), device=rho.device)
+    nb = int(_lib.lib().qst_workspace_bytes_general(n, p, K, QST_OP_POVM_PROBS))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=rho.device)
+    _lib.check(_lib.lib().qst_povm_probs_general(n, p, rho.data_ptr(), ld, K, arr, out.data_ptr(), ws.data_ptr(), nb,
+                                                 _stream(rho.device)), "qst_povm_probs_general")
+    return out
+
+
+def likelihood_forward_general(T: torch.Tensor, f: torch.Tensor, povms, prec=None, with_grad_matrix: bool = True):
+    """qst_likelihood_general: L summed over the settings and G' for
+    grad_product.  povms as in _general_povm_arg; f of shape (S, K^N) or
+    (K^N,) for one setting.  Returns (out = [L, F], tau, G, bad)."""
+    n, ld = _matrix(T, "T")
+    pr = _prec(T.dtype, prec)
+    S, K, arr = _general_povm_arg(povms, n)
+    f2 = f.reshape(S, K ** n) if f.dim() == 1 else f
+    if tuple(f2.shape) != (S, K ** n) or f2.dtype != real_dtype(pr) or not f2.is_contiguous():
+        raise ValueError(f"f must be a contiguous {real_dtype(pr)} tensor of shape ({S}, {K ** n})")
+    out = torch.empty(2, dtype=torch.float64, device=T.device)
+    bad = torch.empty(2, dtype=torch.int64, device=T.device)
+    tau = torch.empty((), dtype=torch.float64, device=T.device)
+    G = torch.empty(T.shape, dtype=T.dtype, device=T.device) if with_grad_matrix else None
+    nb = int(_lib.lib().qst_workspace_bytes_general(n, pr, K, QST_OP_LIKELIHOOD))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=T.device)
+    _lib.check(_lib.lib().qst_likelihood_general(n, pr, T.data_ptr(), ld, S, K, arr, f2.data_ptr(), tau.data_ptr(),
+                                                 out.data_ptr(), bad.data_ptr(), _ptr(G),
+                                                 0 if G is None else G.stride(0), ws.data_ptr(), nb,
+                                                 _stream(T.device)), "qst_likelihood_general")
+    return out, tau, G, bad
+
+
+class GeneralLikelihoodFn(torch.autograd.Function):
+    """L(T) summed over general product-POVM settings; forward =
+    qst_likelihood_general (L and G'), backward = qst_grad_product."""
+
+    @staticmethod
+    def forward(ctx, T, f, povms, prec):
+        ctx.prec = prec
+        out, tau, G, _ = likelihood_forward_general(T, f, povms, prec, with_grad_matrix=ctx.needs_input_grad[0])
+        ctx.save_for_backward(T, G, tau)
+        return out[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        T, G, tau = ctx.saved_tensors
+        up = g.detach().to(torch.float64).reshape(1).contiguous()
+        return grad_product(G, T, tau, ctx.prec, up), None, None, None
+
+
+def likelihood_general(T: torch.Tensor, f: torch.Tensor, povms, prec=None):
+    """Differentiable negative log-likelihood over general product-POVM
+    settings (a K-element POVM per qubit, several settings)."""
+    return GeneralLikelihoodFn.apply(T, f, povms, prec)
 
 
 def likelihood(T: torch.Tensor, f: torch.Tensor, prec=None, recompute: bool | None = None, povm=None,

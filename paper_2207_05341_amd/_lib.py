@@ -30,6 +30,10 @@ SIGNATURES = {
     "qst_likelihood_fc": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz,
                                  _vp]),
     "qst_likelihood_noalloc": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    "qst_workspace_bytes_general": (_sz, [_int, _int, _int, _int]),
+    "qst_povm_probs_general": (_int, [_int, _int, _vp, _i64, _int, _vp, _vp, _vp, _sz, _vp]),
+    "qst_likelihood_general": (_int, [_int, _int, _vp, _i64, _int, _int, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
+                                       _sz, _vp]),
     "qst_grad_product": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_state_premap": (_int, [_int, _int, _int, _vp, _i64, _vp, _i64, _vp]),
     "qst_abs_map": (_int, [_int, _int, ctypes.c_double, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),

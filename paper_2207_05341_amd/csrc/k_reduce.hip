@@ -308,6 +308,18 @@ hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double
   return hipGetLastError();
 }
 
+hipError_t launch_nll_partials(qst_prec prec, const void* p, const void* f, int64_t D, double* partials,
+                               hipStream_t s) {
+  const int nb = kReduceBlocks;
+  if (prec == QST_F64)
+    nll_partial_kernel<double, true><<<nb, 256, 0, s>>>(static_cast<const double*>(p),
+                                                        static_cast<const double*>(f), D, partials);
+  else
+    nll_partial_kernel<float, true><<<nb, 256, 0, s>>>(static_cast<const float*>(p),
+                                                       static_cast<const float*>(f), D, partials);
+  return hipGetLastError();
+}
+
 hipError_t launch_likelihood_finish(const double* part, int nb, const double* Fpart, double* nll_dev,
                                    unsigned long long* bad_dev, hipStream_t s, double* fc_dev) {
   likelihood_finish_kernel<<<1, 256, 0, s>>>(part, nb, Fpart, nll_dev, bad_dev, fc_dev);

@@ -3,6 +3,7 @@
 // contract of each call.
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "qst_kernels.h"
 #include "qst_plan.h"
@@ -470,7 +471,69 @@ qst_status likelihood_impl(int n, qst_prec prec, const void* T, int64_t ldT, con
 
 }  // namespace
 
+namespace {
+
+GeneralBufs general_bufs(void* ws, const GeneralLayout& L) {
+  return GeneralBufs{reinterpret_cast<double*>(ws_at(ws, L.partials)), reinterpret_cast<double*>(ws_at(ws, L.scal)),
+                     L.inter0 ? ws_at(ws, L.inter0) : nullptr, L.inter1 ? ws_at(ws, L.inter1) : nullptr,
+                     ws_at(ws, L.e), L.h ? ws_at(ws, L.h) : nullptr, ws_at(ws, L.bufA), ws_at(ws, L.bufB),
+                     L.p ? ws_at(ws, L.p) : nullptr};
+}
+
+}  // namespace
+
 extern "C" {
+
+qst_status qst_povm_probs_general(int n, qst_prec prec, const void* rho, int64_t ld_rho, int K,
+                                  const double* povm_host, void* p, void* ws, size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(rho, ld_rho, n, "rho", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(p, "p", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_povm_general(n, K, 1, povm_host, msg)) != QST_OK) return fail(st, msg);
+  const GeneralLayout L = general_layout(n, prec, K, false);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+  std::vector<double> C(size_t(n) * K * 4);
+  general_factors(n, K, 1, povm_host, C.data());
+  hipError_t e = launch_general_probs(prec, n, K, C.data(), rho, ld_rho, p, general_bufs(ws, L),
+                                      static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "general POVM map");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_likelihood_general(int n, qst_prec prec, const void* T, int64_t ldT, int settings, int K,
+                                  const double* povm_host, const void* f, double* tau_dev, double* nll_dev,
+                                  unsigned long long* bad_dev, void* G, int64_t ldG, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(f, "f", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(tau_dev, "tau_dev", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(nll_dev, "nll_dev", msg)) != QST_OK) return fail(st, msg);
+  if (G && (st = check_matrix(G, ldG, n, "G", msg)) != QST_OK) return fail(st, msg);
+  if (G == T) return fail(QST_ERR_INVALID_ARG, "G must not alias T");
+  if ((st = check_povm_general(n, K, settings, povm_host, msg)) != QST_OK) return fail(st, msg);
+  const GeneralLayout L = general_layout(n, prec, K, true);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+  std::vector<double> C(size_t(settings) * n * K * 4);
+  general_factors(n, K, settings, povm_host, C.data());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t d = int64_t(1) << n;
+  void* rho = ws_at(ws, L.rho);
+  hipError_t e = run_state_map(prec, T, ldT, rho, d, n, reinterpret_cast<double*>(ws_at(ws, L.partials)), tau_dev,
+                               L.has_sk ? ws_at(ws, L.sk) : nullptr, s, nullptr, nullptr,
+                               L.has_planes ? ws_at(ws, L.planes) : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "state map");
+  e = launch_general_likelihood(prec, n, K, settings, C.data(), rho, d, f, G, ldG, nll_dev, bad_dev,
+                                general_bufs(ws, L), s);
+  if (e != hipSuccess) return hip_fail(e, "general POVM likelihood");
+  clear_error();
+  return QST_OK;
+}
 
 qst_status qst_grad_product(int n, qst_prec prec, const void* G, int64_t ldG, const void* T, int64_t ldT,
                             const double* tau_dev, const double* upstream_dev, void* gradT, int64_t ld_grad,

@@ -105,6 +105,32 @@ hipError_t launch_povm(bool adjoint, qst_prec prec, const PovmPlan& pl, const do
                        const double* F_dev, void* inter0, void* inter1, hipStream_t s,
                        bool use_fast = true);
 
+// Stage 1 of the NLL over D entries of p and f: FP64 partials [4][kReduceBlocks]
+// (L, F, bad0, bad1) as launch_nll's.
+hipError_t launch_nll_partials(qst_prec prec, const void* p, const void* f, int64_t D, double* partials,
+                               hipStream_t s);
+
+// Workspace pieces of the general-POVM calls (general_layout).
+struct GeneralBufs {
+  double* partials;  // kReduceBlocks x 4
+  double* scal;      // 4 per setting: L_s, F_s, bad0_s, bad1_s
+  void *inter0, *inter1;  // product-POVM pass intermediates
+  void *e, *h;            // 4^N reals: Pauli coordinates of rho; summed adjoint input
+  void *bufA, *bufB;      // max(4, K)^N reals each: the real passes
+  void* p;                // K^N reals: one setting's probabilities
+};
+
+// p (K^N reals) of a product POVM with real Pauli factors C[i][k][b]
+// (general_factors, one setting) from rho.
+hipError_t launch_general_probs(qst_prec prec, int n, int K, const double* C, const void* rho, int64_t ld_rho,
+                                void* p, const GeneralBufs& b, hipStream_t s);
+// Sum over the settings of the NLL (nll_dev = [L, F]) and, with G, the
+// adjoint matrix G' = sum_s sum_k (F_s - f^s_k / p^s_k) M^s_k written in
+// full; f: settings x K^N reals, setting-major.
+hipError_t launch_general_likelihood(qst_prec prec, int n, int K, int settings, const double* C, const void* rho,
+                                     int64_t ld_rho, const void* f, void* G, int64_t ldG, double* nll_dev,
+                                     unsigned long long* bad_dev, const GeneralBufs& b, hipStream_t s);
+
 // nll[0] = L, nll[1] = F, bad[0..1] counts (bad may be NULL).
 hipError_t launch_nll(qst_prec prec, const void* p, const void* f, int n, double* partials,
                       double* nll_dev, unsigned long long* bad_dev, hipStream_t s);

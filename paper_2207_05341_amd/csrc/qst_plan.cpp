@@ -348,9 +348,143 @@ void povm_mode_matrices(const double* M, double W[32], double V[32]) {
   }
 }
 
+int64_t general_outcomes(int n, int K) {
+  int64_t D = 1;
+  for (int i = 0; i < n; ++i) {
+    D *= K;
+    if (D > kGeneralMaxOutcomes) return -1;
+  }
+  return D;
+}
+
+qst_status check_povm_general(int n, int K, int settings, const double* M, std::string& msg) {
+  if (K < 2 || K > kGeneralMaxK) {
+    msg = "K=" + std::to_string(K) + " outside [2, " + std::to_string(kGeneralMaxK) + "]";
+    return QST_ERR_INVALID_ARG;
+  }
+  if (settings < 1 || settings > kGeneralMaxSettings) {
+    msg = "settings=" + std::to_string(settings) + " outside [1, " + std::to_string(kGeneralMaxSettings) + "]";
+    return QST_ERR_INVALID_ARG;
+  }
+  if (general_outcomes(n, K) < 0) {
+    msg = "K^N = " + std::to_string(K) + "^" + std::to_string(n) + " exceeds 2^30 outcomes";
+    return QST_ERR_UNSUPPORTED;
+  }
+  if (!M) {
+    msg = "povm_host is NULL";
+    return QST_ERR_INVALID_ARG;
+  }
+  for (int s = 0; s < settings; ++s) {
+    for (int i = 0; i < n; ++i) {
+      const double* P = M + (int64_t(s) * n + i) * K * 8;
+      double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      const std::string where = "setting " + std::to_string(s) + ", qubit " + std::to_string(i + 1);
+      for (int k = 0; k < K; ++k) {
+        const double* m = P + 8 * k;  // [0][0], [0][1], [1][0], [1][1] as (re, im)
+        for (int j = 0; j < 8; ++j) {
+          if (!std::isfinite(m[j])) {
+            msg = where + ": POVM entry is not finite";
+            return QST_ERR_INVALID_ARG;
+          }
+          sum[j] += m[j];
+        }
+        if (std::fabs(m[1]) > 1e-12 || std::fabs(m[7]) > 1e-12 || std::fabs(m[2] - m[4]) > 1e-12 ||
+            std::fabs(m[3] + m[5]) > 1e-12) {
+          msg = where + ": element " + std::to_string(k) + " is not Hermitian";
+          return QST_ERR_INVALID_ARG;
+        }
+        // smallest eigenvalue of [[a, b], [conj b, c]]
+        const double a = m[0], c = m[6], h = 0.5 * (a - c);
+        const double lmin = 0.5 * (a + c) - std::sqrt(h * h + m[2] * m[2] + m[3] * m[3]);
+        if (lmin < -1e-12) {
+          msg = where + ": element " + std::to_string(k) + " is not positive semidefinite";
+          return QST_ERR_INVALID_ARG;
+        }
+      }
+      const double eye[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+      for (int j = 0; j < 8; ++j) {
+        if (std::fabs(sum[j] - eye[j]) > 1e-12) {
+          msg = where + ": POVM elements do not sum to the identity";
+          return QST_ERR_INVALID_ARG;
+        }
+      }
+    }
+  }
+  return QST_OK;
+}
+
+void general_factors(int n, int K, int settings, const double* M, double* C) {
+  for (int s = 0; s < settings; ++s)
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < K; ++k) {
+        const double* m = M + ((int64_t(s) * n + i) * K + k) * 8;
+        double* c = C + ((int64_t(s) * n + i) * K + k) * 4;
+        // Tr(M I), Tr(M X) = 2 Re M01, Tr(M Y) = -2 Im M01, Tr(M Z), halved
+        // (M Hermitian: M10 = conj M01)
+        c[0] = 0.5 * (m[0] + m[6]);
+        c[1] = m[2];
+        c[2] = -m[3];
+        c[3] = 0.5 * (m[0] - m[6]);
+      }
+}
+
+void pauli_mode_matrices(double W[32], double V[32]) {
+  // I, X, Y = [[0, -i], [i, 0]], Z as K = 4 matrices in the povm_host layout
+  const double P[32] = {1, 0, 0, 0, 0, 0, 1, 0,    // I
+                        0, 0, 1, 0, 1, 0, 0, 0,    // X
+                        0, 0, 0, -1, 0, 1, 0, 0,   // Y
+                        1, 0, 0, 0, 0, 0, -1, 0};  // Z
+  povm_mode_matrices(P, W, V);
+}
+
+GeneralLayout general_layout(int n, qst_prec prec, int K, bool with_state) {
+  GeneralLayout w;
+  const size_t cb = complex_bytes(prec), rb = real_bytes(prec);
+  const size_t d = size_t(1) << n, D = d * d;
+  const int64_t DK = general_outcomes(n, K);
+  const size_t M = DK < 0 ? D : std::max(D, size_t(DK));  // largest mixed tensor of the real passes
+  const PovmPlan pl = make_povm_plan(n, prec);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
+  w.scal = take(size_t(4 * kGeneralMaxSettings + 8) * sizeof(double));
+  if (pl.passes >= 2) w.inter0 = take(D * cb);
+  if (pl.passes >= 3) w.inter1 = take(D * cb);
+  w.e = take(D * rb);
+  w.bufA = take(M * rb);
+  w.bufB = take(M * rb);
+  if (with_state) {
+    w.h = take(D * rb);
+    w.p = take((DK < 0 ? 0 : size_t(DK)) * rb);
+    w.rho = take(D * cb);
+    if (prec == QST_BF16GEMM && d > size_t(kBf16SplitMaxDim)) {
+      w.planes = take(2 * D * sizeof(uint16_t));
+      w.has_planes = true;
+    }
+    if (n >= kStreamKMinQubits) {
+      w.sk = take(stream_k_partial_bytes(prec));
+      w.has_sk = true;
+    }
+  }
+  w.total = off;
+  return w;
+}
+
 }  // namespace qst
 
 extern "C" {
+
+size_t qst_workspace_bytes_general(int n_qubits, qst_prec prec, int K, int op) {
+  std::string msg;
+  if (qst::check_common(n_qubits, prec, msg) != QST_OK) return 0;
+  if (K < 2 || K > qst::kGeneralMaxK || qst::general_outcomes(n_qubits, K) < 0) return 0;
+  if (op != QST_OP_POVM_PROBS && op != QST_OP_LIKELIHOOD) return 0;
+  return qst::general_layout(n_qubits, prec, K, op == QST_OP_LIKELIHOOD).total;
+}
 
 size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op) {
   std::string msg;

@@ -135,4 +135,34 @@ const char* last_error_cstr();
 // double[32], from a POVM given as in qst_povm_probs.
 void povm_mode_matrices(const double* povm_host, double W[32], double V[32]);
 
+// General product POVMs (qst_povm_probs_general, qst_likelihood_general):
+// K outcomes per qubit (2 <= K <= kGeneralMaxK), a POVM of its own on each
+// qubit, up to kGeneralMaxSettings settings, K^N <= kGeneralMaxOutcomes.
+constexpr int kGeneralMaxK = 8;
+constexpr int kGeneralMaxSettings = 64;
+constexpr int64_t kGeneralMaxOutcomes = int64_t(1) << 30;
+// K^N, or -1 when it exceeds kGeneralMaxOutcomes.
+int64_t general_outcomes(int n, int K);
+// Shape limits and, for every setting and qubit, a POVM: each element
+// Hermitian and positive semidefinite, the K elements summing to I
+// (povm_host: settings x N x K x 2 x 2 complex (re, im), row-major).
+qst_status check_povm_general(int n, int K, int settings, const double* povm_host, std::string& msg);
+// Real per-qubit factors C[s][i][k][b] = Tr(M^(s,i)_k P_b) / 2 over the
+// Pauli basis P = (I, X, Y, Z): Tr(M_k sigma) = sum_b C[k][b] Tr(P_b sigma).
+void general_factors(int n, int K, int settings, const double* povm_host, double* C);
+// Mode matrices (as povm_mode_matrices) of the Pauli set (I, X, Y, Z):
+// the forward map then gives the Pauli coordinates Tr(P_b rho), the
+// adjoint map the synthesis sum_b h_b P_b.
+void pauli_mode_matrices(double W[32], double V[32]);
+
+// Workspace of the general-POVM calls (byte offsets).  with_state: the
+// likelihood call (state map, rho, settings' probabilities, adjoint);
+// otherwise qst_povm_probs_general (Pauli passes and the real passes).
+struct GeneralLayout {
+  size_t partials = 0, scal = 0, sk = 0, planes = 0, rho = 0, inter0 = 0, inter1 = 0;
+  size_t e = 0, h = 0, bufA = 0, bufB = 0, p = 0, total = 0;
+  bool has_sk = false, has_planes = false;
+};
+GeneralLayout general_layout(int n, qst_prec prec, int K, bool with_state);
+
 }  // namespace qst

@@ -165,8 +165,10 @@ __device__ __forceinline__ void kd_pass_body(const PassArgs& a, const ModeMatrix
   tri_decode(lb / nchunks, Rhi, Chi);
   const int64_t kd0 = ch * J;
   const int64_t obase = ((int64_t(Rhi) << Up) | Chi) * (kd * TILE);
+  // adjoint from the outcome side: the cotangent F - f/p of (f, p), or with
+  // p == NULL the values of f as given
   double F = 0.0;
-  if constexpr (ADJ && PSIDE) F = *a.F;
+  if constexpr (ADJ && PSIDE) F = a.p ? *a.F : 0.0;
 
 #pragma unroll
   for (int step = 0; step < RD::n; ++step) {
@@ -199,7 +201,8 @@ __device__ __forceinline__ void kd_pass_body(const PassArgs& a, const ModeMatrix
           const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
           if constexpr (PSIDE) {
             const int64_t k = int64_t(kg) * kd + kd0 + j;
-            x[m] = Cx<R>{cotangent(F, static_cast<const R*>(a.f)[k], static_cast<const R*>(a.p)[k]), R(0)};
+            const R fk = static_cast<const R*>(a.f)[k];
+            x[m] = Cx<R>{a.p ? cotangent(F, fk, static_cast<const R*>(a.p)[k]) : fk, R(0)};
           } else {
             x[m] = static_cast<const Cx<R>*>(a.in)[obase + int64_t(kg) * kd + kd0 + j];
           }

@@ -208,8 +208,11 @@ __device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatri
   const int lgE = 2 * g + lgJ;
   const int lgC = 2 * (n - U) - lgJ;  // chunks of J outcome digits per pair
 
+  // outcome side in: the cotangent F - f/p of (f, p), or with p == NULL the
+  // values of f as given
   double F = 0.0;
-  if constexpr (PSIDE) F = *a.F;
+  [[maybe_unused]] const bool direct = a.p == nullptr;
+  if constexpr (PSIDE) F = direct ? 0.0 : *a.F;
   const int total = elems * nb;
   BlockWalk<UNI> walk(bid0, lgC, lgJ);
   for (int base0 = 0; base0 < total; base0 += LB * int(blockDim.x)) {
@@ -231,7 +234,7 @@ __device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatri
       if constexpr (PSIDE) {
         const int64_t k = int64_t(kg) * kd + kd0 + j;
         vr[u] = static_cast<const R*>(a.f)[k];
-        vi[u] = static_cast<const R*>(a.p)[k];
+        vi[u] = direct ? R(1) : static_cast<const R*>(a.p)[k];
       } else {
         const int64_t base = ((int64_t(Rhi) << Up) | Chi) * (kd * tile);
         const Cx<R> v = static_cast<const Cx<R>*>(a.in)[base + int64_t(kg) * kd + kd0 + j];
@@ -243,7 +246,7 @@ __device__ __forceinline__ void adj_pass_impl(const PassArgs& a, const ModeMatri
     for (int u = 0; u < LB; ++u) {
       if (dst[u] < 0) continue;
       // cotangent g'_k = F - f_k / p_k (F where f_k = 0)
-      if constexpr (PSIDE) buf[dst[u]] = Cx<R>{cotangent(F, vr[u], vi[u]), R(0)};
+      if constexpr (PSIDE) buf[dst[u]] = Cx<R>{direct ? vr[u] : cotangent(F, vr[u], vi[u]), R(0)};
       else buf[dst[u]] = Cx<R>{vr[u], vi[u]};
     }
   }

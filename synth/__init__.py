@@ -113,3 +113,16 @@ def unit_directions(g: np.random.Generator, d: int, count: int) -> list[np.ndarr
 def batch_qubit_counts(g: np.random.Generator, count: int, lo: int = 3, hi: int = 8) -> np.ndarray:
     """Qubit counts drawn uniformly from {lo, ..., hi} for batched instances."""
     return g.integers(lo, hi + 1, size=count)
+
+
+def random_povm(g: np.random.Generator, K: int) -> np.ndarray:
+    """A random K-element single-qubit POVM, shape (K, 2, 2): A_k = B_k B_k^dagger
+    (B_k complex Gaussian 2 x 2), made to sum to I as S^(-1/2) A_k S^(-1/2)
+    with S = sum_k A_k.  Every element is full rank."""
+    A = []
+    for _ in range(K):
+        B = g.standard_normal((2, 2)) + 1j * g.standard_normal((2, 2))
+        A.append(B @ B.conj().T)
+    w, v = np.linalg.eigh(sum(A))
+    s = (v / np.sqrt(w)) @ v.conj().T
+    return np.array([s @ a @ s for a in A])

@@ -226,6 +226,48 @@ def test_likelihood_noalloc_limits(L):
         == lib_mod.QST_ERR_INVALID_ARG
 
 
+def test_general_povm_validation(L):
+    """qst_povm_probs_general / qst_likelihood_general reject, before any
+    device call: K outside [2, 8], settings outside [1, 64], K^N above 2^30,
+    a NULL table, and per qubit a non-Hermitian or non-PSD element or
+    elements that do not sum to I; the workspace sizes grow with K."""
+    import numpy as np
+
+    def table(mats):
+        flat = np.ascontiguousarray(np.asarray(mats, dtype=np.complex128)).view(np.float64).ravel()
+        return (ctypes.c_double * flat.size)(*flat.tolist())
+
+    proj = np.array([np.diag([1.0, 0.0]), np.diag([0.0, 1.0])]).astype(complex)
+    n, d = 3, 8
+    ws = L.qst_workspace_bytes_general(n, 1, 2, lib_mod.QST_OP_LIKELIHOOD)
+    assert ws > 0 and L.qst_workspace_bytes_general(n, 1, 6, lib_mod.QST_OP_LIKELIHOOD) > ws
+    assert L.qst_workspace_bytes_general(n, 1, 9, lib_mod.QST_OP_LIKELIHOOD) == 0
+    assert L.qst_workspace_bytes_general(n, 1, 2, lib_mod.QST_OP_NLL) == 0
+    W = ctypes.c_void_p(0x30000)
+
+    def lik(tab, K=2, S=1, nq=n):
+        return L.qst_likelihood_general(nq, 1, FAKE, 1 << nq, S, K, tab, FAKE2, FAKE, FAKE2, None, None, 0, W, ws,
+                                        None)
+
+    good = table([proj] * n)
+    assert lik(None) == lib_mod.QST_ERR_INVALID_ARG and "NULL" in _err(L)
+    assert lik(good, K=1) == lib_mod.QST_ERR_INVALID_ARG and "K=1" in _err(L)
+    assert lik(good, K=9) == lib_mod.QST_ERR_INVALID_ARG
+    assert lik(good, S=0) == lib_mod.QST_ERR_INVALID_ARG and "settings" in _err(L)
+    assert lik(good, S=65) == lib_mod.QST_ERR_INVALID_ARG
+    assert lik(table([proj] * 13), K=8, nq=11) == lib_mod.QST_ERR_UNSUPPORTED and "2^30" in _err(L)
+    nonherm = proj.copy()
+    nonherm[0, 0, 1] = 0.1
+    assert lik(table([proj, nonherm, proj])) == lib_mod.QST_ERR_INVALID_ARG and "qubit 2" in _err(L) \
+        and "Hermitian" in _err(L)
+    notpsd = np.array([np.diag([1.2, 0.0]), np.diag([-0.2, 1.0])]).astype(complex)
+    assert lik(table([proj, proj, notpsd])) == lib_mod.QST_ERR_INVALID_ARG and "positive" in _err(L)
+    short = np.array([np.diag([0.9, 0.0]), np.diag([0.0, 1.0])]).astype(complex)
+    assert lik(table([short, proj, proj])) == lib_mod.QST_ERR_INVALID_ARG and "identity" in _err(L)
+    wsp = L.qst_workspace_bytes_general(n, 1, 2, lib_mod.QST_OP_POVM_PROBS)
+    assert L.qst_povm_probs_general(n, 1, FAKE, d, 2, good, FAKE2, W, wsp - 1, None) == lib_mod.QST_ERR_WORKSPACE
+
+
 def test_grad_product_validation(L):
     n, d = 10, 1024
     ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_GRAD_PRODUCT)

@@ -738,15 +738,7 @@ def test_rprop_step_matches_the_library_optimiser():
 # --------------------------------------------------------------------------
 
 def random_povm(g, K):
-    """A random K-element qubit POVM: A_k = B_k B_k^dagger made to sum to I
-    by S^(-1/2) A_k S^(-1/2), S = sum A_k (full rank elements)."""
-    A = []
-    for _ in range(K):
-        B = g.standard_normal((2, 2)) + 1j * g.standard_normal((2, 2))
-        A.append(B @ B.conj().T)
-    w, v = np.linalg.eigh(sum(A))
-    s = (v / np.sqrt(w)) @ v.conj().T
-    return np.array([s @ a @ s for a in A])
+    return S.random_povm(g, K)
 
 
 def tr2(M, rho):
