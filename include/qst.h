@@ -342,9 +342,12 @@ qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X
  * qst_likelihood) gives rho = Q |Lambda|^P Q^dagger / Tr |Lambda|^P, the
  * P-order absolute projection; P = 2 is Chol_H (Eq. unified_DP).
  * The eigendecomposition is a cyclic two-sided Jacobi method in FP64 on the
- * device, whatever prec; the call synchronises the stream once per sweep
- * (it reads the off-diagonal norm on the host to stop: at 1e-14 of ||H||_F
- * for QST_F64, 1e-10 for the FP32-storage precisions).
+ * device, whatever prec.  After each sweep a kernel decides on the device
+ * whether to stop (off-diagonal norm at 1e-14 of ||H||_F for QST_F64, 1e-10
+ * for the FP32-storage precisions, or at the rounding floor); this call
+ * reads that decision on the host after each sweep to stop enqueuing (so it
+ * synchronises the stream once per sweep).  qst_abs_map_async is the same
+ * map without any synchronisation.
  *   P      [in]  finite, >= 0.
  *   T      [in]  d x d complex (prec's storage type), row stride ldT, device.
  *   Q0     [in]  NULL, or a warm start: a unitary d x d complex FP64 matrix
@@ -368,6 +371,26 @@ qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X
  */
 qst_status qst_abs_map(int n_qubits, qst_prec prec, double P, const void* T, int64_t ldT, const void* Q0, void* A,
                        int64_t ldA, void* Q, double* lam, int* sweeps, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * qst_abs_map for streams that must not be synchronised (HIP graph capture,
+ * pipelined training loops): at most max_sweeps Jacobi sweeps are enqueued
+ * (1 <= max_sweeps <= 40) and the stopping rule is applied on the device
+ * after each; rounds after convergence return at once (an empty launch
+ * each), and A, Q and lam are then computed as by qst_abs_map.  Nothing is
+ * read back and the call returns before the work runs.
+ *   sweeps_dev [out] one int, device: the sweeps taken, or -1 when the
+ *                    off-diagonal norm was not finite or had not met the
+ *                    stopping rule after max_sweeps (A, Q and lam are then
+ *                    those of the last sweep and must not be used).
+ * A warm start (Q0 from the previous step) usually needs 2 or 3 sweeps at
+ * the training-loop pace (T moved by about 1e-3 of its scale); a cold start
+ * about 10 to 12 at d = 1024.  Other arguments, workspace and argument errors
+ * as qst_abs_map.
+ */
+qst_status qst_abs_map_async(int n_qubits, qst_prec prec, double P, const void* T, int64_t ldT, const void* Q0,
+                             void* A, int64_t ldA, void* Q, double* lam, int max_sweeps, int* sweeps_dev, void* ws,
+                             size_t ws_bytes, void* stream);
 
 /*
  * Adjoint of qst_abs_map: dL/dT from dL/dA (both the gradient convention of
@@ -406,12 +429,24 @@ qst_status qst_abs_map_backward(int n_qubits, qst_prec prec, double P, const voi
  *                (not checked), row stride ldR, device.
  *   F_dev  [out] one double, device.
  *   sweeps [out] host int, may be NULL: the Jacobi sweeps taken.
- * Workspace: qst_workspace_bytes(N, prec, QST_OP_ABS_MAP).  Synchronises the
- * stream once per sweep.  QST_ERR_INVALID_ARG when the sweeps do not
- * converge (non-finite input).
+ * Workspace: qst_workspace_bytes(N, prec, QST_OP_ABS_MAP).  Reads the
+ * device's stopping decision after each sweep (one synchronisation per
+ * sweep; qst_fidelity_general_async has none).  QST_ERR_INVALID_ARG when
+ * the sweeps do not converge (non-finite input).
  */
 qst_status qst_fidelity_general(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* rho,
                                 int64_t ldR, double* F_dev, int* sweeps, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * qst_fidelity_general without synchronisation: at most max_sweeps sweeps
+ * (1..40) with the stopping rule applied on the device, F_q computed from
+ * the last of them; sweeps_dev [out] one device int, the sweeps taken or -1
+ * (not finite, or not converged: F_dev must not be used then).  Other
+ * arguments as qst_fidelity_general.
+ */
+qst_status qst_fidelity_general_async(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* rho,
+                                      int64_t ldR, double* F_dev, int max_sweeps, int* sweeps_dev, void* ws,
+                                      size_t ws_bytes, void* stream);
 
 /*
  * Quantum fidelity against a target of low rank r (Sec. 2.3 Eq. F_QF):

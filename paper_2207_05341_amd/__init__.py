@@ -22,7 +22,8 @@ __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
     "likelihood_forward", "likelihood_forward_noalloc", "likelihood_forward_fc", "povm_probs_general",
     "likelihood_forward_general", "likelihood_general", "GeneralLikelihoodFn", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
-    "abs_map_backward", "AbsMapFn", "AbsProjection", "fidelity_lowrank", "fidelity_general",
+    "abs_map_backward", "abs_map_async", "AbsMapFn", "AbsProjection", "fidelity_lowrank", "fidelity_general",
+    "fidelity_general_async",
     "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
     "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
 ]
@@ -152,6 +153,34 @@ def abs_map(T: torch.Tensor, P: float, prec=None, out: torch.Tensor | None = Non
     return out, Q, lam, sweeps.value
 
 
+def abs_map_async(T: torch.Tensor, P: float, prec=None, max_sweeps: int = 16, out: torch.Tensor | None = None,
+                  Q0: torch.Tensor | None = None, Q: torch.Tensor | None = None, lam: torch.Tensor | None = None,
+                  sweeps: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """abs_map without synchronisation (qst_abs_map_async): at most
+    max_sweeps Jacobi sweeps, the stopping rule applied on the device.
+    Returns (A, Q, lam, sweeps) with sweeps a 0-dim int32 device tensor
+    (the sweeps taken, -1 when not converged: then A, Q and lam are not
+    valid).  Every output and the workspace may be passed in, so that the
+    call can be captured in a HIP graph without allocating."""
+    n, ld = _matrix(T, "T")
+    p = _prec(T.dtype, prec)
+    d = 1 << n
+    if Q0 is not None and (Q0.shape != (d, d) or Q0.dtype != torch.complex128 or not Q0.is_contiguous()
+                           or Q0.device != T.device):
+        raise ValueError("Q0 must be a d x d contiguous complex128 matrix on T's device")
+    out = torch.empty((d, d), dtype=T.dtype, device=T.device) if out is None else out
+    Q = torch.empty((d, d), dtype=torch.complex128, device=T.device) if Q is None else Q
+    lam = torch.empty(d, dtype=torch.float64, device=T.device) if lam is None else lam
+    sweeps = torch.empty((), dtype=torch.int32, device=T.device) if sweeps is None else sweeps
+    nb = workspace_bytes(n, p, QST_OP_ABS_MAP)
+    if ws is None:
+        ws, nb = _workspace(n, p, QST_OP_ABS_MAP, T.device)
+    _lib.check(_lib.lib().qst_abs_map_async(n, p, float(P), T.data_ptr(), ld, _ptr(Q0), out.data_ptr(), out.stride(0),
+                                            Q.data_ptr(), lam.data_ptr(), int(max_sweeps), sweeps.data_ptr(),
+                                            _ptr(ws), nb, _stream(T.device)), "qst_abs_map_async")
+    return out, Q, lam, sweeps
+
+
 def abs_map_backward(Q: torch.Tensor, lam: torch.Tensor, P: float, GA: torch.Tensor, prec=None,
                      out: torch.Tensor | None = None) -> torch.Tensor:
     """dL/dT from dL/dA through the absolute map (qst_abs_map_backward)."""
@@ -175,12 +204,21 @@ class AbsMapFn(torch.autograd.Function):
     """T' = Q |Lambda|^(P/2) Q^dagger of the Hermitian part of T, backward by
     qst_abs_map_backward (saves Q and the eigenvalues).  state: None, or a
     dict whose "Q" (if present) warm-starts the eigensolver and receives
-    this call's Q and sweeps."""
+    this call's Q and sweeps; with state["max_sweeps"] set and a warm start,
+    the call is the unsynchronised qst_abs_map_async with that bound (its
+    sweeps a device tensor)."""
 
     @staticmethod
     def forward(ctx, T, P, prec, state=None):
         Q0 = None if state is None else state.get("Q")
-        A, Q, lam, sweeps = abs_map(T, P, prec, Q0=Q0)
+        bound = None if state is None else state.get("max_sweeps")
+        if Q0 is not None and bound:
+            prev = state.get("sweeps")
+            if isinstance(prev, torch.Tensor) and int(prev.item()) < 0:
+                raise QstError(1, "qst_abs_map_async", "the previous call had not converged within max_sweeps")
+            A, Q, lam, sweeps = abs_map_async(T, P, prec, max_sweeps=bound, Q0=Q0)
+        else:
+            A, Q, lam, sweeps = abs_map(T, P, prec, Q0=Q0)
         if state is not None:
             state["Q"], state["sweeps"] = Q, sweeps
         ctx.P, ctx.prec = P, prec
@@ -196,21 +234,29 @@ class AbsMapFn(torch.autograd.Function):
 class AbsProjection:
     """The P-order absolute map for a training loop: each call returns
     T' = Q |Lambda|^(P/2) Q^dagger (differentiable) and keeps Q to warm-start
-    the next call's eigensolver.  Use as likelihood(proj(T), f)."""
+    the next call's eigensolver.  Use as likelihood(proj(T), f).
 
-    def __init__(self, P: float, prec=None):
+    max_sweeps: None -- every call synchronises once per sweep to stop;
+    an int -- the warm-started calls (all but the first) run without any
+    synchronisation, at most that many sweeps, and a call that had not
+    converged is reported by the next one (QstError)."""
+
+    def __init__(self, P: float, prec=None, max_sweeps: int | None = None):
         self.P, self.prec = float(P), prec
+        self.max_sweeps = max_sweeps
         self.state: dict = {}
 
     def __call__(self, T: torch.Tensor) -> torch.Tensor:
         Q = self.state.get("Q")
         if Q is not None and (Q.shape != (T.shape[0], T.shape[0]) or Q.device != T.device):
             self.state = {}
+        self.state["max_sweeps"] = self.max_sweeps
         return AbsMapFn.apply(T, self.P, self.prec, self.state)
 
     @property
     def sweeps(self) -> int | None:
-        return self.state.get("sweeps")
+        s = self.state.get("sweeps")
+        return int(s.item()) if isinstance(s, torch.Tensor) else s
 
 
 class StatePremapFn(torch.autograd.Function):
@@ -394,6 +440,24 @@ def fidelity_lowrank(T: torch.Tensor, W: torch.Tensor, prec=None) -> torch.Tenso
     _lib.check(_lib.lib().qst_fidelity_lowrank(n, pr, T.data_ptr(), ld, W.data_ptr(), W.stride(0), r, F.data_ptr(),
                                                _ptr(ws), nb, _stream(T.device)), "qst_fidelity_lowrank")
     return F
+
+
+def fidelity_general_async(T: torch.Tensor, rho: torch.Tensor, prec=None, max_sweeps: int = 16):
+    """fidelity_general without synchronisation (qst_fidelity_general_async):
+    returns (F, sweeps), a 0-dim float64 and a 0-dim int32 device tensor
+    (sweeps -1: not converged within max_sweeps, F not valid)."""
+    n, ld = _matrix(T, "T")
+    n2, ldr = _matrix(rho, "rho")
+    if n2 != n or rho.dtype != T.dtype:
+        raise ValueError("rho must match T in size and dtype")
+    pr = _prec(T.dtype, prec)
+    F = torch.empty((), dtype=torch.float64, device=T.device)
+    sweeps = torch.empty((), dtype=torch.int32, device=T.device)
+    ws, nb = _workspace(n, pr, QST_OP_ABS_MAP, T.device)
+    _lib.check(_lib.lib().qst_fidelity_general_async(n, pr, T.data_ptr(), ld, rho.data_ptr(), ldr, F.data_ptr(),
+                                                     int(max_sweeps), sweeps.data_ptr(), _ptr(ws), nb,
+                                                     _stream(T.device)), "qst_fidelity_general_async")
+    return F, sweeps
 
 
 def fidelity_general(T: torch.Tensor, rho: torch.Tensor, prec=None):

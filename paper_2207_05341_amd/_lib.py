@@ -37,6 +37,9 @@ SIGNATURES = {
     "qst_grad_product": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_state_premap": (_int, [_int, _int, _int, _vp, _i64, _vp, _i64, _vp]),
     "qst_abs_map": (_int, [_int, _int, ctypes.c_double, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "qst_abs_map_async": (_int, [_int, _int, ctypes.c_double, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _int, _vp, _vp,
+                                  _sz, _vp]),
+    "qst_fidelity_general_async": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _int, _vp, _vp, _sz, _vp]),
     "qst_abs_map_backward": (_int, [_int, _int, ctypes.c_double, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "qst_fnn_forward": (_int, [_int, _int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_fnn_backward": (_int, [_int, _int, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),

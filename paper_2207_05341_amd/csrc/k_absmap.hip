@@ -20,10 +20,17 @@
 // diag(1, e^(-i phi)) makes the 2 x 2 block real symmetric and the classical
 // rotation angle (tangent t of the smaller root of t^2 + 2 zeta t - 1 = 0,
 // zeta = (b - a) / (2 |c|)) diagonalises it.  After each sweep (d - 1
-// rounds) the host reads the off-diagonal norm; sweeps stop when it is
-// below 1e-14 of ||H||_F (1e-10 for FP32 storage), or below 1e-10 of it
-// and no longer falling by half (the rounding floor), which Jacobi's
-// quadratic convergence reaches in a few sweeps.
+// rounds) a one-workgroup kernel sums the off-diagonal norm and decides on
+// the device: the sweeps stop when it is below 1e-14 of ||H||_F (1e-10 for
+// FP32 storage), or below 1e-10 of it and no longer falling by half (the
+// rounding floor), which Jacobi's quadratic convergence reaches in a few
+// sweeps.  The decision sets a flag in the workspace that every later round
+// kernel reads first and returns on, so a fixed number of enqueued sweeps
+// (the graph-capturable calls) costs one empty launch per skipped round;
+// the synchronous calls read the flag on the host after each sweep and
+// stop enqueuing.  d - 1 is odd, so the diagonalised matrix sits in the
+// first ping-pong buffer after an even number of sweeps and in the second
+// after an odd one; the state records which.
 //
 // Adjoint: for a spectral function A = g(H), g(l) = |l|^(P/2), the
 // first-order change is Q (Gamma o (Q^dagger dH Q)) Q^dagger with Gamma the
@@ -53,7 +60,6 @@ namespace {
 using C64 = Cx<double>;
 
 constexpr int kTB = 32;          // tile side of the transposes
-constexpr int kMaxSweeps = 40;   // Jacobi sweeps before giving up (non-finite input)
 
 __device__ __forceinline__ C64 cmul(C64 a, C64 b) { return C64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ __forceinline__ C64 cscale(C64 a, double s) { return C64{a.re * s, a.im * s}; }
@@ -104,9 +110,27 @@ __device__ __forceinline__ Rot rot_of(const C64* A, int d, int p, int q) {
 // and diagonal entries it wrote.
 constexpr int kRoundThreads = 128;
 
+// Device-side state of the sweeps (in the workspace).
+struct JacobiState {
+  int done;     // 1 once the stopping rule held (or the norm was not finite)
+  int sweeps;   // sweeps taken when done, -1 if not converged or not finite
+  int parity;   // buffer of the diagonalised matrix: 0 = first, 1 = second
+  int pad;
+  double prev;  // relative off-diagonal norm after the previous sweep
+};
+
+__global__ void jacobi_reset_kernel(JacobiState* st) {
+  st->done = 0;
+  st->sweeps = -1;
+  st->parity = 0;
+  st->prev = HUGE_VAL;
+}
+
 __global__ __launch_bounds__(kRoundThreads) void jacobi_round_kernel(const C64* __restrict__ Ain,
                                                                      C64* __restrict__ Aout, C64* __restrict__ Vt,
-                                                                     int d, int t, double* __restrict__ part) {
+                                                                     int d, int t, double* __restrict__ part,
+                                                                     const JacobiState* __restrict__ st) {
+  if (st->done) return;  // converged in an earlier sweep: nothing to rotate
   __shared__ double red[2][kRoundThreads / 64];
   const int m = d - 1, half = d >> 1;
   const int k = blockIdx.x, c = blockIdx.y;
@@ -189,6 +213,43 @@ __global__ __launch_bounds__(256) void jacobi_norms_kernel(const double* __restr
   }
 }
 
+// After sweep `sweep` (of at most max_sweeps): the off-diagonal and
+// diagonal squared norms from the round partials (fixed order), and the
+// stopping rule.  Nothing once done.
+__global__ __launch_bounds__(256) void jacobi_check_kernel(const double* __restrict__ part, int count,
+                                                           JacobiState* __restrict__ st, double tol, int sweep,
+                                                           int max_sweeps) {
+  if (st->done) return;
+  __shared__ double lds4[4];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < count; k += 256) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  a = block_sum256(a, lds4);
+  b = block_sum256(b, lds4);
+  if (threadIdx.x != 0) return;
+  const double off = a, tot = a + b;
+  st->parity = sweep & 1;
+  if (!isfinite(off) || !isfinite(tot)) {
+    st->done = 1;
+    st->sweeps = -1;
+    return;
+  }
+  const double r = tot > 0.0 ? sqrt(off / tot) : 0.0;
+  if (r <= tol || (r <= 1e-10 && r > 0.5 * st->prev)) {
+    st->done = 1;
+    st->sweeps = sweep;
+  } else {
+    st->prev = r;
+    if (sweep >= max_sweeps) st->done = 1;  // sweeps stays -1: not converged
+  }
+}
+
+__global__ void jacobi_sweeps_out_kernel(const JacobiState* __restrict__ st, int* __restrict__ out) {
+  *out = st->sweeps;
+}
+
 __global__ __launch_bounds__(256) void identity_kernel(C64* __restrict__ X, int n) {
   const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (e >= (int64_t(1) << (2 * n))) return;
@@ -198,11 +259,14 @@ __global__ __launch_bounds__(256) void identity_kernel(C64* __restrict__ X, int 
 
 __global__ void set_scalar_kernel(double* x, double v) { *x = v; }
 
-// lam[i] = A[i][i] (real), sc[i] = |lam[i]|^(P/4).
-__global__ __launch_bounds__(256) void spectrum_kernel(const C64* __restrict__ A, int d, double P,
+// lam[i] = A[i][i] (real; A the diagonalised matrix, in A0 or A1 as the
+// sweep state says), sc[i] = |lam[i]|^(P/4).
+__global__ __launch_bounds__(256) void spectrum_kernel(const C64* __restrict__ A0, const C64* __restrict__ A1,
+                                                       const JacobiState* __restrict__ st, int d, double P,
                                                        double* __restrict__ lam, double* __restrict__ sc) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= d) return;
+  const C64* A = st->parity ? A1 : A0;
   const double l = A[int64_t(i) * d + i].re;
   lam[i] = l;
   sc[i] = pow(fabs(l), 0.25 * P);
@@ -305,6 +369,7 @@ struct Bufs {
   C64 *b0, *b1, *b2;
   double *part, *scal;
   void* sk;
+  JacobiState* st;
 };
 
 Bufs carve(int n, void* ws) {
@@ -312,7 +377,7 @@ Bufs carve(int n, void* ws) {
   unsigned char* w = static_cast<unsigned char*>(ws);
   return Bufs{reinterpret_cast<C64*>(w + L.b0), reinterpret_cast<C64*>(w + L.b1), reinterpret_cast<C64*>(w + L.b2),
               reinterpret_cast<double*>(w + L.part), reinterpret_cast<double*>(w + L.scal),
-              L.sk_bytes ? static_cast<void*>(w + L.sk) : nullptr};
+              L.sk_bytes ? static_cast<void*>(w + L.sk) : nullptr, reinterpret_cast<JacobiState*>(w + L.state)};
 }
 
 unsigned elem_blocks(int n) { return unsigned(((int64_t(1) << (2 * n)) + 255) / 256); }
@@ -356,34 +421,36 @@ hipError_t store_out(qst_prec prec, const C64* X, void* Y, int64_t ldy, int n, h
 // order).
 double sweep_tol(qst_prec prec) { return prec == QST_F64 ? 1e-14 : 1e-10; }
 
-// Jacobi sweeps on *cur (ping-pong with *nxt; V^T rotated in b.b2) until
-// the stopping rule holds; on return *cur holds the diagonalised matrix and
-// *sweeps the sweeps taken, or -1 (non-finite or not converged).
-hipError_t jacobi_sweeps(const Bufs& b, int n, C64*& cur, C64*& nxt, hipStream_t s, int* sweeps, double tol) {
-  *sweeps = -1;
+// Jacobi sweeps on b.b0 (ping-pong with b.b1; V^T rotated in b.b2), at
+// most max_sweeps, the stopping rule decided on the device (JacobiState).
+// sync: the host reads the state after each sweep and stops enqueuing
+// once done (*sweeps then holds the sweeps taken, or -1); otherwise all
+// max_sweeps are enqueued and nothing is read back.
+hipError_t jacobi_sweeps(const Bufs& b, int n, hipStream_t s, int max_sweeps, double tol, bool sync, int* sweeps) {
+  if (sweeps) *sweeps = -1;
   const int d = 1 << n, half = d >> 1;
   const int chunks = (half + kRoundThreads - 1) / kRoundThreads;
   hipError_t e;
-  double prev = HUGE_VAL, host[2];
-  for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
+  jacobi_reset_kernel<<<1, 1, 0, s>>>(b.st);
+  C64 *cur = b.b0, *nxt = b.b1;
+  for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
     for (int t = 0; t < d - 1; ++t) {
-      jacobi_round_kernel<<<dim3(half, chunks), kRoundThreads, 0, s>>>(cur, nxt, b.b2, d, t, b.part);
+      jacobi_round_kernel<<<dim3(half, chunks), kRoundThreads, 0, s>>>(cur, nxt, b.b2, d, t, b.part, b.st);
       C64* x = cur;
       cur = nxt;
       nxt = x;
     }
-    jacobi_norms_kernel<<<1, 256, 0, s>>>(b.part, half * chunks, b.scal + 2);
+    jacobi_check_kernel<<<1, 256, 0, s>>>(b.part, half * chunks, b.st, tol, sweep, max_sweeps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(host, b.scal + 2, sizeof(host), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    const double off = host[0], tot = host[0] + host[1];
-    if (!std::isfinite(off) || !std::isfinite(tot)) return hipSuccess;
-    const double r = tot > 0.0 ? std::sqrt(off / tot) : 0.0;
-    if (r <= tol || (r <= 1e-10 && r > 0.5 * prev)) {
-      *sweeps = sweep;
-      return hipSuccess;
+    if (sync) {
+      JacobiState host;
+      if ((e = hipMemcpyAsync(&host, b.st, sizeof(host), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      if (host.done) {
+        if (sweeps) *sweeps = host.sweeps;
+        return hipSuccess;
+      }
     }
-    prev = r;
   }
   return hipSuccess;
 }
@@ -421,10 +488,13 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const C64* __restrict__ X, i
 }
 
 // F = (sum_i sqrt(max(C_ii, 0)))^2 / tau over the diagonal of the
-// diagonalised C, in a fixed order (one workgroup).
-__global__ __launch_bounds__(256) void fq_finish_kernel(const C64* __restrict__ C, int d,
+// diagonalised C (in C0 or C1 as the sweep state says), in a fixed order
+// (one workgroup).
+__global__ __launch_bounds__(256) void fq_finish_kernel(const C64* __restrict__ C0, const C64* __restrict__ C1,
+                                                        const JacobiState* __restrict__ st, int d,
                                                         const double* __restrict__ tau, double* __restrict__ F) {
   __shared__ double lds4[4];
+  const C64* C = st->parity ? C1 : C0;
   double a = 0.0;
   for (int i = threadIdx.x; i < d; i += 256) a += sqrt(fmax(C[int64_t(i) * d + i].re, 0.0));
   a = block_sum256(a, lds4);
@@ -434,10 +504,11 @@ __global__ __launch_bounds__(256) void fq_finish_kernel(const C64* __restrict__ 
 }  // namespace
 
 hipError_t launch_fidelity_general(qst_prec prec, int n, const void* T, int64_t ldT, const void* rho, int64_t ldR,
-                                   double* F, void* ws, hipStream_t s, int* sweeps) {
-  *sweeps = -1;
+                                   double* F, void* ws, hipStream_t s, int* sweeps, int max_sweeps, int* sweeps_dev) {
   const int d = 1 << n, half = d >> 1;
   const Bufs b = carve(n, ws);
+  const bool sync = sweeps_dev == nullptr;
+  if (sweeps) *sweeps = -1;
   hipError_t e;
   ProfScope prof("fidelity_general", s);
   set_scalar_kernel<<<1, 1, 0, s>>>(b.scal, 2.0);
@@ -452,18 +523,20 @@ hipError_t launch_fidelity_general(qst_prec prec, int n, const void* T, int64_t 
   if ((e = product64(b.b2, b.b1, b.b0, d, n, b, s)) != hipSuccess) return e;                  // C = T^dagger rho T
   identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  C64 *cur = b.b0, *nxt = b.b1;
-  if ((e = jacobi_sweeps(b, n, cur, nxt, s, sweeps, sweep_tol(prec))) != hipSuccess) return e;
-  if (*sweeps < 0) return hipSuccess;
-  fq_finish_kernel<<<1, 256, 0, s>>>(cur, d, b.scal + 4, F);
+  if ((e = jacobi_sweeps(b, n, s, max_sweeps, sweep_tol(prec), sync, sweeps)) != hipSuccess) return e;
+  if (sync && *sweeps < 0) return hipSuccess;
+  fq_finish_kernel<<<1, 256, 0, s>>>(b.b0, b.b1, b.st, d, b.scal + 4, F);
+  if (sweeps_dev) jacobi_sweeps_out_kernel<<<1, 1, 0, s>>>(b.st, sweeps_dev);
   return hipGetLastError();
 }
 
 hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, const void* Q0, void* A,
-                          int64_t ldA, void* Q, double* lam, void* ws, hipStream_t s, int* sweeps) {
-  *sweeps = -1;
+                          int64_t ldA, void* Q, double* lam, void* ws, hipStream_t s, int* sweeps, int max_sweeps,
+                          int* sweeps_dev) {
   const int d = 1 << n;
   const Bufs b = carve(n, ws);
+  const bool sync = sweeps_dev == nullptr;
+  if (sweeps) *sweeps = -1;
   hipError_t e;
   ProfScope prof("abs_map", s);
   set_scalar_kernel<<<1, 1, 0, s>>>(b.scal, 2.0);
@@ -479,20 +552,22 @@ hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t
     identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  C64 *cur = b.b0, *nxt = b.b1;
-  if ((e = jacobi_sweeps(b, n, cur, nxt, s, sweeps, sweep_tol(prec))) != hipSuccess) return e;
-  if (*sweeps < 0) return hipSuccess;
-  // cur holds Lambda on its diagonal, b.b2 = V^T; the other buffer is free.
+  if ((e = jacobi_sweeps(b, n, s, max_sweeps, sweep_tol(prec), sync, sweeps)) != hipSuccess) return e;
+  if (sync && *sweeps < 0) return hipSuccess;
+  // the diagonalised matrix is in b0 or b1 (its diagonal read by
+  // spectrum_kernel); b.b2 = V^T; b0 and b1 are free afterwards
   double* sc = b.part;  // |lam|^(P/4), d values
-  spectrum_kernel<<<(d + 255) / 256, 256, 0, s>>>(cur, d, P, lam, sc);
+  spectrum_kernel<<<(d + 255) / 256, 256, 0, s>>>(b.b0, b.b1, b.st, d, P, lam, sc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = transpose64(b.b2, d, static_cast<C64*>(Q), d, n, false, nullptr, s)) != hipSuccess) return e;
-  if ((e = transpose64(b.b2, d, nxt, d, n, false, sc, s)) != hipSuccess) return e;  // U = Q diag(sc)
-  conj_rows_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, cur, n, sc);                 // U^dagger
+  if ((e = transpose64(b.b2, d, b.b1, d, n, false, sc, s)) != hipSuccess) return e;  // U = Q diag(sc)
+  conj_rows_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, b.b0, n, sc);                 // U^dagger
   if ((e = hipGetLastError()) != hipSuccess) return e;
   C64* out64 = prec == QST_F64 ? static_cast<C64*>(A) : b.b2;
-  if ((e = product64(nxt, cur, out64, prec == QST_F64 ? ldA : d, n, b, s)) != hipSuccess) return e;
-  return store_out(prec, out64, A, ldA, n, s);
+  if ((e = product64(b.b1, b.b0, out64, prec == QST_F64 ? ldA : d, n, b, s)) != hipSuccess) return e;
+  if ((e = store_out(prec, out64, A, ldA, n, s)) != hipSuccess) return e;
+  if (sweeps_dev) jacobi_sweeps_out_kernel<<<1, 1, 0, s>>>(b.st, sweeps_dev);
+  return hipGetLastError();
 }
 
 hipError_t launch_abs_map_backward(qst_prec prec, int n, double P, const void* Q, const double* lam, const void* GA,

@@ -100,7 +100,8 @@ qst_status qst_abs_map(int n, qst_prec prec, double P, const void* T, int64_t ld
   if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_ABS_MAP, false).total, msg)) != QST_OK)
     return fail(st, msg);
   int taken = -1;
-  hipError_t e = launch_abs_map(prec, n, P, T, ldT, Q0, A, ldA, Q, lam, ws, static_cast<hipStream_t>(stream), &taken);
+  hipError_t e = launch_abs_map(prec, n, P, T, ldT, Q0, A, ldA, Q, lam, ws, static_cast<hipStream_t>(stream), &taken,
+                                kJacobiMaxSweeps, nullptr);
   if (e != hipSuccess) return hip_fail(e, "absolute map");
   if (sweeps) *sweeps = taken;
   if (taken < 0)
@@ -120,11 +121,62 @@ qst_status qst_fidelity_general(int n, qst_prec prec, const void* T, int64_t ldT
   if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_ABS_MAP, false).total, msg)) != QST_OK)
     return fail(st, msg);
   int taken = -1;
-  hipError_t e = launch_fidelity_general(prec, n, T, ldT, rho, ldR, F_dev, ws, static_cast<hipStream_t>(stream), &taken);
+  hipError_t e = launch_fidelity_general(prec, n, T, ldT, rho, ldR, F_dev, ws, static_cast<hipStream_t>(stream), &taken,
+                                         kJacobiMaxSweeps, nullptr);
   if (e != hipSuccess) return hip_fail(e, "general fidelity");
   if (sweeps) *sweeps = taken;
   if (taken < 0)
     return fail(QST_ERR_INVALID_ARG, "general fidelity: the Jacobi sweeps did not converge (are T and rho finite?)");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_abs_map_async(int n, qst_prec prec, double P, const void* T, int64_t ldT, const void* Q0, void* A,
+                             int64_t ldA, void* Q, double* lam, int max_sweeps, int* sweeps_dev, void* ws,
+                             size_t ws_bytes, void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(A, ldA, n, "A", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(Q, "Q", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(lam, "lam", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(sweeps_dev, "sweeps_dev", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_abs_order(P, msg)) != QST_OK) return fail(st, msg);
+  if (max_sweeps < 1 || max_sweeps > kJacobiMaxSweeps)
+    return fail(QST_ERR_INVALID_ARG, "max_sweeps=" + std::to_string(max_sweeps) + " outside [1, " +
+                                         std::to_string(kJacobiMaxSweeps) + "]");
+  if (A == T && ldA != ldT) return fail(QST_ERR_INVALID_ARG, "in place (A == T) needs ldA == ldT");
+  if (Q == T || Q == A || Q == static_cast<void*>(lam)) return fail(QST_ERR_INVALID_ARG, "Q must not alias T, A or lam");
+  if (Q0 && (Q0 == T || Q0 == A || Q0 == static_cast<const void*>(lam)))
+    return fail(QST_ERR_INVALID_ARG, "Q0 must not alias T, A or lam");
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_ABS_MAP, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  hipError_t e = launch_abs_map(prec, n, P, T, ldT, Q0, A, ldA, Q, lam, ws, static_cast<hipStream_t>(stream), nullptr,
+                                max_sweeps, sweeps_dev);
+  if (e != hipSuccess) return hip_fail(e, "absolute map");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_fidelity_general_async(int n, qst_prec prec, const void* T, int64_t ldT, const void* rho, int64_t ldR,
+                                      double* F_dev, int max_sweeps, int* sweeps_dev, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(rho, ldR, n, "rho", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(F_dev, "F_dev", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_ptr(sweeps_dev, "sweeps_dev", msg)) != QST_OK) return fail(st, msg);
+  if (max_sweeps < 1 || max_sweeps > kJacobiMaxSweeps)
+    return fail(QST_ERR_INVALID_ARG, "max_sweeps=" + std::to_string(max_sweeps) + " outside [1, " +
+                                         std::to_string(kJacobiMaxSweeps) + "]");
+  if ((st = check_ws(ws, ws_bytes, workspace_layout(n, prec, QST_OP_ABS_MAP, false).total, msg)) != QST_OK)
+    return fail(st, msg);
+  hipError_t e = launch_fidelity_general(prec, n, T, ldT, rho, ldR, F_dev, ws, static_cast<hipStream_t>(stream),
+                                         nullptr, max_sweeps, sweeps_dev);
+  if (e != hipSuccess) return hip_fail(e, "general fidelity");
   clear_error();
   return QST_OK;
 }

@@ -51,15 +51,21 @@ hipError_t launch_fidelity_classical(qst_prec prec, const void* ph, const void* 
                                      hipStream_t s);
 
 // P-order absolute map and its adjoint (workspace laid out by
-// absmap_layout).  launch_abs_map synchronises s once per Jacobi sweep and
-// sets *sweeps to the sweeps taken, or -1 when the off-diagonal norm is not
-// finite or does not converge.
+// absmap_layout).  At most max_sweeps Jacobi sweeps, the stopping rule
+// decided on the device.  sweeps_dev == NULL: synchronous -- the host reads
+// the decision after each sweep, stops enqueuing once it holds, and sets
+// *sweeps to the sweeps taken or -1 (norm not finite, or not converged;
+// nothing after the sweeps is launched then).  Otherwise asynchronous and
+// graph-capturable: all max_sweeps are enqueued (the rounds after
+// convergence return at once), the rest of the map always runs, and the
+// sweeps taken (or -1) land in the device int *sweeps_dev.
 hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, const void* Q0, void* A,
-                          int64_t ldA, void* Q, double* lam, void* ws, hipStream_t s, int* sweeps);
+                          int64_t ldA, void* Q, double* lam, void* ws, hipStream_t s, int* sweeps, int max_sweeps,
+                          int* sweeps_dev);
 // F_q against a general target rho: one eigensolve of T^dagger rho T (the
-// absolute-map workspace; synchronises s once per sweep like launch_abs_map).
+// absolute-map workspace; sweeps as launch_abs_map).
 hipError_t launch_fidelity_general(qst_prec prec, int n, const void* T, int64_t ldT, const void* rho, int64_t ldR,
-                                   double* F, void* ws, hipStream_t s, int* sweeps);
+                                   double* F, void* ws, hipStream_t s, int* sweeps, int max_sweeps, int* sweeps_dev);
 hipError_t launch_abs_map_backward(qst_prec prec, int n, double P, const void* Q, const double* lam, const void* GA,
                                    int64_t ldGA, void* GT, int64_t ldGT, void* ws, hipStream_t s);
 

@@ -125,6 +125,7 @@ AbsMapLayout absmap_layout(int n) {
   const size_t chunks = (d / 2 + 127) / 128;
   a.part = take(std::max(d, d * chunks) * sizeof(double));
   a.scal = take(8 * sizeof(double));
+  a.state = take(64);  // the Jacobi sweep state (done flag, sweeps, parity, previous norm)
   if (n >= kStreamKMinQubits) {
     a.sk_bytes = stream_k_partial_bytes(QST_F64);
     a.sk = take(a.sk_bytes);

@@ -53,8 +53,11 @@ bool fused_likelihood(const PovmPlan& pl, qst_prec prec);
 // |lambda|^(P/4)), a few FP64 scalars and the FP64 stream-K partial tiles of
 // the complex products (N >= kStreamKMinQubits).
 struct AbsMapLayout {
-  size_t b0 = 0, b1 = 0, b2 = 0, part = 0, scal = 0, sk = 0, sk_bytes = 0, total = 0;
+  size_t b0 = 0, b1 = 0, b2 = 0, part = 0, scal = 0, state = 0, sk = 0, sk_bytes = 0, total = 0;
 };
+// Jacobi sweeps the absolute map and the general fidelity allow (the
+// graph-capturable calls take a smaller bound of their own).
+constexpr int kJacobiMaxSweeps = 40;
 AbsMapLayout absmap_layout(int n);
 qst_status check_abs_order(double P, std::string& msg);  // P finite and >= 0
 

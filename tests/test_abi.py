@@ -339,6 +339,20 @@ def test_abs_map_validation(L):
     assert bwd(GT=Q) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
     assert bwd(nb=0) == lib_mod.QST_ERR_WORKSPACE
 
+    SW = ctypes.c_void_p(0x60000)
+
+    def fwd_async(max_sweeps=8, sw=SW, T=FAKE, nb=ws):
+        return L.qst_abs_map_async(n, 0, 1.5, T, d, None, FAKE2, d, Q, lam, max_sweeps, sw, W, nb, None)
+
+    assert fwd_async(max_sweeps=0) == lib_mod.QST_ERR_INVALID_ARG and "max_sweeps" in _err(L)
+    assert fwd_async(max_sweeps=41) == lib_mod.QST_ERR_INVALID_ARG and "max_sweeps" in _err(L)
+    assert fwd_async(sw=None) == lib_mod.QST_ERR_INVALID_ARG and "sweeps_dev" in _err(L)
+    assert fwd_async(T=None) == lib_mod.QST_ERR_INVALID_ARG and "T is NULL" in _err(L)
+    assert fwd_async(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
+    assert L.qst_fidelity_general_async(n, 0, FAKE, d, FAKE2, d, W, 0, SW, W, ws, None) == lib_mod.QST_ERR_INVALID_ARG
+    assert L.qst_fidelity_general_async(n, 0, FAKE, d, FAKE2, d, W, 8, None, W, ws, None) \
+        == lib_mod.QST_ERR_INVALID_ARG and "sweeps_dev" in _err(L)
+
 
 def test_likelihood_fc_validation(L):
     n, d = 7, 128

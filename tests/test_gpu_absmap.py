@@ -279,3 +279,88 @@ def test_abs_map_non_finite_input_is_an_error():
     T[3, 5] = 0.0
     A, _, _, sweeps = qst.abs_map(torch.from_numpy(T).to(DEV), 1.5, "f64")
     assert sweeps > 0 and rel_fro(A.cpu().numpy(), O.abs_map(T, 1.5)[0]) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_abs_map_async_equals_sync(prec):
+    """qst_abs_map_async (stopping rule on the device, nothing read back)
+    against qst_abs_map: the same sweeps and bitwise the same A, Q, lam;
+    too few sweeps report -1; qst_fidelity_general_async likewise."""
+    n, d, P = 6, 64, 1.5
+    g = S.rng(8900)
+    T = dev_matrix(S.ginibre(g, d).astype(ctype(prec)))
+    A, Q, lam, sw = qst.abs_map(T, P, prec)
+    A2, Q2, lam2, sw2 = qst.abs_map_async(T, P, prec, max_sweeps=20)
+    torch.cuda.synchronize()
+    assert int(sw2.item()) == sw
+    assert torch.equal(A, A2) and torch.equal(Q, Q2) and torch.equal(lam, lam2)
+    _, _, _, sw3 = qst.abs_map_async(T, P, prec, max_sweeps=2)
+    assert int(sw3.item()) == -1
+    rho = dev_matrix(S.depolarised_pure(S.haar_vector(g, d), 0.2).astype(ctype(prec)))
+    F, fs = qst.fidelity_general(T, rho, prec)
+    F2, fs2 = qst.fidelity_general_async(T, rho, prec, max_sweeps=20)
+    torch.cuda.synchronize()
+    assert int(fs2.item()) == fs and float(F2.item()) == float(F.item())
+
+
+def test_abs_map_async_graph_replays():
+    """qst_abs_map_async captured in a HIP graph (outputs, workspace and the
+    warm start preallocated): three replays, with eager library work and
+    synchronisations between them, each bitwise equal to the eager call."""
+    n, d, P, prec = 7, 128, 1.0, "f32"
+    g = S.rng(8910)
+    T = dev_matrix(S.ginibre(g, d).astype(np.complex64))
+    _, Q0, _, _ = qst.abs_map(T, P, prec)
+    T2 = (T + 1e-3 * dev_matrix(S.ginibre(g, d).astype(np.complex64))).contiguous()
+    A_e, Q_e, lam_e, sw_e = qst.abs_map_async(T2, P, prec, max_sweeps=6, Q0=Q0)
+    torch.cuda.synchronize()
+    assert 0 < int(sw_e.item()) <= 6
+    A = torch.empty_like(A_e)
+    Q = torch.empty_like(Q_e)
+    lam = torch.empty_like(lam_e)
+    sw = torch.empty_like(sw_e)
+    ws = torch.empty(qst.workspace_bytes(n, qst.QST_F32, qst._lib.QST_OP_ABS_MAP), dtype=torch.uint8, device=DEV)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        qst.abs_map_async(T2, P, prec, max_sweeps=6, Q0=Q0, out=A, Q=Q, lam=lam, sweeps=sw, ws=ws)  # warm-up
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        qst.abs_map_async(T2, P, prec, max_sweeps=6, Q0=Q0, out=A, Q=Q, lam=lam, sweeps=sw, ws=ws)
+    for k in range(3):
+        A.zero_()
+        lam.zero_()
+        sw.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        say(f"replay {k}: sweeps {int(sw.item())}")
+        assert torch.equal(A, A_e) and torch.equal(Q, Q_e) and torch.equal(lam, lam_e)
+        assert int(sw.item()) == int(sw_e.item())
+        qst.abs_map(T, P, prec)  # eager work on the same stream between replays
+        torch.cuda.synchronize()
+
+
+def test_abs_projection_unsynchronised_warm_steps():
+    """AbsProjection(max_sweeps=...) runs its warm-started calls without
+    synchronising: the same losses and gradients as the synchronous
+    projection over a drifting T."""
+    n, d, P, prec = 7, 128, 1.5, "f64"
+    g = S.rng(8920)
+    T1, E = S.ginibre(g, d), S.ginibre(g, d)
+    psi = S.haar_vector(g, d)
+    f = torch.from_numpy(S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))).to(DEV)
+    sync_p, async_p = qst.AbsProjection(P, prec), qst.AbsProjection(P, prec, max_sweeps=6)
+    for k in range(4):
+        Tk = T1 + (1e-3 * k) * E
+        out = []
+        for proj in (sync_p, async_p):
+            Tg = torch.from_numpy(Tk).to(DEV).requires_grad_(True)
+            L = qst.likelihood(proj(Tg), f, prec)
+            L.backward()
+            out.append((float(L.item()), Tg.grad.cpu().numpy()))
+        (Ls, gs), (La, ga) = out
+        say(f"step {k}: sweeps sync {sync_p.sweeps} async {async_p.sweeps}")
+        assert async_p.sweeps == sync_p.sweeps
+        assert Ls == La and np.array_equal(gs, ga)
