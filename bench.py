@@ -354,6 +354,20 @@ def abs_projection(qst, prec, dev, n=10, P=1.5, reps=5):
     torch.cuda.synchronize()
     warm_s = time.perf_counter() - t0
     warm_sweeps = proj.sweeps
+    # the same warm steps with the stopping rule left on the device (no
+    # synchronisation inside the step; at most 6 sweeps)
+    proj_a = qst.AbsProjection(P, prec, max_sweeps=6)
+    proj_a(T)
+    steps_a = []
+    for k in range(1, 4):
+        Tw = (T + (1e-3 * k) * GA).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = qst.likelihood(proj_a(Tw), f, prec)
+        L.backward()
+        torch.cuda.synchronize()
+        steps_a.append(time.perf_counter() - t0)
+    warm_async_sweeps = proj_a.sweeps
     # F_q against a full-rank target (a depolarised pure state) by one
     # eigensolve of T^dagger rho T
     rho = torch.from_numpy(S.depolarised_pure(S.haar_vector(g, d), 0.3).astype(ct)).to(dev)
@@ -362,11 +376,12 @@ def abs_projection(qst, prec, dev, n=10, P=1.5, reps=5):
     F, fsweeps = qst.fidelity_general(T, rho, prec)
     float(F.item())
     fq_s = time.perf_counter() - t0
-    del A, Q, lam, T, GA, Tg, Tw, proj, rho
+    del A, Q, lam, T, GA, Tg, Tw, proj, proj_a, rho
     return {"n_qubits": n, "P": P, "forward_ms": round(1e3 * fwd_s, 1), "sweeps": sweeps,
             "round_us": round(round_us, 2), "round_GB_s": round(gbs, 1), "round_hbm_frac": round(gbs / 8000.0, 3),
             "backward_ms": round(bwd_ms, 3), "step_ms": round(1e3 * step_s, 1),
             "warm_step_ms": round(1e3 * warm_s, 1), "warm_sweeps": warm_sweeps,
+            "warm_step_unsynchronised_ms": round(1e3 * min(steps_a), 1), "warm_unsynchronised_sweeps": warm_async_sweeps,
             "fidelity_general_ms": round(1e3 * fq_s, 1), "fidelity_general_sweeps": fsweeps,
             "note": "forward wall time (synchronises once per sweep) divided over its rounds; warm step: T moved "
                     "by 1e-3, eigensolver started from the previous eigenvectors (AbsProjection)"}
@@ -498,6 +513,72 @@ def _oracle_eval(O, Tq, fq):
     return p, L, (2.0 / tau) * (G @ Tq)
 
 
+def general_povms(qst, prec, dev, reps=10):
+    """General product POVMs (a K-element POVM per qubit, several settings):
+    (a) the Pauli-6 POVM, M_(+-j) = (I +- sigma_j)/6, on every qubit at
+    N = 10 (6^10 = 60,466,176 outcomes); (b) the three Pauli bases as three
+    settings of K = 2 projectors at N = 11.  One step = qst_likelihood_general
+    + qst_grad_product.  The real per-qubit factor passes are timed by the
+    library's events (scope general_factor_pass) and their achieved GB/s is
+    from algorithmic bytes: a pass over [A][m][B] reads A m_in B values and
+    writes A m_out B (the first adjoint pass also reads f; the last one of
+    each setting after the first reads its output to accumulate)."""
+    import numpy as np
+    import torch
+
+    import synth as S
+    from paper_2207_05341_amd import _lib
+
+    I2 = np.eye(2, dtype=complex)
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    Y = np.array([[0, -1j], [1j, 0]])
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    pauli6 = np.array([(I2 + X) / 6, (I2 - X) / 6, (I2 + Y) / 6, (I2 - Y) / 6, (I2 + Z) / 6, (I2 - Z) / 6])
+    bases = [np.array([(I2 + P) / 2, (I2 - P) / 2]) for P in (X, Y, Z)]
+    ct = np.complex128 if prec == "f64" else np.complex64
+    rt = np.float64 if prec == "f64" else np.float32
+    rb = 8 if prec == "f64" else 4
+    g = S.rng(31)
+    out = {}
+    for key, n, K, settings in (("pauli6_n10", 10, 6, [np.array([pauli6] * 10)]),
+                                ("pauli_bases_3settings_n11", 11, 2, [np.array([b] * 11) for b in bases])):
+        d, DK, Sn = 1 << n, K ** n, len(settings)
+        T = torch.from_numpy(S.ginibre(g, d).astype(ct)).to(dev)
+        fs = np.stack([S.multinomial_freqs(g, 10_000_000, S.porter_thomas_probs(g, DK, 0.1)) for _ in range(Sn)])
+        f = torch.from_numpy(fs.astype(rt)).to(dev)
+        povms = np.stack(settings)
+
+        def stepg():
+            o, tau, G, _ = qst.likelihood_forward_general(T, f, povms, prec)
+            return qst.grad_product(G, T, tau, prec)
+
+        for _ in range(2):
+            stepg()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            stepg()
+        torch.cuda.synchronize()
+        step_s = (time.perf_counter() - t0) / reps
+        _lib.profile_report(reset=True)
+        _lib.profile_enable(True, "general_factor_pass")
+        for _ in range(reps):
+            stepg()
+        torch.cuda.synchronize()
+        _lib.profile_enable(False)
+        calls, ms = _lib.profile_report(reset=True)["general_factor_pass"]
+        fwd = sum(4 ** (j - 1) * K ** (n - j) * (4 + K) for j in range(1, n + 1))
+        adj = fwd + DK + 4 ** n  # f read by the first adjoint pass; h read back by the last
+        nbytes = rb * (Sn * (fwd + adj) - 4 ** n)  # the first setting writes h without reading it
+        gbs = nbytes * reps / (ms * 1e-3) / 1e9
+        out[key] = {"n_qubits": n, "K": K, "settings": Sn, "outcomes_per_setting": DK,
+                    "step_ms": round(1e3 * step_s, 3), "factor_passes_ms_per_step": round(ms / reps, 3),
+                    "factor_pass_launches_per_step": calls // reps,
+                    "factor_passes_GB_s": round(gbs, 1), "factor_passes_hbm_frac": round(gbs / 8000.0, 3)}
+        del T, f
+    return out
+
+
 def cpu_baseline(T, f, prec):
     """FP64 oracle timed on a bounded sample of the same N = 11 workload (the
     measured precision's T and f widened to FP64): full forward + adjoint
@@ -595,12 +676,14 @@ def main():
                               / torch.linalg.vector_norm(g64)),
         }
         del p, out, grad
-        _, names = time_steps(qst, T, f, prec, 1, 1, only="", fused=fused)
-        breakdown = {}
-        for name in names:
-            breakdown.update(time_steps(qst, T, f, prec, max(20, steps // 2), 3, only=name, fused=fused)[1])
-        dom = max(breakdown, key=lambda k: breakdown[k][1] / breakdown[k][0])
+        # the scopes and the dominant one from a short loop that times them all
+        _, names = time_steps(qst, T, f, prec, 3, 2, only="", fused=fused)
+        dom = max(names, key=lambda k: names[k][1] / names[k][0])
         sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom, fused=fused)
+        breakdown = {dom: kdom[dom]}
+        for name in names:
+            if name != dom:
+                breakdown.update(time_steps(qst, T, f, prec, steps, 3, only=name, fused=fused)[1])
         return sec, breakdown, dom, kdom, acc, res
 
     sec, kern, dom, kdom, acc, res_main = measure(args.prec, args.steps, args.warmup)
@@ -672,6 +755,7 @@ def main():
     fids = fidelities(qst, Tm, args.prec, f=fm)
     net = network(qst, fm, args.prec, long_run=args.nnqst_run)
     absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
+    genp = general_povms(qst, args.prec, dev)
     del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu, acc_oracle = None, None
@@ -731,6 +815,7 @@ def main():
         "paths": paths,
         "state_maps": modes,
         "abs_projection": absp,
+        "general_povm": genp,
         "fidelity": fids,
         "network": net,
         "batched": batch,

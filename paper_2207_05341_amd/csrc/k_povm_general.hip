@@ -84,6 +84,7 @@ void launch_factor_k(int mode, const R* in, R* out, int64_t A, int64_t B, const 
 template <typename R>
 hipError_t launch_factor(int K, int mode, const void* in, void* out, int64_t A, int64_t B, const RealFactor& C,
                          const void* f, const double* Fs, int accumulate, hipStream_t s) {
+  ProfScope prof("general_factor_pass", s);
   const R* i = static_cast<const R*>(in);
   R* o = static_cast<R*>(out);
   const R* fr = static_cast<const R*>(f);
