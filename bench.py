@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precision paths")
     ap.add_argument("--no-long", action="store_true",
-                    help="skip the runs of many small launches (absolute projection)")
+                    help="skip the records of the absolute projection and of the general POVMs")
     ap.add_argument("--nnqst-run", action="store_true",
                     help="also train a fresh network for 1000 Rprop steps at N=11 (an end-to-end use of the "
                          "library, not part of the headline measurement)")
@@ -755,7 +755,7 @@ def main():
     fids = fidelities(qst, Tm, args.prec, f=fm)
     net = network(qst, fm, args.prec, long_run=args.nnqst_run)
     absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
-    genp = general_povms(qst, args.prec, dev)
+    genp = None if args.no_long else general_povms(qst, args.prec, dev)
     del Tm, fm
     batch = None if args.no_batched else batched(qst, args.prec, dev)
     cpu, acc_oracle = None, None

@@ -646,6 +646,27 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int tr, int tc, type
 // parameter.
 static __constant__ ModeMatrix kTetraNoMatrix = {};
 
+// The first POVM pass over the 2^G x 2^G sub-tiles of a BM x BM tile of rho
+// at tile coordinates (tr, tc), held in lds in the sub-tile-major swizzled
+// layout lds[((r >> G) * S + (c >> G)) * 4^G + swz<G>(r & M, c & M)], by the
+// 256 threads of the workgroup (4^(G-2) per sub-tile); the lower sub-tiles
+// (Rhi >= Chi) go to g.x0.  Contains barriers.
+template <typename R, int G>
+__device__ __forceinline__ void x0_rounds(const GemmArgs& g, int64_t tr, int64_t tc, Cx<R>* lds) {
+  constexpr int S = BM >> G;
+  constexpr int TG = 1 << (2 * G);
+  constexpr int NT = 1 << (2 * (G - 2));
+  const int tl = (threadIdx.x & 255) / NT, t = (threadIdx.x & 255) % NT;
+  const int64_t Rhi = tr * S + tl / S, Chi = tc * S + tl % S;
+  Cx<R>* L = lds + tl * TG;
+  const int bq = t & ((1 << (G - 2)) - 1), aq = t >> (G - 2);
+  Cx<R> x[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) x[m] = L[swz<G>(4 * aq + blk_ri(m), 4 * bq + blk_ci(m))];
+  Cx<R>* out = Rhi >= Chi ? static_cast<Cx<R>*>(g.x0) + ((Rhi << g.x0up) | Chi) * int64_t(TG) : nullptr;
+  mat_fwd_rounds<R, true, G>(x, L, t, kTetraNoMatrix, out);
+}
+
 // First POVM pass applied to a finished T T^dagger tile (see GemmArgs::x0).
 // lds: BM x BM complex values of the workgroup's shared memory (aliasing the
 // panel buffers, which the caller no longer reads).
@@ -674,15 +695,7 @@ __device__ __forceinline__ void x0_tile(const GemmArgs& g, int tr, int tc, typen
       }
     }
   __syncthreads();
-  const int tl = threadIdx.x / NT, t = threadIdx.x % NT;
-  const int64_t Rhi = int64_t(tr) * S + tl / S, Chi = int64_t(tc) * S + tl % S;
-  Cx<R>* L = lds + tl * TG;
-  const int bq = t & ((1 << (G - 2)) - 1), aq = t >> (G - 2);
-  Cx<R> x[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) x[m] = L[swz<G>(4 * aq + blk_ri(m), 4 * bq + blk_ci(m))];
-  Cx<R>* out = Rhi >= Chi ? static_cast<Cx<R>*>(g.x0) + ((Rhi << g.x0up) | Chi) * int64_t(TG) : nullptr;
-  mat_fwd_rounds<R, true, G>(x, L, t, kTetraNoMatrix, out);
+  x0_rounds<R, G>(g, tr, tc, lds);
 }
 
 // Shared memory of a product kernel: the policy's panel buffers, and with
