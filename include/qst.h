@@ -341,52 +341,60 @@ qst_status qst_state_premap(int n_qubits, qst_prec prec, int mode, const void* X
  * Hermitian positive semidefinite, so that the state map of A (qst_state_map,
  * qst_likelihood) gives rho = Q |Lambda|^P Q^dagger / Tr |Lambda|^P, the
  * P-order absolute projection; P = 2 is Chol_H (Eq. unified_DP).
- * The eigendecomposition is a cyclic two-sided Jacobi method in FP64 on the
- * device, whatever prec.  After each sweep a kernel decides on the device
- * whether to stop (off-diagonal norm at 1e-14 of ||H||_F for QST_F64, 1e-10
- * for the FP32-storage precisions, or at the rounding floor); this call
- * reads that decision on the host after each sweep to stop enqueuing (so it
- * synchronises the stream once per sweep).  qst_abs_map_async is the same
- * map without any synchronisation.
+ * The eigendecomposition runs in FP64 on the device, whatever prec.  Without
+ * Q0 it is a direct solver: Householder reduction to a real tridiagonal
+ * matrix, eigenvalues by multisection of Sturm counts, eigenvectors by
+ * twisted factorizations (inverse iteration with orthogonalisation within
+ * clusters of eigenvalues closer than 1e-7 ||H||), one Newton-Schulz
+ * orthogonalisation step, and the blocked back-transformation; a fixed
+ * sequence of launches, after which this call reads one status word (one
+ * synchronisation).  With Q0 it is a cyclic two-sided Jacobi method on
+ * Q0^dagger H Q0: after each sweep a kernel decides on the device whether
+ * to stop (off-diagonal norm at 1e-14 of ||H||_F for QST_F64, 1e-10 for the
+ * FP32-storage precisions, or at the rounding floor), and this call reads
+ * that decision after each sweep to stop enqueuing.  qst_abs_map_async is
+ * the same map without any synchronisation.
  *   P      [in]  finite, >= 0.
  *   T      [in]  d x d complex (prec's storage type), row stride ldT, device.
- *   Q0     [in]  NULL, or a warm start: a unitary d x d complex FP64 matrix
- *                laid out as Q (normally the Q of an earlier call on a
- *                nearby T, e.g. the previous training step); the sweeps then
- *                run on Q0^dagger H Q0, which takes fewer of them.  The
- *                result does not depend on Q0 beyond rounding as long as Q0
- *                is unitary.  Q0 may be Q; it must not overlap T, A or lam.
+ *   Q0     [in]  NULL (the direct solver), or a warm start for the Jacobi
+ *                solver: a unitary d x d complex FP64 matrix laid out as Q
+ *                (normally the Q of an earlier call on a nearby T); the
+ *                sweeps then run on Q0^dagger H Q0.  The result does not
+ *                depend on Q0 beyond rounding as long as Q0 is unitary.  The
+ *                direct solver is faster than a warm start from d = 64 on.
+ *                Q0 may be Q; it must not overlap T, A or lam.
  *   A      [out] d x d complex (prec's storage type), row stride ldA, device.
  *                A == T with ldA == ldT works in place.
  *   Q      [out] d x d complex FP64 (interleaved re, im), row-major, row
  *                stride d, device: the eigenvectors of H as columns.
  *   lam    [out] d doubles, device: the eigenvalues of H, lam[i] belonging to
  *                column i of Q (no particular order).
- *   sweeps [out] host int, may be NULL: the Jacobi sweeps taken.
+ *   sweeps [out] host int, may be NULL: the Jacobi sweeps taken (0 for the
+ *                direct solver).
  * Q and lam are what qst_abs_map_backward needs.  Q must not overlap T, A or
  * lam.  Workspace: qst_workspace_bytes(N, prec, QST_OP_ABS_MAP) (three
- * d x d FP64 complex buffers).  Returns QST_ERR_INVALID_ARG when H is not
- * finite (the off-diagonal norm is not finite) or the sweeps do not
- * converge.
+ * d x d FP64 complex buffers and the solver's smaller arrays).  Returns
+ * QST_ERR_INVALID_ARG when H is not finite or the sweeps do not converge.
  */
 qst_status qst_abs_map(int n_qubits, qst_prec prec, double P, const void* T, int64_t ldT, const void* Q0, void* A,
                        int64_t ldA, void* Q, double* lam, int* sweeps, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * qst_abs_map for streams that must not be synchronised (HIP graph capture,
- * pipelined training loops): at most max_sweeps Jacobi sweeps are enqueued
- * (1 <= max_sweeps <= 40) and the stopping rule is applied on the device
- * after each; rounds after convergence return at once (an empty launch
- * each), and A, Q and lam are then computed as by qst_abs_map.  Nothing is
- * read back and the call returns before the work runs.
- *   sweeps_dev [out] one int, device: the sweeps taken, or -1 when the
- *                    off-diagonal norm was not finite or had not met the
- *                    stopping rule after max_sweeps (A, Q and lam are then
- *                    those of the last sweep and must not be used).
+ * pipelined training loops).  Nothing is read back and the call returns
+ * before the work runs.  Without Q0 the direct solver runs as in
+ * qst_abs_map (max_sweeps is checked but not used).  With Q0 at most
+ * max_sweeps Jacobi sweeps are enqueued (1 <= max_sweeps <= 40) and the
+ * stopping rule is applied on the device after each; rounds after
+ * convergence return at once (an empty launch each), and A, Q and lam are
+ * then computed as by qst_abs_map.
+ *   sweeps_dev [out] one int, device: the sweeps taken (0 for the direct
+ *                    solver), or -1 when H was not finite or the warm
+ *                    sweeps had not met the stopping rule after max_sweeps
+ *                    (A, Q and lam must not be used then).
  * A warm start (Q0 from the previous step) usually needs 2 or 3 sweeps at
- * the training-loop pace (T moved by about 1e-3 of its scale); a cold start
- * about 10 to 12 at d = 1024.  Other arguments, workspace and argument errors
- * as qst_abs_map.
+ * the training-loop pace (T moved by about 1e-3 of its scale).  Other
+ * arguments, workspace and argument errors as qst_abs_map.
  */
 qst_status qst_abs_map_async(int n_qubits, qst_prec prec, double P, const void* T, int64_t ldT, const void* Q0,
                              void* A, int64_t ldA, void* Q, double* lam, int max_sweeps, int* sweeps_dev, void* ws,
@@ -420,29 +428,28 @@ qst_status qst_abs_map_backward(int n_qubits, qst_prec prec, double P, const voi
  * the same nonzero eigenvalues (rho_hat's factor T stands in for the first
  * decomposition of Eq. fq_decom), so F_q = (sum_i sqrt(lambda_i))^2 / tau
  * with lambda_i the eigenvalues of T^dagger rho T (two FP64 complex
- * products and the FP64 Jacobi eigensolver of qst_abs_map; rounding-level
- * negative eigenvalues read as 0).  For a target of low rank prefer
+ * products, then the Householder reduction and the multisection of the
+ * direct solver of qst_abs_map, eigenvalues only; rounding-level negative
+ * eigenvalues read as 0).  For a target of low rank prefer
  * qst_fidelity_lowrank: here each of the d - r zero eigenvalues can add
  * the square root of its rounding error.
  *   T      [in]  d x d complex, row stride ldT, device.
  *   rho    [in]  d x d complex Hermitian positive semidefinite with trace 1
  *                (not checked), row stride ldR, device.
  *   F_dev  [out] one double, device.
- *   sweeps [out] host int, may be NULL: the Jacobi sweeps taken.
- * Workspace: qst_workspace_bytes(N, prec, QST_OP_ABS_MAP).  Reads the
- * device's stopping decision after each sweep (one synchronisation per
- * sweep; qst_fidelity_general_async has none).  QST_ERR_INVALID_ARG when
- * the sweeps do not converge (non-finite input).
+ *   sweeps [out] host int, may be NULL: 0 (no Jacobi sweeps).
+ * Workspace: qst_workspace_bytes(N, prec, QST_OP_ABS_MAP).  Reads one status
+ * word at the end (one synchronisation; qst_fidelity_general_async has
+ * none).  QST_ERR_INVALID_ARG when the input is not finite.
  */
 qst_status qst_fidelity_general(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* rho,
                                 int64_t ldR, double* F_dev, int* sweeps, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * qst_fidelity_general without synchronisation: at most max_sweeps sweeps
- * (1..40) with the stopping rule applied on the device, F_q computed from
- * the last of them; sweeps_dev [out] one device int, the sweeps taken or -1
- * (not finite, or not converged: F_dev must not be used then).  Other
- * arguments as qst_fidelity_general.
+ * qst_fidelity_general without synchronisation; max_sweeps (1..40) is
+ * checked but not used (no Jacobi sweeps run); sweeps_dev [out] one device
+ * int, 0, or -1 when the input was not finite (F_dev must not be used
+ * then).  Other arguments as qst_fidelity_general.
  */
 qst_status qst_fidelity_general_async(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* rho,
                                       int64_t ldR, double* F_dev, int max_sweeps, int* sweeps_dev, void* ws,

@@ -129,8 +129,9 @@ def abs_map(T: torch.Tensor, P: float, prec=None, out: torch.Tensor | None = Non
     """A = Q |Lambda|^(P/2) Q^dagger for the Hermitian part of T (qst_abs_map;
     the state map of A is the P-order absolute projection).  Returns
     (A, Q, lam, sweeps): Q d x d complex128, lam d float64, both on T's
-    device, and the Jacobi sweeps taken.  Q0: optional warm start (a unitary
-    Q from an earlier call on a nearby T).  Synchronises the stream."""
+    device, and the Jacobi sweeps taken (0: the direct solver, which runs
+    without Q0).  Q0: optional warm start for the Jacobi solver (a unitary Q
+    from an earlier call on a nearby T).  Synchronises the stream."""
     n, ld = _matrix(T, "T")
     p = _prec(T.dtype, prec)
     d = 1 << n
@@ -156,8 +157,9 @@ def abs_map(T: torch.Tensor, P: float, prec=None, out: torch.Tensor | None = Non
 def abs_map_async(T: torch.Tensor, P: float, prec=None, max_sweeps: int = 16, out: torch.Tensor | None = None,
                   Q0: torch.Tensor | None = None, Q: torch.Tensor | None = None, lam: torch.Tensor | None = None,
                   sweeps: torch.Tensor | None = None, ws: torch.Tensor | None = None):
-    """abs_map without synchronisation (qst_abs_map_async): at most
-    max_sweeps Jacobi sweeps, the stopping rule applied on the device.
+    """abs_map without synchronisation (qst_abs_map_async): the direct solver
+    without Q0; with Q0, at most max_sweeps warm-started Jacobi sweeps, the
+    stopping rule applied on the device.
     Returns (A, Q, lam, sweeps) with sweeps a 0-dim int32 device tensor
     (the sweeps taken, -1 when not converged: then A, Q and lam are not
     valid).  Every output and the workspace may be passed in, so that the
@@ -203,19 +205,21 @@ def abs_map_backward(Q: torch.Tensor, lam: torch.Tensor, P: float, GA: torch.Ten
 class AbsMapFn(torch.autograd.Function):
     """T' = Q |Lambda|^(P/2) Q^dagger of the Hermitian part of T, backward by
     qst_abs_map_backward (saves Q and the eigenvalues).  state: None, or a
-    dict whose "Q" (if present) warm-starts the eigensolver and receives
-    this call's Q and sweeps; with state["max_sweeps"] set and a warm start,
-    the call is the unsynchronised qst_abs_map_async with that bound (its
-    sweeps a device tensor)."""
+    dict that receives this call's Q and sweeps; with state["warm"] its "Q"
+    (if present) warm-starts the Jacobi eigensolver, otherwise the direct
+    solver runs.  With state["max_sweeps"] set the call is the
+    unsynchronised qst_abs_map_async (with that bound on the warm-started
+    Jacobi sweeps; its sweeps a device tensor)."""
 
     @staticmethod
     def forward(ctx, T, P, prec, state=None):
-        Q0 = None if state is None else state.get("Q")
+        Q0 = state.get("Q") if state is not None and state.get("warm") else None
         bound = None if state is None else state.get("max_sweeps")
-        if Q0 is not None and bound:
+        if bound:
             prev = state.get("sweeps")
             if isinstance(prev, torch.Tensor) and int(prev.item()) < 0:
-                raise QstError(1, "qst_abs_map_async", "the previous call had not converged within max_sweeps")
+                raise QstError(1, "qst_abs_map_async", "the previous call had failed (not finite, or not "
+                                                       "converged within max_sweeps)")
             A, Q, lam, sweeps = abs_map_async(T, P, prec, max_sweeps=bound, Q0=Q0)
         else:
             A, Q, lam, sweeps = abs_map(T, P, prec, Q0=Q0)
@@ -233,17 +237,21 @@ class AbsMapFn(torch.autograd.Function):
 
 class AbsProjection:
     """The P-order absolute map for a training loop: each call returns
-    T' = Q |Lambda|^(P/2) Q^dagger (differentiable) and keeps Q to warm-start
-    the next call's eigensolver.  Use as likelihood(proj(T), f).
+    T' = Q |Lambda|^(P/2) Q^dagger (differentiable).  Use as
+    likelihood(proj(T), f).
 
-    max_sweeps: None -- every call synchronises once per sweep to stop;
-    an int -- the warm-started calls (all but the first) run without any
-    synchronisation, at most that many sweeps, and a call that had not
-    converged is reported by the next one (QstError)."""
+    warm: False -- every call runs the direct eigensolver (a fixed sequence
+    of launches); True -- each call keeps Q to warm-start the next call's
+    Jacobi eigensolver.  max_sweeps: None -- synchronous calls (one
+    synchronisation per call, or per Jacobi sweep when warm); an int -- the
+    calls run without any synchronisation (the warm ones with at most that
+    many sweeps), and a call that failed is reported by the next one
+    (QstError)."""
 
-    def __init__(self, P: float, prec=None, max_sweeps: int | None = None):
+    def __init__(self, P: float, prec=None, max_sweeps: int | None = None, warm: bool = False):
         self.P, self.prec = float(P), prec
         self.max_sweeps = max_sweeps
+        self.warm = bool(warm)
         self.state: dict = {}
 
     def __call__(self, T: torch.Tensor) -> torch.Tensor:
@@ -251,6 +259,7 @@ class AbsProjection:
         if Q is not None and (Q.shape != (T.shape[0], T.shape[0]) or Q.device != T.device):
             self.state = {}
         self.state["max_sweeps"] = self.max_sweeps
+        self.state["warm"] = self.warm
         return AbsMapFn.apply(T, self.P, self.prec, self.state)
 
     @property
@@ -445,7 +454,7 @@ def fidelity_lowrank(T: torch.Tensor, W: torch.Tensor, prec=None) -> torch.Tenso
 def fidelity_general_async(T: torch.Tensor, rho: torch.Tensor, prec=None, max_sweeps: int = 16):
     """fidelity_general without synchronisation (qst_fidelity_general_async):
     returns (F, sweeps), a 0-dim float64 and a 0-dim int32 device tensor
-    (sweeps -1: not converged within max_sweeps, F not valid)."""
+    (sweeps 0; -1: the input was not finite, F not valid)."""
     n, ld = _matrix(T, "T")
     n2, ldr = _matrix(rho, "rho")
     if n2 != n or rho.dtype != T.dtype:
@@ -463,7 +472,7 @@ def fidelity_general_async(T: torch.Tensor, rho: torch.Tensor, prec=None, max_sw
 def fidelity_general(T: torch.Tensor, rho: torch.Tensor, prec=None):
     """F_q(T T^dagger / Tr, rho) for any target density matrix rho (d x d,
     T's dtype) by one eigensolve of T^dagger rho T (qst_fidelity_general).
-    Returns (F as a 0-dim float64 device tensor, Jacobi sweeps).
+    Returns (F as a 0-dim float64 device tensor, 0 -- no Jacobi sweeps run).
     Synchronises the stream."""
     n, ld = _matrix(T, "T")
     n2, ldr = _matrix(rho, "rho")

@@ -1,11 +1,15 @@
 // The P-order absolute map of Sec. 3.2 (Eq. abs_P) and its adjoint.
 //
-// Forward: H = (T + T^dagger) / 2 in FP64, H = Q Lambda Q^dagger by a
-// cyclic two-sided Jacobi method, and A = Q |Lambda|^(P/2) Q^dagger =
+// Forward: H = (T + T^dagger) / 2 in FP64, H = Q Lambda Q^dagger (by the
+// direct solver of k_eigh.hip, or, from a warm start, by the cyclic
+// two-sided Jacobi method below), and A = Q |Lambda|^(P/2) Q^dagger =
 // U U^dagger with U = Q |Lambda|^(P/4) (one complex product on MFMA).  The
 // likelihood path's state map of A, A A^dagger / Tr(A A^dagger) =
 // Q |Lambda|^P Q^dagger / Tr |Lambda|^P, is then the P-order absolute
 // projection.
+//
+// The general fidelity takes the eigenvalues of T^dagger rho T from the
+// direct solver.
 //
 // Jacobi: the d indices are paired by the round-robin (circle) schedule, in
 // which round t of d - 1 pairs every index once: pair 0 is (0, 1 + t) and
@@ -250,13 +254,6 @@ __global__ void jacobi_sweeps_out_kernel(const JacobiState* __restrict__ st, int
   *out = st->sweeps;
 }
 
-__global__ __launch_bounds__(256) void identity_kernel(C64* __restrict__ X, int n) {
-  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (e >= (int64_t(1) << (2 * n))) return;
-  const int64_t r = e >> n, c = e & ((int64_t(1) << n) - 1);
-  X[e] = C64{r == c ? 1.0 : 0.0, 0.0};
-}
-
 __global__ void set_scalar_kernel(double* x, double v) { *x = v; }
 
 // lam[i] = A[i][i] (real; A the diagonalised matrix, in A0 or A1 as the
@@ -270,6 +267,13 @@ __global__ __launch_bounds__(256) void spectrum_kernel(const C64* __restrict__ A
   const double l = A[int64_t(i) * d + i].re;
   lam[i] = l;
   sc[i] = pow(fabs(l), 0.25 * P);
+}
+
+// sc[i] = |lam[i]|^(P/4).
+__global__ __launch_bounds__(256) void power_scale_kernel(const double* __restrict__ lam, int d, double P,
+                                                          double* __restrict__ sc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < d) sc[i] = pow(fabs(lam[i]), 0.25 * P);
 }
 
 // Y[i][j] = op(X[j][i]) * (scale ? scale[j] : 1), op = conj or identity;
@@ -370,6 +374,7 @@ struct Bufs {
   double *part, *scal;
   void* sk;
   JacobiState* st;
+  void* eig;
 };
 
 Bufs carve(int n, void* ws) {
@@ -377,7 +382,8 @@ Bufs carve(int n, void* ws) {
   unsigned char* w = static_cast<unsigned char*>(ws);
   return Bufs{reinterpret_cast<C64*>(w + L.b0), reinterpret_cast<C64*>(w + L.b1), reinterpret_cast<C64*>(w + L.b2),
               reinterpret_cast<double*>(w + L.part), reinterpret_cast<double*>(w + L.scal),
-              L.sk_bytes ? static_cast<void*>(w + L.sk) : nullptr, reinterpret_cast<JacobiState*>(w + L.state)};
+              L.sk_bytes ? static_cast<void*>(w + L.sk) : nullptr, reinterpret_cast<JacobiState*>(w + L.state),
+              static_cast<void*>(w + L.eig)};
 }
 
 unsigned elem_blocks(int n) { return unsigned(((int64_t(1) << (2 * n)) + 255) / 256); }
@@ -487,18 +493,40 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const C64* __restrict__ X, i
   }
 }
 
-// F = (sum_i sqrt(max(C_ii, 0)))^2 / tau over the diagonal of the
-// diagonalised C (in C0 or C1 as the sweep state says), in a fixed order
-// (one workgroup).
-__global__ __launch_bounds__(256) void fq_finish_kernel(const C64* __restrict__ C0, const C64* __restrict__ C1,
-                                                        const JacobiState* __restrict__ st, int d,
-                                                        const double* __restrict__ tau, double* __restrict__ F) {
+// F = (sum_i sqrt(max(lam_i, 0)))^2 / tau over the d eigenvalues, in a
+// fixed order (one workgroup).
+__global__ __launch_bounds__(256) void fq_eig_finish_kernel(const double* __restrict__ lam, int d,
+                                                            const double* __restrict__ tau, double* __restrict__ F) {
   __shared__ double lds4[4];
-  const C64* C = st->parity ? C1 : C0;
   double a = 0.0;
-  for (int i = threadIdx.x; i < d; i += 256) a += sqrt(fmax(C[int64_t(i) * d + i].re, 0.0));
+  for (int i = threadIdx.x; i < d; i += 256) a += sqrt(fmax(lam[i], 0.0));
   a = block_sum256(a, lds4);
   if (threadIdx.x == 0) *F = a * a / *tau;
+}
+
+// Reads the eigensolver's status (0 or -1) on the host: one synchronisation.
+hipError_t read_status(const EighWork& w, hipStream_t s, int* out) {
+  hipError_t e;
+  if ((e = hipMemcpyAsync(out, w.status, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+// H (b0, d x d FP64 Hermitian, overwritten) = Q diag(lam) Q^dagger by the
+// direct solver: Q (d x d FP64, eigenvectors as columns) and lam; b1 holds
+// the reflectors, b2 the tridiagonal's eigenvectors.
+hipError_t eigh_direct(const Bufs& b, int n, double* lam, C64* Q, hipStream_t s) {
+  const int d = 1 << n;
+  const EighWork w = eigh_work(n, b.eig);
+  hipError_t e;
+  if ((e = launch_tridiagonalize(n, b.b0, b.b1, w, s)) != hipSuccess) return e;
+  if ((e = launch_tri_eigvals(n, w, lam, s)) != hipSuccess) return e;
+  if ((e = launch_tri_vectors(n, w, lam, b.b0, b.b2, s)) != hipSuccess) return e;
+  // one Newton-Schulz step: Z <- Z (1.5 I - 0.5 Z^T Z) (Z real, in b2)
+  if ((e = transpose64(b.b2, d, b.b0, d, n, false, nullptr, s)) != hipSuccess) return e;
+  if ((e = product64(b.b0, b.b2, Q, d, n, b, s)) != hipSuccess) return e;
+  if ((e = launch_ns_matrix(n, Q, b.b0, s)) != hipSuccess) return e;
+  if ((e = product64(b.b2, b.b0, Q, d, n, b, s)) != hipSuccess) return e;
+  return launch_back_transform(n, b.b1, w, Q, b.b2, s);
 }
 
 }  // namespace
@@ -521,13 +549,21 @@ hipError_t launch_fidelity_general(qst_prec prec, int n, const void* T, int64_t 
   if ((e = product64(b.b2, b.b0, b.b1, d, n, b, s)) != hipSuccess) return e;                  // rho T
   if ((e = transpose64(b.b0, d, b.b2, d, n, true, nullptr, s)) != hipSuccess) return e;      // T^dagger
   if ((e = product64(b.b2, b.b1, b.b0, d, n, b, s)) != hipSuccess) return e;                  // C = T^dagger rho T
-  identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
+  (void)max_sweeps;
+  // the eigenvalues of the Hermitian part of C by the direct solver
+  const EighWork w = eigh_work(n, b.eig);
+  if ((e = herm_to64(QST_F64, b.b0, d, b.b1, n, s)) != hipSuccess) return e;
+  if ((e = launch_tridiagonalize(n, b.b1, b.b2, w, s)) != hipSuccess) return e;
+  if ((e = launch_tri_eigvals(n, w, b.part, s)) != hipSuccess) return e;
+  fq_eig_finish_kernel<<<1, 256, 0, s>>>(b.part, d, b.scal + 4, F);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = jacobi_sweeps(b, n, s, max_sweeps, sweep_tol(prec), sync, sweeps)) != hipSuccess) return e;
-  if (sync && *sweeps < 0) return hipSuccess;
-  fq_finish_kernel<<<1, 256, 0, s>>>(b.b0, b.b1, b.st, d, b.scal + 4, F);
-  if (sweeps_dev) jacobi_sweeps_out_kernel<<<1, 1, 0, s>>>(b.st, sweeps_dev);
-  return hipGetLastError();
+  if (sweeps_dev) return launch_eigh_status(w, sweeps_dev, s);
+  if (sync) {
+    int st = -1;
+    if ((e = read_status(w, s, &st)) != hipSuccess) return e;
+    if (sweeps) *sweeps = st;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t ldT, const void* Q0, void* A,
@@ -541,16 +577,34 @@ hipError_t launch_abs_map(qst_prec prec, int n, double P, const void* T, int64_t
   ProfScope prof("abs_map", s);
   set_scalar_kernel<<<1, 1, 0, s>>>(b.scal, 2.0);
   if ((e = herm_to64(prec, T, ldT, b.b0, n, s)) != hipSuccess) return e;
-  if (Q0) {
+  if (!Q0) {
+    // cold start: the direct solver (a fixed sequence of launches)
+    C64* q = static_cast<C64*>(Q);
+    if ((e = eigh_direct(b, n, lam, q, s)) != hipSuccess) return e;
+    double* sc = b.part;  // |lam|^(P/4), d values
+    power_scale_kernel<<<(d + 255) / 256, 256, 0, s>>>(lam, d, P, sc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = transpose64(q, d, b.b2, d, n, false, nullptr, s)) != hipSuccess) return e;  // V^T = Q^T
+    if ((e = transpose64(b.b2, d, b.b1, d, n, false, sc, s)) != hipSuccess) return e;  // U = Q diag(sc)
+    conj_rows_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, b.b0, n, sc);                 // U^dagger
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    C64* out64 = prec == QST_F64 ? static_cast<C64*>(A) : b.b2;
+    if ((e = product64(b.b1, b.b0, out64, prec == QST_F64 ? ldA : d, n, b, s)) != hipSuccess) return e;
+    if ((e = store_out(prec, out64, A, ldA, n, s)) != hipSuccess) return e;
+    const EighWork w = eigh_work(n, b.eig);
+    if (sweeps_dev) return launch_eigh_status(w, sweeps_dev, s);
+    int st = -1;
+    if ((e = read_status(w, s, &st)) != hipSuccess) return e;
+    if (sweeps) *sweeps = st;
+    return hipSuccess;
+  }
+  {
     // Warm start from a unitary Q0: Jacobi on Q0^dagger H Q0 with V = Q0.
     const C64* q0 = static_cast<const C64*>(Q0);
     if ((e = transpose64(q0, d, b.b1, d, n, true, nullptr, s)) != hipSuccess) return e;  // Q0^dagger
     if ((e = product64(b.b0, q0, b.b2, d, n, b, s)) != hipSuccess) return e;               // H Q0
     if ((e = product64(b.b1, b.b2, b.b0, d, n, b, s)) != hipSuccess) return e;             // Q0^dagger H Q0
     if ((e = transpose64(q0, d, b.b2, d, n, false, nullptr, s)) != hipSuccess) return e;  // V^T = Q0^T
-  } else {
-    identity_kernel<<<elem_blocks(n), 256, 0, s>>>(b.b2, n);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = jacobi_sweeps(b, n, s, max_sweeps, sweep_tol(prec), sync, sweeps)) != hipSuccess) return e;
   if (sync && *sweeps < 0) return hipSuccess;

@@ -105,7 +105,7 @@ qst_status qst_abs_map(int n, qst_prec prec, double P, const void* T, int64_t ld
   if (e != hipSuccess) return hip_fail(e, "absolute map");
   if (sweeps) *sweeps = taken;
   if (taken < 0)
-    return fail(QST_ERR_INVALID_ARG, "absolute map: the Jacobi sweeps did not converge (is T finite?)");
+    return fail(QST_ERR_INVALID_ARG, "absolute map: the eigendecomposition did not converge (is T finite?)");
   clear_error();
   return QST_OK;
 }
@@ -126,7 +126,8 @@ qst_status qst_fidelity_general(int n, qst_prec prec, const void* T, int64_t ldT
   if (e != hipSuccess) return hip_fail(e, "general fidelity");
   if (sweeps) *sweeps = taken;
   if (taken < 0)
-    return fail(QST_ERR_INVALID_ARG, "general fidelity: the Jacobi sweeps did not converge (are T and rho finite?)");
+    return fail(QST_ERR_INVALID_ARG, "general fidelity: the eigendecomposition did not converge (are T and rho "
+                                     "finite?)");
   clear_error();
   return QST_OK;
 }

@@ -50,6 +50,33 @@ hipError_t launch_fidelity_classical_part(qst_prec prec, const void* ph, const v
 hipError_t launch_fidelity_classical(qst_prec prec, const void* ph, const void* p, int n, void* ws, double* F,
                                      hipStream_t s);
 
+// Direct Hermitian eigensolver (FP64; k_eigh.hip), its small arrays laid
+// out by eigh_layout in the absolute map's workspace.
+struct EighWork {
+  double *diag = nullptr, *off = nullptr, *p0 = nullptr, *p1 = nullptr;
+  void *tau = nullptr, *y0 = nullptr, *y1 = nullptr, *scal = nullptr, *tfac = nullptr, *pbuf = nullptr,
+       *xbuf = nullptr;
+  int *bstart = nullptr, *bend = nullptr, *status = nullptr;
+};
+EighWork eigh_work(int n, void* eig_area);
+// H (d x d complex FP64, Hermitian, both triangles; overwritten) -> the
+// tridiagonal (w.diag, w.off), the reflector scalars (w.tau) and the
+// reflector rows in V (d x d complex FP64).
+hipError_t launch_tridiagonalize(int n, void* A, void* V, const EighWork& w, hipStream_t s);
+// Splits the tridiagonal, sets *w.status (0, or -1 if not finite), and the
+// eigenvalues (lam, d values; ascending within each unreduced block).
+hipError_t launch_tri_eigvals(int n, const EighWork& w, double* lam, hipStream_t s);
+// The orthonormal eigenvectors of the tridiagonal as the columns of Z (d x d
+// complex FP64, real values); scratch: d x d complex FP64.
+hipError_t launch_tri_vectors(int n, const EighWork& w, const double* lam, void* scratch, void* Z, hipStream_t s);
+// M = 1.5 I - 0.5 G (the Newton-Schulz matrix), d x d complex FP64.
+hipError_t launch_ns_matrix(int n, const void* G, void* M, hipStream_t s);
+// Z <- Q_H Z with Q_H the product of the reflectors (V, w.tau), in place;
+// W: d x d complex FP64 scratch (the blocks' V T factors).
+hipError_t launch_back_transform(int n, const void* V, const EighWork& w, void* Z, void* W, hipStream_t s);
+// *out = *w.status.
+hipError_t launch_eigh_status(const EighWork& w, int* out, hipStream_t s);
+
 // P-order absolute map and its adjoint (workspace laid out by
 // absmap_layout).  At most max_sweeps Jacobi sweeps, the stopping rule
 // decided on the device.  sweeps_dev == NULL: synchronous -- the host reads

@@ -130,8 +130,40 @@ AbsMapLayout absmap_layout(int n) {
     a.sk_bytes = stream_k_partial_bytes(QST_F64);
     a.sk = take(a.sk_bytes);
   }
+  a.eig = take(eigh_layout(n).total);
   a.total = off;
   return a;
+}
+
+EighLayout eigh_layout(int n) {
+  EighLayout e;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t d = size_t(1) << n;
+  const size_t blocks = (d - 1 + kEighBlock - 1) / kEighBlock;
+  e.diag = take(d * sizeof(double));
+  e.off = take(d * sizeof(double));
+  e.tau = take(d * 16);
+  e.y0 = take(d * 16);
+  e.y1 = take(d * 16);
+  e.p0 = take(kTrdMaxGroups * sizeof(double));
+  e.p1 = take(kTrdMaxGroups * sizeof(double));
+  e.bstart = take(d * sizeof(int));
+  e.bend = take(d * sizeof(int));
+  e.scal = take(8 * sizeof(double));
+  e.tfac = take(blocks * kEighBlock * kEighBlock * 16);
+  // partial products of the back-transformation, or the blocks' partial
+  // Gram matrices, whichever is larger
+  const size_t chunks = (d - 1 + eigh_chunk_rows(int(d)) - 1) / eigh_chunk_rows(int(d));
+  const size_t grams = blocks * size_t(eigh_gram_chunks(int(d))) * kEighBlock * kEighBlock;
+  e.pbuf = take(std::max(std::max<size_t>(chunks, 1) * kEighBlock * d, grams) * 16);
+  e.xbuf = take(kEighBlock * d * 16);
+  e.total = off;
+  return e;
 }
 
 WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {

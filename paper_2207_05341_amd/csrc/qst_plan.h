@@ -53,8 +53,27 @@ bool fused_likelihood(const PovmPlan& pl, qst_prec prec);
 // |lambda|^(P/4)), a few FP64 scalars and the FP64 stream-K partial tiles of
 // the complex products (N >= kStreamKMinQubits).
 struct AbsMapLayout {
-  size_t b0 = 0, b1 = 0, b2 = 0, part = 0, scal = 0, state = 0, sk = 0, sk_bytes = 0, total = 0;
+  size_t b0 = 0, b1 = 0, b2 = 0, part = 0, scal = 0, state = 0, sk = 0, sk_bytes = 0, eig = 0, total = 0;
 };
+// The direct eigensolver's small arrays (offsets from AbsMapLayout::eig):
+// the tridiagonal (diagonal, off-diagonal), the reflector scalars, the two
+// ping-pong matrix-vector products and their partial sums, the unreduced
+// block of every index, scalars and status, and the triangular factors of
+// the blocked back-transformation.
+constexpr int kEighBlock = 64;          // reflectors per back-transformation block
+constexpr int kTrdMaxGroups = 256;      // workgroups of a reduction step
+struct EighLayout {
+  size_t diag = 0, off = 0, tau = 0, y0 = 0, y1 = 0, p0 = 0, p1 = 0, bstart = 0, bend = 0, scal = 0, tfac = 0,
+         pbuf = 0, xbuf = 0, total = 0;
+};
+EighLayout eigh_layout(int n);
+// Rows per partial-sum chunk of the back-transformation (a multiple of 16):
+// d / 16 from d = 1024, else 64, so that there are at most 16 chunks (at
+// most d / 64 below 1024).
+inline int eigh_chunk_rows(int d) { return d / 16 > 64 ? d / 16 : 64; }
+// Rows per partial Gram matrix of a block of reflectors, and their number.
+constexpr int kEighGramRows = 128;
+inline int eigh_gram_chunks(int d) { return (d - 1 + kEighGramRows - 1) / kEighGramRows; }
 // Jacobi sweeps the absolute map and the general fidelity allow (the
 // graph-capturable calls take a smaller bound of their own).
 constexpr int kJacobiMaxSweeps = 40;

@@ -10,8 +10,10 @@ P = 0 and P = 4, scipy's fractional matrix powers and central differences).
 * dL/dT from a random dL/dA against the oracle's adjoint (independent of
   the eigenvector phases and order, which differ between the two);
 * closed forms: P = 0 gives I, P = 4 gives H H; P = 2 through the whole
-  likelihood equals the library's Chol_H mode; a diagonal T takes one sweep
-  and returns its diagonal;
+  likelihood equals the library's Chol_H mode; a diagonal T returns its
+  diagonal exactly;
+* the direct solver (cold calls) and the warm-started Jacobi solver agree;
+  degenerate spectra (the cluster treatment) against the oracle;
 * the whole chain T -> A -> likelihood differentiated by autograd against
   the oracle's grad_T_abs.
 
@@ -74,8 +76,7 @@ def test_abs_map_against_oracle(prec, n):
         say(f"N={n} {prec} P={P}: sweeps {sweeps}, {1e3 * dt:.1f} ms, A rel err {e:.2e}")
         assert e <= TOL[prec], (P, e)
         assert np.abs(Qn.conj().T @ Qn - np.eye(d)).max() <= 1e-13 * d
-        # the sweeps stop at an off-diagonal norm of 1e-14 (FP64) or 1e-10
-        # (FP32 storage) of ||H||
+        assert sweeps == 0  # the direct solver
         assert rel_fro((Qn * ln) @ Qn.conj().T, H) <= (1e-13 if prec == "f64" else 1e-9)
         assert np.abs(np.sort(ln) - lam_w).max() <= 1e-13 * np.abs(lam_w).max()
     A2 = qst.abs_map(Tg, 1.5, prec)[0]
@@ -107,8 +108,8 @@ def test_abs_map_backward_against_oracle(prec, n):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_abs_map_closed_forms(prec):
-    """P = 0: A = I; P = 4: A = H H; a diagonal T: one sweep, lam = its
-    real diagonal."""
+    """P = 0: A = I; P = 4: A = H H; a diagonal T: lam = its real diagonal
+    exactly (every reflector is the identity)."""
     g = S.rng(8300)
     n, d = 7, 128
     T = S.ginibre(g, d).astype(ctype(prec))
@@ -120,7 +121,7 @@ def test_abs_map_closed_forms(prec):
     assert rel_fro(A4, H @ H) <= TOL[prec]
     D = np.diag(g.standard_normal(d) + 1j * g.standard_normal(d)).astype(ctype(prec))
     A, Q, lam, sweeps = qst.abs_map(dev_matrix(D), 2.0, prec)
-    assert sweeps == 1
+    assert sweeps == 0
     assert np.array_equal(lam.cpu().numpy(), np.diag(D).real.astype(np.float64))
     assert rel_fro(A.cpu().numpy(), np.diag(np.abs(np.diag(D).real)).astype(np.complex128)) <= TOL[prec]
 
@@ -210,8 +211,8 @@ def test_abs_map_n11_against_oracle(prec):
     el = float(np.abs(np.sort(lam.cpu().numpy()) - np.sort(lw)).max() / np.abs(lw).max())
     say(f"N=11 {prec} P={P}: sweeps {sweeps}, {dt:.2f} s, A rel err {e:.2e}, "
         f"dL/dT rel err {eg:.2e}, spectrum {el:.2e}")
-    # FP64: both sides' eigendecompositions (the library's Jacobi, LAPACK's
-    # in the oracle) have backward errors that grow about linearly with d,
+    # FP64: both sides' eigendecompositions (the library's, LAPACK's in the
+    # oracle) have backward errors that grow about linearly with d,
     # and the adjoint is first order in them; the 1e-12 met up to d = 1024
     # scales to 2e-12 at d = 2048
     tol = 2e-12 if prec == "f64" else TOL[prec]
@@ -221,9 +222,10 @@ def test_abs_map_n11_against_oracle(prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_abs_map_warm_start(prec):
-    """Warm start from the eigenvectors of a nearby matrix: the same A and
-    dL/dT as a cold start (to the tolerance), in fewer sweeps; AbsProjection
-    over a drifting T (a training loop's pattern) against cold-start calls."""
+    """Warm start (the Jacobi solver) from the eigenvectors of a nearby
+    matrix: the same A and dL/dT as a cold start (the direct solver) to the
+    tolerance, in a few sweeps; AbsProjection(warm=True) over a drifting T
+    (a training loop's pattern) against cold-start calls."""
     n, d, P = 7, 128, 1.5
     g = S.rng(8700)
     T1 = S.ginibre(g, d)
@@ -232,8 +234,8 @@ def test_abs_map_warm_start(prec):
     _, Q1, _, _ = qst.abs_map(dev_matrix(T1.astype(ctype(prec))), P, prec)
     A_c, Q_c, lam_c, sw_c = qst.abs_map(dev_matrix(T2), P, prec)
     A_w, Q_w, lam_w, sw_w = qst.abs_map(dev_matrix(T2), P, prec, Q0=Q1)
-    say(f"{prec}: cold {sw_c} sweeps, warm {sw_w} sweeps")
-    assert sw_w < sw_c
+    say(f"{prec}: cold {sw_c} sweeps (direct), warm {sw_w} sweeps")
+    assert sw_c == 0 and 1 <= sw_w <= 4
     A_o = O.abs_map(T2.astype(np.complex128), P)[0]
     assert rel_fro(A_w.cpu().numpy(), A_o) <= TOL[prec]
     assert rel_fro(A_w.cpu().numpy(), A_c.cpu().numpy()) <= TOL[prec]
@@ -245,7 +247,7 @@ def test_abs_map_warm_start(prec):
     f = S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))
     rt = torch.float64 if prec == "f64" else torch.float32
     fg = torch.from_numpy(f).to(DEV, rt)
-    proj = qst.AbsProjection(P, prec)
+    proj = qst.AbsProjection(P, prec, warm=True)
     for k in range(4):
         Tk = (T1 + (1e-3 * k) * E).astype(ctype(prec))
         out = []
@@ -258,13 +260,64 @@ def test_abs_map_warm_start(prec):
         say(f"  step {k}: warm sweeps {proj.sweeps}, L {Lw:.12f} vs {Lc:.12f}")
         assert abs(Lw - Lc) <= TOL[prec] * abs(Lc) and rel_fro(gw, gc) <= 10 * TOL[prec]
         if k:
-            assert proj.sweeps < sw_c
+            assert 1 <= proj.sweeps <= 4
+
+
+@pytest.mark.parametrize("case", ["4-fold", "two values", "cluster 1e-9", "identity + 1e-9 G", "rank 6"])
+def test_abs_map_degenerate_spectra(case):
+    """Repeated and nearly repeated eigenvalues (the direct solver's cluster
+    treatment, and splitting of the tridiagonal): A and dL/dT against the
+    oracle, Q unitary, Q Lambda Q^dagger = H."""
+    n, d, P = 7, 128, 1.5
+    g = S.rng(8750)
+    U = np.linalg.qr(S.ginibre(g, d))[0]
+    if case == "4-fold":
+        lam = np.repeat(g.standard_normal(d // 4), 4)
+    elif case == "two values":
+        lam = np.repeat(g.standard_normal(2), d // 2)
+    elif case == "cluster 1e-9":
+        lam = np.sort(g.standard_normal(d))
+        lam[d // 2:d // 2 + 5] = lam[d // 2] + 1e-9 * np.arange(5)
+    elif case == "rank 6":
+        lam = np.zeros(d)
+        lam[:6] = g.standard_normal(6)
+    else:
+        lam = np.ones(d)
+    H = (U * lam) @ U.conj().T
+    if case == "identity + 1e-9 G":
+        H = np.eye(d) + 1e-9 * O.hermitian_part(S.ginibre(g, d))
+    H = O.hermitian_part(H)
+    A, Q, lw, sweeps = qst.abs_map(dev_matrix(H), P, "f64")
+    GA = S.ginibre(g, d)
+    GT = qst.abs_map_backward(Q, lw, P, dev_matrix(GA), "f64")
+    torch.cuda.synchronize()
+    A_w, Qo, lo = O.abs_map(H, P)
+    Qn, ln = Q.cpu().numpy(), lw.cpu().numpy()
+    e = rel_fro(A.cpu().numpy(), A_w)
+    uq = np.abs(Qn.conj().T @ Qn - np.eye(d)).max()
+    res = rel_fro((Qn * ln) @ Qn.conj().T, H)
+    say(f"{case}: A rel err {e:.2e}, |Q^H Q - I| {uq:.1e}, residual {res:.1e}")
+    assert sweeps == 0
+    assert uq <= 1e-13 * d and res <= 1e-13
+    # rank 6: the d - 6 zero eigenvalues come out at the rounding level on
+    # both sides, and |l|^(3/4) of them differs by about (1e-16)^(3/4)
+    assert e <= (1e-10 if case == "rank 6" else TOL["f64"])
+    if case in ("4-fold", "two values", "cluster 1e-9"):
+        # the oracle's adjoint on the constructed spectrum (ascending, as
+        # eigh orders its Q), so that ties are exact: its divided differences
+        # are the plain quotient, which LAPACK's eigenvalues of a repeated
+        # eigenvalue (apart by rounding) would turn into cancellation; near
+        # ties 1e-9 apart still cost it about 1e-16 / 1e-9 relative
+        want = O.abs_map_backward(Qo, np.sort(lam), P, GA)
+        eg = rel_fro(GT.cpu().numpy(), want)
+        say(f"  dL/dT rel err {eg:.2e}")
+        assert eg <= (1e-6 if case == "cluster 1e-9" else 1e-12)
 
 
 def test_abs_map_non_finite_input_is_an_error():
-    """A NaN in T makes the off-diagonal norm non-finite after the first
-    sweep: qst_abs_map and qst_fidelity_general return QST_ERR_INVALID_ARG
-    (raised as QstError) instead of a result."""
+    """A NaN in T makes the tridiagonal matrix non-finite: qst_abs_map and
+    qst_fidelity_general return QST_ERR_INVALID_ARG (raised as QstError)
+    instead of a result; so does a warm-started call."""
     d = 16
     g = S.rng(8800)
     T = S.ginibre(g, d)
@@ -275,26 +328,36 @@ def test_abs_map_non_finite_input_is_an_error():
     rho = torch.eye(d, dtype=torch.complex128, device=DEV) / d
     with pytest.raises(qst.QstError, match="did not converge"):
         qst.fidelity_general(Tg, rho, "f64")
+    Q0 = torch.eye(d, dtype=torch.complex128, device=DEV)
+    with pytest.raises(qst.QstError, match="did not converge"):
+        qst.abs_map(Tg, 1.5, "f64", Q0=Q0)
     # the library stays usable
     T[3, 5] = 0.0
     A, _, _, sweeps = qst.abs_map(torch.from_numpy(T).to(DEV), 1.5, "f64")
-    assert sweeps > 0 and rel_fro(A.cpu().numpy(), O.abs_map(T, 1.5)[0]) <= TOL["f64"]
+    assert sweeps == 0 and rel_fro(A.cpu().numpy(), O.abs_map(T, 1.5)[0]) <= TOL["f64"]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_abs_map_async_equals_sync(prec):
-    """qst_abs_map_async (stopping rule on the device, nothing read back)
-    against qst_abs_map: the same sweeps and bitwise the same A, Q, lam;
-    too few sweeps report -1; qst_fidelity_general_async likewise."""
+    """qst_abs_map_async (nothing read back) against qst_abs_map: the same
+    sweeps and bitwise the same A, Q, lam, for the direct solver and for a
+    warm start (stopping rule on the device); too few warm sweeps report -1;
+    qst_fidelity_general_async likewise."""
     n, d, P = 6, 64, 1.5
     g = S.rng(8900)
     T = dev_matrix(S.ginibre(g, d).astype(ctype(prec)))
     A, Q, lam, sw = qst.abs_map(T, P, prec)
     A2, Q2, lam2, sw2 = qst.abs_map_async(T, P, prec, max_sweeps=20)
     torch.cuda.synchronize()
-    assert int(sw2.item()) == sw
+    assert sw == 0 and int(sw2.item()) == sw
     assert torch.equal(A, A2) and torch.equal(Q, Q2) and torch.equal(lam, lam2)
-    _, _, _, sw3 = qst.abs_map_async(T, P, prec, max_sweeps=2)
+    T2 = (T + 1e-3 * dev_matrix(S.ginibre(g, d).astype(ctype(prec)))).contiguous()
+    A, Qw, lam, sw = qst.abs_map(T2, P, prec, Q0=Q)
+    A2, Qw2, lam2, sw2 = qst.abs_map_async(T2, P, prec, max_sweeps=20, Q0=Q)
+    torch.cuda.synchronize()
+    assert sw >= 1 and int(sw2.item()) == sw
+    assert torch.equal(A, A2) and torch.equal(Qw, Qw2) and torch.equal(lam, lam2)
+    _, _, _, sw3 = qst.abs_map_async(T2, P, prec, max_sweeps=1, Q0=Q)
     assert int(sw3.item()) == -1
     rho = dev_matrix(S.depolarised_pure(S.haar_vector(g, d), 0.2).astype(ctype(prec)))
     F, fs = qst.fidelity_general(T, rho, prec)
@@ -303,18 +366,22 @@ def test_abs_map_async_equals_sync(prec):
     assert int(fs2.item()) == fs and float(F2.item()) == float(F.item())
 
 
-def test_abs_map_async_graph_replays():
+@pytest.mark.parametrize("warm", [True, False])
+def test_abs_map_async_graph_replays(warm):
     """qst_abs_map_async captured in a HIP graph (outputs, workspace and the
-    warm start preallocated): three replays, with eager library work and
+    warm start preallocated), for the warm-started Jacobi solver and for the
+    direct solver: three replays, with eager library work and
     synchronisations between them, each bitwise equal to the eager call."""
     n, d, P, prec = 7, 128, 1.0, "f32"
     g = S.rng(8910)
     T = dev_matrix(S.ginibre(g, d).astype(np.complex64))
     _, Q0, _, _ = qst.abs_map(T, P, prec)
+    if not warm:
+        Q0 = None
     T2 = (T + 1e-3 * dev_matrix(S.ginibre(g, d).astype(np.complex64))).contiguous()
     A_e, Q_e, lam_e, sw_e = qst.abs_map_async(T2, P, prec, max_sweeps=6, Q0=Q0)
     torch.cuda.synchronize()
-    assert 0 < int(sw_e.item()) <= 6
+    assert (0 < int(sw_e.item()) <= 6) if warm else int(sw_e.item()) == 0
     A = torch.empty_like(A_e)
     Q = torch.empty_like(Q_e)
     lam = torch.empty_like(lam_e)
@@ -342,16 +409,18 @@ def test_abs_map_async_graph_replays():
         torch.cuda.synchronize()
 
 
-def test_abs_projection_unsynchronised_warm_steps():
-    """AbsProjection(max_sweeps=...) runs its warm-started calls without
-    synchronising: the same losses and gradients as the synchronous
-    projection over a drifting T."""
+@pytest.mark.parametrize("warm", [False, True])
+def test_abs_projection_unsynchronised_warm_steps(warm):
+    """AbsProjection(max_sweeps=...) runs its calls without synchronising
+    (the direct solver, or warm-started Jacobi sweeps): the same losses and
+    gradients as the synchronous projection over a drifting T."""
     n, d, P, prec = 7, 128, 1.5, "f64"
     g = S.rng(8920)
     T1, E = S.ginibre(g, d), S.ginibre(g, d)
     psi = S.haar_vector(g, d)
     f = torch.from_numpy(S.multinomial_freqs(g, 100_000, O.probs_real(S.depolarised_pure(psi, 0.1)))).to(DEV)
-    sync_p, async_p = qst.AbsProjection(P, prec), qst.AbsProjection(P, prec, max_sweeps=6)
+    sync_p = qst.AbsProjection(P, prec, warm=warm)
+    async_p = qst.AbsProjection(P, prec, max_sweeps=6, warm=warm)
     for k in range(4):
         Tk = T1 + (1e-3 * k) * E
         out = []
