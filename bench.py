@@ -151,14 +151,17 @@ def time_steps(qst, T, f, prec, steps, warmup, only=None, fused=True):
     return (t1 - t0) / steps, kern
 
 
-def batched(qst, prec, dev, reps=20):
+def batched(qst, prec, dev, reps=20, accuracy_sample=48):
     """Batched form: 1024 instances, N uniform on {3..8} (seed 9), Ginibre T,
     Porter-Thomas stand-in frequencies from 10^5 shots each.  One graph
     replay of the persistent launch vs 1024 separate single-instance call
-    sequences (qst_likelihood + qst_grad_product) through the same C ABI."""
+    sequences (qst_likelihood + qst_grad_product) through the same C ABI;
+    the tuned launch shape; the error of L and of the gradient against the
+    FP64 oracle over a sample of instances (every N, the largest included)."""
     import numpy as np
     import torch
 
+    import oracle as O
     import synth as S
 
     g = S.rng(9)
@@ -174,7 +177,7 @@ def batched(qst, prec, dev, reps=20):
     T_all, f_all = plan.pack(Ts, fs, dev)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
-        plan.run(T_all, f_all, use_graph=True)  # tunes, captures
+        nll, grad, _ = plan.run(T_all, f_all, use_graph=True)  # tunes, captures
         side.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(side)
@@ -183,6 +186,20 @@ def batched(qst, prec, dev, reps=20):
         ev1.record(side)
     side.synchronize()
     graph_ms = ev0.elapsed_time(ev1) / reps
+    # accuracy against the oracle (on the same rounded inputs)
+    nll_h, grad_h = nll.cpu().numpy(), grad.cpu().numpy()
+    sample = sorted(set(list(range(0, 1024, 1024 // accuracy_sample)) + [i for i in range(1024) if ns[i] == 8][:4]))
+    worst_L = worst_g = 0.0
+    for i in sample:
+        T64, f64 = Ts[i].astype(np.complex128), fs[i].astype(np.float64)
+        rho, tau = O.state_map(T64)
+        p = O.probs_real(rho)
+        L_ref = O.nll_vec(p, f64)
+        g_ref = (2.0 / tau) * (O.adjoint(O.cotangent(p, f64), ns[i]) @ T64)
+        d = 1 << ns[i]
+        gi = grad_h[plan.t_off[i]:plan.t_off[i + 1]].reshape(d, d)
+        worst_L = max(worst_L, abs(nll_h[i, 0] - L_ref) / abs(L_ref))
+        worst_g = max(worst_g, float(np.linalg.norm(gi - g_ref) / np.linalg.norm(g_ref)))
     # separate launches
     Tg = [torch.from_numpy(T).to(dev) for T in Ts]
     fg = [torch.from_numpy(f).to(dev) for f in fs]
@@ -198,7 +215,8 @@ def batched(qst, prec, dev, reps=20):
     return {"instances": len(ns), "n_range": [3, 8], "precision": prec,
             "graph_ms_per_batch": graph_ms, "instances_per_s": len(ns) / (graph_ms * 1e-3),
             "separate_launches_ms": sep_ms, "speedup_vs_separate": sep_ms / graph_ms,
-            "tflops": flops / (graph_ms * 1e-3) / 1e12, "tuned": info}
+            "tflops": flops / (graph_ms * 1e-3) / 1e12, "tuned": info,
+            "vs_oracle": {"instances": len(sample), "max_rel_err_L": worst_L, "max_rel_err_grad": worst_g}}
 
 
 def state_maps(qst, T, f, prec, reps=50):
@@ -756,7 +774,11 @@ def main():
     absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
     genp = None if args.no_long else general_povms(qst, args.prec, dev)
     del Tm, fm
-    batch = None if args.no_batched else batched(qst, args.prec, dev)
+    batch = None
+    if not args.no_batched:
+        batch = batched(qst, args.prec, dev)
+        if args.prec != "f64":  # the FP64 path's batch, for its speed at its accuracy
+            batch["f64"] = batched(qst, "f64", dev)
     cpu, acc_oracle = None, None
     if not args.no_cpu_baseline:
         # the timed oracle leg also gives the reference outputs for the

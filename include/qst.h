@@ -583,8 +583,9 @@ size_t qst_profile_report(char* buf, size_t len, int reset);
  * t_off and f_off (count + 1 entries each) come from qst_batch_offsets.
  * The plan owns device memory (descriptor table, work counter, per-workgroup
  * scratch) and, in graph mode, a HIP graph, until qst_batch_plan_destroy.
- * On its first run the plan times its candidate launch shapes (grid size,
- * instance order) on the given buffers and keeps the fastest; with a cache
+ * On its first run the plan times its candidate launch shapes (workgroup
+ * size, the POVM pass plan of N = 7 and 8, grid size, instance order) on the
+ * given buffers and keeps the fastest; with a cache
  * file (tune_cache, else the QST_TUNE_CACHE environment variable; NULL/unset
  * = no cache) the choice is appended there and reused by later plans with
  * the same precision, POVM kind, qubit-count histogram and device.
@@ -608,6 +609,13 @@ qst_status qst_batch_run(qst_batch_plan* plan, const void* T_all, const void* f_
  * instances first), tuned_ms (time of one batch when tuned). */
 qst_status qst_batch_info(const qst_batch_plan* plan, int* grid, int* sorted_order,
                           double* tuned_ms);
+
+/* The rest of the tuned shape: threads (workgroup size: 512 or 256 for
+ * QST_F32, 256 otherwise) and register_round_passes (1: N = 7, 8 run the
+ * register-round pair of POVM passes with the likelihood fused into the
+ * second, for the tetrahedral POVM in FP64 and FP32; 0: the generic
+ * per-qubit passes).  Either pointer may be NULL. */
+qst_status qst_batch_shape(const qst_batch_plan* plan, int* threads, int* register_round_passes);
 
 void qst_batch_plan_destroy(qst_batch_plan* plan);
 

@@ -827,7 +827,10 @@ class BatchPlan:
         grid, so, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         _lib.check(_lib.lib().qst_batch_info(self._handle, ctypes.byref(grid), ctypes.byref(so), ctypes.byref(ms)),
                    "qst_batch_info")
-        return {"grid": grid.value, "sorted_order": bool(so.value), "tuned_ms": ms.value}
+        th, rr = ctypes.c_int(), ctypes.c_int()
+        _lib.check(_lib.lib().qst_batch_shape(self._handle, ctypes.byref(th), ctypes.byref(rr)), "qst_batch_shape")
+        return {"grid": grid.value, "sorted_order": bool(so.value), "tuned_ms": ms.value, "threads": th.value,
+                "register_round_passes": bool(rr.value)}
 
     def close(self):
         if self._handle is not None:

@@ -58,6 +58,7 @@ SIGNATURES = {
     "qst_batch_offsets": (_int, [_vp, _vp, _vp]),
     "qst_batch_run": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
     "qst_batch_info": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]),
+    "qst_batch_shape": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "qst_batch_plan_destroy": (None, [_vp]),
 }
 

@@ -14,8 +14,11 @@
 //
 // The host plan (qst_batch_plan_*) owns the descriptor table, the work
 // counter, the scratch and an optional HIP graph of (counter reset + kernel),
-// and picks the grid size and instance order with a small autotuner whose
-// choices can be cached in a text file.
+// and picks the launch shape with a small autotuner whose choices can be
+// cached in a text file: the grid size, the instance order, the workgroup
+// size (FP32: 512 threads with two product tiles at a time, or 256 with
+// one) and the POVM pass plan of N = 7, 8 (the register-round pair of
+// passes with the fused likelihood, or the generic per-qubit passes).
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -64,6 +67,7 @@ struct BatchArgs {
   unsigned char* scratch;
   int64_t stride;  // bytes of scratch per workgroup
   int nmax;
+  int fast_forms;  // 1: the register-round pass forms where a plan has one; 0: generic passes
   BatchPlanTable plan;
   ModeMatrix W, V;
 };
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
     // last pass fused with the likelihood (for the tetrahedral POVM in FP32
     // and FP64: with the general 4 x 4 form, or beside the BF16 products,
     // they would cost registers -- spills, or the second BF16 workgroup per CU)
-    const int fastp = (TETRA && !BF16) ? fast_plan(b.plan, n, sizeof(R) == 8) : 0;
+    const int fastp = (TETRA && !BF16 && b.fast_forms) ? fast_plan(b.plan, n, sizeof(R) == 8) : 0;
     double acc = 0.0, facc = 0.0;
     for (int64_t e0 = 0; e0 < D; e0 += kBatch * THREADS) {
       Cx<R> v[kBatch];
@@ -518,57 +522,49 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(BatchArgs b) {
   }
 }
 
-// Workgroup size of the batched kernel: 512 (two tile groups) for FP32,
-// whose registers allow two waves per SIMD; 256 for FP64 and BF16.
-template <typename R, bool BF16>
-constexpr int kBatchThreads = (sizeof(R) == 4 && !BF16) ? 512 : 256;
+// Workgroup sizes of the batched kernel: FP32 512 (two tile groups; its
+// registers allow two waves per SIMD) or 256; FP64 and BF16 256.
+template <typename R, bool BF16, int NT>
+void* batch_kernel_fn(bool tetra) {
+  using namespace gemm;
+  if constexpr (BF16) {
+    return tetra ? reinterpret_cast<void*>(&batch_kernel<HerkBf16Policy, HemmBf16x3Policy, float, true, true, NT>)
+                 : reinterpret_cast<void*>(&batch_kernel<HerkBf16Policy, HemmBf16x3Policy, float, false, true, NT>);
+  } else {
+    return tetra ? reinterpret_cast<void*>(&batch_kernel<BatchHerk<R>, BatchHemm<R>, R, true, false, NT>)
+                 : reinterpret_cast<void*>(&batch_kernel<BatchHerk<R>, BatchHemm<R>, R, false, false, NT>);
+  }
+}
 
-template <typename R, bool TETRA, bool BF16>
-struct BatchKernelOf;
-template <bool TETRA>
-struct BatchKernelOf<double, TETRA, false> {
-  static void* fn() {
-    return reinterpret_cast<void*>(
-        &batch_kernel<BatchHerk<double>, BatchHemm<double>, double, TETRA, false, kBatchThreads<double, false>>);
-  }
-};
-template <bool TETRA>
-struct BatchKernelOf<float, TETRA, false> {
-  static void* fn() {
-    return reinterpret_cast<void*>(
-        &batch_kernel<BatchHerk<float>, BatchHemm<float>, float, TETRA, false, kBatchThreads<float, false>>);
-  }
-};
-template <bool TETRA>
-struct BatchKernelOf<float, TETRA, true> {
-  static void* fn() {
-    return reinterpret_cast<void*>(
-        &batch_kernel<gemm::HerkBf16Policy, gemm::HemmBf16x3Policy, float, TETRA, true, kBatchThreads<float, true>>);
-  }
-};
-
-template <class PH, class PM, typename R, bool BF16>
+template <class PH, class PM, typename R, bool BF16, int NT>
 hipError_t launch_batch_t(bool tetra, const BatchArgs& a, int grid, hipStream_t s) {
-  constexpr int NT = kBatchThreads<R, BF16>;
   if (tetra) batch_kernel<PH, PM, R, true, BF16, NT><<<unsigned(grid), NT, 0, s>>>(a);
   else batch_kernel<PH, PM, R, false, BF16, NT><<<unsigned(grid), NT, 0, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_kernel(qst_prec prec, bool tetra, const BatchArgs& a, int grid, hipStream_t s) {
+hipError_t launch_batch_kernel(qst_prec prec, bool tetra, const BatchArgs& a, int grid, int threads, hipStream_t s) {
   using namespace gemm;
-  if (prec == QST_F64) return launch_batch_t<BatchHerk<double>, BatchHemm<double>, double, false>(tetra, a, grid, s);
-  if (prec == QST_F32) return launch_batch_t<BatchHerk<float>, BatchHemm<float>, float, false>(tetra, a, grid, s);
-  return launch_batch_t<HerkBf16Policy, HemmBf16x3Policy, float, true>(tetra, a, grid, s);
+  if (prec == QST_F64)
+    return launch_batch_t<BatchHerk<double>, BatchHemm<double>, double, false, 256>(tetra, a, grid, s);
+  if (prec == QST_F32) {
+    if (threads == 256) return launch_batch_t<BatchHerk<float>, BatchHemm<float>, float, false, 256>(tetra, a, grid, s);
+    return launch_batch_t<BatchHerk<float>, BatchHemm<float>, float, false, 512>(tetra, a, grid, s);
+  }
+  return launch_batch_t<HerkBf16Policy, HemmBf16x3Policy, float, true, 256>(tetra, a, grid, s);
 }
 
-int batch_occupancy(qst_prec prec) {
-  void* fn = prec == QST_F64 ? BatchKernelOf<double, true, false>::fn()
-             : prec == QST_F32 ? BatchKernelOf<float, true, false>::fn()
-                               : BatchKernelOf<float, true, true>::fn();
-  const int threads = prec == QST_F64 ? kBatchThreads<double, false>
-                      : prec == QST_F32 ? kBatchThreads<float, false>
-                                        : kBatchThreads<float, true>;
+// The workgroup sizes a precision offers (the first is the default).
+std::vector<int> batch_thread_options(qst_prec prec) {
+  if (prec == QST_F32) return {512, 256};
+  return {256};
+}
+
+int batch_occupancy(qst_prec prec, int threads) {
+  void* fn = prec == QST_F64   ? batch_kernel_fn<double, false, 256>(true)
+             : prec == QST_F32 ? (threads == 256 ? batch_kernel_fn<float, false, 256>(true)
+                                                 : batch_kernel_fn<float, false, 512>(true))
+                               : batch_kernel_fn<float, true, 256>(true);
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), threads, 0) != hipSuccess ||
       n <= 0)
@@ -598,12 +594,16 @@ struct qst_batch_plan {
   int* d_counter = nullptr;
   unsigned char* d_scratch = nullptr;
   int cus = 256;
-  int occ = 1;
+  std::vector<int> thread_options;  // workgroup sizes offered (first: default)
+  std::vector<int> occ;             // occupancy of each
+  int max_grid = 0;                 // the scratch covers this many workgroups
   // tuning
   std::string cache_path, key;
   bool tuned = false;
   int grid = 0;
   bool sorted_order = true;
+  int threads = 256;
+  bool fast_forms = true;
   double tuned_ms = 0.0;
   // graph
   hipGraph_t graph = nullptr;
@@ -616,6 +616,8 @@ struct qst_batch_plan {
   hipStream_t g_stream = nullptr;
   int g_grid = 0;
   bool g_sorted = true;
+  int g_threads = 0;
+  bool g_fast = true;
 };
 
 namespace qst {
@@ -655,7 +657,17 @@ bool read_cache(qst_batch_plan* p) {
     int grid = 0, sorted = 1;
     double ms = 0;
     if (ls >> key >> grid >> sorted >> ms && key == p->key && grid > 0) {
-      p->grid = std::min(grid, p->cus * p->occ);
+      int threads = p->thread_options[0], fast = 1;
+      if (!(ls >> threads >> fast)) {  // a line without the shape fields: the defaults
+        threads = p->thread_options[0];
+        fast = 1;
+      }
+      size_t v = 0;
+      while (v < p->thread_options.size() && p->thread_options[v] != threads) ++v;
+      if (v == p->thread_options.size()) continue;  // a size this precision does not offer
+      p->threads = threads;
+      p->fast_forms = fast != 0;
+      p->grid = std::min(grid, p->cus * p->occ[v]);
       p->sorted_order = sorted != 0;
       p->tuned_ms = ms;
       p->tuned = true;
@@ -667,16 +679,18 @@ bool read_cache(qst_batch_plan* p) {
 void write_cache(const qst_batch_plan* p) {
   if (p->cache_path.empty()) return;
   std::ofstream out(p->cache_path, std::ios::app);
-  out << p->key << " " << p->grid << " " << (p->sorted_order ? 1 : 0) << " " << p->tuned_ms << "\n";
+  out << p->key << " " << p->grid << " " << (p->sorted_order ? 1 : 0) << " " << p->tuned_ms << " " << p->threads
+      << " " << (p->fast_forms ? 1 : 0) << "\n";
 }
 
-hipError_t enqueue(qst_batch_plan* p, int grid, bool sorted, hipStream_t s) {
+hipError_t enqueue(qst_batch_plan* p, int grid, bool sorted, int threads, bool fast, hipStream_t s) {
   qst::BatchArgs a = p->args;
   a.order = sorted ? p->d_order : p->d_order_natural;
+  a.fast_forms = fast ? 1 : 0;
   qst::reset_counter_kernel<<<1, 1, 0, s>>>(p->d_counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return qst::launch_batch_kernel(p->prec, p->tetra, a, grid, s);
+  return qst::launch_batch_kernel(p->prec, p->tetra, a, grid, threads, s);
 }
 
 }  // namespace
@@ -722,11 +736,18 @@ qst_status qst_batch_plan_create(const int* n_qubits, int count, qst_prec prec, 
     free_plan(p);
     return qst::fail_status(QST_ERR_HIP, std::string("device query: ") + hipGetErrorString(e));
   }
-  p->occ = std::max(1, qst::batch_occupancy(prec));
+  p->thread_options = qst::batch_thread_options(prec);
+  int occ_max = 1;
+  for (int th : p->thread_options) {
+    p->occ.push_back(std::max(1, qst::batch_occupancy(prec, th)));
+    occ_max = std::max(occ_max, p->occ.back());
+  }
+  p->threads = p->thread_options[0];
   const int64_t dmax = int64_t(1) << p->nmax, Dmax = dmax * dmax;
   const size_t cb = qst::complex_bytes(prec), rb = qst::real_bytes(prec);
   const int64_t stride = int64_t((2 * Dmax * cb + Dmax * rb + 64 + 255) / 256 * 256);
-  const int max_grid = p->cus * p->occ;
+  const int max_grid = p->cus * occ_max;
+  p->max_grid = max_grid;
   e = hipMalloc(&p->d_items, sizeof(qst::BatchItem) * count);
   if (e == hipSuccess) e = hipMalloc(&p->d_order, sizeof(int) * count);
   if (e == hipSuccess) e = hipMalloc(&p->d_order_natural, sizeof(int) * count);
@@ -775,7 +796,7 @@ qst_status qst_batch_plan_create(const int* n_qubits, int count, qst_prec prec, 
     if (env) path = env;
   }
   p->cache_path = path;
-  p->grid = max_grid;
+  p->grid = p->cus * p->occ[0];
   read_cache(p);
   *out = p;
   qst::clear_error();
@@ -803,27 +824,38 @@ qst_status qst_batch_run(qst_batch_plan* p, const void* T_all, const void* f_all
   p->args.grad_all = grad_all;
   hipError_t e;
   if (!p->tuned) {
-    // autotune: grid (CUs x {1..occupancy}) x order (cost-sorted, natural)
+    // autotune: workgroup size x POVM pass plan of N = 7, 8 (register-round
+    // forms or generic passes; the former exist for the tetrahedral POVM in
+    // FP32 and FP64) x grid (CUs x {1..occupancy}) x order (cost-sorted,
+    // natural); the fastest of three timed runs after a warm-up each
     hipEvent_t a = nullptr, b = nullptr;
     e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     double best = 1e30;
-    int best_grid = p->grid;
-    bool best_sorted = true;
-    for (int m = 1; m <= p->occ && e == hipSuccess; ++m) {
-      for (int so = 1; so >= 0 && e == hipSuccess; --so) {
-        const int grid = p->cus * m;
-        e = enqueue(p, grid, so != 0, s);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(a, s);
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = enqueue(p, grid, so != 0, s);
-        if (e == hipSuccess) e = hipEventRecord(b, s);
-        if (e == hipSuccess) e = hipEventSynchronize(b);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-        if (e == hipSuccess && ms / 3.0 < best) {
-          best = ms / 3.0;
-          best_grid = grid;
-          best_sorted = so != 0;
+    int best_grid = p->grid, best_threads = p->threads;
+    bool best_sorted = true, best_fast = true;
+    const bool has_fast = p->tetra && p->prec != QST_BF16GEMM;
+    for (size_t v = 0; v < p->thread_options.size() && e == hipSuccess; ++v) {
+      const int th = p->thread_options[v];
+      for (int fast = 1; fast >= (has_fast ? 0 : 1) && e == hipSuccess; --fast) {
+        for (int m = 1; m <= p->occ[v] && e == hipSuccess; ++m) {
+          for (int so = 1; so >= 0 && e == hipSuccess; --so) {
+            const int grid = p->cus * m;
+            e = enqueue(p, grid, so != 0, th, fast != 0, s);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(a, s);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = enqueue(p, grid, so != 0, th, fast != 0, s);
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e == hipSuccess && ms / 3.0 < best) {
+              best = ms / 3.0;
+              best_grid = grid;
+              best_sorted = so != 0;
+              best_threads = th;
+              best_fast = fast != 0;
+            }
+          }
         }
       }
     }
@@ -832,19 +864,21 @@ qst_status qst_batch_run(qst_batch_plan* p, const void* T_all, const void* f_all
     if (e != hipSuccess) return qst::fail_status(QST_ERR_HIP, std::string("batch tuning: ") + hipGetErrorString(e));
     p->grid = best_grid;
     p->sorted_order = best_sorted;
+    p->threads = best_threads;
+    p->fast_forms = best_fast;
     p->tuned_ms = best;
     p->tuned = true;
     write_cache(p);
   }
   if (!use_graph) {
-    e = enqueue(p, p->grid, p->sorted_order, s);
+    e = enqueue(p, p->grid, p->sorted_order, p->threads, p->fast_forms, s);
     if (e != hipSuccess) return qst::fail_status(QST_ERR_HIP, std::string("batch launch: ") + hipGetErrorString(e));
     qst::clear_error();
     return QST_OK;
   }
   const bool stale = !p->exec || p->g_T != T_all || p->g_f != f_all || p->g_nll != nll_out || p->g_bad != bad_out ||
                      p->g_grad != grad_all || p->g_stream != s || p->g_grid != p->grid ||
-                     p->g_sorted != p->sorted_order;
+                     p->g_sorted != p->sorted_order || p->g_threads != p->threads || p->g_fast != p->fast_forms;
   if (stale) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -852,7 +886,7 @@ qst_status qst_batch_run(qst_batch_plan* p, const void* T_all, const void* f_all
     p->graph = nullptr;
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      const hipError_t e1 = enqueue(p, p->grid, p->sorted_order, s);
+      const hipError_t e1 = enqueue(p, p->grid, p->sorted_order, p->threads, p->fast_forms, s);
       e = hipStreamEndCapture(s, &p->graph);
       if (e == hipSuccess) e = e1;
     }
@@ -866,10 +900,19 @@ qst_status qst_batch_run(qst_batch_plan* p, const void* T_all, const void* f_all
     p->g_stream = s;
     p->g_grid = p->grid;
     p->g_sorted = p->sorted_order;
+    p->g_threads = p->threads;
+    p->g_fast = p->fast_forms;
   }
   e = hipGraphLaunch(p->exec, s);
   if (e != hipSuccess) return qst::fail_status(QST_ERR_HIP, std::string("batch graph launch: ") + hipGetErrorString(e));
   qst::clear_error();
+  return QST_OK;
+}
+
+qst_status qst_batch_shape(const qst_batch_plan* p, int* threads, int* register_round_passes) {
+  if (!p) return qst::fail_status(QST_ERR_INVALID_ARG, "plan is NULL");
+  if (threads) *threads = p->threads;
+  if (register_round_passes) *register_round_passes = p->fast_forms ? 1 : 0;
   return QST_OK;
 }
 

@@ -156,3 +156,48 @@ def test_batch_small_n_and_general_povm():
         assert abs(nll[i, 0] - L) <= 1e-12 * abs(L)
         assert rel_fro(grads[i], gr) <= 1e-12
     plan.close()
+
+
+@pytest.mark.parametrize("prec,threads,rr", [("f32", 512, 1), ("f32", 512, 0), ("f32", 256, 1), ("f32", 256, 0),
+                                             ("f64", 256, 1), ("f64", 256, 0)])
+def test_batch_every_tuned_shape(batch1024, tmp_path, prec, threads, rr):
+    """Every launch shape the autotuner may choose (workgroup size, register-
+    round or generic POVM passes for N = 7, 8), forced through the tuning
+    cache: the plan reports it and its results match the oracle."""
+    ns, Ts, fs, ref = batch1024
+    sel = list(range(0, 1024, 16)) + [i for i in range(1024) if ns[i] >= 7][:32]
+    ns_s = [ns[i] for i in sel]
+    Tq, fq = quantize([Ts[i] for i in sel], [fs[i] for i in sel], prec)
+    cache = tmp_path / "tune.txt"
+    plan = qst.BatchPlan(ns_s, prec, tune_cache=str(cache))
+    T_all, f_all = plan.pack(Tq, fq, DEV)
+    plan.run(T_all, f_all, use_graph=False)
+    torch.cuda.synchronize()
+    tuned = plan.info()
+    plan.close()
+    fields = cache.read_text().split()
+    assert len(fields) == 6 and int(fields[4]) == tuned["threads"] and int(fields[5]) == int(tuned["register_round_passes"])
+    key, grid = fields[0], int(fields[1])
+    with open(cache, "a") as fh:
+        fh.write(f"{key} {grid} 1 0.0 {threads} {rr}\n")
+    plan = qst.BatchPlan(ns_s, prec, tune_cache=str(cache))
+    info = plan.info()
+    say(f"{prec}: tuned {tuned}; forced {info}")
+    assert info["threads"] == threads and info["register_round_passes"] == bool(rr)
+    T_all, f_all = plan.pack(Tq, fq, DEV)
+    nll, grad, bad = plan.run(T_all, f_all, use_graph=False)
+    torch.cuda.synchronize()
+    nll = nll.cpu().numpy()
+    grads = unpack(plan, grad)
+    assert (bad.cpu().numpy() == 0).all()
+    worst_L = worst_g = 0.0
+    for k, i in enumerate(sel):
+        if prec == "f64":
+            L_ref, g_ref = ref[i]
+        else:
+            L_ref, g_ref = oracle_one(Tq[k].astype(np.complex128), fq[k].astype(np.float64))
+        worst_L = max(worst_L, abs(nll[k, 0] - L_ref) / abs(L_ref))
+        worst_g = max(worst_g, rel_fro(grads[k], g_ref))
+    say(f"  worst relative L error {worst_L:.3e}, worst gradient error {worst_g:.3e}")
+    assert worst_L <= TOL[prec] and worst_g <= TOL[prec]
+    plan.close()
