@@ -211,11 +211,8 @@ def test_abs_map_n11_against_oracle(prec):
     el = float(np.abs(np.sort(lam.cpu().numpy()) - np.sort(lw)).max() / np.abs(lw).max())
     say(f"N=11 {prec} P={P}: sweeps {sweeps}, {dt:.2f} s, A rel err {e:.2e}, "
         f"dL/dT rel err {eg:.2e}, spectrum {el:.2e}")
-    # FP64: both sides' eigendecompositions (the library's, LAPACK's in the
-    # oracle) have backward errors that grow about linearly with d,
-    # and the adjoint is first order in them; the 1e-12 met up to d = 1024
-    # scales to 2e-12 at d = 2048
-    tol = 2e-12 if prec == "f64" else TOL[prec]
+    # FP64: the direct solver's errors at d = 2048 are about 1e-14
+    tol = TOL[prec]
     assert e <= tol and eg <= tol
     assert el <= (1e-13 if prec == "f64" else 1e-9)
 
