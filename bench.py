@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16", "f32x6"])
     ap.add_argument("--n", type=int, default=11)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precision paths")
@@ -722,16 +722,29 @@ def main():
             # multiply-add (4 d^2 (d+1) and 8 d^3), is reported beside it.
             herk = dom.startswith("herk")
             counted = 4.0 * d * d * (d + 1) if herk else 8.0 * d ** 3
+            x6 = dom.endswith("x6")
             bf16 = dom.endswith(("bf16", "bf16x3"))
-            peak_key = "bf16" if bf16 else ("f64" if dom.endswith("f64") else "f32")
-            executed = counted * (0.75 if not bf16 else (1.0 if herk else 3.0))
+            peak_key = "bf16" if (bf16 or x6) else ("f64" if dom.endswith("f64") else "f32")
+            if x6:
+                # three real products per complex product, six bf16 products
+                # per real product; T T^dagger on 128 x 128 lower tiles (the
+                # diagonal tiles in full): 3 x 6 x 2 x 128^2 x d per tile
+                t = d // 128
+                executed = (36.0 * 128 * 128 * d * (t * (t + 1) // 2)) if herk else 36.0 * d ** 3
+            else:
+                executed = counted * (0.75 if not bf16 else (1.0 if herk else 3.0))
             ach = executed / avg_s / 1e12
-            form = ("3 d^2(d+1)" if herk else "6 d^3") if not bf16 else ("4 d^2(d+1)" if herk else "24 d^3")
+            if x6:
+                form = "36 x 128^2 d per lower 128-tile" if herk else "36 d^3"
+            else:
+                form = ("3 d^2(d+1)" if herk else "6 d^3") if not bf16 else ("4 d^2(d+1)" if herk else "24 d^3")
             roofline = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[peak_key],
                         "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[peak_key], "traffic": traffic_of(dom),
                         "algorithmic_per_launch": f"{executed:.4g} flop ({form}, d={d}: "
-                                                  + ("3M complex product, 3 real products" if not bf16 else
-                                                     "4 real products per complex product") + ")",
+                                                  + ("3M complex product, 3 real products, 6 bf16 products "
+                                                     "each" if x6 else "3M complex product, 3 real products"
+                                                     if not bf16 else "4 real products per complex product")
+                                                  + ")",
                         "avg_launch_us": avg_s * 1e6, "launches": kdom[dom][0],
                         "counted_per_launch": f"{counted:.4g} flop ({'4d^2(d+1)' if herk else '8d^3'}, "
                                               "8 flop per complex multiply-add)",
@@ -788,7 +801,7 @@ def main():
 
         cpu, ref = cpu_baseline(T_np, f_np, args.prec)
         refs = {args.prec: ref}
-        storage = {"f64": "f64", "f32": "f32", "bf16": "f32"}  # the BF16 path takes complex64 T
+        storage = {"f64": "f64", "f32": "f32", "bf16": "f32", "f32x6": "f32"}  # complex64 T except FP64
         for prec in path_res:
             if storage[prec] == storage[args.prec]:
                 refs[prec] = ref

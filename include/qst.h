@@ -73,7 +73,16 @@ typedef enum {
    * 2e-3 relative.  tau is the FP64 sum over the same represented T.  The
    * gradient product G' T always uses split bfloat16 operands (hi + lo,
    * three products). */
-  QST_BF16GEMM = 2
+  QST_BF16GEMM = 2,
+  /* complex64 storage, FP32 POVM passes, tau and the log-likelihood sum in
+   * FP64, as QST_F32; for d >= 128 the two complex products run on the
+   * BF16 MFMA with every FP32 operand split exactly into three bfloat16
+   * parts (x = h + m + l) and six partial products per real product (hh,
+   * hm, mh, hl, lh, mm: what is dropped is below 2^-26 of |a||b|), FP32
+   * accumulation.  Results agree with QST_F32 to the order of FP32
+   * rounding; the products run about twice as fast.  Below d = 128 the
+   * products are those of QST_F32.  The batched form runs it as QST_F32. */
+  QST_F32X6 = 3
 } qst_prec;
 
 typedef enum {

@@ -14,7 +14,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (QST_BF16GEMM, QST_F32, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MAP, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
+from ._lib import (QST_BF16GEMM, QST_F32, QST_F32X6, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MAP, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
                    QST_FIDELITY_MAX_RANK, QST_OP_FIDELITY, QST_OP_FNN, QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS,
                    QST_OP_STATE_MAP, QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER, QstError, workspace_bytes)
 
@@ -25,10 +25,10 @@ __all__ = [
     "abs_map_backward", "abs_map_async", "AbsMapFn", "AbsProjection", "fidelity_lowrank", "fidelity_general",
     "fidelity_general_async",
     "fidelity_classical", "fnn_forward", "fnn_backward", "FnnFn", "MappingNetwork", "Rprop",
-    "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_MAX_QUBITS",
+    "workspace_bytes", "QstError", "QST_F64", "QST_F32", "QST_BF16GEMM", "QST_F32X6", "QST_MAX_QUBITS",
 ]
 
-PRECISIONS = {"f64": QST_F64, "f32": QST_F32, "bf16": QST_BF16GEMM}
+PRECISIONS = {"f64": QST_F64, "f32": QST_F32, "bf16": QST_BF16GEMM, "f32x6": QST_F32X6}
 _NAMES = {v: k for k, v in PRECISIONS.items()}
 
 

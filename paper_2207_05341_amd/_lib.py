@@ -11,7 +11,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqst.so")
 
 QST_OK, QST_ERR_INVALID_ARG, QST_ERR_UNSUPPORTED, QST_ERR_WORKSPACE, QST_ERR_HIP = range(5)
-QST_F64, QST_F32, QST_BF16GEMM = 0, 1, 2
+QST_F64, QST_F32, QST_BF16GEMM, QST_F32X6 = 0, 1, 2, 3
 QST_OP_STATE_MAP, QST_OP_POVM_PROBS, QST_OP_NLL, QST_OP_NLL_BACKWARD = 0, 1, 2, 3
 QST_OP_LIKELIHOOD, QST_OP_GRAD_PRODUCT, QST_OP_FIDELITY, QST_OP_FNN, QST_OP_ABS_MAP = 4, 5, 6, 7, 8
 QST_FIDELITY_MAX_RANK = 32

@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqst.so")
 
-SOURCES = ["qst_plan.cpp", "k_reduce.hip", "k_povm.hip", "k_povm_fast.hip", "k_gemm.hip", "qst_profile.hip", "k_batch.hip", "k_premap.hip", "k_fidelity.hip", "k_fnn.hip", "k_absmap.hip", "k_eigh.hip", "k_povm_general.hip", "qst_api.hip"]
+SOURCES = ["qst_plan.cpp", "k_reduce.hip", "k_povm.hip", "k_povm_fast.hip", "k_gemm.hip", "qst_profile.hip", "k_batch.hip", "k_premap.hip", "k_fidelity.hip", "k_fnn.hip", "k_absmap.hip", "k_eigh.hip", "k_povm_general.hip", "k_xgemm.hip", "qst_api.hip"]
 ARCH = "gfx950"
 
 

@@ -712,7 +712,7 @@ qst_status qst_batch_plan_create(const int* n_qubits, int count, qst_prec prec, 
   }
   qst_batch_plan* p = new qst_batch_plan();
   p->count = count;
-  p->prec = prec;
+  p->prec = qst::storage_prec(prec);  // instances have d <= 256: QST_F32X6 runs as QST_F32
   p->tetra = povm_host == nullptr;
   p->n.assign(n_qubits, n_qubits + count);
   p->t_off.assign(count + 1, 0);

@@ -376,6 +376,10 @@ hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int
                        const double* tau_partials, double* tau_dev, void* sk_partial, hipStream_t s,
                        const Pass0Out* x0, const void* planes) {
   const int d = 1 << n;
+  if (prec == QST_F32X6) {
+    if (use_x6(prec, n)) return launch_x6_herk(T, ldt, rho, ldr, n, tau_partials, tau_dev, const_cast<void*>(planes), sk_partial, s, x0);
+    prec = QST_F32;
+  }
   if (x0 && (d < BM || x0->g < 4 || x0->g > 6 || !x0->tetra)) return hipErrorInvalidValue;
   ProfScope prof(d < BM ? "herk_small" : (prec == QST_F64 ? "herk_f64" : prec == QST_F32 ? "herk_f32" : "herk_bf16"), s);
   if (d < BM) {
@@ -599,6 +603,10 @@ hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T,
                        int64_t ldo, int n, const double* tau_dev, const double* upstream_dev,
                        void* sk_partial, hipStream_t s, void* planes) {
   const int d = 1 << n;
+  if (prec == QST_F32X6) {
+    if (use_x6(prec, n)) return launch_x6_hemm(G, ldg, T, ldt, out, ldo, n, tau_dev, upstream_dev, planes, s);
+    prec = QST_F32;
+  }
   ProfScope prof(d < BM ? "hemm_small" : (prec == QST_F64 ? "hemm_f64" : prec == QST_F32 ? "hemm_f32" : "hemm_bf16x3"), s);
   if (d < BM) {
     if (prec == QST_F64)

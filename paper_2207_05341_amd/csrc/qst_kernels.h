@@ -129,6 +129,15 @@ hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T,
                        void* out, int64_t ldo, int n, const double* tau_dev,
                        const double* upstream_dev, void* sk_partial, hipStream_t s, void* planes = nullptr);
 
+// QST_F32X6 products (k_xgemm.hip), d >= kX6Tile.  T T^dagger: planes
+// x6_herk_plane_bytes(n) and partials x6_partial_bytes(n) of workspace; as
+// launch_herk otherwise.  G' T: planes x6_hemm_plane_bytes(n); as
+// launch_hemm otherwise.
+hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, int n, const double* tau_partials,
+                          double* tau_dev, void* planes, void* partials, hipStream_t s, const Pass0Out* x0);
+hipError_t launch_x6_hemm(const void* G, int64_t ldg, const void* T, int64_t ldt, void* out, int64_t ldo, int n,
+                          const double* tau_dev, const double* upstream_dev, void* planes, hipStream_t s);
+
 // Forward (adjoint=false): mat = rho (lower triangle read) -> pvec.
 // Adjoint (adjoint=true): g' = F - f/p from (pvec, fvec, F_dev) -> mat = G'
 // (written in full).  mode_matrix: W (forward) or V (adjoint) as 4 x 4

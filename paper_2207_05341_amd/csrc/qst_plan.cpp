@@ -178,21 +178,29 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
     off = align_up(off + bytes);
     return at;
   };
-  const bool sk = n >= kStreamKMinQubits;
-  const bool planes = prec == QST_BF16GEMM && d > size_t(kBf16SplitMaxDim);
-  const bool hemm_planes = prec == QST_BF16GEMM && d >= 1024;
+  const bool x6 = use_x6(prec, n);
+  // stream-K partial tiles: the QST_F32X6 T T^dagger always, the other
+  // products from kStreamKMinQubits
+  const bool sk = x6 || n >= kStreamKMinQubits;
+  const size_t sk_bytes = x6 ? x6_partial_bytes(n) : stream_k_partial_bytes(prec);
+  const bool planes = (prec == QST_BF16GEMM && d > size_t(kBf16SplitMaxDim)) || x6;
+  const bool hemm_planes = (prec == QST_BF16GEMM && d >= 1024) || x6;
+  // bf16 planes of d x d: the BF16 path's (2 for T T^dagger, 8 for G' T)
+  // or the QST_F32X6 split planes (12 and 18)
+  const size_t herk_planes = x6 ? 12 : 2, hemm_plane_count = x6 ? 18 : 8;
   auto take_planes = [&](size_t count) {  // count planes of d x d bf16
     w.planes = take(count * D * sizeof(uint16_t));
     w.has_planes = true;
   };
+  auto take_sk = [&]() {
+    w.sk = take(sk_bytes);
+    w.has_sk = true;
+  };
   switch (op) {
     case QST_OP_STATE_MAP:
       w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
-      if (planes) take_planes(2);
-      if (sk) {
-        w.sk = take(stream_k_partial_bytes(prec));
-        w.has_sk = true;
-      }
+      if (planes) take_planes(herk_planes);
+      if (sk) take_sk();
       break;
     case QST_OP_NLL:
       w.partials = take(size_t(kReduceBlocks) * 4 * sizeof(double));
@@ -212,13 +220,10 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
         w.p = take(D * rb);
       }
       if (hemm_planes)
-        take_planes(8);  // also holds T's two planes of the recomputed state map
+        take_planes(hemm_plane_count);  // also holds T's planes of the recomputed state map
       else if (recompute && planes)
-        take_planes(2);
-      if (sk) {
-        w.sk = take(stream_k_partial_bytes(prec));
-        w.has_sk = true;
-      }
+        take_planes(herk_planes);
+      if (sk && (recompute || !x6)) take_sk();
       break;
     case QST_OP_LIKELIHOOD: {
       const bool fused = fused_likelihood(pl, prec);
@@ -228,19 +233,13 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
       if (pl.passes >= 2) w.inter0 = take(D * cb);
       if (pl.passes >= 3) w.inter1 = take(D * cb);
       if (!fused) w.p = take(D * rb);
-      if (planes) take_planes(2);
-      if (sk) {
-        w.sk = take(stream_k_partial_bytes(prec));
-        w.has_sk = true;
-      }
+      if (planes) take_planes(herk_planes);
+      if (sk) take_sk();
       break;
     }
     case QST_OP_GRAD_PRODUCT:
-      if (hemm_planes) take_planes(8);
-      if (sk) {
-        w.sk = take(stream_k_partial_bytes(prec));
-        w.has_sk = true;
-      }
+      if (hemm_planes) take_planes(hemm_plane_count);
+      if (sk && !x6) take_sk();
       break;
     case QST_OP_FIDELITY:
       off = fidelity_layout(n).total;
@@ -494,13 +493,20 @@ GeneralLayout general_layout(int n, qst_prec prec, int K, bool with_state) {
     w.h = take(D * rb);
     w.p = take((DK < 0 ? 0 : size_t(DK)) * rb);
     w.rho = take(D * cb);
-    if (prec == QST_BF16GEMM && d > size_t(kBf16SplitMaxDim)) {
-      w.planes = take(2 * D * sizeof(uint16_t));
+    if (use_x6(prec, n)) {
+      w.planes = take(x6_herk_plane_bytes(n));
       w.has_planes = true;
-    }
-    if (n >= kStreamKMinQubits) {
-      w.sk = take(stream_k_partial_bytes(prec));
+      w.sk = take(x6_partial_bytes(n));
       w.has_sk = true;
+    } else {
+      if (prec == QST_BF16GEMM && d > size_t(kBf16SplitMaxDim)) {
+        w.planes = take(2 * D * sizeof(uint16_t));
+        w.has_planes = true;
+      }
+      if (n >= kStreamKMinQubits) {
+        w.sk = take(stream_k_partial_bytes(prec));
+        w.has_sk = true;
+      }
     }
   }
   w.total = off;

@@ -14,7 +14,76 @@ namespace qst {
 // Elements of one complex scalar in bytes for a precision's storage type.
 inline size_t complex_bytes(qst_prec p) { return p == QST_F64 ? 16 : 8; }
 inline size_t real_bytes(qst_prec p) { return p == QST_F64 ? 8 : 4; }
-inline bool prec_valid(int p) { return p == QST_F64 || p == QST_F32 || p == QST_BF16GEMM; }
+inline bool prec_valid(int p) { return p == QST_F64 || p == QST_F32 || p == QST_BF16GEMM || p == QST_F32X6; }
+// Storage and pass arithmetic of a precision (QST_F32X6 differs from
+// QST_F32 in its complex products only).
+inline qst_prec storage_prec(qst_prec p) { return p == QST_F32X6 ? QST_F32 : p; }
+
+// QST_F32X6 products (k_xgemm.hip): 128 x 128 output tiles; T T^dagger runs
+// stream-K on at most kX6MaxGrid workgroups, each leaving at most two
+// partial tiles (re, im FP32).  Operand planes: T T^dagger reads the rows of
+// T in four groups (re, im, re + im, re - im) of three bf16 splits (24 bytes
+// per element); G' T reads G' and T^T in three groups (18 bytes each).
+constexpr int kX6Tile = 128;
+constexpr int kX6MaxGrid = 256;
+inline bool use_x6(qst_prec p, int n) { return p == QST_F32X6 && (int64_t(1) << n) >= kX6Tile; }
+// Schedule of the QST_F32X6 T T^dagger (lower 128 x 128 tiles) on P
+// workgroups, one per CU.  Each tile's K range is cut into sk equal parts
+// ("units"; sk the smallest power of two with tiles x sk >= P, each unit at
+// least 8 K panels).  Workgroup w takes units w, w + P, ... for `rounds`
+// whole rounds -- every workgroup of a round covers the same K range at the
+// same time, so the operand panels it streams are shared in L2 -- and the
+// `left` units that remain are shared out as contiguous slices of their
+// (unit, panel) sequence (stream-K), at most two slices per workgroup.  A
+// tile finished by one workgroup (sk = 1, a whole round unit) is written
+// directly; every other contribution is a partial tile that the fix-up adds
+// in K order.
+struct X6HerkSched {
+  int64_t P = 1;  // workgroups of the rounds (one per CU)
+  int64_t Q = 1;  // workgroups taking slices
+  int64_t ntiles = 0, sk = 1, kh = 0, units = 0, rounds = 0, main = 0, left = 0, left_iters = 0;
+  int64_t slots = 0;  // partial tiles: one per round unit when sk > 1, two per slice worker
+};
+inline X6HerkSched x6_herk_sched(int n, int cus) {
+  X6HerkSched s;
+  const int64_t d = int64_t(1) << n, t = d / kX6Tile, kiters = d / 16;
+  s.P = cus < 1 ? 1 : (cus > kX6MaxGrid ? kX6MaxGrid : cus);
+  s.ntiles = t * (t + 1) / 2;
+  while (s.ntiles * s.sk < s.P && kiters / (2 * s.sk) >= 8) s.sk *= 2;
+  s.kh = kiters / s.sk;
+  // rounds only with units of at least 32 panels; otherwise the units are
+  // the tiles and all of them are shared out in slices (plain stream-K: a
+  // slice then holds whole tiles and at most two partial ones)
+  if (s.kh < 32) {
+    s.sk = 1;
+    s.kh = kiters;
+  }
+  s.units = s.ntiles * s.sk;
+  s.rounds = s.units / s.P;
+  s.main = s.rounds * s.P;
+  s.left = s.units - s.main;
+  s.left_iters = s.left * s.kh;
+  // slices of at least 4 panels after rounds (all workgroups share the
+  // tail), 16 without them
+  const int64_t min_slice = s.rounds > 0 ? 4 : 16;
+  s.Q = s.left_iters / min_slice;
+  if (s.Q > s.P) s.Q = s.P;
+  if (s.Q < 1) s.Q = 1;
+  if (s.left_iters == 0) s.Q = 0;
+  s.slots = (s.sk > 1 ? s.main : 0) + 2 * s.Q;
+  return s;
+}
+inline size_t x6_partial_bytes(int n) {
+  // the largest schedule over devices with up to kX6MaxGrid compute units
+  size_t most = 0;
+  for (int cus = 1; cus <= kX6MaxGrid; ++cus) {
+    const size_t slots = size_t(x6_herk_sched(n, cus).slots);
+    if (slots > most) most = slots;
+  }
+  return most * 2 * kX6Tile * kX6Tile * sizeof(float);
+}
+inline size_t x6_herk_plane_bytes(int n) { return (size_t(1) << (2 * n)) * 24; }
+inline size_t x6_hemm_plane_bytes(int n) { return (size_t(1) << (2 * n)) * 36; }
 
 // The product-POVM map is applied in passes.  Pass j contracts a group of
 // g_j consecutive qubits inside on-chip memory; groups run from the least

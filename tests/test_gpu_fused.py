@@ -20,7 +20,7 @@ qst = pytest.importorskip("paper_2207_05341_amd")
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3, "f32x6": 1e-5}
 DEV = "cuda:0"
 
 
@@ -89,7 +89,7 @@ def check(T, f, prec, povm=None, upstream=None):
     return L, grad
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 @pytest.mark.parametrize("n", [1, 4, 6, 7, 8, 9, 10])
 def test_fused_against_oracle(n, prec):
     """N <= 6: one POVM pass (the library runs the separate kernels); N >= 7:
@@ -99,7 +99,7 @@ def test_fused_against_oracle(n, prec):
     check(T, f, prec)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 @pytest.mark.parametrize("n", [7, 9])
 def test_fused_equals_separate_calls(n, prec):
     say(f"fused vs separate calls n={n} prec={prec}")
@@ -109,7 +109,7 @@ def test_fused_equals_separate_calls(n, prec):
     # p agrees to rounding (the two kernels may contract products into FMAs
     # differently) and L is summed over a different block partition
     assert abs(L - L2) <= (1e-13 if prec == "f64" else 1e-7) * abs(L2)
-    assert rel_fro(grad, grad2) <= {"f64": 1e-12, "f32": 1e-6, "bf16": 1e-5}[prec]
+    assert rel_fro(grad, grad2) <= {"f64": 1e-12, "f32": 1e-6, "bf16": 1e-5, "f32x6": 1e-6}[prec]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -167,7 +167,7 @@ def test_fused_edge_cases(prec):
     assert math.isnan(L) and bad[1] == 1
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 def test_fused_determinism(prec):
     say(f"fused determinism prec={prec}")
     T, f, _ = depolarised_case(10, 3500, 0.05, 10 ** 6)
@@ -203,7 +203,7 @@ def n11(request):
     return T, f
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 def test_fused_n11(n11, prec):
     """Config 3, fused call and separate-call route, each against the oracle."""
     say(f"fused N=11 {prec}")

@@ -24,7 +24,7 @@ qst = pytest.importorskip("paper_2207_05341_amd")
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3, "f32x6": 1e-5}
 
 
 def say(*a):
@@ -79,7 +79,7 @@ def run_general(T, fs, settings, prec, upstream=None):
     return float(out[0].item()), float(out[1].item()), G.cpu().numpy(), grad.cpu().numpy(), bad.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 @pytest.mark.parametrize("n,K,nset", [(1, 2, 1), (3, 3, 3), (4, 6, 2), (6, 2, 3), (7, 3, 3), (9, 2, 3), (10, 3, 2)])
 def test_likelihood_general_against_oracle(n, K, nset, prec):
     """L summed over settings, G' and dL/dT against the oracle's

@@ -31,7 +31,7 @@ qst = pytest.importorskip("paper_2207_05341_amd")
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3, "f32x6": 1e-5}
 DEV = "cuda:0"
 RANK = 8
 
@@ -82,7 +82,7 @@ def oracle_full(T, f):
     return rho, tau, p, L, G, (2.0 / tau) * (G @ T)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 def test_n12_against_full_oracle(n12, prec):
     T, f, cache = n12
     key = "f64" if prec == "f64" else "f32"
@@ -143,7 +143,7 @@ def fro(a):
     return float(torch.linalg.vector_norm(a.to(torch.complex128)).item())
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 def test_n13_sampled_outcomes_and_invariants(n13, prec):
     T, f, ks, p_w, tau_w = n13
     say(f"N=13 {prec}: separate-call path, {len(ks)} sampled outcomes")
@@ -161,7 +161,7 @@ def test_n13_sampled_outcomes_and_invariants(n13, prec):
     say(f"  sampled p rel {e_p:.3e}  tau rel {e_tau:.3e}")
     assert e_p <= TOL[prec]
     # BF16: tau is the trace of the split operands the products use
-    assert e_tau <= {"f64": 1e-12, "f32": 1e-6, "bf16": TOL["bf16"]}[prec]
+    assert e_tau <= {"f64": 1e-12, "f32": 1e-6, "bf16": TOL["bf16"], "f32x6": 1e-6}[prec]
     assert host(bad).tolist() == [0, 0]
 
     say(f"N=13 {prec}: qst_likelihood + qst_grad_product")

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI, via the thin binding) against
 the FP64 CPU oracle on identical seeded inputs.
 
-Tolerances (relative): FP64 1e-12, FP32 1e-5, BF16 T T^dagger 2e-3.
+Tolerances (relative): FP64 1e-12, FP32 1e-5, BF16 T T^dagger 2e-3, FP32 with
+split-bf16 products (f32x6) 1e-5.
   p:    max|dp| / max|p|        L: |dL| / |L|       grad: ||dgrad||_F / ||grad||_F
   rho:  max|drho| / max|rho|
 For FP32 / BF16 the oracle consumes the same complex64 / float32 values,
@@ -21,7 +22,7 @@ qst = pytest.importorskip("paper_2207_05341_amd")
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3, "f32x6": 1e-5}
 DEV = "cuda:0"
 
 
@@ -86,8 +87,8 @@ def bf16_split(x):
 # several passes, single-tile and small-matrix paths)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("n", [1, 3, 5, 6, 7, 9, 10])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
+@pytest.mark.parametrize("n", [1, 3, 5, 6, 7, 8, 9, 10])
 def test_state_map(n, prec):
     say(f"state_map n={n} prec={prec}")
     g = S.rng(2000 + n)
@@ -225,8 +226,8 @@ def test_config2_n8_f32(r):
     check_chain(T, f, "f32")
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("n", [2, 5, 6, 7, 9, 10])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
+@pytest.mark.parametrize("n", [2, 5, 6, 7, 8, 9, 10])
 def test_chain_sizes(n, prec):
     say(f"chain n={n} prec={prec}")
     T, f, _ = depolarised_case(n, 2400 + n, 0.1, 20 * 4 ** n)
@@ -246,7 +247,7 @@ def test_general_povm(n, prec):
     check_chain(T, f, prec, povm=M)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 def test_recompute_equals_stored_and_determinism(prec):
     say(f"recompute / determinism prec={prec}")
     T, f, _ = depolarised_case(9, 2600, 0.05, 10 ** 6)
@@ -329,7 +330,7 @@ def n11(request):
     return T, f, oracle_chain(T, f)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 def test_config3_n11(n11, prec):
     say(f"config 3: N=11 {prec}")
     T, f, w = n11

@@ -15,7 +15,7 @@ qst = pytest.importorskip("paper_2207_05341_amd")
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3, "f32x6": 1e-5}
 
 
 def say(*a):
@@ -26,7 +26,7 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
 def test_noalloc_equals_workspace_call(prec):
     ct = np.complex128 if prec == "f64" else np.complex64
     rt = np.float64 if prec == "f64" else np.float32
