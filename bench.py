@@ -7,8 +7,12 @@ in HBM before timing starts:
     cotangent, adjoint POVM map -> G'; the last POVM pass, the NLL terms, the
     cotangent and the first adjoint pass fused, p never stored)
     ->  qst_grad_product (2/tau G' T).
-The same step as four separate calls with p stored (qst_state_map,
-qst_povm_probs, qst_nll, qst_nll_backward) is reported alongside.
+The headline path is QST_F32X6 (FP32 storage and FP32-level accuracy; the
+two complex products as six split-bf16 products per real product on the BF16
+matrix cores); the FP64, FP32 (FP32 MFMA products) and BF16 paths and the
+same step as four separate calls with p stored (qst_state_map,
+qst_povm_probs, qst_nll, qst_nll_backward) are reported alongside, each with
+its error against the FP64 oracle.
 
 Workload (N = 11): T 2048 x 2048 complex Ginibre (seed 6); frequencies from
 10^7 multinomial shots of a Porter-Thomas stand-in distribution of a
@@ -33,6 +37,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "likelihood fwd+bwd evals/sec at N=11 on 1 GPU; % HBM/MFMA peak; max|Δp| vs FP64"
+
+PREC_NOTE = {
+    "f64": "complex128 storage, FP64 MFMA products, FP64 POVM passes and NLL",
+    "f32": "complex64 storage, FP32 MFMA products (3M form), FP32 POVM passes, tau and NLL sum in FP64",
+    "bf16": "complex64 storage, T T^dagger on bf16-rounded T (BF16 MFMA, FP32 accumulate), G' T with split "
+            "bf16 operands, FP32 POVM passes, tau and NLL sum in FP64",
+    "f32x6": "complex64 storage; both complex products with every FP32 operand split exactly into three bf16 "
+             "parts, six partial products per real product (3M form) on the BF16 MFMA, FP32 accumulation "
+             "(FP32-accurate); FP32 POVM passes, tau and NLL sum in FP64",
+}
 
 # MI355X published peaks
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
@@ -73,7 +87,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16", "f32x6"])
+    ap.add_argument("--prec", default="f32x6", choices=["f64", "f32", "bf16", "f32x6"],
+                    help="precision path of the headline step (default f32x6: FP32 storage and accuracy, "
+                         "complex products as six split-bf16 products on the BF16 MFMA)")
     ap.add_argument("--n", type=int, default=11)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precision paths")
@@ -767,7 +783,7 @@ def main():
 
     paths, path_res = {}, {}
     if not args.no_variants:
-        for prec in ("f64", "f32", "bf16"):
+        for prec in ("f64", "f32", "bf16", "f32x6"):
             if prec == args.prec:
                 continue
             s2, k2, _, _, a2, path_res[prec] = measure(prec, max(10, args.steps // 2), 3)
@@ -838,7 +854,8 @@ def main():
         "config": {"workload": f"N={n} single state: T {d}x{d} complex Ginibre, {4 ** n} tetrahedral-POVM "
                                f"outcomes, f from 10^7 multinomial shots; forward+adjoint as qst_likelihood + "
                                f"qst_grad_product (p not stored)",
-                   "n_qubits": n, "precision": args.prec, "parallelism": "none (1 GPU)"},
+                   "n_qubits": n, "precision": args.prec, "precision_note": PREC_NOTE[args.prec],
+                   "parallelism": "none (1 GPU)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": acc_oracle,
