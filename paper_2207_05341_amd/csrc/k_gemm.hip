@@ -377,7 +377,7 @@ hipError_t launch_herk(qst_prec prec, const void* T, int64_t ldt, void* rho, int
                        const Pass0Out* x0, const void* planes) {
   const int d = 1 << n;
   if (prec == QST_F32X6) {
-    if (use_x6(prec, n)) return launch_x6_herk(T, ldt, rho, ldr, n, tau_partials, tau_dev, const_cast<void*>(planes), sk_partial, s, x0);
+    if (use_x6(prec, n)) return hipErrorInvalidValue;  // launch_x6_herk forms tau itself
     prec = QST_F32;
   }
   if (x0 && (d < BM || x0->g < 4 || x0->g > 6 || !x0->tetra)) return hipErrorInvalidValue;

@@ -268,7 +268,7 @@ hipError_t launch_tau(qst_prec prec, const void* T, int64_t ld, int n, double* p
                       double* tau_dev, hipStream_t s, const void* f, void* planes) {
   const int nb = kReduceBlocks;
   ProfScope prof("tau_reduce", s);
-  prec = storage_prec(prec);  // QST_F32X6 splits T inside its product launch
+  prec = storage_prec(prec);  // QST_F32X6 reaches here only below kX6Tile, where it runs as QST_F32
   const Cx<double>* T64 = static_cast<const Cx<double>*>(T);
   const Cx<float>* T32 = static_cast<const Cx<float>*>(T);
   const double* f64 = static_cast<const double*>(f);

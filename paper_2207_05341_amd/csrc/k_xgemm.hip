@@ -43,6 +43,7 @@
 // the tile's epilogue (rho, or the first POVM pass).  G' T has (d / 128)^2
 // tiles, one per workgroup, numbered so that each XCD runs 4 x 8 blocks of
 // tiles.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -59,6 +60,7 @@ namespace qst {
 namespace {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -131,6 +133,82 @@ __global__ __launch_bounds__(256) void x6_split_kernel(const Cx<float>* __restri
 #pragma unroll
     for (int e = 0; e < 8; ++e) g2[e] = re[e] - im[e];
     split3(g2, out[9 * XUNIT], out[10 * XUNIT], out[11 * XUNIT]);
+  }
+}
+
+// The planes of T as the row operand (x6_split_kernel<false, 4>) together
+// with the FP64 partial sums of tau = sum |T_ij|^2 and, with f, of
+// F = sum_k f_k: workgroup b of nb writes partials[b] (its unit blocks
+// b, b + nb, ..., four per pass, one per wave) and partials[nb + b] (f
+// over the contiguous range [b D / nb, (b + 1) D / nb), D = d^2), each
+// summed in a fixed order, so T is read once on the likelihood path.  The
+// first 16 values of f per thread are loaded before the unit blocks, so
+// that their loads are in flight together with those of T.
+template <bool WITH_F>
+__global__ __launch_bounds__(256) void x6_split_tau_kernel(const Cx<float>* __restrict__ X, int64_t ld, int d,
+                                                           u16x8* __restrict__ P, double* __restrict__ partials,
+                                                           const float* __restrict__ f) {
+  constexpr int NT = 256, NW = NT / 64, U = 16;
+  __shared__ double red[NW];
+  const int nb = gridDim.x;
+  const int64_t D = int64_t(d) * d;
+  const int64_t fbeg = D * blockIdx.x / nb, fend = D * (blockIdx.x + 1) / nb;
+  float fv[U];
+  if constexpr (WITH_F) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = fbeg + threadIdx.x + u * NT;
+      fv[u] = e < fend ? f[e] : 0.f;
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  const int nkb = d / 16;
+  const int64_t nblk = int64_t(d / 32) * nkb;
+  double acc = 0.0, accf = 0.0;
+  for (int64_t b0 = int64_t(blockIdx.x) * NW; b0 < nblk; b0 += int64_t(nb) * NW) {
+    const int64_t blk = b0 + (threadIdx.x >> 6);  // unit block (rb, kb)
+    if (blk >= nblk) continue;
+    const int64_t rb = blk / nkb, kb = blk % nkb;
+    const int64_t row = rb * 32 + (lane & 31);
+    const int64_t k0 = kb * 16 + 8 * (lane >> 5);
+    float re[8], im[8], g2[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const Cx<float> v = X[row * ld + k0 + e];
+      re[e] = v.re;
+      im[e] = v.im;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc += double(re[e]) * double(re[e]) + double(im[e]) * double(im[e]);
+    u16x8* out = P + blk * (4 * 3 * XUNIT) + lane;
+    split3(re, out[0 * XUNIT], out[1 * XUNIT], out[2 * XUNIT]);
+    split3(im, out[3 * XUNIT], out[4 * XUNIT], out[5 * XUNIT]);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) g2[e] = re[e] + im[e];
+    split3(g2, out[6 * XUNIT], out[7 * XUNIT], out[8 * XUNIT]);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) g2[e] = re[e] - im[e];
+    split3(g2, out[9 * XUNIT], out[10 * XUNIT], out[11 * XUNIT]);
+  }
+  if constexpr (WITH_F) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) accf += double(fv[u]);
+    // the rest of the range (N >= 12), U strided loads per thread at a time
+    for (int64_t e0 = fbeg + threadIdx.x + U * NT; e0 < fend; e0 += U * NT) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = e0 + u * NT;
+        fv[u] = e < fend ? f[e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) accf += double(fv[u]);
+    }
+  }
+  const double st = block_sum256(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = st;
+  if constexpr (WITH_F) {
+    const double sf = block_sum256(accf, red);
+    if (threadIdx.x == 0) partials[nb + blockIdx.x] = sf;
   }
 }
 
@@ -556,14 +634,17 @@ struct X6Contrib {
 // the product kernel) of the contributions to lower tile t in K order and
 // applies the epilogue to it (rho, or the first POVM pass); the upper
 // quadrant of a diagonal tile is the mirror of the lower one and skipped.
-// Thread th holds values th + 256 m, m < 32, of the quadrant's 8192-float
-// block (layout of x6_store_partial with w = q); loads of up to four
-// contributions are in flight before they are added, in order.
+// Tiles go in reverse order: the leftover units, whose tiles carry the most
+// contributions, belong to the last tiles, which thus start first.  Thread
+// th holds values 4 (th + 256 m) + c, m < 8, c < 4, of the quadrant's
+// 8192-float block (layout of x6_store_partial with w = q), loaded as
+// 16-byte vectors; the loads of up to four contributions are in flight
+// before they are added, in order.
 template <int X0G>
 __global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
   __shared__ __align__(16) Cx<float> L[64 * 64];
   const X6HerkSched& sc = a.sc;
-  const int64_t t = blockIdx.x >> 2;
+  const int64_t t = sc.ntiles - 1 - (blockIdx.x >> 2);
   const int q = blockIdx.x & 3, qr = q >> 1, qc = q & 1;
   int tr, tc;
   tri_decode(t, tr, tc);
@@ -571,9 +652,9 @@ __global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
   const int th = threadIdx.x;
   X6Contrib it(sc, t);
   if (it.finished()) return;
-  float acc[32], v[4][32];
+  f4v acc[8], v[4][8];
 #pragma unroll
-  for (int m = 0; m < 32; ++m) acc[m] = 0.f;
+  for (int m = 0; m < 8; ++m) acc[m] = f4v{0.f, 0.f, 0.f, 0.f};
   // four contributions in flight, then added in order
   while (true) {
     int64_t sl[4];
@@ -582,37 +663,39 @@ __global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (sl[k] >= 0) {
-        const float* src = x6_slot(a, sl[k]) + q * 8192;
+        const f4v* src = reinterpret_cast<const f4v*>(x6_slot(a, sl[k]) + q * 8192);
 #pragma unroll
-        for (int m = 0; m < 32; ++m) v[k][m] = src[th + 256 * m];
+        for (int m = 0; m < 8; ++m) v[k][m] = src[th + 256 * m];
       }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (sl[k] >= 0) {
 #pragma unroll
-        for (int m = 0; m < 32; ++m) acc[m] += v[k][m];
+        for (int m = 0; m < 8; ++m) acc[m] += v[k][m];
       }
     if (sl[3] < 0) break;
   }
   const double scale = 1.0 / x6_tau(a, false);
-  // value index e = th + 256 m = ((ij * 16 + v) * 2 + part) * 64 + lane
+  // value index e = 4 (th + 256 m) + c = ((ij * 16 + v) * 2 + part) * 64 + lane
   const float sc32 = float(scale);
-  const int lane = th & 63;
   if constexpr (X0G == 0) {
     Cx<float>* C = static_cast<Cx<float>*>(a.C);
     float* Cf = reinterpret_cast<float*>(C);
 #pragma unroll
-    for (int m = 0; m < 32; ++m) {
-      const int e = th + 256 * m;
-      const int part = (e >> 6) & 1, vv = (e >> 7) & 15, ij = e >> 11;
-      const int i = ij >> 1, j = ij & 1;
-      const int64_t r = int64_t(tr) * XT + qr * 64 + i * 32 + 8 * (vv >> 2) + 4 * (lane >> 5) + (vv & 3);
-      const int64_t c = int64_t(tc) * XT + qc * 64 + j * 32 + (lane & 31);
-      Cf[2 * (r * a.ldc + c) + part] = acc[m] * sc32;
-      // the mirror: every off-diagonal tile, and the lower-left quadrant of
-      // a diagonal tile (whose upper-right quadrant is not computed here)
-      if (tr != tc || qr != qc) Cf[2 * (c * a.ldc + r) + part] = part ? -acc[m] * sc32 : acc[m] * sc32;
-    }
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const int e = 4 * (th + 256 * m) + c4;
+        const int lane = e & 63, part = (e >> 6) & 1, vv = (e >> 7) & 15, ij = e >> 11;
+        const int i = ij >> 1, j = ij & 1;
+        const int64_t r = int64_t(tr) * XT + qr * 64 + i * 32 + 8 * (vv >> 2) + 4 * (lane >> 5) + (vv & 3);
+        const int64_t c = int64_t(tc) * XT + qc * 64 + j * 32 + (lane & 31);
+        const float x = acc[m][c4] * sc32;
+        Cf[2 * (r * a.ldc + c) + part] = x;
+        // the mirror: every off-diagonal tile, and the lower-left quadrant
+        // of a diagonal tile (whose upper-right quadrant is not computed here)
+        if (tr != tc || qr != qc) Cf[2 * (c * a.ldc + r) + part] = part ? -x : x;
+      }
   } else {
     constexpr int G = X0G;
     constexpr int S = 64 >> G;
@@ -620,13 +703,15 @@ __global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
     constexpr int M = (1 << G) - 1;
     float* Lf = reinterpret_cast<float*>(L);
 #pragma unroll
-    for (int m = 0; m < 32; ++m) {
-      const int e = th + 256 * m;
-      const int part = (e >> 6) & 1, vv = (e >> 7) & 15, ij = e >> 11;
-      const int i = ij >> 1, j = ij & 1;
-      const int r = i * 32 + 8 * (vv >> 2) + 4 * (lane >> 5) + (vv & 3), c = j * 32 + (lane & 31);
-      Lf[2 * (((r >> G) * S + (c >> G)) * TG + swz<G>(r & M, c & M)) + part] = acc[m] * sc32;
-    }
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const int e = 4 * (th + 256 * m) + c4;
+        const int lane = e & 63, part = (e >> 6) & 1, vv = (e >> 7) & 15, ij = e >> 11;
+        const int i = ij >> 1, j = ij & 1;
+        const int r = i * 32 + 8 * (vv >> 2) + 4 * (lane >> 5) + (vv & 3), c = j * 32 + (lane & 31);
+        Lf[2 * (((r >> G) * S + (c >> G)) * TG + swz<G>(r & M, c & M)) + part] = acc[m][c4] * sc32;
+      }
     __syncthreads();
     gemm::GemmArgs g{};
     g.x0 = a.x0;
@@ -678,17 +763,24 @@ hipError_t x6_run_herk(XArgs a, int n, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, int n, const double* tau_partials,
-                          double* tau_dev, void* planes, void* partials, hipStream_t s, const Pass0Out* x0) {
+hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, int n, double* tau_partials,
+                          const void* f, double* tau_dev, void* planes, void* partials, hipStream_t s,
+                          const Pass0Out* x0) {
   const int d = 1 << n;
-  if (d < kX6Tile) return hipErrorInvalidValue;
+  if (d < kX6Tile || !tau_partials) return hipErrorInvalidValue;
   if (x0 && (x0->g < 4 || x0->g > 6 || !x0->tetra)) return hipErrorInvalidValue;
-  ProfScope prof("herk_x6", s);
-  const int64_t units = int64_t(d / 32) * (d / 16);
   u16x8* P = static_cast<u16x8*>(planes);
-  x6_split_kernel<false, 4><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(T), ldt, d, P);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  {
+    ProfScope prof("x6_split_t", s);
+    const Cx<float>* Tf = static_cast<const Cx<float>*>(T);
+    if (f)
+      x6_split_tau_kernel<true><<<kReduceBlocks, 256, 0, s>>>(Tf, ldt, d, P, tau_partials, static_cast<const float*>(f));
+    else
+      x6_split_tau_kernel<false><<<kReduceBlocks, 256, 0, s>>>(Tf, ldt, d, P, tau_partials, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  ProfScope prof("herk_x6", s);
   XArgs a{};
   a.A = P;
   a.B = P;
@@ -701,7 +793,7 @@ hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, in
   a.d = d;
   a.tau = tau_dev;
   a.tau_part = tau_partials;
-  a.tau_out = tau_partials ? tau_dev : nullptr;
+  a.tau_out = tau_dev;
   a.part = static_cast<float*>(partials);
   a.ntiles = (d / XT) * (d / XT + 1) / 2;
   a.kIters = d / 16;
@@ -718,15 +810,17 @@ hipError_t launch_x6_hemm(const void* G, int64_t ldg, const void* T, int64_t ldt
                           const double* tau_dev, const double* upstream_dev, void* planes, hipStream_t s) {
   const int d = 1 << n;
   if (d < kX6Tile) return hipErrorInvalidValue;
-  ProfScope prof("hemm_x6", s);
   const int64_t units = int64_t(d / 32) * (d / 16);
   u16x8* PG = static_cast<u16x8*>(planes);
   u16x8* PT = PG + units * 9 * XUNIT;
-  x6_split_kernel<false, 3><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(G), ldg, d, PG);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  x6_split_kernel<true, 3><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(T), ldt, d, PT);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipError_t e;
+  {
+    ProfScope prof("x6_split_gt", s);
+    x6_split_kernel<false, 3><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(G), ldg, d, PG);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    x6_split_kernel<true, 3><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(T), ldt, d, PT);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if ((e = x6_allow_lds(x6_hemm_kernel)) != hipSuccess) return e;
   XArgs a{};
   a.A = PG;
@@ -742,7 +836,8 @@ hipError_t launch_x6_hemm(const void* G, int64_t ldg, const void* T, int64_t ldt
   a.up = upstream_dev;
   a.kIters = d / 16;
   const int ts = d / XT;
-  x6_hemm_kernel<<<unsigned(ts * ts), 256, XLDS, s>>>(a);
+  ProfScope prof("hemm_x6", s, true);
+  hipExtLaunchKernelGGL(x6_hemm_kernel, dim3(unsigned(ts * ts)), dim3(256), XLDS, s, prof.start(), prof.stop(), 0, a);
   return hipGetLastError();
 }
 

@@ -31,10 +31,12 @@ qst_status hip_fail(hipError_t e, const char* what) {
 // With x0, the first POVM pass is applied to rho's tiles in the product
 // kernel and rho itself is not written.
 // planes: workspace for the bf16 planes of T (BF16 path, d >
-// kBf16SplitMaxDim), or NULL.
+// kBf16SplitMaxDim; QST_F32X6 from d = kX6Tile, where the kernel that
+// splits T forms the partial sums), or NULL.
 hipError_t run_state_map(qst_prec prec, const void* T, int64_t ldT, void* rho, int64_t ldr, int n,
                          double* partials, double* tau_dev, void* sk, hipStream_t s, const void* f = nullptr,
                          const Pass0Out* x0 = nullptr, void* planes = nullptr) {
+  if (use_x6(prec, n)) return launch_x6_herk(T, ldT, rho, ldr, n, partials, f, tau_dev, planes, sk, s, x0);
   const bool fold = n >= 6;
   hipError_t e = launch_tau(prec, T, ldT, n, partials, fold ? nullptr : tau_dev, s, f, planes);
   if (e != hipSuccess) return e;

@@ -12,17 +12,25 @@
 namespace qst {
 
 // Brackets the kernel launched while it is alive with timing events when
-// qst_profile_enable(1) is in effect (no-op otherwise).
+// qst_profile_enable(1) is in effect (no-op otherwise).  With in_launch, the
+// scope records nothing itself: its one kernel is launched with
+// hipExtLaunchKernelGGL(..., start(), stop(), ...), whose events are stamped
+// when that dispatch starts and ends (no queue time of separate event
+// packets in the interval); start() and stop() are NULL when inactive.
 class ProfScope {
  public:
-  ProfScope(const char* name, hipStream_t s);
+  ProfScope(const char* name, hipStream_t s, bool in_launch = false);
   ~ProfScope();
   ProfScope(const ProfScope&) = delete;
   ProfScope& operator=(const ProfScope&) = delete;
+  hipEvent_t start() const { return a_; }
+  hipEvent_t stop() const { return b_; }
 
  private:
   int idx_ = -1;
   hipStream_t s_;
+  bool in_launch_ = false;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 
 // tau = sum |T_ij|^2 (FP64; over bf16-rounded T for QST_BF16GEMM): the
@@ -130,11 +138,15 @@ hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T,
                        const double* upstream_dev, void* sk_partial, hipStream_t s, void* planes = nullptr);
 
 // QST_F32X6 products (k_xgemm.hip), d >= kX6Tile.  T T^dagger: planes
-// x6_herk_plane_bytes(n) and partials x6_partial_bytes(n) of workspace; as
-// launch_herk otherwise.  G' T: planes x6_hemm_plane_bytes(n); as
-// launch_hemm otherwise.
-hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, int n, const double* tau_partials,
-                          double* tau_dev, void* planes, void* partials, hipStream_t s, const Pass0Out* x0);
+// x6_herk_plane_bytes(n) and partials x6_partial_bytes(n) of workspace; the
+// kernel that splits T also writes the kReduceBlocks partial sums of tau at
+// tau_partials and, with f (4^N FP32 values), those of F = sum f at
+// tau_partials + kReduceBlocks (launch_tau is not called); tau is stored at
+// tau_dev; rho and x0 as launch_herk.  G' T: planes x6_hemm_plane_bytes(n);
+// as launch_hemm otherwise.
+hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, int n, double* tau_partials,
+                          const void* f, double* tau_dev, void* planes, void* partials, hipStream_t s,
+                          const Pass0Out* x0);
 hipError_t launch_x6_hemm(const void* G, int64_t ldg, const void* T, int64_t ldt, void* out, int64_t ldo, int n,
                           const double* tau_dev, const double* upstream_dev, void* planes, hipStream_t s);
 
