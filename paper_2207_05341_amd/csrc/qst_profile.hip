@@ -1,7 +1,8 @@
 // Optional per-kernel timing: when enabled, each timed scope of the library
 // (one kernel, or a fixed short sequence under one name) is bracketed by two
-// hipEvents recorded on its launch stream.  The report
-// waits for the events and sums the elapsed times per kernel name.
+// hipEvents recorded on its launch stream (or, for a single kernel, taken
+// by its launch as start and stop events).  The report waits for the events
+// and sums the elapsed times per kernel name.
 #include <cstdio>
 #include <map>
 #include <mutex>
@@ -48,20 +49,24 @@ hipEvent_t take_event(State& st) {
 
 }  // namespace
 
-ProfScope::ProfScope(const char* name, hipStream_t s) : s_(s) {
+ProfScope::ProfScope(const char* name, hipStream_t s, bool in_launch) : s_(s), in_launch_(in_launch) {
   State& st = state();
   std::lock_guard<std::mutex> lock(st.mu);
   if (!st.enabled) return;
   if (!st.only.empty() && st.only != name) return;
   hipEvent_t a = take_event(st), b = take_event(st);
   if (!a || !b) return;
-  if (hipEventRecord(a, s) != hipSuccess) return;
+  if (!in_launch && hipEventRecord(a, s) != hipSuccess) return;
   st.pending.push_back({name, a, b});
   idx_ = int(st.pending.size()) - 1;
+  if (in_launch) {
+    a_ = a;
+    b_ = b;
+  }
 }
 
 ProfScope::~ProfScope() {
-  if (idx_ < 0) return;
+  if (idx_ < 0 || in_launch_) return;
   State& st = state();
   std::lock_guard<std::mutex> lock(st.mu);
   if (idx_ < int(st.pending.size())) (void)hipEventRecord(st.pending[idx_].b, s_);
