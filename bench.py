@@ -99,10 +99,16 @@ def parse():
                     help="also train a fresh network for 1000 Rprop steps at N=11 (an end-to-end use of the "
                          "library, not part of the headline measurement)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="measure the headline step alone (no other paths, side records, batched form or CPU "
+                         "leg), e.g. under a profiler whose per-kernel averages should cover only that step")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy (torch.neg) of this many MiB first, as the "
                          "reference dispatch for scaling memory-traffic counters")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.headline_only:
+        args.no_variants = args.no_long = args.no_batched = args.no_cpu_baseline = True
+    return args
 
 
 def make_inputs(n: int):
@@ -797,9 +803,11 @@ def main():
     del p64, g64
 
     Tm, fm = to_prec(T_np, f_np, args.prec, dev)
-    modes = state_maps(qst, Tm, fm, args.prec)
-    fids = fidelities(qst, Tm, args.prec, f=fm)
-    net = network(qst, fm, args.prec, long_run=args.nnqst_run)
+    modes = fids = net = None
+    if not args.headline_only:
+        modes = state_maps(qst, Tm, fm, args.prec)
+        fids = fidelities(qst, Tm, args.prec, f=fm)
+        net = network(qst, fm, args.prec, long_run=args.nnqst_run)
     absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
     genp = None if args.no_long else general_povms(qst, args.prec, dev)
     del Tm, fm
