@@ -56,12 +56,18 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE (separate runs, KiB per dispatch), each scaled by what the same
 # counter reads for one plain 256 MiB device copy in the same run.  A figure
 # holds only for the kernel sources it was measured on (SHA-256 over the
-# files below, in order); otherwise the reported traffic is null.
-TRAFFIC_SOURCES = ["paper_2207_05341_amd/csrc/k_gemm.hip", "paper_2207_05341_amd/csrc/qst_gemm_tiles.h",
-                   "paper_2207_05341_amd/csrc/qst_device.h"]
+# record's source files, in order); otherwise the reported traffic is null.
+TRAFFIC_F32_SOURCES = ["paper_2207_05341_amd/csrc/k_gemm.hip", "paper_2207_05341_amd/csrc/qst_gemm_tiles.h",
+                       "paper_2207_05341_amd/csrc/qst_device.h"]
+TRAFFIC_X6_SOURCES = ["paper_2207_05341_amd/csrc/k_xgemm.hip", "paper_2207_05341_amd/csrc/qst_device.h",
+                      "paper_2207_05341_amd/csrc/qst_plan.h"]
 TRAFFIC = {
     # N = 11, d = 2048: 173433.0 KiB fetched x 1.9998 + 32768.0 KiB written x 1.0000
-    "hemm_f32": {"bytes": 388.71e6, "sources_sha256": "1e7a7a10ffb5a3dc9b5656b1a4dc8e43e07207dfe3b35e626d9354c8b7cf152d"},
+    "hemm_f32": {"bytes": 388.71e6, "sources": TRAFFIC_F32_SOURCES,
+                 "sources_sha256": "1e7a7a10ffb5a3dc9b5656b1a4dc8e43e07207dfe3b35e626d9354c8b7cf152d"},
+    # N = 11, d = 2048: 247292.0 KiB fetched x 1.9998 + 84736.0 KiB written x 1.0000
+    "hemm_x6": {"bytes": 593.18e6, "sources": TRAFFIC_X6_SOURCES,
+                "sources_sha256": "a4ce3f50f576dc819c1404eefa888ced8099c24dfab2100928ae1c6d030ad6f8"},
 }
 
 
@@ -77,7 +83,7 @@ def sources_sha256(paths):
 
 def traffic_of(kernel):
     rec = TRAFFIC.get(kernel)
-    if not rec or rec["sources_sha256"] != sources_sha256(TRAFFIC_SOURCES):
+    if not rec or rec["sources_sha256"] != sources_sha256(rec["sources"]):
         return None
     return rec["bytes"]
 
