@@ -251,7 +251,7 @@ struct XArgs {
   int d;
   const double* tau;       // tau, or NULL with tau_part
   const double* tau_part;  // FP64 partial sums of tau (kReduceBlocks), folded by every workgroup
-  double* tau_out;         // where workgroup 0 stores the folded tau
+  double* tau_out;         // where workgroup 0 of the T T^dagger fix-up stores the folded tau
   const double* up;        // HEMM: upstream scalar or NULL
   float* part;             // HERK partial tiles [slots][re, im][TILE] in the MFMA layout
   int ntiles, kIters;
@@ -414,8 +414,11 @@ __device__ __forceinline__ int x6_row(int wr, int i, int v, int lane) {
 }
 __device__ __forceinline__ int x6_col(int wc, int j, int lane) { return wc * 64 + j * 32 + (lane & 31); }
 
-// Partial of a tile segment, per lane in the MFMA layout:
-// element (((w * 4 + i * 2 + j) * 16 + v) * 2 + part) * 64 + lane.
+// Partial of a tile segment, 16 bytes per lane and store: values
+// 4 vq .. 4 vq + 3 of block ij = 2 i + j, part p (re, im) of wave w's lane l
+// at floats ((((4 w + ij) 2 + p) 4 + vq) 64 + l) 4 .. + 3 (each store of a
+// wave is 1 KB contiguous; wave w's 64 x 64 quadrant is floats
+// [8192 w, 8192 (w + 1))).
 __device__ __forceinline__ float* x6_slot(const XArgs& a, int64_t slot) {
   return a.part + slot * int64_t(2 * kXTileVals);
 }
@@ -423,19 +426,20 @@ __device__ __forceinline__ float* x6_slot(const XArgs& a, int64_t slot) {
 // of the worker's range, 1: the last) of slice worker w
 __device__ __forceinline__ int64_t x6_unit_slot(int64_t u) { return u; }
 __device__ __forceinline__ int64_t x6_slice_slot(const X6HerkSched& sc, int64_t w, int which) {
-  return (sc.sk > 1 ? sc.main : 0) + 2 * w + which;
+  return (sc.sk > 1 ? sc.main : 0) + (sc.tq ? w : 2 * w + which);
 }
 __device__ __forceinline__ void x6_store_partial(float* dst, const f16v (&re)[2][2], const f16v (&im)[2][2]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  f4v* d4 = reinterpret_cast<f4v*>(dst);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t o = (((w * 4 + i * 2 + j) * 16 + v) * 2) * 64 + lane;
-        dst[o] = re[i][j][v];
-        dst[o + 64] = im[i][j][v];
+      for (int vq = 0; vq < 4; ++vq) {
+        const int64_t o = (((w * 4 + i * 2 + j) * 2) * 4 + vq) * 64 + lane;
+        d4[o] = f4v{re[i][j][4 * vq], re[i][j][4 * vq + 1], re[i][j][4 * vq + 2], re[i][j][4 * vq + 3]};
+        d4[o + 256] = f4v{im[i][j][4 * vq], im[i][j][4 * vq + 1], im[i][j][4 * vq + 2], im[i][j][4 * vq + 3]};
       }
 }
 
@@ -546,8 +550,13 @@ __global__ __launch_bounds__(256, 1) void x6_herk_kernel(XArgs a) {
   extern __shared__ __align__(16) char lds[];
   const X6HerkSched& sc = a.sc;
   const int64_t w = xcd_order(blockIdx.x, gridDim.x);
-  const double tau = x6_tau(a, true);
-  const double scale = 1.0 / tau;
+  // 1 / tau, formed on the first whole tile this workgroup finishes (a
+  // split tile's partials are scaled in the fix-up, which stores tau)
+  double scale = 0.0;
+  auto tile_scale = [&]() {
+    if (scale == 0.0) scale = 1.0 / x6_tau(a, false);
+    return scale;
+  };
   for (int64_t r = 0; r < sc.rounds; ++r) {
     const int64_t u = r * sc.P + w;
     int64_t t;
@@ -558,18 +567,28 @@ __global__ __launch_bounds__(256, 1) void x6_herk_kernel(XArgs a) {
     f16v re[2][2], im[2][2];
     x6_zero(re, im);
     x6_segment<true>(a, lds, tr, tc, k0, k0 + int(sc.kh), re, im);
-    if (sc.sk == 1) x6_epilogue<true, X0G>(a, tr, tc, re, im, scale, lds);
+    if (sc.sk == 1) x6_epilogue<true, X0G>(a, tr, tc, re, im, tile_scale(), lds);
     else x6_store_partial(x6_slot(a, x6_unit_slot(u)), re, im);
   }
   if (w >= sc.Q) return;
-  int64_t it = x6_slice_start(w, sc.Q, sc.left_iters);
-  const int64_t end = x6_slice_start(w + 1, sc.Q, sc.left_iters);
+  // transposed slices: one piece, slice w / left of unit w % left
+  int64_t it = sc.tq ? 0 : x6_slice_start(w, sc.Q, sc.left_iters);
+  const int64_t end = sc.tq ? 1 : x6_slice_start(w + 1, sc.Q, sc.left_iters);
   const int64_t first_unit = it / sc.kh;
   while (it < end) {
-    const int64_t j = it / sc.kh;  // leftover unit
-    const int kb = int(it % sc.kh);
-    const int ke = int(std::min<int64_t>(sc.kh, kb + (end - it)));
-    it += ke - kb;
+    int64_t j;  // leftover unit
+    int kb, ke;
+    if (sc.tq) {
+      j = w % sc.left;
+      kb = int((w / sc.left) * sc.ps);
+      ke = kb + int(sc.ps);
+      it = end;
+    } else {
+      j = it / sc.kh;
+      kb = int(it % sc.kh);
+      ke = int(std::min<int64_t>(sc.kh, kb + (end - it)));
+      it += ke - kb;
+    }
     int64_t t;
     int k0;
     x6_unit(sc, sc.main + j, t, k0);
@@ -579,9 +598,9 @@ __global__ __launch_bounds__(256, 1) void x6_herk_kernel(XArgs a) {
     x6_zero(re, im);
     x6_segment<true>(a, lds, tr, tc, k0 + kb, k0 + ke, re, im);
     if (sc.sk == 1 && kb == 0 && ke == sc.kh) {
-      x6_epilogue<true, X0G>(a, tr, tc, re, im, scale, lds);
+      x6_epilogue<true, X0G>(a, tr, tc, re, im, tile_scale(), lds);
     } else {
-      x6_store_partial(x6_slot(a, x6_slice_slot(sc, w, j == first_unit ? 0 : 1)), re, im);
+      x6_store_partial(x6_slot(a, x6_slice_slot(sc, w, j == first_unit ? 0 : 1)), re, im);  // slot w with tq
     }
   }
 }
@@ -608,6 +627,7 @@ struct X6Contrib {
   __device__ bool finished() const {
     if (sc.sk != 1) return false;
     if (t < sc.main) return true;  // a round unit: the whole tile
+    if (sc.tq) return sc.tq == 1;  // one transposed slice per unit: the whole tile
     int64_t lo, h;
     x6_owners(sc, t - sc.main, lo, h);
     return lo == h;  // inside one worker's slice: finished there
@@ -615,6 +635,7 @@ struct X6Contrib {
   __device__ int64_t next() {
     while (true) {
       if (wg <= hi) {  // slice partials of leftover unit j
+        if (sc.tq) return x6_slice_slot(sc, j + sc.left * wg++, 0);  // slice wg of unit j: worker j + left wg
         const int64_t first_unit = x6_slice_start(wg, sc.Q, sc.left_iters) / sc.kh;
         const int64_t slot = x6_slice_slot(sc, wg, j == first_unit ? 0 : 1);
         ++wg;
@@ -625,7 +646,12 @@ struct X6Contrib {
       ++s;
       if (u < sc.main) return x6_unit_slot(u);
       j = u - sc.main;
-      x6_owners(sc, j, wg, hi);
+      if (sc.tq) {
+        wg = 0;
+        hi = sc.tq - 1;
+      } else {
+        x6_owners(sc, j, wg, hi);
+      }
     }
   }
 };
@@ -644,6 +670,7 @@ template <int X0G>
 __global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
   __shared__ __align__(16) Cx<float> L[64 * 64];
   const X6HerkSched& sc = a.sc;
+  if (blockIdx.x == 0) (void)x6_tau(a, true);  // stores tau (the product kernel does not)
   const int64_t t = sc.ntiles - 1 - (blockIdx.x >> 2);
   const int q = blockIdx.x & 3, qr = q >> 1, qc = q & 1;
   int tr, tc;
@@ -676,8 +703,10 @@ __global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
     if (sl[3] < 0) break;
   }
   const double scale = 1.0 / x6_tau(a, false);
-  // value index e = 4 (th + 256 m) + c = ((ij * 16 + v) * 2 + part) * 64 + lane
+  // vector th + 256 m of the quadrant holds values 4 vq + c of block
+  // ij = m / 2, part m % 2, lane th % 64, vq = th / 64
   const float sc32 = float(scale);
+  const int lane = th & 63, vq = th >> 6;
   if constexpr (X0G == 0) {
     Cx<float>* C = static_cast<Cx<float>*>(a.C);
     float* Cf = reinterpret_cast<float*>(C);
@@ -685,8 +714,7 @@ __global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
     for (int m = 0; m < 8; ++m)
 #pragma unroll
       for (int c4 = 0; c4 < 4; ++c4) {
-        const int e = 4 * (th + 256 * m) + c4;
-        const int lane = e & 63, part = (e >> 6) & 1, vv = (e >> 7) & 15, ij = e >> 11;
+        const int part = m & 1, vv = 4 * vq + c4, ij = m >> 1;
         const int i = ij >> 1, j = ij & 1;
         const int64_t r = int64_t(tr) * XT + qr * 64 + i * 32 + 8 * (vv >> 2) + 4 * (lane >> 5) + (vv & 3);
         const int64_t c = int64_t(tc) * XT + qc * 64 + j * 32 + (lane & 31);
@@ -706,8 +734,7 @@ __global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
     for (int m = 0; m < 8; ++m)
 #pragma unroll
       for (int c4 = 0; c4 < 4; ++c4) {
-        const int e = 4 * (th + 256 * m) + c4;
-        const int lane = e & 63, part = (e >> 6) & 1, vv = (e >> 7) & 15, ij = e >> 11;
+        const int part = m & 1, vv = 4 * vq + c4, ij = m >> 1;
         const int i = ij >> 1, j = ij & 1;
         const int r = i * 32 + 8 * (vv >> 2) + 4 * (lane >> 5) + (vv & 3), c = j * 32 + (lane & 31);
         Lf[2 * (((r >> G) * S + (c >> G)) * TG + swz<G>(r & M, c & M)) + part] = acc[m][c4] * sc32;
@@ -755,9 +782,7 @@ hipError_t x6_run_herk(XArgs a, int n, hipStream_t s) {
   const int64_t grid = a.sc.rounds > 0 ? a.sc.P : a.sc.Q;
   x6_herk_kernel<X0G><<<unsigned(grid), 256, XLDS, s>>>(a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  XArgs f = a;
-  f.tau_out = nullptr;
-  x6_fixup_kernel<X0G><<<unsigned(a.ntiles) * 4, 256, 0, s>>>(f);
+  x6_fixup_kernel<X0G><<<unsigned(a.ntiles) * 4, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -42,7 +42,9 @@ struct X6HerkSched {
   int64_t P = 1;  // workgroups of the rounds (one per CU)
   int64_t Q = 1;  // workgroups taking slices
   int64_t ntiles = 0, sk = 1, kh = 0, units = 0, rounds = 0, main = 0, left = 0, left_iters = 0;
-  int64_t slots = 0;  // partial tiles: one per round unit when sk > 1, two per slice worker
+  int64_t slots = 0;  // partial tiles: one per round unit when sk > 1, two per slice worker (one with tq)
+  int64_t tq = 0;     // transposed slices: slices per leftover unit (0: contiguous slices)
+  int64_t ps = 0;     // panels per transposed slice
 };
 inline X6HerkSched x6_herk_sched(int n, int cus) {
   X6HerkSched s;
@@ -70,7 +72,16 @@ inline X6HerkSched x6_herk_sched(int n, int cus) {
   if (s.Q > s.P) s.Q = s.P;
   if (s.Q < 1) s.Q = 1;
   if (s.left_iters == 0) s.Q = 0;
-  s.slots = (s.sk > 1 ? s.main : 0) + 2 * s.Q;
+  // After rounds, when the leftover units split evenly into the Q slices,
+  // slice worker w takes the (w / left)-th of the tq equal slices of unit
+  // w % left: the workers of an XCD (consecutive w) then stream the same K
+  // panels of several tiles at once, and every slice lies inside one unit
+  // (one partial tile each).
+  if (s.rounds > 0 && s.left > 0 && s.Q % s.left == 0 && s.kh % (s.Q / s.left) == 0) {
+    s.tq = s.Q / s.left;
+    s.ps = s.kh / s.tq;
+  }
+  s.slots = (s.sk > 1 ? s.main : 0) + (s.tq ? s.Q : 2 * s.Q);
   return s;
 }
 inline size_t x6_partial_bytes(int n) {
