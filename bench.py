@@ -2,17 +2,18 @@
 """Likelihood forward + adjoint throughput at N = 11 on one MI355X.
 
 One step = the whole hot path on one batch of synthetic input, inputs resident
-in HBM before timing starts:
-    qst_likelihood (tau, T T^dagger, POVM map over 4^11 outcomes, NLL,
-    cotangent, adjoint POVM map -> G'; the last POVM pass, the NLL terms, the
-    cotangent and the first adjoint pass fused, p never stored)
-    ->  qst_grad_product (2/tau G' T).
+in HBM before timing starts, as one call, qst_likelihood_grad:
+    tau, T T^dagger, POVM map over 4^11 outcomes, NLL, cotangent, adjoint
+    POVM map -> G' (the last POVM pass, the NLL terms, the cotangent and the
+    first adjoint pass fused, p never stored), then 2/tau G' T.
 The headline path is QST_F32X6 (FP32 storage and FP32-level accuracy; the
 two complex products as six split-bf16 products per real product on the BF16
-matrix cores); the FP64, FP32 (FP32 MFMA products) and BF16 paths and the
-same step as four separate calls with p stored (qst_state_map,
-qst_povm_probs, qst_nll, qst_nll_backward) are reported alongside, each with
-its error against the FP64 oracle.
+matrix cores, their operand planes formed inside the call); the FP64, FP32
+(FP32 MFMA products) and BF16 paths, the same step as two calls
+(qst_likelihood returning G', then qst_grad_product) and as four separate
+calls with p stored (qst_state_map, qst_povm_probs, qst_nll,
+qst_nll_backward) are reported alongside, each with its error against the
+FP64 oracle.
 
 Workload (N = 11): T 2048 x 2048 complex Ginibre (seed 6); frequencies from
 10^7 multinomial shots of a Porter-Thomas stand-in distribution of a
@@ -137,11 +138,19 @@ def to_prec(T, f, prec, dev):
             torch.from_numpy(np.ascontiguousarray(f.astype(rt))).to(dev))
 
 
-def step(qst, T, f, prec, fused=True):
-    """One pass of the whole path.  fused: qst_likelihood (tau, rho, p, L, F and
-    G' in one call; p never stored) then qst_grad_product.  Otherwise the four
-    separate calls with p stored between them."""
-    if fused:
+ROUTES = ("one_call", "two_calls", "separate")
+
+
+def step(qst, T, f, prec, route="one_call"):
+    """One pass of the whole path.  one_call: qst_likelihood_grad (L and dL/dT
+    in one call; p and G' never leave the library's workspace); two_calls:
+    qst_likelihood (tau, rho, p, L, F and G'; p never stored) then
+    qst_grad_product; separate: the four separate calls with p stored
+    between them."""
+    if route == "one_call":
+        out, _, grad, _ = qst.likelihood_grad(T, f, prec)
+        return out, grad
+    if route == "two_calls":
         out, tau, G, _ = qst.likelihood_forward(T, f, prec)
         grad = qst.grad_product(G, T, tau, prec)
         return out, grad
@@ -152,7 +161,7 @@ def step(qst, T, f, prec, fused=True):
     return out, grad
 
 
-def time_steps(qst, T, f, prec, steps, warmup, only=None, fused=True):
+def time_steps(qst, T, f, prec, steps, warmup, only=None, route="one_call"):
     """Run warmup + steps; with `only`, the library times that kernel scope
     (HIP events on its launch stream) inside the same steps; `only=""` times
     every scope (each bracketing event costs queue time, so that loop is a
@@ -162,14 +171,14 @@ def time_steps(qst, T, f, prec, steps, warmup, only=None, fused=True):
     from paper_2207_05341_amd import _lib
 
     for _ in range(warmup):
-        step(qst, T, f, prec, fused)
+        step(qst, T, f, prec, route)
     torch.cuda.synchronize()
     if only is not None:
         _lib.profile_report(reset=True)
         _lib.profile_enable(True, only or None)
     t0 = time.perf_counter()
     for _ in range(steps):
-        step(qst, T, f, prec, fused)
+        step(qst, T, f, prec, route)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern = {}
@@ -701,13 +710,13 @@ def main():
     del rho64, T64, f64
     torch.cuda.synchronize()
 
-    def measure(prec, steps, warmup, fused=True):
+    def measure(prec, steps, warmup, route="one_call"):
         """The path's outputs (for accuracy); a per-kernel breakdown (each
         scope timed alone, in warmed loops: the events bracketing a scope
         add their queue time to it only); then the timed loop, in which
         only the dominant kernel is bracketed by events."""
         T, f = to_prec(T_np, f_np, prec, dev)
-        out, grad = step(qst, T, f, prec, fused)
+        out, grad = step(qst, T, f, prec, route)
         rho, _ = qst.state_map(T, prec)
         p = qst.povm_probs(rho, prec)  # the forward map alone, for max|dp|
         del rho
@@ -722,13 +731,13 @@ def main():
         }
         del p, out, grad
         # the scopes and the dominant one from a short loop that times them all
-        _, names = time_steps(qst, T, f, prec, 3, 2, only="", fused=fused)
+        _, names = time_steps(qst, T, f, prec, 3, 2, only="", route=route)
         dom = max(names, key=lambda k: names[k][1] / names[k][0])
-        sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom, fused=fused)
+        sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom, route=route)
         breakdown = {dom: kdom[dom]}
         for name in names:
             if name != dom:
-                breakdown.update(time_steps(qst, T, f, prec, steps, 3, only=name, fused=fused)[1])
+                breakdown.update(time_steps(qst, T, f, prec, steps, 3, only=name, route=route)[1])
         return sec, breakdown, dom, kdom, acc, res
 
     sec, kern, dom, kdom, acc, res_main = measure(args.prec, args.steps, args.warmup)
@@ -801,7 +810,12 @@ def main():
             s2, k2, _, _, a2, path_res[prec] = measure(prec, max(10, args.steps // 2), 3)
             paths[prec] = {"evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
                            "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()}}
-        s2, k2, _, _, a2, _ = measure(args.prec, max(10, args.steps // 2), 3, fused=False)
+        s2, k2, _, _, a2, _ = measure(args.prec, max(10, args.steps // 2), 3, route="two_calls")
+        paths[args.prec + "_two_calls"] = {
+            "evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
+            "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()},
+            "note": "qst_likelihood (G' returned) then qst_grad_product"}
+        s2, k2, _, _, a2, _ = measure(args.prec, max(10, args.steps // 2), 3, route="separate")
         paths[args.prec + "_separate_calls"] = {
             "evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
             "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()},
@@ -866,8 +880,8 @@ def main():
         "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": f"N={n} single state: T {d}x{d} complex Ginibre, {4 ** n} tetrahedral-POVM "
-                               f"outcomes, f from 10^7 multinomial shots; forward+adjoint as qst_likelihood + "
-                               f"qst_grad_product (p not stored)",
+                               f"outcomes, f from 10^7 multinomial shots; forward+adjoint as one call, qst_likelihood_grad "
+                               f"(p and G' not stored)",
                    "n_qubits": n, "precision": args.prec, "precision_note": PREC_NOTE[args.prec],
                    "parallelism": "none (1 GPU)"},
         "roofline": roofline,

@@ -94,7 +94,8 @@ typedef enum {
   QST_OP_GRAD_PRODUCT = 5,
   QST_OP_FIDELITY = 6,
   QST_OP_FNN = 7,
-  QST_OP_ABS_MAP = 8
+  QST_OP_ABS_MAP = 8,
+  QST_OP_LIKELIHOOD_GRAD = 9
 } qst_op;
 
 /*
@@ -300,6 +301,30 @@ qst_status qst_likelihood_fc(int n_qubits, qst_prec prec, const void* T, int64_t
                              const void* p_target, const double* povm_host, double* tau_dev, double* nll_dev,
                              double* fc_dev, unsigned long long* bad_dev, void* G, int64_t ldG, void* ws,
                              size_t ws_bytes, void* stream);
+
+/*
+ * Likelihood and gradient in one call (Eq. MLE_T): tau, L, F and the
+ * counters as qst_likelihood, and
+ *   gradT = dL/dRe T + i dL/dIm T = (2 / tau) G' T,
+ * what qst_likelihood followed by qst_grad_product (upstream 1) gives;
+ * G' itself is not returned.  With QST_F32X6 from d = 128 the kernel that
+ * splits T for T T^dagger also writes T^T's planes for the gradient
+ * product, and where the first POVM stage covers 5 or 6 qubits
+ * (tetrahedral POVM, N = 9, 10, 11, 13) the adjoint's last stage writes G'
+ * directly as that product's planes.  tau, L, F and the counters equal
+ * qst_likelihood's bitwise; gradT equals the two calls' bitwise, except on
+ * that last route, where it agrees to rounding (the adjoint stage that
+ * writes planes is a kernel instance of its own, whose sums may contract
+ * into FMAs differently).
+ *   gradT    [out] d x d complex, row stride ld_grad, device; must not
+ *                  overlap T.
+ * Workspace: qst_workspace_bytes(N, prec, QST_OP_LIKELIHOOD_GRAD).  Other
+ * arguments and errors as qst_likelihood.
+ */
+qst_status qst_likelihood_grad(int n_qubits, qst_prec prec, const void* T, int64_t ldT, const void* f,
+                               const double* povm_host, double* tau_dev, double* nll_dev,
+                               unsigned long long* bad_dev, void* gradT, int64_t ld_grad, void* ws,
+                               size_t ws_bytes, void* stream);
 
 /*
  * Gradient product, the last step of the adjoint (Eq. MLE_T):

@@ -15,12 +15,13 @@ import torch
 
 from . import _lib
 from ._lib import (QST_BF16GEMM, QST_F32, QST_F32X6, QST_F64, QST_MAX_QUBITS, QST_OP_ABS_MAP, QST_OP_GRAD_PRODUCT, QST_OP_LIKELIHOOD,
+                   QST_OP_LIKELIHOOD_GRAD,
                    QST_FIDELITY_MAX_RANK, QST_OP_FIDELITY, QST_OP_FNN, QST_OP_NLL, QST_OP_NLL_BACKWARD, QST_OP_POVM_PROBS,
                    QST_OP_STATE_MAP, QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER, QstError, workspace_bytes)
 
 __all__ = [
     "PRECISIONS", "STATE_MAPS", "state_premap", "state_map", "povm_probs", "nll", "nll_backward",
-    "likelihood_forward", "likelihood_forward_noalloc", "likelihood_forward_fc", "povm_probs_general",
+    "likelihood_forward", "likelihood_grad", "likelihood_forward_noalloc", "likelihood_forward_fc", "povm_probs_general",
     "likelihood_forward_general", "likelihood_general", "GeneralLikelihoodFn", "grad_product", "likelihood", "LikelihoodFn", "StatePremapFn", "abs_map",
     "abs_map_backward", "abs_map_async", "AbsMapFn", "AbsProjection", "fidelity_lowrank", "fidelity_general",
     "fidelity_general_async",
@@ -367,6 +368,26 @@ def likelihood_forward(T: torch.Tensor, f: torch.Tensor, prec=None, povm=None, w
                                          out.data_ptr(), bad.data_ptr(), _ptr(G), 0 if G is None else G.stride(0),
                                          _ptr(ws), nb, _stream(T.device)), "qst_likelihood")
     return out, tau, G, bad
+
+
+def likelihood_grad(T: torch.Tensor, f: torch.Tensor, prec=None, povm=None):
+    """L and its gradient in one library call (qst_likelihood_grad): returns
+    (out, tau, grad, bad) with out = [L, F] (float64), tau (0-dim float64),
+    grad = dL/dRe T + i dL/dIm T (T's dtype and shape) and bad as
+    likelihood_forward -- the results of likelihood_forward followed by
+    grad_product, bitwise, without G'."""
+    n, ld = _matrix(T, "T")
+    pr = _prec(T.dtype, prec)
+    _vector(f, "f", n, real_dtype(pr))
+    out = torch.empty(2, dtype=torch.float64, device=T.device)
+    bad = torch.empty(2, dtype=torch.int64, device=T.device)
+    tau = torch.empty((), dtype=torch.float64, device=T.device)
+    grad = torch.empty(T.shape, dtype=T.dtype, device=T.device)
+    ws, nb = _workspace(n, pr, QST_OP_LIKELIHOOD_GRAD, T.device)
+    _lib.check(_lib.lib().qst_likelihood_grad(n, pr, T.data_ptr(), ld, f.data_ptr(), _povm_arg(povm), tau.data_ptr(),
+                                              out.data_ptr(), bad.data_ptr(), grad.data_ptr(), grad.stride(0),
+                                              _ptr(ws), nb, _stream(T.device)), "qst_likelihood_grad")
+    return out, tau, grad, bad
 
 
 def likelihood_forward_noalloc(T: torch.Tensor, f: torch.Tensor, prec=None, povm=None, G: torch.Tensor | None = None,

@@ -14,6 +14,7 @@ QST_OK, QST_ERR_INVALID_ARG, QST_ERR_UNSUPPORTED, QST_ERR_WORKSPACE, QST_ERR_HIP
 QST_F64, QST_F32, QST_BF16GEMM, QST_F32X6 = 0, 1, 2, 3
 QST_OP_STATE_MAP, QST_OP_POVM_PROBS, QST_OP_NLL, QST_OP_NLL_BACKWARD = 0, 1, 2, 3
 QST_OP_LIKELIHOOD, QST_OP_GRAD_PRODUCT, QST_OP_FIDELITY, QST_OP_FNN, QST_OP_ABS_MAP = 4, 5, 6, 7, 8
+QST_OP_LIKELIHOOD_GRAD = 9
 QST_FIDELITY_MAX_RANK = 32
 QST_MAX_QUBITS = 13
 QST_PREMAP_HERMITIAN, QST_PREMAP_LOWER = 1, 2
@@ -35,6 +36,7 @@ SIGNATURES = {
     "qst_likelihood_general": (_int, [_int, _int, _vp, _i64, _int, _int, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                        _sz, _vp]),
     "qst_grad_product": (_int, [_int, _int, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
+    "qst_likelihood_grad": (_int, [_int, _int, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "qst_state_premap": (_int, [_int, _int, _int, _vp, _i64, _vp, _i64, _vp]),
     "qst_abs_map": (_int, [_int, _int, ctypes.c_double, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "qst_abs_map_async": (_int, [_int, _int, ctypes.c_double, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _int, _vp, _vp,

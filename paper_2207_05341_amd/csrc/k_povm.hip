@@ -120,7 +120,7 @@ hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W,
                              const void* rho, int64_t ld_rho, const void* fvec, const double* Fpart, void* G,
                              int64_t ldG, void* inter0, void* inter1, double* part, double* nll_dev,
                              unsigned long long* bad_dev, bool pass0_done, hipStream_t s, const void* pt,
-                             double* fc_dev) {
+                             double* fc_dev, void* gplanes) {
   static const char* kFwd[4] = {"povm_fwd_p0", "povm_fwd_p1", "povm_fwd_p2", "povm_fwd_p3"};
   static const char* kAdj[4] = {"povm_adj_p0", "povm_adj_p1", "povm_adj_p2", "povm_adj_p3"};
   ModeMatrix Af, Aa;
@@ -163,12 +163,13 @@ hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W,
     if ((e = launch_likelihood_finish(part, int(nb), Fpart, nll_dev, bad_dev, s, pt ? fc_dev : nullptr)) != hipSuccess)
       return e;
   }
-  if (!G) return hipSuccess;
+  if (!G && !gplanes) return hipSuccess;
   for (int j = P - 2; j >= 0; --j) {
     PassArgs a = args(j);
     a.in = bufs[j & 1];
     a.out = j == 0 ? G : bufs[(j - 1) & 1];
     a.ld = ldG;
+    if (j == 0) a.gplanes = gplanes;
     ProfScope prof(kAdj[j], s);
     if (!launch_pass_fast(true, prec, tetra, a, Aa, j == 0, false, povm_pass_blocks(pl, j), s, &e))
       return hipErrorInvalidValue;

@@ -36,11 +36,11 @@ namespace {
 // Matrix-side pass (pass 0) and outcome-side passes (passes 1..): one
 // logical block per workgroup (fast_pass::mat_pass_body / kd_pass_body).
 // ---------------------------------------------------------------------------
-template <typename R, bool ADJ, bool TETRA, int G>
+template <typename R, bool ADJ, bool TETRA, int G, bool PLANES = false>
 __global__ __launch_bounds__(256) void mat_pass(PassArgs a, ModeMatrix A, int64_t ntiles) {
   constexpr int TPW = 256 >> (2 * (G - 2));
   __shared__ Cx<R> lds[TPW << (2 * G)];
-  fast_pass::mat_pass_body<R, ADJ, TETRA, G>(a, A, ntiles, blockIdx.x, threadIdx.x, lds);
+  fast_pass::mat_pass_body<R, ADJ, TETRA, G, PLANES>(a, A, ntiles, blockIdx.x, threadIdx.x, lds);
 }
 
 template <typename R, bool ADJ, bool TETRA, int G, int J, bool PSIDE>
@@ -144,6 +144,19 @@ bool launch_pass_fast(bool adjoint, qst_prec prec, bool tetra, const PassArgs& a
       else { if (tetra) QST_MAT(float, false, true, G); else QST_MAT(float, false, false, G); }    \
     }                                                                                             \
   } while (0)
+  if (matside && adjoint && a.gplanes) {  // G' as split planes: FP32 adjoint, g = 5 or 6
+    if (f64 || pside || a.J != 1 || a.g < 5 || a.g > 6) return false;
+    const unsigned grid = unsigned((blocks + (256 >> (2 * (a.g - 2))) - 1) / (256 >> (2 * (a.g - 2))));
+    if (a.g == 5) {
+      if (tetra) mat_pass<float, true, true, 5, true><<<grid, 256, 0, s>>>(a, A, blocks);
+      else mat_pass<float, true, false, 5, true><<<grid, 256, 0, s>>>(a, A, blocks);
+    } else {
+      if (tetra) mat_pass<float, true, true, 6, true><<<grid, 256, 0, s>>>(a, A, blocks);
+      else mat_pass<float, true, false, 6, true><<<grid, 256, 0, s>>>(a, A, blocks);
+    }
+    *err = hipGetLastError();
+    return true;
+  }
   if (matside && !pside && a.J == 1 && a.g >= 4 && a.g <= 6) {
     if (a.g == 4) QST_MAT_ALL(4);
     else if (a.g == 5) QST_MAT_ALL(5);

@@ -54,6 +54,7 @@
 #include "qst_gemm_tiles.h"
 #include "qst_kernels.h"
 #include "qst_plan.h"
+#include "qst_split.h"
 
 namespace qst {
 
@@ -61,7 +62,6 @@ namespace {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef float f4v __attribute__((ext_vector_type(4)));
-typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 constexpr int XT = kX6Tile;               // output tile (complex)
@@ -74,32 +74,8 @@ constexpr int XUNIT = 64;                 // 16-byte vectors per 1 KB unit
 static_assert((XDIST - 2) * 6 < 64, "vmcnt immediate");
 
 // ---------------------------------------------------------------------------
-// Split
+// Split (helpers in qst_split.h)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
-  const bf2v v = {(__bf16)a, (__bf16)b};
-  return __builtin_bit_cast(uint32_t, v);
-}
-__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
-__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
-
-// x = H + M + L exactly, eight values, bf16 bit patterns packed in pairs.
-__device__ __forceinline__ void split3(const float (&x)[8], u16x8& H, u16x8& M, u16x8& L) {
-  u32x4 h, m, l;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    h[i] = bf16x2_rne(x[2 * i], x[2 * i + 1]);
-    float r0 = x[2 * i] - bf16_lo(h[i]), r1 = x[2 * i + 1] - bf16_hi(h[i]);
-    m[i] = bf16x2_rne(r0, r1);
-    r0 -= bf16_lo(m[i]);
-    r1 -= bf16_hi(m[i]);
-    l[i] = bf16x2_rne(r0, r1);
-  }
-  H = __builtin_bit_cast(u16x8, h);
-  M = __builtin_bit_cast(u16x8, m);
-  L = __builtin_bit_cast(u16x8, l);
-}
-
 // Planes of a d x d complex FP32 matrix X (leading dimension ld) as the
 // row operand (TRANS false: row r, k = column) or as the rows of X^T (TRANS
 // true: row r = column of X, k = row of X).  Groups: re, im, re + im, and
@@ -116,40 +92,41 @@ __global__ __launch_bounds__(256) void x6_split_kernel(const Cx<float>* __restri
   const int64_t rb = blk / nkb, kb = blk % nkb;
   const int64_t row = rb * 32 + (lane & 31);
   const int64_t k0 = kb * 16 + 8 * (lane >> 5);
-  float re[8], im[8], g2[8];
+  float re[8], im[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const Cx<float> v = TRANS ? X[(k0 + e) * ld + row] : X[row * ld + k0 + e];
     re[e] = v.re;
     im[e] = v.im;
   }
-  u16x8* out = P + blk * (NG * 3 * XUNIT) + lane;
-  split3(re, out[0 * XUNIT], out[1 * XUNIT], out[2 * XUNIT]);
-  split3(im, out[3 * XUNIT], out[4 * XUNIT], out[5 * XUNIT]);
-#pragma unroll
-  for (int e = 0; e < 8; ++e) g2[e] = re[e] + im[e];
-  split3(g2, out[6 * XUNIT], out[7 * XUNIT], out[8 * XUNIT]);
-  if constexpr (NG == 4) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) g2[e] = re[e] - im[e];
-    split3(g2, out[9 * XUNIT], out[10 * XUNIT], out[11 * XUNIT]);
-  }
+  write_unit_block<NG>(P + blk * (NG * 3 * XUNIT) + lane, re, im);
 }
 
-// The planes of T as the row operand (x6_split_kernel<false, 4>) together
-// with the FP64 partial sums of tau = sum |T_ij|^2 and, with f, of
-// F = sum_k f_k: workgroup b of nb writes partials[b] (its unit blocks
-// b, b + nb, ..., four per pass, one per wave) and partials[nb + b] (f
-// over the contiguous range [b D / nb, (b + 1) D / nb), D = d^2), each
-// summed in a fixed order, so T is read once on the likelihood path.  The
-// first 16 values of f per thread are loaded before the unit blocks, so
-// that their loads are in flight together with those of T.
-template <bool WITH_F>
+// The planes of T as the row operand of T T^dagger (groups re, im, re + im,
+// re - im) and, with TT, of T^T as the column operand of G' T (re, im,
+// re + im), with the FP64 partial sums of tau = sum |T_ij|^2 and, with f,
+// of F = sum_k f_k: workgroup b of nb writes partials[b] (its 32 x 32
+// blocks b, b + nb, ..., four per pass, one per wave) and partials[nb + b]
+// (f over [b D / nb, (b + 1) D / nb), D = d^2), each summed in a fixed
+// order, so that T is read once.  A wave reads its block as the slots of
+// two row-operand unit blocks (lane u: row u % 32, columns 16 h + 8 (u / 32)
+// .. + 7, h = 0, 1); with TT it passes the block through LDS (8 KB per
+// wave, 16-byte chunks swizzled by row) and reads the two unit blocks of
+// T^T (lane u: column u % 32, rows 16 h + 8 (u / 32) .. + 7).  The first 16
+// values of f per thread are loaded first, so that their loads are in
+// flight together with those of T.
+__device__ __forceinline__ int split_swz(int r, int c) {  // (r, c) of a 32 x 32 block, complex index
+  return r * 32 + 2 * (((c >> 1) ^ r) & 15) + (c & 1);
+}
+
+template <bool WITH_F, bool TT>
 __global__ __launch_bounds__(256) void x6_split_tau_kernel(const Cx<float>* __restrict__ X, int64_t ld, int d,
-                                                           u16x8* __restrict__ P, double* __restrict__ partials,
+                                                           u16x8* __restrict__ P, u16x8* __restrict__ PT,
+                                                           double* __restrict__ partials,
                                                            const float* __restrict__ f) {
   constexpr int NT = 256, NW = NT / 64, U = 16;
   __shared__ double red[NW];
+  __shared__ Cx<float> blkL[TT ? NW : 1][TT ? 32 * 32 : 1];
   const int nb = gridDim.x;
   const int64_t D = int64_t(d) * d;
   const int64_t fbeg = D * blockIdx.x / nb, fend = D * (blockIdx.x + 1) / nb;
@@ -161,34 +138,48 @@ __global__ __launch_bounds__(256) void x6_split_tau_kernel(const Cx<float>* __re
       fv[u] = e < fend ? f[e] : 0.f;
     }
   }
-  const int lane = threadIdx.x & 63;
-  const int nkb = d / 16;
-  const int64_t nblk = int64_t(d / 32) * nkb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = lane & 31, hq = lane >> 5;
+  const int nkb = d / 16, nb32 = d / 32;
+  const int64_t nblk = int64_t(nb32) * nb32;
   double acc = 0.0, accf = 0.0;
+  // the loop bound is the same for the whole workgroup (barriers inside)
   for (int64_t b0 = int64_t(blockIdx.x) * NW; b0 < nblk; b0 += int64_t(nb) * NW) {
-    const int64_t blk = b0 + (threadIdx.x >> 6);  // unit block (rb, kb)
-    if (blk >= nblk) continue;
-    const int64_t rb = blk / nkb, kb = blk % nkb;
-    const int64_t row = rb * 32 + (lane & 31);
-    const int64_t k0 = kb * 16 + 8 * (lane >> 5);
-    float re[8], im[8], g2[8];
+    const int64_t blk = b0 + wv;
+    const bool act = blk < nblk;
+    const int64_t br = act ? blk / nb32 : 0, bc = act ? blk % nb32 : 0;
+    if (act) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const Cx<float> v = X[row * ld + k0 + e];
-      re[e] = v.re;
-      im[e] = v.im;
+      for (int h = 0; h < 2; ++h) {
+        float re[8], im[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const Cx<float> v = X[(32 * br + row) * ld + 32 * bc + 16 * h + 8 * hq + e];
+          re[e] = v.re;
+          im[e] = v.im;
+          acc += double(v.re) * double(v.re) + double(v.im) * double(v.im);
+          if constexpr (TT) blkL[wv][split_swz(row, 16 * h + 8 * hq + e)] = v;
+        }
+        write_unit_block<4>(P + (br * nkb + 2 * bc + h) * (4 * 3 * XUNIT) + lane, re, im);
+      }
     }
+    if constexpr (TT) {
+      __syncthreads();
+      if (act) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) acc += double(re[e]) * double(re[e]) + double(im[e]) * double(im[e]);
-    u16x8* out = P + blk * (4 * 3 * XUNIT) + lane;
-    split3(re, out[0 * XUNIT], out[1 * XUNIT], out[2 * XUNIT]);
-    split3(im, out[3 * XUNIT], out[4 * XUNIT], out[5 * XUNIT]);
+        for (int h = 0; h < 2; ++h) {
+          float re[8], im[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) g2[e] = re[e] + im[e];
-    split3(g2, out[6 * XUNIT], out[7 * XUNIT], out[8 * XUNIT]);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) g2[e] = re[e] - im[e];
-    split3(g2, out[9 * XUNIT], out[10 * XUNIT], out[11 * XUNIT]);
+          for (int e = 0; e < 8; ++e) {
+            const Cx<float> v = blkL[wv][split_swz(16 * h + 8 * hq + e, row)];
+            re[e] = v.re;
+            im[e] = v.im;
+          }
+          write_unit_block<3>(PT + (bc * nkb + 2 * br + h) * (3 * 3 * XUNIT) + lane, re, im);
+        }
+      }
+      __syncthreads();
+    }
   }
   if constexpr (WITH_F) {
 #pragma unroll
@@ -790,7 +781,7 @@ hipError_t x6_run_herk(XArgs a, int n, hipStream_t s) {
 
 hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, int n, double* tau_partials,
                           const void* f, double* tau_dev, void* planes, void* partials, hipStream_t s,
-                          const Pass0Out* x0) {
+                          const Pass0Out* x0, void* tt_planes) {
   const int d = 1 << n;
   if (d < kX6Tile || !tau_partials) return hipErrorInvalidValue;
   if (x0 && (x0->g < 4 || x0->g > 6 || !x0->tetra)) return hipErrorInvalidValue;
@@ -798,10 +789,12 @@ hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, in
   {
     ProfScope prof("x6_split_t", s);
     const Cx<float>* Tf = static_cast<const Cx<float>*>(T);
-    if (f)
-      x6_split_tau_kernel<true><<<kReduceBlocks, 256, 0, s>>>(Tf, ldt, d, P, tau_partials, static_cast<const float*>(f));
-    else
-      x6_split_tau_kernel<false><<<kReduceBlocks, 256, 0, s>>>(Tf, ldt, d, P, tau_partials, nullptr);
+    const float* ff = static_cast<const float*>(f);
+    u16x8* PT = static_cast<u16x8*>(tt_planes);
+    if (f && PT) x6_split_tau_kernel<true, true><<<kReduceBlocks, 256, 0, s>>>(Tf, ldt, d, P, PT, tau_partials, ff);
+    else if (f) x6_split_tau_kernel<true, false><<<kReduceBlocks, 256, 0, s>>>(Tf, ldt, d, P, PT, tau_partials, ff);
+    else if (PT) x6_split_tau_kernel<false, true><<<kReduceBlocks, 256, 0, s>>>(Tf, ldt, d, P, PT, tau_partials, ff);
+    else x6_split_tau_kernel<false, false><<<kReduceBlocks, 256, 0, s>>>(Tf, ldt, d, P, PT, tau_partials, ff);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -832,19 +825,24 @@ hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, in
 }
 
 hipError_t launch_x6_hemm(const void* G, int64_t ldg, const void* T, int64_t ldt, void* out, int64_t ldo, int n,
-                          const double* tau_dev, const double* upstream_dev, void* planes, hipStream_t s) {
+                          const double* tau_dev, const double* upstream_dev, void* planes, hipStream_t s,
+                          bool g_ready, bool t_ready) {
   const int d = 1 << n;
   if (d < kX6Tile) return hipErrorInvalidValue;
   const int64_t units = int64_t(d / 32) * (d / 16);
   u16x8* PG = static_cast<u16x8*>(planes);
   u16x8* PT = PG + units * 9 * XUNIT;
   hipError_t e;
-  {
+  if (!g_ready || !t_ready) {
     ProfScope prof("x6_split_gt", s);
-    x6_split_kernel<false, 3><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(G), ldg, d, PG);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    x6_split_kernel<true, 3><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(T), ldt, d, PT);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!g_ready) {
+      x6_split_kernel<false, 3><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(G), ldg, d, PG);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!t_ready) {
+      x6_split_kernel<true, 3><<<unsigned((units + 3) / 4), 256, 0, s>>>(static_cast<const Cx<float>*>(T), ldt, d, PT);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   if ((e = x6_allow_lds(x6_hemm_kernel)) != hipSuccess) return e;
   XArgs a{};

@@ -33,10 +33,12 @@ qst_status hip_fail(hipError_t e, const char* what) {
 // planes: workspace for the bf16 planes of T (BF16 path, d >
 // kBf16SplitMaxDim; QST_F32X6 from d = kX6Tile, where the kernel that
 // splits T forms the partial sums), or NULL.
+// ttplanes (QST_F32X6 only, or NULL): T^T's planes for the gradient product,
+// written by the same kernel that splits T.
 hipError_t run_state_map(qst_prec prec, const void* T, int64_t ldT, void* rho, int64_t ldr, int n,
                          double* partials, double* tau_dev, void* sk, hipStream_t s, const void* f = nullptr,
-                         const Pass0Out* x0 = nullptr, void* planes = nullptr) {
-  if (use_x6(prec, n)) return launch_x6_herk(T, ldT, rho, ldr, n, partials, f, tau_dev, planes, sk, s, x0);
+                         const Pass0Out* x0 = nullptr, void* planes = nullptr, void* ttplanes = nullptr) {
+  if (use_x6(prec, n)) return launch_x6_herk(T, ldT, rho, ldr, n, partials, f, tau_dev, planes, sk, s, x0, ttplanes);
   const bool fold = n >= 6;
   hipError_t e = launch_tau(prec, T, ldT, n, partials, fold ? nullptr : tau_dev, s, f, planes);
   if (e != hipSuccess) return e;
@@ -45,7 +47,8 @@ hipError_t run_state_map(qst_prec prec, const void* T, int64_t ldT, void* rho, i
 
 qst_status likelihood_impl(int n, qst_prec prec, const void* T, int64_t ldT, const void* f, const double* povm_host,
                            double* tau_dev, double* nll_dev, unsigned long long* bad_dev, void* G, int64_t ldG,
-                           void* ws, size_t ws_bytes, void* stream, const void* pt, double* fc_dev);
+                           void* ws, size_t ws_bytes, void* stream, const void* pt, double* fc_dev,
+                           void* gplanes = nullptr, void* ttplanes = nullptr);
 
 }  // namespace
 
@@ -467,9 +470,14 @@ extern "C" qst_status qst_likelihood_noalloc(int n, qst_prec prec, const void* T
 
 namespace {
 
+// gplanes / ttplanes (the combined likelihood-and-gradient call, QST_F32X6
+// with a fused plan whose pass 0 writes planes): adjoint pass 0 writes G' as
+// the gradient product's planes at gplanes (G unused), and the T split writes
+// T^T's planes at ttplanes.
 qst_status likelihood_impl(int n, qst_prec prec, const void* T, int64_t ldT, const void* f, const double* povm_host,
                            double* tau_dev, double* nll_dev, unsigned long long* bad_dev, void* G, int64_t ldG,
-                           void* ws, size_t ws_bytes, void* stream, const void* pt, double* fc_dev) {
+                           void* ws, size_t ws_bytes, void* stream, const void* pt, double* fc_dev,
+                           void* gplanes, void* ttplanes) {
   std::string msg;
   qst_status st;
   if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
@@ -497,13 +505,16 @@ qst_status likelihood_impl(int n, qst_prec prec, const void* T, int64_t ldT, con
   // product tiles for every fused plan)
   const bool x0 = fused && tetra && d >= 64 && pl.g[0] >= 4 && pl.g[0] <= 6;
   const Pass0Out p0{ws_at(ws, L.inter0), pl.g[0], true};
+  if ((gplanes || ttplanes) && !(use_x6(prec, n) && fused && x0 && pass0_writes_planes(pl)))
+    return fail(QST_ERR_INVALID_ARG, "operand planes requested where the plan cannot form them");
   hipError_t e = run_state_map(prec, T, ldT, rho, d, n, partials, tau_dev, L.has_sk ? ws_at(ws, L.sk) : nullptr, s,
-                               fused ? f : nullptr, x0 ? &p0 : nullptr, L.has_planes ? ws_at(ws, L.planes) : nullptr);
+                               fused ? f : nullptr, x0 ? &p0 : nullptr, L.has_planes ? ws_at(ws, L.planes) : nullptr,
+                               ttplanes);
   if (e != hipSuccess) return hip_fail(e, "state map");
   if (fused) {
     e = launch_povm_fused(prec, pl, W, V, tetra, rho, d, f, partials + kReduceBlocks, G, ldG, ws_at(ws, L.inter0),
                           ws_at(ws, L.inter1), reinterpret_cast<double*>(ws_at(ws, L.fpart)), nll_dev, bad_dev, x0,
-                          s, pt, fc_dev);
+                          s, pt, fc_dev, gplanes);
     if (e != hipSuccess) return hip_fail(e, "fused POVM / likelihood passes");
   } else {
     void* p = ws_at(ws, L.p);
@@ -607,6 +618,48 @@ qst_status qst_grad_product(int n, qst_prec prec, const void* G, int64_t ldG, co
                              L.has_sk ? ws_at(ws, L.sk) : nullptr, static_cast<hipStream_t>(stream),
                              L.has_planes ? ws_at(ws, L.planes) : nullptr);
   if (e != hipSuccess) return hip_fail(e, "G' T");
+  clear_error();
+  return QST_OK;
+}
+
+qst_status qst_likelihood_grad(int n, qst_prec prec, const void* T, int64_t ldT, const void* f,
+                               const double* povm_host, double* tau_dev, double* nll_dev,
+                               unsigned long long* bad_dev, void* gradT, int64_t ld_grad, void* ws, size_t ws_bytes,
+                               void* stream) {
+  std::string msg;
+  qst_status st;
+  if ((st = check_common(n, prec, msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(T, ldT, n, "T", msg)) != QST_OK) return fail(st, msg);
+  if ((st = check_matrix(gradT, ld_grad, n, "gradT", msg)) != QST_OK) return fail(st, msg);
+  if (gradT == T) return fail(QST_ERR_INVALID_ARG, "gradT must not alias T");
+  const WsLayout L = workspace_layout(n, prec, QST_OP_LIKELIHOOD_GRAD, false);
+  if ((st = check_ws(ws, ws_bytes, L.total, msg)) != QST_OK) return fail(st, msg);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const PovmPlan pl = make_povm_plan(n, prec);
+  const int64_t d = int64_t(1) << n;
+  void* tp = L.has_tplanes ? ws_at(ws, L.tplanes) : nullptr;
+  // QST_F32X6 with the tetrahedral POVM and a plan whose adjoint pass 0
+  // writes planes: both operands' planes are formed inside the likelihood
+  // (the same bits as the split kernels would write from G' and T)
+  const bool in_call = use_x6(prec, n) && povm_host == nullptr && fused_likelihood(pl, prec) &&
+                       pass0_writes_planes(pl) && tp != nullptr;
+  if (in_call) {
+    unsigned char* gpl = static_cast<unsigned char*>(tp);
+    unsigned char* tpl = gpl + x6_hemm_plane_bytes(n) / 2;
+    if ((st = likelihood_impl(n, prec, T, ldT, f, povm_host, tau_dev, nll_dev, bad_dev, nullptr, 0, ws, ws_bytes,
+                              stream, nullptr, nullptr, gpl, tpl)) != QST_OK)
+      return st;
+    hipError_t e = launch_x6_hemm(nullptr, 0, T, ldT, gradT, ld_grad, n, tau_dev, nullptr, tp, s, true, true);
+    if (e != hipSuccess) return hip_fail(e, "G' T");
+  } else {
+    void* G = ws_at(ws, L.gmat);
+    if ((st = likelihood_impl(n, prec, T, ldT, f, povm_host, tau_dev, nll_dev, bad_dev, G, d, ws, ws_bytes, stream,
+                              nullptr, nullptr)) != QST_OK)
+      return st;
+    hipError_t e = launch_hemm(prec, G, d, T, ldT, gradT, ld_grad, n, tau_dev, nullptr,
+                               L.has_sk ? ws_at(ws, L.sk) : nullptr, s, tp);
+    if (e != hipSuccess) return hip_fail(e, "G' T");
+  }
   clear_error();
   return QST_OK;
 }

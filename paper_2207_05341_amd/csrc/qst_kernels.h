@@ -142,13 +142,17 @@ hipError_t launch_hemm(qst_prec prec, const void* G, int64_t ldg, const void* T,
 // kernel that splits T also writes the kReduceBlocks partial sums of tau at
 // tau_partials and, with f (4^N FP32 values), those of F = sum f at
 // tau_partials + kReduceBlocks (launch_tau is not called); tau is stored at
-// tau_dev; rho and x0 as launch_herk.  G' T: planes x6_hemm_plane_bytes(n);
-// as launch_hemm otherwise.
+// tau_dev; rho and x0 as launch_herk.  With tt_planes (x6_hemm_plane_bytes(n)
+// / 2 bytes) the same kernel also writes T^T's planes for G' T there.
+// G' T: planes x6_hemm_plane_bytes(n), G''s planes in the first half and
+// T^T's in the second; g_ready / t_ready: that half holds its planes
+// already (G / T are then not read); as launch_hemm otherwise.
 hipError_t launch_x6_herk(const void* T, int64_t ldt, void* rho, int64_t ldr, int n, double* tau_partials,
                           const void* f, double* tau_dev, void* planes, void* partials, hipStream_t s,
-                          const Pass0Out* x0);
+                          const Pass0Out* x0, void* tt_planes = nullptr);
 hipError_t launch_x6_hemm(const void* G, int64_t ldg, const void* T, int64_t ldt, void* out, int64_t ldo, int n,
-                          const double* tau_dev, const double* upstream_dev, void* planes, hipStream_t s);
+                          const double* tau_dev, const double* upstream_dev, void* planes, hipStream_t s,
+                          bool g_ready = false, bool t_ready = false);
 
 // Forward (adjoint=false): mat = rho (lower triangle read) -> pvec.
 // Adjoint (adjoint=true): g' = F - f/p from (pvec, fvec, F_dev) -> mat = G'
@@ -201,12 +205,15 @@ hipError_t launch_likelihood_finish(const double* part, int nb, const double* Fp
 // inter0), the fused last pass (+ NLL finish into nll_dev / bad_dev), and, if
 // G is not NULL, the adjoint passes P-2..0.  part: FP64 partials [4][blocks
 // of the last pass]; Fpart: the kReduceBlocks F partials.  With pt (4^N
-// reals), the last pass also forms F_c against pt into fc_dev.
+// reals), the last pass also forms F_c against pt into fc_dev.  With
+// gplanes (FP32 storage, pass0_writes_planes(pl)), adjoint pass 0 writes G'
+// as the split planes of the QST_F32X6 gradient product there instead of
+// writing G (which may then be NULL).
 hipError_t launch_povm_fused(qst_prec prec, const PovmPlan& pl, const double* W, const double* V, bool tetra,
                              const void* rho, int64_t ld_rho, const void* fvec, const double* Fpart, void* G,
                              int64_t ldG, void* inter0, void* inter1, double* part, double* nll_dev,
                              unsigned long long* bad_dev, bool pass0_done, hipStream_t s, const void* pt = nullptr,
-                             double* fc_dev = nullptr);
+                             double* fc_dev = nullptr, void* gplanes = nullptr);
 
 hipError_t launch_fsum(qst_prec prec, const void* f, int n, double* partials, double* F_dev,
                        hipStream_t s);

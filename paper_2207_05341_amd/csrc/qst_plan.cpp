@@ -250,6 +250,20 @@ WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute) {
     case QST_OP_ABS_MAP:
       off = absmap_layout(n).total;
       break;
+    case QST_OP_LIKELIHOOD_GRAD: {
+      // the likelihood's layout (same offsets), then G' for the routes that
+      // form it, and the planes of the gradient product (QST_F32X6: G''s
+      // then T^T's; BF16 path from d = 1024: split planes of G' and T^T);
+      // the likelihood's partial tiles serve the gradient product too
+      w = workspace_layout(n, prec, QST_OP_LIKELIHOOD, false);
+      off = w.total;
+      w.gmat = take(D * cb);
+      if (hemm_planes) {
+        w.tplanes = take(x6 ? x6_hemm_plane_bytes(n) : hemm_plane_count * D * sizeof(uint16_t));
+        w.has_tplanes = true;
+      }
+      break;
+    }
     default:
       return WsLayout{};
   }
@@ -528,7 +542,7 @@ size_t qst_workspace_bytes_general(int n_qubits, qst_prec prec, int K, int op) {
 size_t qst_workspace_bytes(int n_qubits, qst_prec prec, int op) {
   std::string msg;
   if (qst::check_common(n_qubits, prec, msg) != QST_OK) return 0;
-  if (op < QST_OP_STATE_MAP || op > QST_OP_ABS_MAP) return 0;
+  if (op < QST_OP_STATE_MAP || op > QST_OP_LIKELIHOOD_GRAD) return 0;
   return qst::workspace_layout(n_qubits, prec, op, /*recompute=*/true).total;
 }
 

@@ -128,6 +128,10 @@ bool fast_pass_available(const PovmPlan& pl, int j, qst_prec prec);
 // specialised.
 bool fused_likelihood(const PovmPlan& pl, qst_prec prec);
 
+// Whether adjoint pass 0 of a fused plan can write G' as split operand
+// planes (first group of 5 or 6 qubits: tiles of at least 32 rows).
+inline bool pass0_writes_planes(const PovmPlan& pl) { return pl.passes >= 2 && (pl.g[0] == 5 || pl.g[0] == 6); }
+
 // Absolute-map workspace (qst_abs_map, qst_abs_map_backward): three d x d
 // complex FP64 buffers, d FP64 values (Jacobi norm partials, then
 // |lambda|^(P/4)), a few FP64 scalars and the FP64 stream-K partial tiles of
@@ -174,8 +178,10 @@ struct WsLayout {
   size_t fpart = 0;      // fused likelihood pass: FP64 partials [4][blocks]
   size_t planes = 0;     // BF16 path: bf16(T) as re and im planes for T T^dagger (d > kBf16SplitMaxDim,
                          // 4 d^2 bytes); split planes of G' and T^T for G' T (d >= 1024, 16 d^2 bytes)
+  size_t tplanes = 0;    // combined likelihood-and-gradient call: planes of G' T (G''s, then T^T's)
   bool has_sk = false;
   bool has_planes = false;
+  bool has_tplanes = false;
 };
 
 WsLayout workspace_layout(int n, qst_prec prec, int op, bool recompute);

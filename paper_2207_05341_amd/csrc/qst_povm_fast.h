@@ -8,6 +8,7 @@
 #include "qst_device.h"
 #include "qst_povm_ops.h"
 #include "qst_povm_rounds.h"
+#include "qst_split.h"
 
 namespace qst {
 namespace fast_pass {
@@ -19,9 +20,17 @@ namespace fast_pass {
 // call with index wb (thread tid of 256) covers tiles wb * TPW ..; tiles
 // past ntiles load nothing and store nothing.  lds holds TPW * 4^G values.
 // ---------------------------------------------------------------------------
-template <typename R, bool ADJ, bool TETRA, int G>
+//
+// PLANES (adjoint, FP32, G = 5 or 6): instead of G' itself, G' as the split
+// operand planes of the QST_F32X6 gradient product (row operand, groups
+// re, im, re + im, three exact bf16 parts; layout of qst_split.h) at
+// a.gplanes: each tile, then its conjugate transpose (off the diagonal),
+// passes through LDS row-major (16-byte chunks swizzled by row) and every
+// thread writes four unit-block slots.
+template <typename R, bool ADJ, bool TETRA, int G, bool PLANES = false>
 __device__ __forceinline__ void mat_pass_body(const PassArgs& a, const ModeMatrix& A, int64_t ntiles, int64_t wb,
                                               unsigned tid, Cx<R> (&lds)[(256 >> (2 * (G - 2))) << (2 * G)]) {
+  static_assert(!PLANES || (ADJ && G >= 5 && sizeof(R) == 4), "planes from FP32 adjoint tiles of 32 or 64 rows");
   constexpr int NT = 1 << (2 * (G - 2));
   constexpr int TPW = 256 / NT;
   constexpr int TILE = 1 << (2 * G);
@@ -114,7 +123,7 @@ __device__ __forceinline__ void mat_pass_body(const PassArgs& a, const ModeMatri
           L[swz<G>(r, c)] = x[m];
         }
         __syncthreads();
-      } else if (active) {
+      } else if (active && !PLANES) {
         Cx<R> blk[4][4];
 #pragma unroll
         for (int m = 0; m < 16; ++m) blk[blk_ri(m)][blk_ci(m)] = x[m];
@@ -132,6 +141,44 @@ __device__ __forceinline__ void mat_pass_body(const PassArgs& a, const ModeMatri
 #pragma unroll
             for (int ri = 0; ri < 4; ++ri) row[ri] = Cx<R>{blk[ri][ci].re, -blk[ri][ci].im};
           }
+        }
+      }
+    }
+    if constexpr (PLANES) {
+      constexpr int S = 1 << G;  // tile side
+      // (r, c) of the tile in LDS: row-major, 16-byte chunks swizzled by row
+      auto at = [](int r, int c) { return r * S + 2 * (((c >> 1) ^ r) & (S / 2 - 1)) + (c & 1); };
+      __syncthreads();  // every thread is past its round-0 reads of L
+      if (active) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) L[at(4 * aq + blk_ri(m), 4 * bq + blk_ci(m))] = x[m];
+      }
+      __syncthreads();
+      if (active) {
+        // slots of the tile: 2 (tile, mirror) x (S / 32) row blocks x
+        // (S / 16) k blocks x 64 lanes, four per thread
+        constexpr int UB = (S / 32) * (S / 16);
+        const int64_t nkb = (int64_t(1) << a.n) / 16;
+        u16x8* PL = static_cast<u16x8*>(a.gplanes);
+#pragma unroll
+        for (int i = 0; i < (2 * UB * 64) / NT; ++i) {
+          const int it = t + NT * i;
+          const bool mir = it >= UB * 64;
+          if (mir && Rhi == Chi) continue;  // a diagonal tile is its own mirror
+          const int ub = (it / 64) % UB, ln = it % 64;
+          const int rbl = ub / (S / 16), kbl = ub % (S / 16);
+          const int rr = rbl * 32 + (ln & 31), k0 = kbl * 16 + 8 * (ln >> 5);
+          float re[8], im[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            // G'[R0 + rr][C0 + k0 + e], or for the mirror G'[C0 + rr][R0 + k0 + e]
+            // = conj(G'[R0 + k0 + e][C0 + rr])
+            const Cx<R> v = mir ? L[at(k0 + e, rr)] : L[at(rr, k0 + e)];
+            re[e] = v.re;
+            im[e] = mir ? -v.im : v.im;
+          }
+          const int64_t rbg = (mir ? C0 : R0) / 32 + rbl, kbg = (mir ? R0 : C0) / 16 + kbl;
+          write_unit_block<3>(PL + (rbg * nkb + kbg) * (3 * 3 * kX6UnitVecs) + ln, re, im);
         }
       }
     }

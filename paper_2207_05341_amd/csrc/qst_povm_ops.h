@@ -30,6 +30,7 @@ struct PassArgs {
   const double* Fpart;  // fused last pass: kReduceBlocks FP64 partial sums of F = sum f
   double* part;         // fused last pass: FP64 partials [4][blocks] (L, F_c terms, bad0, bad1)
   const void* pt;       // fused last pass: target distribution of F_c, or NULL
+  void* gplanes;        // adjoint pass 0 of the combined call: G' as split operand planes instead of G'
   int64_t ld;           // row stride of the matrix (rho or G')
   int n, U, g, J;
 };

@@ -53,7 +53,7 @@ def test_status_strings(L):
 def test_workspace_sizes(L):
     ws = lib_mod.workspace_bytes
     # invalid requests
-    assert ws(0, 0, 0) == 0 and ws(14, 0, 0) == 0 and ws(5, 7, 0) == 0 and ws(5, 0, 9) == 0
+    assert ws(0, 0, 0) == 0 and ws(14, 0, 0) == 0 and ws(5, 7, 0) == 0 and ws(5, 0, 10) == 0
     # single-pass POVM needs no workspace; N=11 needs one 4^N complex intermediate
     assert ws(6, 0, lib_mod.QST_OP_POVM_PROBS) == 0
     assert ws(11, lib_mod.QST_F64, lib_mod.QST_OP_POVM_PROBS) >= 16 * 4 ** 11
@@ -76,7 +76,13 @@ def test_workspace_sizes(L):
             # BF16 state map from N = 8: bf16 planes of T (4 d^2 bytes)
             if prec == 2 and n >= 8:
                 assert ws(n, prec, lib_mod.QST_OP_STATE_MAP) >= 4 * 4 ** n
-    assert ws(5, 0, 9) == 0
+            # the combined call: the likelihood's workspace plus G'
+            assert ws(n, prec, lib_mod.QST_OP_LIKELIHOOD_GRAD) >= ws(n, prec, lib_mod.QST_OP_LIKELIHOOD) + cb * 4 ** n
+        # QST_F32X6 from d = 128: the planes of G' T as well (36 d^2 bytes)
+        if n >= 7:
+            assert ws(n, lib_mod.QST_F32X6, lib_mod.QST_OP_LIKELIHOOD_GRAD) >= \
+                ws(n, lib_mod.QST_F32X6, lib_mod.QST_OP_LIKELIHOOD) + (8 + 36) * 4 ** n
+    assert ws(5, 0, 10) == 0
     # absolute map: three d x d complex FP64 buffers, any storage precision
     for n in (1, 6, 12):
         for prec in (0, 1, 2):
@@ -284,6 +290,24 @@ def test_grad_product_validation(L):
     assert call(ldg=5) == lib_mod.QST_ERR_INVALID_ARG
     assert call(grad=FAKE) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
     assert call(grad=FAKE2) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
+
+
+def test_likelihood_grad_validation(L):
+    n, d = 10, 1024
+    ws = lib_mod.workspace_bytes(n, 0, lib_mod.QST_OP_LIKELIHOOD_GRAD)
+    W = ctypes.c_void_p(0x30000)
+    out, tau, nll = ctypes.c_void_p(0x50000), ctypes.c_void_p(0x60000), ctypes.c_void_p(0x70000)
+
+    def call(n=n, prec=0, T=FAKE, ldT=d, f=FAKE2, grad=out, ldg=d, tau=tau, nll=nll, nb=ws):
+        return L.qst_likelihood_grad(n, prec, T, ldT, f, None, tau, nll, None, grad, ldg, W, nb, None)
+
+    assert call(n=0) == lib_mod.QST_ERR_INVALID_ARG and "n_qubits" in _err(L)
+    assert call(prec=9) == lib_mod.QST_ERR_INVALID_ARG and "precision" in _err(L)
+    assert call(T=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(grad=None) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(ldg=5) == lib_mod.QST_ERR_INVALID_ARG
+    assert call(grad=FAKE) == lib_mod.QST_ERR_INVALID_ARG and "alias" in _err(L)
     assert call(nb=ws - 1) == lib_mod.QST_ERR_WORKSPACE
 
 

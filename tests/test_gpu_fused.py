@@ -243,3 +243,67 @@ def test_fused_n12_f32_against_recompute():
                 torch.linalg.vector_norm(grad2.to(torch.complex128)))
     say(f"  grad rel diff {err:.2e}")
     assert err <= 5e-6  # two FP32 evaluation orders (both are checked against the oracle at 1e-5 elsewhere)
+
+
+# ---------------------------------------------------------------------------
+# qst_likelihood_grad: L and dL/dT in one call, against qst_likelihood
+# followed by qst_grad_product.  Every case but one runs the two stages in
+# sequence through the workspace and must agree bitwise.  With QST_F32X6 and
+# plans whose first POVM stage covers 5 or 6 qubits (N = 9, 10, 11 here) the
+# gradient product's planes are formed inside the call (the T split writes
+# T^T's planes, the adjoint's last stage writes G''s): L, F and tau are
+# still bitwise equal, the gradient agrees to rounding (that adjoint stage
+# is a kernel instance of its own, whose sums the compiler may contract
+# into FMAs differently).
+# ---------------------------------------------------------------------------
+
+def run_combined(T, f, prec, povm=None):
+    Tg, fg = to_dev(T.astype(ctype(prec))), to_dev(f.astype(rtype(prec)))
+    out, tau, grad, bad = qst.likelihood_grad(Tg, fg, prec, povm)
+    out2, tau2, G2, bad2 = qst.likelihood_forward(Tg, fg, prec, povm)
+    grad2 = qst.grad_product(G2, Tg, tau2, prec)
+    torch.cuda.synchronize()
+    return (host(out), host(tau), host(grad), host(bad)), (host(out2), host(tau2), host(grad2), host(bad2))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32x6"])
+@pytest.mark.parametrize("n", [3, 7, 8, 9, 10, 11, 12])
+def test_likelihood_grad_equals_two_calls(n, prec):
+    say(f"likelihood_grad vs likelihood_forward + grad_product n={n} prec={prec}")
+    T, f, _ = depolarised_case(n, 3800 + n, 0.05, 20 * 4 ** n)
+    a, b = run_combined(T, f, prec)
+    in_call = prec == "f32x6" and n in (9, 10, 11)
+    for x, y, what in zip(a, b, ("out", "tau", "grad", "bad")):
+        if what == "grad" and in_call:
+            e = rel_fro(x, y)
+            say(f"  in-call planes: grad rel {e:.2e}, max |d| / max |grad| {np.max(np.abs(x - y)) / np.max(np.abs(y)):.2e}")
+            assert e <= 1e-6, e
+        else:
+            assert np.array_equal(x, y), (what, n, prec)
+
+
+def test_likelihood_grad_general_povm_f32x6():
+    """A non-tetrahedral POVM takes the two-stage route inside the call."""
+    say("likelihood_grad, rotated tetrahedron POVM, n=9 f32x6")
+    g = S.rng(3900)
+    U, _ = np.linalg.qr(S.ginibre(g, 2))
+    M = np.array([U @ m @ U.conj().T for m in O.tetrahedral_povm()])
+    T, f, _ = depolarised_case(9, 3910, 0.2, 10 ** 6)
+    a, b = run_combined(T, f, "f32x6", povm=M)
+    for x, y, what in zip(a, b, ("out", "tau", "grad", "bad")):
+        assert np.array_equal(x, y), what
+
+
+@pytest.mark.parametrize("n", [7, 9, 10])
+def test_likelihood_grad_against_oracle_f32x6(n):
+    say(f"likelihood_grad n={n} f32x6 against the oracle")
+    T, f, _ = depolarised_case(n, 4000 + n, 0.1, 20 * 4 ** n)
+    Tq = T.astype(np.complex64)
+    fq = f.astype(np.float32)
+    out, tau, grad, bad = qst.likelihood_grad(to_dev(Tq), to_dev(fq), "f32x6")
+    torch.cuda.synchronize()
+    wL, wtau, _, wgrad = oracle(Tq.astype(np.complex128), fq.astype(np.float64))
+    assert abs(float(out[0].item()) - wL) <= TOL["f32x6"] * abs(wL)
+    assert abs(float(tau.item()) - wtau) <= 1e-12 * wtau
+    assert rel_fro(host(grad), wgrad) <= TOL["f32x6"]
+    assert host(bad).tolist() == [0, 0]
