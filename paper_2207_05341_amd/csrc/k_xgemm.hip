@@ -206,6 +206,16 @@ __global__ __launch_bounds__(256) void x6_split_tau_kernel(const Cx<float>* __re
 // ---------------------------------------------------------------------------
 // Product kernel
 // ---------------------------------------------------------------------------
+// A wave-uniform pointer moved into scalar registers.  The builtin takes
+// and returns a signed 32-bit value per half; each half is taken back as
+// unsigned, so that the high half is not sign-extended over.
+__device__ __forceinline__ const u16x8* uniform_ptr(const u16x8* p) {
+  const uint64_t u = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(u)));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(u >> 32)));
+  return reinterpret_cast<const u16x8*>((uint64_t(hi) << 32) | uint64_t(lo));
+}
+
 // global -> LDS copy of one 16-byte vector per lane into the 1 KB at LDS
 // byte address lds (wave-uniform).  Written as an asm statement so that the
 // compiler's wait-count pass, which cannot tell ring slots apart, does not
@@ -291,25 +301,40 @@ __device__ __forceinline__ void x6_segment(const XArgs& a, char* lds, int tr, in
   const uint32_t lbase = __builtin_amdgcn_readfirstlane(lds_address(lds));
   // this wave's six units of every slab: unit q = 6 w + i, A (q < 12) or B,
   // split (q % 12) / 4, row block q % 4; all of it wave-uniform except the
-  // lane's 16-byte offset
+  // lane's 16-byte offset.  cbase[i]: unit i's address at panel 0, group 0
+  // (scalar registers: the asm operand requires them); a slab adds
+  // (kp ng + g) 3 units.
   const uint32_t voff = uint32_t(lane) * 16;
-  auto dma_one = [&](int s, int i) {  // slab s of the segment (panel clamped)
-    const int kp = kb + min(s / 3, ke - kb - 1), prod = s % 3;
+  const u16x8* cbase[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
     const int q = 6 * w + i;
     const bool isB = q >= 12;
     const int sp = (q % 12) / 4, rb = q % 4;
-    const int ng = isB ? a.ngB : a.ngA;
-    const int g = prod < 2 ? prod : (isB ? a.gB2 : a.gA2);
     const int64_t r0 = int64_t(isB ? tc : tr) * (XT / 32) + rb;
-    const u16x8* base = (isB ? a.B : a.A) + (((r0 * nkb + kp) * ng + g) * 3 + sp) * XUNIT;
-    dma16(base, voff, lbase + uint32_t((s % XNSLOT) * XSLOT + q * 1024));
+    cbase[i] = uniform_ptr((isB ? a.B : a.A) + ((r0 * nkb * (isB ? a.ngB : a.ngA)) * 3 + sp) * XUNIT);
+  }
+  const int npan = ke - kb;
+  // copies of slab s = 3 kp + prod of the segment (panel clamped to the
+  // last); prod is a compile-time constant at every call
+  auto dma_slab = [&](int s, int kp, int prod) {
+    const int kpa = kb + min(kp, npan - 1);
+    const int64_t offA = (int64_t(kpa) * a.ngA + (prod < 2 ? prod : a.gA2)) * 3 * XUNIT;
+    const int64_t offB = (int64_t(kpa) * a.ngB + (prod < 2 ? prod : a.gB2)) * 3 * XUNIT;
+    const uint32_t slot = lbase + uint32_t((s % XNSLOT) * XSLOT);
+    return [=](int i) {
+      const int q = 6 * w + i;
+      dma16(cbase[i] + (q >= 12 ? offB : offA), voff, slot + uint32_t(q * 1024));
+    };
   };
   u16x8 fa[3][3][2], fb[3][3][2];  // [product][split][block]
   f16v acc[3][2][2];
 #pragma unroll
-  for (int s = 0; s < XDIST; ++s)
+  for (int s = 0; s < XDIST; ++s) {
+    const auto copy = dma_slab(s, s / 3, s % 3);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) dma_one(s, i);
+    for (int i = 0; i < 6; ++i) copy(i);
+  }
   QST_VMCNT((XDIST - 1) * 6);
   __builtin_amdgcn_s_barrier();
   {
@@ -329,7 +354,6 @@ __device__ __forceinline__ void x6_segment(const XArgs& a, char* lds, int tr, in
   constexpr int SA[6] = {0, 0, 0, 1, 1, 2}, SB[6] = {0, 1, 2, 0, 1, 0};
   constexpr int RD_AB[12] = {0, 0, 1, 1, 1, 1, 1, 1, 0, 0, 0, 0};  // 0: A, 1: B
   constexpr int RD_SP[12] = {0, 0, 0, 0, 1, 1, 2, 2, 1, 1, 2, 2};
-  const int npan = ke - kb;
   for (int c0 = 0; c0 < npan; c0 += XCHAIN) {
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -351,6 +375,7 @@ __device__ __forceinline__ void x6_segment(const XArgs& a, char* lds, int tr, in
         __builtin_amdgcn_sched_barrier(0);
         const int np = prod == 2 ? 0 : prod + 1;
         const u16x8* L = reinterpret_cast<const u16x8*>(lds + ((s + 1) % XNSLOT) * XSLOT);
+        const auto copy = dma_slab(s + XDIST, kp + (prod + XDIST) / 3, (prod + XDIST) % 3);
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
 #pragma unroll
@@ -367,7 +392,7 @@ __device__ __forceinline__ void x6_segment(const XArgs& a, char* lds, int tr, in
               else fb[np][sp][bi] = L[(12 + sp * 4 + wc * 2 + bi) * XUNIT + lane];
             }
           } else {
-            dma_one(s + XDIST, q);
+            copy(q);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
