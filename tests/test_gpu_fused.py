@@ -307,3 +307,26 @@ def test_likelihood_grad_against_oracle_f32x6(n):
     assert abs(float(tau.item()) - wtau) <= 1e-12 * wtau
     assert rel_fro(host(grad), wgrad) <= TOL["f32x6"]
     assert host(bad).tolist() == [0, 0]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f32x6"])
+def test_likelihood_grad_padded_T(prec):
+    """T as a view with row stride d + 8 (n = 9): the same results as the
+    two calls on the same view (the in-call-planes route to rounding)."""
+    say(f"likelihood_grad with a padded T, n=9 prec={prec}")
+    n, d = 9, 512
+    T, f, _ = depolarised_case(n, 4100, 0.05, 10 ** 6)
+    big = torch.zeros((d, d + 8), dtype=torch.complex64, device=DEV)
+    big[:, :d] = to_dev(T.astype(np.complex64))
+    Tv = big[:, :d]
+    fg = to_dev(f.astype(np.float32))
+    out, tau, grad, bad = qst.likelihood_grad(Tv, fg, prec)
+    out2, tau2, G2, _ = qst.likelihood_forward(Tv, fg, prec)
+    grad2 = qst.grad_product(G2, Tv, tau2, prec)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2) and torch.equal(tau, tau2)
+    if prec == "f32x6":
+        assert rel_fro(host(grad), host(grad2)) <= 1e-6
+    else:
+        assert torch.equal(grad, grad2)
+    assert host(bad).tolist() == [0, 0]
