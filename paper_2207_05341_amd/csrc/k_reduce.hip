@@ -230,22 +230,47 @@ __global__ __launch_bounds__(256) void likelihood_finish_kernel(const double* __
                                                                 unsigned long long* __restrict__ bad,
                                                                 double* __restrict__ fc) {
   __shared__ double red[4];
-  double sums[4];
-  if (fc) {  // F_c = (sum of the F_c terms)^2 from slot 1
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[int64_t(nb) + b];
-    acc = block_sum256(acc, red);
-    if (threadIdx.x == 0) fc[0] = acc * acc;
-  }
-  for (int i = 0; i < 4; ++i) {
-    if (i == 1) {
-      sums[1] = sum_partials256(Fpart, kReduceBlocks, red);
-      continue;
+  // Each thread sums slots 0, 2, 3 (and the F_c slot 1) of part with stride
+  // 256 and the F partials likewise, in increasing index, as before; the
+  // loads of all of them are issued U per array before any of the adds
+  // (indices past the end are clamped and their values not added), so the
+  // arrays' latencies overlap.  Block sums as sum_partials256 / block_sum256.
+  constexpr int U = 4;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // slots 0, 2, 3, F, F_c
+  const int nmax = nb > kReduceBlocks ? nb : kReduceBlocks;
+  for (int b0 = threadIdx.x; b0 < nmax; b0 += 256 * U) {
+    double v[5][U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + 256 * u;
+      const int bp = b < nb ? b : nb - 1, bf = b < kReduceBlocks ? b : kReduceBlocks - 1;
+      v[0][u] = part[bp];
+      v[1][u] = part[int64_t(2) * nb + bp];
+      v[2][u] = part[int64_t(3) * nb + bp];
+      v[3][u] = Fpart[bf];
+      v[4][u] = fc ? part[int64_t(nb) + bp] : 0.0;
     }
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[int64_t(i) * nb + b];
-    sums[i] = block_sum256(acc, red);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + 256 * u;
+      if (b < nb) {
+        acc[0] += v[0][u];
+        acc[1] += v[1][u];
+        acc[2] += v[2][u];
+        acc[4] += v[4][u];
+      }
+      if (b < kReduceBlocks) acc[3] += v[3][u];
+    }
   }
+  if (fc) {  // F_c = (sum of the F_c terms)^2 from slot 1
+    const double t = block_sum256(acc[4], red);
+    if (threadIdx.x == 0) fc[0] = t * t;
+  }
+  double sums[4];
+  sums[0] = block_sum256(acc[0], red);
+  sums[1] = block_sum256(acc[3], red);
+  sums[2] = block_sum256(acc[1], red);
+  sums[3] = block_sum256(acc[2], red);
   if (threadIdx.x == 0) {
     double L = sums[0];
     if (sums[1] != sums[1] || sums[3] > 0.0) {
