@@ -683,42 +683,65 @@ struct X6Contrib {
 // 16-byte vectors; the loads of up to four contributions are in flight
 // before they are added, in order.
 template <int X0G>
-__global__ __launch_bounds__(256) void x6_fixup_kernel(XArgs a) {
+__global__ __launch_bounds__(256, 3) void x6_fixup_kernel(XArgs a) {
   __shared__ __align__(16) Cx<float> L[64 * 64];
+  __shared__ double red[4];
   const X6HerkSched& sc = a.sc;
-  if (blockIdx.x == 0) (void)x6_tau(a, true);  // stores tau (the product kernel does not)
   const int64_t t = sc.ntiles - 1 - (blockIdx.x >> 2);
   const int q = blockIdx.x & 3, qr = q >> 1, qc = q & 1;
   int tr, tc;
   tri_decode(t, tr, tc);
-  if (tr == tc && qr < qc) return;
+  const bool skip = tr == tc && qr < qc;  // mirror quadrant of a diagonal tile
   const int th = threadIdx.x;
   X6Contrib it(sc, t);
-  if (it.finished()) return;
-  f4v acc[8], v[4][8];
+  if (blockIdx.x != 0 && (skip || it.finished())) return;
+  // tau's partial sums (x6_tau's order), loaded now so that their latency
+  // overlaps the contributions' loads; workgroup 0 also stores tau
+  double tp[kReduceBlocks / 256];
+#pragma unroll
+  for (int k = 0; k < kReduceBlocks / 256; ++k) tp[k] = a.tau_part[th + 256 * k];
+  if (blockIdx.x == 0 && (skip || it.finished())) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kReduceBlocks / 256; ++k) acc += tp[k];
+    const double tau = block_sum256(acc, red);
+    if (th == 0 && a.tau_out) *a.tau_out = tau;
+    return;
+  }
+  f4v acc[8], v[2][8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) acc[m] = f4v{0.f, 0.f, 0.f, 0.f};
-  // four contributions in flight, then added in order
+  // two contributions in flight (most tiles have two), then added in order
   while (true) {
-    int64_t sl[4];
+    int64_t sl[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sl[k] = it.next();
+    for (int k = 0; k < 2; ++k) sl[k] = it.next();
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 2; ++k)
       if (sl[k] >= 0) {
         const f4v* src = reinterpret_cast<const f4v*>(x6_slot(a, sl[k]) + q * 8192);
 #pragma unroll
         for (int m = 0; m < 8; ++m) v[k][m] = src[th + 256 * m];
       }
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 2; ++k)
       if (sl[k] >= 0) {
 #pragma unroll
         for (int m = 0; m < 8; ++m) acc[m] += v[k][m];
       }
-    if (sl[3] < 0) break;
+    if (sl[1] < 0) break;
   }
-  const double scale = 1.0 / x6_tau(a, false);
+  double tacc = 0.0;
+#pragma unroll
+  for (int k = 0; k < kReduceBlocks / 256; ++k) tacc += tp[k];
+  const double tau = block_sum256(tacc, red);
+  __shared__ double tau_sh;
+  if (th == 0) {
+    tau_sh = tau;
+    if (blockIdx.x == 0 && a.tau_out) *a.tau_out = tau;
+  }
+  __syncthreads();
+  const double scale = 1.0 / tau_sh;
   // vector th + 256 m of the quadrant holds values 4 vq + c of block
   // ij = m / 2, part m % 2, lane th % 64, vq = th / 64
   const float sc32 = float(scale);
