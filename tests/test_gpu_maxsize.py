@@ -202,3 +202,25 @@ def test_n13_sampled_outcomes_and_invariants(n13, prec):
             del E
         say(f"  central differences: worst |fd - <grad,E>| / |grad| = {worst:.3e}")
         assert worst <= 1e-5
+
+
+def test_n13_one_call_f32x6(n13):
+    """qst_likelihood_grad at N = 13 (plan 5, 4, 4: the gradient product's
+    planes formed inside the call, pass 0 on 32 x 32 tiles) against the two
+    calls: L, F and tau bitwise, the gradient to rounding."""
+    T, f, ks, p_w, tau_w = n13
+    say("N=13 f32x6: qst_likelihood_grad vs qst_likelihood + qst_grad_product")
+    Tg, fg = to_dev(T.astype(np.complex64)), to_dev(f.astype(np.float32))
+    out, tau, grad, bad = qst.likelihood_grad(Tg, fg, "f32x6")
+    torch.cuda.synchronize()
+    grad_h = host(grad)
+    del grad
+    out2, tau2, G, bad2 = qst.likelihood_forward(Tg, fg, "f32x6")
+    grad2 = qst.grad_product(G, Tg, tau2, "f32x6")
+    torch.cuda.synchronize()
+    del G
+    assert torch.equal(out, out2) and torch.equal(tau, tau2)
+    e = rel_fro(grad_h, host(grad2))
+    say(f"  grad rel {e:.2e}")
+    assert e <= 1e-6
+    assert host(bad).tolist() == [0, 0]
