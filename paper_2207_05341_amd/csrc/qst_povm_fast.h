@@ -318,8 +318,11 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
   __builtin_assume(tid < 256);
 
   const int U = a.U;  // == G
-  const int64_t kd = int64_t(1) << (2 * (a.n - U));
-  const int64_t kd0 = lb * J;
+  // element indices of X, f and the target stay below 4^N <= 2^26 (N <= 13):
+  // 32-bit, which saves 64-bit vector address arithmetic
+  static_assert(QST_MAX_QUBITS <= 15, "32-bit outcome indices");
+  const uint32_t kd = 1u << (2 * (a.n - U));
+  const uint32_t kd0 = uint32_t(lb) * J;
   Cx<R>* X = static_cast<Cx<R>*>(a.out);  // in place: a.in == a.out
   const R* f = static_cast<const R*>(a.f);
   // f for the outcomes of the last round, loaded now so that it arrives
@@ -335,7 +338,7 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         const int kg = u + ((m >> 2) << (2 * RD::bA[rl])) + ((m & 3) << (2 * RD::bB[rl]));
-        fpre[bi][m] = f[int64_t(kg) * kd + kd0 + j];
+        fpre[bi][m] = f[uint32_t(kg) * kd + kd0 + j];
       }
     }
   }
@@ -361,7 +364,7 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
           rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
           const bool mir = r < c;
           const int rr = mir ? c : r, cc = mir ? r : c;
-          Cx<R> v = X[((int64_t(rr) << U) | cc) * kd + kd0 + j];
+          Cx<R> v = X[((uint32_t(rr) << U) | uint32_t(cc)) * kd + kd0 + j];
           if (mir) v.im = -v.im;
           x[m] = v;
         }
@@ -382,7 +385,7 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
 #pragma unroll
           for (int m = 0; m < 16; ++m) {
             const int kg = u + ((m >> 2) << (2 * bA)) + ((m & 3) << (2 * bB));
-            qk[m] = static_cast<const R*>(a.pt)[int64_t(kg) * kd + kd0 + j];
+            qk[m] = static_cast<const R*>(a.pt)[uint32_t(kg) * kd + kd0 + j];
           }
         }
       }
@@ -451,7 +454,7 @@ __device__ __forceinline__ void kd_fused_body(const PassArgs& a, const ModeMatri
         for (int m = 0; m < 16; ++m) {
           int r, c;
           rc_of(rf, cf, bA, bB, m >> 2, m & 3, r, c);
-          if (r >= c) X[((int64_t(r) << U) | c) * kd + kd0 + j] = x[m];
+          if (r >= c) X[((uint32_t(r) << U) | uint32_t(c)) * kd + kd0 + j] = x[m];
         }
       }
     }
