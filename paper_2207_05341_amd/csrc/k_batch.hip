@@ -736,15 +736,15 @@ qst_status qst_batch_plan_create(const int* n_qubits, int count, qst_prec prec, 
     free_plan(p);
     return qst::fail_status(QST_ERR_HIP, std::string("device query: ") + hipGetErrorString(e));
   }
-  p->thread_options = qst::batch_thread_options(prec);
+  p->thread_options = qst::batch_thread_options(p->prec);
   int occ_max = 1;
   for (int th : p->thread_options) {
-    p->occ.push_back(std::max(1, qst::batch_occupancy(prec, th)));
+    p->occ.push_back(std::max(1, qst::batch_occupancy(p->prec, th)));
     occ_max = std::max(occ_max, p->occ.back());
   }
   p->threads = p->thread_options[0];
   const int64_t dmax = int64_t(1) << p->nmax, Dmax = dmax * dmax;
-  const size_t cb = qst::complex_bytes(prec), rb = qst::real_bytes(prec);
+  const size_t cb = qst::complex_bytes(p->prec), rb = qst::real_bytes(p->prec);
   const int64_t stride = int64_t((2 * Dmax * cb + Dmax * rb + 64 + 255) / 256 * 256);
   const int max_grid = p->cus * occ_max;
   p->max_grid = max_grid;
@@ -768,7 +768,7 @@ qst_status qst_batch_plan_create(const int* n_qubits, int count, qst_prec prec, 
   a.stride = stride;
   a.nmax = p->nmax;
   for (int m = 1; m <= qst::kBatchMaxQubits; ++m) {
-    const qst::PovmPlan pl = qst::make_povm_plan(m, prec);
+    const qst::PovmPlan pl = qst::make_povm_plan(m, p->prec);
     a.plan.passes[m] = pl.passes;
     for (int j = 0; j < 4; ++j) {
       a.plan.g[m][j] = pl.g[j];
@@ -786,7 +786,7 @@ qst_status qst_batch_plan_create(const int* n_qubits, int count, qst_prec prec, 
   int hist[qst::kBatchMaxQubits + 1] = {0};
   for (int i = 0; i < count; ++i) ++hist[p->n[i]];
   std::ostringstream key;
-  key << "prec" << int(prec) << (p->tetra ? "-tetra" : "-povm") << "-n";
+  key << "prec" << int(p->prec) << (p->tetra ? "-tetra" : "-povm") << "-n";
   for (int m = 1; m <= qst::kBatchMaxQubits; ++m) key << (m > 1 ? "." : "") << hist[m];
   key << "-" << device_name(p->device);
   p->key = key.str();

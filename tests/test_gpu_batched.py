@@ -201,3 +201,27 @@ def test_batch_every_tuned_shape(batch1024, tmp_path, prec, threads, rr):
     say(f"  worst relative L error {worst_L:.3e}, worst gradient error {worst_g:.3e}")
     assert worst_L <= TOL[prec] and worst_g <= TOL[prec]
     plan.close()
+
+
+def test_batch_f32x6_runs_as_f32(batch1024, tmp_path):
+    """Batched instances have d <= 256, so a QST_F32X6 plan is an FP32 plan:
+    the same tuning key, launch shapes and results.  The two plans share a
+    tuning cache; the second takes the first's tuned shape and must give
+    the same bits."""
+    ns, Ts, fs, _ = batch1024
+    sel = list(range(0, 1024, 8))
+    ns_s = [ns[i] for i in sel]
+    Tq, fq = quantize([Ts[i] for i in sel], [fs[i] for i in sel], "f32")
+    cache = tmp_path / "tune.txt"
+    outs = []
+    for prec in ("f32", "f32x6"):
+        plan = qst.BatchPlan(ns_s, prec, tune_cache=str(cache))
+        T_all, f_all = plan.pack(Tq, fq, DEV)
+        nll, grad, bad = plan.run(T_all, f_all, use_graph=False)
+        torch.cuda.synchronize()
+        outs.append((plan.info(), nll.cpu().numpy(), grad.cpu().numpy(), bad.cpu().numpy()))
+        plan.close()
+    say(f"f32 plan {outs[0][0]}, f32x6 plan {outs[1][0]}")
+    assert outs[0][0]["threads"] == outs[1][0]["threads"] and outs[0][0]["grid"] == outs[1][0]["grid"]
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
+    assert (outs[1][3] == 0).all()
