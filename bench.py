@@ -15,6 +15,15 @@ calls with p stored (qst_state_map, qst_povm_probs, qst_nll,
 qst_nll_backward) are reported alongside, each with its error against the
 FP64 oracle.
 
+Timing: each timed loop first runs untimed steps for --settle-ms (200 ms),
+then --warmup steps, then exactly --steps timed steps between two device
+synchronisations.  The settle phase is there because the GPU's clocks move
+for some tens of milliseconds after a sustained load starts (a kernel trace
+of 273 steps: the gradient product at 235 us for the first launches, 270 us
+around launch 10, 228 us from launch 50 on), so a loop timed right after 5
+warm-up steps would average over that transient instead of the steady state
+a training loop runs in.
+
 Workload (N = 11): T 2048 x 2048 complex Ginibre (seed 6); frequencies from
 10^7 multinomial shots of a Porter-Thomas stand-in distribution of a
 depolarised random pure state (q = 0.05).
@@ -63,12 +72,12 @@ TRAFFIC_F32_SOURCES = ["paper_2207_05341_amd/csrc/k_gemm.hip", "paper_2207_05341
 TRAFFIC_X6_SOURCES = ["paper_2207_05341_amd/csrc/k_xgemm.hip", "paper_2207_05341_amd/csrc/qst_device.h",
                       "paper_2207_05341_amd/csrc/qst_plan.h"]
 TRAFFIC = {
-    # N = 11, d = 2048: 173433.0 KiB fetched x 1.9998 + 32768.0 KiB written x 1.0000
-    "hemm_f32": {"bytes": 388.71e6, "sources": TRAFFIC_F32_SOURCES,
-                 "sources_sha256": "1e7a7a10ffb5a3dc9b5656b1a4dc8e43e07207dfe3b35e626d9354c8b7cf152d"},
-    # N = 11, d = 2048: 247292.0 KiB fetched x 1.9998 + 84736.0 KiB written x 1.0000
-    "hemm_x6": {"bytes": 593.18e6, "sources": TRAFFIC_X6_SOURCES,
-                "sources_sha256": "a4ce3f50f576dc819c1404eefa888ced8099c24dfab2100928ae1c6d030ad6f8"},
+    # N = 11, d = 2048: 173432.6 KiB fetched x 1.9998 + 32768.0 KiB written x 1.0000
+    "hemm_f32": {"bytes": 388.72e6, "sources": TRAFFIC_F32_SOURCES,
+                 "sources_sha256": "cf7d877ef3298deb050ec257066709cd3d9f4e78d6553e910532b1148e99dacf"},
+    # N = 11, d = 2048: 247286.1 KiB fetched x 1.9998 + 84736.0 KiB written x 1.0000
+    "hemm_x6": {"bytes": 593.17e6, "sources": TRAFFIC_X6_SOURCES,
+                "sources_sha256": "d09ab1f8635f1bf9b1863e152fde7527a0dafdafa4b12012e41997eddc26166a"},
 }
 
 
@@ -94,6 +103,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--settle-ms", type=float, default=200.0,
+                    help="untimed steps for this long before the warmup of every timed loop, so that the "
+                         "timed steps see the GPU's steady clocks (0: none)")
     ap.add_argument("--prec", default="f32x6", choices=["f64", "f32", "bf16", "f32x6"],
                     help="precision path of the headline step (default f32x6: FP32 storage and accuracy, "
                          "complex products as six split-bf16 products on the BF16 MFMA)")
@@ -161,15 +173,23 @@ def step(qst, T, f, prec, route="one_call"):
     return out, grad
 
 
-def time_steps(qst, T, f, prec, steps, warmup, only=None, route="one_call"):
-    """Run warmup + steps; with `only`, the library times that kernel scope
-    (HIP events on its launch stream) inside the same steps; `only=""` times
+def time_steps(qst, T, f, prec, steps, warmup, only=None, route="one_call", settle_s=0.0):
+    """Run untimed steps for settle_s seconds (the GPU's clocks move for
+    some tens of milliseconds after a load starts: measured in a kernel
+    trace, G' T went 235 -> 270 -> 228 us over the first 50 steps), then
+    warmup + steps; with `only`, the library times that kernel scope (HIP
+    events on its launch stream) inside the same steps; `only=""` times
     every scope (each bracketing event costs queue time, so that loop is a
     breakdown, not the throughput figure)."""
     import torch
 
     from paper_2207_05341_amd import _lib
 
+    t_end = time.perf_counter() + settle_s
+    while time.perf_counter() < t_end:
+        for _ in range(10):
+            step(qst, T, f, prec, route)
+        torch.cuda.synchronize()
     for _ in range(warmup):
         step(qst, T, f, prec, route)
     torch.cuda.synchronize()
@@ -679,6 +699,11 @@ def cpu_baseline(T, f, prec):
     return rec, ref
 
 
+def note(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -733,7 +758,7 @@ def main():
         # the scopes and the dominant one from a short loop that times them all
         _, names = time_steps(qst, T, f, prec, 3, 2, only="", route=route)
         dom = max(names, key=lambda k: names[k][1] / names[k][0])
-        sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom, route=route)
+        sec, kdom = time_steps(qst, T, f, prec, steps, warmup, only=dom, route=route, settle_s=args.settle_ms / 1e3)
         breakdown = {dom: kdom[dom]}
         for name in names:
             if name != dom:
@@ -741,6 +766,7 @@ def main():
         return sec, breakdown, dom, kdom, acc, res
 
     sec, kern, dom, kdom, acc, res_main = measure(args.prec, args.steps, args.warmup)
+    note(f"headline {args.prec}: {1e3 * sec:.4f} ms per step")
     kern_us = {k: 1e3 * ms / calls for k, (calls, ms) in kern.items()}
 
     # roofline of the dominant kernel (largest share of the step), its
@@ -808,14 +834,17 @@ def main():
             if prec == args.prec:
                 continue
             s2, k2, _, _, a2, path_res[prec] = measure(prec, max(10, args.steps // 2), 3)
+            note(f"path {prec}: {1e3 * s2:.4f} ms per step")
             paths[prec] = {"evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
                            "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()}}
         s2, k2, _, _, a2, _ = measure(args.prec, max(10, args.steps // 2), 3, route="two_calls")
+        note(f"path {args.prec} two calls: {1e3 * s2:.4f} ms per step")
         paths[args.prec + "_two_calls"] = {
             "evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
             "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()},
             "note": "qst_likelihood (G' returned) then qst_grad_product"}
         s2, k2, _, _, a2, _ = measure(args.prec, max(10, args.steps // 2), 3, route="separate")
+        note(f"path {args.prec} separate calls: {1e3 * s2:.4f} ms per step")
         paths[args.prec + "_separate_calls"] = {
             "evals_per_s": 1.0 / s2, "ms_per_step": 1e3 * s2, "accuracy_vs_f64": a2,
             "kernels_us": {k: round(1e3 * ms / c, 2) for k, (c, ms) in k2.items()},
@@ -826,16 +855,22 @@ def main():
     modes = fids = net = None
     if not args.headline_only:
         modes = state_maps(qst, Tm, fm, args.prec)
+        note("state maps done")
         fids = fidelities(qst, Tm, args.prec, f=fm)
+        note("fidelities done")
         net = network(qst, fm, args.prec, long_run=args.nnqst_run)
+        note("network done")
     absp = None if args.no_long else abs_projection(qst, args.prec, fm.device)
     genp = None if args.no_long else general_povms(qst, args.prec, dev)
+    if not args.no_long:
+        note("absolute projection and general POVMs done")
     del Tm, fm
     batch = None
     if not args.no_batched:
         batch = batched(qst, args.prec, dev)
         if args.prec != "f64":  # the FP64 path's batch, for its speed at its accuracy
             batch["f64"] = batched(qst, "f64", dev)
+        note("batched form done")
     cpu, acc_oracle = None, None
     if not args.no_cpu_baseline:
         # the timed oracle leg also gives the reference outputs for the
@@ -844,6 +879,7 @@ def main():
         import oracle as O
 
         cpu, ref = cpu_baseline(T_np, f_np, args.prec)
+        note("CPU oracle leg done")
         refs = {args.prec: ref}
         storage = {"f64": "f64", "f32": "f32", "bf16": "f32", "f32x6": "f32"}  # complex64 T except FP64
         for prec in path_res:
@@ -873,6 +909,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_ms": args.settle_ms,
         "ms_per_step": 1e3 * sec,
         "higher_is_better": True,
         "scaling": "weak",
