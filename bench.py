@@ -66,15 +66,16 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE (separate runs, KiB per dispatch), each scaled by what the same
 # counter reads for one plain 256 MiB device copy in the same run.  A figure
 # holds only for the kernel sources it was measured on (SHA-256 over the
-# record's source files, in order); otherwise the reported traffic is null.
+# record's source files, in order, the build script with its flags among
+# them); otherwise the reported traffic is null.
 TRAFFIC_F32_SOURCES = ["paper_2207_05341_amd/csrc/k_gemm.hip", "paper_2207_05341_amd/csrc/qst_gemm_tiles.h",
-                       "paper_2207_05341_amd/csrc/qst_device.h"]
+                       "paper_2207_05341_amd/csrc/qst_device.h", "paper_2207_05341_amd/build.py"]
 TRAFFIC_X6_SOURCES = ["paper_2207_05341_amd/csrc/k_xgemm.hip", "paper_2207_05341_amd/csrc/qst_device.h",
-                      "paper_2207_05341_amd/csrc/qst_plan.h"]
+                      "paper_2207_05341_amd/csrc/qst_plan.h", "paper_2207_05341_amd/build.py"]
 TRAFFIC = {
     # N = 11, d = 2048: 173432.6 KiB fetched x 1.9998 + 32768.0 KiB written x 1.0000
     "hemm_f32": {"bytes": 388.72e6, "sources": TRAFFIC_F32_SOURCES,
-                 "sources_sha256": "cf7d877ef3298deb050ec257066709cd3d9f4e78d6553e910532b1148e99dacf"},
+                 "sources_sha256": "92d43825669e57af5b4f19e9eb0247c3d2ccf7bd79bec7799dba5a7c54c5f5ab"},
     # N = 11, d = 2048: 247286.1 KiB fetched x 1.9998 + 84736.0 KiB written x 1.0000
     "hemm_x6": {"bytes": 593.17e6, "sources": TRAFFIC_X6_SOURCES,
                 "sources_sha256": "d09ab1f8635f1bf9b1863e152fde7527a0dafdafa4b12012e41997eddc26166a"},

@@ -44,9 +44,19 @@ def common_flags() -> list[str]:
     ]
 
 
+# Per-source flags.  k_xgemm.hip: MFMA accumulators in VGPRs (the LLVM
+# AMDGPU option selecting the VGPR form of the MFMA instructions).  With the
+# default AGPR form the register allocator spills the split-bf16 products'
+# FP32 chain totals to scratch memory; the reloads at every chain close are
+# vector-memory loads queued behind the in-flight global-to-LDS copies of
+# the operand ring, so each close waited for the whole ring.  In the VGPR
+# form the totals spill to AGPRs and the MFMA loops are unchanged.
+SOURCE_FLAGS = {"k_xgemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [hipcc(), *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *common_flags(), *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -789,9 +789,9 @@ __global__ __launch_bounds__(256, 3) void x6_fixup_kernel(XArgs a) {
 
 // The product kernels use more LDS than the static limit: raise the
 // per-kernel limit once per device before the first launch.
-template <typename K>
-hipError_t x6_allow_lds(K kernel) {
-  static std::mutex mu;
+template <auto K>
+hipError_t x6_allow_lds() {
+  static std::mutex mu;  // one flag set per kernel
   static bool done[64] = {};
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -799,7 +799,7 @@ hipError_t x6_allow_lds(K kernel) {
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
   std::lock_guard<std::mutex> lock(mu);
   if (!done[dev]) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, XLDS);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize, XLDS);
     if (e != hipSuccess) return e;
     done[dev] = true;
   }
@@ -815,7 +815,7 @@ int x6_cus() {
 
 template <int X0G>
 hipError_t x6_run_herk(XArgs a, int n, hipStream_t s) {
-  hipError_t e = x6_allow_lds(x6_herk_kernel<X0G>);
+  hipError_t e = x6_allow_lds<x6_herk_kernel<X0G>>();
   if (e != hipSuccess) return e;
   a.sc = x6_herk_sched(n, x6_cus());
   const int64_t grid = a.sc.rounds > 0 ? a.sc.P : a.sc.Q;
@@ -892,7 +892,7 @@ hipError_t launch_x6_hemm(const void* G, int64_t ldg, const void* T, int64_t ldt
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
-  if ((e = x6_allow_lds(x6_hemm_kernel)) != hipSuccess) return e;
+  if ((e = x6_allow_lds<x6_hemm_kernel>()) != hipSuccess) return e;
   XArgs a{};
   a.A = PG;
   a.B = PT;
