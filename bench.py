@@ -76,9 +76,9 @@ TRAFFIC = {
     # N = 11, d = 2048: 173432.6 KiB fetched x 1.9998 + 32768.0 KiB written x 1.0000
     "hemm_f32": {"bytes": 388.72e6, "sources": TRAFFIC_F32_SOURCES,
                  "sources_sha256": "92d43825669e57af5b4f19e9eb0247c3d2ccf7bd79bec7799dba5a7c54c5f5ab"},
-    # N = 11, d = 2048: 247286.1 KiB fetched x 1.9998 + 84736.0 KiB written x 1.0000
-    "hemm_x6": {"bytes": 593.17e6, "sources": TRAFFIC_X6_SOURCES,
-                "sources_sha256": "d09ab1f8635f1bf9b1863e152fde7527a0dafdafa4b12012e41997eddc26166a"},
+    # N = 11, d = 2048: 221292.0 KiB fetched x 1.9998 + 32768.0 KiB written x 1.0000
+    "hemm_x6": {"bytes": 486.72e6, "sources": TRAFFIC_X6_SOURCES,
+                "sources_sha256": "d07ab688a35ba92bf5fc8a9fcf87fd584398d052e065de90a6fb1023555d4950"},
 }
 
 
